@@ -1,0 +1,488 @@
+"""FP64 CPU oracle: one explicit RK3 time step of the implicit, second-order,
+discrete-forcing immersed-boundary method on a staggered Cartesian grid,
+followed by an FFT / tridiagonal pressure projection.
+
+TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+CPU-baseline leg of the benchmark may import this module.  It shares no code
+with the GPU library and never calls it.
+
+Every function cites the passage of the paper (arXiv 2506.14328) it follows.
+Where the paper is silent the reading taken is stated in the docstring
+(readings R1..R13; the same list is kept with the design notes).
+
+Conventions
+-----------
+x streamwise (periodic), y wall-normal (bounded by the box walls y_lo, y_hi),
+z spanwise (periodic).  Arrays are indexed [j, k, i] (x fastest):
+  p   cell centres          (x_c[i], y_c[j], z_c[k])       shape (ny-1, nz, nx)
+  u   west faces            (i*dx,   y_c[j], z_c[k])
+  v   south faces           (x_c[i], y_f[j], z_c[k])       (face j = ny-1 is the north
+                                                             box wall: implicit zero)
+  w   back faces            (x_c[i], y_c[j], k*dz)
+Ghost rows of u and w at j = -1 and j = ny-1 lie outside the box; they are
+always external (value 0) and only carry SDF samples.
+Pi is the mean streamwise pressure gradient, entering the u-momentum
+equation as -Pi (the paper's notation in Sec. 2.5, Eq. (18)).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+from typing import Dict, Optional, Tuple
+
+import numpy as np
+import scipy.fft
+
+# Rai & Moin RK3 coefficients (Sec. 2.4, Eq. (17)): c_k = a_k + b_k.
+RK_A = np.array([64.0, 50.0, 90.0]) / 120.0
+RK_B = np.array([0.0, -34.0, -50.0]) / 120.0
+RK_C = RK_A + RK_B
+
+CFR, CPG = 0, 1
+B_EXP, B_EULER, B_TAYLOR2 = 0, 1, 2
+
+
+@dataclass
+class OGrid:
+    nx: int
+    ny: int
+    nz: int
+    lx: float
+    lz: float
+    y_lo: float
+    y_hi: float
+    nu: float
+    dt: float
+    forcing: int = CFR
+    q_target_or_pi: float = 0.0
+    b_mode: int = B_EXP
+
+    @property
+    def dx(self):
+        return self.lx / self.nx
+
+    @property
+    def dz(self):
+        return self.lz / self.nz
+
+    @property
+    def dy(self):
+        return (self.y_hi - self.y_lo) / (self.ny - 1)
+
+    @property
+    def shape(self):
+        return (self.ny - 1, self.nz, self.nx)
+
+    @classmethod
+    def from_case(cls, c) -> "OGrid":
+        return cls(c.nx, c.ny, c.nz, c.lx, c.lz, c.y_lo, c.y_hi, c.nu, c.dt,
+                   c.forcing, c.q_target_or_pi, c.b_mode)
+
+
+# --------------------------------------------------------------------------------------
+# Neighbour access on the staggered arrays (periodic x, z; zero beyond the y rows).
+# --------------------------------------------------------------------------------------
+def sx(f, d):
+    """f at i+d (periodic in x)."""
+    return np.roll(f, -d, axis=2)
+
+
+def sz(f, d):
+    """f at k+d (periodic in z)."""
+    return np.roll(f, -d, axis=1)
+
+
+def sy(f, d):
+    """f at j+d, zero outside the stored rows (ghost rows / north wall are zero)."""
+    out = np.zeros_like(f)
+    if d > 0:
+        out[:-d] = f[d:]
+    elif d < 0:
+        out[-d:] = f[:d]
+    else:
+        out[:] = f
+    return out
+
+
+# --------------------------------------------------------------------------------------
+# Geometry: staircase classification and wall distances (Sec. 2.2, Sec. 3.3)
+# --------------------------------------------------------------------------------------
+def classify(g: OGrid, sdf_u, sdf_v, sdf_w) -> Dict[str, np.ndarray]:
+    """Internal/external tags per component grid and for pressure (Sec. 3.3).
+
+    Each velocity grid is compared with the boundary on its own: a point is
+    internal iff its signed distance is > 0 (reading R7: s <= 0 is solid).
+    v on the two box-wall faces is always external.  A pressure cell is
+    internal iff at least one of its six faces is an internal velocity point.
+    """
+    int_u = sdf_u[1:-1] > 0.0
+    int_v = sdf_v[:-1] > 0.0
+    int_v[0] = False
+    int_w = sdf_w[1:-1] > 0.0
+    int_p = (int_u | sx(int_u, 1) | int_v | sy(int_v, 1) | int_w | sz(int_w, 1))
+    return {"u": int_u, "v": int_v, "w": int_w, "p": int_p}
+
+
+def _arm_lambda(nu, h, sP, sQ, extQ, box_dist):
+    """Contribution nu * d2(-1) (h - delta)/delta of one stencil arm (Eq. (7)).
+
+    delta is the distance from the internal point to the wall along the arm:
+    the linear zero crossing of the signed distance between the point and its
+    external neighbour (reading R8), or the box wall when that is nearer.
+    d2(-1) = 1/h^2 for the uniform three-point second derivative (Eq. (3)).
+    """
+    with np.errstate(divide="ignore", invalid="ignore"):
+        d_sdf = np.where(sQ <= 0.0, h * sP / (sP - sQ), np.inf)
+    delta = np.minimum(d_sdf, box_dist)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        contrib = np.where(extQ, nu * (h - delta) / (delta * h * h), 0.0)
+    return contrib
+
+
+def wall_lambda(g: OGrid, sdf_full: np.ndarray, comp: str, internal: np.ndarray) -> np.ndarray:
+    """IBM centre-weight correction lambda per point of one component grid.
+
+    Sec. 2.2, Eqs. (5)-(7): the ghost value is the linear extrapolation
+    through zero at the wall; substituted into the Laplacian it only changes
+    the centre coefficient by lambda = d2(-1) (h - delta)/delta.  The viscous
+    factor nu multiplies it (reading R9).  Corrections from different arms
+    add up independently (end of Sec. 2.2).
+    """
+    nu = g.nu
+    if comp in ("u", "w"):
+        s = sdf_full[1:-1]
+        s_dn = sdf_full[:-2]          # row j-1 (ghost row -1 for j = 0)
+        s_up = sdf_full[2:]           # row j+1 (ghost row ny-1 for j = ny-2)
+        nrow = s.shape[0]
+        ext_dn = s_dn <= 0.0
+        ext_up = s_up <= 0.0
+        ext_dn[0] = True              # ghost rows are outside the box
+        ext_up[-1] = True
+        box_dn = np.full(s.shape, np.inf)
+        box_up = np.full(s.shape, np.inf)
+        box_dn[0] = 0.5 * g.dy        # u, w of row 0 sit dy/2 above the south box wall
+        box_up[-1] = 0.5 * g.dy
+    else:  # v: faces 0..ny-1 are all stored in sdf_full; face 0 and ny-1 are box walls
+        s = sdf_full[:-1]
+        s_dn = np.zeros_like(s)
+        s_dn[1:] = sdf_full[:-2]
+        s_up = sdf_full[1:]
+        ext_dn = s_dn <= 0.0
+        ext_up = s_up <= 0.0
+        ext_dn[1] = True              # neighbour face 0 is the south box wall
+        ext_up[-1] = True             # neighbour face ny-1 is the north box wall
+        box_dn = np.full(s.shape, np.inf)
+        box_up = np.full(s.shape, np.inf)
+        box_dn[1] = g.dy
+        box_up[-1] = g.dy
+    lam = np.zeros(s.shape)
+    for h, sQ, extQ, bd in (
+        (g.dx, sx(s, -1), sx(s, -1) <= 0.0, np.inf),
+        (g.dx, sx(s, +1), sx(s, +1) <= 0.0, np.inf),
+        (g.dz, sz(s, -1), sz(s, -1) <= 0.0, np.inf),
+        (g.dz, sz(s, +1), sz(s, +1) <= 0.0, np.inf),
+        (g.dy, s_dn, ext_dn, box_dn),
+        (g.dy, s_up, ext_up, box_up),
+    ):
+        lam += _arm_lambda(nu, h, s, sQ, extQ, bd)
+    lam = np.where(internal, lam, 0.0)
+    return lam
+
+
+def stage_coefficients(lam: np.ndarray, k: int, dt: float, b_mode: int = B_EXP):
+    """(B, A) of the implicit IBM update for RK stage k (Sec. 2.4, Eqs. (14)-(16)).
+
+    With x = lambda c_k dt (reading R5):
+      exponential fit  B = x/(e^x - 1),  A = x + B  (B = 1 at x = 0, B = 0 for huge x)
+      implicit Euler   B = 1,            A = 1 + x
+      Taylor-2         B = 1/(1 + x/2),  A = x + B   (reciprocal of the Taylor
+                                                       expansion of 1/B, Sec. 2.4)
+    """
+    x = lam * RK_C[k] * dt
+    if b_mode == B_EXP:
+        with np.errstate(over="ignore", invalid="ignore", divide="ignore"):
+            B = np.where(x > 0.0, x / np.expm1(np.minimum(x, 700.0)), 1.0)
+        B = np.where(x > 700.0, 0.0, B)
+        A = x + B
+    elif b_mode == B_EULER:
+        B = np.ones_like(x)
+        A = 1.0 + x
+    elif b_mode == B_TAYLOR2:
+        B = 1.0 / (1.0 + 0.5 * x)
+        A = x + B
+    else:
+        raise ValueError(b_mode)
+    return B, A
+
+
+# --------------------------------------------------------------------------------------
+# Discrete operators (Sec. 2.1: second-order central differences on the staggered grid)
+# --------------------------------------------------------------------------------------
+def convection(g: OGrid, u, v, w):
+    """Convective terms N(u) in divergence form with two-point averages (reading R1).
+
+    No IBM correction of the convective terms: external and ghost values enter
+    as zero (Sec. 3.1 and the opening of Sec. 2).
+    """
+    dx, dy, dz = g.dx, g.dy, g.dz
+    h = 0.5
+    # u-momentum at (i*dx, y_c[j], z_c[k])
+    Nu = ((h * (u + sx(u, 1))) ** 2 - (h * (sx(u, -1) + u)) ** 2) / dx
+    Nu += (h * (u + sy(u, 1)) * h * (sx(sy(v, 1), -1) + sy(v, 1))
+           - h * (sy(u, -1) + u) * h * (sx(v, -1) + v)) / dy
+    Nu += (h * (u + sz(u, 1)) * h * (sx(sz(w, 1), -1) + sz(w, 1))
+           - h * (sz(u, -1) + u) * h * (sx(w, -1) + w)) / dz
+    # v-momentum at (x_c[i], y_f[j], z_c[k])
+    Nv = (h * (v + sx(v, 1)) * h * (sx(sy(u, -1), 1) + sx(u, 1))
+          - h * (sx(v, -1) + v) * h * (sy(u, -1) + u)) / dx
+    Nv += ((h * (v + sy(v, 1))) ** 2 - (h * (sy(v, -1) + v)) ** 2) / dy
+    Nv += (h * (v + sz(v, 1)) * h * (sz(sy(w, -1), 1) + sz(w, 1))
+           - h * (sz(v, -1) + v) * h * (sy(w, -1) + w)) / dz
+    # w-momentum at (x_c[i], y_c[j], k*dz)
+    Nw = (h * (w + sx(w, 1)) * h * (sx(sz(u, -1), 1) + sx(u, 1))
+          - h * (sx(w, -1) + w) * h * (sz(u, -1) + u)) / dx
+    Nw += (h * (w + sy(w, 1)) * h * (sz(sy(v, 1), -1) + sy(v, 1))
+           - h * (sy(w, -1) + w) * h * (sz(v, -1) + v)) / dy
+    Nw += ((h * (w + sz(w, 1))) ** 2 - (h * (sz(w, -1) + w)) ** 2) / dz
+    return Nu, Nv, Nw
+
+
+def laplacian(g: OGrid, f):
+    """Seven-point Laplacian, Eq. (3), with external/ghost neighbours equal to zero.
+
+    Sec. 2.4: as long as external values are zero and the right-hand side is
+    explicit, the unmodified Laplacian is used; the wall enters through lambda.
+    """
+    return ((sx(f, 1) - 2.0 * f + sx(f, -1)) / g.dx ** 2
+            + (sy(f, 1) - 2.0 * f + sy(f, -1)) / g.dy ** 2
+            + (sz(f, 1) - 2.0 * f + sz(f, -1)) / g.dz ** 2)
+
+
+def gradient(g: OGrid, p):
+    """G p on the u, v, w faces (row 0 of the v component is the box wall, unused)."""
+    return ((p - sx(p, -1)) / g.dx, (p - sy(p, -1)) / g.dy, (p - sz(p, -1)) / g.dz)
+
+
+def divergence(g: OGrid, u, v, w):
+    """D u at every cell: forward differences to the cell's faces; v on the north
+    box wall face is zero."""
+    return (sx(u, 1) - u) / g.dx + (sy(v, 1) - v) / g.dy + (sz(w, 1) - w) / g.dz
+
+
+def explicit_rhs(g: OGrid, u, v, w, tags):
+    """H = -N(u) + nu L(u) at internal points (Sec. 2.4, Eq. (9)); zero elsewhere."""
+    Nu, Nv, Nw = convection(g, u, v, w)
+    Hu = np.where(tags["u"], -Nu + g.nu * laplacian(g, u), 0.0)
+    Hv = np.where(tags["v"], -Nv + g.nu * laplacian(g, v), 0.0)
+    Hw = np.where(tags["w"], -Nw + g.nu * laplacian(g, w), 0.0)
+    return Hu, Hv, Hw
+
+
+# --------------------------------------------------------------------------------------
+# Pressure Poisson solve: FFT in x and z, tridiagonal in y (Sec. 2.1: solved exactly)
+# --------------------------------------------------------------------------------------
+def modified_wavenumbers(n: int, h: float, half: bool) -> np.ndarray:
+    """Eigenvalues of the periodic three-point second difference: (4/h^2) sin^2(pi m/n)."""
+    m = np.arange(n // 2 + 1 if half else n)
+    return (4.0 / (h * h)) * np.sin(np.pi * m / n) ** 2
+
+
+def thomas(lower, diag, upper, rhs):
+    """Thomas algorithm for tridiagonal systems along axis 0, vectorised over the rest."""
+    n = rhs.shape[0]
+    cp = np.empty(diag.shape, dtype=np.float64)
+    dp = np.empty(rhs.shape, dtype=rhs.dtype)
+    cp[0] = upper[0] / diag[0]
+    dp[0] = rhs[0] / diag[0]
+    for j in range(1, n):
+        den = diag[j] - lower[j] * cp[j - 1]
+        cp[j] = upper[j] / den
+        dp[j] = (rhs[j] - lower[j] * dp[j - 1]) / den
+    x = np.empty_like(dp)
+    x[-1] = dp[-1]
+    for j in range(n - 2, -1, -1):
+        x[j] = dp[j] - cp[j] * x[j + 1]
+    return x
+
+
+def poisson_solve(g: OGrid, rhs: np.ndarray) -> Tuple[np.ndarray, float]:
+    """Solve D G phi = rhs - mean(rhs) on the full box, zero-mean phi (readings R6, R11).
+
+    Periodic x, z: real FFT in x, complex FFT in z, modified wavenumbers.
+    In y, for each Fourier mode, the three-point operator with homogeneous
+    Neumann closure (v = 0 on the box walls: the first and last rows carry -1
+    instead of -2).  Mode (0,0) is singular: its right-hand side mean is
+    removed, phi_0 = 0 fixes the constant, and the mean of phi is removed.
+    Returns (phi, mean of rhs that was removed).
+    """
+    n = g.ny - 1
+    rh = scipy.fft.fft(scipy.fft.rfft(rhs, axis=2), axis=1)          # (n, nz, mh)
+    mean00 = rh[:, 0, 0].mean()
+    rh[:, 0, 0] -= mean00
+    kx2 = modified_wavenumbers(g.nx, g.dx, half=True)
+    kz2 = modified_wavenumbers(g.nz, g.dz, half=False)
+    K2 = kz2[:, None] + kx2[None, :]
+    idy2 = 1.0 / (g.dy * g.dy)
+    shape = (n,) + K2.shape
+    lower = np.full(shape, idy2)
+    upper = np.full(shape, idy2)
+    diag = np.broadcast_to(-2.0 * idy2 - K2, shape).copy()
+    diag[0] += idy2
+    diag[-1] += idy2
+    lower[0] = 0.0
+    upper[-1] = 0.0
+    # gauge of the singular (0,0) mode: replace its first row by phi_0 = 0
+    diag[0, 0, 0] = 1.0
+    upper[0, 0, 0] = 0.0
+    rh[0, 0, 0] = 0.0
+    ph = thomas(lower, diag, upper, rh)
+    ph[:, 0, 0] -= ph[:, 0, 0].mean()
+    phi = scipy.fft.irfft(scipy.fft.ifft(ph, axis=1), n=g.nx, axis=2)
+    return phi, float(mean00.real) / (g.nx * g.nz)
+
+
+# --------------------------------------------------------------------------------------
+# Solver state and the RK3 substep (Sec. 2.4, Eq. (16); Sec. 2.1 projection)
+# --------------------------------------------------------------------------------------
+class Oracle:
+    """Plain FP64 solver for one channel instance."""
+
+    def __init__(self, g: OGrid):
+        self.g = g
+        self.tags = None
+        self.lam = None
+        self.coef = None
+        self.S = None
+        shp = g.shape
+        self.u = np.zeros(shp)
+        self.v = np.zeros(shp)
+        self.w = np.zeros(shp)
+        self.p = np.zeros(shp)
+        self.H = None
+        self.step_count = 0
+        self.time = 0.0
+        self.pi_last = 0.0
+        self.q_last = 0.0
+        self.diag = {}
+
+    # -- geometry ------------------------------------------------------------------
+    def set_geometry(self, sdf_u, sdf_v, sdf_w, ibm: bool = True):
+        """Classification, lambda and per-stage coefficients.  ibm=False keeps the
+        bare staircase (lambda = 0 everywhere), the first-order baseline of Sec. 2.2."""
+        g = self.g
+        self.tags = classify(g, sdf_u, sdf_v, sdf_w)
+        if not self.tags["p"].any():
+            raise ValueError("geometry has no fluid")
+        self.lam = {
+            "u": wall_lambda(g, sdf_u, "u", self.tags["u"]),
+            "v": wall_lambda(g, sdf_v, "v", self.tags["v"]),
+            "w": wall_lambda(g, sdf_w, "w", self.tags["w"]),
+        }
+        if not ibm:
+            self.lam = {c: np.zeros_like(l) for c, l in self.lam.items()}
+        self.coef = []
+        for k in range(3):
+            self.coef.append({c: stage_coefficients(self.lam[c], k, g.dt, g.b_mode) for c in "uvw"})
+        # response of the flow rate to a unit pressure gradient at each stage
+        self.S = [self.flow_rate(np.where(self.tags["u"], RK_C[k] * g.dt / self.coef[k]["u"][1], 0.0))
+                  for k in range(3)]
+
+    def set_state(self, u, v, w, p):
+        self.u, self.v, self.w, self.p = (np.array(a, dtype=np.float64) for a in (u, v, w, p))
+        self.H = None
+
+    def flow_rate(self, f):
+        """Q = (1/nx) sum over internal u faces of f dy dz (mean flux through x-planes)."""
+        g = self.g
+        return float(np.sum(np.where(self.tags["u"], f, 0.0)) * g.dy * g.dz / g.nx)
+
+    # -- one RK substep --------------------------------------------------------------
+    def substep(self, k: int):
+        g, t = self.g, self.tags
+        dt, ck = g.dt, RK_C[k]
+        # explicit right-hand side at the current stage (Eq. (9) without the IBM term)
+        Hn = explicit_rhs(g, self.u, self.v, self.w, t)
+        Gp = gradient(g, self.p)
+        star = []
+        for c, f, Hc, Gc in zip("uvw", (self.u, self.v, self.w), Hn, Gp):
+            r = dt * RK_A[k] * Hc - ck * dt * Gc                     # reading R2
+            if RK_B[k] != 0.0:
+                r = r + dt * RK_B[k] * self.H[("uvw").index(c)]
+            B, A = self.coef[k][c]
+            # Eq. (16): (lambda c_k dt + B) w* - B w = dt (a_k f_k + b_k f_{k-1})
+            star.append(np.where(t[c], (B * f + r) / A, 0.0))        # reading R3
+        us, vs, ws = star
+        # mean pressure gradient (reading R4)
+        invA_u = 1.0 / self.coef[k]["u"][1]
+        if g.forcing == CFR:
+            q0 = self.flow_rate(us)
+            pi = (q0 - g.q_target_or_pi) / self.S[k]
+        else:
+            pi = g.q_target_or_pi
+        us = np.where(t["u"], us - pi * ck * dt * invA_u, 0.0)
+        self.pi_last = pi
+        # projection (Sec. 2.1; continuity on the full box, Sec. 3.3, reading R6)
+        rhs = divergence(g, us, vs, ws) / (ck * dt)
+        phi, mean_removed = poisson_solve(g, rhs)
+        Gx, Gy, Gz = gradient(g, phi)
+        un = us - ck * dt * Gx
+        vn = vs - ck * dt * Gy
+        vn[0] = 0.0                                                     # south box wall
+        wn = ws - ck * dt * Gz
+        div_full = divergence(g, un, vn, wn)
+        resid = divergence(g, *gradient_full(g, phi)) - (rhs - mean_removed)
+        self.diag = {
+            "div_max_fullbox": float(np.abs(div_full).max()),
+            "poisson_rel_residual": float(np.abs(resid).max() / max(np.abs(rhs).max(), 1e-300)),
+            "rhs_mean_removed": mean_removed,
+        }
+        # external faces back to zero (Sec. 3.3); only internal pressure is updated
+        self.u = np.where(t["u"], un, 0.0)
+        self.v = np.where(t["v"], vn, 0.0)
+        self.w = np.where(t["w"], wn, 0.0)
+        self.p = np.where(t["p"], self.p + phi, 0.0)
+        self.H = Hn
+        self.q_last = self.flow_rate(self.u)
+
+    def step(self, nsteps: int = 1):
+        for _ in range(nsteps):
+            for k in range(3):
+                self.substep(k)
+            self.step_count += 1
+            self.time += self.g.dt
+
+    # -- diagnostics -------------------------------------------------------------------
+    def stats(self) -> Dict[str, float]:
+        g, t = self.g, self.tags
+        d = divergence(g, self.u, self.v, self.w)
+        out = dict(self.diag)
+        out.update({
+            "step": self.step_count,
+            "time": self.time,
+            "q": self.flow_rate(self.u),
+            "pi_last": self.pi_last,
+            "div_max_internal_leak": float(np.abs(np.where(t["p"], d, 0.0)).max()),
+            "ke": float(0.5 * (np.sum(self.u ** 2) + np.sum(self.v ** 2) + np.sum(self.w ** 2))
+                        * g.dx * g.dy * g.dz),
+            "cfl_max": float(np.max(np.abs(self.u) / g.dx + np.abs(self.v) / g.dy
+                                    + np.abs(self.w) / g.dz) * g.dt),
+            "n_internal": [int(t[c].sum()) for c in "uvw"],
+            "n_ibm": [int((self.lam[c] > 0).sum()) for c in "uvw"],
+            "n_p_internal": int(t["p"].sum()),
+            "nan_flag": int(not (np.isfinite(self.u).all() and np.isfinite(self.v).all()
+                                 and np.isfinite(self.w).all() and np.isfinite(self.p).all())),
+        })
+        return out
+
+
+def gradient_full(g: OGrid, phi):
+    """G phi on all faces with the v component zeroed on the south box wall."""
+    Gx, Gy, Gz = gradient(g, phi)
+    Gy = Gy.copy()
+    Gy[0] = 0.0
+    return Gx, Gy, Gz
+
+
+def solve_pressure(g: OGrid, rhs: np.ndarray):
+    """Stand-alone Poisson solve, the operation behind the library's solve-pressure call."""
+    return poisson_solve(g, np.asarray(rhs, dtype=np.float64))
