@@ -1,0 +1,174 @@
+/*
+ * ibm.h -- C ABI of the MI355X (gfx950) implementation of one explicit RK3 time
+ * step of the implicit, second-order, discrete-forcing immersed-boundary method
+ * (Luchini et al., arXiv 2506.14328) on a staggered Cartesian channel grid,
+ * with an FFT (x, z) / tridiagonal (y) pressure projection.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Status: every function returns IBM_OK (0) or a negative IBM_ERR_* code; no
+ *   C++ exception crosses the ABI.  ibm_last_error() gives a message.
+ * Handle: opaque, owned by the library, released by ibm_destroy().
+ * Memory: every array argument is a DEVICE pointer (HIP global memory, e.g. a
+ *   torch tensor on the GPU), contiguous, in the layout stated below.  The
+ *   library copies what it keeps and never frees caller memory.  Internal
+ *   fields live in device memory the library allocates at create time.
+ * Stream: all work is enqueued on the hipStream_t given at create, in stream
+ *   order.  Only ibm_stats(), ibm_get_geometry()/ibm_get_ibm_list(),
+ *   ibm_profile_read() and ibm_set_geometry() synchronise that stream.
+ * Precision: fixed at create.  IBM_FP64 stores and computes everything in
+ *   double.  IBM_FP32_STORAGE stores velocity, pressure and spectra as float
+ *   and evaluates stencils and FFTs in float; the wall-normal tridiagonal
+ *   solves, the flow-rate reductions and the immersed-boundary coefficients
+ *   stay double.
+ *
+ * Grid (x streamwise periodic, y wall-normal bounded, z spanwise periodic):
+ *   nx, nz cells in the periodic directions; ny wall-normal FACES including
+ *   both box walls, so there are ny-1 cells in y.  Uniform spacings
+ *   dx = lx/nx, dz = lz/nz, dy = (y_hi-y_lo)/(ny-1) (Sec. 2.1 of the paper:
+ *   staggered grid, pressure at cell centres, velocity components at faces).
+ * Field layout: [j][k][i], i (x) fastest, shape (ny-1, nz, nx):
+ *   p at cell centres, u at west faces, w at back faces, v at south faces
+ *   (row j = face j; face ny-1 is the north box wall and is implicitly 0;
+ *   face 0 is the south box wall and is always 0).
+ * SDF layout (signed distance to the solid, > 0 in the fluid, FP64):
+ *   sdf_u (ny+1, nz, nx): rows j = -1..ny-1 at u positions (two ghost rows
+ *                         outside the box, used only for wall distances)
+ *   sdf_v (ny,   nz, nx): faces j = 0..ny-1 at v positions
+ *   sdf_w (ny+1, nz, nx): rows j = -1..ny-1 at w positions
+ */
+#ifndef IBM_H
+#define IBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  IBM_OK = 0,
+  IBM_ERR_ARG = -1,      /* invalid argument / descriptor / size mismatch   */
+  IBM_ERR_OOM = -2,      /* device allocation failed                        */
+  IBM_ERR_DEVICE = -3,   /* a HIP runtime call or kernel launch failed      */
+  IBM_ERR_STATE = -4,    /* call out of order (e.g. step before geometry)   */
+  IBM_ERR_UNSTABLE = -5  /* NaN/Inf detected or CFL above sqrt(3)           */
+};
+
+enum { IBM_FP64 = 0, IBM_FP32_STORAGE = 1 };
+enum { IBM_CFR = 0, IBM_CPG = 1 };               /* constant flow rate / pressure gradient */
+enum { IBM_B_EXP = 0, IBM_B_EULER = 1, IBM_B_TAYLOR2 = 2 };
+
+typedef struct ibm_ctx* ibm_handle;
+
+/* One channel instance.  n_inst descriptors are passed to ibm_create_grid. */
+typedef struct {
+  int32_t nx, ny, nz;   /* nx even, nx/2 and nz with prime factors in {2,3,5}; ny >= 3 */
+  int32_t forcing;      /* IBM_CFR: hold the flow rate at q_target_or_pi;
+                           IBM_CPG: fixed mean pressure gradient Pi = q_target_or_pi
+                           (Pi enters the u-momentum equation as -Pi, Sec. 2.5 notation) */
+  int32_t b_mode;       /* coefficient B of the implicit IBM update, Sec. 2.4:
+                           IBM_B_EXP = exponential fit x/(e^x-1), Eq. (14);
+                           IBM_B_EULER = 1 (first order); IBM_B_TAYLOR2 = 1/(1+x/2) */
+  int32_t ibm;          /* 1: immersed-boundary correction on; 0: bare staircase */
+  double lx, lz, y_lo, y_hi;
+  double nu, dt;        /* kinematic viscosity (1/Re_bulk), fixed time step */
+  double q_target_or_pi;
+} ibm_grid_desc;
+
+typedef struct {
+  int64_t step;
+  double time;
+  double q;                     /* flow rate (1/nx) sum_{internal u} u dy dz */
+  double pi_last;               /* mean pressure gradient of the last substep */
+  double div_max_fullbox;       /* max |D u| after the last projection, before external
+                                   faces are reset (needs ibm_set_diagnostics(h, 1)) */
+  double div_max_internal_leak; /* max |D u| over internal pressure cells, current state */
+  double poisson_rel_residual;  /* ||D G phi - (rhs - mean)||_inf / ||rhs||_inf (diagnostics on) */
+  double rhs_mean_removed;      /* mean of the Poisson right-hand side removed by the gauge */
+  double ke;                    /* 1/2 sum |u|^2 dx dy dz */
+  double cfl_max;               /* max (|u|/dx + |v|/dy + |w|/dz) dt */
+  int64_t n_internal[3];        /* internal u, v, w points */
+  int64_t n_ibm[3];             /* points with lambda > 0 per component */
+  int64_t n_p_internal;         /* internal pressure cells */
+  int32_t nan_flag;             /* 1 if any field holds NaN/Inf */
+  int32_t reserved;
+} ibm_stats_t;
+
+/* Create n_inst channel instances (n_inst = 1 in this version) at the given
+ * precision, all work on hip_stream (a hipStream_t; NULL = default stream).
+ * Validates the descriptor (IBM_ERR_ARG), allocates device fields and the FFT
+ * and tridiagonal plans (IBM_ERR_OOM).  Fields start at zero. */
+int ibm_create_grid(const ibm_grid_desc* desc, int32_t n_inst, int32_t precision,
+                    void* hip_stream, ibm_handle* out);
+
+/* Staircase tagging and immersed-boundary coefficients from signed-distance
+ * samples (Sec. 2.2 Eqs. (5)-(7), Sec. 2.4 Eqs. (14)-(16), Sec. 3.3):
+ * per component grid, a point is internal iff s > 0; a pressure cell is
+ * internal iff one of its faces is internal; for each internal point the
+ * centre-weight correction lambda = nu * sum_arms (h - delta)/(delta h^2) over
+ * the arms whose neighbour is external, delta being the linear zero crossing
+ * of s along the arm (or the box wall when nearer); per RK stage k,
+ * x = lambda c_k dt, B(x) per b_mode, A = x + B.  sdf_* are FP64 device
+ * arrays in the SDF layout above; they may be freed on return.  Returns
+ * IBM_ERR_ARG if no pressure cell is internal.  Synchronises the stream. */
+int ibm_set_geometry(ibm_handle h, int32_t inst, const double* sdf_u, const double* sdf_v,
+                     const double* sdf_w);
+
+/* Copy a velocity/pressure state in (set) or out (get).  Arrays are device
+ * pointers of the storage type (double for IBM_FP64, float for
+ * IBM_FP32_STORAGE), field layout above.  set clears the stored explicit
+ * right-hand side of the previous stage.  Values at external points are
+ * taken as given; the next substep resets them. */
+int ibm_set_state(ibm_handle h, int32_t inst, const void* u, const void* v, const void* w,
+                  const void* p);
+int ibm_get_state(ibm_handle h, int32_t inst, void* u, void* v, void* w, void* p);
+
+/* Advance every instance by nsteps full RK3 steps (3 substeps each), Sec. 2.4
+ * Eq. (16) with the incremental pressure-correction projection of Sec. 2.1
+ * after every substep.  No host synchronisation.  IBM_ERR_STATE before
+ * ibm_set_geometry. */
+int ibm_step(ibm_handle h, int32_t nsteps);
+
+/* Stand-alone pressure solve on the full box: D G phi = rhs - mean(rhs),
+ * zero-mean phi (periodic x, z; homogeneous Neumann at the y box walls).
+ * rhs, phi: device arrays of the storage type, cell layout.  The removed
+ * mean is reported by the next ibm_stats(). */
+int ibm_solve_pressure(ibm_handle h, int32_t inst, const void* rhs, void* phi);
+
+/* Diagnostics of the current state (synchronises the stream). */
+int ibm_stats(ibm_handle h, int32_t inst, ibm_stats_t* out);
+
+/* 1: at the last substep of every ibm_step call, also measure the full-box
+ * divergence before external faces are reset and the Poisson residual. */
+int ibm_set_diagnostics(ibm_handle h, int32_t on);
+
+/* Inspection of the geometry preprocessing (synchronises the stream).
+ * tags: device uint8 array, cell layout; bit 0/1/2 = u/v/w internal,
+ * bit 3 = pressure internal, bit 4/5/6 = u/v/w carries an IBM correction.
+ * idx: device int32 [n_ibm[comp]] linear cell indices (ascending);
+ * lambda: device double [n]; coef: device double [3][n][2] = (B_k, 1/A_k). */
+int ibm_get_geometry(ibm_handle h, int32_t inst, uint8_t* tags, int64_t* n_ibm3);
+int ibm_get_ibm_list(ibm_handle h, int32_t inst, int32_t comp, int32_t* idx, double* lambda,
+                     double* coef);
+
+/* Per-kernel timing with HIP events recorded on the library's stream around
+ * every launch while enabled (kernel ids: see ibm_kernel_name).  read()
+ * synchronises, returns the accumulated milliseconds and launch counts for
+ * up to max kernels and resets the accumulators. */
+int ibm_profile(ibm_handle h, int32_t on);
+int ibm_profile_read(ibm_handle h, double* total_ms, int64_t* launches, int32_t max);
+const char* ibm_kernel_name(int32_t id);
+int32_t ibm_num_kernels(void);
+
+/* Bytes of device memory the library holds for this handle. */
+int64_t ibm_device_bytes(ibm_handle h);
+
+int ibm_destroy(ibm_handle h);
+const char* ibm_last_error(ibm_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IBM_H */

@@ -1,0 +1,657 @@
+// Host side of libibm: descriptor validation, device allocation, FFT / tridiagonal
+// plans, orchestration of the RK3 substeps on the caller's stream, and the C ABI
+// declared in include/ibm.h.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ibm.h"
+#include "ibm_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct Instance {
+  ibm_grid_desc d{};
+  GridParams g{};
+  FFTPlan px{}, pz{};
+  // device allocations
+  std::vector<DevBuf> bufs;
+  void *u = nullptr, *v = nullptr, *w = nullptr, *p = nullptr;
+  void *us = nullptr, *vs = nullptr, *ws = nullptr;
+  void *Hu = nullptr, *Hv = nullptr, *Hw = nullptr, *phi = nullptr, *spec = nullptr;
+  double* cp = nullptr;
+  double2* dp = nullptr;
+  uint8_t* tag = nullptr;
+  double* qpart = nullptr;
+  double* red_part = nullptr;
+  double* small = nullptr;         // S3[3] pi[1] pi_hist[2] mean[1] red_out[8] diag_out[4]
+  int32_t* itotal = nullptr;
+  double2* rtw = nullptr;
+  double *kx2 = nullptr, *kz2 = nullptr;
+  // immersed-boundary lists
+  DevBuf ibm_idx, ibm_coef, ibm_lam;
+  IbmLists L{};
+  int64_t n_int[3] = {0, 0, 0}, n_ibm[3] = {0, 0, 0}, n_pint = 0;
+  bool geom_ready = false;
+  bool diag_valid = false;
+  int64_t step = 0;
+  double time = 0.0;
+
+  double* S3() { return small; }
+  double* pi() { return small + 3; }
+  double* pi_hist() { return small + 4; }
+  double* mean() { return small + 6; }
+  double* red_out() { return small + 7; }
+  double* diag_out() { return small + 15; }
+};
+
+}  // namespace
+
+struct ibm_ctx {
+  int precision = IBM_FP64;
+  hipStream_t stream = nullptr;
+  std::vector<Instance> inst;
+  std::string err;
+  bool diag = false;
+  // profiling
+  bool prof = false;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> ev_kid;
+  size_t ev_used = 0;
+  double prof_ms[K_NUM_KERNELS] = {};
+  int64_t prof_n[K_NUM_KERNELS] = {};
+};
+
+namespace {
+
+int fail(ibm_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  g_last_error = msg;
+  return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                        \
+  do {                                                                                           \
+    hipError_t _e = (expr);                                                                      \
+    if (_e != hipSuccess)                                                                        \
+      return fail(ctx, IBM_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(_e));       \
+  } while (0)
+
+template <class F>
+hipError_t timed(ibm_ctx* c, int kid, F&& launch) {
+  if (c->prof && c->ev_used + 1 < c->ev.size()) {
+    hipEvent_t a = c->ev[c->ev_used], b = c->ev[c->ev_used + 1];
+    c->ev_kid[c->ev_used / 2] = kid;
+    c->ev_used += 2;
+    hipError_t e = hipEventRecord(a, c->stream);
+    if (e != hipSuccess) return e;
+    e = launch();
+    if (e != hipSuccess) return e;
+    return hipEventRecord(b, c->stream);
+  }
+  return launch();
+}
+
+bool factor_235(int n, int* radix, int* nst) {
+  int k = 0;
+  while (n % 4 == 0 && k < 20) { radix[k++] = 4; n /= 4; }
+  while (n % 2 == 0 && k < 20) { radix[k++] = 2; n /= 2; }
+  while (n % 3 == 0 && k < 20) { radix[k++] = 3; n /= 3; }
+  while (n % 5 == 0 && k < 20) { radix[k++] = 5; n /= 5; }
+  *nst = k;
+  return n == 1;
+}
+
+int dalloc(ibm_ctx* c, Instance& I, void** out, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) return fail(c, IBM_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  I.bufs.push_back({p, bytes});
+  *out = p;
+  return IBM_OK;
+}
+
+int make_plan(ibm_ctx* c, Instance& I, int n, FFTPlan* pl) {
+  pl->n = n;
+  if (!factor_235(n, pl->radix, &pl->nst))
+    return fail(c, IBM_ERR_ARG, "FFT length " + std::to_string(n) + " has a prime factor outside {2,3,5}");
+  std::vector<double2> t64(n);
+  std::vector<float2> t32(n);
+  for (int m = 0; m < n; ++m) {
+    const double a = 2.0 * M_PI * (double)m / (double)n;
+    t64[m] = make_double2(std::cos(a), -std::sin(a));
+    t32[m] = make_float2((float)t64[m].x, (float)t64[m].y);
+  }
+  void *d64, *d32;
+  int rc;
+  if ((rc = dalloc(c, I, &d64, n * sizeof(double2)))) return rc;
+  if ((rc = dalloc(c, I, &d32, n * sizeof(float2)))) return rc;
+  HIPCHK(c, hipMemcpy(d64, t64.data(), n * sizeof(double2), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(d32, t32.data(), n * sizeof(float2), hipMemcpyHostToDevice));
+  pl->tw64 = (const double2*)d64;
+  pl->tw32 = (const float2*)d32;
+  return IBM_OK;
+}
+
+int validate(ibm_ctx* c, const ibm_grid_desc& d) {
+  if (d.nx < 2 || (d.nx & 1)) return fail(c, IBM_ERR_ARG, "nx must be even and >= 2");
+  if (d.nz < 1) return fail(c, IBM_ERR_ARG, "nz must be >= 1");
+  if (d.ny < 3) return fail(c, IBM_ERR_ARG, "ny (wall-normal faces) must be >= 3");
+  if (d.nx > 1024 || d.nz > 1024) return fail(c, IBM_ERR_ARG, "nx and nz are limited to 1024");
+  int r[20], ns;
+  if (!factor_235(d.nx / 2, r, &ns) || !factor_235(d.nz, r, &ns))
+    return fail(c, IBM_ERR_ARG, "nx/2 and nz must have prime factors in {2,3,5}");
+  const double cells = (double)d.nx * (double)(d.ny - 1) * (double)d.nz;
+  if (cells * 3.0 > 2.0e9) return fail(c, IBM_ERR_ARG, "grid too large for 32-bit cell indexing");
+  if (!(d.dt > 0.0) || !(d.nu > 0.0)) return fail(c, IBM_ERR_ARG, "dt and nu must be > 0");
+  if (!(d.lx > 0.0) || !(d.lz > 0.0) || !(d.y_hi > d.y_lo)) return fail(c, IBM_ERR_ARG, "invalid box extents");
+  if (d.forcing != IBM_CFR && d.forcing != IBM_CPG) return fail(c, IBM_ERR_ARG, "invalid forcing");
+  if (d.b_mode < 0 || d.b_mode > 2) return fail(c, IBM_ERR_ARG, "invalid b_mode");
+  return IBM_OK;
+}
+
+int init_instance(ibm_ctx* c, Instance& I, const ibm_grid_desc& d) {
+  I.d = d;
+  GridParams& g = I.g;
+  g.nx = d.nx;
+  g.ny1 = d.ny - 1;
+  g.nz = d.nz;
+  g.nhalf = d.nx / 2;
+  g.mh = d.nx / 2 + 1;
+  g.nrows = g.ny1 * g.nz;
+  g.nmodes = g.nz * g.mh;
+  g.ncell = (int64_t)g.nx * g.ny1 * g.nz;
+  g.dx = d.lx / d.nx;
+  g.dz = d.lz / d.nz;
+  g.dy = (d.y_hi - d.y_lo) / (d.ny - 1);
+  g.idx = 1.0 / g.dx;
+  g.idy = 1.0 / g.dy;
+  g.idz = 1.0 / g.dz;
+  g.idx2 = 1.0 / (g.dx * g.dx);
+  g.idy2 = 1.0 / (g.dy * g.dy);
+  g.idz2 = 1.0 / (g.dz * g.dz);
+  g.nu = d.nu;
+  g.dt = d.dt;
+  int rc;
+  if ((rc = make_plan(c, I, g.nhalf, &I.px))) return rc;
+  if ((rc = make_plan(c, I, g.nz, &I.pz))) return rc;
+  const size_t ts = (c->precision == IBM_FP64) ? sizeof(double) : sizeof(float);
+  const size_t fb = (size_t)g.ncell * ts;
+  void** fields[] = {&I.u, &I.v, &I.w, &I.p, &I.us, &I.vs, &I.ws, &I.Hu, &I.Hv, &I.Hw, &I.phi};
+  for (void** f : fields) {
+    if ((rc = dalloc(c, I, f, fb))) return rc;
+    HIPCHK(c, hipMemsetAsync(*f, 0, fb, c->stream));
+  }
+  const size_t nspec = (size_t)g.ny1 * g.nmodes;
+  if ((rc = dalloc(c, I, &I.spec, nspec * 2 * ts))) return rc;
+  if ((rc = dalloc(c, I, (void**)&I.cp, nspec * sizeof(double)))) return rc;
+  if ((rc = dalloc(c, I, (void**)&I.dp, nspec * sizeof(double2)))) return rc;
+  if ((rc = dalloc(c, I, (void**)&I.tag, (size_t)g.ncell))) return rc;
+  HIPCHK(c, hipMemsetAsync(I.tag, 0, (size_t)g.ncell, c->stream));
+  const size_t mom_blocks = (size_t)((g.nx + 63) / 64) * ((g.nz + 3) / 4) * g.ny1;
+  const size_t lst_blocks = (size_t)((3 * g.ncell + 255) / 256);
+  if ((rc = dalloc(c, I, (void**)&I.qpart, (mom_blocks + lst_blocks + 1) * sizeof(double)))) return rc;
+  const size_t cell_blocks = (size_t)((g.ncell + 255) / 256);
+  const size_t red_n = std::max(mom_blocks * 6, (cell_blocks + lst_blocks) * 4) + 16;
+  if ((rc = dalloc(c, I, (void**)&I.red_part, red_n * sizeof(double)))) return rc;
+  if ((rc = dalloc(c, I, (void**)&I.small, 32 * sizeof(double)))) return rc;
+  HIPCHK(c, hipMemsetAsync(I.small, 0, 32 * sizeof(double), c->stream));
+  if ((rc = dalloc(c, I, (void**)&I.itotal, 16 * sizeof(int32_t)))) return rc;
+  // real-FFT unpacking twiddles e^{-2 pi i m/nx}, m = 0..nx/2, and modified wavenumbers
+  std::vector<double2> rt(g.mh);
+  for (int m = 0; m < g.mh; ++m) {
+    const double a = 2.0 * M_PI * (double)m / (double)g.nx;
+    rt[m] = make_double2(std::cos(a), -std::sin(a));
+  }
+  std::vector<double> kx(g.mh), kz(g.nz);
+  for (int m = 0; m < g.mh; ++m) {
+    const double s = std::sin(M_PI * m / g.nx);
+    kx[m] = (4.0 / (g.dx * g.dx)) * (s * s);
+  }
+  for (int n = 0; n < g.nz; ++n) {
+    const double s = std::sin(M_PI * n / g.nz);
+    kz[n] = (4.0 / (g.dz * g.dz)) * (s * s);
+  }
+  if ((rc = dalloc(c, I, (void**)&I.rtw, g.mh * sizeof(double2)))) return rc;
+  if ((rc = dalloc(c, I, (void**)&I.kx2, g.mh * sizeof(double)))) return rc;
+  if ((rc = dalloc(c, I, (void**)&I.kz2, g.nz * sizeof(double)))) return rc;
+  HIPCHK(c, hipMemcpy(I.rtw, rt.data(), g.mh * sizeof(double2), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(I.kx2, kx.data(), g.mh * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(I.kz2, kz.data(), g.nz * sizeof(double), hipMemcpyHostToDevice));
+  return IBM_OK;
+}
+
+template <typename T>
+Fields<T> fields_of(Instance& I) {
+  Fields<T> f;
+  f.u = (T*)I.u; f.v = (T*)I.v; f.w = (T*)I.w; f.p = (T*)I.p;
+  f.us = (T*)I.us; f.vs = (T*)I.vs; f.ws = (T*)I.ws;
+  f.Hu = (T*)I.Hu; f.Hv = (T*)I.Hv; f.Hw = (T*)I.Hw;
+  f.phi = (T*)I.phi;
+  f.spec = (cplx<T>*)I.spec;
+  f.tag = I.tag;
+  return f;
+}
+
+#define RUNK(ctx, kid, expr)                                                                     \
+  do {                                                                                           \
+    hipError_t _e = timed(ctx, kid, [&]() { return (expr); });                                   \
+    if (_e != hipSuccess)                                                                        \
+      return fail(ctx, IBM_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(_e));       \
+  } while (0)
+
+// Pressure solve of the current right-hand side: forward FFTs, tridiagonal, inverse FFTs.
+template <typename T>
+int poisson(ibm_ctx* c, Instance& I, Fields<T>& f, T* phi_out) {
+  const GridParams& g = I.g;
+  RUNK(c, K_FFTZ_FWD, launch_fftz<T>(g, f.spec, I.pz, -1, c->stream));
+  RUNK(c, K_TRI, launch_tri<T>(g, f.spec, I.kx2, I.kz2, I.cp, I.dp, I.mean(), c->stream));
+  RUNK(c, K_FFTZ_INV, launch_fftz<T>(g, f.spec, I.pz, +1, c->stream));
+  RUNK(c, K_IFFTX, launch_ifftx<T>(g, f.spec, phi_out, I.px, I.rtw, c->stream));
+  return IBM_OK;
+}
+
+template <typename T>
+int run_steps(ibm_ctx* c, Instance& I, int nsteps) {
+  const GridParams& g = I.g;
+  Fields<T> f = fields_of<T>(I);
+  const double scale = g.dy * g.dz / g.nx;
+  for (int s = 0; s < nsteps; ++s) {
+    for (int k = 0; k < 3; ++k) {
+      StageConsts sc;
+      sc.ak_dt = rk_a(k) * g.dt;
+      sc.bk_dt = rk_b(k) * g.dt;
+      sc.ck_dt = rk_c(k) * g.dt;
+      sc.stage = k;
+      sc.use_hold = (k > 0);
+      sc.write_h = (k < 2);
+      int nq1 = 0, nq2 = 0;
+      RUNK(c, K_MOMENTUM, launch_momentum<T>(g, f, sc, I.qpart, &nq1, c->stream));
+      if (I.L.n_total > 0) RUNK(c, K_IBM_FIX, launch_ibm_fix<T>(g, f, I.L, k, I.qpart + nq1, &nq2, c->stream));
+      RUNK(c, K_CFR, launch_cfr(I.qpart, nq1 + nq2, scale, I.d.forcing, I.d.q_target_or_pi, I.S3(), k, I.pi(),
+                                I.pi_hist(), c->stream));
+      if (I.L.n_u > 0) RUNK(c, K_IBM_PI, launch_ibm_pi<T>(f, I.L, k, sc.ck_dt, I.pi(), c->stream));
+      RUNK(c, K_DIV_FFTX, launch_div_fftx<T>(g, f, I.px, I.rtw, sc.ck_dt, I.pi(), (const T*)nullptr, c->stream));
+      int rc = poisson<T>(c, I, f, f.phi);
+      if (rc) return rc;
+      if (c->diag && s == nsteps - 1 && k == 2) {
+        int np = 0;
+        RUNK(c, K_DIAG, launch_diag<T>(g, f, sc.ck_dt, I.pi(), I.mean(), I.red_part, &np, c->stream));
+        RUNK(c, K_DIAG, launch_reduce_final(I.red_part, np, 0, 3, I.diag_out(), c->stream));
+        I.diag_valid = true;
+      }
+      RUNK(c, K_CORRECT, launch_correct<T>(g, f, sc.ck_dt, I.pi(), c->stream));
+    }
+    I.step += 1;
+    I.time += g.dt;
+  }
+  return IBM_OK;
+}
+
+int count_mask(ibm_ctx* c, Instance& I, uint8_t mask, int32_t* blk, int nblk, int64_t* out) {
+  HIPCHK(c, launch_count_flags(I.tag, I.g.ncell, mask, blk, nblk, c->stream));
+  HIPCHK(c, launch_scan_counts(blk, nblk, I.itotal, c->stream));
+  int32_t tot = 0;
+  HIPCHK(c, hipMemcpyAsync(&tot, I.itotal, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  *out = tot;
+  return IBM_OK;
+}
+
+void free_buf(DevBuf& b) {
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+int set_geometry_impl(ibm_ctx* c, Instance& I, const double* su, const double* sv, const double* sw) {
+  const GridParams& g = I.g;
+  hipStream_t st = c->stream;
+  const size_t nc = (size_t)g.ncell;
+  double *lam_u = nullptr, *lam_v = nullptr, *lam_w = nullptr;
+  int32_t* blk = nullptr;
+  const int nblk = (int)((nc + 255) / 256);
+  auto cleanup = [&]() {
+    if (lam_u) (void)hipFree(lam_u);
+    if (lam_v) (void)hipFree(lam_v);
+    if (lam_w) (void)hipFree(lam_w);
+    if (blk) (void)hipFree(blk);
+  };
+  if (hipMalloc((void**)&lam_u, nc * 8) != hipSuccess || hipMalloc((void**)&lam_v, nc * 8) != hipSuccess ||
+      hipMalloc((void**)&lam_w, nc * 8) != hipSuccess || hipMalloc((void**)&blk, (nblk + 1) * 4) != hipSuccess) {
+    cleanup();
+    return fail(c, IBM_ERR_OOM, "geometry temporaries");
+  }
+  int rc = IBM_OK;
+  do {
+    hipError_t e = timed(c, K_GEOM, [&]() {
+      return launch_geom_lambda(g, su, sv, sw, I.d.ibm, I.tag, lam_u, lam_v, lam_w, st);
+    });
+    if (e == hipSuccess) e = launch_geom_ptag(g, I.tag, st);
+    if (e != hipSuccess) { rc = fail(c, IBM_ERR_DEVICE, std::string("geometry: ") + hipGetErrorString(e)); break; }
+    const uint8_t imask[3] = {TAG_U, TAG_V, TAG_W};
+    const uint8_t bmask[3] = {TAG_UI, TAG_VI, TAG_WI};
+    for (int q = 0; q < 3 && !rc; ++q) rc = count_mask(c, I, imask[q], blk, nblk, &I.n_int[q]);
+    if (!rc) rc = count_mask(c, I, TAG_P, blk, nblk, &I.n_pint);
+    for (int q = 0; q < 3 && !rc; ++q) rc = count_mask(c, I, bmask[q], blk, nblk, &I.n_ibm[q]);
+    if (rc) break;
+    if (I.n_pint == 0) { rc = fail(c, IBM_ERR_ARG, "geometry has no fluid"); break; }
+    const int64_t ntot = I.n_ibm[0] + I.n_ibm[1] + I.n_ibm[2];
+    free_buf(I.ibm_idx);
+    free_buf(I.ibm_coef);
+    free_buf(I.ibm_lam);
+    const size_t nalloc = (size_t)std::max<int64_t>(ntot, 1);
+    if (hipMalloc(&I.ibm_idx.p, nalloc * 4) != hipSuccess || hipMalloc(&I.ibm_coef.p, nalloc * 3 * 16) != hipSuccess ||
+        hipMalloc(&I.ibm_lam.p, nalloc * 8) != hipSuccess) {
+      rc = fail(c, IBM_ERR_OOM, "immersed-boundary lists");
+      break;
+    }
+    I.ibm_idx.bytes = nalloc * 4;
+    I.ibm_coef.bytes = nalloc * 48;
+    I.ibm_lam.bytes = nalloc * 8;
+    int32_t* idx = (int32_t*)I.ibm_idx.p;
+    double2* coef = (double2*)I.ibm_coef.p;
+    double* lamo = (double*)I.ibm_lam.p;
+    const double* lam_dense[3] = {lam_u, lam_v, lam_w};
+    int64_t off = 0;
+    for (int q = 0; q < 3; ++q) {
+      // block offsets for this mask (scan), then compaction and coefficients
+      e = launch_count_flags(I.tag, g.ncell, bmask[q], blk, nblk, st);
+      if (e == hipSuccess) e = launch_scan_counts(blk, nblk, I.itotal, st);
+      if (e == hipSuccess) e = launch_compact(I.tag, g.ncell, bmask[q], blk, idx + off, nblk, st);
+      if (e == hipSuccess) e = launch_ibm_coef(idx, lam_dense[q], (int)I.n_ibm[q], I.d.dt, I.d.b_mode, lamo, coef,
+                                               (int)ntot, (int)off, st);
+      if (e != hipSuccess) { rc = fail(c, IBM_ERR_DEVICE, std::string("ibm lists: ") + hipGetErrorString(e)); break; }
+      off += I.n_ibm[q];
+    }
+    if (rc) break;
+    I.L.idx = idx;
+    I.L.coef = coef;
+    I.L.n_u = (int)I.n_ibm[0];
+    I.L.n_v = (int)I.n_ibm[1];
+    I.L.n_w = (int)I.n_ibm[2];
+    I.L.n_total = (int)ntot;
+    int np = 0;
+    e = launch_s_k(g, I.tag, I.L, I.d.dt, I.red_part, &np, st);
+    if (e == hipSuccess) e = launch_s_k_final(I.red_part, np, I.d.dt * g.dy * g.dz / g.nx, I.S3(), st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) { rc = fail(c, IBM_ERR_DEVICE, std::string("S_k: ") + hipGetErrorString(e)); break; }
+    I.geom_ready = true;
+    I.diag_valid = false;
+  } while (0);
+  cleanup();
+  return rc;
+}
+
+int check_inst(ibm_ctx* c, int32_t inst) {
+  if (!c) return fail(nullptr, IBM_ERR_ARG, "null handle");
+  if (inst < 0 || inst >= (int32_t)c->inst.size()) return fail(c, IBM_ERR_ARG, "instance index out of range");
+  return IBM_OK;
+}
+
+}  // namespace
+
+// =======================================================================================
+// C ABI
+// =======================================================================================
+extern "C" {
+
+int ibm_create_grid(const ibm_grid_desc* desc, int32_t n_inst, int32_t precision, void* hip_stream,
+                    ibm_handle* out) {
+  if (!desc || !out) return fail(nullptr, IBM_ERR_ARG, "null argument");
+  *out = nullptr;
+  if (n_inst != 1) return fail(nullptr, IBM_ERR_ARG, "this version supports n_inst = 1");
+  if (precision != IBM_FP64 && precision != IBM_FP32_STORAGE) return fail(nullptr, IBM_ERR_ARG, "invalid precision");
+  ibm_ctx* c = new (std::nothrow) ibm_ctx();
+  if (!c) return fail(nullptr, IBM_ERR_OOM, "host allocation");
+  c->precision = precision;
+  c->stream = (hipStream_t)hip_stream;
+  int rc = validate(c, desc[0]);
+  if (!rc) {
+    c->inst.resize(1);
+    rc = init_instance(c, c->inst[0], desc[0]);
+  }
+  if (!rc) {
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) rc = fail(c, IBM_ERR_DEVICE, hipGetErrorString(e));
+  }
+  if (rc) {
+    ibm_destroy(c);
+    return rc;
+  }
+  *out = c;
+  return IBM_OK;
+}
+
+int ibm_set_geometry(ibm_handle h, int32_t inst, const double* sdf_u, const double* sdf_v, const double* sdf_w) {
+  int rc = check_inst(h, inst);
+  if (rc) return rc;
+  if (!sdf_u || !sdf_v || !sdf_w) return fail(h, IBM_ERR_ARG, "null SDF pointer");
+  return set_geometry_impl(h, h->inst[inst], sdf_u, sdf_v, sdf_w);
+}
+
+int ibm_set_state(ibm_handle h, int32_t inst, const void* u, const void* v, const void* w, const void* p) {
+  int rc = check_inst(h, inst);
+  if (rc) return rc;
+  Instance& I = h->inst[inst];
+  const size_t fb = (size_t)I.g.ncell * (h->precision == IBM_FP64 ? 8 : 4);
+  const void* src[4] = {u, v, w, p};
+  void* dst[4] = {I.u, I.v, I.w, I.p};
+  for (int q = 0; q < 4; ++q) {
+    if (!src[q]) return fail(h, IBM_ERR_ARG, "null state pointer");
+    HIPCHK(h, hipMemcpyAsync(dst[q], src[q], fb, hipMemcpyDeviceToDevice, h->stream));
+  }
+  I.diag_valid = false;
+  return IBM_OK;
+}
+
+int ibm_get_state(ibm_handle h, int32_t inst, void* u, void* v, void* w, void* p) {
+  int rc = check_inst(h, inst);
+  if (rc) return rc;
+  Instance& I = h->inst[inst];
+  const size_t fb = (size_t)I.g.ncell * (h->precision == IBM_FP64 ? 8 : 4);
+  void* dst[4] = {u, v, w, p};
+  const void* src[4] = {I.u, I.v, I.w, I.p};
+  for (int q = 0; q < 4; ++q) {
+    if (!dst[q]) continue;
+    HIPCHK(h, hipMemcpyAsync(dst[q], src[q], fb, hipMemcpyDeviceToDevice, h->stream));
+  }
+  return IBM_OK;
+}
+
+int ibm_step(ibm_handle h, int32_t nsteps) {
+  if (!h) return fail(nullptr, IBM_ERR_ARG, "null handle");
+  if (nsteps < 0) return fail(h, IBM_ERR_ARG, "nsteps < 0");
+  for (Instance& I : h->inst) {
+    if (!I.geom_ready) return fail(h, IBM_ERR_STATE, "ibm_step before ibm_set_geometry");
+    const int rc = (h->precision == IBM_FP64) ? run_steps<double>(h, I, nsteps) : run_steps<float>(h, I, nsteps);
+    if (rc) return rc;
+  }
+  return IBM_OK;
+}
+
+int ibm_solve_pressure(ibm_handle h, int32_t inst, const void* rhs, void* phi) {
+  int rc = check_inst(h, inst);
+  if (rc) return rc;
+  if (!rhs || !phi) return fail(h, IBM_ERR_ARG, "null pointer");
+  Instance& I = h->inst[inst];
+  if (h->precision == IBM_FP64) {
+    Fields<double> f = fields_of<double>(I);
+    RUNK(h, K_DIV_FFTX, launch_div_fftx<double>(I.g, f, I.px, I.rtw, 1.0, I.pi(), (const double*)rhs, h->stream));
+    return poisson<double>(h, I, f, (double*)phi);
+  }
+  Fields<float> f = fields_of<float>(I);
+  RUNK(h, K_DIV_FFTX, launch_div_fftx<float>(I.g, f, I.px, I.rtw, 1.0, I.pi(), (const float*)rhs, h->stream));
+  return poisson<float>(h, I, f, (float*)phi);
+}
+
+int ibm_set_diagnostics(ibm_handle h, int32_t on) {
+  if (!h) return fail(nullptr, IBM_ERR_ARG, "null handle");
+  h->diag = on != 0;
+  return IBM_OK;
+}
+
+int ibm_stats(ibm_handle h, int32_t inst, ibm_stats_t* out) {
+  int rc = check_inst(h, inst);
+  if (rc) return rc;
+  if (!out) return fail(h, IBM_ERR_ARG, "null output");
+  Instance& I = h->inst[inst];
+  const GridParams& g = I.g;
+  int np = 0;
+  if (h->precision == IBM_FP64) {
+    RUNK(h, K_STATS, launch_stats<double>(g, fields_of<double>(I), I.red_part, &np, h->stream));
+  } else {
+    RUNK(h, K_STATS, launch_stats<float>(g, fields_of<float>(I), I.red_part, &np, h->stream));
+  }
+  RUNK(h, K_STATS, launch_reduce_final(I.red_part, np, 3, 3, I.red_out(), h->stream));
+  double host[32];
+  HIPCHK(h, hipMemcpyAsync(host, I.small, sizeof(host), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  const double* ro = host + 7;
+  const double* dg = host + 15;
+  memset(out, 0, sizeof(*out));
+  out->step = I.step;
+  out->time = I.time;
+  out->q = ro[0] * g.dy * g.dz / g.nx;
+  out->pi_last = host[4];
+  out->ke = 0.5 * ro[1] * g.dx * g.dy * g.dz;
+  out->nan_flag = ro[2] > 0.0 ? 1 : 0;
+  out->cfl_max = ro[3];
+  out->div_max_internal_leak = ro[4];
+  out->rhs_mean_removed = host[6];
+  if (I.diag_valid) {
+    out->div_max_fullbox = dg[0];
+    out->poisson_rel_residual = dg[2] > 0.0 ? dg[1] / dg[2] : 0.0;
+  } else {
+    out->div_max_fullbox = -1.0;
+    out->poisson_rel_residual = -1.0;
+  }
+  for (int q = 0; q < 3; ++q) {
+    out->n_internal[q] = I.n_int[q];
+    out->n_ibm[q] = I.n_ibm[q];
+  }
+  out->n_p_internal = I.n_pint;
+  if (out->nan_flag) return fail(h, IBM_ERR_UNSTABLE, "NaN/Inf in the state");
+  if (out->cfl_max > std::sqrt(3.0)) return fail(h, IBM_ERR_UNSTABLE, "CFL above sqrt(3)");
+  return IBM_OK;
+}
+
+int ibm_get_geometry(ibm_handle h, int32_t inst, uint8_t* tags, int64_t* n_ibm3) {
+  int rc = check_inst(h, inst);
+  if (rc) return rc;
+  Instance& I = h->inst[inst];
+  if (!I.geom_ready) return fail(h, IBM_ERR_STATE, "no geometry");
+  if (tags) HIPCHK(h, hipMemcpyAsync(tags, I.tag, (size_t)I.g.ncell, hipMemcpyDeviceToDevice, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (n_ibm3)
+    for (int q = 0; q < 3; ++q) n_ibm3[q] = I.n_ibm[q];
+  return IBM_OK;
+}
+
+int ibm_get_ibm_list(ibm_handle h, int32_t inst, int32_t comp, int32_t* idx, double* lambda, double* coef) {
+  int rc = check_inst(h, inst);
+  if (rc) return rc;
+  Instance& I = h->inst[inst];
+  if (!I.geom_ready) return fail(h, IBM_ERR_STATE, "no geometry");
+  if (comp < 0 || comp > 2) return fail(h, IBM_ERR_ARG, "comp must be 0, 1 or 2");
+  const int64_t off = (comp >= 1 ? I.n_ibm[0] : 0) + (comp >= 2 ? I.n_ibm[1] : 0);
+  const int64_t n = I.n_ibm[comp];
+  const int64_t ntot = I.L.n_total;
+  if (n > 0) {
+    if (idx)
+      HIPCHK(h, hipMemcpyAsync(idx, (int32_t*)I.ibm_idx.p + off, n * 4, hipMemcpyDeviceToDevice, h->stream));
+    if (lambda)
+      HIPCHK(h, hipMemcpyAsync(lambda, (double*)I.ibm_lam.p + off, n * 8, hipMemcpyDeviceToDevice, h->stream));
+    if (coef)
+      for (int k = 0; k < 3; ++k)
+        HIPCHK(h, hipMemcpyAsync(coef + (size_t)k * n * 2, (double2*)I.ibm_coef.p + k * ntot + off, n * 16,
+                                 hipMemcpyDeviceToDevice, h->stream));
+  }
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return IBM_OK;
+}
+
+int ibm_profile(ibm_handle h, int32_t on) {
+  if (!h) return fail(nullptr, IBM_ERR_ARG, "null handle");
+  if (on && h->ev.empty()) {
+    const size_t n = 2 * 65536;
+    h->ev.resize(n);
+    h->ev_kid.resize(n / 2);
+    for (size_t e = 0; e < n; ++e) HIPCHK(h, hipEventCreate(&h->ev[e]));
+  }
+  h->prof = on != 0;
+  return IBM_OK;
+}
+
+int ibm_profile_read(ibm_handle h, double* total_ms, int64_t* launches, int32_t max) {
+  if (!h) return fail(nullptr, IBM_ERR_ARG, "null handle");
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  for (size_t e = 0; e + 1 < h->ev_used; e += 2) {
+    float ms = 0.f;
+    HIPCHK(h, hipEventElapsedTime(&ms, h->ev[e], h->ev[e + 1]));
+    const int kid = h->ev_kid[e / 2];
+    h->prof_ms[kid] += ms;
+    h->prof_n[kid] += 1;
+  }
+  h->ev_used = 0;
+  for (int k = 0; k < K_NUM_KERNELS && k < max; ++k) {
+    if (total_ms) total_ms[k] = h->prof_ms[k];
+    if (launches) launches[k] = h->prof_n[k];
+    h->prof_ms[k] = 0.0;
+    h->prof_n[k] = 0;
+  }
+  return IBM_OK;
+}
+
+const char* ibm_kernel_name(int32_t id) {
+  static const char* names[K_NUM_KERNELS] = {"momentum", "ibm_fix", "cfr", "ibm_pi", "div_fftx", "fftz_fwd",
+                                             "tri", "fftz_inv", "ifftx", "correct", "diag", "stats", "geom",
+                                             "copy"};
+  if (id < 0 || id >= K_NUM_KERNELS) return "unknown";
+  return names[id];
+}
+
+int32_t ibm_num_kernels(void) { return K_NUM_KERNELS; }
+
+int64_t ibm_device_bytes(ibm_handle h) {
+  if (!h) return 0;
+  int64_t b = 0;
+  for (Instance& I : h->inst) {
+    for (auto& x : I.bufs) b += (int64_t)x.bytes;
+    b += I.ibm_idx.bytes + I.ibm_coef.bytes + I.ibm_lam.bytes;
+  }
+  return b;
+}
+
+int ibm_destroy(ibm_handle h) {
+  if (!h) return IBM_OK;
+  (void)hipStreamSynchronize(h->stream);
+  for (Instance& I : h->inst) {
+    for (auto& x : I.bufs) (void)hipFree(x.p);
+    I.bufs.clear();
+    free_buf(I.ibm_idx);
+    free_buf(I.ibm_coef);
+    free_buf(I.ibm_lam);
+  }
+  for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+  delete h;
+  return IBM_OK;
+}
+
+const char* ibm_last_error(ibm_handle h) {
+  if (h) return h->err.c_str();
+  return g_last_error.c_str();
+}
+
+}  // extern "C"

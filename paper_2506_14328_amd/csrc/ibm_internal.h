@@ -1,0 +1,200 @@
+// Internal declarations shared by the HIP translation units of libibm.
+// Device code targets gfx950 (CDNA4, 64-wide wavefronts) only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define IBM_WAVE 64
+
+// Tag bits (one byte per cell, cell layout [j][k][i]).
+enum : uint8_t {
+  TAG_U = 1u << 0,   // u (west face) internal
+  TAG_V = 1u << 1,   // v (south face) internal
+  TAG_W = 1u << 2,   // w (back face) internal
+  TAG_P = 1u << 3,   // pressure cell internal
+  TAG_UI = 1u << 4,  // u carries an immersed-boundary correction (lambda > 0)
+  TAG_VI = 1u << 5,
+  TAG_WI = 1u << 6,
+};
+
+// Kernel ids (profiling).
+enum KernelId {
+  K_MOMENTUM = 0, K_IBM_FIX, K_CFR, K_IBM_PI, K_DIV_FFTX, K_FFTZ_FWD, K_TRI, K_FFTZ_INV,
+  K_IFFTX, K_CORRECT, K_DIAG, K_STATS, K_GEOM, K_COPY, K_NUM_KERNELS
+};
+
+template <typename T>
+struct cplx {
+  T x, y;
+};
+
+// Geometry and constants of one instance, passed to kernels by value.
+struct GridParams {
+  int nx, ny1, nz;      // cells per direction (ny1 = ny-1)
+  int mh;               // nx/2 + 1 retained x modes
+  int nhalf;            // nx/2 (length of the packed complex x transform)
+  int nrows;            // ny1*nz rows of nx points
+  int nmodes;           // nz*mh Fourier modes per y plane
+  int64_t ncell;        // nx*ny1*nz
+  double dx, dy, dz;
+  double idx, idy, idz;
+  double idx2, idy2, idz2;
+  double nu, dt;
+};
+
+// Twiddle/stage description of one complex FFT length, resident on the device.
+struct FFTPlan {
+  int n;                // transform length
+  int nst;              // number of radix stages
+  int radix[20];        // radix of each stage (4, 2, 3 or 5)
+  const double2* tw64;  // exp(-2 pi i m / n), m = 0..n-1
+  const float2* tw32;
+};
+
+// ---------------------------------------------------------------------------------------
+// Small device helpers
+// ---------------------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> cconj(cplx<T> a) { return {a.x, -a.y}; }
+
+template <typename T> __device__ __forceinline__ cplx<T> twiddle(const FFTPlan& p, int m, int sign);
+template <>
+__device__ __forceinline__ cplx<double> twiddle<double>(const FFTPlan& p, int m, int sign) {
+  double2 t = p.tw64[m];
+  return {t.x, sign < 0 ? t.y : -t.y};
+}
+template <>
+__device__ __forceinline__ cplx<float> twiddle<float>(const FFTPlan& p, int m, int sign) {
+  float2 t = p.tw32[m];
+  return {t.x, sign < 0 ? t.y : -t.y};
+}
+
+// Wave-level and block-level reductions (fixed order: deterministic).
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = IBM_WAVE / 2; o > 0; o >>= 1) v += __shfl_down(v, o, IBM_WAVE);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = IBM_WAVE / 2; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, IBM_WAVE));
+  return v;
+}
+// Reduce over the block; result valid in thread 0.  smem holds >= blockDim/64 doubles.
+template <bool IS_MAX>
+__device__ __forceinline__ double block_reduce(double v, double* smem) {
+  const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+  const int nthr = blockDim.x * blockDim.y * blockDim.z;
+  const int lane = tid & (IBM_WAVE - 1), wid = tid / IBM_WAVE, nw = (nthr + IBM_WAVE - 1) / IBM_WAVE;
+  v = IS_MAX ? wave_max(v) : wave_sum(v);
+  __syncthreads();
+  if (lane == 0) smem[wid] = v;
+  __syncthreads();
+  double r = IS_MAX ? 0.0 : 0.0;
+  if (tid == 0) {
+    r = smem[0];
+    for (int w = 1; w < nw; ++w) r = IS_MAX ? fmax(r, smem[w]) : r + smem[w];
+  }
+  return r;
+}
+
+// ---------------------------------------------------------------------------------------
+// Launchers (one per kernel; defined in the .hip files).  All take the stream.
+// ---------------------------------------------------------------------------------------
+struct StageConsts {
+  double ak_dt, bk_dt, ck_dt;
+  int stage;      // 0, 1, 2
+  int use_hold;   // b_k != 0
+  int write_h;    // H needed by the next stage
+};
+
+struct IbmLists {
+  const int32_t* idx;      // [n_u | n_v | n_w] linear cell indices
+  const double2* coef;     // [3 stages][n_total] (B, 1/A)
+  int n_u, n_v, n_w, n_total;
+};
+
+template <typename T>
+struct Fields {
+  T *u, *v, *w, *p;          // state
+  T *us, *vs, *ws;           // predictor (u*)
+  T *Hu, *Hv, *Hw;           // explicit right-hand side of the previous stage
+  T* phi;                    // pressure increment
+  cplx<T>* spec;             // spectral work array (ny1, nz, mh)
+  const uint8_t* tag;
+};
+
+// step kernels
+template <typename T>
+hipError_t launch_momentum(const GridParams& g, const Fields<T>& f, const StageConsts& s, double* qpart,
+                           int* nqpart, hipStream_t st);
+template <typename T>
+hipError_t launch_ibm_fix(const GridParams& g, const Fields<T>& f, const IbmLists& L, int stage, double* qpart,
+                          int* nqpart, hipStream_t st);
+hipError_t launch_cfr(const double* qpart, int nq, double scale, int forcing, double q_target_or_pi,
+                      const double* S3, int stage, double* pi_out, double* pi_hist, hipStream_t st);
+template <typename T>
+hipError_t launch_ibm_pi(const Fields<T>& f, const IbmLists& L, int stage, double ck_dt, const double* pi,
+                         hipStream_t st);
+template <typename T>
+hipError_t launch_div_fftx(const GridParams& g, const Fields<T>& f, const FFTPlan& px, const double2* rtw,
+                           double ck_dt, const double* pi, const T* rhs_in, hipStream_t st);
+template <typename T>
+hipError_t launch_fftz(const GridParams& g, cplx<T>* spec, const FFTPlan& pz, int sign, hipStream_t st);
+template <typename T>
+hipError_t launch_tri(const GridParams& g, cplx<T>* spec, const double* kx2, const double* kz2,
+                      double* cp, double2* dp, double* mean_out, hipStream_t st);
+template <typename T>
+hipError_t launch_ifftx(const GridParams& g, const cplx<T>* spec, T* out, const FFTPlan& px,
+                        const double2* rtw, hipStream_t st);
+template <typename T>
+hipError_t launch_correct(const GridParams& g, const Fields<T>& f, double ck_dt, const double* pi,
+                          hipStream_t st);
+
+// diagnostics
+template <typename T>
+hipError_t launch_diag(const GridParams& g, const Fields<T>& f, double ck_dt, const double* pi,
+                       const double* mean, double* part, int* npart, hipStream_t st);
+template <typename T>
+hipError_t launch_stats(const GridParams& g, const Fields<T>& f, double* part, int* npart, hipStream_t st);
+hipError_t launch_reduce_final(const double* part, int npart, int nsum, int nmax, double* out,
+                               hipStream_t st);
+
+// geometry
+hipError_t launch_geom_lambda(const GridParams& g, const double* su, const double* sv, const double* sw,
+                              int ibm_on, uint8_t* tag, double* lam_u, double* lam_v, double* lam_w,
+                              hipStream_t st);
+hipError_t launch_geom_ptag(const GridParams& g, uint8_t* tag, hipStream_t st);
+hipError_t launch_count_flags(const uint8_t* tag, int64_t n, uint8_t mask, int32_t* blk_counts,
+                              int nblk, hipStream_t st);
+hipError_t launch_scan_counts(int32_t* blk_counts, int nblk, int32_t* total, hipStream_t st);
+hipError_t launch_compact(const uint8_t* tag, int64_t n, uint8_t mask, const int32_t* blk_offsets,
+                          int32_t* idx_out, int nblk, hipStream_t st);
+hipError_t launch_ibm_coef(const int32_t* idx, const double* lam_dense, int n, double dt, int b_mode,
+                           double* lam_out, double2* coef /* [3][n_total] at offset */, int n_total,
+                           int offset, hipStream_t st);
+hipError_t launch_s_k(const GridParams& g, const uint8_t* tag, const IbmLists& L, double dt, double* part,
+                      int* npart, hipStream_t st);
+hipError_t launch_s_k_final(const double* part, int npart, double scale, double* S3, hipStream_t st);
+
+// state copy helpers
+template <typename T>
+hipError_t launch_copy(const T* src, T* dst, int64_t n, hipStream_t st);
+
+// RK3 constants (Sec. 2.4, Eq. (17)); c_k = a_k + b_k.
+static const double RK_A[3] = {64.0 / 120.0, 50.0 / 120.0, 90.0 / 120.0};
+static const double RK_B[3] = {0.0, -34.0 / 120.0, -50.0 / 120.0};
+__host__ __device__ __forceinline__ double rk_a(int k) {
+  return k == 0 ? 64.0 / 120.0 : (k == 1 ? 50.0 / 120.0 : 90.0 / 120.0);
+}
+__host__ __device__ __forceinline__ double rk_b(int k) {
+  return k == 0 ? 0.0 / 120.0 : (k == 1 ? -34.0 / 120.0 : -50.0 / 120.0);
+}
+__host__ __device__ __forceinline__ double rk_c(int k) { return rk_a(k) + rk_b(k); }

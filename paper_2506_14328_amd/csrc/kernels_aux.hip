@@ -1,0 +1,439 @@
+// Geometry preprocessing (Sec. 2.2, Sec. 2.4, Sec. 3.3) and diagnostics.
+#include "ibm_internal.h"
+
+namespace {
+
+constexpr int BX = 64;
+constexpr int BZ = 4;
+
+__device__ __forceinline__ int wrap_p(int i, int n) { return (i + 1 == n) ? 0 : i + 1; }
+__device__ __forceinline__ int wrap_m(int i, int n) { return (i == 0) ? n - 1 : i - 1; }
+
+// Contribution nu (h - delta)/(delta h^2) of one arm whose neighbour is external
+// (Eq. (7) with d2(-1) = 1/h^2); delta = linear zero crossing of the signed distance
+// between the point and the neighbour, or the box wall distance when that is nearer.
+__device__ __forceinline__ double arm(double nu, double h, double sP, double sQ, bool extQ, double box) {
+  if (!extQ) return 0.0;
+  double delta = (sQ <= 0.0) ? h * sP / (sP - sQ) : INFINITY;
+  delta = fmin(delta, box);
+  return nu * (h - delta) / (delta * h * h);
+}
+
+// Tags of u, v, w and lambda per component at every cell (j, k, i).
+//  sdf_u, sdf_w: (ny+1, nz, nx), row jj = j+1 holds row j; sdf_v: (ny, nz, nx) faces.
+__global__ __launch_bounds__(256) void k_geom_lambda(GridParams g, const double* __restrict__ su,
+                                                    const double* __restrict__ sv, const double* __restrict__ sw,
+                                                    int ibm_on, uint8_t* __restrict__ tag,
+                                                    double* __restrict__ lam_u, double* __restrict__ lam_v,
+                                                    double* __restrict__ lam_w) {
+  const int i = blockIdx.x * BX + threadIdx.x;
+  const int k = blockIdx.y * BZ + threadIdx.y;
+  const int j = blockIdx.z;
+  if (i >= g.nx || k >= g.nz) return;
+  const int nx = g.nx, nz = g.nz, ny1 = g.ny1;
+  const int ip = wrap_p(i, nx), im = wrap_m(i, nx), kp = wrap_p(k, nz), km = wrap_m(k, nz);
+  const int plane = nx * nz;
+  const int c = (j * nz + k) * nx + i;
+  const double nu = g.nu, dx = g.dx, dy = g.dy, dz = g.dz;
+  uint8_t t = 0;
+  // u and w: sample row jj = j + 1; ghost rows jj = 0 and jj = ny are outside the box.
+  for (int comp = 0; comp < 3; comp += 2) {
+    const double* s = comp == 0 ? su : sw;
+    const int o = (j + 1) * plane + k * nx;
+    const double sP = s[o + i];
+    double lam = 0.0;
+    const bool in = sP > 0.0;
+    if (in) {
+      const double sxm = s[o + im], sxp = s[o + ip];
+      const double szm = s[o + (km - k) * nx + i], szp = s[o + (kp - k) * nx + i];
+      const double sdn = s[o - plane + i], sup = s[o + plane + i];
+      const bool gdn = (j == 0), gup = (j == ny1 - 1);
+      lam += arm(nu, dx, sP, sxm, sxm <= 0.0, INFINITY);
+      lam += arm(nu, dx, sP, sxp, sxp <= 0.0, INFINITY);
+      lam += arm(nu, dz, sP, szm, szm <= 0.0, INFINITY);
+      lam += arm(nu, dz, sP, szp, szp <= 0.0, INFINITY);
+      lam += arm(nu, dy, sP, sdn, gdn || sdn <= 0.0, gdn ? 0.5 * dy : INFINITY);
+      lam += arm(nu, dy, sP, sup, gup || sup <= 0.0, gup ? 0.5 * dy : INFINITY);
+      if (!ibm_on) lam = 0.0;
+      t |= (comp == 0) ? TAG_U : TAG_W;
+      if (lam > 0.0) t |= (comp == 0) ? TAG_UI : TAG_WI;
+    }
+    (comp == 0 ? lam_u : lam_w)[c] = lam;
+  }
+  // v on face j; faces 0 and ny-1 are the box walls.
+  {
+    const int o = j * plane + k * nx;
+    const double sP = sv[o + i];
+    double lam = 0.0;
+    if (j >= 1 && sP > 0.0) {
+      const double sxm = sv[o + im], sxp = sv[o + ip];
+      const double szm = sv[o + (km - k) * nx + i], szp = sv[o + (kp - k) * nx + i];
+      const double sdn = sv[o - plane + i], sup = sv[o + plane + i];
+      const bool wdn = (j - 1 == 0), wup = (j + 1 == ny1);
+      lam += arm(nu, dx, sP, sxm, sxm <= 0.0, INFINITY);
+      lam += arm(nu, dx, sP, sxp, sxp <= 0.0, INFINITY);
+      lam += arm(nu, dz, sP, szm, szm <= 0.0, INFINITY);
+      lam += arm(nu, dz, sP, szp, szp <= 0.0, INFINITY);
+      lam += arm(nu, dy, sP, sdn, wdn || sdn <= 0.0, wdn ? dy : INFINITY);
+      lam += arm(nu, dy, sP, sup, wup || sup <= 0.0, wup ? dy : INFINITY);
+      if (!ibm_on) lam = 0.0;
+      t |= TAG_V;
+      if (lam > 0.0) t |= TAG_VI;
+    }
+    lam_v[c] = lam;
+  }
+  tag[c] = t;
+}
+
+// Pressure cell internal iff one of its six faces is an internal velocity point.
+__global__ __launch_bounds__(256) void k_geom_ptag(GridParams g, uint8_t* __restrict__ tag) {
+  const int i = blockIdx.x * BX + threadIdx.x;
+  const int k = blockIdx.y * BZ + threadIdx.y;
+  const int j = blockIdx.z;
+  if (i >= g.nx || k >= g.nz) return;
+  const int nx = g.nx, nz = g.nz;
+  const int c = (j * nz + k) * nx + i;
+  const uint8_t t = tag[c];
+  const uint8_t te = tag[c - i + wrap_p(i, nx)] & TAG_U;
+  const uint8_t tn = (j + 1 < g.ny1) ? (tag[c + nx * nz] & TAG_V) : 0;
+  const uint8_t tt = tag[c + (wrap_p(k, nz) - k) * nx] & TAG_W;
+  const bool pin = (t & (TAG_U | TAG_V | TAG_W)) || te || tn || tt;
+  if (pin) tag[c] = t | TAG_P;
+}
+
+// Count cells whose tag has `mask` set, per block of 256 cells.
+__global__ __launch_bounds__(256) void k_count_flags(const uint8_t* __restrict__ tag, int64_t n, uint8_t mask,
+                                                    int32_t* __restrict__ counts) {
+  __shared__ int32_t wc[4];
+  const int64_t e = blockIdx.x * 256ll + threadIdx.x;
+  const bool f = (e < n) && (tag[e] & mask);
+  const uint64_t b = __ballot(f);
+  const int lane = threadIdx.x % IBM_WAVE, wid = threadIdx.x / IBM_WAVE;
+  if (lane == 0) wc[wid] = __popcll(b);
+  __syncthreads();
+  if (threadIdx.x == 0) counts[blockIdx.x] = wc[0] + wc[1] + wc[2] + wc[3];
+}
+
+// Exclusive scan of the block counts (single block, sequential chunks); total at the end.
+__global__ __launch_bounds__(1024) void k_scan_counts(int32_t* __restrict__ counts, int nblk,
+                                                     int32_t* __restrict__ total) {
+  __shared__ int32_t buf[1024];
+  __shared__ int32_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int base = 0; base < nblk; base += 1024) {
+    const int e = base + threadIdx.x;
+    const int32_t v = (e < nblk) ? counts[e] : 0;
+    buf[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+      const int32_t add = (threadIdx.x >= o) ? buf[threadIdx.x - o] : 0;
+      __syncthreads();
+      buf[threadIdx.x] += add;
+      __syncthreads();
+    }
+    if (e < nblk) counts[e] = carry + buf[threadIdx.x] - v;
+    __syncthreads();
+    if (threadIdx.x == 1023) carry += buf[1023];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) total[0] = carry;
+}
+
+// Write the ascending linear indices of flagged cells at their scanned offsets.
+__global__ __launch_bounds__(256) void k_compact(const uint8_t* __restrict__ tag, int64_t n, uint8_t mask,
+                                                const int32_t* __restrict__ offsets, int32_t* __restrict__ out) {
+  __shared__ int32_t wc[4];
+  const int64_t e = blockIdx.x * 256ll + threadIdx.x;
+  const bool f = (e < n) && (tag[e] & mask);
+  const uint64_t b = __ballot(f);
+  const int lane = threadIdx.x % IBM_WAVE, wid = threadIdx.x / IBM_WAVE;
+  if (lane == 0) wc[wid] = __popcll(b);
+  __syncthreads();
+  int base = offsets[blockIdx.x];
+  for (int w = 0; w < wid; ++w) base += wc[w];
+  const uint64_t below = (lane == 0) ? 0ull : (b & ((~0ull) >> (64 - lane)));
+  if (f) out[base + __popcll(below)] = (int32_t)e;
+}
+
+// lambda and per-stage (B, 1/A) of each immersed-boundary point (Eqs. (14)-(16)).
+__global__ __launch_bounds__(256) void k_ibm_coef(const int32_t* __restrict__ idx, const double* __restrict__ lam_dense,
+                                                 int n, double dt, int b_mode, double* __restrict__ lam_out,
+                                                 double2* __restrict__ coef, int n_total, int offset) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const double lam = lam_dense[idx[offset + e]];
+  lam_out[offset + e] = lam;
+  for (int k = 0; k < 3; ++k) {
+    const double ck = rk_c(k);
+    const double x = lam * ck * dt;
+    double B, A;
+    if (b_mode == 1) {          // implicit Euler: B = 1
+      B = 1.0;
+      A = 1.0 + x;
+    } else if (b_mode == 2) {   // reciprocal of the second-order Taylor expansion of 1/B
+      B = 1.0 / (1.0 + 0.5 * x);
+      A = x + B;
+    } else {                    // exponential fit B = x / (e^x - 1)
+      B = (x > 700.0) ? 0.0 : ((x > 0.0) ? x / expm1(x) : 1.0);
+      A = x + B;
+    }
+    coef[(size_t)k * n_total + offset + e] = make_double2(B, 1.0 / A);
+  }
+}
+
+// S_k partials: number of internal non-IBM u points (column 0) and sum over IBM u points
+// of 1/A_k (columns 1..3).  part layout: [block][4].
+__global__ __launch_bounds__(256) void k_s_cells(GridParams g, const uint8_t* __restrict__ tag,
+                                                double* __restrict__ part) {
+  __shared__ double red[4];
+  const int64_t e = blockIdx.x * 256ll + threadIdx.x;
+  double c = 0.0;
+  if (e < g.ncell) c = ((tag[e] & (TAG_U | TAG_UI)) == TAG_U) ? 1.0 : 0.0;
+  const double tot = block_reduce<false>(c, red);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x * 4 + 0] = tot;
+    part[blockIdx.x * 4 + 1] = 0.0;
+    part[blockIdx.x * 4 + 2] = 0.0;
+    part[blockIdx.x * 4 + 3] = 0.0;
+  }
+}
+__global__ __launch_bounds__(256) void k_s_list(IbmLists L, double* __restrict__ part) {
+  __shared__ double red[4];
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  for (int k = 0; k < 3; ++k) {
+    const double v = (e < L.n_u) ? L.coef[(size_t)k * L.n_total + e].y : 0.0;
+    const double tot = block_reduce<false>(v, red);
+    if (threadIdx.x == 0) part[blockIdx.x * 4 + 1 + k] = tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x * 4] = 0.0;
+}
+__global__ __launch_bounds__(1024) void k_s_final(const double* __restrict__ part, int npart, double scale,
+                                                 double* __restrict__ S3) {
+  __shared__ double red[16];
+  double acc[4];
+  for (int v = 0; v < 4; ++v) {
+    double s = 0.0;
+    for (int e = threadIdx.x; e < npart; e += blockDim.x) s += part[e * 4 + v];
+    acc[v] = block_reduce<false>(s, red);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < 3; ++k) {
+      const double ckdt = rk_c(k) * scale;   // scale carries dt dy dz / nx
+      S3[k] = (acc[0] + acc[1 + k]) * ckdt;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Diagnostics
+// ---------------------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ double fval(const T* a, int c) { return (double)a[c]; }
+
+// Full-box divergence after the projection and before external faces are reset, the
+// Poisson residual D G phi - (rhs - mean) and max |rhs|.  part: [block][3] (max).
+template <typename T>
+__global__ __launch_bounds__(256) void k_diag(GridParams g, Fields<T> f, double ck_dt, const double* __restrict__ pi,
+                                             const double* __restrict__ mean, double* __restrict__ part) {
+  __shared__ double red[4];
+  const int i = blockIdx.x * BX + threadIdx.x;
+  const int k = blockIdx.y * BZ + threadIdx.y;
+  const int j = blockIdx.z;
+  double dmax = 0.0, rmax = 0.0, hmax = 0.0;
+  if (i < g.nx && k < g.nz) {
+    const int nx = g.nx, nz = g.nz, plane = nx * nz;
+    const int ip = wrap_p(i, nx), im = wrap_m(i, nx), kp = wrap_p(k, nz), km = wrap_m(k, nz);
+    const int c = (j * nz + k) * nx + i;
+    const bool hasN = j + 1 < g.ny1, hasS = j > 0;
+    const double pk = pi[0] * ck_dt;
+    auto ust = [&](int cc) {
+      const uint8_t t = f.tag[cc];
+      return fval(f.us, cc) - (((t & (TAG_U | TAG_UI)) == TAG_U) ? pk : 0.0);
+    };
+    const double ph = fval(f.phi, c);
+    const double phe = fval(f.phi, c - i + ip), phw = fval(f.phi, c - i + im);
+    const double pht = fval(f.phi, c + (kp - k) * nx), phb = fval(f.phi, c + (km - k) * nx);
+    const double phn = hasN ? fval(f.phi, c + plane) : 0.0, phs = hasS ? fval(f.phi, c - plane) : 0.0;
+    // u* on the six faces
+    const double uw = ust(c), ue = ust(c - i + ip);
+    const double vs = fval(f.vs, c), vn = hasN ? fval(f.vs, c + plane) : 0.0;
+    const double wb = fval(f.ws, c), wt = fval(f.ws, c + (kp - k) * nx);
+    // gradients of phi on the faces (no flux through the box walls)
+    const double gxw = (ph - phw) * g.idx, gxe = (phe - ph) * g.idx;
+    const double gys = hasS ? (ph - phs) * g.idy : 0.0, gyn = hasN ? (phn - ph) * g.idy : 0.0;
+    const double gzb = (ph - phb) * g.idz, gzt = (pht - ph) * g.idz;
+    const double divs = (ue - uw) * g.idx + (vn - vs) * g.idy + (wt - wb) * g.idz;
+    const double rhs = divs / ck_dt;
+    const double dg = (gxe - gxw) * g.idx + (gyn - gys) * g.idy + (gzt - gzb) * g.idz;
+    const double unew_div = divs - ck_dt * dg;
+    dmax = fabs(unew_div);
+    rmax = fabs(dg - (rhs - mean[0]));
+    hmax = fabs(rhs);
+  }
+  const double a = block_reduce<true>(dmax, red);
+  __syncthreads();
+  const double b = block_reduce<true>(rmax, red);
+  __syncthreads();
+  const double cmax = block_reduce<true>(hmax, red);
+  if (threadIdx.x == 0 && threadIdx.y == 0) {
+    const int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    part[bid * 3 + 0] = a;
+    part[bid * 3 + 1] = b;
+    part[bid * 3 + 2] = cmax;
+  }
+}
+
+// State statistics. part: [block][6] = (sum u over internal u, sum |u|^2, nan count,
+//                                      max cfl, max |D u| over internal p, 0)
+template <typename T>
+__global__ __launch_bounds__(256) void k_stats(GridParams g, Fields<T> f, double* __restrict__ part) {
+  __shared__ double red[4];
+  const int i = blockIdx.x * BX + threadIdx.x;
+  const int k = blockIdx.y * BZ + threadIdx.y;
+  const int j = blockIdx.z;
+  double qs = 0.0, ke = 0.0, nan = 0.0, cfl = 0.0, leak = 0.0;
+  if (i < g.nx && k < g.nz) {
+    const int nx = g.nx, nz = g.nz, plane = nx * nz;
+    const int ip = wrap_p(i, nx), kp = wrap_p(k, nz);
+    const int c = (j * nz + k) * nx + i;
+    const uint8_t t = f.tag[c];
+    const double u = fval(f.u, c), v = fval(f.v, c), w = fval(f.w, c), p = fval(f.p, c);
+    if (t & TAG_U) qs = u;
+    ke = u * u + v * v + w * w;
+    nan = (isfinite(u) && isfinite(v) && isfinite(w) && isfinite(p)) ? 0.0 : 1.0;
+    cfl = (fabs(u) * g.idx + fabs(v) * g.idy + fabs(w) * g.idz) * g.dt;
+    if (t & TAG_P) {
+      const double ue = fval(f.u, c - i + ip);
+      const double vn = (j + 1 < g.ny1) ? fval(f.v, c + plane) : 0.0;
+      const double wt = fval(f.w, c + (kp - k) * nx);
+      leak = fabs((ue - u) * g.idx + (vn - v) * g.idy + (wt - w) * g.idz);
+    }
+  }
+  const double a = block_reduce<false>(qs, red);
+  __syncthreads();
+  const double b = block_reduce<false>(ke, red);
+  __syncthreads();
+  const double cc = block_reduce<false>(nan, red);
+  __syncthreads();
+  const double d = block_reduce<true>(isfinite(cfl) ? cfl : 1e300, red);
+  __syncthreads();
+  const double e = block_reduce<true>(isfinite(leak) ? leak : 1e300, red);
+  if (threadIdx.x == 0 && threadIdx.y == 0) {
+    const int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    double* o = part + bid * 6;
+    o[0] = a;
+    o[1] = b;
+    o[2] = cc;
+    o[3] = d;
+    o[4] = e;
+    o[5] = 0.0;
+  }
+}
+
+// Column-wise reduction of part[npart][nsum + nmax]: sums then maxima.  One block per column.
+__global__ __launch_bounds__(256) void k_reduce_final(const double* __restrict__ part, int npart, int nsum,
+                                                     int nmax, double* __restrict__ out) {
+  __shared__ double red[4];
+  const int col = blockIdx.x;
+  const int nc = nsum + nmax;
+  const bool ismax = col >= nsum;
+  double s = 0.0;
+  for (int e = threadIdx.x; e < npart; e += blockDim.x) {
+    const double v = part[(size_t)e * nc + col];
+    s = ismax ? fmax(s, v) : s + v;
+  }
+  const double r = ismax ? block_reduce<true>(s, red) : block_reduce<false>(s, red);
+  if (threadIdx.x == 0) out[col] = r;
+}
+
+}  // namespace
+
+static inline dim3 cell_grid(const GridParams& g) {
+  return dim3((g.nx + BX - 1) / BX, (g.nz + BZ - 1) / BZ, g.ny1);
+}
+
+hipError_t launch_geom_lambda(const GridParams& g, const double* su, const double* sv, const double* sw,
+                              int ibm_on, uint8_t* tag, double* lam_u, double* lam_v, double* lam_w,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_geom_lambda, cell_grid(g), dim3(BX, BZ), 0, st, g, su, sv, sw, ibm_on, tag, lam_u, lam_v,
+                     lam_w);
+  return hipGetLastError();
+}
+
+hipError_t launch_geom_ptag(const GridParams& g, uint8_t* tag, hipStream_t st) {
+  hipLaunchKernelGGL(k_geom_ptag, cell_grid(g), dim3(BX, BZ), 0, st, g, tag);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_flags(const uint8_t* tag, int64_t n, uint8_t mask, int32_t* blk_counts, int nblk,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_count_flags, dim3(nblk), dim3(256), 0, st, tag, n, mask, blk_counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_counts(int32_t* blk_counts, int nblk, int32_t* total, hipStream_t st) {
+  hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, blk_counts, nblk, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact(const uint8_t* tag, int64_t n, uint8_t mask, const int32_t* blk_offsets,
+                          int32_t* idx_out, int nblk, hipStream_t st) {
+  hipLaunchKernelGGL(k_compact, dim3(nblk), dim3(256), 0, st, tag, n, mask, blk_offsets, idx_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_ibm_coef(const int32_t* idx, const double* lam_dense, int n, double dt, int b_mode,
+                           double* lam_out, double2* coef, int n_total, int offset, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ibm_coef, dim3((n + 255) / 256), dim3(256), 0, st, idx, lam_dense, n, dt, b_mode, lam_out,
+                     coef, n_total, offset);
+  return hipGetLastError();
+}
+
+hipError_t launch_s_k(const GridParams& g, const uint8_t* tag, const IbmLists& L, double dt, double* part,
+                      int* npart, hipStream_t st) {
+  (void)dt;
+  const int nb1 = (int)((g.ncell + 255) / 256);
+  const int nb2 = (L.n_u + 255) / 256;
+  hipLaunchKernelGGL(k_s_cells, dim3(nb1), dim3(256), 0, st, g, tag, part);
+  if (nb2 > 0) hipLaunchKernelGGL(k_s_list, dim3(nb2), dim3(256), 0, st, L, part + (size_t)nb1 * 4);
+  *npart = nb1 + nb2;
+  return hipGetLastError();
+}
+
+hipError_t launch_s_k_final(const double* part, int npart, double scale, double* S3, hipStream_t st) {
+  hipLaunchKernelGGL(k_s_final, dim3(1), dim3(1024), 0, st, part, npart, scale, S3);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_diag(const GridParams& g, const Fields<T>& f, double ck_dt, const double* pi,
+                       const double* mean, double* part, int* npart, hipStream_t st) {
+  const dim3 grid = cell_grid(g);
+  hipLaunchKernelGGL(k_diag<T>, grid, dim3(BX, BZ), 0, st, g, f, ck_dt, pi, mean, part);
+  *npart = grid.x * grid.y * grid.z;
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_stats(const GridParams& g, const Fields<T>& f, double* part, int* npart, hipStream_t st) {
+  const dim3 grid = cell_grid(g);
+  hipLaunchKernelGGL(k_stats<T>, grid, dim3(BX, BZ), 0, st, g, f, part);
+  *npart = grid.x * grid.y * grid.z;
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_final(const double* part, int npart, int nsum, int nmax, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_final, dim3(nsum + nmax), dim3(256), 0, st, part, npart, nsum, nmax, out);
+  return hipGetLastError();
+}
+
+template hipError_t launch_diag<double>(const GridParams&, const Fields<double>&, double, const double*,
+                                        const double*, double*, int*, hipStream_t);
+template hipError_t launch_diag<float>(const GridParams&, const Fields<float>&, double, const double*,
+                                       const double*, double*, int*, hipStream_t);
+template hipError_t launch_stats<double>(const GridParams&, const Fields<double>&, double*, int*, hipStream_t);
+template hipError_t launch_stats<float>(const GridParams&, const Fields<float>&, double*, int*, hipStream_t);

@@ -1,0 +1,66 @@
+"""Shared helpers of the GPU parity tests (inputs from ibm_inputs, reference from the oracle)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import ibm_inputs as I
+from oracle.ibm_oracle import OGrid, Oracle
+
+
+def device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def to_dev(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device=device(), dtype=dtype)
+
+
+def rel_err(a, b):
+    return float(np.abs(np.asarray(a, dtype=np.float64) - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def case(name, **kw):
+    base = dict(
+        wavy_small=dict(nx=80, ny=13, nz=10, lx=2 * math.pi, lz=math.pi, y_lo=-1.2, y_hi=1.0, nu=1 / 800.0,
+                        dt=0.01, q_target_or_pi=2 * math.pi, seed=11, geometry="wavy",
+                        geo_params=(0.1, math.pi / 2)),
+        flat_small=dict(nx=16, ny=33, nz=8, lx=2 * math.pi, lz=math.pi, y_lo=-1.0, y_hi=1.0, nu=0.01,
+                        dt=0.02, q_target_or_pi=2 * math.pi, seed=1, geometry="flat", geo_params=(0.37,)),
+        ellip_small=dict(nx=96, ny=9, nz=12, lx=2 * math.pi, lz=math.pi, y_lo=-1.0, y_hi=1.0, nu=1 / 300.0,
+                         dt=0.005, q_target_or_pi=2 * math.pi, seed=4, geometry="ellipsoids",
+                         geo_params=(12,)),
+        minimal=dict(nx=2, ny=3, nz=1, lx=1.0, lz=1.0, y_lo=-1.0, y_hi=1.0, nu=0.1, dt=0.01,
+                     q_target_or_pi=1.0, seed=3, geometry="flat", geo_params=(0.2,)),
+        wavy_160=dict(nx=160, ny=9, nz=20, lx=2 * math.pi, lz=math.pi, y_lo=-1.2, y_hi=1.0, nu=1 / 1000.0,
+                      dt=0.004, q_target_or_pi=2 * math.pi, seed=5, geometry="wavy",
+                      geo_params=(0.12, math.pi / 2)),
+    )[name]
+    base.update(kw)
+    return I.Case(name=name, **base)
+
+
+def oracle_run(c, nsteps, ibm=True, state=None):
+    sdf = I.make_sdf(c)
+    if state is None:
+        u0, v0, w0 = I.make_initial(c, sdf)
+        p0 = np.zeros_like(u0)
+    else:
+        u0, v0, w0, p0 = state
+    o = Oracle(OGrid.from_case(c))
+    o.set_geometry(*sdf, ibm=ibm)
+    o.set_state(u0, v0, w0, p0)
+    o.step(nsteps)
+    return o, sdf, (u0, v0, w0, p0)
+
+
+def gpu_grid(c, sdf, state, precision="fp64", ibm=True):
+    from paper_2506_14328_amd import IbmGrid
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    g = IbmGrid.from_case(c, precision=precision, ibm=ibm)
+    g.set_geometry(*[to_dev(s) for s in sdf])
+    g.set_state(*[to_dev(a, dt) for a in state])
+    return g

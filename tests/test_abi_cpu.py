@@ -1,0 +1,90 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports every
+entry point declared in include/ibm.h, the ctypes structures match the C layout
+(compiled with gcc from the header), and invalid descriptors are rejected before
+any device work."""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ibm.h")
+LIB = os.path.join(ROOT, "paper_2506_14328_amd", "libibm.so")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(ibm_[a-z_0-9]+)\s*\(", txt)))
+
+
+needs_lib = pytest.mark.skipif(not os.path.exists(LIB), reason="libibm.so not built")
+
+
+@needs_lib
+def test_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    from paper_2506_14328_amd.ibm import EXPORTED
+    assert sorted(EXPORTED) == names
+
+
+def test_struct_layout_matches_c():
+    from paper_2506_14328_amd.ibm import IbmGridDesc, IbmStats
+    src = r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "ibm.h"
+#define OFF(T, f) printf(#T " " #f " %zu\n", offsetof(T, f))
+int main(void) {
+  printf("ibm_grid_desc size %zu\n", sizeof(ibm_grid_desc));
+  printf("ibm_stats_t size %zu\n", sizeof(ibm_stats_t));
+  OFF(ibm_grid_desc, nx); OFF(ibm_grid_desc, ibm); OFF(ibm_grid_desc, lx); OFF(ibm_grid_desc, q_target_or_pi);
+  OFF(ibm_stats_t, ke); OFF(ibm_stats_t, n_internal); OFF(ibm_stats_t, n_p_internal); OFF(ibm_stats_t, nan_flag);
+  return 0;
+}
+'''
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "l.c")
+        exe = os.path.join(d, "l")
+        open(c, "w").write(src)
+        subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
+        out = subprocess.check_output([exe], text=True).split("\n")
+    vals = {}
+    for line in out:
+        if line.strip():
+            t, f, v = line.split()
+            vals[(t, f)] = int(v)
+    assert vals[("ibm_grid_desc", "size")] == ctypes.sizeof(IbmGridDesc)
+    assert vals[("ibm_stats_t", "size")] == ctypes.sizeof(IbmStats)
+    for (t, f), v in vals.items():
+        if f == "size":
+            continue
+        cls = IbmGridDesc if t == "ibm_grid_desc" else IbmStats
+        assert getattr(cls, f).offset == v, (t, f)
+
+
+@needs_lib
+@pytest.mark.parametrize("bad", [
+    dict(nx=7), dict(nx=14), dict(nz=7), dict(ny=2), dict(dt=0.0), dict(nu=-1.0), dict(y_hi=-2.0),
+    dict(forcing=3), dict(b_mode=9), dict(nx=2048),
+])
+def test_invalid_descriptor_rejected(bad):
+    from paper_2506_14328_amd.ibm import IBM_ERR_ARG, IbmGridDesc
+    lib = ctypes.CDLL(LIB)
+    d = dict(nx=8, ny=5, nz=4, forcing=0, b_mode=0, ibm=1, lx=1.0, lz=1.0, y_lo=-1.0, y_hi=1.0, nu=0.01,
+             dt=0.01, q_target_or_pi=1.0)
+    d.update(bad)
+    desc = IbmGridDesc(**d)
+    h = ctypes.c_void_p()
+    lib.ibm_create_grid.argtypes = [ctypes.POINTER(IbmGridDesc), ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
+    rc = lib.ibm_create_grid(ctypes.byref(desc), 1, 0, None, ctypes.byref(h))
+    assert rc == IBM_ERR_ARG
+    assert not h.value

@@ -1,0 +1,215 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Bars: integer/byte work (tags, IBM index lists) bit-exact; FP64 floating point
+within 1e-12 relative (max-norm relative to the field's max); the IBM
+coefficients within 1e-14 relative.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import ibm_inputs as I
+from oracle.ibm_oracle import OGrid, Oracle, poisson_solve
+from tests.gpu_helpers import case, device, gpu_grid, oracle_run, rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TAGBITS = {"u": 1, "v": 2, "w": 4, "p": 8}
+
+
+def _oracle_tags(o):
+    t = np.zeros(o.g.shape, dtype=np.uint8)
+    for c, b in TAGBITS.items():
+        t |= np.where(o.tags[c], b, 0).astype(np.uint8)
+    for c, b in (("u", 16), ("v", 32), ("w", 64)):
+        t |= np.where(o.lam[c] > 0, b, 0).astype(np.uint8)
+    return t
+
+
+@pytest.mark.parametrize("name", ["wavy_small", "flat_small", "ellip_small", "minimal", "wavy_160"])
+@pytest.mark.parametrize("b_mode", [0, 1, 2])
+def test_geometry_parity(name, b_mode):
+    c = case(name, b_mode=b_mode)
+    o, sdf, st = oracle_run(c, 0)
+    g = gpu_grid(c, sdf, st)
+    tags, n = g.geometry()
+    tags = tags.cpu().numpy()
+    assert np.array_equal(tags, _oracle_tags(o))
+    for comp, cn in enumerate("uvw"):
+        idx, lam, coef = g.ibm_list(comp)
+        ref_idx = np.flatnonzero(o.lam[cn].ravel() > 0)
+        assert np.array_equal(idx.cpu().numpy(), ref_idx)
+        ref_lam = o.lam[cn].ravel()[ref_idx]
+        if ref_idx.size:
+            assert np.abs(lam.cpu().numpy() - ref_lam).max() <= 1e-14 * ref_lam.max()
+            cf = coef.cpu().numpy()
+            for k in range(3):
+                B, A = o.coef[k][cn]
+                assert np.abs(cf[k, :, 0] - B.ravel()[ref_idx]).max() <= 1e-14
+                assert np.abs(cf[k, :, 1] - 1.0 / A.ravel()[ref_idx]).max() <= 1e-14
+    s = g.stats()
+    assert s["n_internal"] == [int(o.tags[q].sum()) for q in "uvw"]
+    assert s["n_p_internal"] == int(o.tags["p"].sum())
+    g.close()
+
+
+POISSON_SHAPES = [(4, 5, 4), (6, 9, 6), (10, 7, 5), (20, 5, 10), (160, 5, 4), (2, 3, 1), (80, 13, 10),
+                  (96, 33, 96), (192, 9, 3), (512, 5, 16), (32, 33, 16), (40, 17, 25)]
+
+
+@pytest.mark.parametrize("shape", POISSON_SHAPES)
+def test_solve_pressure_parity(shape):
+    nx, ny, nz = shape
+    c = I.Case(nx=nx, ny=ny, nz=nz, lx=2.0, lz=1.3, y_lo=-1.0, y_hi=0.7, nu=0.01, dt=0.01)
+    rng = np.random.default_rng(nx * 1000 + ny * 10 + nz)
+    rhs = rng.standard_normal((ny - 1, nz, nx)) + 0.3     # nonzero mean on purpose
+    phi_ref, mean_ref = poisson_solve(OGrid.from_case(c), rhs)
+    from paper_2506_14328_amd import IbmGrid
+    g = IbmGrid.from_case(c)
+    phi = g.solve_pressure(to_dev(rhs)).cpu().numpy()
+    assert rel_err(phi, phi_ref) < 1e-12
+    s = g.stats()
+    assert abs(s["rhs_mean_removed"] - mean_ref) < 1e-13
+    g.close()
+
+
+@pytest.mark.parametrize("name,nsteps", [("wavy_small", 1), ("wavy_small", 4), ("flat_small", 3),
+                                         ("ellip_small", 2), ("minimal", 5), ("wavy_160", 2)])
+def test_step_parity_fp64(name, nsteps):
+    c = case(name)
+    o, sdf, st = oracle_run(c, nsteps)
+    g = gpu_grid(c, sdf, st)
+    g.set_diagnostics(True)
+    g.step(nsteps)
+    u, v, w, p = [t.cpu().numpy() for t in g.get_state()]
+    scale = max(np.abs(o.u).max(), np.abs(o.v).max(), np.abs(o.w).max())
+    for a, b in ((u, o.u), (v, o.v), (w, o.w)):
+        assert np.abs(a - b).max() <= 1e-12 * scale
+    assert rel_err(p, o.p) < 1e-10
+    s = g.stats()
+    os_ = o.stats()
+    assert math.isclose(s["pi_last"], o.pi_last, rel_tol=1e-10, abs_tol=1e-14)
+    assert math.isclose(s["q"], os_["q"], rel_tol=1e-12)
+    assert s["div_max_fullbox"] <= 1e-12 * scale / min(o.g.dx, o.g.dy, o.g.dz)
+    assert s["poisson_rel_residual"] < 1e-12
+    assert abs(s["div_max_internal_leak"] - os_["div_max_internal_leak"]) <= 1e-10 * max(os_["div_max_internal_leak"], 1e-8)
+    g.close()
+
+
+@pytest.mark.parametrize("b_mode", [1, 2])
+def test_step_parity_b_modes(b_mode):
+    c = case("wavy_small", b_mode=b_mode)
+    o, sdf, st = oracle_run(c, 2)
+    g = gpu_grid(c, sdf, st)
+    g.step(2)
+    u, v, w, p = [t.cpu().numpy() for t in g.get_state()]
+    assert rel_err(u, o.u) < 1e-12 and rel_err(w, o.w) < 1e-12
+
+
+def test_step_parity_staircase_and_cpg():
+    c = case("wavy_small", forcing=1, q_target_or_pi=-0.01)
+    o, sdf, st = oracle_run(c, 2, ibm=False)
+    g = gpu_grid(c, sdf, st, ibm=False)
+    g.step(2)
+    u, v, w, p = [t.cpu().numpy() for t in g.get_state()]
+    assert rel_err(u, o.u) < 1e-12 and rel_err(v, o.v) < 1e-12 and rel_err(w, o.w) < 1e-12
+    assert g.stats()["n_ibm"] == [0, 0, 0]
+
+
+def test_poiseuille_workload_parity_and_fixed_point():
+    """The 32x33x16 plane Poiseuille workload: 100 steps against the oracle, then the
+    exact discrete steady solution stays fixed on the GPU."""
+    c = I.make_case("poiseuille")
+    o, sdf, st = oracle_run(c, 100)
+    g = gpu_grid(c, sdf, st)
+    g.step(100)
+    u, v, w, p = [t.cpu().numpy() for t in g.get_state()]
+    assert rel_err(u, o.u) < 1e-12
+    # fixed point
+    og = o.g
+    yc = og.y_lo + (np.arange(og.ny - 1) + 0.5) * og.dy
+    hw = 1.0 - 0.37 * og.dy
+    delta = yc[0] + hw
+    prof = hw * hw - yc * yc + delta * (og.dy - delta)
+    a = og.q_target_or_pi / (og.lz * prof.sum() * og.dy)
+    ue = np.broadcast_to((a * prof)[:, None, None], og.shape).copy()
+    z = np.zeros(og.shape)
+    g.set_state(to_dev(ue), to_dev(z), to_dev(z), to_dev(z))
+    g.step(5)
+    u = g.get_state()[0].cpu().numpy()
+    assert rel_err(u, ue) < 1e-13
+    assert math.isclose(g.stats()["pi_last"], -2 * og.nu * a, rel_tol=1e-10)
+    g.close()
+
+
+def test_wavy_workload_full_size_parity():
+    """The 192x129x96 sinusoidal-wall FP64 workload, full arrays, 1 step, against the oracle."""
+    c = I.make_case("wavy")
+    o, sdf, st = oracle_run(c, 1)
+    g = gpu_grid(c, sdf, st)
+    g.set_diagnostics(True)
+    g.step(1)
+    u, v, w, p = [t.cpu().numpy() for t in g.get_state()]
+    for a, b in ((u, o.u), (v, o.v), (w, o.w)):
+        assert rel_err(a, b) < 1e-12
+    s = g.stats()
+    assert s["div_max_fullbox"] < 1e-12 / o.g.dy
+    g.close()
+
+
+def test_determinism_bitwise():
+    c = case("wavy_160")
+    o, sdf, st = oracle_run(c, 0)
+    outs = []
+    for _ in range(2):
+        g = gpu_grid(c, sdf, st)
+        g.step(3)
+        outs.append([t.cpu().numpy() for t in g.get_state()])
+        g.close()
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
+def test_fp32_storage_close_to_fp64():
+    c = case("wavy_160")
+    o, sdf, st = oracle_run(c, 0)
+    g64 = gpu_grid(c, sdf, st, "fp64")
+    g32 = gpu_grid(c, sdf, st, "fp32")
+    g64.step(20)
+    g32.step(20)
+    a = [t.cpu().numpy() for t in g64.get_state()]
+    b = [t.double().cpu().numpy() for t in g32.get_state()]
+    for x, y in zip(a[:3], b[:3]):
+        assert rel_err(y, x) < 1e-5
+    g64.close()
+    g32.close()
+
+
+def test_error_paths():
+    from paper_2506_14328_amd import IbmError, IbmGrid
+    c = case("wavy_small")
+    g = IbmGrid.from_case(c)
+    with pytest.raises(IbmError) as e:
+        g.step(1)
+    assert e.value.code == -4
+    sdf = [to_dev(-np.abs(s) - 1.0) for s in I.make_sdf(c)]   # all solid
+    with pytest.raises(IbmError) as e:
+        g.set_geometry(*sdf)
+    assert e.value.code == -1
+    with pytest.raises(ValueError):
+        g.set_state(*[torch.zeros((3, 3, 3), dtype=torch.float64, device=device())] * 4)
+    g.close()
+
+
+def test_nan_detected():
+    c = case("wavy_small")
+    o, sdf, st = oracle_run(c, 0)
+    u = st[0].copy()
+    u[3, 2, 5] = np.nan
+    g = gpu_grid(c, sdf, (u, st[1], st[2], st[3]))
+    g.step(1)
+    s = g.stats()
+    assert s["nan_flag"] == 1 and s["unstable"]
+    g.close()
