@@ -1,0 +1,260 @@
+"""Benchmark of the RK3 immersed-boundary step on one MI355X.
+
+Workload (default): the FP64 sinusoidal-wall channel, 192x129x96 cells-faces
+(192 x 128 x 96 = 2,359,296 cells), constant flow rate at Re_bulk = 2800,
+dt = 0.008, seeded synthetic inputs (no dataset).  One "step" is one full RK3
+time step = 3 substeps of the whole hot path (momentum + immersed-boundary
+update + flow-rate control + FFT/tridiagonal projection + correction).
+
+Prints ONE JSON line with the throughput in cell-updates per second per RK
+substep, the roofline figures of the dominant kernel (timed live with HIP
+events on the library's stream during the timed region), the FP64 CPU oracle
+timed on a bounded sample, and the other measured forms.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell-updates/s per RK substep + % HBM peak; FP64 vs FP32-storage vs batched"
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, vendor figure
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="wavy", help="wavy | wavy_large | ellipsoids | poiseuille")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the extra forms (FP32, large grid, IBM off)")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="run warmup + steps without extra forms or baseline (for rocprofv3)")
+    ap.add_argument("--copy-calibration-mb", type=float, default=0.0,
+                    help="also run a plain device copy of this many MiB (PMC counter calibration)")
+    return ap.parse_args()
+
+
+# --------------------------------------------------------------------------------------
+# Algorithmic HBM bytes per launch of each kernel (values that must move at least once).
+#   C = cells, M = spectral points (nx/2+1)*nz*(ny-1), s = bytes per stored value,
+#   n_ibm = immersed-boundary points (all components), n_u = those of u.
+# --------------------------------------------------------------------------------------
+def algorithmic_bytes(kernel, C, M, s, n_ibm, n_u):
+    if kernel == "momentum":
+        # reads u, v, w, p, tag, H_prev (stages 2, 3); writes u*, H (stages 1, 2): avg 11 fields + tag
+        return C * (11 * s + 1)
+    if kernel == "ibm_fix":
+        return n_ibm * (4 + 16 + 3 * s)
+    if kernel == "ibm_pi":
+        return n_u * (4 + 16 + 2 * s)
+    if kernel == "div_fftx":
+        return C * (3 * s + 1) + M * 2 * s
+    if kernel in ("fftz_fwd", "fftz_inv", "tri"):
+        return M * 4 * s
+    if kernel == "ifftx":
+        return M * 2 * s + C * s
+    if kernel == "correct":
+        return C * (9 * s + 1)
+    if kernel == "cfr":
+        return 0
+    raise KeyError(kernel)
+
+
+def step_bytes(C, M, s, n_ibm, n_u):
+    per_sub = sum(algorithmic_bytes(k, C, M, s, n_ibm, n_u) for k in
+                  ("momentum", "ibm_fix", "ibm_pi", "div_fftx", "fftz_fwd", "tri", "fftz_inv", "ifftx", "correct"))
+    return 3 * per_sub
+
+
+def kernel_source_digest():
+    h = hashlib.sha256()
+    for f in ("kernels_step.hip", "fft_lds.h", "ibm_internal.h"):
+        with open(os.path.join(ROOT, "paper_2506_14328_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel, workload, precision):
+    """HBM traffic per launch from the committed rocprofv3 PMC summary, if it was taken on
+    the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}_{precision}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_digest") != kernel_source_digest():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def build_inputs(name):
+    import numpy as np
+    import ibm_inputs as I
+    c = I.make_case(name)
+    sdf = I.make_sdf(c)
+    u, v, w = I.make_initial(c, sdf)
+    return c, sdf, (u, v, w, np.zeros_like(u))
+
+
+def make_grid(c, sdf, st, precision, ibm=True):
+    import torch
+    from paper_2506_14328_amd import IbmGrid
+    dev = torch.device("cuda", 0)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    g = IbmGrid.from_case(c, precision=precision, ibm=ibm)
+    g.set_geometry(*[torch.from_numpy(a).to(dev) for a in sdf])
+    g.set_state(*[torch.from_numpy(a).to(dev, dt) for a in st])
+    return g
+
+
+def timed_run(g, steps, warmup, profile_kernel=None):
+    """Warmup, then exactly `steps` steps between two device synchronisations.
+    With profile_kernel, HIP events bracket every launch of that kernel."""
+    import torch
+    g.step(warmup)
+    if profile_kernel:
+        g.profile([profile_kernel])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.step(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = g.profile_read() if profile_kernel else {}
+    g.profile(False)
+    return el, prof
+
+
+def dominant_kernel(g, nsteps=3):
+    g.profile(True)
+    g.step(nsteps)
+    prof = g.profile_read()
+    g.profile(False)
+    tot = sum(v[0] for v in prof.values())
+    k = max(prof, key=lambda n: prof[n][0])
+    return k, {n: round(100.0 * v[0] / tot, 1) for n, v in prof.items()}
+
+
+def measure(name, precision, steps, warmup, ibm=True, inputs=None):
+    c, sdf, st = inputs if inputs is not None else build_inputs(name)
+    g = make_grid(c, sdf, st, precision, ibm)
+    stats0 = g.stats()
+    kern, shares = dominant_kernel(g)
+    el, prof = timed_run(g, steps, warmup, kern)
+    C = c.nx * (c.ny - 1) * c.nz
+    M = (c.nx // 2 + 1) * c.nz * (c.ny - 1)
+    s = 8 if precision == "fp64" else 4
+    n_ibm = sum(stats0["n_ibm"])
+    ms, cnt = prof[kern]
+    avg_s = ms / cnt * 1e-3
+    abytes = algorithmic_bytes(kern, C, M, s, n_ibm, stats0["n_ibm"][0])
+    achieved = abytes / avg_s / 1e9
+    stats = g.stats()
+    g.close()
+    return dict(case=c, cells=C, el=el, value=C * 3 * steps / el, ms_per_step=el / steps * 1e3,
+                kernel=kern, kernel_avg_us=avg_s * 1e6, kernel_launches=cnt, kernel_bytes=abytes,
+                achieved_gbs=achieved, shares=shares, stats=stats,
+                step_gbs=step_bytes(C, M, s, n_ibm, stats0["n_ibm"][0]) * steps / el / 1e9,
+                ibm_fraction=n_ibm / (3.0 * C))
+
+
+def cpu_baseline(name, target_s=12.0):
+    """The FP64 oracle, as it stands, on the same workload: 1 untimed step, then as many
+    whole steps as fit in about target_s seconds (at least 1)."""
+    import numpy as np
+    from oracle.ibm_oracle import OGrid, Oracle
+    c, sdf, st = build_inputs(name)
+    o = Oracle(OGrid.from_case(c))
+    o.set_geometry(*sdf)
+    o.set_state(*st)
+    t = time.perf_counter()
+    o.step(1)
+    first = time.perf_counter() - t
+    n = max(1, int(target_s / max(first, 1e-3)))
+    t = time.perf_counter()
+    o.step(n)
+    el = time.perf_counter() - t
+    C = c.nx * (c.ny - 1) * c.nz
+    return {"value": C * 3 * n / el, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} RK3 steps ({3 * n} substeps) of the {c.name} workload after 1 warm-up step, "
+                      f"NumPy/SciPy FP64, single thread; {el:.1f} s"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": a.gpus}), flush=True)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}), flush=True)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+
+    if a.copy_calibration_mb > 0:
+        n = int(a.copy_calibration_mb * (1 << 20) // 8)
+        x = torch.ones(n, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(f"copy calibration: {n * 8} bytes read, {n * 8} bytes written per launch", flush=True)
+
+    inputs = build_inputs(a.workload)
+    r = measure(a.workload, a.precision, a.steps, a.warmup, inputs=inputs)
+    if a.profile_only:
+        print(json.dumps({"workload": r["case"].name, "ms_per_step": r["ms_per_step"], "kernel": r["kernel"],
+                          "kernel_avg_us": r["kernel_avg_us"]}), flush=True)
+        return
+    c = r["case"]
+    traffic = load_traffic(r["kernel"], c.name, a.precision)
+    roof = {"bound": "hbm", "achieved": round(r["achieved_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": r["kernel"], "kernel_avg_us": round(r["kernel_avg_us"], 2),
+            "algorithmic_bytes_per_launch": int(r["kernel_bytes"]),
+            "step_algorithmic_GBs": round(r["step_gbs"], 1)}
+    out = {"metric": METRIC, "value": r["value"], "unit": "cell-updates/s", "n_gpus": 1, "steps": a.steps,
+           "warmup": a.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64" if a.precision == "fp64" else "f32",
+           "data": "synthetic (seeded sinusoidal-wall channel, laminar + solenoidal perturbation)",
+           "config": {"workload": c.name, "grid_faces": [c.nx, c.ny, c.nz], "cells": r["cells"],
+                      "precision": a.precision, "Re_bulk": round(1.0 / c.nu), "dt": c.dt,
+                      "forcing": "constant flow rate", "ibm_point_fraction": round(r["ibm_fraction"], 4)},
+           "roofline": roof, "kernel_time_share_pct": r["shares"]}
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(a.workload)
+    if not a.no_forms:
+        forms = []
+        fp32 = measure(a.workload, "fp32", a.steps, a.warmup, inputs=inputs)
+        forms.append(_form(fp32, "fp32"))
+        off = measure(a.workload, a.precision, a.steps, a.warmup, ibm=False, inputs=inputs)
+        forms.append(dict(_form(off, a.precision), ibm="off (staircase)"))
+        big = build_inputs("wavy_large")
+        for prec in ("fp64", "fp32"):
+            forms.append(_form(measure("wavy_large", prec, 20, 3, inputs=big), prec))
+        out["forms"] = forms
+    print(json.dumps(out), flush=True)
+
+
+def _form(r, prec):
+    return {"workload": r["case"].name, "precision": prec, "value": r["value"], "ms_per_step": r["ms_per_step"],
+            "dominant_kernel": r["kernel"], "kernel_frac_hbm": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4),
+            "step_algorithmic_GBs": round(r["step_gbs"], 1)}
+
+
+if __name__ == "__main__":
+    main()

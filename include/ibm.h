@@ -153,10 +153,12 @@ int ibm_get_ibm_list(ibm_handle h, int32_t inst, int32_t comp, int32_t* idx, dou
                      double* coef);
 
 /* Per-kernel timing with HIP events recorded on the library's stream around
- * every launch while enabled (kernel ids: see ibm_kernel_name).  read()
- * synchronises, returns the accumulated milliseconds and launch counts for
- * up to max kernels and resets the accumulators. */
-int ibm_profile(ibm_handle h, int32_t on);
+ * every launch of the kernels selected by kernel_mask (bit k = kernel id k,
+ * see ibm_kernel_name; -1 = all, 0 = off).  read() synchronises, returns the
+ * accumulated milliseconds and launch counts for up to max kernels and
+ * resets the accumulators.  At most 65536 launches are recorded between
+ * two reads. */
+int ibm_profile(ibm_handle h, int32_t kernel_mask);
 int ibm_profile_read(ibm_handle h, double* total_ms, int64_t* launches, int32_t max);
 const char* ibm_kernel_name(int32_t id);
 int32_t ibm_num_kernels(void);

@@ -63,7 +63,8 @@ struct ibm_ctx {
   std::vector<Instance> inst;
   std::string err;
   bool diag = false;
-  // profiling
+  // profiling: bit k of prof_mask selects kernel id k
+  uint32_t prof_mask = 0;
   bool prof = false;
   std::vector<hipEvent_t> ev;
   std::vector<int> ev_kid;
@@ -89,7 +90,7 @@ int fail(ibm_ctx* c, int code, const std::string& msg) {
 
 template <class F>
 hipError_t timed(ibm_ctx* c, int kid, F&& launch) {
-  if (c->prof && c->ev_used + 1 < c->ev.size()) {
+  if (c->prof && ((c->prof_mask >> kid) & 1u) && c->ev_used + 1 < c->ev.size()) {
     hipEvent_t a = c->ev[c->ev_used], b = c->ev[c->ev_used + 1];
     c->ev_kid[c->ev_used / 2] = kid;
     c->ev_used += 2;
@@ -591,6 +592,7 @@ int ibm_profile(ibm_handle h, int32_t on) {
     for (size_t e = 0; e < n; ++e) HIPCHK(h, hipEventCreate(&h->ev[e]));
   }
   h->prof = on != 0;
+  h->prof_mask = (uint32_t)on;
   return IBM_OK;
 }
 

@@ -201,8 +201,23 @@ class IbmGrid:
         self._check(self.lib.ibm_get_ibm_list(self._h, 0, comp, _ptr(idx), _ptr(lam), _ptr(coef)))
         return idx[:m], lam[:m], coef[:, :m]
 
-    def profile(self, on: bool = True):
-        self._check(self.lib.ibm_profile(self._h, 1 if on else 0))
+    def kernel_names(self):
+        return [self.lib.ibm_kernel_name(k).decode() for k in range(self.lib.ibm_num_kernels())]
+
+    def profile(self, on=True):
+        """on: True (all kernels), False (off), an int mask, or a list of kernel names."""
+        if on is True:
+            mask = -1
+        elif on is False or on is None:
+            mask = 0
+        elif isinstance(on, int):
+            mask = on
+        else:
+            names = self.kernel_names()
+            mask = 0
+            for n in on:
+                mask |= 1 << names.index(n)
+        self._check(self.lib.ibm_profile(self._h, int(mask)))
 
     def profile_read(self) -> Dict[str, Tuple[float, int]]:
         nk = self.lib.ibm_num_kernels()

@@ -87,14 +87,16 @@ def test_step_parity_fp64(name, nsteps):
     scale = max(np.abs(o.u).max(), np.abs(o.v).max(), np.abs(o.w).max())
     for a, b in ((u, o.u), (v, o.v), (w, o.w)):
         assert np.abs(a - b).max() <= 1e-12 * scale
-    assert rel_err(p, o.p) < 1e-10
+    # pressure against its dynamic scale U^2 (p itself can be near zero in quiet flows)
+    assert np.abs(p - o.p).max() <= 1e-11 * max(np.abs(o.p).max(), scale * scale)
     s = g.stats()
     os_ = o.stats()
     assert math.isclose(s["pi_last"], o.pi_last, rel_tol=1e-10, abs_tol=1e-14)
     assert math.isclose(s["q"], os_["q"], rel_tol=1e-12)
-    assert s["div_max_fullbox"] <= 1e-12 * scale / min(o.g.dx, o.g.dy, o.g.dz)
+    div_tol = 1e-12 * scale / min(o.g.dx, o.g.dy, o.g.dz)
+    assert s["div_max_fullbox"] <= div_tol
     assert s["poisson_rel_residual"] < 1e-12
-    assert abs(s["div_max_internal_leak"] - os_["div_max_internal_leak"]) <= 1e-10 * max(os_["div_max_internal_leak"], 1e-8)
+    assert abs(s["div_max_internal_leak"] - os_["div_max_internal_leak"]) <= div_tol
     g.close()
 
 
