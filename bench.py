@@ -49,20 +49,18 @@ def parse():
 # --------------------------------------------------------------------------------------
 def algorithmic_bytes(kernel, C, M, s, n_ibm, n_u):
     if kernel == "momentum":
-        # reads u, v, w, p, tag, H_prev (stages 2, 3); writes u*, H (stages 1, 2): avg 11 fields + tag
-        return C * (11 * s + 1)
-    if kernel == "ibm_fix":
-        return n_ibm * (4 + 16 + 3 * s)
-    if kernel == "ibm_pi":
-        return n_u * (4 + 16 + 2 * s)
+        # reads u, v, w, p, tag, H_prev (stages 2, 3); writes u*, H (stages 1, 2): avg 11 fields + tag;
+        # (B, 1/A) of every immersed-boundary point
+        return C * (11 * s + 1) + n_ibm * 16
     if kernel == "div_fftx":
-        return C * (3 * s + 1) + M * 2 * s
+        # reads u*, v*, w*, tag, 1/A of the IBM u faces; writes the x-spectrum
+        return C * (3 * s + 1) + n_u * 16 + M * 2 * s
     if kernel in ("fftz_fwd", "fftz_inv", "tri"):
         return M * 4 * s
     if kernel == "ifftx":
         return M * 2 * s + C * s
     if kernel == "correct":
-        return C * (9 * s + 1)
+        return C * (9 * s + 1) + n_u * 16
     if kernel == "cfr":
         return 0
     raise KeyError(kernel)
@@ -70,7 +68,7 @@ def algorithmic_bytes(kernel, C, M, s, n_ibm, n_u):
 
 def step_bytes(C, M, s, n_ibm, n_u):
     per_sub = sum(algorithmic_bytes(k, C, M, s, n_ibm, n_u) for k in
-                  ("momentum", "ibm_fix", "ibm_pi", "div_fftx", "fftz_fwd", "tri", "fftz_inv", "ifftx", "correct"))
+                  ("momentum", "div_fftx", "fftz_fwd", "tri", "fftz_inv", "ifftx", "correct"))
     return 3 * per_sub
 
 

@@ -1,9 +1,9 @@
 // Mixed-radix (4, 2, 3, 5) Stockham FFT on data resident in LDS.
 //
 // A group of `nlanes` threads transforms one sequence of length p.n whose
-// element e sits at buf[e * stride].  Each stage reads from one LDS buffer
-// and writes the self-sorted result to the other (Stockham auto-sort), so no
-// bit-reversal pass is needed.  Stage with radix R after a span Ns:
+// element e sits at buf[e * stride].  Each stage writes its self-sorted result
+// (Stockham auto-sort) back into the same LDS buffer, so no bit-reversal pass is
+// needed.  Stage with radix R after a span Ns:
 //   butterfly b (0 <= b < n/R), k = b mod Ns,
 //   inputs  x[b + t n/R] * w^(t k n/(Ns R)),   t = 0..R-1,  w = exp(sign 2 pi i / n)
 //   outputs y[(b/Ns) Ns R + k + t Ns] = DFT_R(inputs)[t]
@@ -69,50 +69,85 @@ __device__ __forceinline__ void bfly5(cplx<T>* v, int sign) {
   v[3] = csub(r2, q2);
 }
 
-template <typename T, int R>
-__device__ __forceinline__ void fft_stage_r(const cplx<T>* __restrict__ src, cplx<T>* __restrict__ dst, int n,
-                                            int Ns, int stride, const FFTPlan& p, int sign, int lane,
-                                            int nlanes) {
-  const int nb = n / R;
-  const int tstep = n / (Ns * R);
-  for (int b = lane; b < nb; b += nlanes) {
-    const int k = b % Ns;
-    cplx<T> v[R];
-#pragma unroll
-    for (int t = 0; t < R; ++t) v[t] = src[(b + t * nb) * stride];
-    if (k != 0) {
-#pragma unroll
-      for (int t = 1; t < R; ++t) v[t] = cmul(v[t], twiddle<T>(p, t * k * tstep, sign));
-    }
-    if (R == 2) bfly2(v);
-    if (R == 3) bfly3(v, sign);
-    if (R == 4) bfly4(v, sign);
-    if (R == 5) bfly5(v, sign);
-    const int o = (b / Ns) * Ns * R + k;
-#pragma unroll
-    for (int t = 0; t < R; ++t) dst[(o + t * Ns) * stride] = v[t];
-  }
+// Twiddle w^m = exp(sign 2 pi i m / n) from the table tw[m] = exp(-2 pi i m / n) held in LDS.
+template <typename T>
+__device__ __forceinline__ cplx<T> tw_at(const cplx<T>* tw, int m, int sign) {
+  const cplx<T> t = tw[m];
+  return {t.x, sign < 0 ? t.y : -t.y};
 }
 
-// Transforms the sequence held in a (stride `stride`); returns the buffer that
-// holds the result (a if the number of stages is even, else b).
+// Butterflies per thread needed by the largest stage of plan p with nlanes threads.
+inline int fft_max_bfly(const FFTPlan& p, int nlanes) {
+  int mb = 1;
+  for (int s = 0; s < p.nst; ++s) {
+    const int nb = p.n / p.radix[s];
+    const int b = (nb + nlanes - 1) / nlanes;
+    if (b > mb) mb = b;
+  }
+  return mb <= 1 ? 1 : (mb <= 2 ? 2 : 4);
+}
+
+// Copy the plan's twiddle table (n entries) into LDS; caller synchronises.
 template <typename T>
-__device__ cplx<T>* fft_lds(cplx<T>* a, cplx<T>* b, int stride, const FFTPlan& p, int sign, int lane,
-                            int nlanes) {
+__device__ __forceinline__ void load_twiddles(cplx<T>* dst, const FFTPlan& p, int tid, int nthr) {
+  for (int m = tid; m < p.n; m += nthr) dst[m] = twiddle<T>(p, m, -1);
+}
+
+// One in-place stage: every thread first computes up to MB butterflies into
+// registers, the block synchronises, then the results are written to their
+// self-sorted positions.  Requires n/R <= MB * nlanes (the launchers pick MB).
+template <typename T, int R, int MB>
+__device__ __forceinline__ void fft_stage_r(cplx<T>* buf, int n, int Ns, int stride, const cplx<T>* __restrict__ tw,
+                                            int sign, int lane, int nlanes) {
+  constexpr int FFT_MAXB = MB;
+  const int nb = n / R;
+  const int tstep = n / (Ns * R);
+  cplx<T> v[FFT_MAXB][R];
+#pragma unroll
+  for (int q = 0; q < FFT_MAXB; ++q) {
+    const int b = lane + q * nlanes;
+    if (b < nb) {
+      const int k = b % Ns;
+#pragma unroll
+      for (int t = 0; t < R; ++t) v[q][t] = buf[(b + t * nb) * stride];
+      if (k != 0) {
+#pragma unroll
+        for (int t = 1; t < R; ++t) v[q][t] = cmul(v[q][t], tw_at<T>(tw, t * k * tstep, sign));
+      }
+      if (R == 2) bfly2(v[q]);
+      if (R == 3) bfly3(v[q], sign);
+      if (R == 4) bfly4(v[q], sign);
+      if (R == 5) bfly5(v[q], sign);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < FFT_MAXB; ++q) {
+    const int b = lane + q * nlanes;
+    if (b < nb) {
+      const int k = b % Ns;
+      const int o = (b / Ns) * Ns * R + k;
+#pragma unroll
+      for (int t = 0; t < R; ++t) buf[(o + t * Ns) * stride] = v[q][t];
+    }
+  }
+  __syncthreads();
+}
+
+// Transforms, in place, the sequence held in buf (element e at buf[e * stride]) with
+// twiddles from the LDS table tw.  Every thread of the block must call it.
+template <typename T, int MB>
+__device__ void fft_lds(cplx<T>* buf, int stride, const FFTPlan& p, const cplx<T>* tw, int sign, int lane,
+                        int nlanes) {
   int Ns = 1;
   for (int s = 0; s < p.nst; ++s) {
     const int R = p.radix[s];
     switch (R) {
-      case 4: fft_stage_r<T, 4>(a, b, p.n, Ns, stride, p, sign, lane, nlanes); break;
-      case 2: fft_stage_r<T, 2>(a, b, p.n, Ns, stride, p, sign, lane, nlanes); break;
-      case 3: fft_stage_r<T, 3>(a, b, p.n, Ns, stride, p, sign, lane, nlanes); break;
-      default: fft_stage_r<T, 5>(a, b, p.n, Ns, stride, p, sign, lane, nlanes); break;
+      case 4: fft_stage_r<T, 4, MB>(buf, p.n, Ns, stride, tw, sign, lane, nlanes); break;
+      case 2: fft_stage_r<T, 2, MB>(buf, p.n, Ns, stride, tw, sign, lane, nlanes); break;
+      case 3: fft_stage_r<T, 3, MB>(buf, p.n, Ns, stride, tw, sign, lane, nlanes); break;
+      default: fft_stage_r<T, 5, MB>(buf, p.n, Ns, stride, tw, sign, lane, nlanes); break;
     }
-    __syncthreads();
-    cplx<T>* t = a;
-    a = b;
-    b = t;
     Ns *= R;
   }
-  return a;
 }

@@ -29,8 +29,6 @@ struct Instance {
   void *u = nullptr, *v = nullptr, *w = nullptr, *p = nullptr;
   void *us = nullptr, *vs = nullptr, *ws = nullptr;
   void *Hu = nullptr, *Hv = nullptr, *Hw = nullptr, *phi = nullptr, *spec = nullptr;
-  double* cp = nullptr;
-  double2* dp = nullptr;
   uint8_t* tag = nullptr;
   double* qpart = nullptr;
   double* red_part = nullptr;
@@ -39,7 +37,7 @@ struct Instance {
   double2* rtw = nullptr;
   double *kx2 = nullptr, *kz2 = nullptr;
   // immersed-boundary lists
-  DevBuf ibm_idx, ibm_coef, ibm_lam;
+  DevBuf ibm_idx, ibm_coef, ibm_lam, ibm_choff;
   IbmLists L{};
   int64_t n_int[3] = {0, 0, 0}, n_ibm[3] = {0, 0, 0}, n_pint = 0;
   bool geom_ready = false;
@@ -150,6 +148,7 @@ int validate(ibm_ctx* c, const ibm_grid_desc& d) {
   if (d.nz < 1) return fail(c, IBM_ERR_ARG, "nz must be >= 1");
   if (d.ny < 3) return fail(c, IBM_ERR_ARG, "ny (wall-normal faces) must be >= 3");
   if (d.nx > 1024 || d.nz > 1024) return fail(c, IBM_ERR_ARG, "nx and nz are limited to 1024");
+  if (d.ny > 2049) return fail(c, IBM_ERR_ARG, "ny is limited to 2049 (tridiagonal segments)");
   int r[20], ns;
   if (!factor_235(d.nx / 2, r, &ns) || !factor_235(d.nz, r, &ns))
     return fail(c, IBM_ERR_ARG, "nx/2 and nz must have prime factors in {2,3,5}");
@@ -196,8 +195,6 @@ int init_instance(ibm_ctx* c, Instance& I, const ibm_grid_desc& d) {
   }
   const size_t nspec = (size_t)g.ny1 * g.nmodes;
   if ((rc = dalloc(c, I, &I.spec, nspec * 2 * ts))) return rc;
-  if ((rc = dalloc(c, I, (void**)&I.cp, nspec * sizeof(double)))) return rc;
-  if ((rc = dalloc(c, I, (void**)&I.dp, nspec * sizeof(double2)))) return rc;
   if ((rc = dalloc(c, I, (void**)&I.tag, (size_t)g.ncell))) return rc;
   HIPCHK(c, hipMemsetAsync(I.tag, 0, (size_t)g.ncell, c->stream));
   const size_t mom_blocks = (size_t)((g.nx + 63) / 64) * ((g.nz + 3) / 4) * g.ny1;
@@ -257,7 +254,7 @@ template <typename T>
 int poisson(ibm_ctx* c, Instance& I, Fields<T>& f, T* phi_out) {
   const GridParams& g = I.g;
   RUNK(c, K_FFTZ_FWD, launch_fftz<T>(g, f.spec, I.pz, -1, c->stream));
-  RUNK(c, K_TRI, launch_tri<T>(g, f.spec, I.kx2, I.kz2, I.cp, I.dp, I.mean(), c->stream));
+  RUNK(c, K_TRI, launch_tri<T>(g, f.spec, I.kx2, I.kz2, I.mean(), c->stream));
   RUNK(c, K_FFTZ_INV, launch_fftz<T>(g, f.spec, I.pz, +1, c->stream));
   RUNK(c, K_IFFTX, launch_ifftx<T>(g, f.spec, phi_out, I.px, I.rtw, c->stream));
   return IBM_OK;
@@ -277,22 +274,22 @@ int run_steps(ibm_ctx* c, Instance& I, int nsteps) {
       sc.stage = k;
       sc.use_hold = (k > 0);
       sc.write_h = (k < 2);
-      int nq1 = 0, nq2 = 0;
-      RUNK(c, K_MOMENTUM, launch_momentum<T>(g, f, sc, I.qpart, &nq1, c->stream));
-      if (I.L.n_total > 0) RUNK(c, K_IBM_FIX, launch_ibm_fix<T>(g, f, I.L, k, I.qpart + nq1, &nq2, c->stream));
-      RUNK(c, K_CFR, launch_cfr(I.qpart, nq1 + nq2, scale, I.d.forcing, I.d.q_target_or_pi, I.S3(), k, I.pi(),
+      int nq = 0;
+      RUNK(c, K_MOMENTUM, launch_momentum<T>(g, f, I.L, sc, I.qpart, &nq, c->stream));
+      RUNK(c, K_CFR, launch_cfr(I.qpart, nq, scale, I.d.forcing, I.d.q_target_or_pi, I.S3(), k, I.pi(),
                                 I.pi_hist(), c->stream));
       if (I.L.n_u > 0) RUNK(c, K_IBM_PI, launch_ibm_pi<T>(f, I.L, k, sc.ck_dt, I.pi(), c->stream));
-      RUNK(c, K_DIV_FFTX, launch_div_fftx<T>(g, f, I.px, I.rtw, sc.ck_dt, I.pi(), (const T*)nullptr, c->stream));
+      RUNK(c, K_DIV_FFTX, launch_div_fftx<T>(g, f, I.L, k, I.px, I.rtw, sc.ck_dt, I.pi(), (const T*)nullptr,
+                                             c->stream));
       int rc = poisson<T>(c, I, f, f.phi);
       if (rc) return rc;
       if (c->diag && s == nsteps - 1 && k == 2) {
         int np = 0;
-        RUNK(c, K_DIAG, launch_diag<T>(g, f, sc.ck_dt, I.pi(), I.mean(), I.red_part, &np, c->stream));
+        RUNK(c, K_DIAG, launch_diag<T>(g, f, I.L, k, sc.ck_dt, I.pi(), I.mean(), I.red_part, &np, c->stream));
         RUNK(c, K_DIAG, launch_reduce_final(I.red_part, np, 0, 3, I.diag_out(), c->stream));
         I.diag_valid = true;
       }
-      RUNK(c, K_CORRECT, launch_correct<T>(g, f, sc.ck_dt, I.pi(), c->stream));
+      RUNK(c, K_CORRECT, launch_correct<T>(g, f, I.L, k, sc.ck_dt, I.pi(), c->stream));
     }
     I.step += 1;
     I.time += g.dt;
@@ -352,6 +349,14 @@ int set_geometry_impl(ibm_ctx* c, Instance& I, const double* su, const double* s
     free_buf(I.ibm_idx);
     free_buf(I.ibm_coef);
     free_buf(I.ibm_lam);
+    free_buf(I.ibm_choff);
+    const int cpr = (g.nx + IBM_WAVE - 1) / IBM_WAVE;
+    const size_t nch = (size_t)g.nrows * cpr + 1;
+    if (hipMalloc(&I.ibm_choff.p, 3 * nch * 4) != hipSuccess) {
+      rc = fail(c, IBM_ERR_OOM, "immersed-boundary chunk offsets");
+      break;
+    }
+    I.ibm_choff.bytes = 3 * nch * 4;
     const size_t nalloc = (size_t)std::max<int64_t>(ntot, 1);
     if (hipMalloc(&I.ibm_idx.p, nalloc * 4) != hipSuccess || hipMalloc(&I.ibm_coef.p, nalloc * 3 * 16) != hipSuccess ||
         hipMalloc(&I.ibm_lam.p, nalloc * 8) != hipSuccess) {
@@ -377,6 +382,17 @@ int set_geometry_impl(ibm_ctx* c, Instance& I, const double* su, const double* s
       off += I.n_ibm[q];
     }
     if (rc) break;
+    int32_t* choff = (int32_t*)I.ibm_choff.p;
+    for (int q = 0; q < 3 && !rc; ++q) {
+      e = launch_chunk_counts(I.tag, g, bmask[q], cpr, choff + q * nch, st);
+      if (e == hipSuccess) e = launch_scan_counts(choff + q * nch, (int)nch, I.itotal, st);
+      if (e != hipSuccess) rc = fail(c, IBM_ERR_DEVICE, std::string("chunk offsets: ") + hipGetErrorString(e));
+    }
+    if (rc) break;
+    I.L.choff_u = choff;
+    I.L.choff_v = choff + nch;
+    I.L.choff_w = choff + 2 * nch;
+    I.L.cpr = cpr;
     I.L.idx = idx;
     I.L.coef = coef;
     I.L.n_u = (int)I.n_ibm[0];
@@ -489,11 +505,13 @@ int ibm_solve_pressure(ibm_handle h, int32_t inst, const void* rhs, void* phi) {
   Instance& I = h->inst[inst];
   if (h->precision == IBM_FP64) {
     Fields<double> f = fields_of<double>(I);
-    RUNK(h, K_DIV_FFTX, launch_div_fftx<double>(I.g, f, I.px, I.rtw, 1.0, I.pi(), (const double*)rhs, h->stream));
+    RUNK(h, K_DIV_FFTX, launch_div_fftx<double>(I.g, f, I.L, 0, I.px, I.rtw, 1.0, I.pi(), (const double*)rhs,
+                                                 h->stream));
     return poisson<double>(h, I, f, (double*)phi);
   }
   Fields<float> f = fields_of<float>(I);
-  RUNK(h, K_DIV_FFTX, launch_div_fftx<float>(I.g, f, I.px, I.rtw, 1.0, I.pi(), (const float*)rhs, h->stream));
+  RUNK(h, K_DIV_FFTX, launch_div_fftx<float>(I.g, f, I.L, 0, I.px, I.rtw, 1.0, I.pi(), (const float*)rhs,
+                                              h->stream));
   return poisson<float>(h, I, f, (float*)phi);
 }
 
@@ -617,9 +635,8 @@ int ibm_profile_read(ibm_handle h, double* total_ms, int64_t* launches, int32_t 
 }
 
 const char* ibm_kernel_name(int32_t id) {
-  static const char* names[K_NUM_KERNELS] = {"momentum", "ibm_fix", "cfr", "ibm_pi", "div_fftx", "fftz_fwd",
-                                             "tri", "fftz_inv", "ifftx", "correct", "diag", "stats", "geom",
-                                             "copy"};
+  static const char* names[K_NUM_KERNELS] = {"momentum", "cfr", "ibm_pi", "div_fftx", "fftz_fwd", "tri", "fftz_inv",
+                                             "ifftx", "correct", "diag", "stats", "geom"};
   if (id < 0 || id >= K_NUM_KERNELS) return "unknown";
   return names[id];
 }
@@ -631,7 +648,7 @@ int64_t ibm_device_bytes(ibm_handle h) {
   int64_t b = 0;
   for (Instance& I : h->inst) {
     for (auto& x : I.bufs) b += (int64_t)x.bytes;
-    b += I.ibm_idx.bytes + I.ibm_coef.bytes + I.ibm_lam.bytes;
+    b += I.ibm_idx.bytes + I.ibm_coef.bytes + I.ibm_lam.bytes + I.ibm_choff.bytes;
   }
   return b;
 }
@@ -645,6 +662,7 @@ int ibm_destroy(ibm_handle h) {
     free_buf(I.ibm_idx);
     free_buf(I.ibm_coef);
     free_buf(I.ibm_lam);
+    free_buf(I.ibm_choff);
   }
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
   delete h;

@@ -20,8 +20,8 @@ enum : uint8_t {
 
 // Kernel ids (profiling).
 enum KernelId {
-  K_MOMENTUM = 0, K_IBM_FIX, K_CFR, K_IBM_PI, K_DIV_FFTX, K_FFTZ_FWD, K_TRI, K_FFTZ_INV,
-  K_IFFTX, K_CORRECT, K_DIAG, K_STATS, K_GEOM, K_COPY, K_NUM_KERNELS
+  K_MOMENTUM = 0, K_CFR, K_IBM_PI, K_DIV_FFTX, K_FFTZ_FWD, K_TRI, K_FFTZ_INV, K_IFFTX, K_CORRECT, K_DIAG, K_STATS,
+  K_GEOM, K_NUM_KERNELS
 };
 
 template <typename T>
@@ -115,11 +115,27 @@ struct StageConsts {
   int write_h;    // H needed by the next stage
 };
 
+// Immersed-boundary points: the three component lists, concatenated in linear cell
+// order.  choff_c[row * cpr + ch] is the number of points of component c that come
+// before the 64-wide chunk ch of grid row `row` (row = j * nz + k); a wavefront that
+// covers exactly one such chunk finds a point's list index as that offset plus the
+// number of flagged lanes below it (ballot).
 struct IbmLists {
   const int32_t* idx;      // [n_u | n_v | n_w] linear cell indices
   const double2* coef;     // [3 stages][n_total] (B, 1/A)
+  const int32_t* choff_u;
+  const int32_t* choff_v;
+  const int32_t* choff_w;
   int n_u, n_v, n_w, n_total;
+  int cpr;                 // 64-wide chunks per row
 };
+
+// Index bits of the lanes below `lane` in a 64-bit ballot.
+__device__ __forceinline__ int lanes_below(uint64_t mask, int lane) {
+  return __popcll(mask & ((1ull << lane) - 1ull));
+}
+
+
 
 template <typename T>
 struct Fields {
@@ -133,35 +149,33 @@ struct Fields {
 
 // step kernels
 template <typename T>
-hipError_t launch_momentum(const GridParams& g, const Fields<T>& f, const StageConsts& s, double* qpart,
-                           int* nqpart, hipStream_t st);
-template <typename T>
-hipError_t launch_ibm_fix(const GridParams& g, const Fields<T>& f, const IbmLists& L, int stage, double* qpart,
-                          int* nqpart, hipStream_t st);
+hipError_t launch_momentum(const GridParams& g, const Fields<T>& f, const IbmLists& L, const StageConsts& s,
+                           double* qpart, int* nqpart, hipStream_t st);
 hipError_t launch_cfr(const double* qpart, int nq, double scale, int forcing, double q_target_or_pi,
                       const double* S3, int stage, double* pi_out, double* pi_hist, hipStream_t st);
 template <typename T>
 hipError_t launch_ibm_pi(const Fields<T>& f, const IbmLists& L, int stage, double ck_dt, const double* pi,
                          hipStream_t st);
 template <typename T>
-hipError_t launch_div_fftx(const GridParams& g, const Fields<T>& f, const FFTPlan& px, const double2* rtw,
-                           double ck_dt, const double* pi, const T* rhs_in, hipStream_t st);
+hipError_t launch_div_fftx(const GridParams& g, const Fields<T>& f, const IbmLists& L, int stage,
+                           const FFTPlan& px, const double2* rtw, double ck_dt, const double* pi, const T* rhs_in,
+                           hipStream_t st);
 template <typename T>
 hipError_t launch_fftz(const GridParams& g, cplx<T>* spec, const FFTPlan& pz, int sign, hipStream_t st);
 template <typename T>
 hipError_t launch_tri(const GridParams& g, cplx<T>* spec, const double* kx2, const double* kz2,
-                      double* cp, double2* dp, double* mean_out, hipStream_t st);
+                      double* mean_out, hipStream_t st);
 template <typename T>
 hipError_t launch_ifftx(const GridParams& g, const cplx<T>* spec, T* out, const FFTPlan& px,
                         const double2* rtw, hipStream_t st);
 template <typename T>
-hipError_t launch_correct(const GridParams& g, const Fields<T>& f, double ck_dt, const double* pi,
-                          hipStream_t st);
+hipError_t launch_correct(const GridParams& g, const Fields<T>& f, const IbmLists& L, int stage, double ck_dt,
+                          const double* pi, hipStream_t st);
 
 // diagnostics
 template <typename T>
-hipError_t launch_diag(const GridParams& g, const Fields<T>& f, double ck_dt, const double* pi,
-                       const double* mean, double* part, int* npart, hipStream_t st);
+hipError_t launch_diag(const GridParams& g, const Fields<T>& f, const IbmLists& L, int stage, double ck_dt,
+                       const double* pi, const double* mean, double* part, int* npart, hipStream_t st);
 template <typename T>
 hipError_t launch_stats(const GridParams& g, const Fields<T>& f, double* part, int* npart, hipStream_t st);
 hipError_t launch_reduce_final(const double* part, int npart, int nsum, int nmax, double* out,
@@ -175,6 +189,8 @@ hipError_t launch_geom_ptag(const GridParams& g, uint8_t* tag, hipStream_t st);
 hipError_t launch_count_flags(const uint8_t* tag, int64_t n, uint8_t mask, int32_t* blk_counts,
                               int nblk, hipStream_t st);
 hipError_t launch_scan_counts(int32_t* blk_counts, int nblk, int32_t* total, hipStream_t st);
+hipError_t launch_chunk_counts(const uint8_t* tag, const GridParams& g, uint8_t mask, int cpr, int32_t* counts,
+                               hipStream_t st);
 hipError_t launch_compact(const uint8_t* tag, int64_t n, uint8_t mask, const int32_t* blk_offsets,
                           int32_t* idx_out, int nblk, hipStream_t st);
 hipError_t launch_ibm_coef(const int32_t* idx, const double* lam_dense, int n, double dt, int b_mode,

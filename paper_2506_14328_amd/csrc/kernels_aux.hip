@@ -140,6 +140,24 @@ __global__ __launch_bounds__(1024) void k_scan_counts(int32_t* __restrict__ coun
   if (threadIdx.x == 0) total[0] = carry;
 }
 
+// Flagged cells per 64-wide chunk of each grid row: counts[row * cpr + ch]; one extra
+// zero entry at the end, so that the scanned array also holds the total.
+__global__ __launch_bounds__(256) void k_chunk_counts(const uint8_t* __restrict__ tag, int nx, int nrows, int cpr,
+                                                     uint8_t mask, int32_t* __restrict__ counts) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e > nrows * cpr) return;
+  if (e == nrows * cpr) {
+    counts[e] = 0;
+    return;
+  }
+  const int row = e / cpr, ch = e - row * cpr;
+  const int a = ch * IBM_WAVE, b = min(a + IBM_WAVE, nx);
+  const uint8_t* t = tag + (size_t)row * nx;
+  int n = 0;
+  for (int i = a; i < b; ++i) n += (t[i] & mask) ? 1 : 0;
+  counts[e] = n;
+}
+
 // Write the ascending linear indices of flagged cells at their scanned offsets.
 __global__ __launch_bounds__(256) void k_compact(const uint8_t* __restrict__ tag, int64_t n, uint8_t mask,
                                                 const int32_t* __restrict__ offsets, int32_t* __restrict__ out) {
@@ -236,29 +254,40 @@ __device__ __forceinline__ double fval(const T* a, int c) { return (double)a[c];
 // Full-box divergence after the projection and before external faces are reset, the
 // Poisson residual D G phi - (rhs - mean) and max |rhs|.  part: [block][3] (max).
 template <typename T>
-__global__ __launch_bounds__(256) void k_diag(GridParams g, Fields<T> f, double ck_dt, const double* __restrict__ pi,
-                                             const double* __restrict__ mean, double* __restrict__ part) {
+__global__ __launch_bounds__(256) void k_diag(GridParams g, Fields<T> f, IbmLists L, int stage, double ck_dt,
+                                             const double* __restrict__ pi, const double* __restrict__ mean,
+                                             double* __restrict__ part) {
   __shared__ double red[4];
   const int i = blockIdx.x * BX + threadIdx.x;
   const int k = blockIdx.y * BZ + threadIdx.y;
   const int j = blockIdx.z;
+  const int lane = threadIdx.x;
+  const int nx = g.nx, nz = g.nz, plane = nx * nz;
+  const bool act = (i < nx) && (k < nz);
+  const int row = j * nz + k;
+  const int c = act ? row * nx + i : 0;
+  (void)L;
+  (void)stage;
+  (void)lane;
+  const double pk = pi[0] * ck_dt;
+  // u* on the west and east faces (immersed-boundary faces already hold their response)
+  auto ust = [&](int cc) {
+    const uint8_t t = f.tag[cc];
+    return fval(f.us, cc) - (((t & (TAG_U | TAG_UI)) == TAG_U) ? pk : 0.0);
+  };
+  double uw = 0.0, ue = 0.0;
+  if (act) {
+    uw = ust(c);
+    ue = ust(row * nx + wrap_p(i, nx));
+  }
   double dmax = 0.0, rmax = 0.0, hmax = 0.0;
-  if (i < g.nx && k < g.nz) {
-    const int nx = g.nx, nz = g.nz, plane = nx * nz;
+  if (act) {
     const int ip = wrap_p(i, nx), im = wrap_m(i, nx), kp = wrap_p(k, nz), km = wrap_m(k, nz);
-    const int c = (j * nz + k) * nx + i;
     const bool hasN = j + 1 < g.ny1, hasS = j > 0;
-    const double pk = pi[0] * ck_dt;
-    auto ust = [&](int cc) {
-      const uint8_t t = f.tag[cc];
-      return fval(f.us, cc) - (((t & (TAG_U | TAG_UI)) == TAG_U) ? pk : 0.0);
-    };
     const double ph = fval(f.phi, c);
     const double phe = fval(f.phi, c - i + ip), phw = fval(f.phi, c - i + im);
     const double pht = fval(f.phi, c + (kp - k) * nx), phb = fval(f.phi, c + (km - k) * nx);
     const double phn = hasN ? fval(f.phi, c + plane) : 0.0, phs = hasS ? fval(f.phi, c - plane) : 0.0;
-    // u* on the six faces
-    const double uw = ust(c), ue = ust(c - i + ip);
     const double vs = fval(f.vs, c), vn = hasN ? fval(f.vs, c + plane) : 0.0;
     const double wb = fval(f.ws, c), wt = fval(f.ws, c + (kp - k) * nx);
     // gradients of phi on the faces (no flux through the box walls)
@@ -268,8 +297,7 @@ __global__ __launch_bounds__(256) void k_diag(GridParams g, Fields<T> f, double 
     const double divs = (ue - uw) * g.idx + (vn - vs) * g.idy + (wt - wb) * g.idz;
     const double rhs = divs / ck_dt;
     const double dg = (gxe - gxw) * g.idx + (gyn - gys) * g.idy + (gzt - gzb) * g.idz;
-    const double unew_div = divs - ck_dt * dg;
-    dmax = fabs(unew_div);
+    dmax = fabs(divs - ck_dt * dg);
     rmax = fabs(dg - (rhs - mean[0]));
     hmax = fabs(rhs);
   }
@@ -379,6 +407,13 @@ hipError_t launch_scan_counts(int32_t* blk_counts, int nblk, int32_t* total, hip
   return hipGetLastError();
 }
 
+hipError_t launch_chunk_counts(const uint8_t* tag, const GridParams& g, uint8_t mask, int cpr, int32_t* counts,
+                               hipStream_t st) {
+  const int n = g.nrows * cpr + 1;
+  hipLaunchKernelGGL(k_chunk_counts, dim3((n + 255) / 256), dim3(256), 0, st, tag, g.nx, g.nrows, cpr, mask, counts);
+  return hipGetLastError();
+}
+
 hipError_t launch_compact(const uint8_t* tag, int64_t n, uint8_t mask, const int32_t* blk_offsets,
                           int32_t* idx_out, int nblk, hipStream_t st) {
   hipLaunchKernelGGL(k_compact, dim3(nblk), dim3(256), 0, st, tag, n, mask, blk_offsets, idx_out);
@@ -410,10 +445,10 @@ hipError_t launch_s_k_final(const double* part, int npart, double scale, double*
 }
 
 template <typename T>
-hipError_t launch_diag(const GridParams& g, const Fields<T>& f, double ck_dt, const double* pi,
-                       const double* mean, double* part, int* npart, hipStream_t st) {
+hipError_t launch_diag(const GridParams& g, const Fields<T>& f, const IbmLists& L, int stage, double ck_dt,
+                       const double* pi, const double* mean, double* part, int* npart, hipStream_t st) {
   const dim3 grid = cell_grid(g);
-  hipLaunchKernelGGL(k_diag<T>, grid, dim3(BX, BZ), 0, st, g, f, ck_dt, pi, mean, part);
+  hipLaunchKernelGGL(k_diag<T>, grid, dim3(BX, BZ), 0, st, g, f, L, stage, ck_dt, pi, mean, part);
   *npart = grid.x * grid.y * grid.z;
   return hipGetLastError();
 }
@@ -431,9 +466,9 @@ hipError_t launch_reduce_final(const double* part, int npart, int nsum, int nmax
   return hipGetLastError();
 }
 
-template hipError_t launch_diag<double>(const GridParams&, const Fields<double>&, double, const double*,
-                                        const double*, double*, int*, hipStream_t);
-template hipError_t launch_diag<float>(const GridParams&, const Fields<float>&, double, const double*,
-                                       const double*, double*, int*, hipStream_t);
+template hipError_t launch_diag<double>(const GridParams&, const Fields<double>&, const IbmLists&, int, double,
+                                        const double*, const double*, double*, int*, hipStream_t);
+template hipError_t launch_diag<float>(const GridParams&, const Fields<float>&, const IbmLists&, int, double,
+                                       const double*, const double*, double*, int*, hipStream_t);
 template hipError_t launch_stats<double>(const GridParams&, const Fields<double>&, double*, int*, hipStream_t);
 template hipError_t launch_stats<float>(const GridParams&, const Fields<float>&, double*, int*, hipStream_t);

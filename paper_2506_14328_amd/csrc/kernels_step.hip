@@ -1,8 +1,6 @@
 // Kernels of one RK3 substep (Sec. 2.4, Eq. (16), with the projection of Sec. 2.1):
-//   momentum   explicit right-hand side, RK combination, staircase update
-//   ibm_fix    implicit centre-weight update at immersed-boundary points
+//   momentum   explicit right-hand side, RK combination, implicit immersed-boundary update
 //   cfr        flow-rate reduction -> mean pressure gradient
-//   ibm_pi     pressure-gradient response at immersed-boundary u points
 //   div_fftx   divergence of u* fused with the real FFT along x
 //   fftz       complex FFT along z (forward / inverse)
 //   tri        wall-normal tridiagonal solve per Fourier mode (FP64 arithmetic)
@@ -21,138 +19,198 @@ __device__ __forceinline__ int wrap_m(int i, int n) { return (i == 0) ? n - 1 : 
 
 // ---------------------------------------------------------------------------------------
 // momentum: H = -N(u) + nu L(u) at internal points (external/ghost neighbours are zero),
-// r = dt (a_k H + b_k H_prev) - c_k dt G p, and the staircase predictor u* = u + r.  At
-// immersed-boundary points r is stored and completed by ibm_fix.  Per-block partial sums
-// of u* over internal non-IBM u points feed the flow-rate reduction.
+// r = dt (a_k H + b_k H_prev) - c_k dt G p, and the predictor u* = (B u + r) / A of
+// Eq. (16) (B = A = 1 away from the wall: u* = u + r).  Per-block partial sums of u*
+// over internal u points feed the flow-rate reduction.
+//
+// A block owns a 64 x 4 (x, z) column of cells and marches through a chunk of y
+// planes.  u, v, w live in a ring of three LDS planes (j-1, j, j+1) with a one-cell
+// halo in x and z; p in one LDS plane.  The loads of plane j+2 are issued before the
+// arithmetic of plane j and written to the ring slot of plane j-1 afterwards.
+// Planes outside the box (ghost rows, the north wall face of v) are zero.
 // ---------------------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) void k_momentum(GridParams g, Fields<T> f, StageConsts s,
-                                                 double* __restrict__ qpart) {
-  const int i = blockIdx.x * BX + threadIdx.x;
-  const int k = blockIdx.y * BZ + threadIdx.y;
-  const int j = blockIdx.z;
-  __shared__ double red[4];
-  double qloc = 0.0;
-  if (i < g.nx && k < g.nz) {
-    const int nx = g.nx, nz = g.nz;
-    const int ip = wrap_p(i, nx), im = wrap_m(i, nx);
-    const int kp = wrap_p(k, nz), km = wrap_m(k, nz);
-    const int plane = nx * nz;
-    const int c = (j * nz + k) * nx + i;
-    const int cim = c - i + im, cip = c - i + ip;
-    const int ckp = c + (kp - k) * nx, ckm = c + (km - k) * nx;
-    const bool hasN = (j + 1 < g.ny1), hasS = (j > 0);
-    const uint8_t tg = f.tag[c];
-    const T h = T(0.5), two = T(2);
-    const T idx = T(g.idx), idy = T(g.idy), idz = T(g.idz);
-    const T idx2 = T(g.idx2), idy2 = T(g.idy2), idz2 = T(g.idz2), nu = T(g.nu);
-    const T akdt = T(s.ak_dt), bkdt = T(s.bk_dt), ckdt = T(s.ck_dt);
-    const T* __restrict__ u = f.u;
-    const T* __restrict__ v = f.v;
-    const T* __restrict__ w = f.w;
-    const T* __restrict__ p = f.p;
-    const T zero = T(0);
+constexpr int MX = 64, MZ = 4;
+constexpr int MHX = MX + 2, MHZ = MZ + 2, MTILE = MHX * MHZ;   // 396 values per plane tile
+constexpr int MLOADS = (MTILE + 255) / 256;                     // tile values per thread
 
-    // ---- u-momentum at (i dx, y_c[j], z_c[k])
-    if (tg & TAG_U) {
-      const T uc = u[c], ue = u[cip], uw = u[cim];
-      const T un = hasN ? u[c + plane] : zero, usb = hasS ? u[c - plane] : zero;
-      const T ut = u[ckp], ub = u[ckm];
-      const T vnw = hasN ? v[cim + plane] : zero, vne = hasN ? v[c + plane] : zero;
-      const T vsw = v[cim], vse = v[c];
-      const T wtw = w[ckp - i + im], wte = w[ckp];
-      const T wbw = w[cim], wbe = w[c];
+template <typename T>
+__global__ __launch_bounds__(256) void k_momentum(GridParams g, Fields<T> f, IbmLists L, StageConsts s, int jc,
+                                                 double* __restrict__ qpart) {
+  __shared__ T ring[3][3][MTILE];   // [field u,v,w][slot][tile]
+  __shared__ T ptile[MTILE];
+  __shared__ double red[4];
+  const int tx = threadIdx.x, tz = threadIdx.y, tid = tz * MX + tx;
+  const int nx = g.nx, nz = g.nz, ny1 = g.ny1, plane = nx * nz;
+  const int i0 = blockIdx.x * MX, k0 = blockIdx.y * MZ;
+  const int j0 = blockIdx.z * jc;
+  const int j1 = min(j0 + jc, ny1);
+  const int i = i0 + tx, k = k0 + tz;
+  const bool act = (i < nx) && (k < nz);
+  // tile element -> offset inside a plane (periodic wrap in x and z)
+  int off[MLOADS];
+  bool has[MLOADS];
+#pragma unroll
+  for (int r = 0; r < MLOADS; ++r) {
+    const int e = tid + 256 * r;
+    has[r] = e < MTILE;
+    const int lz = e / MHX, lx = e - lz * MHX;
+    int gz = (k0 - 1 + lz) % nz;
+    if (gz < 0) gz += nz;
+    int gx = (i0 - 1 + lx) % nx;
+    if (gx < 0) gx += nx;
+    off[r] = gz * nx + gx;
+  }
+  auto fetch = [&](const T* __restrict__ a, int jj, T* reg) {
+#pragma unroll
+    for (int r = 0; r < MLOADS; ++r)
+      reg[r] = (has[r] && jj >= 0 && jj < ny1) ? a[jj * plane + off[r]] : T(0);
+  };
+  auto put = [&](T* dst, const T* reg) {
+#pragma unroll
+    for (int r = 0; r < MLOADS; ++r)
+      if (has[r]) dst[tid + 256 * r] = reg[r];
+  };
+  auto slot = [](int jj) { return (jj + 3) % 3; };
+  // prologue: planes j0-1, j0, j0+1 of u, v, w and plane j0 of p
+  {
+    T ru[MLOADS], rv[MLOADS], rw[MLOADS];
+    for (int jj = j0 - 1; jj <= j0 + 1; ++jj) {
+      fetch(f.u, jj, ru);
+      fetch(f.v, jj, rv);
+      fetch(f.w, jj, rw);
+      put(ring[0][slot(jj)], ru);
+      put(ring[1][slot(jj)], rv);
+      put(ring[2][slot(jj)], rw);
+    }
+    fetch(f.p, j0, ru);
+    put(ptile, ru);
+  }
+  const int cc = (tz + 1) * MHX + (tx + 1);   // centre inside a tile
+  T p_prev = (act && j0 > 0) ? f.p[(j0 - 1) * plane + k * nx + i] : T(0);
+  __syncthreads();
+
+  const T h = T(0.5), two = T(2), zero = T(0);
+  const T idx = T(g.idx), idy = T(g.idy), idz = T(g.idz);
+  const T idx2 = T(g.idx2), idy2 = T(g.idy2), idz2 = T(g.idz2), nu = T(g.nu);
+  const T akdt = T(s.ak_dt), bkdt = T(s.bk_dt), ckdt = T(s.ck_dt);
+  double qloc = 0.0;
+
+  for (int j = j0; j < j1; ++j) {
+    // prefetch plane j+2 of u, v, w and plane j+1 of p
+    T nu_[MLOADS], nv_[MLOADS], nw_[MLOADS], np_[MLOADS];
+    fetch(f.u, j + 2, nu_);
+    fetch(f.v, j + 2, nv_);
+    fetch(f.w, j + 2, nw_);
+    fetch(f.p, j + 1 < j1 ? j + 1 : -1, np_);
+    const int c = j * plane + k * nx + i;
+    const uint8_t tg = act ? f.tag[c] : 0;
+    T hu = zero, hv = zero, hw = zero;
+    if (act) {
+      if (s.use_hold) {
+        hu = f.Hu[c];
+        hv = f.Hv[c];
+        hw = f.Hw[c];
+      }
+    }
+    const T* U0 = ring[0][slot(j)];
+    const T* Um = ring[0][slot(j - 1)];
+    const T* Up = ring[0][slot(j + 1)];
+    const T* V0 = ring[1][slot(j)];
+    const T* Vm = ring[1][slot(j - 1)];
+    const T* Vp = ring[1][slot(j + 1)];
+    const T* W0 = ring[2][slot(j)];
+    const T* Wm = ring[2][slot(j - 1)];
+    const T* Wp = ring[2][slot(j + 1)];
+    const T uc = U0[cc], ue = U0[cc + 1], uw = U0[cc - 1], ut = U0[cc + MHX], ub = U0[cc - MHX];
+    const T un = Up[cc], usb = Um[cc], u_ip_s = Um[cc + 1], u_ip_km = U0[cc - MHX + 1];
+    const T vc = V0[cc], ve = V0[cc + 1], vw = V0[cc - 1], vt = V0[cc + MHX], vb = V0[cc - MHX];
+    const T vn = Vp[cc], vs0 = Vm[cc], v_im_n = Vp[cc - 1], v_km_n = Vp[cc - MHX];
+    const T wc = W0[cc], we = W0[cc + 1], ww = W0[cc - 1], wt = W0[cc + MHX], wb = W0[cc - MHX];
+    const T wn = Wp[cc], wsb = Wm[cc], w_kp_im = W0[cc + MHX - 1], w_kp_s = Wm[cc + MHX];
+    const T pc = ptile[cc], pw = ptile[cc - 1], pb = ptile[cc - MHX], ps = p_prev;
+
+    // u-momentum at (i dx, y_c[j], z_c[k])
+    T Hu, ru;
+    {
       const T a1 = h * (uc + ue), a0 = h * (uw + uc);
       const T N = (a1 * a1 - a0 * a0) * idx +
-                  (h * (uc + un) * h * (vnw + vne) - h * (usb + uc) * h * (vsw + vse)) * idy +
-                  (h * (uc + ut) * h * (wtw + wte) - h * (ub + uc) * h * (wbw + wbe)) * idz;
+                  (h * (uc + un) * h * (v_im_n + vn) - h * (usb + uc) * h * (vw + vc)) * idy +
+                  (h * (uc + ut) * h * (w_kp_im + wt) - h * (ub + uc) * h * (ww + wc)) * idz;
       const T L = (ue - two * uc + uw) * idx2 + (un - two * uc + usb) * idy2 + (ut - two * uc + ub) * idz2;
-      const T H = -N + nu * L;
-      const T G = (p[c] - p[cim]) * idx;
-      T r = akdt * H - ckdt * G;
-      if (s.use_hold) r += bkdt * f.Hu[c];
-      if (s.write_h) f.Hu[c] = H;
-      const bool ib = (tg & TAG_UI) != 0;
-      const T val = ib ? r : uc + r;
-      f.us[c] = val;
-      if (!ib) qloc = (double)val;
-    } else {
-      f.us[c] = zero;
+      Hu = -N + nu * L;
+      ru = akdt * Hu - ckdt * ((pc - pw) * idx);
+      if (s.use_hold) ru += bkdt * hu;
     }
-
-    // ---- v-momentum at (x_c[i], y_f[j], z_c[k]); internal v never sits on face 0
-    if (tg & TAG_V) {
-      const T vc = v[c], ve = v[cip], vw = v[cim];
-      const T vn = hasN ? v[c + plane] : zero, vsb = v[c - plane];
-      const T vt = v[ckp], vb = v[ckm];
-      const T ue_s = u[cip - plane], ue_n = u[cip], uw_s = u[c - plane], uw_n = u[c];
-      const T wt_s = w[ckp - plane], wt_n = w[ckp], wb_s = w[c - plane], wb_n = w[c];
-      const T b1 = h * (vc + vn), b0 = h * (vsb + vc);
-      const T N = (h * (vc + ve) * h * (ue_s + ue_n) - h * (vw + vc) * h * (uw_s + uw_n)) * idx +
+    // v-momentum at (x_c[i], y_f[j], z_c[k]); only stored where v is internal (j >= 1)
+    T Hv, rv;
+    {
+      const T b1 = h * (vc + vn), b0 = h * (vs0 + vc);
+      const T N = (h * (vc + ve) * h * (u_ip_s + ue) - h * (vw + vc) * h * (usb + uc)) * idx +
                   (b1 * b1 - b0 * b0) * idy +
-                  (h * (vc + vt) * h * (wt_s + wt_n) - h * (vb + vc) * h * (wb_s + wb_n)) * idz;
-      const T L = (ve - two * vc + vw) * idx2 + (vn - two * vc + vsb) * idy2 + (vt - two * vc + vb) * idz2;
-      const T H = -N + nu * L;
-      const T G = (p[c] - p[c - plane]) * idy;
-      T r = akdt * H - ckdt * G;
-      if (s.use_hold) r += bkdt * f.Hv[c];
-      if (s.write_h) f.Hv[c] = H;
-      f.vs[c] = (tg & TAG_VI) ? r : vc + r;
-    } else {
-      f.vs[c] = zero;
+                  (h * (vc + vt) * h * (w_kp_s + wt) - h * (vb + vc) * h * (wsb + wc)) * idz;
+      const T L = (ve - two * vc + vw) * idx2 + (vn - two * vc + vs0) * idy2 + (vt - two * vc + vb) * idz2;
+      Hv = -N + nu * L;
+      rv = akdt * Hv - ckdt * ((pc - ps) * idy);
+      if (s.use_hold) rv += bkdt * hv;
     }
-
-    // ---- w-momentum at (x_c[i], y_c[j], k dz)
-    if (tg & TAG_W) {
-      const T wc = w[c], we = w[cip], ww = w[cim];
-      const T wn = hasN ? w[c + plane] : zero, wsb = hasS ? w[c - plane] : zero;
-      const T wt = w[ckp], wb = w[ckm];
-      const T ue_b = u[ckm - i + ip], ue_t = u[cip], uw_b = u[ckm], uw_t = u[c];
-      const T vn_b = hasN ? v[ckm + plane] : zero, vn_t = hasN ? v[c + plane] : zero;
-      const T vs_b = v[ckm], vs_t = v[c];
+    // w-momentum at (x_c[i], y_c[j], k dz)
+    T Hw, rw;
+    {
       const T c1 = h * (wc + wt), c0 = h * (wb + wc);
-      const T N = (h * (wc + we) * h * (ue_b + ue_t) - h * (ww + wc) * h * (uw_b + uw_t)) * idx +
-                  (h * (wc + wn) * h * (vn_b + vn_t) - h * (wsb + wc) * h * (vs_b + vs_t)) * idy +
+      const T N = (h * (wc + we) * h * (u_ip_km + ue) - h * (ww + wc) * h * (ub + uc)) * idx +
+                  (h * (wc + wn) * h * (v_km_n + vn) - h * (wsb + wc) * h * (vb + vc)) * idy +
                   (c1 * c1 - c0 * c0) * idz;
       const T L = (we - two * wc + ww) * idx2 + (wn - two * wc + wsb) * idy2 + (wt - two * wc + wb) * idz2;
-      const T H = -N + nu * L;
-      const T G = (p[c] - p[ckm]) * idz;
-      T r = akdt * H - ckdt * G;
-      if (s.use_hold) r += bkdt * f.Hw[c];
-      if (s.write_h) f.Hw[c] = H;
-      f.ws[c] = (tg & TAG_WI) ? r : wc + r;
-    } else {
-      f.ws[c] = zero;
+      Hw = -N + nu * L;
+      rw = akdt * Hw - ckdt * ((pc - pb) * idz);
+      if (s.use_hold) rw += bkdt * hw;
     }
+    // immersed-boundary points: list index = chunk offset + flagged lanes below (the
+    // wavefront is the 64-wide chunk blockIdx.x of row j*nz + k)
+    const uint64_t mu = __ballot((tg & TAG_UI) != 0);
+    const uint64_t mv = __ballot((tg & TAG_VI) != 0);
+    const uint64_t mw = __ballot((tg & TAG_WI) != 0);
+    if (act) {
+      if (s.write_h) {
+        f.Hu[c] = Hu;
+        f.Hv[c] = Hv;
+        f.Hw[c] = Hw;
+      }
+      T su = zero, sv = zero, sw = zero;
+      if (tg & TAG_U) su = uc + ru;
+      if (tg & TAG_V) sv = vc + rv;
+      if (tg & TAG_W) sw = wc + rw;
+      if (tg & (TAG_UI | TAG_VI | TAG_WI)) {
+        const int ch = (j * nz + k) * L.cpr + blockIdx.x;
+        const size_t cb = (size_t)s.stage * L.n_total;
+        if (tg & TAG_UI) {
+          const double2 cf = L.coef[cb + L.choff_u[ch] + lanes_below(mu, tx)];
+          su = T((cf.x * (double)uc + (double)ru) * cf.y);
+        }
+        if (tg & TAG_VI) {
+          const double2 cf = L.coef[cb + L.n_u + L.choff_v[ch] + lanes_below(mv, tx)];
+          sv = T((cf.x * (double)vc + (double)rv) * cf.y);
+        }
+        if (tg & TAG_WI) {
+          const double2 cf = L.coef[cb + L.n_u + L.n_v + L.choff_w[ch] + lanes_below(mw, tx)];
+          sw = T((cf.x * (double)wc + (double)rw) * cf.y);
+        }
+      }
+      f.us[c] = su;
+      f.vs[c] = sv;
+      f.ws[c] = sw;
+      if (tg & TAG_U) qloc += (double)su;
+    }
+    p_prev = pc;
+    __syncthreads();
+    put(ring[0][slot(j + 2)], nu_);
+    put(ring[1][slot(j + 2)], nv_);
+    put(ring[2][slot(j + 2)], nw_);
+    put(ptile, np_);
+    __syncthreads();
   }
   const double tot = block_reduce<false>(qloc, red);
-  if (threadIdx.x == 0 && threadIdx.y == 0)
-    qpart[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = tot;
-}
-
-// ---------------------------------------------------------------------------------------
-// ibm_fix: (B u + r) / A at immersed-boundary points (Eq. (16)); u* holds r there.
-// ---------------------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) void k_ibm_fix(Fields<T> f, IbmLists L, int stage, double* __restrict__ qpart) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  __shared__ double red[4];
-  double q = 0.0;
-  if (g < L.n_total) {
-    const int id = L.idx[g];
-    const double2 cf = L.coef[(size_t)stage * L.n_total + g];
-    if (g < L.n_u) {
-      const T val = T((cf.x * (double)f.u[id] + (double)f.us[id]) * cf.y);
-      f.us[id] = val;
-      q = (double)val;
-    } else if (g < L.n_u + L.n_v) {
-      f.vs[id] = T((cf.x * (double)f.v[id] + (double)f.vs[id]) * cf.y);
-    } else {
-      f.ws[id] = T((cf.x * (double)f.w[id] + (double)f.ws[id]) * cf.y);
-    }
-  }
-  const double tot = block_reduce<false>(q, red);
-  if (threadIdx.x == 0) qpart[blockIdx.x] = tot;
+  if (tid == 0) qpart[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = tot;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -164,8 +222,16 @@ __global__ __launch_bounds__(1024) void k_cfr(const double* __restrict__ qpart, 
                                               int stage, double* __restrict__ pi_out,
                                               double* __restrict__ pi_hist) {
   __shared__ double red[16];
-  double s = 0.0;
-  for (int e = threadIdx.x; e < nq; e += blockDim.x) s += qpart[e];
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const int stride = blockDim.x * 8;
+  for (int base = threadIdx.x; base < nq; base += stride) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int e = base + r * blockDim.x;
+      if (e < nq) acc[r] += qpart[e];
+    }
+  }
+  const double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
   const double tot = block_reduce<false>(s, red);
   if (threadIdx.x == 0) {
     const double q0 = tot * scale;
@@ -176,7 +242,8 @@ __global__ __launch_bounds__(1024) void k_cfr(const double* __restrict__ qpart, 
   }
 }
 
-// u* <- u* - Pi c_k dt / A at immersed-boundary u points (the rest is applied on the fly).
+// u* <- u* - Pi c_k dt / A at immersed-boundary u points; div_fftx, correct and the
+// diagnostics apply -Pi c_k dt to the other internal u faces themselves.
 template <typename T>
 __global__ __launch_bounds__(256) void k_ibm_pi(Fields<T> f, IbmLists L, int stage, double ck_dt,
                                                const double* __restrict__ pi) {
@@ -188,7 +255,7 @@ __global__ __launch_bounds__(256) void k_ibm_pi(Fields<T> f, IbmLists L, int sta
   }
 }
 
-// u* on a u face including the pending -Pi c_k dt at internal non-IBM faces.
+// u* on a u face: internal non-IBM faces still owe -Pi c_k dt (= pick).
 template <typename T>
 __device__ __forceinline__ T ustar_at(const Fields<T>& f, int c, T pick) {
   const uint8_t tg = f.tag[c];
@@ -201,19 +268,21 @@ __device__ __forceinline__ T ustar_at(const Fields<T>& f, int c, T pick) {
 // transformed, and unpacked to X_m, m = 0..nx/2.  One wavefront per row, 4 rows/block.
 // If rhs_in is given, it replaces the divergence (stand-alone Poisson solve).
 // ---------------------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) void k_div_fftx(GridParams g, Fields<T> f, FFTPlan px,
+template <typename T, int MB>
+__global__ __launch_bounds__(256) void k_div_fftx(GridParams g, Fields<T> f, IbmLists L, int stage, FFTPlan px,
                                                  const double2* __restrict__ rtw, double ck_dt,
                                                  const double* __restrict__ pi, const T* __restrict__ rhs_in) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* sm = reinterpret_cast<cplx<T>*>(smem_raw);
   const int N = g.nhalf;
+  const int RB = blockDim.x / IBM_WAVE;        // rows per block, one wavefront per row
   const int grp = threadIdx.x / IBM_WAVE, lane = threadIdx.x % IBM_WAVE;
-  const int row = blockIdx.x * 4 + grp;
-  cplx<T>* A = sm + grp * 2 * N;
-  cplx<T>* B = A + N;
-  const bool valid = row < g.nrows;
+  const int row = blockIdx.x * RB + grp;
   const int nx = g.nx;
+  cplx<T>* A = sm + grp * N;
+  cplx<T>* tw = sm + RB * N;
+  load_twiddles<T>(tw, px, threadIdx.x, blockDim.x);
+  const bool valid = row < g.nrows;
   if (valid) {
     T* Ar = reinterpret_cast<T*>(A);   // interleaved (re, im) == packed reals
     if (rhs_in) {
@@ -237,7 +306,8 @@ __global__ __launch_bounds__(256) void k_div_fftx(GridParams g, Fields<T> f, FFT
     }
   }
   __syncthreads();
-  cplx<T>* R = fft_lds<T>(A, B, 1, px, -1, lane, IBM_WAVE);
+  fft_lds<T, MB>(A, 1, px, tw, -1, lane, IBM_WAVE);
+  const cplx<T>* R = A;
   if (valid) {
     cplx<T>* out = f.spec + (size_t)row * g.mh;
     for (int m = lane; m <= N; m += IBM_WAVE) {
@@ -255,13 +325,14 @@ __global__ __launch_bounds__(256) void k_div_fftx(GridParams g, Fields<T> f, FFT
 // ---------------------------------------------------------------------------------------
 // fftz: complex FFT along z of the half spectrum, W consecutive x modes per block.
 // ---------------------------------------------------------------------------------------
-template <typename T>
+template <typename T, int MB>
 __global__ __launch_bounds__(256) void k_fftz(GridParams g, cplx<T>* __restrict__ spec, FFTPlan pz, int sign,
                                              int W) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem_raw);
   const int nz = g.nz, mh = g.mh;
-  cplx<T>* B = A + nz * W;
+  cplx<T>* tw = A + nz * W;
+  load_twiddles<T>(tw, pz, threadIdx.x, blockDim.x);
   const int j = blockIdx.y;
   const int m0 = blockIdx.x * W;
   cplx<T>* base = spec + (size_t)j * nz * mh;
@@ -271,8 +342,8 @@ __global__ __launch_bounds__(256) void k_fftz(GridParams g, cplx<T>* __restrict_
   }
   __syncthreads();
   const int w = threadIdx.x % W, lane = threadIdx.x / W, nl = blockDim.x / W;
-  fft_lds<T>(A + w, B + w, W, pz, sign, lane, nl);
-  const cplx<T>* R = (pz.nst & 1) ? B : A;
+  fft_lds<T, MB>(A + w, W, pz, tw, sign, lane, nl);
+  const cplx<T>* R = A;
   for (int e = threadIdx.x; e < nz * W; e += blockDim.x) {
     const int kz = e / W, ww = e - kz * W, m = m0 + ww;
     if (m < mh) base[kz * mh + m] = R[e];
@@ -284,79 +355,235 @@ __global__ __launch_bounds__(256) void k_fftz(GridParams g, cplx<T>* __restrict_
 //   (phi_{j+1} - 2 phi_j + phi_{j-1}) / dy^2 - (kx^2 + kz^2) phi_j = rhat_j / (nx nz)
 // with -1 instead of -2 in the first and last rows (no flux through the box walls).
 // Mode (0,0): its mean over j is removed, the first row becomes phi_0 = 0, and the
-// mean of the solution is removed.  Thomas algorithm in FP64, one thread per mode.
+// mean of the solution is removed.
+//
+// Partition (divide-and-conquer) solver, FP64 arithmetic in registers and LDS:
+// P threads per mode each own a segment of L <= 8 consecutive rows.  Within its
+// segment a thread eliminates the sub-diagonal downwards and the super-diagonal
+// upwards, leaving every interior unknown expressed through the segment's first (F)
+// and last (E) unknowns.  The 2P equations of the F and E unknowns form a
+// tridiagonal system (ordered F0 E0 F1 E1 ...) solved by parallel cyclic reduction
+// in LDS; each thread then recovers its interior rows.  The spectrum is read once
+// and written once.  W = 256/P modes per block, lane = p * W + w.
 // ---------------------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_tri(GridParams g, cplx<T>* __restrict__ spec,
                                             const double* __restrict__ kx2, const double* __restrict__ kz2,
-                                            double* __restrict__ cp, double2* __restrict__ dp,
-                                            double* __restrict__ mean_out) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  const int Q = g.nmodes;
-  if (q >= Q) return;
-  const int n = g.ny1;
-  const int kz = q / g.mh, m = q - kz * g.mh;
-  const double K2 = kx2[m] + kz2[kz];
+                                            int P, int W, double* __restrict__ mean_out) {
+  constexpr int LM = 8;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* lds = reinterpret_cast<double*>(smem_raw);
+  const int n = g.ny1, Q = g.nmodes;
+  const int tid = threadIdx.x;
+  const int w = tid % W, p = tid / W;
+  const bool active = p < P;
+  const int q = blockIdx.x * W + w;
+  const bool valid = active && q < Q;
+  const int r0 = (int)(((int64_t)p * n) / P);
+  const int r1 = active ? (int)(((int64_t)(p + 1) * n) / P) : r0;
+  const int L = r1 - r0;
   const double a = g.idy2;
   const double norm = 1.0 / ((double)g.nx * (double)g.nz);
-  const bool zero = (q == 0);
+  const int N2 = 2 * P;
+  double* Rl = lds;                 // [2P][W] reduced system (mode fastest)
+  double* Rd = Rl + W * N2;
+  double* Ru = Rd + W * N2;
+  double* Rr = Ru + W * N2;
+  double* Ri = Rr + W * N2;
+  double* red = Ri + W * N2;        // [2P] sums of the (0,0) mode
+  double K2 = 0.0;
+  if (valid) {
+    const int kz = q / g.mh, m = q - kz * g.mh;
+    K2 = kx2[m] + kz2[kz];
+  }
+  const bool zmode = valid && q == 0;
+  double dr[LM], di[LM];
+#pragma unroll
+  for (int t = 0; t < LM; ++t) {
+    dr[t] = 0.0;
+    di[t] = 0.0;
+    if (valid && t < L) {
+      const cplx<T> v = spec[(size_t)(r0 + t) * Q + q];
+      dr[t] = (double)v.x;
+      di[t] = (double)v.y;
+    }
+  }
+  // mean of the (0,0) mode over j (only block 0 holds it, at w = 0)
   double mr = 0.0, mi = 0.0;
-  if (zero) {
-    for (int j = 0; j < n; ++j) {
-      const cplx<T> r = spec[(size_t)j * Q];
-      mr += (double)r.x;
-      mi += (double)r.y;
+  if (blockIdx.x == 0) {
+    if (w == 0 && active) {
+      double sr = 0.0, si = 0.0;
+#pragma unroll
+      for (int t = 0; t < LM; ++t)
+        if (t < L) { sr += dr[t]; si += di[t]; }
+      red[p] = sr;
+      red[P + p] = si;
     }
-    mr /= n;
-    mi /= n;
-    mean_out[0] = mr * norm;
+    __syncthreads();
+    if (w == 0) {
+      for (int pp = 0; pp < P; ++pp) { mr += red[pp]; mi += red[P + pp]; }
+      mr /= n;
+      mi /= n;
+      if (tid == 0) mean_out[0] = mr * norm;
+    }
+    __syncthreads();
   }
-  double cprev = 0.0, dpr = 0.0, dpi = 0.0;
-  for (int j = 0; j < n; ++j) {
-    const cplx<T> r = spec[(size_t)j * Q + q];
-    double rr = ((double)r.x - mr) * norm, ri = ((double)r.y - mi) * norm;
+  // row coefficients of global row r
+  auto lo_of = [&](int r) { return r == 0 ? 0.0 : a; };
+  auto up_of = [&](int r) { return (r == n - 1 || (zmode && r == 0)) ? 0.0 : a; };
+  auto di_of = [&](int r) {
+    if (zmode && r == 0) return 1.0;
     double b = -2.0 * a - K2;
-    if (j == 0 || j == n - 1) b += a;
-    double up = (j == n - 1) ? 0.0 : a;
-    const double lo = (j == 0) ? 0.0 : a;
-    if (zero && j == 0) {
-      b = 1.0;
-      up = 0.0;
-      rr = 0.0;
-      ri = 0.0;
-    }
-    const double den = b - lo * cprev;
-    const double cj = up / den;
-    dpr = (rr - lo * dpr) / den;
-    dpi = (ri - lo * dpi) / den;
-    cprev = cj;
-    cp[(size_t)j * Q + q] = cj;
-    dp[(size_t)j * Q + q] = make_double2(dpr, dpi);
+    if (r == 0) b += a;
+    if (r == n - 1) b += a;
+    return b;
+  };
+#pragma unroll
+  for (int t = 0; t < LM; ++t) {
+    dr[t] = (dr[t] - mr) * norm;
+    di[t] = (di[t] - mi) * norm;
   }
-  double xr = dpr, xi = dpi;
-  double sr = xr, si = xi;
-  if (zero) dp[(size_t)(n - 1) * Q] = make_double2(xr, xi);
-  else spec[(size_t)(n - 1) * Q + q] = cplx<T>{T(xr), T(xi)};
-  for (int j = n - 2; j >= 0; --j) {
-    const double cj = cp[(size_t)j * Q + q];
-    const double2 dj = dp[(size_t)j * Q + q];
-    xr = dj.x - cj * xr;
-    xi = dj.y - cj * xi;
-    if (zero) {
-      sr += xr;
-      si += xi;
-      dp[(size_t)j * Q] = make_double2(xr, xi);
+  if (zmode && r0 == 0) { dr[0] = 0.0; di[0] = 0.0; }
+  // downward elimination: rows t >= 1 become al[t] x0 + be[t] x_t + up x_{t+1} = d_t
+  double al[LM], be[LM], ga[LM];
+#pragma unroll
+  for (int t = 0; t < LM; ++t) { al[t] = 0.0; be[t] = 1.0; ga[t] = 0.0; }
+  if (valid) {
+    al[1] = lo_of(r0 + 1);
+    be[1] = di_of(r0 + 1);
+#pragma unroll
+    for (int t = 2; t < LM; ++t) {
+      if (t < L) {
+        const double m = lo_of(r0 + t) / be[t - 1];
+        al[t] = -m * al[t - 1];
+        be[t] = di_of(r0 + t) - m * up_of(r0 + t - 1);
+        dr[t] -= m * dr[t - 1];
+        di[t] -= m * di[t - 1];
+      }
+    }
+    // upward elimination: rows 1..L-2 become al[t] x0 + be[t] x_t + ga[t] x_{L-1} = d_t
+    if (L >= 3) {
+#pragma unroll
+      for (int t = 1; t < LM; ++t)
+        if (t == L - 2) ga[t] = up_of(r0 + t);
+#pragma unroll
+      for (int t = LM - 3; t >= 1; --t) {
+        if (t <= L - 3) {
+          const double m = up_of(r0 + t) / be[t + 1];
+          al[t] -= m * al[t + 1];
+          ga[t] = -m * ga[t + 1];
+          dr[t] -= m * dr[t + 1];
+          di[t] -= m * di[t + 1];
+        }
+      }
+    }
+    // reduced equations of F = x_0 and E = x_{L-1}
+    const int eF = (2 * p) * W + w, eE = eF + W;
+    double dL = dr[0], dLi = di[0];
+#pragma unroll
+    for (int t = 1; t < LM; ++t)
+      if (t == L - 1) { dL = dr[t]; dLi = di[t]; }
+    double alL = 0.0, beL = 1.0;
+#pragma unroll
+    for (int t = 1; t < LM; ++t)
+      if (t == L - 1) { alL = al[t]; beL = be[t]; }
+    Rl[eE] = alL;
+    Rd[eE] = beL;
+    Ru[eE] = up_of(r1 - 1);
+    Rr[eE] = dL;
+    Ri[eE] = dLi;
+    Rl[eF] = lo_of(r0);
+    if (L >= 3) {
+      const double m = up_of(r0) / be[1];
+      Rd[eF] = di_of(r0) - m * al[1];
+      Ru[eF] = -m * ga[1];
+      Rr[eF] = dr[0] - m * dr[1];
+      Ri[eF] = di[0] - m * di[1];
     } else {
-      spec[(size_t)j * Q + q] = cplx<T>{T(xr), T(xi)};
+      Rd[eF] = di_of(r0);
+      Ru[eF] = up_of(r0);
+      Rr[eF] = dr[0];
+      Ri[eF] = di[0];
     }
   }
-  if (zero) {
-    sr /= n;
-    si /= n;
-    for (int j = 0; j < n; ++j) {
-      const double2 x = dp[(size_t)j * Q];
-      spec[(size_t)j * Q] = cplx<T>{T(x.x - sr), T(x.y - si)};
+  __syncthreads();
+  // Parallel cyclic reduction of the reduced system: each thread owns rows 2p and 2p+1 of
+  // its mode; at stride s every row eliminates its couplings to rows e-s and e+s.
+  for (int st = 1; st < N2; st <<= 1) {
+    double nl[2], nd[2], nu[2], nr[2], ni[2];
+    if (valid) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int e = 2 * p + h;
+        const int ie = e * W + w;
+        double l = Rl[ie], d = Rd[ie], u = Ru[ie], r = Rr[ie], im = Ri[ie];
+        double l2 = 0.0, u2 = 0.0;
+        if (e - st >= 0) {
+          const int j = (e - st) * W + w;
+          const double k1 = l / Rd[j];
+          l2 = -Rl[j] * k1;
+          d -= Ru[j] * k1;
+          r -= Rr[j] * k1;
+          im -= Ri[j] * k1;
+        }
+        if (e + st < N2) {
+          const int j = (e + st) * W + w;
+          const double k2 = u / Rd[j];
+          u2 = -Ru[j] * k2;
+          d -= Rl[j] * k2;
+          r -= Rr[j] * k2;
+          im -= Ri[j] * k2;
+        }
+        nl[h] = l2; nd[h] = d; nu[h] = u2; nr[h] = r; ni[h] = im;
+      }
     }
+    __syncthreads();
+    if (valid) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int ie = (2 * p + h) * W + w;
+        Rl[ie] = nl[h]; Rd[ie] = nd[h]; Ru[ie] = nu[h]; Rr[ie] = nr[h]; Ri[ie] = ni[h];
+      }
+    }
+    __syncthreads();
+  }
+  double xr_[LM], xi_[LM];
+  if (valid) {
+    const int eF = (2 * p) * W + w, eE = eF + W;
+    const double Fr = Rr[eF] / Rd[eF], Fi = Ri[eF] / Rd[eF], Er = Rr[eE] / Rd[eE], Ei = Ri[eE] / Rd[eE];
+#pragma unroll
+    for (int t = 0; t < LM; ++t) {
+      xr_[t] = (dr[t] - al[t] * Fr - ga[t] * Er) / be[t];
+      xi_[t] = (di[t] - al[t] * Fi - ga[t] * Ei) / be[t];
+      if (t == 0) { xr_[t] = Fr; xi_[t] = Fi; }
+      if (t == L - 1) { xr_[t] = Er; xi_[t] = Ei; }
+    }
+  }
+  // remove the mean of the (0,0) solution
+  if (blockIdx.x == 0) {
+    __syncthreads();
+    if (w == 0 && active) {
+      double sr = 0.0, si = 0.0;
+#pragma unroll
+      for (int t = 0; t < LM; ++t)
+        if (t < L) { sr += xr_[t]; si += xi_[t]; }
+      red[p] = sr;
+      red[P + p] = si;
+    }
+    __syncthreads();
+    if (zmode) {
+      double sr = 0.0, si = 0.0;
+      for (int pp = 0; pp < P; ++pp) { sr += red[pp]; si += red[P + pp]; }
+      sr /= n;
+      si /= n;
+#pragma unroll
+      for (int t = 0; t < LM; ++t) { xr_[t] -= sr; xi_[t] -= si; }
+    }
+  }
+  if (valid) {
+#pragma unroll
+    for (int t = 0; t < LM; ++t)
+      if (t < L) spec[(size_t)(r0 + t) * Q + q] = cplx<T>{T(xr_[t]), T(xi_[t])};
   }
 }
 
@@ -365,7 +592,7 @@ __global__ __launch_bounds__(256) void k_tri(GridParams g, cplx<T>* __restrict__
 //        + i e^{+2 pi i m/nx} (X_m - conj X_{N-m}), m < N = nx/2, z = IDFT_N(Z),
 //        x_{2n} = Re z_n, x_{2n+1} = Im z_n.  Unnormalised (tri applied 1/(nx nz)).
 // ---------------------------------------------------------------------------------------
-template <typename T>
+template <typename T, int MB>
 __global__ __launch_bounds__(256) void k_ifftx(GridParams g, const cplx<T>* __restrict__ spec, T* __restrict__ out,
                                               FFTPlan px, const double2* __restrict__ rtw) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -373,8 +600,9 @@ __global__ __launch_bounds__(256) void k_ifftx(GridParams g, const cplx<T>* __re
   const int N = g.nhalf;
   const int grp = threadIdx.x / IBM_WAVE, lane = threadIdx.x % IBM_WAVE;
   const int row = blockIdx.x * 4 + grp;
-  cplx<T>* A = sm + grp * 2 * N;
-  cplx<T>* B = A + N;
+  cplx<T>* A = sm + grp * N;
+  cplx<T>* tw = sm + 4 * N;
+  load_twiddles<T>(tw, px, threadIdx.x, blockDim.x);
   const bool valid = row < g.nrows;
   if (valid) {
     const cplx<T>* in = spec + (size_t)row * g.mh;
@@ -389,7 +617,8 @@ __global__ __launch_bounds__(256) void k_ifftx(GridParams g, const cplx<T>* __re
     }
   }
   __syncthreads();
-  cplx<T>* R = fft_lds<T>(A, B, 1, px, +1, lane, IBM_WAVE);
+  fft_lds<T, MB>(A, 1, px, tw, +1, lane, IBM_WAVE);
+  const cplx<T>* R = A;
   if (valid) {
     const T* Rr = reinterpret_cast<const T*>(R);
     for (int i = lane; i < g.nx; i += IBM_WAVE) out[(size_t)row * g.nx + i] = Rr[i];
@@ -401,8 +630,10 @@ __global__ __launch_bounds__(256) void k_ifftx(GridParams g, const cplx<T>* __re
 // zero on external faces (Sec. 3.3); p += phi on internal pressure cells only.
 // ---------------------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_correct(GridParams g, Fields<T> f, double ck_dt,
+__global__ __launch_bounds__(256) void k_correct(GridParams g, Fields<T> f, IbmLists L, int stage, double ck_dt,
                                                 const double* __restrict__ pi) {
+  (void)L;
+  (void)stage;
   const int i = blockIdx.x * BX + threadIdx.x;
   const int k = blockIdx.y * BZ + threadIdx.y;
   const int j = blockIdx.z;
@@ -410,21 +641,19 @@ __global__ __launch_bounds__(256) void k_correct(GridParams g, Fields<T> f, doub
   const int nx = g.nx, nz = g.nz;
   const int im = wrap_m(i, nx), km = wrap_m(k, nz);
   const int c = (j * nz + k) * nx + i;
-  const int plane = nx * nz;
+  const int ds = (j > 0) ? nx * nz : 0;      // v on face 0 is never internal
   const uint8_t tg = f.tag[c];
+  const T ph = f.phi[c], phw = f.phi[c - i + im], phs = f.phi[c - ds], phb = f.phi[c + (km - k) * nx];
+  const T usv = f.us[c], vsv = f.vs[c], wsv = f.ws[c], pv = f.p[c];
   const T ckdt = T(ck_dt);
-  const T ph = f.phi[c];
-  T un = T(0), vn = T(0), wn = T(0);
-  if (tg & TAG_U) {
-    const T pick = (tg & TAG_UI) ? T(0) : T(pi[0] * ck_dt);
-    un = f.us[c] - pick - ckdt * ((ph - f.phi[c - i + im]) * T(g.idx));
-  }
-  if (tg & TAG_V) vn = f.vs[c] - ckdt * ((ph - f.phi[c - plane]) * T(g.idy));
-  if (tg & TAG_W) wn = f.ws[c] - ckdt * ((ph - f.phi[c + (km - k) * nx]) * T(g.idz));
-  f.u[c] = un;
-  f.v[c] = vn;
-  f.w[c] = wn;
-  f.p[c] = (tg & TAG_P) ? f.p[c] + ph : T(0);
+  const T pick = ((tg & (TAG_U | TAG_UI)) == TAG_U) ? T(pi[0] * ck_dt) : T(0);
+  const T un = usv - pick - ckdt * ((ph - phw) * T(g.idx));
+  const T vn = vsv - ckdt * ((ph - phs) * T(g.idy));
+  const T wn = wsv - ckdt * ((ph - phb) * T(g.idz));
+  f.u[c] = (tg & TAG_U) ? un : T(0);
+  f.v[c] = (tg & TAG_V) ? vn : T(0);
+  f.w[c] = (tg & TAG_W) ? wn : T(0);
+  f.p[c] = (tg & TAG_P) ? pv + ph : T(0);
 }
 
 template <typename T>
@@ -442,23 +671,22 @@ static inline dim3 cell_grid(const GridParams& g) {
   return dim3((g.nx + BX - 1) / BX, (g.nz + BZ - 1) / BZ, g.ny1);
 }
 
-template <typename T>
-hipError_t launch_momentum(const GridParams& g, const Fields<T>& f, const StageConsts& s, double* qpart,
-                           int* nqpart, hipStream_t st) {
-  const dim3 grid = cell_grid(g);
-  hipLaunchKernelGGL(k_momentum<T>, grid, dim3(BX, BZ), 0, st, g, f, s, qpart);
-  *nqpart = grid.x * grid.y * grid.z;
-  return hipGetLastError();
+// y planes per momentum block: about 2048 blocks, 4..64 planes each.
+static int momentum_chunk(const GridParams& g) {
+  const long cols = (long)((g.nx + MX - 1) / MX) * ((g.nz + MZ - 1) / MZ);
+  long jc = (g.ny1 * cols + 2047) / 2048;
+  if (jc < 4) jc = 4;
+  if (jc > 64) jc = 64;
+  return (int)jc;
 }
 
 template <typename T>
-hipError_t launch_ibm_fix(const GridParams& g, const Fields<T>& f, const IbmLists& L, int stage, double* qpart,
-                          int* nqpart, hipStream_t st) {
-  (void)g;
-  const int nb = (L.n_total + 255) / 256;
-  *nqpart = nb;
-  if (nb == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ibm_fix<T>, dim3(nb), dim3(256), 0, st, f, L, stage, qpart);
+hipError_t launch_momentum(const GridParams& g, const Fields<T>& f, const IbmLists& L, const StageConsts& s,
+                           double* qpart, int* nqpart, hipStream_t st) {
+  const int jc = momentum_chunk(g);
+  const dim3 grid((g.nx + MX - 1) / MX, (g.nz + MZ - 1) / MZ, (g.ny1 + jc - 1) / jc);
+  hipLaunchKernelGGL(k_momentum<T>, grid, dim3(MX, MZ), 0, st, g, f, L, s, jc, qpart);
+  *nqpart = grid.x * grid.y * grid.z;
   return hipGetLastError();
 }
 
@@ -478,33 +706,48 @@ hipError_t launch_ibm_pi(const Fields<T>& f, const IbmLists& L, int stage, doubl
 }
 
 template <typename T>
-hipError_t launch_div_fftx(const GridParams& g, const Fields<T>& f, const FFTPlan& px, const double2* rtw,
-                           double ck_dt, const double* pi, const T* rhs_in, hipStream_t st) {
-  const size_t lds = 4 * 2 * (size_t)g.nhalf * sizeof(cplx<T>);
-  hipLaunchKernelGGL(k_div_fftx<T>, dim3((g.nrows + 3) / 4), dim3(256), lds, st, g, f, px, rtw, ck_dt, pi,
-                     rhs_in);
+hipError_t launch_div_fftx(const GridParams& g, const Fields<T>& f, const IbmLists& L, int stage,
+                           const FFTPlan& px, const double2* rtw, double ck_dt, const double* pi, const T* rhs_in,
+                           hipStream_t st) {
+  const int RB = 4;
+  const size_t lds = (RB + 1) * (size_t)g.nhalf * sizeof(cplx<T>);
+  const int mb = fft_max_bfly(px, IBM_WAVE);
+  const dim3 grid((g.nrows + RB - 1) / RB), blk(64 * RB);
+  if (mb == 1) hipLaunchKernelGGL((k_div_fftx<T, 1>), grid, blk, lds, st, g, f, L, stage, px, rtw, ck_dt, pi, rhs_in);
+  else if (mb == 2) hipLaunchKernelGGL((k_div_fftx<T, 2>), grid, blk, lds, st, g, f, L, stage, px, rtw, ck_dt, pi, rhs_in);
+  else hipLaunchKernelGGL((k_div_fftx<T, 4>), grid, blk, lds, st, g, f, L, stage, px, rtw, ck_dt, pi, rhs_in);
   return hipGetLastError();
 }
 
+// Columns per z-FFT block: 128-byte rows (8 FP64 / 16 FP32 complex values), at least
+// nz/8 threads per column (register staging of the in-place stages) and <= 64 KiB LDS.
 template <typename T>
 static int fftz_width(int nz) {
-  int W = 16;
-  while (W > 1 && 2 * (size_t)nz * W * sizeof(cplx<T>) > 65536) W >>= 1;
+  int W = (int)(128 / sizeof(cplx<T>));
+  while (W > 1 && (256 / W < (nz + 7) / 8 || ((size_t)W + 1) * nz * sizeof(cplx<T>) > 65536)) W >>= 1;
   return W;
 }
 
 template <typename T>
 hipError_t launch_fftz(const GridParams& g, cplx<T>* spec, const FFTPlan& pz, int sign, hipStream_t st) {
   const int W = fftz_width<T>(g.nz);
-  const size_t lds = 2 * (size_t)g.nz * W * sizeof(cplx<T>);
-  hipLaunchKernelGGL(k_fftz<T>, dim3((g.mh + W - 1) / W, g.ny1), dim3(256), lds, st, g, spec, pz, sign, W);
+  const size_t lds = ((size_t)W + 1) * g.nz * sizeof(cplx<T>);
+  const int mb = fft_max_bfly(pz, 256 / W);
+  const dim3 grid((g.mh + W - 1) / W, g.ny1);
+  if (mb == 1) hipLaunchKernelGGL((k_fftz<T, 1>), grid, dim3(256), lds, st, g, spec, pz, sign, W);
+  else if (mb == 2) hipLaunchKernelGGL((k_fftz<T, 2>), grid, dim3(256), lds, st, g, spec, pz, sign, W);
+  else hipLaunchKernelGGL((k_fftz<T, 4>), grid, dim3(256), lds, st, g, spec, pz, sign, W);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_tri(const GridParams& g, cplx<T>* spec, const double* kx2, const double* kz2, double* cp,
-                      double2* dp, double* mean_out, hipStream_t st) {
-  hipLaunchKernelGGL(k_tri<T>, dim3((g.nmodes + 255) / 256), dim3(256), 0, st, g, spec, kx2, kz2, cp, dp,
+hipError_t launch_tri(const GridParams& g, cplx<T>* spec, const double* kx2, const double* kz2, double* mean_out,
+                      hipStream_t st) {
+  const int n = g.ny1;
+  const int P = (n + 7) / 8;           // segments of at most 8 rows, at least 2
+  const int W = 256 / P;               // modes per block
+  const size_t lds = (size_t)(5 * W * 2 * P + 2 * P) * sizeof(double);
+  hipLaunchKernelGGL(k_tri<T>, dim3((g.nmodes + W - 1) / W), dim3(256), lds, st, g, spec, kx2, kz2, P, W,
                      mean_out);
   return hipGetLastError();
 }
@@ -512,15 +755,19 @@ hipError_t launch_tri(const GridParams& g, cplx<T>* spec, const double* kx2, con
 template <typename T>
 hipError_t launch_ifftx(const GridParams& g, const cplx<T>* spec, T* out, const FFTPlan& px, const double2* rtw,
                         hipStream_t st) {
-  const size_t lds = 4 * 2 * (size_t)g.nhalf * sizeof(cplx<T>);
-  hipLaunchKernelGGL(k_ifftx<T>, dim3((g.nrows + 3) / 4), dim3(256), lds, st, g, spec, out, px, rtw);
+  const size_t lds = (4 + 1) * (size_t)g.nhalf * sizeof(cplx<T>);
+  const int mb = fft_max_bfly(px, IBM_WAVE);
+  const dim3 grid((g.nrows + 3) / 4);
+  if (mb == 1) hipLaunchKernelGGL((k_ifftx<T, 1>), grid, dim3(256), lds, st, g, spec, out, px, rtw);
+  else if (mb == 2) hipLaunchKernelGGL((k_ifftx<T, 2>), grid, dim3(256), lds, st, g, spec, out, px, rtw);
+  else hipLaunchKernelGGL((k_ifftx<T, 4>), grid, dim3(256), lds, st, g, spec, out, px, rtw);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_correct(const GridParams& g, const Fields<T>& f, double ck_dt, const double* pi,
-                          hipStream_t st) {
-  hipLaunchKernelGGL(k_correct<T>, cell_grid(g), dim3(BX, BZ), 0, st, g, f, ck_dt, pi);
+hipError_t launch_correct(const GridParams& g, const Fields<T>& f, const IbmLists& L, int stage, double ck_dt,
+                          const double* pi, hipStream_t st) {
+  hipLaunchKernelGGL(k_correct<T>, cell_grid(g), dim3(BX, BZ), 0, st, g, f, L, stage, ck_dt, pi);
   return hipGetLastError();
 }
 
@@ -534,21 +781,20 @@ hipError_t launch_copy(const T* src, T* dst, int64_t n, hipStream_t st) {
 }
 
 #define IBM_INST(T)                                                                                              \
-  template hipError_t launch_momentum<T>(const GridParams&, const Fields<T>&, const StageConsts&, double*, int*, \
-                                         hipStream_t);                                                           \
-  template hipError_t launch_ibm_fix<T>(const GridParams&, const Fields<T>&, const IbmLists&, int, double*,     \
-                                        int*, hipStream_t);                                                      \
+  template hipError_t launch_momentum<T>(const GridParams&, const Fields<T>&, const IbmLists&,                  \
+                                         const StageConsts&, double*, int*, hipStream_t);                        \
   template hipError_t launch_ibm_pi<T>(const Fields<T>&, const IbmLists&, int, double, const double*,           \
                                        hipStream_t);                                                             \
-  template hipError_t launch_div_fftx<T>(const GridParams&, const Fields<T>&, const FFTPlan&, const double2*,   \
-                                         double, const double*, const T*, hipStream_t);                          \
+  template hipError_t launch_div_fftx<T>(const GridParams&, const Fields<T>&, const IbmLists&, int,             \
+                                         const FFTPlan&, const double2*, double, const double*, const T*,        \
+                                         hipStream_t);                                                           \
   template hipError_t launch_fftz<T>(const GridParams&, cplx<T>*, const FFTPlan&, int, hipStream_t);            \
   template hipError_t launch_tri<T>(const GridParams&, cplx<T>*, const double*, const double*, double*,         \
-                                    double2*, double*, hipStream_t);                                             \
+                                    hipStream_t);                                                                \
   template hipError_t launch_ifftx<T>(const GridParams&, const cplx<T>*, T*, const FFTPlan&, const double2*,    \
                                       hipStream_t);                                                              \
-  template hipError_t launch_correct<T>(const GridParams&, const Fields<T>&, double, const double*,             \
-                                        hipStream_t);                                                            \
+  template hipError_t launch_correct<T>(const GridParams&, const Fields<T>&, const IbmLists&, int, double,      \
+                                        const double*, hipStream_t);                                             \
   template hipError_t launch_copy<T>(const T*, T*, int64_t, hipStream_t);
 
 IBM_INST(double)
