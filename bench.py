@@ -31,7 +31,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="wavy", help="wavy | wavy_large | ellipsoids | poiseuille")
+    ap.add_argument("--workload", default="wavy", help="wavy | wavy_large | poiseuille")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the extra forms (FP32, large grid, IBM off)")
@@ -61,14 +61,16 @@ def algorithmic_bytes(kernel, C, M, s, n_ibm, n_u):
         return M * 2 * s + C * s
     if kernel == "correct":
         return C * (9 * s + 1) + n_u * 16
-    if kernel == "cfr":
-        return 0
+    if kernel == "cfr_pi":
+        # index, 1/A and u* read-modify-write of each immersed-boundary u face (the flow-rate
+        # partials are a few kB)
+        return n_u * (4 + 8 + 2 * s)
     raise KeyError(kernel)
 
 
 def step_bytes(C, M, s, n_ibm, n_u):
     per_sub = sum(algorithmic_bytes(k, C, M, s, n_ibm, n_u) for k in
-                  ("momentum", "div_fftx", "fftz_fwd", "tri", "fftz_inv", "ifftx", "correct"))
+                  ("momentum", "cfr_pi", "div_fftx", "fftz_fwd", "tri", "fftz_inv", "ifftx", "correct"))
     return 3 * per_sub
 
 
@@ -114,8 +116,8 @@ def make_grid(c, sdf, st, precision, ibm=True):
     dev = torch.device("cuda", 0)
     dt = torch.float64 if precision == "fp64" else torch.float32
     g = IbmGrid.from_case(c, precision=precision, ibm=ibm)
-    g.set_geometry(*[torch.from_numpy(a).to(dev) for a in sdf])
-    g.set_state(*[torch.from_numpy(a).to(dev, dt) for a in st])
+    g.set_geometry(*[torch.as_tensor(a).to(dev) for a in sdf])
+    g.set_state(*[torch.as_tensor(a).to(dev, dt) for a in st])
     return g
 
 
@@ -137,20 +139,28 @@ def timed_run(g, steps, warmup, profile_kernel=None):
 
 
 def dominant_kernel(g, nsteps=3):
-    g.profile(True)
-    g.step(nsteps)
-    prof = g.profile_read()
+    """The kernel with the largest total time, each kernel timed in a pass of its own."""
+    names = [n for n in g.kernel_names() if n not in ("diag", "stats", "geom")]
+    tot = {}
+    for n in names:
+        g.profile([n])
+        g.step(nsteps)
+        prof = g.profile_read()
+        if n in prof:
+            tot[n] = prof[n][0]
     g.profile(False)
-    tot = sum(v[0] for v in prof.values())
-    k = max(prof, key=lambda n: prof[n][0])
-    return k, {n: round(100.0 * v[0] / tot, 1) for n, v in prof.items()}
+    s = sum(tot.values())
+    k = max(tot, key=lambda n: tot[n])
+    return k, {n: round(100.0 * v / s, 1) for n, v in tot.items()}
 
 
-def measure(name, precision, steps, warmup, ibm=True, inputs=None):
+def measure(name, precision, steps, warmup, ibm=True, inputs=None, autotune=True, keep_state=False):
     c, sdf, st = inputs if inputs is not None else build_inputs(name)
     g = make_grid(c, sdf, st, precision, ibm)
     stats0 = g.stats()
+    tuned = g.autotune(2) if autotune else g.tuning()
     kern, shares = dominant_kernel(g)
+    g.set_state(*[__import__("torch").as_tensor(a).to("cuda", g.dtype) for a in st])
     el, prof = timed_run(g, steps, warmup, kern)
     C = c.nx * (c.ny - 1) * c.nz
     M = (c.nx // 2 + 1) * c.nz * (c.ny - 1)
@@ -161,12 +171,65 @@ def measure(name, precision, steps, warmup, ibm=True, inputs=None):
     abytes = algorithmic_bytes(kern, C, M, s, n_ibm, stats0["n_ibm"][0])
     achieved = abytes / avg_s / 1e9
     stats = g.stats()
+    state = [t.double().cpu().numpy() for t in g.get_state()] if keep_state else None
     g.close()
     return dict(case=c, cells=C, el=el, value=C * 3 * steps / el, ms_per_step=el / steps * 1e3,
                 kernel=kern, kernel_avg_us=avg_s * 1e6, kernel_launches=cnt, kernel_bytes=abytes,
-                achieved_gbs=achieved, shares=shares, stats=stats,
+                achieved_gbs=achieved, shares=shares, stats=stats, tuning=tuned, state=state,
                 step_gbs=step_bytes(C, M, s, n_ibm, stats0["n_ibm"][0]) * steps / el / 1e9,
                 ibm_fraction=n_ibm / (3.0 * C))
+
+
+def precision_errors(a64, a32):
+    """Per-field max and L2 error of the FP32-storage state against the FP64 one."""
+    import numpy as np
+    out = {}
+    for name, x, y in zip("uvwp", a64, a32):
+        den_max = max(np.abs(x).max(), 1e-300)
+        den_l2 = max(np.sqrt((x * x).sum()), 1e-300)
+        out[name] = {"max_rel": float(np.abs(y - x).max() / den_max),
+                     "l2_rel": float(np.sqrt(((y - x) ** 2).sum()) / den_l2)}
+    return out
+
+
+def measure_ensemble(n=96, steps=200, warmup=3, seed=5):
+    """The ragged ensemble in FP32 storage: one HIP-graph launch per RK3 step of all
+    instances (instances as parallel graph branches) vs the same kernels launched one
+    instance after another on one stream."""
+    import torch
+    import ibm_inputs as I
+    from ibm_inputs import torch_gen as TG
+    from paper_2506_14328_amd import IbmGrid
+    cases = I.ensemble_cases(n, seed)
+    dev = torch.device("cuda", 0)
+    g = IbmGrid.ensemble(cases, precision="fp32")
+    states = []
+    for i, c in enumerate(cases):
+        sdf, st = TG.make_inputs(c, dev, torch.float32)
+        g.set_geometry(*sdf, inst=i)
+        g.set_state(*st, inst=i)
+        states.append(st)
+        del sdf
+    torch.cuda.synchronize()
+    cells = sum(c.nx * (c.ny - 1) * c.nz for c in cases)
+    res = {}
+    for mode in ("sequential", "graph"):
+        g.tune(graph=1 if mode == "graph" else 0)
+        for i, st in enumerate(states):
+            g.set_state(*st, inst=i)
+        g.step(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.step(steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        res[mode] = {"value": cells * 3 * steps / el, "ms_per_step": el / steps * 1e3}
+    bad = sum(1 for i in range(n) if g.stats(inst=i)["nan_flag"])
+    g.close()
+    return {"workload": f"ensemble_{n}_wavy_ragged", "precision": "fp32", "instances": n, "cells": cells,
+            "steps": steps, "value": res["graph"]["value"], "ms_per_step": res["graph"]["ms_per_step"],
+            "sequential_value": res["sequential"]["value"],
+            "graph_speedup": res["graph"]["value"] / res["sequential"]["value"], "instances_with_nan": bad}
 
 
 def cpu_baseline(name, target_s=12.0):
@@ -232,18 +295,36 @@ def main():
            "config": {"workload": c.name, "grid_faces": [c.nx, c.ny, c.nz], "cells": r["cells"],
                       "precision": a.precision, "Re_bulk": round(1.0 / c.nu), "dt": c.dt,
                       "forcing": "constant flow rate", "ibm_point_fraction": round(r["ibm_fraction"], 4)},
-           "roofline": roof, "kernel_time_share_pct": r["shares"]}
+           "roofline": roof, "kernel_time_share_pct": r["shares"], "tuning": r["tuning"]}
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(a.workload)
     if not a.no_forms:
+        import torch
         forms = []
-        fp32 = measure(a.workload, "fp32", a.steps, a.warmup, inputs=inputs)
-        forms.append(_form(fp32, "fp32"))
+        forms.append(_form(measure(a.workload, "fp32", a.steps, a.warmup, inputs=inputs), "fp32"))
         off = measure(a.workload, a.precision, a.steps, a.warmup, ibm=False, inputs=inputs)
-        forms.append(dict(_form(off, a.precision), ibm="off (staircase)"))
+        forms.append(dict(_form(off, a.precision), ibm="off (staircase)",
+                          ibm_cost_pct=round(100.0 * (r["ms_per_step"] / off["ms_per_step"] - 1.0), 1)))
+        # large sinusoidal channel: FP64 and FP32 storage from the same start, 200 steps
         big = build_inputs("wavy_large")
+        r64 = measure("wavy_large", "fp64", 200, 3, inputs=big, keep_state=True)
+        r32 = measure("wavy_large", "fp32", 200, 3, inputs=big, keep_state=True)
+        err = precision_errors(r64["state"], r32["state"])
+        forms.append(_form(r64, "fp64"))
+        forms.append(dict(_form(r32, "fp32"), error_vs_fp64_after_200_steps=err))
+        del big, r64, r32
+        # complex geometry: union of 64 ellipsoids, 300 steps
+        from ibm_inputs import torch_gen as TG
+        import ibm_inputs as I
+        ce = I.make_case("ellipsoids")
+        sdf_e, st_e = TG.make_inputs(ce, torch.device("cuda", 0), torch.float64)
+        inp_e = (ce, sdf_e, st_e)
         for prec in ("fp64", "fp32"):
-            forms.append(_form(measure("wavy_large", prec, 20, 3, inputs=big), prec))
+            re_ = measure("ellipsoids", prec, 300, 3, inputs=inp_e)
+            forms.append(dict(_form(re_, prec), ibm_point_fraction=round(re_["ibm_fraction"], 4)))
+        del sdf_e, st_e, inp_e
+        torch.cuda.empty_cache()
+        forms.append(measure_ensemble())
         out["forms"] = forms
     print(json.dumps(out), flush=True)
 
@@ -251,7 +332,8 @@ def main():
 def _form(r, prec):
     return {"workload": r["case"].name, "precision": prec, "value": r["value"], "ms_per_step": r["ms_per_step"],
             "dominant_kernel": r["kernel"], "kernel_frac_hbm": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4),
-            "step_algorithmic_GBs": round(r["step_gbs"], 1)}
+            "step_algorithmic_GBs": round(r["step_gbs"], 1),
+            "step_frac_hbm": round(r["step_gbs"] / HBM_PEAK_GBS, 4), "tuning": r["tuning"]}
 
 
 if __name__ == "__main__":

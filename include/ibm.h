@@ -95,8 +95,10 @@ typedef struct {
   int32_t reserved;
 } ibm_stats_t;
 
-/* Create n_inst channel instances (n_inst = 1 in this version) at the given
- * precision, all work on hip_stream (a hipStream_t; NULL = default stream).
+/* Create n_inst independent channel instances (an ensemble of ragged sizes is
+ * allowed; desc points to n_inst descriptors) at the given precision, all work on
+ * hip_stream (a hipStream_t; NULL = default stream).  Instances are addressed by
+ * their index in the per-instance calls; ibm_step advances all of them.
  * Validates the descriptor (IBM_ERR_ARG), allocates device fields and the FFT
  * and tridiagonal plans (IBM_ERR_OOM).  Fields start at zero. */
 int ibm_create_grid(const ibm_grid_desc* desc, int32_t n_inst, int32_t precision,
@@ -162,6 +164,31 @@ int ibm_profile(ibm_handle h, int32_t kernel_mask);
 int ibm_profile_read(ibm_handle h, double* total_ms, int64_t* launches, int32_t max);
 const char* ibm_kernel_name(int32_t id);
 int32_t ibm_num_kernels(void);
+
+/* Launch-shape knobs (performance only: every setting gives the same result up to
+ * the rounding of the reordered FP64 flow-rate sum and tridiagonal elimination).
+ * 0 = automatic choice.
+ *   IBM_TUNE_MOMENTUM_PLANES  y planes marched by one momentum block
+ *   IBM_TUNE_FFTZ_WIDTH       x modes per z-FFT block (power of two; invalid
+ *                             widths fall back to the automatic one)
+ *   IBM_TUNE_TRI_ROWS         rows per thread of the tridiagonal solver: 4 or 8 */
+enum { IBM_TUNE_MOMENTUM_PLANES = 0, IBM_TUNE_FFTZ_WIDTH = 1, IBM_TUNE_TRI_ROWS = 2,
+       IBM_TUNE_GRAPH = 3,            /* 1: ibm_step replays a HIP graph of one RK3 step of all
+                                         instances (captured on first use, rebuilt after any
+                                         geometry/tuning/diagnostics change); instances run as
+                                         independent graph branches.  Ignored while diagnostics
+                                         or profiling are on. */
+       IBM_TUNE_GRAPH_BRANCHES = 4 }; /* capture streams for the graph (0 = up to 8) */
+int ibm_tune_set(ibm_handle h, int32_t param, int32_t value);
+int ibm_tune_get(ibm_handle h, int32_t param, int32_t* value);
+
+/* Autotuner: for each knob in turn, time steps_per_trial RK3 steps (after one
+ * warm-up step) from the current state for every candidate value with HIP events,
+ * and keep the fastest.  The state (u, v, w, p, step count, time) is saved before
+ * and restored after, so the trajectory is unchanged.  chosen (may be NULL)
+ * receives the 3 selected values.  Synchronises the stream.  IBM_ERR_STATE
+ * before ibm_set_geometry. */
+int ibm_autotune(ibm_handle h, int32_t steps_per_trial, int32_t* chosen);
 
 /* Bytes of device memory the library holds for this handle. */
 int64_t ibm_device_bytes(ibm_handle h);

@@ -39,6 +39,7 @@ struct Instance {
   // immersed-boundary lists
   DevBuf ibm_idx, ibm_coef, ibm_lam, ibm_choff;
   IbmLists L{};
+  Tuning tu{};
   int64_t n_int[3] = {0, 0, 0}, n_ibm[3] = {0, 0, 0}, n_pint = 0;
   bool geom_ready = false;
   bool diag_valid = false;
@@ -69,6 +70,15 @@ struct ibm_ctx {
   size_t ev_used = 0;
   double prof_ms[K_NUM_KERNELS] = {};
   int64_t prof_n[K_NUM_KERNELS] = {};
+  // graph execution: one RK3 step of every instance captured once, replayed per step
+  bool use_graph = false;
+  int n_branches = 0;                  // capture streams (instances spread round-robin)
+  hipStream_t cap = nullptr;           // capture origin stream
+  std::vector<hipStream_t> aux;
+  hipEvent_t ev_fork = nullptr;
+  std::vector<hipEvent_t> ev_join;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
 };
 
 namespace {
@@ -251,17 +261,19 @@ Fields<T> fields_of(Instance& I) {
 
 // Pressure solve of the current right-hand side: forward FFTs, tridiagonal, inverse FFTs.
 template <typename T>
-int poisson(ibm_ctx* c, Instance& I, Fields<T>& f, T* phi_out) {
+int poisson(ibm_ctx* c, Instance& I, Fields<T>& f, T* phi_out, hipStream_t st) {
   const GridParams& g = I.g;
-  RUNK(c, K_FFTZ_FWD, launch_fftz<T>(g, f.spec, I.pz, -1, c->stream));
-  RUNK(c, K_TRI, launch_tri<T>(g, f.spec, I.kx2, I.kz2, I.mean(), c->stream));
-  RUNK(c, K_FFTZ_INV, launch_fftz<T>(g, f.spec, I.pz, +1, c->stream));
-  RUNK(c, K_IFFTX, launch_ifftx<T>(g, f.spec, phi_out, I.px, I.rtw, c->stream));
+  RUNK(c, K_FFTZ_FWD, launch_fftz<T>(g, f.spec, I.pz, -1, I.tu, st));
+  RUNK(c, K_TRI, launch_tri<T>(g, f.spec, I.kx2, I.kz2, I.mean(), I.tu, st));
+  RUNK(c, K_FFTZ_INV, launch_fftz<T>(g, f.spec, I.pz, +1, I.tu, st));
+  RUNK(c, K_IFFTX, launch_ifftx<T>(g, f.spec, phi_out, I.px, I.rtw, st));
   return IBM_OK;
 }
 
+// nsteps RK3 steps of one instance, launched on st.  count: advance the step/time
+// counters (false while the launches are only being captured into a graph).
 template <typename T>
-int run_steps(ibm_ctx* c, Instance& I, int nsteps) {
+int run_steps(ibm_ctx* c, Instance& I, int nsteps, hipStream_t st, bool count = true) {
   const GridParams& g = I.g;
   Fields<T> f = fields_of<T>(I);
   const double scale = g.dy * g.dz / g.nx;
@@ -275,22 +287,21 @@ int run_steps(ibm_ctx* c, Instance& I, int nsteps) {
       sc.use_hold = (k > 0);
       sc.write_h = (k < 2);
       int nq = 0;
-      RUNK(c, K_MOMENTUM, launch_momentum<T>(g, f, I.L, sc, I.qpart, &nq, c->stream));
-      RUNK(c, K_CFR, launch_cfr(I.qpart, nq, scale, I.d.forcing, I.d.q_target_or_pi, I.S3(), k, I.pi(),
-                                I.pi_hist(), c->stream));
-      if (I.L.n_u > 0) RUNK(c, K_IBM_PI, launch_ibm_pi<T>(f, I.L, k, sc.ck_dt, I.pi(), c->stream));
-      RUNK(c, K_DIV_FFTX, launch_div_fftx<T>(g, f, I.L, k, I.px, I.rtw, sc.ck_dt, I.pi(), (const T*)nullptr,
-                                             c->stream));
-      int rc = poisson<T>(c, I, f, f.phi);
+      RUNK(c, K_MOMENTUM, launch_momentum<T>(g, f, I.L, sc, I.tu, I.qpart, &nq, st));
+      RUNK(c, K_CFR_PI, launch_cfr_pi<T>(f, I.L, k, sc.ck_dt, I.qpart, nq, scale, I.d.forcing, I.d.q_target_or_pi,
+                                         I.S3(), I.pi(), I.pi_hist(), st));
+      RUNK(c, K_DIV_FFTX, launch_div_fftx<T>(g, f, I.L, k, I.px, I.rtw, sc.ck_dt, I.pi(), (const T*)nullptr, st));
+      int rc = poisson<T>(c, I, f, f.phi, st);
       if (rc) return rc;
       if (c->diag && s == nsteps - 1 && k == 2) {
         int np = 0;
-        RUNK(c, K_DIAG, launch_diag<T>(g, f, I.L, k, sc.ck_dt, I.pi(), I.mean(), I.red_part, &np, c->stream));
-        RUNK(c, K_DIAG, launch_reduce_final(I.red_part, np, 0, 3, I.diag_out(), c->stream));
+        RUNK(c, K_DIAG, launch_diag<T>(g, f, I.L, k, sc.ck_dt, I.pi(), I.mean(), I.red_part, &np, st));
+        RUNK(c, K_DIAG, launch_reduce_final(I.red_part, np, 0, 3, I.diag_out(), st));
         I.diag_valid = true;
       }
-      RUNK(c, K_CORRECT, launch_correct<T>(g, f, I.L, k, sc.ck_dt, I.pi(), c->stream));
+      RUNK(c, K_CORRECT, launch_correct<T>(g, f, I.L, k, sc.ck_dt, I.pi(), st));
     }
+    if (!count) continue;
     I.step += 1;
     I.time += g.dt;
   }
@@ -417,6 +428,57 @@ int check_inst(ibm_ctx* c, int32_t inst) {
   return IBM_OK;
 }
 
+void drop_graph(ibm_ctx* c) {
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->gexec = nullptr;
+  c->graph = nullptr;
+}
+
+// Capture one RK3 step of every instance: instance i goes to capture stream i mod B,
+// forked from and joined back to the origin stream, so that independent instances are
+// independent branches of the graph.
+template <typename T>
+int build_graph(ibm_ctx* c) {
+  drop_graph(c);
+  const int B = std::max(1, std::min<int>(c->n_branches > 0 ? c->n_branches : 8, (int)c->inst.size()));
+  if (!c->cap) HIPCHK(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+  if (!c->ev_fork) HIPCHK(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+  while ((int)c->aux.size() < B) {
+    hipStream_t s2;
+    HIPCHK(c, hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
+    c->aux.push_back(s2);
+    hipEvent_t e;
+    HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    c->ev_join.push_back(e);
+  }
+  HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+  int rc = IBM_OK;
+  hipError_t e = hipEventRecord(c->ev_fork, c->cap);
+  for (int b = 0; b < B && e == hipSuccess; ++b) e = hipStreamWaitEvent(c->aux[b], c->ev_fork, 0);
+  if (e != hipSuccess) rc = fail(c, IBM_ERR_DEVICE, std::string("graph fork: ") + hipGetErrorString(e));
+  for (size_t i = 0; i < c->inst.size() && !rc; ++i) rc = run_steps<T>(c, c->inst[i], 1, c->aux[i % B], false);
+  for (int b = 0; b < B && !rc; ++b) {
+    e = hipEventRecord(c->ev_join[b], c->aux[b]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(c->cap, c->ev_join[b], 0);
+    if (e != hipSuccess) rc = fail(c, IBM_ERR_DEVICE, std::string("graph join: ") + hipGetErrorString(e));
+  }
+  hipGraph_t gr = nullptr;
+  const hipError_t ee = hipStreamEndCapture(c->cap, &gr);
+  if (!rc && ee != hipSuccess) rc = fail(c, IBM_ERR_DEVICE, std::string("end capture: ") + hipGetErrorString(ee));
+  if (rc) {
+    if (gr) (void)hipGraphDestroy(gr);
+    return rc;
+  }
+  c->graph = gr;
+  e = hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    drop_graph(c);
+    return fail(c, IBM_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+  }
+  return IBM_OK;
+}
+
 }  // namespace
 
 // =======================================================================================
@@ -428,16 +490,17 @@ int ibm_create_grid(const ibm_grid_desc* desc, int32_t n_inst, int32_t precision
                     ibm_handle* out) {
   if (!desc || !out) return fail(nullptr, IBM_ERR_ARG, "null argument");
   *out = nullptr;
-  if (n_inst != 1) return fail(nullptr, IBM_ERR_ARG, "this version supports n_inst = 1");
+  if (n_inst < 1 || n_inst > 65536) return fail(nullptr, IBM_ERR_ARG, "n_inst must be in 1..65536");
   if (precision != IBM_FP64 && precision != IBM_FP32_STORAGE) return fail(nullptr, IBM_ERR_ARG, "invalid precision");
   ibm_ctx* c = new (std::nothrow) ibm_ctx();
   if (!c) return fail(nullptr, IBM_ERR_OOM, "host allocation");
   c->precision = precision;
   c->stream = (hipStream_t)hip_stream;
-  int rc = validate(c, desc[0]);
+  int rc = IBM_OK;
+  for (int i = 0; i < n_inst && !rc; ++i) rc = validate(c, desc[i]);
   if (!rc) {
-    c->inst.resize(1);
-    rc = init_instance(c, c->inst[0], desc[0]);
+    c->inst.resize(n_inst);
+    for (int i = 0; i < n_inst && !rc; ++i) rc = init_instance(c, c->inst[i], desc[i]);
   }
   if (!rc) {
     hipError_t e = hipStreamSynchronize(c->stream);
@@ -455,6 +518,7 @@ int ibm_set_geometry(ibm_handle h, int32_t inst, const double* sdf_u, const doub
   int rc = check_inst(h, inst);
   if (rc) return rc;
   if (!sdf_u || !sdf_v || !sdf_w) return fail(h, IBM_ERR_ARG, "null SDF pointer");
+  drop_graph(h);
   return set_geometry_impl(h, h->inst[inst], sdf_u, sdf_v, sdf_w);
 }
 
@@ -490,9 +554,23 @@ int ibm_get_state(ibm_handle h, int32_t inst, void* u, void* v, void* w, void* p
 int ibm_step(ibm_handle h, int32_t nsteps) {
   if (!h) return fail(nullptr, IBM_ERR_ARG, "null handle");
   if (nsteps < 0) return fail(h, IBM_ERR_ARG, "nsteps < 0");
-  for (Instance& I : h->inst) {
+  for (Instance& I : h->inst)
     if (!I.geom_ready) return fail(h, IBM_ERR_STATE, "ibm_step before ibm_set_geometry");
-    const int rc = (h->precision == IBM_FP64) ? run_steps<double>(h, I, nsteps) : run_steps<float>(h, I, nsteps);
+  if (h->use_graph && !h->diag && !h->prof && nsteps > 0) {
+    if (!h->gexec) {
+      const int rc = (h->precision == IBM_FP64) ? build_graph<double>(h) : build_graph<float>(h);
+      if (rc) return rc;
+    }
+    for (int s = 0; s < nsteps; ++s) HIPCHK(h, hipGraphLaunch(h->gexec, h->stream));
+    for (Instance& I : h->inst) {
+      I.step += nsteps;
+      I.time += nsteps * I.g.dt;
+    }
+    return IBM_OK;
+  }
+  for (Instance& I : h->inst) {
+    const int rc = (h->precision == IBM_FP64) ? run_steps<double>(h, I, nsteps, h->stream)
+                                              : run_steps<float>(h, I, nsteps, h->stream);
     if (rc) return rc;
   }
   return IBM_OK;
@@ -507,17 +585,18 @@ int ibm_solve_pressure(ibm_handle h, int32_t inst, const void* rhs, void* phi) {
     Fields<double> f = fields_of<double>(I);
     RUNK(h, K_DIV_FFTX, launch_div_fftx<double>(I.g, f, I.L, 0, I.px, I.rtw, 1.0, I.pi(), (const double*)rhs,
                                                  h->stream));
-    return poisson<double>(h, I, f, (double*)phi);
+    return poisson<double>(h, I, f, (double*)phi, h->stream);
   }
   Fields<float> f = fields_of<float>(I);
   RUNK(h, K_DIV_FFTX, launch_div_fftx<float>(I.g, f, I.L, 0, I.px, I.rtw, 1.0, I.pi(), (const float*)rhs,
                                               h->stream));
-  return poisson<float>(h, I, f, (float*)phi);
+  return poisson<float>(h, I, f, (float*)phi, h->stream);
 }
 
 int ibm_set_diagnostics(ibm_handle h, int32_t on) {
   if (!h) return fail(nullptr, IBM_ERR_ARG, "null handle");
   h->diag = on != 0;
+  drop_graph(h);
   return IBM_OK;
 }
 
@@ -601,6 +680,149 @@ int ibm_get_ibm_list(ibm_handle h, int32_t inst, int32_t comp, int32_t* idx, dou
   return IBM_OK;
 }
 
+int ibm_tune_set(ibm_handle h, int32_t param, int32_t value) {
+  if (!h) return fail(nullptr, IBM_ERR_ARG, "null handle");
+  if (value < 0) return fail(h, IBM_ERR_ARG, "tuning value must be >= 0 (0 = automatic)");
+  drop_graph(h);
+  if (param == IBM_TUNE_GRAPH) {
+    h->use_graph = value != 0;
+    return IBM_OK;
+  }
+  if (param == IBM_TUNE_GRAPH_BRANCHES) {
+    h->n_branches = value;
+    return IBM_OK;
+  }
+  for (Instance& I : h->inst) {
+    switch (param) {
+      case IBM_TUNE_MOMENTUM_PLANES: I.tu.mom_jc = value; break;
+      case IBM_TUNE_FFTZ_WIDTH: I.tu.fftz_w = value; break;
+      case IBM_TUNE_TRI_ROWS:
+        if (value != 0 && value != 4 && value != 8) return fail(h, IBM_ERR_ARG, "tri rows must be 0, 4 or 8");
+        I.tu.tri_rows = value;
+        break;
+      default: return fail(h, IBM_ERR_ARG, "unknown tuning parameter");
+    }
+  }
+  return IBM_OK;
+}
+
+int ibm_tune_get(ibm_handle h, int32_t param, int32_t* value) {
+  if (!h || !value) return fail(h, IBM_ERR_ARG, "null argument");
+  const Tuning& t = h->inst[0].tu;
+  switch (param) {
+    case IBM_TUNE_MOMENTUM_PLANES: *value = t.mom_jc; break;
+    case IBM_TUNE_FFTZ_WIDTH: *value = t.fftz_w; break;
+    case IBM_TUNE_TRI_ROWS: *value = t.tri_rows; break;
+    case IBM_TUNE_GRAPH: *value = h->use_graph ? 1 : 0; break;
+    case IBM_TUNE_GRAPH_BRANCHES: *value = h->n_branches; break;
+    default: return fail(h, IBM_ERR_ARG, "unknown tuning parameter");
+  }
+  return IBM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+template <typename T>
+int autotune_impl(ibm_ctx* c, Instance& I, int steps, int32_t* chosen) {
+  const GridParams& g = I.g;
+  const size_t fb = (size_t)g.ncell * sizeof(T);
+  void* save[4] = {nullptr, nullptr, nullptr, nullptr};
+  void* fld[4] = {I.u, I.v, I.w, I.p};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = IBM_OK;
+  const int64_t step0 = I.step;
+  const double time0 = I.time;
+  const bool prof = c->prof, diag = c->diag;
+  c->prof = false;
+  c->diag = false;
+  auto cleanup = [&]() {
+    for (void* p : save)
+      if (p) (void)hipFree(p);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    c->prof = prof;
+    c->diag = diag;
+  };
+  for (int q = 0; q < 4; ++q)
+    if (hipMalloc(&save[q], fb) != hipSuccess) {
+      cleanup();
+      return fail(c, IBM_ERR_OOM, "autotune state copy");
+    }
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    cleanup();
+    return fail(c, IBM_ERR_DEVICE, "autotune events");
+  }
+  for (int q = 0; q < 4 && !rc; ++q)
+    if (hipMemcpyAsync(save[q], fld[q], fb, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+      rc = fail(c, IBM_ERR_DEVICE, "autotune save");
+  // time `steps` steps from the saved state with the current knobs
+  auto trial = [&](float* ms) -> int {
+    for (int q = 0; q < 4; ++q)
+      if (hipMemcpyAsync(fld[q], save[q], fb, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+        return fail(c, IBM_ERR_DEVICE, "autotune restore");
+    int r = run_steps<T>(c, I, 1, c->stream);
+    if (r) return r;
+    if (hipEventRecord(e0, c->stream) != hipSuccess) return fail(c, IBM_ERR_DEVICE, "event");
+    r = run_steps<T>(c, I, steps, c->stream);
+    if (r) return r;
+    if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(ms, e0, e1) != hipSuccess)
+      return fail(c, IBM_ERR_DEVICE, "autotune timing");
+    return IBM_OK;
+  };
+  // candidates per knob, searched one knob at a time
+  std::vector<int> jc = {0, 2, 4, 6, 8, 12, 16, 24, 32, 48, 64};
+  int wv[8];
+  const int nw = fftz_widths<T>(g, I.pz, wv, 8);
+  std::vector<int> fw(wv, wv + nw);
+  std::vector<int> tr = {8, 4};
+  std::vector<int>* cand[3] = {&jc, &fw, &tr};
+  int* knob[3] = {&I.tu.mom_jc, &I.tu.fftz_w, &I.tu.tri_rows};
+  for (int kq = 0; kq < 3 && !rc; ++kq) {
+    float best = 1e30f;
+    int bestv = *knob[kq];
+    for (int v : *cand[kq]) {
+      if (kq == 0 && v > g.ny1) continue;
+      *knob[kq] = v;
+      float ms = 0.f;
+      rc = trial(&ms);
+      if (rc) break;
+      if (ms < best) {
+        best = ms;
+        bestv = v;
+      }
+    }
+    *knob[kq] = bestv;
+    if (chosen) chosen[kq] = bestv;
+  }
+  for (int q = 0; q < 4 && !rc; ++q)
+    if (hipMemcpyAsync(fld[q], save[q], fb, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+      rc = fail(c, IBM_ERR_DEVICE, "autotune restore");
+  if (!rc && hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(c, IBM_ERR_DEVICE, "autotune sync");
+  I.step = step0;
+  I.time = time0;
+  I.diag_valid = false;
+  cleanup();
+  return rc;
+}
+}  // namespace
+
+extern "C" {
+
+int ibm_autotune(ibm_handle h, int32_t steps_per_trial, int32_t* chosen) {
+  if (!h) return fail(nullptr, IBM_ERR_ARG, "null handle");
+  if (steps_per_trial < 1) return fail(h, IBM_ERR_ARG, "steps_per_trial must be >= 1");
+  drop_graph(h);
+  for (Instance& I : h->inst) {
+    if (!I.geom_ready) return fail(h, IBM_ERR_STATE, "autotune before ibm_set_geometry");
+    const int rc = (h->precision == IBM_FP64) ? autotune_impl<double>(h, I, steps_per_trial, chosen)
+                                              : autotune_impl<float>(h, I, steps_per_trial, chosen);
+    if (rc) return rc;
+  }
+  return IBM_OK;
+}
+
 int ibm_profile(ibm_handle h, int32_t on) {
   if (!h) return fail(nullptr, IBM_ERR_ARG, "null handle");
   if (on && h->ev.empty()) {
@@ -635,7 +857,7 @@ int ibm_profile_read(ibm_handle h, double* total_ms, int64_t* launches, int32_t 
 }
 
 const char* ibm_kernel_name(int32_t id) {
-  static const char* names[K_NUM_KERNELS] = {"momentum", "cfr", "ibm_pi", "div_fftx", "fftz_fwd", "tri", "fftz_inv",
+  static const char* names[K_NUM_KERNELS] = {"momentum", "cfr_pi", "div_fftx", "fftz_fwd", "tri", "fftz_inv",
                                              "ifftx", "correct", "diag", "stats", "geom"};
   if (id < 0 || id >= K_NUM_KERNELS) return "unknown";
   return names[id];
@@ -665,6 +887,11 @@ int ibm_destroy(ibm_handle h) {
     free_buf(I.ibm_choff);
   }
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+  drop_graph(h);
+  for (hipStream_t s2 : h->aux) (void)hipStreamDestroy(s2);
+  for (hipEvent_t e : h->ev_join) (void)hipEventDestroy(e);
+  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+  if (h->cap) (void)hipStreamDestroy(h->cap);
   delete h;
   return IBM_OK;
 }

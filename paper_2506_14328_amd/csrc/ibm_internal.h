@@ -20,7 +20,7 @@ enum : uint8_t {
 
 // Kernel ids (profiling).
 enum KernelId {
-  K_MOMENTUM = 0, K_CFR, K_IBM_PI, K_DIV_FFTX, K_FFTZ_FWD, K_TRI, K_FFTZ_INV, K_IFFTX, K_CORRECT, K_DIAG, K_STATS,
+  K_MOMENTUM = 0, K_CFR_PI, K_DIV_FFTX, K_FFTZ_FWD, K_TRI, K_FFTZ_INV, K_IFFTX, K_CORRECT, K_DIAG, K_STATS,
   K_GEOM, K_NUM_KERNELS
 };
 
@@ -147,24 +147,34 @@ struct Fields {
   const uint8_t* tag;
 };
 
+// Launch-shape knobs (0 = automatic choice); set directly or by the autotuner.
+struct Tuning {
+  int mom_jc = 0;     // y planes per momentum block
+  int fftz_w = 0;     // x modes per z-FFT block
+  int tri_rows = 0;   // rows per thread of the tridiagonal partition solver (4 or 8)
+};
+
 // step kernels
 template <typename T>
 hipError_t launch_momentum(const GridParams& g, const Fields<T>& f, const IbmLists& L, const StageConsts& s,
-                           double* qpart, int* nqpart, hipStream_t st);
-hipError_t launch_cfr(const double* qpart, int nq, double scale, int forcing, double q_target_or_pi,
-                      const double* S3, int stage, double* pi_out, double* pi_hist, hipStream_t st);
+                           const Tuning& tu, double* qpart, int* nqpart, hipStream_t st);
 template <typename T>
-hipError_t launch_ibm_pi(const Fields<T>& f, const IbmLists& L, int stage, double ck_dt, const double* pi,
-                         hipStream_t st);
+hipError_t launch_cfr_pi(const Fields<T>& f, const IbmLists& L, int stage, double ck_dt, const double* qpart, int nq,
+                         double scale, int forcing, double q_target_or_pi, const double* S3, double* pi_out,
+                         double* pi_hist, hipStream_t st);
 template <typename T>
 hipError_t launch_div_fftx(const GridParams& g, const Fields<T>& f, const IbmLists& L, int stage,
                            const FFTPlan& px, const double2* rtw, double ck_dt, const double* pi, const T* rhs_in,
                            hipStream_t st);
 template <typename T>
-hipError_t launch_fftz(const GridParams& g, cplx<T>* spec, const FFTPlan& pz, int sign, hipStream_t st);
+hipError_t launch_fftz(const GridParams& g, cplx<T>* spec, const FFTPlan& pz, int sign, const Tuning& tu,
+                       hipStream_t st);
 template <typename T>
 hipError_t launch_tri(const GridParams& g, cplx<T>* spec, const double* kx2, const double* kz2,
-                      double* mean_out, hipStream_t st);
+                      double* mean_out, const Tuning& tu, hipStream_t st);
+// Valid z-FFT widths for this grid (ascending), written to out; returns the count.
+template <typename T>
+int fftz_widths(const GridParams& g, const FFTPlan& pz, int* out, int max);
 template <typename T>
 hipError_t launch_ifftx(const GridParams& g, const cplx<T>* spec, T* out, const FFTPlan& px,
                         const double2* rtw, hipStream_t st);

@@ -73,17 +73,21 @@ __global__ __launch_bounds__(256) void k_momentum(GridParams g, Fields<T> f, Ibm
   auto slot = [](int jj) { return (jj + 3) % 3; };
   // prologue: planes j0-1, j0, j0+1 of u, v, w and plane j0 of p
   {
-    T ru[MLOADS], rv[MLOADS], rw[MLOADS];
-    for (int jj = j0 - 1; jj <= j0 + 1; ++jj) {
-      fetch(f.u, jj, ru);
-      fetch(f.v, jj, rv);
-      fetch(f.w, jj, rw);
-      put(ring[0][slot(jj)], ru);
-      put(ring[1][slot(jj)], rv);
-      put(ring[2][slot(jj)], rw);
+    T ru[3][MLOADS], rv[3][MLOADS], rw[3][MLOADS], rp[MLOADS];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      fetch(f.u, j0 - 1 + q, ru[q]);
+      fetch(f.v, j0 - 1 + q, rv[q]);
+      fetch(f.w, j0 - 1 + q, rw[q]);
     }
-    fetch(f.p, j0, ru);
-    put(ptile, ru);
+    fetch(f.p, j0, rp);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      put(ring[0][slot(j0 - 1 + q)], ru[q]);
+      put(ring[1][slot(j0 - 1 + q)], rv[q]);
+      put(ring[2][slot(j0 - 1 + q)], rw[q]);
+    }
+    put(ptile, rp);
   }
   const int cc = (tz + 1) * MHX + (tx + 1);   // centre inside a tile
   T p_prev = (act && j0 > 0) ? f.p[(j0 - 1) * plane + k * nx + i] : T(0);
@@ -214,14 +218,20 @@ __global__ __launch_bounds__(256) void k_momentum(GridParams g, Fields<T> f, Ibm
 }
 
 // ---------------------------------------------------------------------------------------
-// cfr: Q(u*_0) = (dy dz / nx) sum u*_0 over internal u; Pi_k = (Q - Q_t) / S_k so that
-// Q(u*_0 - Pi_k c_k dt / A) = Q_t exactly.  One block; fixed summation order.
+// cfr_pi: Q(u*_0) = (dy dz / nx) sum u*_0 over internal u; Pi_k = (Q - Q_t) / S_k so that
+// Q(u*_0 - Pi_k c_k dt / A) = Q_t exactly (constant pressure gradient: Pi_k = Pi).  Every
+// block reduces the momentum partials in the same fixed order (so all blocks hold the
+// same Pi_k, deterministically); block 0 publishes it for the later kernels; each thread
+// applies u* -= Pi_k c_k dt / A at one immersed-boundary u face.  div_fftx, correct and
+// the diagnostics apply -Pi_k c_k dt to the other internal u faces themselves.
 // ---------------------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_cfr(const double* __restrict__ qpart, int nq, double scale,
-                                              int forcing, double qt, const double* __restrict__ S3,
-                                              int stage, double* __restrict__ pi_out,
-                                              double* __restrict__ pi_hist) {
-  __shared__ double red[16];
+template <typename T>
+__global__ __launch_bounds__(256) void k_cfr_pi(Fields<T> f, IbmLists L, int stage, double ck_dt,
+                                               const double* __restrict__ qpart, int nq, double scale, int forcing,
+                                               double qt, const double* __restrict__ S3,
+                                               double* __restrict__ pi_out, double* __restrict__ pi_hist) {
+  __shared__ double red[4];
+  __shared__ double pi_s;
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   const int stride = blockDim.x * 8;
   for (int base = threadIdx.x; base < nq; base += stride) {
@@ -236,22 +246,19 @@ __global__ __launch_bounds__(1024) void k_cfr(const double* __restrict__ qpart, 
   if (threadIdx.x == 0) {
     const double q0 = tot * scale;
     const double pi = (forcing == 0) ? (q0 - qt) / S3[stage] : qt;
-    pi_out[0] = pi;
-    pi_hist[0] = pi;
-    pi_hist[1] = q0;
+    pi_s = pi;
+    if (blockIdx.x == 0) {
+      pi_out[0] = pi;
+      pi_hist[0] = pi;
+      pi_hist[1] = q0;
+    }
   }
-}
-
-// u* <- u* - Pi c_k dt / A at immersed-boundary u points; div_fftx, correct and the
-// diagnostics apply -Pi c_k dt to the other internal u faces themselves.
-template <typename T>
-__global__ __launch_bounds__(256) void k_ibm_pi(Fields<T> f, IbmLists L, int stage, double ck_dt,
-                                               const double* __restrict__ pi) {
+  __syncthreads();
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g < L.n_u) {
     const int id = L.idx[g];
     const double inva = L.coef[(size_t)stage * L.n_total + g].y;
-    f.us[id] = T((double)f.us[id] - pi[0] * ck_dt * inva);
+    f.us[id] = T((double)f.us[id] - pi_s * ck_dt * inva);
   }
 }
 
@@ -366,11 +373,10 @@ __global__ __launch_bounds__(256) void k_fftz(GridParams g, cplx<T>* __restrict_
 // in LDS; each thread then recovers its interior rows.  The spectrum is read once
 // and written once.  W = 256/P modes per block, lane = p * W + w.
 // ---------------------------------------------------------------------------------------
-template <typename T>
+template <typename T, int LM>
 __global__ __launch_bounds__(256) void k_tri(GridParams g, cplx<T>* __restrict__ spec,
                                             const double* __restrict__ kx2, const double* __restrict__ kz2,
                                             int P, int W, double* __restrict__ mean_out) {
-  constexpr int LM = 8;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* lds = reinterpret_cast<double*>(smem_raw);
   const int n = g.ny1, Q = g.nmodes;
@@ -671,8 +677,9 @@ static inline dim3 cell_grid(const GridParams& g) {
   return dim3((g.nx + BX - 1) / BX, (g.nz + BZ - 1) / BZ, g.ny1);
 }
 
-// y planes per momentum block: about 2048 blocks, 4..64 planes each.
-static int momentum_chunk(const GridParams& g) {
+// y planes per momentum block: about 2048 blocks, 4..64 planes each, unless tuned.
+static int momentum_chunk(const GridParams& g, const Tuning& tu) {
+  if (tu.mom_jc > 0) return tu.mom_jc < g.ny1 ? tu.mom_jc : g.ny1;
   const long cols = (long)((g.nx + MX - 1) / MX) * ((g.nz + MZ - 1) / MZ);
   long jc = (g.ny1 * cols + 2047) / 2048;
   if (jc < 4) jc = 4;
@@ -682,26 +689,21 @@ static int momentum_chunk(const GridParams& g) {
 
 template <typename T>
 hipError_t launch_momentum(const GridParams& g, const Fields<T>& f, const IbmLists& L, const StageConsts& s,
-                           double* qpart, int* nqpart, hipStream_t st) {
-  const int jc = momentum_chunk(g);
+                           const Tuning& tu, double* qpart, int* nqpart, hipStream_t st) {
+  const int jc = momentum_chunk(g, tu);
   const dim3 grid((g.nx + MX - 1) / MX, (g.nz + MZ - 1) / MZ, (g.ny1 + jc - 1) / jc);
   hipLaunchKernelGGL(k_momentum<T>, grid, dim3(MX, MZ), 0, st, g, f, L, s, jc, qpart);
   *nqpart = grid.x * grid.y * grid.z;
   return hipGetLastError();
 }
 
-hipError_t launch_cfr(const double* qpart, int nq, double scale, int forcing, double q_target_or_pi,
-                      const double* S3, int stage, double* pi_out, double* pi_hist, hipStream_t st) {
-  hipLaunchKernelGGL(k_cfr, dim3(1), dim3(1024), 0, st, qpart, nq, scale, forcing, q_target_or_pi, S3, stage,
-                     pi_out, pi_hist);
-  return hipGetLastError();
-}
-
 template <typename T>
-hipError_t launch_ibm_pi(const Fields<T>& f, const IbmLists& L, int stage, double ck_dt, const double* pi,
-                         hipStream_t st) {
-  if (L.n_u == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ibm_pi<T>, dim3((L.n_u + 255) / 256), dim3(256), 0, st, f, L, stage, ck_dt, pi);
+hipError_t launch_cfr_pi(const Fields<T>& f, const IbmLists& L, int stage, double ck_dt, const double* qpart, int nq,
+                         double scale, int forcing, double q_target_or_pi, const double* S3, double* pi_out,
+                         double* pi_hist, hipStream_t st) {
+  const int nb = L.n_u > 0 ? (L.n_u + 255) / 256 : 1;
+  hipLaunchKernelGGL(k_cfr_pi<T>, dim3(nb), dim3(256), 0, st, f, L, stage, ck_dt, qpart, nq, scale, forcing,
+                     q_target_or_pi, S3, pi_out, pi_hist);
   return hipGetLastError();
 }
 
@@ -719,18 +721,39 @@ hipError_t launch_div_fftx(const GridParams& g, const Fields<T>& f, const IbmLis
   return hipGetLastError();
 }
 
-// Columns per z-FFT block: 128-byte rows (8 FP64 / 16 FP32 complex values), at least
-// nz/8 threads per column (register staging of the in-place stages) and <= 64 KiB LDS.
+// A z-FFT width W (x modes per block) is valid when the block's 256 threads give each
+// column enough lanes for the in-place stages (<= 4 butterflies per thread) and the
+// tile plus twiddles fit 64 KiB of LDS.
 template <typename T>
-static int fftz_width(int nz) {
+static bool fftz_width_ok(const GridParams& g, const FFTPlan& pz, int W) {
+  if (W < 1 || W > 256 || 256 % W) return false;
+  int nbmax = 1;
+  for (int s = 0; s < pz.nst; ++s) nbmax = nbmax > pz.n / pz.radix[s] ? nbmax : pz.n / pz.radix[s];
+  if ((nbmax + 256 / W - 1) / (256 / W) > 4) return false;
+  return ((size_t)W + 1) * g.nz * sizeof(cplx<T>) <= 65536;
+}
+
+template <typename T>
+int fftz_widths(const GridParams& g, const FFTPlan& pz, int* out, int max) {
+  int n = 0;
+  for (int W = 1; W <= 64 && n < max; W <<= 1)
+    if (fftz_width_ok<T>(g, pz, W)) out[n++] = W;
+  return n;
+}
+
+// Default: 128-byte rows (8 FP64 / 16 FP32 complex values) or the widest valid below.
+template <typename T>
+static int fftz_width(const GridParams& g, const FFTPlan& pz, const Tuning& tu) {
+  if (tu.fftz_w > 0 && fftz_width_ok<T>(g, pz, tu.fftz_w)) return tu.fftz_w;
   int W = (int)(128 / sizeof(cplx<T>));
-  while (W > 1 && (256 / W < (nz + 7) / 8 || ((size_t)W + 1) * nz * sizeof(cplx<T>) > 65536)) W >>= 1;
+  while (W > 1 && !fftz_width_ok<T>(g, pz, W)) W >>= 1;
   return W;
 }
 
 template <typename T>
-hipError_t launch_fftz(const GridParams& g, cplx<T>* spec, const FFTPlan& pz, int sign, hipStream_t st) {
-  const int W = fftz_width<T>(g.nz);
+hipError_t launch_fftz(const GridParams& g, cplx<T>* spec, const FFTPlan& pz, int sign, const Tuning& tu,
+                       hipStream_t st) {
+  const int W = fftz_width<T>(g, pz, tu);
   const size_t lds = ((size_t)W + 1) * g.nz * sizeof(cplx<T>);
   const int mb = fft_max_bfly(pz, 256 / W);
   const dim3 grid((g.mh + W - 1) / W, g.ny1);
@@ -742,13 +765,19 @@ hipError_t launch_fftz(const GridParams& g, cplx<T>* spec, const FFTPlan& pz, in
 
 template <typename T>
 hipError_t launch_tri(const GridParams& g, cplx<T>* spec, const double* kx2, const double* kz2, double* mean_out,
-                      hipStream_t st) {
+                      const Tuning& tu, hipStream_t st) {
   const int n = g.ny1;
-  const int P = (n + 7) / 8;           // segments of at most 8 rows, at least 2
-  const int W = 256 / P;               // modes per block
+  const int L = (tu.tri_rows == 4) ? 4 : 8;  // rows per thread
+  int P = (n + L - 1) / L;                   // segments of at most L rows ...
+  if (P > n / 2) P = n / 2 > 0 ? n / 2 : 1;  // ... and at least 2
+  if (P > 256) P = 256;
+  const int W = 256 / P;                     // modes per block
   const size_t lds = (size_t)(5 * W * 2 * P + 2 * P) * sizeof(double);
-  hipLaunchKernelGGL(k_tri<T>, dim3((g.nmodes + W - 1) / W), dim3(256), lds, st, g, spec, kx2, kz2, P, W,
-                     mean_out);
+  const dim3 grid((g.nmodes + W - 1) / W);
+  if (L == 4 && (n + P - 1) / P <= 4)
+    hipLaunchKernelGGL((k_tri<T, 4>), grid, dim3(256), lds, st, g, spec, kx2, kz2, P, W, mean_out);
+  else
+    hipLaunchKernelGGL((k_tri<T, 8>), grid, dim3(256), lds, st, g, spec, kx2, kz2, P, W, mean_out);
   return hipGetLastError();
 }
 
@@ -782,15 +811,17 @@ hipError_t launch_copy(const T* src, T* dst, int64_t n, hipStream_t st) {
 
 #define IBM_INST(T)                                                                                              \
   template hipError_t launch_momentum<T>(const GridParams&, const Fields<T>&, const IbmLists&,                  \
-                                         const StageConsts&, double*, int*, hipStream_t);                        \
-  template hipError_t launch_ibm_pi<T>(const Fields<T>&, const IbmLists&, int, double, const double*,           \
-                                       hipStream_t);                                                             \
+                                         const StageConsts&, const Tuning&, double*, int*, hipStream_t);         \
+  template hipError_t launch_cfr_pi<T>(const Fields<T>&, const IbmLists&, int, double, const double*, int,      \
+                                       double, int, double, const double*, double*, double*, hipStream_t);       \
   template hipError_t launch_div_fftx<T>(const GridParams&, const Fields<T>&, const IbmLists&, int,             \
                                          const FFTPlan&, const double2*, double, const double*, const T*,        \
                                          hipStream_t);                                                           \
-  template hipError_t launch_fftz<T>(const GridParams&, cplx<T>*, const FFTPlan&, int, hipStream_t);            \
+  template hipError_t launch_fftz<T>(const GridParams&, cplx<T>*, const FFTPlan&, int, const Tuning&,           \
+                                     hipStream_t);                                                               \
+  template int fftz_widths<T>(const GridParams&, const FFTPlan&, int*, int);                                    \
   template hipError_t launch_tri<T>(const GridParams&, cplx<T>*, const double*, const double*, double*,         \
-                                    hipStream_t);                                                                \
+                                    const Tuning&, hipStream_t);                                                 \
   template hipError_t launch_ifftx<T>(const GridParams&, const cplx<T>*, T*, const FFTPlan&, const double2*,    \
                                       hipStream_t);                                                              \
   template hipError_t launch_correct<T>(const GridParams&, const Fields<T>&, const IbmLists&, int, double,      \

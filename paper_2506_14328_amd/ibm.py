@@ -28,8 +28,9 @@ EXPORTED = [
     "ibm_create_grid", "ibm_set_geometry", "ibm_set_state", "ibm_get_state", "ibm_step",
     "ibm_solve_pressure", "ibm_stats", "ibm_set_diagnostics", "ibm_get_geometry", "ibm_get_ibm_list",
     "ibm_profile", "ibm_profile_read", "ibm_kernel_name", "ibm_num_kernels", "ibm_device_bytes",
-    "ibm_destroy", "ibm_last_error",
+    "ibm_destroy", "ibm_last_error", "ibm_tune_set", "ibm_tune_get", "ibm_autotune",
 ]
+TUNE_PARAMS = {"momentum_planes": 0, "fftz_width": 1, "tri_rows": 2, "graph": 3, "graph_branches": 4}
 
 
 class IbmGridDesc(ctypes.Structure):
@@ -82,6 +83,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "ibm_kernel_name": (ctypes.c_char_p, [c_int32]),
         "ibm_num_kernels": (c_int32, []),
         "ibm_device_bytes": (c_int64, [h]),
+        "ibm_tune_set": (c_int32, [h, c_int32, c_int32]),
+        "ibm_tune_get": (c_int32, [h, c_int32, POINTER(c_int32)]),
+        "ibm_autotune": (c_int32, [h, c_int32, POINTER(c_int32)]),
         "ibm_destroy": (c_int32, [h]),
         "ibm_last_error": (ctypes.c_char_p, [h]),
     }
@@ -97,13 +101,19 @@ def _ptr(t: torch.Tensor) -> int:
     return t.data_ptr()
 
 
+def _desc(c, ibm: bool) -> IbmGridDesc:
+    return IbmGridDesc(c.nx, c.ny, c.nz, c.forcing, c.b_mode, 1 if ibm else 0, c.lx, c.lz, c.y_lo, c.y_hi, c.nu,
+                       c.dt, c.q_target_or_pi)
+
+
 class IbmGrid:
-    """One channel instance on the current HIP device and torch's current stream."""
+    """One channel instance, or an ensemble of independent instances (per-instance calls
+    take `inst`), on the current HIP device and torch's current stream."""
 
     def __init__(self, nx: int, ny: int, nz: int, lx: float, lz: float, y_lo: float, y_hi: float,
                  nu: float, dt: float, forcing: int = IBM_CFR, q_target_or_pi: float = 0.0,
                  b_mode: int = IBM_B_EXP, ibm: bool = True, precision: str = "fp64",
-                 stream: Optional[torch.cuda.Stream] = None):
+                 stream: Optional[torch.cuda.Stream] = None, _descs=None):
         self.lib = load_library()
         if precision not in ("fp64", "fp32"):
             raise ValueError("precision must be 'fp64' or 'fp32'")
@@ -111,20 +121,32 @@ class IbmGrid:
         self.dtype = torch.float64 if precision == "fp64" else torch.float32
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        self.desc = IbmGridDesc(nx, ny, nz, forcing, b_mode, 1 if ibm else 0, lx, lz, y_lo, y_hi, nu, dt,
-                                q_target_or_pi)
-        self.nx, self.ny, self.nz = nx, ny, nz
-        self.shape = (ny - 1, nz, nx)
+        if _descs is None:
+            _descs = [IbmGridDesc(nx, ny, nz, forcing, b_mode, 1 if ibm else 0, lx, lz, y_lo, y_hi, nu, dt,
+                                  q_target_or_pi)]
+        n = len(_descs)
+        self.descs = (IbmGridDesc * n)(*_descs)
+        self.n_inst = n
+        self.dims = [(d.nx, d.ny, d.nz) for d in _descs]
+        self.nx, self.ny, self.nz = self.dims[0]
+        self.shape = (self.ny - 1, self.nz, self.nx)
         self._h = c_void_p()
-        rc = self.lib.ibm_create_grid(ctypes.byref(self.desc), 1,
-                                      IBM_FP64 if precision == "fp64" else IBM_FP32_STORAGE,
+        rc = self.lib.ibm_create_grid(self.descs, n, IBM_FP64 if precision == "fp64" else IBM_FP32_STORAGE,
                                       c_void_p(self.stream.cuda_stream), ctypes.byref(self._h))
         self._check(rc, None)
 
     @classmethod
     def from_case(cls, c, precision: str = "fp64", ibm: bool = True, **kw) -> "IbmGrid":
-        return cls(c.nx, c.ny, c.nz, c.lx, c.lz, c.y_lo, c.y_hi, c.nu, c.dt, c.forcing, c.q_target_or_pi,
-                   c.b_mode, ibm=ibm, precision=precision, **kw)
+        return cls(0, 0, 0, 0, 0, 0, 0, 0, 0, precision=precision, _descs=[_desc(c, ibm)], **kw)
+
+    @classmethod
+    def ensemble(cls, cases, precision: str = "fp32", ibm: bool = True, **kw) -> "IbmGrid":
+        """Independent instances of ragged sizes advanced together by step()."""
+        return cls(0, 0, 0, 0, 0, 0, 0, 0, 0, precision=precision, _descs=[_desc(c, ibm) for c in cases], **kw)
+
+    def shape_of(self, inst: int = 0):
+        nx, ny, nz = self.dims[inst]
+        return (ny - 1, nz, nx)
 
     # -- helpers ---------------------------------------------------------------------------
     def _check(self, rc: int, h=-1):
@@ -142,42 +164,44 @@ class IbmGrid:
             raise TypeError(f"expected dtype {dtype}, got {t.dtype}")
         return t.contiguous()
 
-    def empty(self) -> torch.Tensor:
-        return torch.empty(self.shape, dtype=self.dtype, device=self.device)
+    def empty(self, inst: int = 0) -> torch.Tensor:
+        return torch.empty(self.shape_of(inst), dtype=self.dtype, device=self.device)
 
     # -- API -------------------------------------------------------------------------------
-    def set_geometry(self, sdf_u: torch.Tensor, sdf_v: torch.Tensor, sdf_w: torch.Tensor):
-        ny, nz, nx = self.ny, self.nz, self.nx
+    def set_geometry(self, sdf_u: torch.Tensor, sdf_v: torch.Tensor, sdf_w: torch.Tensor, inst: int = 0):
+        nx, ny, nz = self.dims[inst]
         su = self._field(sdf_u, (ny + 1, nz, nx), torch.float64)
         sv = self._field(sdf_v, (ny, nz, nx), torch.float64)
         sw = self._field(sdf_w, (ny + 1, nz, nx), torch.float64)
-        self._check(self.lib.ibm_set_geometry(self._h, 0, _ptr(su), _ptr(sv), _ptr(sw)))
+        self._check(self.lib.ibm_set_geometry(self._h, inst, _ptr(su), _ptr(sv), _ptr(sw)))
 
-    def set_state(self, u, v, w, p):
-        ts = [self._field(t, self.shape, self.dtype) for t in (u, v, w, p)]
-        self._check(self.lib.ibm_set_state(self._h, 0, *[_ptr(t) for t in ts]))
-        self._keep = ts     # keep the sources alive until the stream-ordered copies ran
+    def set_state(self, u, v, w, p, inst: int = 0):
+        ts = [self._field(t, self.shape_of(inst), self.dtype) for t in (u, v, w, p)]
+        self._check(self.lib.ibm_set_state(self._h, inst, *[_ptr(t) for t in ts]))
+        if not hasattr(self, "_keep"):
+            self._keep = {}
+        self._keep[inst] = ts   # keep the sources alive until the stream-ordered copies ran
 
-    def get_state(self) -> Tuple[torch.Tensor, ...]:
-        out = [self.empty() for _ in range(4)]
-        self._check(self.lib.ibm_get_state(self._h, 0, *[_ptr(t) for t in out]))
+    def get_state(self, inst: int = 0) -> Tuple[torch.Tensor, ...]:
+        out = [self.empty(inst) for _ in range(4)]
+        self._check(self.lib.ibm_get_state(self._h, inst, *[_ptr(t) for t in out]))
         return tuple(out)
 
     def step(self, nsteps: int = 1):
         self._check(self.lib.ibm_step(self._h, int(nsteps)))
 
-    def solve_pressure(self, rhs: torch.Tensor) -> torch.Tensor:
-        r = self._field(rhs, self.shape, self.dtype)
-        phi = self.empty()
-        self._check(self.lib.ibm_solve_pressure(self._h, 0, _ptr(r), _ptr(phi)))
+    def solve_pressure(self, rhs: torch.Tensor, inst: int = 0) -> torch.Tensor:
+        r = self._field(rhs, self.shape_of(inst), self.dtype)
+        phi = self.empty(inst)
+        self._check(self.lib.ibm_solve_pressure(self._h, inst, _ptr(r), _ptr(phi)))
         return phi
 
     def set_diagnostics(self, on: bool = True):
         self._check(self.lib.ibm_set_diagnostics(self._h, 1 if on else 0))
 
-    def stats(self, raise_unstable: bool = False) -> Dict:
+    def stats(self, raise_unstable: bool = False, inst: int = 0) -> Dict:
         s = IbmStats()
-        rc = self.lib.ibm_stats(self._h, 0, ctypes.byref(s))
+        rc = self.lib.ibm_stats(self._h, inst, ctypes.byref(s))
         if rc != IBM_OK and (rc != IBM_ERR_UNSTABLE or raise_unstable):
             self._check(rc)
         d = {f: getattr(s, f) for f, _ in IbmStats._fields_ if f not in ("n_internal", "n_ibm", "reserved")}
@@ -186,19 +210,19 @@ class IbmGrid:
         d["unstable"] = rc == IBM_ERR_UNSTABLE
         return d
 
-    def geometry(self) -> Tuple[torch.Tensor, list]:
-        tags = torch.empty(self.shape, dtype=torch.uint8, device=self.device)
+    def geometry(self, inst: int = 0) -> Tuple[torch.Tensor, list]:
+        tags = torch.empty(self.shape_of(inst), dtype=torch.uint8, device=self.device)
         n = (c_int64 * 3)()
-        self._check(self.lib.ibm_get_geometry(self._h, 0, _ptr(tags), n))
+        self._check(self.lib.ibm_get_geometry(self._h, inst, _ptr(tags), n))
         return tags, list(n)
 
-    def ibm_list(self, comp: int):
-        _, n = self.geometry()
+    def ibm_list(self, comp: int, inst: int = 0):
+        _, n = self.geometry(inst)
         m = n[comp]
         idx = torch.empty(max(m, 1), dtype=torch.int32, device=self.device)
         lam = torch.empty(max(m, 1), dtype=torch.float64, device=self.device)
         coef = torch.empty((3, max(m, 1), 2), dtype=torch.float64, device=self.device)
-        self._check(self.lib.ibm_get_ibm_list(self._h, 0, comp, _ptr(idx), _ptr(lam), _ptr(coef)))
+        self._check(self.lib.ibm_get_ibm_list(self._h, inst, comp, _ptr(idx), _ptr(lam), _ptr(coef)))
         return idx[:m], lam[:m], coef[:, :m]
 
     def kernel_names(self):
@@ -225,6 +249,25 @@ class IbmGrid:
         cnt = (c_int64 * nk)()
         self._check(self.lib.ibm_profile_read(self._h, ms, cnt, nk))
         return {self.lib.ibm_kernel_name(k).decode(): (ms[k], cnt[k]) for k in range(nk) if cnt[k] > 0}
+
+    def tune(self, **knobs):
+        """Set launch-shape knobs by name (momentum_planes, fftz_width, tri_rows); 0 = automatic."""
+        for k, v in knobs.items():
+            self._check(self.lib.ibm_tune_set(self._h, TUNE_PARAMS[k], int(v)))
+
+    def tuning(self) -> Dict[str, int]:
+        out = {}
+        for k, pid in TUNE_PARAMS.items():
+            v = c_int32()
+            self._check(self.lib.ibm_tune_get(self._h, pid, ctypes.byref(v)))
+            out[k] = v.value
+        return out
+
+    def autotune(self, steps_per_trial: int = 2) -> Dict[str, int]:
+        """Run the library's autotuner (state is saved and restored) and return the choice."""
+        ch = (c_int32 * 3)()
+        self._check(self.lib.ibm_autotune(self._h, int(steps_per_trial), ch))
+        return dict(zip(["momentum_planes", "fftz_width", "tri_rows"], list(ch)))
 
     def device_bytes(self) -> int:
         return int(self.lib.ibm_device_bytes(self._h))

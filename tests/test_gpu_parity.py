@@ -215,3 +215,79 @@ def test_nan_detected():
     s = g.stats()
     assert s["nan_flag"] == 1 and s["unstable"]
     g.close()
+
+
+def test_autotune_keeps_trajectory():
+    """The autotuner restores the state: stepping after it matches stepping without it,
+    and every knob setting it tried gives the same result up to rounding."""
+    c = case("wavy_160")
+    o, sdf, st = oracle_run(c, 3)
+    g = gpu_grid(c, sdf, st)
+    chosen = g.autotune(1)
+    assert set(chosen) == {"momentum_planes", "fftz_width", "tri_rows"}
+    assert g.stats()["step"] == 0
+    g.step(3)
+    u, v, w, p = [t.cpu().numpy() for t in g.get_state()]
+    assert rel_err(u, o.u) < 1e-12 and rel_err(v, o.v) < 1e-12 and rel_err(w, o.w) < 1e-12
+    for knobs in (dict(momentum_planes=3, fftz_width=2, tri_rows=4), dict(momentum_planes=64, tri_rows=8)):
+        g2 = gpu_grid(c, sdf, st)
+        g2.tune(**knobs)
+        g2.step(3)
+        u2 = g2.get_state()[0].cpu().numpy()
+        assert rel_err(u2, o.u) < 1e-12
+        g2.close()
+    g.close()
+
+
+def _ensemble_members():
+    return [case("wavy_small"), case("flat_small"), case("ellip_small"), case("wavy_160", nu=1 / 700.0),
+            case("minimal")]
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_ensemble_matches_oracle_per_instance(graph):
+    """Ragged independent instances advanced together equal their own oracle runs."""
+    from paper_2506_14328_amd import IbmGrid
+    members = _ensemble_members()
+    refs = [oracle_run(c, 2) for c in members]
+    g = IbmGrid.ensemble(members, precision="fp64")
+    g.tune(graph=1 if graph else 0, graph_branches=3)
+    for i, (o, sdf, st) in enumerate(refs):
+        g.set_geometry(*[to_dev(s) for s in sdf], inst=i)
+        g.set_state(*[to_dev(a) for a in st], inst=i)
+    g.step(1)
+    g.step(1)
+    for i, (o, sdf, st) in enumerate(refs):
+        u, v, w, p = [t.cpu().numpy() for t in g.get_state(inst=i)]
+        for a, b in ((u, o.u), (v, o.v), (w, o.w)):
+            assert rel_err(a, b) < 1e-12, (i, members[i].name)
+        assert g.stats(inst=i)["step"] == 2
+    g.close()
+
+
+def test_graph_replays_match_eager():
+    """Every replay of the captured step equals the eager launches, with eager work and
+    synchronisations between the replays."""
+    from paper_2506_14328_amd import IbmGrid
+    members = _ensemble_members()[:3]
+    ins = [oracle_run(c, 0) for c in members]
+    gs = []
+    for graph in (False, True):
+        g = IbmGrid.ensemble(members, precision="fp64")
+        g.tune(graph=1 if graph else 0)
+        for i, (o, sdf, st) in enumerate(ins):
+            g.set_geometry(*[to_dev(s) for s in sdf], inst=i)
+            g.set_state(*[to_dev(a) for a in st], inst=i)
+        gs.append(g)
+    for rep in range(4):
+        for g in gs:
+            g.step(1)
+        torch.cuda.synchronize()
+        _ = (torch.ones(1000, device=device()) * rep).sum().item()    # unrelated eager work
+        for i in range(len(members)):
+            a = [t.cpu().numpy() for t in gs[0].get_state(inst=i)]
+            b = [t.cpu().numpy() for t in gs[1].get_state(inst=i)]
+            for x, y in zip(a, b):
+                assert np.array_equal(x, y), (rep, i)
+    for g in gs:
+        g.close()
