@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--no-forms", action="store_true", help="skip the extra forms (FP32, large grid, IBM off)")
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup + steps without extra forms or baseline (for rocprofv3)")
+    ap.add_argument("--tuning", default="",
+                    help="fixed tuning knobs instead of the autotuner, e.g. momentum_planes=12,fftz_width=8")
     ap.add_argument("--copy-calibration-mb", type=float, default=0.0,
                     help="also run a plain device copy of this many MiB (PMC counter calibration)")
     return ap.parse_args()
@@ -154,11 +156,16 @@ def dominant_kernel(g, nsteps=3):
     return k, {n: round(100.0 * v / s, 1) for n, v in tot.items()}
 
 
-def measure(name, precision, steps, warmup, ibm=True, inputs=None, autotune=True, keep_state=False):
+def measure(name, precision, steps, warmup, ibm=True, inputs=None, tuning=None, keep_state=False):
+    """tuning: None runs the autotuner; a dict sets those knobs."""
     c, sdf, st = inputs if inputs is not None else build_inputs(name)
     g = make_grid(c, sdf, st, precision, ibm)
     stats0 = g.stats()
-    tuned = g.autotune(2) if autotune else g.tuning()
+    if tuning is None:
+        tuned = g.autotune(2)
+    else:
+        g.tune(**tuning)
+        tuned = g.tuning()
     kern, shares = dominant_kernel(g)
     g.set_state(*[__import__("torch").as_tensor(a).to("cuda", g.dtype) for a in st])
     el, prof = timed_run(g, steps, warmup, kern)
@@ -268,15 +275,19 @@ def main():
 
     if a.copy_calibration_mb > 0:
         n = int(a.copy_calibration_mb * (1 << 20) // 8)
+        # a streaming kernel of its own name (an elementwise multiply), so that its
+        # counters can be told apart from the library's copies
         x = torch.ones(n, dtype=torch.float64, device="cuda")
         y = torch.empty_like(x)
         for _ in range(3):
-            y.copy_(x)
+            torch.mul(x, 2.0, out=y)
         torch.cuda.synchronize()
-        print(f"copy calibration: {n * 8} bytes read, {n * 8} bytes written per launch", flush=True)
+        print(f"copy calibration (elementwise multiply): {n * 8} bytes read, {n * 8} bytes written per launch",
+              flush=True)
 
     inputs = build_inputs(a.workload)
-    r = measure(a.workload, a.precision, a.steps, a.warmup, inputs=inputs)
+    fixed = {k: int(v) for k, v in (kv.split("=") for kv in a.tuning.split(",") if kv)} if a.tuning else None
+    r = measure(a.workload, a.precision, a.steps, a.warmup, inputs=inputs, tuning=fixed)
     if a.profile_only:
         print(json.dumps({"workload": r["case"].name, "ms_per_step": r["ms_per_step"], "kernel": r["kernel"],
                           "kernel_avg_us": r["kernel_avg_us"]}), flush=True)
