@@ -1,4 +1,4 @@
-// Mixed-radix (4, 2, 3, 5) Stockham FFT on data resident in LDS.
+// Mixed-radix (8, 4, 2, 3, 5) Stockham FFT on data resident in LDS.
 //
 // A group of `nlanes` threads transforms one sequence of length p.n whose
 // element e sits at buf[e * stride].  Each stage writes its self-sorted result
@@ -69,6 +69,30 @@ __device__ __forceinline__ void bfly5(cplx<T>* v, int sign) {
   v[3] = csub(r2, q2);
 }
 
+// 8-point DFT in place (natural order): two 4-point DFTs of the even and odd inputs,
+// combined with the powers of w = exp(sign 2 pi i / 8).
+template <typename T>
+__device__ __forceinline__ void bfly8(cplx<T>* v, int sign) {
+  const T h = T(0.70710678118654752440);   // sqrt(1/2)
+  cplx<T> e[4] = {v[0], v[2], v[4], v[6]};
+  cplx<T> o[4] = {v[1], v[3], v[5], v[7]};
+  bfly4(e, sign);
+  bfly4(o, sign);
+  const T sg = T(sign);
+  // w^1 = h (1 + sign i), w^2 = sign i, w^3 = h (-1 + sign i)
+  const cplx<T> o1 = {h * (o[1].x - sg * o[1].y), h * (o[1].y + sg * o[1].x)};
+  const cplx<T> o2 = {-sg * o[2].y, sg * o[2].x};
+  const cplx<T> o3 = {-h * (o[3].x + sg * o[3].y), h * (sg * o[3].x - o[3].y)};
+  v[0] = cadd(e[0], o[0]);
+  v[4] = csub(e[0], o[0]);
+  v[1] = cadd(e[1], o1);
+  v[5] = csub(e[1], o1);
+  v[2] = cadd(e[2], o2);
+  v[6] = csub(e[2], o2);
+  v[3] = cadd(e[3], o3);
+  v[7] = csub(e[3], o3);
+}
+
 // Twiddle w^m = exp(sign 2 pi i m / n) from the table tw[m] = exp(-2 pi i m / n) held in LDS.
 template <typename T>
 __device__ __forceinline__ cplx<T> tw_at(const cplx<T>* tw, int m, int sign) {
@@ -111,13 +135,20 @@ __device__ __forceinline__ void fft_stage_r(cplx<T>* buf, int n, int Ns, int str
 #pragma unroll
       for (int t = 0; t < R; ++t) v[q][t] = buf[(b + t * nb) * stride];
       if (k != 0) {
+        // w1 = w^(k tstep) from the table, higher powers by repeated multiplication
+        const cplx<T> w1 = tw_at<T>(tw, k * tstep, sign);
+        cplx<T> wt = w1;
 #pragma unroll
-        for (int t = 1; t < R; ++t) v[q][t] = cmul(v[q][t], tw_at<T>(tw, t * k * tstep, sign));
+        for (int t = 1; t < R; ++t) {
+          v[q][t] = cmul(v[q][t], wt);
+          if (t + 1 < R) wt = cmul(wt, w1);
+        }
       }
       if (R == 2) bfly2(v[q]);
       if (R == 3) bfly3(v[q], sign);
       if (R == 4) bfly4(v[q], sign);
       if (R == 5) bfly5(v[q], sign);
+      if (R == 8) bfly8(v[q], sign);
     }
   }
   __syncthreads();
@@ -143,6 +174,7 @@ __device__ void fft_lds(cplx<T>* buf, int stride, const FFTPlan& p, const cplx<T
   for (int s = 0; s < p.nst; ++s) {
     const int R = p.radix[s];
     switch (R) {
+      case 8: fft_stage_r<T, 8, MB>(buf, p.n, Ns, stride, tw, sign, lane, nlanes); break;
       case 4: fft_stage_r<T, 4, MB>(buf, p.n, Ns, stride, tw, sign, lane, nlanes); break;
       case 2: fft_stage_r<T, 2, MB>(buf, p.n, Ns, stride, tw, sign, lane, nlanes); break;
       case 3: fft_stage_r<T, 3, MB>(buf, p.n, Ns, stride, tw, sign, lane, nlanes); break;

@@ -113,6 +113,7 @@ hipError_t timed(ibm_ctx* c, int kid, F&& launch) {
 
 bool factor_235(int n, int* radix, int* nst) {
   int k = 0;
+  while (n % 8 == 0 && k < 20) { radix[k++] = 8; n /= 8; }
   while (n % 4 == 0 && k < 20) { radix[k++] = 4; n /= 4; }
   while (n % 2 == 0 && k < 20) { radix[k++] = 2; n /= 2; }
   while (n % 3 == 0 && k < 20) { radix[k++] = 3; n /= 3; }

@@ -47,7 +47,7 @@ struct GridParams {
 struct FFTPlan {
   int n;                // transform length
   int nst;              // number of radix stages
-  int radix[20];        // radix of each stage (4, 2, 3 or 5)
+  int radix[20];        // radix of each stage (8, 4, 2, 3 or 5)
   const double2* tw64;  // exp(-2 pi i m / n), m = 0..n-1
   const float2* tw32;
 };
