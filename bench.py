@@ -162,7 +162,8 @@ def measure(name, precision, steps, warmup, ibm=True, inputs=None, tuning=None, 
     g = make_grid(c, sdf, st, precision, ibm)
     stats0 = g.stats()
     if tuning is None:
-        tuned = g.autotune(2)
+        # trials of a few milliseconds each, so that timing noise does not decide
+        tuned = g.autotune(max(2, min(10, round(1.5e7 / (c.nx * (c.ny - 1) * c.nz)))))
     else:
         g.tune(**tuning)
         tuned = g.tuning()

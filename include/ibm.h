@@ -171,14 +171,18 @@ int32_t ibm_num_kernels(void);
  *   IBM_TUNE_MOMENTUM_PLANES  y planes marched by one momentum block
  *   IBM_TUNE_FFTZ_WIDTH       x modes per z-FFT block (power of two; invalid
  *                             widths fall back to the automatic one)
- *   IBM_TUNE_TRI_ROWS         rows per thread of the tridiagonal solver: 4 or 8 */
+ *   IBM_TUNE_TRI_ROWS         rows per thread of the tridiagonal solver: 4 or 8
+ *   IBM_TUNE_TILE_ORDER       momentum tiles: 1 = each XCD takes a contiguous run of
+ *                             tiles (neighbours share an L2), 2 = tiles interleaved
+ *                             over the XCDs */
 enum { IBM_TUNE_MOMENTUM_PLANES = 0, IBM_TUNE_FFTZ_WIDTH = 1, IBM_TUNE_TRI_ROWS = 2,
        IBM_TUNE_GRAPH = 3,            /* 1: ibm_step replays a HIP graph of one RK3 step of all
                                          instances (captured on first use, rebuilt after any
                                          geometry/tuning/diagnostics change); instances run as
                                          independent graph branches.  Ignored while diagnostics
                                          or profiling are on. */
-       IBM_TUNE_GRAPH_BRANCHES = 4 }; /* capture streams for the graph (0 = up to 8) */
+       IBM_TUNE_GRAPH_BRANCHES = 4,   /* capture streams for the graph (0 = up to 8) */
+       IBM_TUNE_TILE_ORDER = 5 };
 int ibm_tune_set(ibm_handle h, int32_t param, int32_t value);
 int ibm_tune_get(ibm_handle h, int32_t param, int32_t* value);
 
@@ -186,7 +190,8 @@ int ibm_tune_get(ibm_handle h, int32_t param, int32_t* value);
  * warm-up step) from the current state for every candidate value with HIP events,
  * and keep the fastest.  The state (u, v, w, p, step count, time) is saved before
  * and restored after, so the trajectory is unchanged.  chosen (may be NULL)
- * receives the 3 selected values.  Synchronises the stream.  IBM_ERR_STATE
+ * receives the 4 selected values (momentum planes, z-FFT width, tridiagonal rows,
+ * tile order).  Synchronises the stream.  IBM_ERR_STATE
  * before ibm_set_geometry. */
 int ibm_autotune(ibm_handle h, int32_t steps_per_trial, int32_t* chosen);
 

@@ -26,8 +26,14 @@ struct Instance {
   FFTPlan px{}, pz{};
   // device allocations
   std::vector<DevBuf> bufs;
-  void *u = nullptr, *v = nullptr, *w = nullptr, *p = nullptr;
-  void *us = nullptr, *vs = nullptr, *ws = nullptr;
+  void *u = nullptr, *v = nullptr, *w = nullptr, *p = nullptr;   // state (materialised on request)
+  // Predictor triples and pressures, cycled per substep: between substeps the state is
+  // correct(S[cur], phi, P[cur]) with the last substep's Pi and c_k dt.
+  void* S[3][3] = {};
+  void* P[3] = {};
+  int cur = 0;
+  bool fresh = true;       // u, v, w, p hold the state as set (no step since ibm_set_state)
+  bool mat_valid = true;   // u, v, w, p hold the current state
   void *Hu = nullptr, *Hv = nullptr, *Hw = nullptr, *phi = nullptr, *spec = nullptr;
   uint8_t* tag = nullptr;
   double* qpart = nullptr;
@@ -199,7 +205,9 @@ int init_instance(ibm_ctx* c, Instance& I, const ibm_grid_desc& d) {
   if ((rc = make_plan(c, I, g.nz, &I.pz))) return rc;
   const size_t ts = (c->precision == IBM_FP64) ? sizeof(double) : sizeof(float);
   const size_t fb = (size_t)g.ncell * ts;
-  void** fields[] = {&I.u, &I.v, &I.w, &I.p, &I.us, &I.vs, &I.ws, &I.Hu, &I.Hv, &I.Hw, &I.phi};
+  void** fields[] = {&I.u, &I.v, &I.w, &I.p, &I.S[0][0], &I.S[0][1], &I.S[0][2], &I.S[1][0], &I.S[1][1],
+                     &I.S[1][2], &I.S[2][0], &I.S[2][1], &I.S[2][2], &I.P[0], &I.P[1], &I.P[2],
+                     &I.Hu, &I.Hv, &I.Hw, &I.phi};
   for (void** f : fields) {
     if ((rc = dalloc(c, I, f, fb))) return rc;
     HIPCHK(c, hipMemsetAsync(*f, 0, fb, c->stream));
@@ -241,11 +249,17 @@ int init_instance(ibm_ctx* c, Instance& I, const ibm_grid_desc& d) {
   return IBM_OK;
 }
 
+// Pointers of the current substep: the previous predictor / pressure are slot I.cur,
+// the ones being written slot nxt (= I.cur when nothing is written).
 template <typename T>
-Fields<T> fields_of(Instance& I) {
+Fields<T> fields_of(Instance& I, int nxt = -1) {
+  if (nxt < 0) nxt = I.cur;
   Fields<T> f;
   f.u = (T*)I.u; f.v = (T*)I.v; f.w = (T*)I.w; f.p = (T*)I.p;
-  f.us = (T*)I.us; f.vs = (T*)I.vs; f.ws = (T*)I.ws;
+  f.usp = (T*)I.S[I.cur][0]; f.vsp = (T*)I.S[I.cur][1]; f.wsp = (T*)I.S[I.cur][2];
+  f.pp = (T*)I.P[I.cur];
+  f.us = (T*)I.S[nxt][0]; f.vs = (T*)I.S[nxt][1]; f.ws = (T*)I.S[nxt][2];
+  f.pn = (T*)I.P[nxt];
   f.Hu = (T*)I.Hu; f.Hv = (T*)I.Hv; f.Hw = (T*)I.Hw;
   f.phi = (T*)I.phi;
   f.spec = (cplx<T>*)I.spec;
@@ -276,7 +290,6 @@ int poisson(ibm_ctx* c, Instance& I, Fields<T>& f, T* phi_out, hipStream_t st) {
 template <typename T>
 int run_steps(ibm_ctx* c, Instance& I, int nsteps, hipStream_t st, bool count = true) {
   const GridParams& g = I.g;
-  Fields<T> f = fields_of<T>(I);
   const double scale = g.dy * g.dz / g.nx;
   for (int s = 0; s < nsteps; ++s) {
     for (int k = 0; k < 3; ++k) {
@@ -288,7 +301,15 @@ int run_steps(ibm_ctx* c, Instance& I, int nsteps, hipStream_t st, bool count = 
       sc.use_hold = (k > 0);
       sc.write_h = (k < 2);
       int nq = 0;
-      RUNK(c, K_MOMENTUM, launch_momentum<T>(g, f, I.L, sc, I.tu, I.qpart, &nq, st));
+      const int nxt = (I.cur + 1) % 3;
+      Fields<T> fm = fields_of<T>(I, nxt);
+      // the previous substep (stage k-1, or stage 2 of the previous step) is projected here
+      RUNK(c, K_MOMENTUM, launch_momentum<T>(g, fm, I.L, sc, I.pi(), rk_c((k + 2) % 3) * g.dt, I.tu, I.qpart, &nq,
+                                             st));
+      I.cur = nxt;
+      I.fresh = false;
+      I.mat_valid = false;
+      Fields<T> f = fields_of<T>(I);
       RUNK(c, K_CFR_PI, launch_cfr_pi<T>(f, I.L, k, sc.ck_dt, I.qpart, nq, scale, I.d.forcing, I.d.q_target_or_pi,
                                          I.S3(), I.pi(), I.pi_hist(), st));
       RUNK(c, K_DIV_FFTX, launch_div_fftx<T>(g, f, I.L, k, I.px, I.rtw, sc.ck_dt, I.pi(), (const T*)nullptr, st));
@@ -300,7 +321,6 @@ int run_steps(ibm_ctx* c, Instance& I, int nsteps, hipStream_t st, bool count = 
         RUNK(c, K_DIAG, launch_reduce_final(I.red_part, np, 0, 3, I.diag_out(), st));
         I.diag_valid = true;
       }
-      RUNK(c, K_CORRECT, launch_correct<T>(g, f, I.L, k, sc.ck_dt, I.pi(), st));
     }
     if (!count) continue;
     I.step += 1;
@@ -316,6 +336,35 @@ int count_mask(ibm_ctx* c, Instance& I, uint8_t mask, int32_t* blk, int nblk, in
   HIPCHK(c, hipMemcpyAsync(&tot, I.itotal, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   *out = tot;
+  return IBM_OK;
+}
+
+// Writes the state (u, v, w, p) from the pending projection of the last substep.
+template <typename T>
+int materialize_t(ibm_ctx* c, Instance& I) {
+  if (I.fresh || I.mat_valid) return IBM_OK;
+  Fields<T> f = fields_of<T>(I);
+  f.us = f.usp; f.vs = f.vsp; f.ws = f.wsp;   // the predictor awaiting its projection
+  RUNK(c, K_CORRECT, launch_correct<T>(I.g, f, I.L, 2, rk_c(2) * I.g.dt, I.pi(), c->stream));
+  I.mat_valid = true;
+  return IBM_OK;
+}
+
+int materialize(ibm_ctx* c, Instance& I) {
+  return c->precision == IBM_FP64 ? materialize_t<double>(c, I) : materialize_t<float>(c, I);
+}
+
+// Makes the state in u, v, w, p the starting point of the next step: predictor and
+// pressure slot I.cur take copies, phi and Pi are zero (nothing pending).
+int seed_pending(ibm_ctx* c, Instance& I) {
+  const size_t fb = (size_t)I.g.ncell * (c->precision == IBM_FP64 ? 8 : 4);
+  const void* src[4] = {I.u, I.v, I.w, I.p};
+  void* dst[4] = {I.S[I.cur][0], I.S[I.cur][1], I.S[I.cur][2], I.P[I.cur]};
+  for (int q = 0; q < 4; ++q) HIPCHK(c, hipMemcpyAsync(dst[q], src[q], fb, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipMemsetAsync(I.phi, 0, fb, c->stream));
+  HIPCHK(c, hipMemsetAsync(I.pi(), 0, sizeof(double), c->stream));
+  I.fresh = true;
+  I.mat_valid = true;
   return IBM_OK;
 }
 
@@ -520,7 +569,10 @@ int ibm_set_geometry(ibm_handle h, int32_t inst, const double* sdf_u, const doub
   if (rc) return rc;
   if (!sdf_u || !sdf_v || !sdf_w) return fail(h, IBM_ERR_ARG, "null SDF pointer");
   drop_graph(h);
-  return set_geometry_impl(h, h->inst[inst], sdf_u, sdf_v, sdf_w);
+  Instance& I = h->inst[inst];
+  if ((rc = materialize(h, I))) return rc;   // a pending projection belongs to the old geometry
+  if ((rc = set_geometry_impl(h, I, sdf_u, sdf_v, sdf_w))) return rc;
+  return seed_pending(h, I);
 }
 
 int ibm_set_state(ibm_handle h, int32_t inst, const void* u, const void* v, const void* w, const void* p) {
@@ -530,12 +582,11 @@ int ibm_set_state(ibm_handle h, int32_t inst, const void* u, const void* v, cons
   const size_t fb = (size_t)I.g.ncell * (h->precision == IBM_FP64 ? 8 : 4);
   const void* src[4] = {u, v, w, p};
   void* dst[4] = {I.u, I.v, I.w, I.p};
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < 4; ++q)
     if (!src[q]) return fail(h, IBM_ERR_ARG, "null state pointer");
-    HIPCHK(h, hipMemcpyAsync(dst[q], src[q], fb, hipMemcpyDeviceToDevice, h->stream));
-  }
+  for (int q = 0; q < 4; ++q) HIPCHK(h, hipMemcpyAsync(dst[q], src[q], fb, hipMemcpyDeviceToDevice, h->stream));
   I.diag_valid = false;
-  return IBM_OK;
+  return seed_pending(h, I);
 }
 
 int ibm_get_state(ibm_handle h, int32_t inst, void* u, void* v, void* w, void* p) {
@@ -543,6 +594,7 @@ int ibm_get_state(ibm_handle h, int32_t inst, void* u, void* v, void* w, void* p
   if (rc) return rc;
   Instance& I = h->inst[inst];
   const size_t fb = (size_t)I.g.ncell * (h->precision == IBM_FP64 ? 8 : 4);
+  if ((rc = materialize(h, I))) return rc;
   void* dst[4] = {u, v, w, p};
   const void* src[4] = {I.u, I.v, I.w, I.p};
   for (int q = 0; q < 4; ++q) {
@@ -566,6 +618,8 @@ int ibm_step(ibm_handle h, int32_t nsteps) {
     for (Instance& I : h->inst) {
       I.step += nsteps;
       I.time += nsteps * I.g.dt;
+      I.fresh = false;
+      I.mat_valid = false;
     }
     return IBM_OK;
   }
@@ -607,6 +661,7 @@ int ibm_stats(ibm_handle h, int32_t inst, ibm_stats_t* out) {
   if (!out) return fail(h, IBM_ERR_ARG, "null output");
   Instance& I = h->inst[inst];
   const GridParams& g = I.g;
+  if ((rc = materialize(h, I))) return rc;
   int np = 0;
   if (h->precision == IBM_FP64) {
     RUNK(h, K_STATS, launch_stats<double>(g, fields_of<double>(I), I.red_part, &np, h->stream));
@@ -696,6 +751,10 @@ int ibm_tune_set(ibm_handle h, int32_t param, int32_t value) {
   for (Instance& I : h->inst) {
     switch (param) {
       case IBM_TUNE_MOMENTUM_PLANES: I.tu.mom_jc = value; break;
+      case IBM_TUNE_TILE_ORDER:
+        if (value > 2) return fail(h, IBM_ERR_ARG, "tile order must be 0, 1 or 2");
+        I.tu.tile_order = value;
+        break;
       case IBM_TUNE_FFTZ_WIDTH: I.tu.fftz_w = value; break;
       case IBM_TUNE_TRI_ROWS:
         if (value != 0 && value != 4 && value != 8) return fail(h, IBM_ERR_ARG, "tri rows must be 0, 4 or 8");
@@ -712,6 +771,7 @@ int ibm_tune_get(ibm_handle h, int32_t param, int32_t* value) {
   const Tuning& t = h->inst[0].tu;
   switch (param) {
     case IBM_TUNE_MOMENTUM_PLANES: *value = t.mom_jc; break;
+    case IBM_TUNE_TILE_ORDER: *value = t.tile_order; break;
     case IBM_TUNE_FFTZ_WIDTH: *value = t.fftz_w; break;
     case IBM_TUNE_TRI_ROWS: *value = t.tri_rows; break;
     case IBM_TUNE_GRAPH: *value = h->use_graph ? 1 : 0; break;
@@ -754,6 +814,7 @@ int autotune_impl(ibm_ctx* c, Instance& I, int steps, int32_t* chosen) {
     cleanup();
     return fail(c, IBM_ERR_DEVICE, "autotune events");
   }
+  if (!rc) rc = materialize(c, I);
   for (int q = 0; q < 4 && !rc; ++q)
     if (hipMemcpyAsync(save[q], fld[q], fb, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
       rc = fail(c, IBM_ERR_DEVICE, "autotune save");
@@ -762,7 +823,9 @@ int autotune_impl(ibm_ctx* c, Instance& I, int steps, int32_t* chosen) {
     for (int q = 0; q < 4; ++q)
       if (hipMemcpyAsync(fld[q], save[q], fb, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
         return fail(c, IBM_ERR_DEVICE, "autotune restore");
-    int r = run_steps<T>(c, I, 1, c->stream);
+    int r = seed_pending(c, I);
+    if (r) return r;
+    r = run_steps<T>(c, I, 1, c->stream);
     if (r) return r;
     if (hipEventRecord(e0, c->stream) != hipSuccess) return fail(c, IBM_ERR_DEVICE, "event");
     r = run_steps<T>(c, I, steps, c->stream);
@@ -773,14 +836,19 @@ int autotune_impl(ibm_ctx* c, Instance& I, int steps, int32_t* chosen) {
     return IBM_OK;
   };
   // candidates per knob, searched one knob at a time
-  std::vector<int> jc = {0, 2, 4, 6, 8, 12, 16, 24, 32, 48, 64};
+  std::vector<int> to = {1, 2};
+  std::vector<int> jc = {0, 2, 4, 6, 8, 10, 12, 14, 16, 20, 24, 32, 48, 64};
   int wv[8];
   const int nw = fftz_widths<T>(g, I.pz, wv, 8);
   std::vector<int> fw(wv, wv + nw);
   std::vector<int> tr = {8, 4};
-  std::vector<int>* cand[3] = {&jc, &fw, &tr};
-  int* knob[3] = {&I.tu.mom_jc, &I.tu.fftz_w, &I.tu.tri_rows};
-  for (int kq = 0; kq < 3 && !rc; ++kq) {
+  std::vector<int>* cand[4] = {&jc, &fw, &tr, &to};
+  int* knob[4] = {&I.tu.mom_jc, &I.tu.fftz_w, &I.tu.tri_rows, &I.tu.tile_order};
+  // the tile order first (with the default plane chunk), then the others, then the tile
+  // order again with the chosen plane chunk
+  const int order[5] = {3, 0, 1, 2, 3};
+  for (int oq = 0; oq < 5 && !rc; ++oq) {
+    const int kq = order[oq];
     float best = 1e30f;
     int bestv = *knob[kq];
     for (int v : *cand[kq]) {
@@ -800,6 +868,7 @@ int autotune_impl(ibm_ctx* c, Instance& I, int steps, int32_t* chosen) {
   for (int q = 0; q < 4 && !rc; ++q)
     if (hipMemcpyAsync(fld[q], save[q], fb, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
       rc = fail(c, IBM_ERR_DEVICE, "autotune restore");
+  if (!rc) rc = seed_pending(c, I);
   if (!rc && hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(c, IBM_ERR_DEVICE, "autotune sync");
   I.step = step0;
   I.time = time0;

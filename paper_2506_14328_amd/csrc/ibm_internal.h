@@ -139,8 +139,11 @@ __device__ __forceinline__ int lanes_below(uint64_t mask, int lane) {
 
 template <typename T>
 struct Fields {
-  T *u, *v, *w, *p;          // state
-  T *us, *vs, *ws;           // predictor (u*)
+  T *u, *v, *w, *p;          // state, materialised on request
+  T *us, *vs, *ws;           // predictor (u*) of the current substep
+  T *usp, *vsp, *wsp;        // predictor of the previous substep (its projection pending)
+  T *pp;                     // pressure before the pending increment phi
+  T *pn;                     // pressure after it (written by momentum)
   T *Hu, *Hv, *Hw;           // explicit right-hand side of the previous stage
   T* phi;                    // pressure increment
   cplx<T>* spec;             // spectral work array (ny1, nz, mh)
@@ -152,12 +155,15 @@ struct Tuning {
   int mom_jc = 0;     // y planes per momentum block
   int fftz_w = 0;     // x modes per z-FFT block
   int tri_rows = 0;   // rows per thread of the tridiagonal partition solver (4 or 8)
+  int tile_order = 0; // momentum tiles: 1 contiguous per XCD (default), 2 interleaved
 };
 
 // step kernels
+// pi_prev, ckdt_prev: Pi and c dt of the previous substep, whose projection is pending.
 template <typename T>
 hipError_t launch_momentum(const GridParams& g, const Fields<T>& f, const IbmLists& L, const StageConsts& s,
-                           const Tuning& tu, double* qpart, int* nqpart, hipStream_t st);
+                           const double* pi_prev, double ckdt_prev, const Tuning& tu, double* qpart, int* nqpart,
+                           hipStream_t st);
 template <typename T>
 hipError_t launch_cfr_pi(const Fields<T>& f, const IbmLists& L, int stage, double ck_dt, const double* qpart, int nq,
                          double scale, int forcing, double q_target_or_pi, const double* S3, double* pi_out,

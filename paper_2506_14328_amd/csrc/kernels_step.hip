@@ -23,32 +23,65 @@ __device__ __forceinline__ int wrap_m(int i, int n) { return (i == 0) ? n - 1 : 
 // Eq. (16) (B = A = 1 away from the wall: u* = u + r).  Per-block partial sums of u*
 // over internal u points feed the flow-rate reduction.
 //
+// The projection of the previous substep is folded in: the state it would have written,
+//   u = u*' - Pi' c' dt (non-IBM internal u) - c' dt G phi  on internal faces, 0 elsewhere,
+//   p = p' + phi  on internal cells, 0 elsewhere,
+// is formed here from the previous predictor u*', the increment phi and the previous
+// pressure p' as the planes are loaded (c' = c_{k-1}, Pi' = Pi_{k-1}); p is also written
+// out (f.pn) for the next substep.
+//
 // A block owns a 64 x 4 (x, z) column of cells and marches through a chunk of y
-// planes.  u, v, w live in a ring of three LDS planes (j-1, j, j+1) with a one-cell
-// halo in x and z; p in one LDS plane.  The loads of plane j+2 are issued before the
-// arithmetic of plane j and written to the ring slot of plane j-1 afterwards.
-// Planes outside the box (ghost rows, the north wall face of v) are zero.
+// planes.  u, v, w, p live in a ring of three LDS planes (j-1, j, j+1) with a one-cell
+// halo in x and z.  The loads of plane j+2 are issued before the arithmetic of plane j
+// and their corrected values written to the ring slot of plane j-1 afterwards.  Planes
+// outside the box (ghost rows, the north wall face of v) are zero.
 // ---------------------------------------------------------------------------------------
 constexpr int MX = 64, MZ = 4;
 constexpr int MHX = MX + 2, MHZ = MZ + 2, MTILE = MHX * MHZ;   // 396 values per plane tile
 constexpr int MLOADS = (MTILE + 255) / 256;                     // tile values per thread
 
+// Loaded inputs of one tile value: previous predictor, previous pressure, phi and its
+// west, back and south neighbours, tag.
+template <typename T>
+struct TileRaw {
+  T us, vs, ws, pp, ph, phx, phz, phy;
+  uint8_t tg;
+};
+
+// The 1-D grid's blocks are dealt round-robin to the 8 XCDs (block b to XCD b mod 8, each
+// with its own L2).  Tiles are numbered x fastest, then z, then y chunk.  With xcd_order
+// block b takes tile (b mod 8) * (share of one XCD) + b / 8, so that each XCD works
+// through a contiguous run of tiles and neighbouring tiles, which load each other's
+// halos, share an L2; without it block b takes tile b (the XCDs interleave, which keeps
+// concurrent HBM accesses close together).
+constexpr int NXCD = 8;
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_momentum(GridParams g, Fields<T> f, IbmLists L, StageConsts s, int jc,
-                                                 double* __restrict__ qpart) {
-  __shared__ T ring[3][3][MTILE];   // [field u,v,w][slot][tile]
-  __shared__ T ptile[MTILE];
+                                                 int ntx, int ntz, int xcd_order, const double* __restrict__ pi_prev,
+                                                 double ckdt_prev, double* __restrict__ qpart) {
+  __shared__ T ring[4][3][MTILE];   // [field u,v,w,p][slot][tile]
   __shared__ double red[4];
   const int tx = threadIdx.x, tz = threadIdx.y, tid = tz * MX + tx;
   const int nx = g.nx, nz = g.nz, ny1 = g.ny1, plane = nx * nz;
-  const int i0 = blockIdx.x * MX, k0 = blockIdx.y * MZ;
-  const int j0 = blockIdx.z * jc;
+  int bx, bz, by;
+  {
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int xcd = b % NXCD, q = nb / NXCD, rem = nb % NXCD;
+    const int t = xcd_order ? xcd * q + min(xcd, rem) + b / NXCD : b;
+    bx = t % ntx;
+    bz = (t / ntx) % ntz;
+    by = t / (ntx * ntz);
+  }
+  const int i0 = bx * MX, k0 = bz * MZ;
+  const int j0 = by * jc;
   const int j1 = min(j0 + jc, ny1);
   const int i = i0 + tx, k = k0 + tz;
   const bool act = (i < nx) && (k < nz);
-  // tile element -> offset inside a plane (periodic wrap in x and z)
+  // tile element -> offsets inside a plane (periodic wrap in x and z) of itself and of
+  // its west (x-1) and back (z-1) neighbours
   int off[MLOADS];
-  bool has[MLOADS];
+  bool has[MLOADS], wx0[MLOADS], wz0[MLOADS];   // tile value exists; its x (z) index is 0
 #pragma unroll
   for (int r = 0; r < MLOADS; ++r) {
     const int e = tid + 256 * r;
@@ -59,53 +92,66 @@ __global__ __launch_bounds__(256) void k_momentum(GridParams g, Fields<T> f, Ibm
     int gx = (i0 - 1 + lx) % nx;
     if (gx < 0) gx += nx;
     off[r] = gz * nx + gx;
+    wx0[r] = gx == 0;
+    wz0[r] = gz == 0;
   }
-  auto fetch = [&](const T* __restrict__ a, int jj, T* reg) {
+  const T pick = T(pi_prev[0] * ckdt_prev), ckp = T(ckdt_prev);
+  const T idx = T(g.idx), idy = T(g.idy), idz = T(g.idz);
+  auto fetch = [&](int jj, TileRaw<T>* q) {
 #pragma unroll
-    for (int r = 0; r < MLOADS; ++r)
-      reg[r] = (has[r] && jj >= 0 && jj < ny1) ? a[jj * plane + off[r]] : T(0);
+    for (int r = 0; r < MLOADS; ++r) {
+      q[r] = TileRaw<T>{T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0), 0};
+      if (has[r] && jj >= 0 && jj < ny1) {
+        const int b = jj * plane;
+        q[r].us = f.usp[b + off[r]];
+        q[r].vs = f.vsp[b + off[r]];
+        q[r].ws = f.wsp[b + off[r]];
+        q[r].pp = f.pp[b + off[r]];
+        q[r].ph = f.phi[b + off[r]];
+        q[r].phx = f.phi[b + off[r] + (wx0[r] ? nx - 1 : -1)];
+        q[r].phz = f.phi[b + off[r] + (wz0[r] ? plane - nx : -nx)];
+        q[r].phy = jj > 0 ? f.phi[b - plane + off[r]] : T(0);
+        q[r].tg = f.tag[b + off[r]];
+      }
+    }
   };
-  auto put = [&](T* dst, const T* reg) {
+  // corrected state of the fetched values into ring slot sl
+  auto put = [&](int sl, const TileRaw<T>* q) {
 #pragma unroll
     for (int r = 0; r < MLOADS; ++r)
-      if (has[r]) dst[tid + 256 * r] = reg[r];
+      if (has[r]) {
+        const TileRaw<T>& a = q[r];
+        const int e = tid + 256 * r;
+        const T pk = ((a.tg & (TAG_U | TAG_UI)) == TAG_U) ? pick : T(0);
+        ring[0][sl][e] = (a.tg & TAG_U) ? a.us - pk - ckp * ((a.ph - a.phx) * idx) : T(0);
+        ring[1][sl][e] = (a.tg & TAG_V) ? a.vs - ckp * ((a.ph - a.phy) * idy) : T(0);
+        ring[2][sl][e] = (a.tg & TAG_W) ? a.ws - ckp * ((a.ph - a.phz) * idz) : T(0);
+        ring[3][sl][e] = (a.tg & TAG_P) ? a.pp + a.ph : T(0);
+      }
   };
   auto slot = [](int jj) { return (jj + 3) % 3; };
-  // prologue: planes j0-1, j0, j0+1 of u, v, w and plane j0 of p
+  // prologue: planes j0-1, j0, j0+1
   {
-    T ru[3][MLOADS], rv[3][MLOADS], rw[3][MLOADS], rp[MLOADS];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      fetch(f.u, j0 - 1 + q, ru[q]);
-      fetch(f.v, j0 - 1 + q, rv[q]);
-      fetch(f.w, j0 - 1 + q, rw[q]);
-    }
-    fetch(f.p, j0, rp);
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      put(ring[0][slot(j0 - 1 + q)], ru[q]);
-      put(ring[1][slot(j0 - 1 + q)], rv[q]);
-      put(ring[2][slot(j0 - 1 + q)], rw[q]);
-    }
-    put(ptile, rp);
+    TileRaw<T> q0[MLOADS], q1[MLOADS], q2[MLOADS];
+    fetch(j0 - 1, q0);
+    fetch(j0, q1);
+    fetch(j0 + 1, q2);
+    put(slot(j0 - 1), q0);
+    put(slot(j0), q1);
+    put(slot(j0 + 1), q2);
   }
   const int cc = (tz + 1) * MHX + (tx + 1);   // centre inside a tile
-  T p_prev = (act && j0 > 0) ? f.p[(j0 - 1) * plane + k * nx + i] : T(0);
   __syncthreads();
 
   const T h = T(0.5), two = T(2), zero = T(0);
-  const T idx = T(g.idx), idy = T(g.idy), idz = T(g.idz);
   const T idx2 = T(g.idx2), idy2 = T(g.idy2), idz2 = T(g.idz2), nu = T(g.nu);
   const T akdt = T(s.ak_dt), bkdt = T(s.bk_dt), ckdt = T(s.ck_dt);
   double qloc = 0.0;
 
   for (int j = j0; j < j1; ++j) {
-    // prefetch plane j+2 of u, v, w and plane j+1 of p
-    T nu_[MLOADS], nv_[MLOADS], nw_[MLOADS], np_[MLOADS];
-    fetch(f.u, j + 2, nu_);
-    fetch(f.v, j + 2, nv_);
-    fetch(f.w, j + 2, nw_);
-    fetch(f.p, j + 1 < j1 ? j + 1 : -1, np_);
+    // prefetch plane j+2
+    TileRaw<T> nq[MLOADS];
+    fetch(j + 2, nq);
     const int c = j * plane + k * nx + i;
     const uint8_t tg = act ? f.tag[c] : 0;
     T hu = zero, hv = zero, hw = zero;
@@ -125,13 +171,16 @@ __global__ __launch_bounds__(256) void k_momentum(GridParams g, Fields<T> f, Ibm
     const T* W0 = ring[2][slot(j)];
     const T* Wm = ring[2][slot(j - 1)];
     const T* Wp = ring[2][slot(j + 1)];
+    const T* P0 = ring[3][slot(j)];
+    const T* Pm = ring[3][slot(j - 1)];
     const T uc = U0[cc], ue = U0[cc + 1], uw = U0[cc - 1], ut = U0[cc + MHX], ub = U0[cc - MHX];
     const T un = Up[cc], usb = Um[cc], u_ip_s = Um[cc + 1], u_ip_km = U0[cc - MHX + 1];
     const T vc = V0[cc], ve = V0[cc + 1], vw = V0[cc - 1], vt = V0[cc + MHX], vb = V0[cc - MHX];
     const T vn = Vp[cc], vs0 = Vm[cc], v_im_n = Vp[cc - 1], v_km_n = Vp[cc - MHX];
     const T wc = W0[cc], we = W0[cc + 1], ww = W0[cc - 1], wt = W0[cc + MHX], wb = W0[cc - MHX];
     const T wn = Wp[cc], wsb = Wm[cc], w_kp_im = W0[cc + MHX - 1], w_kp_s = Wm[cc + MHX];
-    const T pc = ptile[cc], pw = ptile[cc - 1], pb = ptile[cc - MHX], ps = p_prev;
+    const T pc = P0[cc], pw = P0[cc - 1], pb = P0[cc - MHX], ps = Pm[cc];
+
 
     // u-momentum at (i dx, y_c[j], z_c[k])
     T Hu, ru;
@@ -170,7 +219,7 @@ __global__ __launch_bounds__(256) void k_momentum(GridParams g, Fields<T> f, Ibm
       if (s.use_hold) rw += bkdt * hw;
     }
     // immersed-boundary points: list index = chunk offset + flagged lanes below (the
-    // wavefront is the 64-wide chunk blockIdx.x of row j*nz + k)
+    // wavefront is the 64-wide chunk bx of row j*nz + k)
     const uint64_t mu = __ballot((tg & TAG_UI) != 0);
     const uint64_t mv = __ballot((tg & TAG_VI) != 0);
     const uint64_t mw = __ballot((tg & TAG_WI) != 0);
@@ -185,7 +234,7 @@ __global__ __launch_bounds__(256) void k_momentum(GridParams g, Fields<T> f, Ibm
       if (tg & TAG_V) sv = vc + rv;
       if (tg & TAG_W) sw = wc + rw;
       if (tg & (TAG_UI | TAG_VI | TAG_WI)) {
-        const int ch = (j * nz + k) * L.cpr + blockIdx.x;
+        const int ch = (j * nz + k) * L.cpr + bx;
         const size_t cb = (size_t)s.stage * L.n_total;
         if (tg & TAG_UI) {
           const double2 cf = L.coef[cb + L.choff_u[ch] + lanes_below(mu, tx)];
@@ -203,18 +252,15 @@ __global__ __launch_bounds__(256) void k_momentum(GridParams g, Fields<T> f, Ibm
       f.us[c] = su;
       f.vs[c] = sv;
       f.ws[c] = sw;
+      f.pn[c] = pc;
       if (tg & TAG_U) qloc += (double)su;
     }
-    p_prev = pc;
     __syncthreads();
-    put(ring[0][slot(j + 2)], nu_);
-    put(ring[1][slot(j + 2)], nv_);
-    put(ring[2][slot(j + 2)], nw_);
-    put(ptile, np_);
+    put(slot(j + 2), nq);
     __syncthreads();
   }
   const double tot = block_reduce<false>(qloc, red);
-  if (tid == 0) qpart[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = tot;
+  if (tid == 0) qpart[blockIdx.x] = tot;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -632,8 +678,11 @@ __global__ __launch_bounds__(256) void k_ifftx(GridParams g, const cplx<T>* __re
 }
 
 // ---------------------------------------------------------------------------------------
-// correct: u = u* - c_k dt G phi on internal faces (the pending -Pi c_k dt included),
-// zero on external faces (Sec. 3.3); p += phi on internal pressure cells only.
+// correct: the state after a projection, written to f.u, f.v, f.w, f.p:
+// u = u* - c_k dt G phi on internal faces (the pending -Pi c_k dt included), zero on
+// external faces (Sec. 3.3); p = p' + phi on internal pressure cells only (p' = f.pp).
+// The step itself folds this into the next momentum; this kernel materialises the state
+// on request.
 // ---------------------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_correct(GridParams g, Fields<T> f, IbmLists L, int stage, double ck_dt,
@@ -650,7 +699,7 @@ __global__ __launch_bounds__(256) void k_correct(GridParams g, Fields<T> f, IbmL
   const int ds = (j > 0) ? nx * nz : 0;      // v on face 0 is never internal
   const uint8_t tg = f.tag[c];
   const T ph = f.phi[c], phw = f.phi[c - i + im], phs = f.phi[c - ds], phb = f.phi[c + (km - k) * nx];
-  const T usv = f.us[c], vsv = f.vs[c], wsv = f.ws[c], pv = f.p[c];
+  const T usv = f.us[c], vsv = f.vs[c], wsv = f.ws[c], pv = f.pp[c];
   const T ckdt = T(ck_dt);
   const T pick = ((tg & (TAG_U | TAG_UI)) == TAG_U) ? T(pi[0] * ck_dt) : T(0);
   const T un = usv - pick - ckdt * ((ph - phw) * T(g.idx));
@@ -689,11 +738,15 @@ static int momentum_chunk(const GridParams& g, const Tuning& tu) {
 
 template <typename T>
 hipError_t launch_momentum(const GridParams& g, const Fields<T>& f, const IbmLists& L, const StageConsts& s,
-                           const Tuning& tu, double* qpart, int* nqpart, hipStream_t st) {
+                           const double* pi_prev, double ckdt_prev, const Tuning& tu, double* qpart, int* nqpart,
+                           hipStream_t st) {
   const int jc = momentum_chunk(g, tu);
-  const dim3 grid((g.nx + MX - 1) / MX, (g.nz + MZ - 1) / MZ, (g.ny1 + jc - 1) / jc);
-  hipLaunchKernelGGL(k_momentum<T>, grid, dim3(MX, MZ), 0, st, g, f, L, s, jc, qpart);
-  *nqpart = grid.x * grid.y * grid.z;
+  const int ntx = (g.nx + MX - 1) / MX, ntz = (g.nz + MZ - 1) / MZ, nty = (g.ny1 + jc - 1) / jc;
+  const int nb = ntx * ntz * nty;
+  const int xo = tu.tile_order == 2 ? 0 : 1;
+  hipLaunchKernelGGL(k_momentum<T>, dim3(nb), dim3(MX, MZ), 0, st, g, f, L, s, jc, ntx, ntz, xo, pi_prev,
+                     ckdt_prev, qpart);
+  *nqpart = nb;
   return hipGetLastError();
 }
 
@@ -811,7 +864,8 @@ hipError_t launch_copy(const T* src, T* dst, int64_t n, hipStream_t st) {
 
 #define IBM_INST(T)                                                                                              \
   template hipError_t launch_momentum<T>(const GridParams&, const Fields<T>&, const IbmLists&,                  \
-                                         const StageConsts&, const Tuning&, double*, int*, hipStream_t);         \
+                                         const StageConsts&, const double*, double, const Tuning&, double*,      \
+                                         int*, hipStream_t);                                                     \
   template hipError_t launch_cfr_pi<T>(const Fields<T>&, const IbmLists&, int, double, const double*, int,      \
                                        double, int, double, const double*, double*, double*, hipStream_t);       \
   template hipError_t launch_div_fftx<T>(const GridParams&, const Fields<T>&, const IbmLists&, int,             \

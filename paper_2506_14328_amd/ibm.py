@@ -30,7 +30,8 @@ EXPORTED = [
     "ibm_profile", "ibm_profile_read", "ibm_kernel_name", "ibm_num_kernels", "ibm_device_bytes",
     "ibm_destroy", "ibm_last_error", "ibm_tune_set", "ibm_tune_get", "ibm_autotune",
 ]
-TUNE_PARAMS = {"momentum_planes": 0, "fftz_width": 1, "tri_rows": 2, "graph": 3, "graph_branches": 4}
+TUNE_PARAMS = {"momentum_planes": 0, "fftz_width": 1, "tri_rows": 2, "graph": 3, "graph_branches": 4,
+               "tile_order": 5}
 
 
 class IbmGridDesc(ctypes.Structure):
@@ -251,7 +252,8 @@ class IbmGrid:
         return {self.lib.ibm_kernel_name(k).decode(): (ms[k], cnt[k]) for k in range(nk) if cnt[k] > 0}
 
     def tune(self, **knobs):
-        """Set launch-shape knobs by name (momentum_planes, fftz_width, tri_rows); 0 = automatic."""
+        """Set launch-shape knobs by name (momentum_planes, fftz_width, tri_rows, tile_order,
+        graph, graph_branches); 0 = automatic."""
         for k, v in knobs.items():
             self._check(self.lib.ibm_tune_set(self._h, TUNE_PARAMS[k], int(v)))
 
@@ -265,9 +267,10 @@ class IbmGrid:
 
     def autotune(self, steps_per_trial: int = 2) -> Dict[str, int]:
         """Run the library's autotuner (state is saved and restored) and return the choice."""
-        ch = (c_int32 * 3)()
+        names = ["momentum_planes", "fftz_width", "tri_rows", "tile_order"]
+        ch = (c_int32 * len(names))()
         self._check(self.lib.ibm_autotune(self._h, int(steps_per_trial), ch))
-        return dict(zip(["momentum_planes", "fftz_width", "tri_rows"], list(ch)))
+        return dict(zip(names, list(ch)))
 
     def device_bytes(self) -> int:
         return int(self.lib.ibm_device_bytes(self._h))

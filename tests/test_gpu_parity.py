@@ -224,12 +224,13 @@ def test_autotune_keeps_trajectory():
     o, sdf, st = oracle_run(c, 3)
     g = gpu_grid(c, sdf, st)
     chosen = g.autotune(1)
-    assert set(chosen) == {"momentum_planes", "fftz_width", "tri_rows"}
+    assert set(chosen) == {"momentum_planes", "fftz_width", "tri_rows", "tile_order"}
     assert g.stats()["step"] == 0
     g.step(3)
     u, v, w, p = [t.cpu().numpy() for t in g.get_state()]
     assert rel_err(u, o.u) < 1e-12 and rel_err(v, o.v) < 1e-12 and rel_err(w, o.w) < 1e-12
-    for knobs in (dict(momentum_planes=3, fftz_width=2, tri_rows=4), dict(momentum_planes=64, tri_rows=8)):
+    for knobs in (dict(momentum_planes=3, fftz_width=2, tri_rows=4, tile_order=2),
+                  dict(momentum_planes=64, tri_rows=8, tile_order=1)):
         g2 = gpu_grid(c, sdf, st)
         g2.tune(**knobs)
         g2.step(3)
