@@ -51,18 +51,20 @@ def parse():
 # --------------------------------------------------------------------------------------
 def algorithmic_bytes(kernel, C, M, s, n_ibm, n_u):
     if kernel == "momentum":
-        # reads u, v, w, p, tag, H_prev (stages 2, 3); writes u*, H (stages 1, 2): avg 11 fields + tag;
+        # the previous substep's projection folded in: reads u*', v*', w*', p', phi, tag,
+        # H_prev (stages 2, 3); writes u*, v*, w*, p, H (stages 1, 2): avg 13 fields + tag;
         # (B, 1/A) of every immersed-boundary point
-        return C * (11 * s + 1) + n_ibm * 16
+        return C * (13 * s + 1) + n_ibm * 16
     if kernel == "div_fftx":
-        # reads u*, v*, w*, tag, 1/A of the IBM u faces; writes the x-spectrum
-        return C * (3 * s + 1) + n_u * 16 + M * 2 * s
+        # reads u*, v*, w*, tag; writes the x-spectrum
+        return C * (3 * s + 1) + M * 2 * s
     if kernel in ("fftz_fwd", "fftz_inv", "tri"):
         return M * 4 * s
     if kernel == "ifftx":
         return M * 2 * s + C * s
     if kernel == "correct":
-        return C * (9 * s + 1) + n_u * 16
+        # materialising the state on request (not part of a step)
+        return C * (9 * s + 1)
     if kernel == "cfr_pi":
         # index, 1/A and u* read-modify-write of each immersed-boundary u face (the flow-rate
         # partials are a few kB)
@@ -72,7 +74,7 @@ def algorithmic_bytes(kernel, C, M, s, n_ibm, n_u):
 
 def step_bytes(C, M, s, n_ibm, n_u):
     per_sub = sum(algorithmic_bytes(k, C, M, s, n_ibm, n_u) for k in
-                  ("momentum", "cfr_pi", "div_fftx", "fftz_fwd", "tri", "fftz_inv", "ifftx", "correct"))
+                  ("momentum", "cfr_pi", "div_fftx", "fftz_fwd", "tri", "fftz_inv", "ifftx"))
     return 3 * per_sub
 
 

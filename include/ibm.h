@@ -187,8 +187,8 @@ int ibm_tune_set(ibm_handle h, int32_t param, int32_t value);
 int ibm_tune_get(ibm_handle h, int32_t param, int32_t* value);
 
 /* Autotuner: for each knob in turn, time steps_per_trial RK3 steps (after one
- * warm-up step) from the current state for every candidate value with HIP events,
- * and keep the fastest.  The state (u, v, w, p, step count, time) is saved before
+ * warm-up step, best of two runs) from the current state for every candidate value
+ * with HIP events, and keep the fastest.  The state (u, v, w, p, step count, time) is saved before
  * and restored after, so the trajectory is unchanged.  chosen (may be NULL)
  * receives the 4 selected values (momentum planes, z-FFT width, tridiagonal rows,
  * tile order).  Synchronises the stream.  IBM_ERR_STATE
