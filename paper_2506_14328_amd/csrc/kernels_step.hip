@@ -97,7 +97,11 @@ __global__ __launch_bounds__(256) void k_momentum(GridParams g, Fields<T> f, Ibm
   }
   const T pick = T(pi_prev[0] * ckdt_prev), ckp = T(ckdt_prev);
   const T idx = T(g.idx), idy = T(g.idy), idz = T(g.idz);
-  auto fetch = [&](int jj, TileRaw<T>* q) {
+  // phi of the plane below each of this thread's tile values (the v correction's
+  // south neighbour) is kept from the previous plane instead of being loaded again;
+  // only the first plane of the prologue loads it (with_phy).
+  T phprev[MLOADS];
+  auto fetch = [&](int jj, TileRaw<T>* q, bool with_phy) {
 #pragma unroll
     for (int r = 0; r < MLOADS; ++r) {
       q[r] = TileRaw<T>{T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0), 0};
@@ -110,35 +114,37 @@ __global__ __launch_bounds__(256) void k_momentum(GridParams g, Fields<T> f, Ibm
         q[r].ph = f.phi[b + off[r]];
         q[r].phx = f.phi[b + off[r] + (wx0[r] ? nx - 1 : -1)];
         q[r].phz = f.phi[b + off[r] + (wz0[r] ? plane - nx : -nx)];
-        q[r].phy = jj > 0 ? f.phi[b - plane + off[r]] : T(0);
+        if (with_phy) q[r].phy = jj > 0 ? f.phi[b - plane + off[r]] : T(0);
         q[r].tg = f.tag[b + off[r]];
       }
     }
   };
   // corrected state of the fetched values into ring slot sl
-  auto put = [&](int sl, const TileRaw<T>* q) {
+  auto put = [&](int sl, const TileRaw<T>* q, bool with_phy) {
 #pragma unroll
     for (int r = 0; r < MLOADS; ++r)
       if (has[r]) {
         const TileRaw<T>& a = q[r];
         const int e = tid + 256 * r;
+        const T phy = with_phy ? a.phy : phprev[r];
         const T pk = ((a.tg & (TAG_U | TAG_UI)) == TAG_U) ? pick : T(0);
         ring[0][sl][e] = (a.tg & TAG_U) ? a.us - pk - ckp * ((a.ph - a.phx) * idx) : T(0);
-        ring[1][sl][e] = (a.tg & TAG_V) ? a.vs - ckp * ((a.ph - a.phy) * idy) : T(0);
+        ring[1][sl][e] = (a.tg & TAG_V) ? a.vs - ckp * ((a.ph - phy) * idy) : T(0);
         ring[2][sl][e] = (a.tg & TAG_W) ? a.ws - ckp * ((a.ph - a.phz) * idz) : T(0);
         ring[3][sl][e] = (a.tg & TAG_P) ? a.pp + a.ph : T(0);
+        phprev[r] = a.ph;
       }
   };
   auto slot = [](int jj) { return (jj + 3) % 3; };
   // prologue: planes j0-1, j0, j0+1
   {
     TileRaw<T> q0[MLOADS], q1[MLOADS], q2[MLOADS];
-    fetch(j0 - 1, q0);
-    fetch(j0, q1);
-    fetch(j0 + 1, q2);
-    put(slot(j0 - 1), q0);
-    put(slot(j0), q1);
-    put(slot(j0 + 1), q2);
+    fetch(j0 - 1, q0, true);
+    fetch(j0, q1, false);
+    fetch(j0 + 1, q2, false);
+    put(slot(j0 - 1), q0, true);
+    put(slot(j0), q1, false);
+    put(slot(j0 + 1), q2, false);
   }
   const int cc = (tz + 1) * MHX + (tx + 1);   // centre inside a tile
   __syncthreads();
@@ -151,7 +157,7 @@ __global__ __launch_bounds__(256) void k_momentum(GridParams g, Fields<T> f, Ibm
   for (int j = j0; j < j1; ++j) {
     // prefetch plane j+2
     TileRaw<T> nq[MLOADS];
-    fetch(j + 2, nq);
+    fetch(j + 2, nq, false);
     const int c = j * plane + k * nx + i;
     const uint8_t tg = act ? f.tag[c] : 0;
     T hu = zero, hv = zero, hw = zero;
@@ -256,7 +262,7 @@ __global__ __launch_bounds__(256) void k_momentum(GridParams g, Fields<T> f, Ibm
       if (tg & TAG_U) qloc += (double)su;
     }
     __syncthreads();
-    put(slot(j + 2), nq);
+    put(slot(j + 2), nq, false);
     __syncthreads();
   }
   const double tot = block_reduce<false>(qloc, red);
