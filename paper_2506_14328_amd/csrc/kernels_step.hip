@@ -31,8 +31,8 @@ __device__ __forceinline__ int wrap_m(int i, int n) { return (i == 0) ? n - 1 : 
 // out (f.pn) for the next substep.
 //
 // A block owns a 64 x 4 (x, z) column of cells and marches through a chunk of y
-// planes.  u, v, w, p live in a ring of three LDS planes (j-1, j, j+1) with a one-cell
-// halo in x and z.  The loads of plane j+2 are issued before the arithmetic of plane j
+// planes.  u, v, w, p live in a ring of four LDS planes (j-1, j, j+1 and the one being
+// filled) with a one-cell halo in x and z.  The loads of plane j+2 are issued before the arithmetic of plane j
 // and their corrected values written to the ring slot of plane j-1 afterwards.  Planes
 // outside the box (ghost rows, the north wall face of v) are zero.
 // ---------------------------------------------------------------------------------------
@@ -60,7 +60,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_momentum(GridParams g, Fields<T> f, IbmLists L, StageConsts s, int jc,
                                                  int ntx, int ntz, int xcd_order, const double* __restrict__ pi_prev,
                                                  double ckdt_prev, double* __restrict__ qpart) {
-  __shared__ T ring[4][3][MTILE];   // [field u,v,w,p][slot][tile]
+  __shared__ T ring[4][4][MTILE];   // [field u,v,w,p][slot][tile]
   __shared__ double red[4];
   const int tx = threadIdx.x, tz = threadIdx.y, tid = tz * MX + tx;
   const int nx = g.nx, nz = g.nz, ny1 = g.ny1, plane = nx * nz;
@@ -135,7 +135,9 @@ __global__ __launch_bounds__(256) void k_momentum(GridParams g, Fields<T> f, Ibm
         phprev[r] = a.ph;
       }
   };
-  auto slot = [](int jj) { return (jj + 3) % 3; };
+  // four slots: plane j+2 goes to the slot of plane j-2, which no wave reads any more
+  // once the barrier closing the previous plane has passed, so one barrier per plane
+  auto slot = [](int jj) { return (jj + 4) & 3; };
   // prologue: planes j0-1, j0, j0+1
   {
     TileRaw<T> q0[MLOADS], q1[MLOADS], q2[MLOADS];
@@ -261,7 +263,6 @@ __global__ __launch_bounds__(256) void k_momentum(GridParams g, Fields<T> f, Ibm
       f.pn[c] = pc;
       if (tg & TAG_U) qloc += (double)su;
     }
-    __syncthreads();
     put(slot(j + 2), nq, false);
     __syncthreads();
   }
