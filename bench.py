@@ -259,9 +259,40 @@ def cpu_baseline(name, target_s=12.0):
     o.step(n)
     el = time.perf_counter() - t
     C = c.nx * (c.ny - 1) * c.nz
+    import platform
+    import scipy
+    model = platform.processor() or "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": C * 3 * n / el, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"{n} RK3 steps ({3 * n} substeps) of the {c.name} workload after 1 warm-up step, "
-                      f"NumPy/SciPy FP64, single thread; {el:.1f} s"}
+                      f"NumPy {np.__version__} / SciPy {scipy.__version__} FP64, one thread (scipy.fft "
+                      f"workers=1), {model}, {os.cpu_count()} logical CPUs visible; {el:.1f} s"}
+
+
+def copy_bandwidth(gib=2.0, reps=10):
+    """Device-to-device copy rate (read + write bytes per second) of a plain torch copy."""
+    import torch
+    n = int(gib * (1 << 30) // 8)
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    e1.synchronize()
+    gbs = 2.0 * n * 8 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del x, y
+    torch.cuda.empty_cache()
+    return gbs
 
 
 def main():
@@ -302,6 +333,7 @@ def main():
             "kernel": r["kernel"], "kernel_avg_us": round(r["kernel_avg_us"], 2),
             "algorithmic_bytes_per_launch": int(r["kernel_bytes"]),
             "step_algorithmic_GBs": round(r["step_gbs"], 1)}
+    roof["measured_copy_GBs"] = round(copy_bandwidth(), 1)   # practical ceiling on this device
     out = {"metric": METRIC, "value": r["value"], "unit": "cell-updates/s", "n_gpus": 1, "steps": a.steps,
            "warmup": a.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64" if a.precision == "fp64" else "f32",
