@@ -386,7 +386,7 @@ __global__ __launch_bounds__(256) void k_div_fftx(GridParams g, Fields<T> f, Ibm
 // fftz: complex FFT along z of the half spectrum, W consecutive x modes per block.
 // ---------------------------------------------------------------------------------------
 template <typename T, int MB>
-__global__ __launch_bounds__(256) void k_fftz(GridParams g, cplx<T>* __restrict__ spec, FFTPlan pz, int sign,
+__global__ __launch_bounds__(512) void k_fftz(GridParams g, cplx<T>* __restrict__ spec, FFTPlan pz, int sign,
                                              int W) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem_raw);
@@ -781,16 +781,25 @@ hipError_t launch_div_fftx(const GridParams& g, const Fields<T>& f, const IbmLis
   return hipGetLastError();
 }
 
-// A z-FFT width W (x modes per block) is valid when the block's 256 threads give each
-// column enough lanes for the in-place stages (<= 4 butterflies per thread) and the
-// tile plus twiddles fit 64 KiB of LDS.
+// Threads of a z-FFT block of width W (x modes): 256, or 512 when 256 would leave
+// more than two butterflies per thread in the largest stage.
+static int fftz_threads(const FFTPlan& pz, int W) {
+  int nbmax = 1;
+  for (int s = 0; s < pz.nst; ++s) nbmax = nbmax > pz.n / pz.radix[s] ? nbmax : pz.n / pz.radix[s];
+  return (W <= 256 && (nbmax + 256 / W - 1) / (256 / W) > 2 && W <= 512) ? 512 : 256;
+}
+
+// A z-FFT width W is valid when the block's threads give each column enough lanes for the
+// in-place stages (<= 4 butterflies per thread) and the tile plus twiddles fit the
+// 160 KiB of LDS a gfx950 workgroup may hold.
 template <typename T>
 static bool fftz_width_ok(const GridParams& g, const FFTPlan& pz, int W) {
   if (W < 1 || W > 256 || 256 % W) return false;
+  const int nt = fftz_threads(pz, W);
   int nbmax = 1;
   for (int s = 0; s < pz.nst; ++s) nbmax = nbmax > pz.n / pz.radix[s] ? nbmax : pz.n / pz.radix[s];
-  if ((nbmax + 256 / W - 1) / (256 / W) > 4) return false;
-  return ((size_t)W + 1) * g.nz * sizeof(cplx<T>) <= 65536;
+  if ((nbmax + nt / W - 1) / (nt / W) > 4) return false;
+  return ((size_t)W + 1) * g.nz * sizeof(cplx<T>) <= 163840;
 }
 
 template <typename T>
@@ -814,12 +823,18 @@ template <typename T>
 hipError_t launch_fftz(const GridParams& g, cplx<T>* spec, const FFTPlan& pz, int sign, const Tuning& tu,
                        hipStream_t st) {
   const int W = fftz_width<T>(g, pz, tu);
+  const int nt = fftz_threads(pz, W);
   const size_t lds = ((size_t)W + 1) * g.nz * sizeof(cplx<T>);
-  const int mb = fft_max_bfly(pz, 256 / W);
+  const int mb = fft_max_bfly(pz, nt / W);
   const dim3 grid((g.mh + W - 1) / W, g.ny1);
-  if (mb == 1) hipLaunchKernelGGL((k_fftz<T, 1>), grid, dim3(256), lds, st, g, spec, pz, sign, W);
-  else if (mb == 2) hipLaunchKernelGGL((k_fftz<T, 2>), grid, dim3(256), lds, st, g, spec, pz, sign, W);
-  else hipLaunchKernelGGL((k_fftz<T, 4>), grid, dim3(256), lds, st, g, spec, pz, sign, W);
+  const void* kfn = mb == 1 ? (const void*)k_fftz<T, 1> : (mb == 2 ? (const void*)k_fftz<T, 2> : (const void*)k_fftz<T, 4>);
+  if (lds > 65536) {
+    const hipError_t e = hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  if (mb == 1) hipLaunchKernelGGL((k_fftz<T, 1>), grid, dim3(nt), lds, st, g, spec, pz, sign, W);
+  else if (mb == 2) hipLaunchKernelGGL((k_fftz<T, 2>), grid, dim3(nt), lds, st, g, spec, pz, sign, W);
+  else hipLaunchKernelGGL((k_fftz<T, 4>), grid, dim3(nt), lds, st, g, spec, pz, sign, W);
   return hipGetLastError();
 }
 
