@@ -205,7 +205,8 @@ def precision_errors(a64, a32):
 def measure_ensemble(n=96, steps=200, warmup=3, seed=5):
     """The ragged ensemble in FP32 storage: one HIP-graph launch per RK3 step of all
     instances (instances as parallel graph branches) vs the same kernels launched one
-    instance after another on one stream."""
+    instance after another on one stream, and vs a graph of batched launches (one launch
+    per kernel for all instances)."""
     import torch
     import ibm_inputs as I
     from ibm_inputs import torch_gen as TG
@@ -223,8 +224,8 @@ def measure_ensemble(n=96, steps=200, warmup=3, seed=5):
     torch.cuda.synchronize()
     cells = sum(c.nx * (c.ny - 1) * c.nz for c in cases)
     res = {}
-    for mode in ("sequential", "graph"):
-        g.tune(graph=1 if mode == "graph" else 0)
+    for mode in ("sequential", "graph", "batched"):
+        g.tune(graph=0 if mode == "sequential" else 1, batch=1 if mode == "batched" else 0)
         for i, st in enumerate(states):
             g.set_state(*st, inst=i)
         g.step(warmup)
@@ -238,7 +239,7 @@ def measure_ensemble(n=96, steps=200, warmup=3, seed=5):
     g.close()
     return {"workload": f"ensemble_{n}_wavy_ragged", "precision": "fp32", "instances": n, "cells": cells,
             "steps": steps, "value": res["graph"]["value"], "ms_per_step": res["graph"]["ms_per_step"],
-            "sequential_value": res["sequential"]["value"],
+            "sequential_value": res["sequential"]["value"], "batched_graph_value": res["batched"]["value"],
             "graph_speedup": res["graph"]["value"] / res["sequential"]["value"], "instances_with_nan": bad}
 
 

@@ -182,7 +182,11 @@ enum { IBM_TUNE_MOMENTUM_PLANES = 0, IBM_TUNE_FFTZ_WIDTH = 1, IBM_TUNE_TRI_ROWS 
                                          independent graph branches.  Ignored while diagnostics
                                          or profiling are on. */
        IBM_TUNE_GRAPH_BRANCHES = 4,   /* capture streams for the graph (0 = up to 8) */
-       IBM_TUNE_TILE_ORDER = 5 };
+       IBM_TUNE_TILE_ORDER = 5,
+       IBM_TUNE_BATCH = 6 };          /* 1: an ensemble is advanced with one launch per kernel for
+                                         all instances (each instance's blocks a contiguous range of
+                                         the grid), also inside the graph.  Ignored for a single
+                                         instance and while diagnostics or profiling are on. */
 int ibm_tune_set(ibm_handle h, int32_t param, int32_t value);
 int ibm_tune_get(ibm_handle h, int32_t param, int32_t* value);
 

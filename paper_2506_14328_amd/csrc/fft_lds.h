@@ -172,7 +172,7 @@ __device__ void fft_lds(cplx<T>* buf, int stride, const FFTPlan& p, const cplx<T
                         int nlanes) {
   int Ns = 1;
   for (int s = 0; s < p.nst; ++s) {
-    const int R = p.radix[s];
+    const int R = (int)((p.rcode >> (4 * s)) & 15u);
     switch (R) {
       case 8: fft_stage_r<T, 8, MB>(buf, p.n, Ns, stride, tw, sign, lane, nlanes); break;
       case 4: fft_stage_r<T, 4, MB>(buf, p.n, Ns, stride, tw, sign, lane, nlanes); break;

@@ -78,6 +78,7 @@ struct ibm_ctx {
   int64_t prof_n[K_NUM_KERNELS] = {};
   // graph execution: one RK3 step of every instance captured once, replayed per step
   bool use_graph = false;
+  bool use_batch = false;              // ensembles: one launch per kernel for all instances
   int n_branches = 0;                  // capture streams (instances spread round-robin)
   hipStream_t cap = nullptr;           // capture origin stream
   std::vector<hipStream_t> aux;
@@ -85,6 +86,22 @@ struct ibm_ctx {
   std::vector<hipEvent_t> ev_join;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
+  // batched launches of an ensemble: per-instance kernel arguments and block offsets,
+  // packed in one device buffer (valid for the instances' predictor slots cur0)
+  struct Batch {
+    bool valid = false;
+    std::vector<int> cur0;
+    void* dbuf = nullptr;
+    const void* mom[3] = {};
+    const void* cfr[3] = {};
+    const void* div[3] = {};
+    const void *fzf = nullptr, *fzi = nullptr, *tri = nullptr, *ifx = nullptr;
+    const int *bo_mom = nullptr, *bo_cfr = nullptr, *bo_div = nullptr, *bo_fz = nullptr, *bo_tri = nullptr,
+              *bo_ifx = nullptr;
+    int n_mom = 0, n_cfr = 0, n_div = 0, n_fz = 0, n_tri = 0, n_ifx = 0;
+    int mb_div = 1, mb_fz = 1, mb_ifx = 1, lm_tri = 4, th_fz = 256;
+    size_t lds_div = 0, lds_fz = 0, lds_tri = 0, lds_ifx = 0;
+  } batch;
 };
 
 namespace {
@@ -142,6 +159,9 @@ int make_plan(ibm_ctx* c, Instance& I, int n, FFTPlan* pl) {
   pl->n = n;
   if (!factor_235(n, pl->radix, &pl->nst))
     return fail(c, IBM_ERR_ARG, "FFT length " + std::to_string(n) + " has a prime factor outside {2,3,5}");
+  if (pl->nst > 16) return fail(c, IBM_ERR_ARG, "FFT length " + std::to_string(n) + " needs too many stages");
+  pl->rcode = 0;
+  for (int s = 0; s < pl->nst; ++s) pl->rcode |= (uint64_t)pl->radix[s] << (4 * s);
   std::vector<double2> t64(n);
   std::vector<float2> t32(n);
   for (int m = 0; m < n; ++m) {
@@ -265,6 +285,27 @@ Fields<T> fields_of(Instance& I, int nxt = -1) {
   f.spec = (cplx<T>*)I.spec;
   f.tag = I.tag;
   return f;
+}
+
+// Pointers for explicit predictor slots (previous = cur, written = nxt).
+template <typename T>
+Fields<T> fields_at(Instance& I, int cur, int nxt) {
+  const int save = I.cur;
+  I.cur = cur;
+  Fields<T> f = fields_of<T>(I, nxt);
+  I.cur = save;
+  return f;
+}
+
+StageConsts stage_consts(const GridParams& g, int k) {
+  StageConsts sc;
+  sc.ak_dt = rk_a(k) * g.dt;
+  sc.bk_dt = rk_b(k) * g.dt;
+  sc.ck_dt = rk_c(k) * g.dt;
+  sc.stage = k;
+  sc.use_hold = (k > 0);
+  sc.write_h = (k < 2);
+  return sc;
 }
 
 #define RUNK(ctx, kid, expr)                                                                     \
@@ -478,11 +519,166 @@ int check_inst(ibm_ctx* c, int32_t inst) {
   return IBM_OK;
 }
 
+void drop_batch(ibm_ctx* c) {
+  if (c->batch.dbuf) (void)hipFree(c->batch.dbuf);
+  c->batch = ibm_ctx::Batch{};
+}
+
 void drop_graph(ibm_ctx* c) {
+  drop_batch(c);
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
   c->gexec = nullptr;
   c->graph = nullptr;
+}
+
+// Per-instance arguments of every step kernel for the batched launches (each grid's own
+// launch shapes; the launch takes the largest template variant and LDS any grid needs).
+template <typename T>
+int build_batch(ibm_ctx* c) {
+  drop_batch(c);
+  ibm_ctx::Batch& b = c->batch;
+  const int n = (int)c->inst.size();
+  std::vector<MomArgs<T>> mom[3];
+  std::vector<CfrArgs<T>> cfr[3];
+  std::vector<DivArgs<T>> dv[3];
+  std::vector<FftzArgs<T>> fzf(n), fzi(n);
+  std::vector<TriArgs<T>> tri(n);
+  std::vector<IfftxArgs<T>> ifx(n);
+  for (int k = 0; k < 3; ++k) {
+    mom[k].resize(n);
+    cfr[k].resize(n);
+    dv[k].resize(n);
+  }
+  std::vector<int> bo[6];
+  for (auto& v : bo) v.assign(n + 1, 0);
+  b.cur0.resize(n);
+  for (int i = 0; i < n; ++i) {
+    Instance& I = c->inst[i];
+    const GridParams& g = I.g;
+    const double scale = g.dy * g.dz / g.nx;
+    b.cur0[i] = I.cur;
+    int nq = 0, mb = 1, th = 256, lm = 4;
+    size_t lds = 0;
+    for (int k = 0; k < 3; ++k) {
+      const int ck = (I.cur + k) % 3, nx = (ck + 1) % 3;
+      const StageConsts sc = stage_consts(g, k);
+      Fields<T> fm = fields_at<T>(I, ck, nx);
+      nq = plan_momentum<T>(g, fm, I.L, sc, I.pi(), rk_c((k + 2) % 3) * g.dt, I.tu, I.qpart, &mom[k][i]);
+      Fields<T> f = fields_at<T>(I, nx, nx);
+      const int nc = plan_cfr_pi<T>(f, I.L, k, sc.ck_dt, I.qpart, nq, scale, I.d.forcing, I.d.q_target_or_pi,
+                                    I.S3(), I.pi(), I.pi_hist(), &cfr[k][i]);
+      const int nd = plan_div_fftx<T>(g, f, I.L, k, I.px, I.rtw, sc.ck_dt, I.pi(), &dv[k][i], &mb, &lds);
+      b.mb_div = std::max(b.mb_div, mb);
+      b.lds_div = std::max(b.lds_div, lds);
+      if (k == 0) {
+        bo[0][i + 1] = nq;
+        bo[1][i + 1] = nc;
+        bo[2][i + 1] = nd;
+      }
+    }
+    Fields<T> f = fields_of<T>(I);
+    bo[3][i + 1] = plan_fftz<T>(g, f.spec, I.pz, -1, I.tu, &fzf[i], &mb, &lds, &th);
+    (void)plan_fftz<T>(g, f.spec, I.pz, +1, I.tu, &fzi[i], &mb, &lds, &th);
+    b.mb_fz = std::max(b.mb_fz, mb);
+    b.lds_fz = std::max(b.lds_fz, lds);
+    b.th_fz = std::max(b.th_fz, th);
+    bo[4][i + 1] = plan_tri<T>(g, f.spec, I.kx2, I.kz2, I.mean(), I.tu, &tri[i], &lm, &lds);
+    b.lm_tri = std::max(b.lm_tri, lm);
+    b.lds_tri = std::max(b.lds_tri, lds);
+    bo[5][i + 1] = plan_ifftx<T>(g, f.spec, f.phi, I.px, I.rtw, &ifx[i], &mb, &lds);
+    b.mb_ifx = std::max(b.mb_ifx, mb);
+    b.lds_ifx = std::max(b.lds_ifx, lds);
+  }
+  for (auto& v : bo)
+    for (int i = 0; i < n; ++i) v[i + 1] += v[i];
+  // pack everything into one host image (256-byte aligned pieces), then one device copy
+  std::vector<unsigned char> img;
+  auto put = [&](const void* src, size_t bytes) {
+    const size_t off = (img.size() + 255) & ~(size_t)255;
+    img.resize(off + bytes);
+    memcpy(img.data() + off, src, bytes);
+    return off;
+  };
+  size_t o_mom[3], o_cfr[3], o_div[3];
+  for (int k = 0; k < 3; ++k) {
+    o_mom[k] = put(mom[k].data(), n * sizeof(MomArgs<T>));
+    o_cfr[k] = put(cfr[k].data(), n * sizeof(CfrArgs<T>));
+    o_div[k] = put(dv[k].data(), n * sizeof(DivArgs<T>));
+  }
+  const size_t o_fzf = put(fzf.data(), n * sizeof(FftzArgs<T>)), o_fzi = put(fzi.data(), n * sizeof(FftzArgs<T>));
+  const size_t o_tri = put(tri.data(), n * sizeof(TriArgs<T>)), o_ifx = put(ifx.data(), n * sizeof(IfftxArgs<T>));
+  size_t o_bo[6];
+  for (int q = 0; q < 6; ++q) o_bo[q] = put(bo[q].data(), (n + 1) * sizeof(int));
+  if (hipMalloc(&b.dbuf, img.size()) != hipSuccess) {
+    b.dbuf = nullptr;
+    return fail(c, IBM_ERR_OOM, "batched launch arguments");
+  }
+  HIPCHK(c, hipMemcpy(b.dbuf, img.data(), img.size(), hipMemcpyHostToDevice));
+  unsigned char* d = (unsigned char*)b.dbuf;
+  for (int k = 0; k < 3; ++k) {
+    b.mom[k] = d + o_mom[k];
+    b.cfr[k] = d + o_cfr[k];
+    b.div[k] = d + o_div[k];
+  }
+  b.fzf = d + o_fzf;
+  b.fzi = d + o_fzi;
+  b.tri = d + o_tri;
+  b.ifx = d + o_ifx;
+  b.bo_mom = (const int*)(d + o_bo[0]);
+  b.bo_cfr = (const int*)(d + o_bo[1]);
+  b.bo_div = (const int*)(d + o_bo[2]);
+  b.bo_fz = (const int*)(d + o_bo[3]);
+  b.bo_tri = (const int*)(d + o_bo[4]);
+  b.bo_ifx = (const int*)(d + o_bo[5]);
+  b.n_mom = bo[0][n];
+  b.n_cfr = bo[1][n];
+  b.n_div = bo[2][n];
+  b.n_fz = bo[3][n];
+  b.n_tri = bo[4][n];
+  b.n_ifx = bo[5][n];
+  b.valid = true;
+  return IBM_OK;
+}
+
+bool batch_current(ibm_ctx* c) {
+  if (!c->batch.valid) return false;
+  for (size_t i = 0; i < c->inst.size(); ++i)
+    if (c->batch.cur0[i] != c->inst[i].cur) return false;
+  return true;
+}
+
+// nsteps RK3 steps of every instance, one launch per kernel for the whole ensemble.
+template <typename T>
+int run_steps_batched(ibm_ctx* c, int nsteps, hipStream_t st, bool count = true) {
+  const ibm_ctx::Batch& b = c->batch;
+  const int n = (int)c->inst.size();
+  for (int s = 0; s < nsteps; ++s) {
+    for (int k = 0; k < 3; ++k) {
+      RUNK(c, K_MOMENTUM, launch_momentum_b<T>((const MomArgs<T>*)b.mom[k], b.bo_mom, n, b.n_mom, st));
+      for (Instance& I : c->inst) {
+        I.cur = (I.cur + 1) % 3;
+        I.fresh = false;
+        I.mat_valid = false;
+      }
+      RUNK(c, K_CFR_PI, launch_cfr_pi_b<T>((const CfrArgs<T>*)b.cfr[k], b.bo_cfr, n, b.n_cfr, st));
+      RUNK(c, K_DIV_FFTX, launch_div_fftx_b<T>((const DivArgs<T>*)b.div[k], b.bo_div, n, b.n_div, b.mb_div,
+                                               b.lds_div, st));
+      RUNK(c, K_FFTZ_FWD, launch_fftz_b<T>((const FftzArgs<T>*)b.fzf, b.bo_fz, n, b.n_fz, b.mb_fz, b.lds_fz,
+                                           b.th_fz, st));
+      RUNK(c, K_TRI, launch_tri_b<T>((const TriArgs<T>*)b.tri, b.bo_tri, n, b.n_tri, b.lm_tri, b.lds_tri, st));
+      RUNK(c, K_FFTZ_INV, launch_fftz_b<T>((const FftzArgs<T>*)b.fzi, b.bo_fz, n, b.n_fz, b.mb_fz, b.lds_fz,
+                                           b.th_fz, st));
+      RUNK(c, K_IFFTX, launch_ifftx_b<T>((const IfftxArgs<T>*)b.ifx, b.bo_ifx, n, b.n_ifx, b.mb_ifx, b.lds_ifx,
+                                         st));
+    }
+    if (!count) continue;
+    for (Instance& I : c->inst) {
+      I.step += 1;
+      I.time += I.g.dt;
+    }
+  }
+  return IBM_OK;
 }
 
 // Capture one RK3 step of every instance: instance i goes to capture stream i mod B,
@@ -491,6 +687,28 @@ void drop_graph(ibm_ctx* c) {
 template <typename T>
 int build_graph(ibm_ctx* c) {
   drop_graph(c);
+  if (c->use_batch && c->inst.size() > 1) {
+    // the batched launches on one stream: seven nodes per substep for the whole ensemble
+    int rc = build_batch<T>(c);
+    if (rc) return rc;
+    if (!c->cap) HIPCHK(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+    HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+    rc = run_steps_batched<T>(c, 1, c->cap, false);
+    hipGraph_t gr = nullptr;
+    const hipError_t ee = hipStreamEndCapture(c->cap, &gr);
+    if (!rc && ee != hipSuccess) rc = fail(c, IBM_ERR_DEVICE, std::string("end capture: ") + hipGetErrorString(ee));
+    if (rc) {
+      if (gr) (void)hipGraphDestroy(gr);
+      return rc;
+    }
+    c->graph = gr;
+    const hipError_t e = hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      drop_graph(c);
+      return fail(c, IBM_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+    return IBM_OK;
+  }
   const int B = std::max(1, std::min<int>(c->n_branches > 0 ? c->n_branches : 8, (int)c->inst.size()));
   if (!c->cap) HIPCHK(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
   if (!c->ev_fork) HIPCHK(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
@@ -609,8 +827,9 @@ int ibm_step(ibm_handle h, int32_t nsteps) {
   if (nsteps < 0) return fail(h, IBM_ERR_ARG, "nsteps < 0");
   for (Instance& I : h->inst)
     if (!I.geom_ready) return fail(h, IBM_ERR_STATE, "ibm_step before ibm_set_geometry");
+  const bool batched = h->use_batch && h->inst.size() > 1 && !h->diag && !h->prof;
   if (h->use_graph && !h->diag && !h->prof && nsteps > 0) {
-    if (!h->gexec) {
+    if (!h->gexec || (batched && !batch_current(h))) {
       const int rc = (h->precision == IBM_FP64) ? build_graph<double>(h) : build_graph<float>(h);
       if (rc) return rc;
     }
@@ -622,6 +841,14 @@ int ibm_step(ibm_handle h, int32_t nsteps) {
       I.mat_valid = false;
     }
     return IBM_OK;
+  }
+  if (batched && nsteps > 0) {
+    if (!batch_current(h)) {
+      const int rc = (h->precision == IBM_FP64) ? build_batch<double>(h) : build_batch<float>(h);
+      if (rc) return rc;
+    }
+    return (h->precision == IBM_FP64) ? run_steps_batched<double>(h, nsteps, h->stream)
+                                      : run_steps_batched<float>(h, nsteps, h->stream);
   }
   for (Instance& I : h->inst) {
     const int rc = (h->precision == IBM_FP64) ? run_steps<double>(h, I, nsteps, h->stream)
@@ -744,6 +971,10 @@ int ibm_tune_set(ibm_handle h, int32_t param, int32_t value) {
     h->use_graph = value != 0;
     return IBM_OK;
   }
+  if (param == IBM_TUNE_BATCH) {
+    h->use_batch = value != 0;
+    return IBM_OK;
+  }
   if (param == IBM_TUNE_GRAPH_BRANCHES) {
     h->n_branches = value;
     return IBM_OK;
@@ -776,6 +1007,7 @@ int ibm_tune_get(ibm_handle h, int32_t param, int32_t* value) {
     case IBM_TUNE_TRI_ROWS: *value = t.tri_rows; break;
     case IBM_TUNE_GRAPH: *value = h->use_graph ? 1 : 0; break;
     case IBM_TUNE_GRAPH_BRANCHES: *value = h->n_branches; break;
+    case IBM_TUNE_BATCH: *value = h->use_batch ? 1 : 0; break;
     default: return fail(h, IBM_ERR_ARG, "unknown tuning parameter");
   }
   return IBM_OK;

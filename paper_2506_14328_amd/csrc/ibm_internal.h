@@ -48,6 +48,7 @@ struct FFTPlan {
   int n;                // transform length
   int nst;              // number of radix stages
   int radix[20];        // radix of each stage (8, 4, 2, 3 or 5)
+  uint64_t rcode;       // the same, 4 bits per stage (stage s at bits 4s..4s+3), for device code
   const double2* tw64;  // exp(-2 pi i m / n), m = 0..n-1
   const float2* tw32;
 };
@@ -157,6 +158,124 @@ struct Tuning {
   int tri_rows = 0;   // rows per thread of the tridiagonal partition solver (4 or 8)
   int tile_order = 0; // momentum tiles: 1 contiguous per XCD (default), 2 interleaved
 };
+
+// Arguments of one grid's step kernels, for the batched launches that advance a whole
+// ensemble of independent grids with one launch per kernel (block ranges per grid).
+template <typename T>
+struct MomArgs {
+  GridParams g;
+  Fields<T> f;
+  IbmLists L;
+  StageConsts s;
+  int jc;
+  int ntx;
+  int ntz;
+  int xcd_order;
+  const double* pi_prev;
+  double ckdt_prev;
+  double* qpart;
+  int gx;   // blocks along x of the instance's grid
+};
+
+template <typename T>
+struct CfrArgs {
+  Fields<T> f;
+  IbmLists L;
+  int stage;
+  double ck_dt;
+  const double* qpart;
+  int nq;
+  double scale;
+  int forcing;
+  double qt;
+  const double* S3;
+  double* pi_out;
+  double* pi_hist;
+  int gx;   // blocks along x of the instance's grid
+};
+
+template <typename T>
+struct DivArgs {
+  GridParams g;
+  Fields<T> f;
+  IbmLists L;
+  int stage;
+  FFTPlan px;
+  const double2* rtw;
+  double ck_dt;
+  const double* pi;
+  const T* rhs_in;
+  int gx;   // blocks along x of the instance's grid
+};
+
+template <typename T>
+struct FftzArgs {
+  GridParams g;
+  cplx<T>* spec;
+  FFTPlan pz;
+  int sign;
+  int W;
+  int gx;   // blocks along x of the instance's grid
+};
+
+template <typename T>
+struct TriArgs {
+  GridParams g;
+  cplx<T>* spec;
+  const double* kx2;
+  const double* kz2;
+  int P;
+  int W;
+  double* mean_out;
+  int gx;   // blocks along x of the instance's grid
+};
+
+template <typename T>
+struct IfftxArgs {
+  GridParams g;
+  const cplx<T>* spec;
+  T* out;
+  FFTPlan px;
+  const double2* rtw;
+  int gx;   // blocks along x of the instance's grid
+};
+
+template <typename T>
+int plan_momentum(const GridParams& g, const Fields<T>& f, const IbmLists& L, const StageConsts& s,
+                  const double* pi_prev, double ckdt_prev, const Tuning& tu, double* qpart, MomArgs<T>* a);
+template <typename T>
+int plan_cfr_pi(const Fields<T>& f, const IbmLists& L, int stage, double ck_dt, const double* qpart, int nq,
+                double scale, int forcing, double q_target_or_pi, const double* S3, double* pi_out, double* pi_hist,
+                CfrArgs<T>* a);
+template <typename T>
+int plan_div_fftx(const GridParams& g, const Fields<T>& f, const IbmLists& L, int stage, const FFTPlan& px,
+                  const double2* rtw, double ck_dt, const double* pi, DivArgs<T>* a, int* mb, size_t* lds);
+template <typename T>
+int plan_fftz(const GridParams& g, cplx<T>* spec, const FFTPlan& pz, int sign, const Tuning& tu, FftzArgs<T>* a,
+              int* mb, size_t* lds, int* threads);
+template <typename T>
+int plan_tri(const GridParams& g, cplx<T>* spec, const double* kx2, const double* kz2, double* mean_out,
+             const Tuning& tu, TriArgs<T>* a, int* lm, size_t* lds);
+template <typename T>
+int plan_ifftx(const GridParams& g, const cplx<T>* spec, T* out, const FFTPlan& px, const double2* rtw,
+               IfftxArgs<T>* a, int* mb, size_t* lds);
+// Batched launches: args and boff (ninst + 1 block offsets) in device memory; ntot blocks.
+template <typename T>
+hipError_t launch_momentum_b(const MomArgs<T>* args, const int* boff, int ninst, int ntot, hipStream_t st);
+template <typename T>
+hipError_t launch_cfr_pi_b(const CfrArgs<T>* args, const int* boff, int ninst, int ntot, hipStream_t st);
+template <typename T>
+hipError_t launch_div_fftx_b(const DivArgs<T>* args, const int* boff, int ninst, int ntot, int mb, size_t lds,
+                             hipStream_t st);
+template <typename T>
+hipError_t launch_fftz_b(const FftzArgs<T>* args, const int* boff, int ninst, int ntot, int mb, size_t lds,
+                         int threads, hipStream_t st);
+template <typename T>
+hipError_t launch_tri_b(const TriArgs<T>* args, const int* boff, int ninst, int ntot, int lm, size_t lds,
+                        hipStream_t st);
+template <typename T>
+hipError_t launch_ifftx_b(const IfftxArgs<T>* args, const int* boff, int ninst, int ntot, int mb, size_t lds,
+                          hipStream_t st);
 
 // step kernels
 // pi_prev, ckdt_prev: Pi and c dt of the previous substep, whose projection is pending.

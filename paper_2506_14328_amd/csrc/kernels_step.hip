@@ -17,6 +17,17 @@ constexpr int BZ = 4;   // z rows per block
 __device__ __forceinline__ int wrap_p(int i, int n) { return (i + 1 == n) ? 0 : i + 1; }
 __device__ __forceinline__ int wrap_m(int i, int n) { return (i == 0) ? n - 1 : i - 1; }
 
+// Instance of block b in a batched launch: boff[i] <= b < boff[i+1] (boff[0] = 0).
+__device__ __forceinline__ int batch_instance(const int* __restrict__ boff, int ninst, int b) {
+  int lo = 0, hi = ninst - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (boff[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 // ---------------------------------------------------------------------------------------
 // momentum: H = -N(u) + nu L(u) at internal points (external/ghost neighbours are zero),
 // r = dt (a_k H + b_k H_prev) - c_k dt G p, and the predictor u* = (B u + r) / A of
@@ -57,16 +68,16 @@ struct TileRaw {
 constexpr int NXCD = 8;
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_momentum(GridParams g, Fields<T> f, IbmLists L, StageConsts s, int jc,
+__device__ __forceinline__ void k_momentum_body(GridParams g, Fields<T> f, IbmLists L, StageConsts s, int jc,
                                                  int ntx, int ntz, int xcd_order, const double* __restrict__ pi_prev,
-                                                 double ckdt_prev, double* __restrict__ qpart) {
+                                                 double ckdt_prev, double* __restrict__ qpart, int bid_x, int bid_y, int nblk) {
   __shared__ T ring[4][4][MTILE];   // [field u,v,w,p][slot][tile]
   __shared__ double red[4];
   const int tx = threadIdx.x, tz = threadIdx.y, tid = tz * MX + tx;
   const int nx = g.nx, nz = g.nz, ny1 = g.ny1, plane = nx * nz;
   int bx, bz, by;
   {
-    const int nb = gridDim.x, b = blockIdx.x;
+    const int nb = nblk, b = bid_x;
     const int xcd = b % NXCD, q = nb / NXCD, rem = nb % NXCD;
     const int t = xcd_order ? xcd * q + min(xcd, rem) + b / NXCD : b;
     bx = t % ntx;
@@ -267,7 +278,24 @@ __global__ __launch_bounds__(256) void k_momentum(GridParams g, Fields<T> f, Ibm
     __syncthreads();
   }
   const double tot = block_reduce<false>(qloc, red);
-  if (tid == 0) qpart[blockIdx.x] = tot;
+  if (tid == 0) qpart[bid_x] = tot;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_momentum(GridParams g, Fields<T> f, IbmLists L, StageConsts s, int jc,
+                                                 int ntx, int ntz, int xcd_order, const double* __restrict__ pi_prev,
+                                                 double ckdt_prev, double* __restrict__ qpart) {
+  k_momentum_body<T>(g, f, L, s, jc, ntx, ntz, xcd_order, pi_prev, ckdt_prev, qpart, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
+// The same for a batch of independent grids in one launch (block ranges boff).
+template <typename T>
+__global__ __launch_bounds__(256) void k_momentum_b(const MomArgs<T>* __restrict__ args,
+    const int* __restrict__ boff, int ninst) {
+  const int i = batch_instance(boff, ninst, blockIdx.x);
+  const MomArgs<T>& a = args[i];
+  const int local = blockIdx.x - boff[i];
+  k_momentum_body<T>(a.g, a.f, a.L, a.s, a.jc, a.ntx, a.ntz, a.xcd_order, a.pi_prev, a.ckdt_prev, a.qpart, local % a.gx, local / a.gx, boff[i + 1] - boff[i]);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -279,10 +307,10 @@ __global__ __launch_bounds__(256) void k_momentum(GridParams g, Fields<T> f, Ibm
 // the diagnostics apply -Pi_k c_k dt to the other internal u faces themselves.
 // ---------------------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_cfr_pi(Fields<T> f, IbmLists L, int stage, double ck_dt,
+__device__ __forceinline__ void k_cfr_pi_body(Fields<T> f, IbmLists L, int stage, double ck_dt,
                                                const double* __restrict__ qpart, int nq, double scale, int forcing,
                                                double qt, const double* __restrict__ S3,
-                                               double* __restrict__ pi_out, double* __restrict__ pi_hist) {
+                                               double* __restrict__ pi_out, double* __restrict__ pi_hist, int bid_x, int bid_y, int nblk) {
   __shared__ double red[4];
   __shared__ double pi_s;
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -300,19 +328,37 @@ __global__ __launch_bounds__(256) void k_cfr_pi(Fields<T> f, IbmLists L, int sta
     const double q0 = tot * scale;
     const double pi = (forcing == 0) ? (q0 - qt) / S3[stage] : qt;
     pi_s = pi;
-    if (blockIdx.x == 0) {
+    if (bid_x == 0) {
       pi_out[0] = pi;
       pi_hist[0] = pi;
       pi_hist[1] = q0;
     }
   }
   __syncthreads();
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int g = bid_x * blockDim.x + threadIdx.x;
   if (g < L.n_u) {
     const int id = L.idx[g];
     const double inva = L.coef[(size_t)stage * L.n_total + g].y;
     f.us[id] = T((double)f.us[id] - pi_s * ck_dt * inva);
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_cfr_pi(Fields<T> f, IbmLists L, int stage, double ck_dt,
+                                               const double* __restrict__ qpart, int nq, double scale, int forcing,
+                                               double qt, const double* __restrict__ S3,
+                                               double* __restrict__ pi_out, double* __restrict__ pi_hist) {
+  k_cfr_pi_body<T>(f, L, stage, ck_dt, qpart, nq, scale, forcing, qt, S3, pi_out, pi_hist, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
+// The same for a batch of independent grids in one launch (block ranges boff).
+template <typename T>
+__global__ __launch_bounds__(256) void k_cfr_pi_b(const CfrArgs<T>* __restrict__ args,
+    const int* __restrict__ boff, int ninst) {
+  const int i = batch_instance(boff, ninst, blockIdx.x);
+  const CfrArgs<T>& a = args[i];
+  const int local = blockIdx.x - boff[i];
+  k_cfr_pi_body<T>(a.f, a.L, a.stage, a.ck_dt, a.qpart, a.nq, a.scale, a.forcing, a.qt, a.S3, a.pi_out, a.pi_hist, local % a.gx, local / a.gx, boff[i + 1] - boff[i]);
 }
 
 // u* on a u face: internal non-IBM faces still owe -Pi c_k dt (= pick).
@@ -329,15 +375,15 @@ __device__ __forceinline__ T ustar_at(const Fields<T>& f, int c, T pick) {
 // If rhs_in is given, it replaces the divergence (stand-alone Poisson solve).
 // ---------------------------------------------------------------------------------------
 template <typename T, int MB>
-__global__ __launch_bounds__(256) void k_div_fftx(GridParams g, Fields<T> f, IbmLists L, int stage, FFTPlan px,
+__device__ __forceinline__ void k_div_fftx_body(GridParams g, Fields<T> f, IbmLists L, int stage, FFTPlan px,
                                                  const double2* __restrict__ rtw, double ck_dt,
-                                                 const double* __restrict__ pi, const T* __restrict__ rhs_in) {
+                                                 const double* __restrict__ pi, const T* __restrict__ rhs_in, int bid_x, int bid_y, int nblk) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* sm = reinterpret_cast<cplx<T>*>(smem_raw);
   const int N = g.nhalf;
   const int RB = blockDim.x / IBM_WAVE;        // rows per block, one wavefront per row
   const int grp = threadIdx.x / IBM_WAVE, lane = threadIdx.x % IBM_WAVE;
-  const int row = blockIdx.x * RB + grp;
+  const int row = bid_x * RB + grp;
   const int nx = g.nx;
   cplx<T>* A = sm + grp * N;
   cplx<T>* tw = sm + RB * N;
@@ -382,19 +428,36 @@ __global__ __launch_bounds__(256) void k_div_fftx(GridParams g, Fields<T> f, Ibm
   }
 }
 
+template <typename T, int MB>
+__global__ __launch_bounds__(256) void k_div_fftx(GridParams g, Fields<T> f, IbmLists L, int stage, FFTPlan px,
+                                                 const double2* __restrict__ rtw, double ck_dt,
+                                                 const double* __restrict__ pi, const T* __restrict__ rhs_in) {
+  k_div_fftx_body<T, MB>(g, f, L, stage, px, rtw, ck_dt, pi, rhs_in, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
+// The same for a batch of independent grids in one launch (block ranges boff).
+template <typename T, int MB>
+__global__ __launch_bounds__(256) void k_div_fftx_b(const DivArgs<T>* __restrict__ args,
+    const int* __restrict__ boff, int ninst) {
+  const int i = batch_instance(boff, ninst, blockIdx.x);
+  const DivArgs<T>& a = args[i];
+  const int local = blockIdx.x - boff[i];
+  k_div_fftx_body<T, MB>(a.g, a.f, a.L, a.stage, a.px, a.rtw, a.ck_dt, a.pi, a.rhs_in, local % a.gx, local / a.gx, boff[i + 1] - boff[i]);
+}
+
 // ---------------------------------------------------------------------------------------
 // fftz: complex FFT along z of the half spectrum, W consecutive x modes per block.
 // ---------------------------------------------------------------------------------------
 template <typename T, int MB>
-__global__ __launch_bounds__(512) void k_fftz(GridParams g, cplx<T>* __restrict__ spec, FFTPlan pz, int sign,
-                                             int W) {
+__device__ __forceinline__ void k_fftz_body(GridParams g, cplx<T>* __restrict__ spec, FFTPlan pz, int sign,
+                                             int W, int bid_x, int bid_y, int nblk) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem_raw);
   const int nz = g.nz, mh = g.mh;
   cplx<T>* tw = A + nz * W;
   load_twiddles<T>(tw, pz, threadIdx.x, blockDim.x);
-  const int j = blockIdx.y;
-  const int m0 = blockIdx.x * W;
+  const int j = bid_y;
+  const int m0 = bid_x * W;
   cplx<T>* base = spec + (size_t)j * nz * mh;
   for (int e = threadIdx.x; e < nz * W; e += blockDim.x) {
     const int kz = e / W, w = e - kz * W, m = m0 + w;
@@ -408,6 +471,22 @@ __global__ __launch_bounds__(512) void k_fftz(GridParams g, cplx<T>* __restrict_
     const int kz = e / W, ww = e - kz * W, m = m0 + ww;
     if (m < mh) base[kz * mh + m] = R[e];
   }
+}
+
+template <typename T, int MB>
+__global__ __launch_bounds__(512) void k_fftz(GridParams g, cplx<T>* __restrict__ spec, FFTPlan pz, int sign,
+                                             int W) {
+  k_fftz_body<T, MB>(g, spec, pz, sign, W, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
+// The same for a batch of independent grids in one launch (block ranges boff).
+template <typename T, int MB>
+__global__ __launch_bounds__(512) void k_fftz_b(const FftzArgs<T>* __restrict__ args,
+    const int* __restrict__ boff, int ninst) {
+  const int i = batch_instance(boff, ninst, blockIdx.x);
+  const FftzArgs<T>& a = args[i];
+  const int local = blockIdx.x - boff[i];
+  k_fftz_body<T, MB>(a.g, a.spec, a.pz, a.sign, a.W, local % a.gx, local / a.gx, boff[i + 1] - boff[i]);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -427,16 +506,16 @@ __global__ __launch_bounds__(512) void k_fftz(GridParams g, cplx<T>* __restrict_
 // and written once.  W = 256/P modes per block, lane = p * W + w.
 // ---------------------------------------------------------------------------------------
 template <typename T, int LM>
-__global__ __launch_bounds__(256) void k_tri(GridParams g, cplx<T>* __restrict__ spec,
+__device__ __forceinline__ void k_tri_body(GridParams g, cplx<T>* __restrict__ spec,
                                             const double* __restrict__ kx2, const double* __restrict__ kz2,
-                                            int P, int W, double* __restrict__ mean_out) {
+                                            int P, int W, double* __restrict__ mean_out, int bid_x, int bid_y, int nblk) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* lds = reinterpret_cast<double*>(smem_raw);
   const int n = g.ny1, Q = g.nmodes;
   const int tid = threadIdx.x;
   const int w = tid % W, p = tid / W;
   const bool active = p < P;
-  const int q = blockIdx.x * W + w;
+  const int q = bid_x * W + w;
   const bool valid = active && q < Q;
   const int r0 = (int)(((int64_t)p * n) / P);
   const int r1 = active ? (int)(((int64_t)(p + 1) * n) / P) : r0;
@@ -469,7 +548,7 @@ __global__ __launch_bounds__(256) void k_tri(GridParams g, cplx<T>* __restrict__
   }
   // mean of the (0,0) mode over j (only block 0 holds it, at w = 0)
   double mr = 0.0, mi = 0.0;
-  if (blockIdx.x == 0) {
+  if (bid_x == 0) {
     if (w == 0 && active) {
       double sr = 0.0, si = 0.0;
 #pragma unroll
@@ -619,7 +698,7 @@ __global__ __launch_bounds__(256) void k_tri(GridParams g, cplx<T>* __restrict__
     }
   }
   // remove the mean of the (0,0) solution
-  if (blockIdx.x == 0) {
+  if (bid_x == 0) {
     __syncthreads();
     if (w == 0 && active) {
       double sr = 0.0, si = 0.0;
@@ -646,19 +725,36 @@ __global__ __launch_bounds__(256) void k_tri(GridParams g, cplx<T>* __restrict__
   }
 }
 
+template <typename T, int LM>
+__global__ __launch_bounds__(256) void k_tri(GridParams g, cplx<T>* __restrict__ spec,
+                                            const double* __restrict__ kx2, const double* __restrict__ kz2,
+                                            int P, int W, double* __restrict__ mean_out) {
+  k_tri_body<T, LM>(g, spec, kx2, kz2, P, W, mean_out, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
+// The same for a batch of independent grids in one launch (block ranges boff).
+template <typename T, int LM>
+__global__ __launch_bounds__(256) void k_tri_b(const TriArgs<T>* __restrict__ args,
+    const int* __restrict__ boff, int ninst) {
+  const int i = batch_instance(boff, ninst, blockIdx.x);
+  const TriArgs<T>& a = args[i];
+  const int local = blockIdx.x - boff[i];
+  k_tri_body<T, LM>(a.g, a.spec, a.kx2, a.kz2, a.P, a.W, a.mean_out, local % a.gx, local / a.gx, boff[i + 1] - boff[i]);
+}
+
 // ---------------------------------------------------------------------------------------
 // ifftx: inverse real FFT along x of each row: Z_m = (X_m + conj X_{N-m})
 //        + i e^{+2 pi i m/nx} (X_m - conj X_{N-m}), m < N = nx/2, z = IDFT_N(Z),
 //        x_{2n} = Re z_n, x_{2n+1} = Im z_n.  Unnormalised (tri applied 1/(nx nz)).
 // ---------------------------------------------------------------------------------------
 template <typename T, int MB>
-__global__ __launch_bounds__(256) void k_ifftx(GridParams g, const cplx<T>* __restrict__ spec, T* __restrict__ out,
-                                              FFTPlan px, const double2* __restrict__ rtw) {
+__device__ __forceinline__ void k_ifftx_body(GridParams g, const cplx<T>* __restrict__ spec, T* __restrict__ out,
+                                              FFTPlan px, const double2* __restrict__ rtw, int bid_x, int bid_y, int nblk) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* sm = reinterpret_cast<cplx<T>*>(smem_raw);
   const int N = g.nhalf;
   const int grp = threadIdx.x / IBM_WAVE, lane = threadIdx.x % IBM_WAVE;
-  const int row = blockIdx.x * 4 + grp;
+  const int row = bid_x * 4 + grp;
   cplx<T>* A = sm + grp * N;
   cplx<T>* tw = sm + 4 * N;
   load_twiddles<T>(tw, px, threadIdx.x, blockDim.x);
@@ -682,6 +778,22 @@ __global__ __launch_bounds__(256) void k_ifftx(GridParams g, const cplx<T>* __re
     const T* Rr = reinterpret_cast<const T*>(R);
     for (int i = lane; i < g.nx; i += IBM_WAVE) out[(size_t)row * g.nx + i] = Rr[i];
   }
+}
+
+template <typename T, int MB>
+__global__ __launch_bounds__(256) void k_ifftx(GridParams g, const cplx<T>* __restrict__ spec, T* __restrict__ out,
+                                              FFTPlan px, const double2* __restrict__ rtw) {
+  k_ifftx_body<T, MB>(g, spec, out, px, rtw, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
+// The same for a batch of independent grids in one launch (block ranges boff).
+template <typename T, int MB>
+__global__ __launch_bounds__(256) void k_ifftx_b(const IfftxArgs<T>* __restrict__ args,
+    const int* __restrict__ boff, int ninst) {
+  const int i = batch_instance(boff, ninst, blockIdx.x);
+  const IfftxArgs<T>& a = args[i];
+  const int local = blockIdx.x - boff[i];
+  k_ifftx_body<T, MB>(a.g, a.spec, a.out, a.px, a.rtw, local % a.gx, local / a.gx, boff[i + 1] - boff[i]);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -883,6 +995,171 @@ hipError_t launch_copy(const T* src, T* dst, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_copy<T>, dim3((unsigned)nb), dim3(256), 0, st, src, dst, n);
   return hipGetLastError();
 }
+
+// =======================================================================================
+// Batched launches: the step kernels of many independent grids in one launch each.  The
+// plan_* functions fill one grid's arguments exactly as the single-grid launchers choose
+// them and return its number of blocks; the batched launch takes the per-grid arguments
+// and the block offsets from device memory and uses the largest template variant and
+// LDS size any grid needs (the kernels read the per-grid sizes at run time).
+// =======================================================================================
+template <typename T>
+int plan_momentum(const GridParams& g, const Fields<T>& f, const IbmLists& L, const StageConsts& s,
+                  const double* pi_prev, double ckdt_prev, const Tuning& tu, double* qpart, MomArgs<T>* a) {
+  const int jc = momentum_chunk(g, tu);
+  const int ntx = (g.nx + MX - 1) / MX, ntz = (g.nz + MZ - 1) / MZ, nty = (g.ny1 + jc - 1) / jc;
+  const int nb = ntx * ntz * nty;
+  *a = MomArgs<T>{g, f, L, s, jc, ntx, ntz, 0, pi_prev, ckdt_prev, qpart, nb};
+  return nb;
+}
+
+template <typename T>
+int plan_cfr_pi(const Fields<T>& f, const IbmLists& L, int stage, double ck_dt, const double* qpart, int nq,
+                double scale, int forcing, double q_target_or_pi, const double* S3, double* pi_out, double* pi_hist,
+                CfrArgs<T>* a) {
+  const int nb = L.n_u > 0 ? (L.n_u + 255) / 256 : 1;
+  *a = CfrArgs<T>{f, L, stage, ck_dt, qpart, nq, scale, forcing, q_target_or_pi, S3, pi_out, pi_hist, nb};
+  return nb;
+}
+
+template <typename T>
+int plan_div_fftx(const GridParams& g, const Fields<T>& f, const IbmLists& L, int stage, const FFTPlan& px,
+                  const double2* rtw, double ck_dt, const double* pi, DivArgs<T>* a, int* mb, size_t* lds) {
+  const int RB = 4;
+  const int nb = (g.nrows + RB - 1) / RB;
+  *a = DivArgs<T>{g, f, L, stage, px, rtw, ck_dt, pi, (const T*)nullptr, nb};
+  *mb = fft_max_bfly(px, IBM_WAVE);
+  *lds = (RB + 1) * (size_t)g.nhalf * sizeof(cplx<T>);
+  return nb;
+}
+
+template <typename T>
+int plan_fftz(const GridParams& g, cplx<T>* spec, const FFTPlan& pz, int sign, const Tuning& tu, FftzArgs<T>* a,
+              int* mb, size_t* lds, int* threads) {
+  const int W = fftz_width<T>(g, pz, tu);
+  const int nt = fftz_threads(pz, W);
+  const int gx = (g.mh + W - 1) / W;
+  *a = FftzArgs<T>{g, spec, pz, sign, W, gx};
+  *mb = fft_max_bfly(pz, nt / W);
+  *lds = ((size_t)W + 1) * g.nz * sizeof(cplx<T>);
+  *threads = nt;
+  return gx * g.ny1;
+}
+
+template <typename T>
+int plan_tri(const GridParams& g, cplx<T>* spec, const double* kx2, const double* kz2, double* mean_out,
+             const Tuning& tu, TriArgs<T>* a, int* lm, size_t* lds) {
+  const int n = g.ny1;
+  const int L = (tu.tri_rows == 4) ? 4 : 8;
+  int P = (n + L - 1) / L;
+  if (P > n / 2) P = n / 2 > 0 ? n / 2 : 1;
+  if (P > 256) P = 256;
+  const int W = 256 / P;
+  const int nb = (g.nmodes + W - 1) / W;
+  *a = TriArgs<T>{g, spec, kx2, kz2, P, W, mean_out, nb};
+  *lm = (L == 4 && (n + P - 1) / P <= 4) ? 4 : 8;
+  *lds = (size_t)(5 * W * 2 * P + 2 * P) * sizeof(double);
+  return nb;
+}
+
+template <typename T>
+int plan_ifftx(const GridParams& g, const cplx<T>* spec, T* out, const FFTPlan& px, const double2* rtw,
+               IfftxArgs<T>* a, int* mb, size_t* lds) {
+  const int nb = (g.nrows + 3) / 4;
+  *a = IfftxArgs<T>{g, spec, out, px, rtw, nb};
+  *mb = fft_max_bfly(px, IBM_WAVE);
+  *lds = (4 + 1) * (size_t)g.nhalf * sizeof(cplx<T>);
+  return nb;
+}
+
+// Dynamic LDS above 64 KiB has to be allowed per kernel.
+static hipError_t allow_lds(const void* kfn, size_t lds) {
+  if (lds <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+template <typename T>
+hipError_t launch_momentum_b(const MomArgs<T>* args, const int* boff, int ninst, int ntot, hipStream_t st) {
+  hipLaunchKernelGGL(k_momentum_b<T>, dim3(ntot), dim3(MX, MZ), 0, st, args, boff, ninst);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cfr_pi_b(const CfrArgs<T>* args, const int* boff, int ninst, int ntot, hipStream_t st) {
+  hipLaunchKernelGGL(k_cfr_pi_b<T>, dim3(ntot), dim3(256), 0, st, args, boff, ninst);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_div_fftx_b(const DivArgs<T>* args, const int* boff, int ninst, int ntot, int mb, size_t lds,
+                             hipStream_t st) {
+  const void* k = mb == 1 ? (const void*)k_div_fftx_b<T, 1> : (mb == 2 ? (const void*)k_div_fftx_b<T, 2> : (const void*)k_div_fftx_b<T, 4>);
+  hipError_t e = allow_lds(k, lds);
+  if (e != hipSuccess) return e;
+  if (mb == 1) hipLaunchKernelGGL((k_div_fftx_b<T, 1>), dim3(ntot), dim3(256), lds, st, args, boff, ninst);
+  else if (mb == 2) hipLaunchKernelGGL((k_div_fftx_b<T, 2>), dim3(ntot), dim3(256), lds, st, args, boff, ninst);
+  else hipLaunchKernelGGL((k_div_fftx_b<T, 4>), dim3(ntot), dim3(256), lds, st, args, boff, ninst);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fftz_b(const FftzArgs<T>* args, const int* boff, int ninst, int ntot, int mb, size_t lds,
+                         int threads, hipStream_t st) {
+  const void* k = mb == 1 ? (const void*)k_fftz_b<T, 1> : (mb == 2 ? (const void*)k_fftz_b<T, 2> : (const void*)k_fftz_b<T, 4>);
+  hipError_t e = allow_lds(k, lds);
+  if (e != hipSuccess) return e;
+  if (mb == 1) hipLaunchKernelGGL((k_fftz_b<T, 1>), dim3(ntot), dim3(threads), lds, st, args, boff, ninst);
+  else if (mb == 2) hipLaunchKernelGGL((k_fftz_b<T, 2>), dim3(ntot), dim3(threads), lds, st, args, boff, ninst);
+  else hipLaunchKernelGGL((k_fftz_b<T, 4>), dim3(ntot), dim3(threads), lds, st, args, boff, ninst);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_tri_b(const TriArgs<T>* args, const int* boff, int ninst, int ntot, int lm, size_t lds,
+                        hipStream_t st) {
+  const void* k = lm == 4 ? (const void*)k_tri_b<T, 4> : (const void*)k_tri_b<T, 8>;
+  hipError_t e = allow_lds(k, lds);
+  if (e != hipSuccess) return e;
+  if (lm == 4) hipLaunchKernelGGL((k_tri_b<T, 4>), dim3(ntot), dim3(256), lds, st, args, boff, ninst);
+  else hipLaunchKernelGGL((k_tri_b<T, 8>), dim3(ntot), dim3(256), lds, st, args, boff, ninst);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_ifftx_b(const IfftxArgs<T>* args, const int* boff, int ninst, int ntot, int mb, size_t lds,
+                          hipStream_t st) {
+  const void* k = mb == 1 ? (const void*)k_ifftx_b<T, 1> : (mb == 2 ? (const void*)k_ifftx_b<T, 2> : (const void*)k_ifftx_b<T, 4>);
+  hipError_t e = allow_lds(k, lds);
+  if (e != hipSuccess) return e;
+  if (mb == 1) hipLaunchKernelGGL((k_ifftx_b<T, 1>), dim3(ntot), dim3(256), lds, st, args, boff, ninst);
+  else if (mb == 2) hipLaunchKernelGGL((k_ifftx_b<T, 2>), dim3(ntot), dim3(256), lds, st, args, boff, ninst);
+  else hipLaunchKernelGGL((k_ifftx_b<T, 4>), dim3(ntot), dim3(256), lds, st, args, boff, ninst);
+  return hipGetLastError();
+}
+
+#define IBM_BATCH_INST(T)                                                                                        \
+  template int plan_momentum<T>(const GridParams&, const Fields<T>&, const IbmLists&, const StageConsts&,       \
+                                const double*, double, const Tuning&, double*, MomArgs<T>*);                    \
+  template int plan_cfr_pi<T>(const Fields<T>&, const IbmLists&, int, double, const double*, int, double, int,  \
+                              double, const double*, double*, double*, CfrArgs<T>*);                            \
+  template int plan_div_fftx<T>(const GridParams&, const Fields<T>&, const IbmLists&, int, const FFTPlan&,      \
+                                const double2*, double, const double*, DivArgs<T>*, int*, size_t*);             \
+  template int plan_fftz<T>(const GridParams&, cplx<T>*, const FFTPlan&, int, const Tuning&, FftzArgs<T>*,      \
+                            int*, size_t*, int*);                                                               \
+  template int plan_tri<T>(const GridParams&, cplx<T>*, const double*, const double*, double*, const Tuning&,   \
+                           TriArgs<T>*, int*, size_t*);                                                         \
+  template int plan_ifftx<T>(const GridParams&, const cplx<T>*, T*, const FFTPlan&, const double2*,             \
+                             IfftxArgs<T>*, int*, size_t*);                                                     \
+  template hipError_t launch_momentum_b<T>(const MomArgs<T>*, const int*, int, int, hipStream_t);               \
+  template hipError_t launch_cfr_pi_b<T>(const CfrArgs<T>*, const int*, int, int, hipStream_t);                 \
+  template hipError_t launch_div_fftx_b<T>(const DivArgs<T>*, const int*, int, int, int, size_t, hipStream_t);  \
+  template hipError_t launch_fftz_b<T>(const FftzArgs<T>*, const int*, int, int, int, size_t, int,              \
+                                       hipStream_t);                                                            \
+  template hipError_t launch_tri_b<T>(const TriArgs<T>*, const int*, int, int, int, size_t, hipStream_t);       \
+  template hipError_t launch_ifftx_b<T>(const IfftxArgs<T>*, const int*, int, int, int, size_t, hipStream_t);
+
+IBM_BATCH_INST(double)
+IBM_BATCH_INST(float)
 
 #define IBM_INST(T)                                                                                              \
   template hipError_t launch_momentum<T>(const GridParams&, const Fields<T>&, const IbmLists&,                  \

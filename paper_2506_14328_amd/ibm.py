@@ -31,7 +31,7 @@ EXPORTED = [
     "ibm_destroy", "ibm_last_error", "ibm_tune_set", "ibm_tune_get", "ibm_autotune",
 ]
 TUNE_PARAMS = {"momentum_planes": 0, "fftz_width": 1, "tri_rows": 2, "graph": 3, "graph_branches": 4,
-               "tile_order": 5}
+               "tile_order": 5, "batch": 6}
 
 
 class IbmGridDesc(ctypes.Structure):
@@ -253,7 +253,7 @@ class IbmGrid:
 
     def tune(self, **knobs):
         """Set launch-shape knobs by name (momentum_planes, fftz_width, tri_rows, tile_order,
-        graph, graph_branches); 0 = automatic."""
+        graph, graph_branches, batch); 0 = automatic."""
         for k, v in knobs.items():
             self._check(self.lib.ibm_tune_set(self._h, TUNE_PARAMS[k], int(v)))
 

@@ -245,14 +245,16 @@ def _ensemble_members():
             case("minimal")]
 
 
-@pytest.mark.parametrize("graph", [False, True])
-def test_ensemble_matches_oracle_per_instance(graph):
-    """Ragged independent instances advanced together equal their own oracle runs."""
+@pytest.mark.parametrize("graph,batch", [(False, False), (True, False), (False, True), (True, True)])
+def test_ensemble_matches_oracle_per_instance(graph, batch):
+    """Ragged independent instances advanced together (per-instance launches, or one
+    launch per kernel for all of them; eager or as a HIP graph) equal their own oracle
+    runs."""
     from paper_2506_14328_amd import IbmGrid
     members = _ensemble_members()
     refs = [oracle_run(c, 2) for c in members]
     g = IbmGrid.ensemble(members, precision="fp64")
-    g.tune(graph=1 if graph else 0, graph_branches=3)
+    g.tune(graph=1 if graph else 0, graph_branches=3, batch=1 if batch else 0)
     for i, (o, sdf, st) in enumerate(refs):
         g.set_geometry(*[to_dev(s) for s in sdf], inst=i)
         g.set_state(*[to_dev(a) for a in st], inst=i)
@@ -267,15 +269,16 @@ def test_ensemble_matches_oracle_per_instance(graph):
 
 
 def test_graph_replays_match_eager():
-    """Every replay of the captured step equals the eager launches, with eager work and
-    synchronisations between the replays."""
+    """Every replay of the captured step (per-instance launches, or one launch per kernel
+    for all instances) equals the eager per-instance launches bit for bit, with eager work
+    and synchronisations between the replays."""
     from paper_2506_14328_amd import IbmGrid
     members = _ensemble_members()[:3]
     ins = [oracle_run(c, 0) for c in members]
     gs = []
-    for graph in (False, True):
+    for graph, batch in ((False, False), (True, False), (True, True), (False, True)):
         g = IbmGrid.ensemble(members, precision="fp64")
-        g.tune(graph=1 if graph else 0)
+        g.tune(graph=1 if graph else 0, batch=1 if batch else 0, tile_order=2)
         for i, (o, sdf, st) in enumerate(ins):
             g.set_geometry(*[to_dev(s) for s in sdf], inst=i)
             g.set_state(*[to_dev(a) for a in st], inst=i)
@@ -287,8 +290,9 @@ def test_graph_replays_match_eager():
         _ = (torch.ones(1000, device=device()) * rep).sum().item()    # unrelated eager work
         for i in range(len(members)):
             a = [t.cpu().numpy() for t in gs[0].get_state(inst=i)]
-            b = [t.cpu().numpy() for t in gs[1].get_state(inst=i)]
-            for x, y in zip(a, b):
-                assert np.array_equal(x, y), (rep, i)
+            for other in gs[1:]:
+                b = [t.cpu().numpy() for t in other.get_state(inst=i)]
+                for x, y in zip(a, b):
+                    assert np.array_equal(x, y), (rep, i)
     for g in gs:
         g.close()

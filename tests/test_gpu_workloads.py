@@ -296,9 +296,10 @@ def test_ellipsoids_full_size_one_step_parity():
 # the 96-instance ragged ensemble
 # ---------------------------------------------------------------------------------------
 def test_ensemble_96_sampled_instances():
-    """All 96 instances advanced together as one graph per step; the smallest instance, a
-    160-point-FFT instance and the largest one are checked against their oracle runs
-    (FP64 within 1e-12, FP32 storage within 1e-5)."""
+    """All 96 instances advanced together as one graph per step of batched launches (one
+    launch per kernel for all instances); the smallest instance, a 160-point-FFT instance
+    and the largest one are checked against their oracle runs (FP64 within 1e-12, FP32
+    storage within 1e-5)."""
     from paper_2506_14328_amd import IbmGrid
     cases = I.ensemble_cases(96, 5)
     cells = [c.nx * (c.ny - 1) * c.nz for c in cases]
@@ -319,7 +320,7 @@ def test_ensemble_96_sampled_instances():
         for i, (sdf, st) in enumerate(inputs):
             g.set_geometry(*sdf, inst=i)
             g.set_state(*[t.to(dt) for t in st], inst=i)
-        g.tune(graph=1)
+        g.tune(graph=1, batch=1)
         g.step(1)
         for i in sample:
             u, v, w, p = [t.double().cpu().numpy() for t in g.get_state(inst=i)]
