@@ -1,7 +1,7 @@
 // Mixed-radix (8, 4, 2, 3, 5) Stockham FFT on data resident in LDS.
 //
 // A group of `nlanes` threads transforms one sequence of length p.n whose
-// element e sits at buf[e * stride].  Each stage writes its self-sorted result
+// element e sits at buf[e << ls].  Each stage writes its self-sorted result
 // (Stockham auto-sort) back into the same LDS buffer, so no bit-reversal pass is
 // needed.  Stage with radix R after a span Ns:
 //   butterfly b (0 <= b < n/R), k = b mod Ns,
@@ -117,23 +117,36 @@ __device__ __forceinline__ void load_twiddles(cplx<T>* dst, const FFTPlan& p, in
   for (int m = tid; m < p.n; m += nthr) dst[m] = twiddle<T>(p, m, -1);
 }
 
+// Quotient b / d for 0 <= b, d < 2^15 with one multiply-high instead of an integer
+// division: with m = ceil(2^31 / d) = (2^31 + e) / d, 0 <= e < d, the product 2 b m / 2^32
+// equals b / d + b e / (d 2^31), and b e < 2^31 keeps its floor at floor(b / d).
+__device__ __forceinline__ uint32_t div_magic(uint32_t d) { return (0x80000000u + d - 1u) / d; }
+__device__ __forceinline__ int div_by(int b, uint32_t m) { return (int)__umulhi((uint32_t)b << 1, m); }
+
 // One in-place stage: every thread first computes up to MB butterflies into
 // registers, the block synchronises, then the results are written to their
 // self-sorted positions.  Requires n/R <= MB * nlanes (the launchers pick MB).
+// Element e of the sequence sits at buf[e << ls].
 template <typename T, int R, int MB>
-__device__ __forceinline__ void fft_stage_r(cplx<T>* buf, int n, int Ns, int stride, const cplx<T>* __restrict__ tw,
+__device__ __forceinline__ void fft_stage_r(cplx<T>* buf, int n, int Ns, int ls, const cplx<T>* __restrict__ tw,
                                             int sign, int lane, int nlanes) {
-  constexpr int FFT_MAXB = MB;
   const int nb = n / R;
-  const int tstep = n / (Ns * R);
-  cplx<T> v[FFT_MAXB][R];
+  const uint32_t mg = div_magic((uint32_t)Ns);
+  const int tstep = div_by(nb, mg);   // n / (Ns R)
+  const int nbs = nb << ls, nss = Ns << ls;
+  cplx<T> v[MB][R];
+  int out[MB];
 #pragma unroll
-  for (int q = 0; q < FFT_MAXB; ++q) {
+  for (int q = 0; q < MB; ++q) {
     const int b = lane + q * nlanes;
+    out[q] = -1;
     if (b < nb) {
-      const int k = b % Ns;
+      const int gNs = div_by(b, mg) * Ns;   // (b / Ns) Ns
+      const int k = b - gNs;
+      out[q] = (b + gNs * (R - 1)) << ls;   // ((b / Ns) Ns R + k) << ls
+      const int bi = b << ls;
 #pragma unroll
-      for (int t = 0; t < R; ++t) v[q][t] = buf[(b + t * nb) * stride];
+      for (int t = 0; t < R; ++t) v[q][t] = buf[bi + t * nbs];
       if (k != 0) {
         // w1 = w^(k tstep) from the table, higher powers by repeated multiplication
         const cplx<T> w1 = tw_at<T>(tw, k * tstep, sign);
@@ -153,32 +166,30 @@ __device__ __forceinline__ void fft_stage_r(cplx<T>* buf, int n, int Ns, int str
   }
   __syncthreads();
 #pragma unroll
-  for (int q = 0; q < FFT_MAXB; ++q) {
-    const int b = lane + q * nlanes;
-    if (b < nb) {
-      const int k = b % Ns;
-      const int o = (b / Ns) * Ns * R + k;
+  for (int q = 0; q < MB; ++q) {
+    if (out[q] >= 0) {
 #pragma unroll
-      for (int t = 0; t < R; ++t) buf[(o + t * Ns) * stride] = v[q][t];
+      for (int t = 0; t < R; ++t) buf[out[q] + t * nss] = v[q][t];
     }
   }
   __syncthreads();
 }
 
-// Transforms, in place, the sequence held in buf (element e at buf[e * stride]) with
-// twiddles from the LDS table tw.  Every thread of the block must call it.
+// Transforms, in place, the sequence held in buf (element e at buf[e << ls], the stride
+// a power of two) with twiddles from the LDS table tw (n < 2^15).  Every thread of the
+// block must call it.
 template <typename T, int MB>
-__device__ void fft_lds(cplx<T>* buf, int stride, const FFTPlan& p, const cplx<T>* tw, int sign, int lane,
+__device__ void fft_lds(cplx<T>* buf, int ls, const FFTPlan& p, const cplx<T>* tw, int sign, int lane,
                         int nlanes) {
   int Ns = 1;
   for (int s = 0; s < p.nst; ++s) {
     const int R = (int)((p.rcode >> (4 * s)) & 15u);
     switch (R) {
-      case 8: fft_stage_r<T, 8, MB>(buf, p.n, Ns, stride, tw, sign, lane, nlanes); break;
-      case 4: fft_stage_r<T, 4, MB>(buf, p.n, Ns, stride, tw, sign, lane, nlanes); break;
-      case 2: fft_stage_r<T, 2, MB>(buf, p.n, Ns, stride, tw, sign, lane, nlanes); break;
-      case 3: fft_stage_r<T, 3, MB>(buf, p.n, Ns, stride, tw, sign, lane, nlanes); break;
-      default: fft_stage_r<T, 5, MB>(buf, p.n, Ns, stride, tw, sign, lane, nlanes); break;
+      case 8: fft_stage_r<T, 8, MB>(buf, p.n, Ns, ls, tw, sign, lane, nlanes); break;
+      case 4: fft_stage_r<T, 4, MB>(buf, p.n, Ns, ls, tw, sign, lane, nlanes); break;
+      case 2: fft_stage_r<T, 2, MB>(buf, p.n, Ns, ls, tw, sign, lane, nlanes); break;
+      case 3: fft_stage_r<T, 3, MB>(buf, p.n, Ns, ls, tw, sign, lane, nlanes); break;
+      default: fft_stage_r<T, 5, MB>(buf, p.n, Ns, ls, tw, sign, lane, nlanes); break;
     }
     Ns *= R;
   }

@@ -220,10 +220,17 @@ int init_instance(ibm_ctx* c, Instance& I, const ibm_grid_desc& d) {
   g.idz2 = 1.0 / (g.dz * g.dz);
   g.nu = d.nu;
   g.dt = d.dt;
+  const size_t ts = (c->precision == IBM_FP64) ? sizeof(double) : sizeof(float);
+  // spectrum rows start on 128-byte lines (8 FP64 or 16 FP32 complex values per line);
+  // a plane spans an odd number of lines, so that the rows of one mode in successive
+  // planes do not all fall on the same memory channels
+  const int line = (int)(128 / (2 * ts));
+  g.mhs = (g.mh + line - 1) / line * line;
+  g.splane = g.nz * g.mhs;
+  if ((g.splane / line) % 2 == 0) g.splane += line;
   int rc;
   if ((rc = make_plan(c, I, g.nhalf, &I.px))) return rc;
   if ((rc = make_plan(c, I, g.nz, &I.pz))) return rc;
-  const size_t ts = (c->precision == IBM_FP64) ? sizeof(double) : sizeof(float);
   const size_t fb = (size_t)g.ncell * ts;
   void** fields[] = {&I.u, &I.v, &I.w, &I.p, &I.S[0][0], &I.S[0][1], &I.S[0][2], &I.S[1][0], &I.S[1][1],
                      &I.S[1][2], &I.S[2][0], &I.S[2][1], &I.S[2][2], &I.P[0], &I.P[1], &I.P[2],
@@ -232,7 +239,7 @@ int init_instance(ibm_ctx* c, Instance& I, const ibm_grid_desc& d) {
     if ((rc = dalloc(c, I, f, fb))) return rc;
     HIPCHK(c, hipMemsetAsync(*f, 0, fb, c->stream));
   }
-  const size_t nspec = (size_t)g.ny1 * g.nmodes;
+  const size_t nspec = (size_t)g.ny1 * g.splane;
   if ((rc = dalloc(c, I, &I.spec, nspec * 2 * ts))) return rc;
   if ((rc = dalloc(c, I, (void**)&I.tag, (size_t)g.ncell))) return rc;
   HIPCHK(c, hipMemsetAsync(I.tag, 0, (size_t)g.ncell, c->stream));

@@ -36,6 +36,8 @@ struct GridParams {
   int nhalf;            // nx/2 (length of the packed complex x transform)
   int nrows;            // ny1*nz rows of nx points
   int nmodes;           // nz*mh Fourier modes per y plane
+  int mhs;              // spectrum row stride: mh rounded up to whole 128-byte lines
+  int splane;           // spectrum elements per y plane (nz*mhs, plus one line if even)
   int64_t ncell;        // nx*ny1*nz
   double dx, dy, dz;
   double idx, idy, idz;
@@ -205,6 +207,7 @@ struct DivArgs {
   double ck_dt;
   const double* pi;
   const T* rhs_in;
+  int ll;   // log2 of the lanes per row
   int gx;   // blocks along x of the instance's grid
 };
 
@@ -237,6 +240,7 @@ struct IfftxArgs {
   T* out;
   FFTPlan px;
   const double2* rtw;
+  int ll;   // log2 of the lanes per row
   int gx;   // blocks along x of the instance's grid
 };
 

@@ -371,18 +371,21 @@ __device__ __forceinline__ T ustar_at(const Fields<T>& f, int c, T pick) {
 // ---------------------------------------------------------------------------------------
 // div_fftx: rhs = D u* / (c_k dt) on every cell, then the real FFT along x of each
 // (j, k) row: the nx reals are packed as nx/2 complex numbers z_n = x_{2n} + i x_{2n+1},
-// transformed, and unpacked to X_m, m = 0..nx/2.  One wavefront per row, 4 rows/block.
+// transformed, and unpacked to X_m, m = 0..nx/2.  2^ll lanes per row (as few as keep
+// every FFT stage at <= 2 butterflies per lane), blockDim.x >> ll rows per block.
 // If rhs_in is given, it replaces the divergence (stand-alone Poisson solve).
 // ---------------------------------------------------------------------------------------
 template <typename T, int MB>
 __device__ __forceinline__ void k_div_fftx_body(GridParams g, Fields<T> f, IbmLists L, int stage, FFTPlan px,
                                                  const double2* __restrict__ rtw, double ck_dt,
-                                                 const double* __restrict__ pi, const T* __restrict__ rhs_in, int bid_x, int bid_y, int nblk) {
+                                                 const double* __restrict__ pi, const T* __restrict__ rhs_in, int ll,
+                                                 int bid_x, int bid_y, int nblk) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* sm = reinterpret_cast<cplx<T>*>(smem_raw);
   const int N = g.nhalf;
-  const int RB = blockDim.x / IBM_WAVE;        // rows per block, one wavefront per row
-  const int grp = threadIdx.x / IBM_WAVE, lane = threadIdx.x % IBM_WAVE;
+  const int RB = blockDim.x >> ll;             // rows per block
+  const int NL = 1 << ll;                      // lanes per row
+  const int grp = threadIdx.x >> ll, lane = threadIdx.x & (NL - 1);
   const int row = bid_x * RB + grp;
   const int nx = g.nx;
   cplx<T>* A = sm + grp * N;
@@ -392,7 +395,7 @@ __device__ __forceinline__ void k_div_fftx_body(GridParams g, Fields<T> f, IbmLi
   if (valid) {
     T* Ar = reinterpret_cast<T*>(A);   // interleaved (re, im) == packed reals
     if (rhs_in) {
-      for (int i = lane; i < nx; i += IBM_WAVE) Ar[i] = rhs_in[row * nx + i];
+      for (int i = lane; i < nx; i += NL) Ar[i] = rhs_in[row * nx + i];
     } else {
       const int j = row / g.nz, k = row - (row / g.nz) * g.nz;
       const int kp = wrap_p(k, g.nz);
@@ -401,7 +404,7 @@ __device__ __forceinline__ void k_div_fftx_body(GridParams g, Fields<T> f, IbmLi
       const T idx = T(g.idx), idy = T(g.idy), idz = T(g.idz);
       const bool hasN = (j + 1 < g.ny1);
       const int plane = nx * g.nz;
-      for (int i = lane; i < nx; i += IBM_WAVE) {
+      for (int i = lane; i < nx; i += NL) {
         const int c = row * nx + i;
         const int ip = wrap_p(i, nx);
         const T ue = ustar_at(f, c - i + ip, pick), uc = ustar_at(f, c, pick);
@@ -412,11 +415,12 @@ __device__ __forceinline__ void k_div_fftx_body(GridParams g, Fields<T> f, IbmLi
     }
   }
   __syncthreads();
-  fft_lds<T, MB>(A, 1, px, tw, -1, lane, IBM_WAVE);
+  fft_lds<T, MB>(A, 0, px, tw, -1, lane, NL);
   const cplx<T>* R = A;
   if (valid) {
-    cplx<T>* out = f.spec + (size_t)row * g.mh;
-    for (int m = lane; m <= N; m += IBM_WAVE) {
+    const int jr = row / g.nz;
+    cplx<T>* out = f.spec + (size_t)jr * g.splane + (size_t)(row - jr * g.nz) * g.mhs;
+    for (int m = lane; m <= N; m += NL) {
       const cplx<T> Zm = R[m == N ? 0 : m];
       const cplx<T> Zc = cconj(R[m == 0 ? 0 : N - m]);
       const cplx<T> s1 = cadd(Zm, Zc), d1 = csub(Zm, Zc);
@@ -431,8 +435,9 @@ __device__ __forceinline__ void k_div_fftx_body(GridParams g, Fields<T> f, IbmLi
 template <typename T, int MB>
 __global__ __launch_bounds__(256) void k_div_fftx(GridParams g, Fields<T> f, IbmLists L, int stage, FFTPlan px,
                                                  const double2* __restrict__ rtw, double ck_dt,
-                                                 const double* __restrict__ pi, const T* __restrict__ rhs_in) {
-  k_div_fftx_body<T, MB>(g, f, L, stage, px, rtw, ck_dt, pi, rhs_in, blockIdx.x, blockIdx.y, gridDim.x);
+                                                 const double* __restrict__ pi, const T* __restrict__ rhs_in,
+                                                 int ll) {
+  k_div_fftx_body<T, MB>(g, f, L, stage, px, rtw, ck_dt, pi, rhs_in, ll, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
 // The same for a batch of independent grids in one launch (block ranges boff).
@@ -442,41 +447,58 @@ __global__ __launch_bounds__(256) void k_div_fftx_b(const DivArgs<T>* __restrict
   const int i = batch_instance(boff, ninst, blockIdx.x);
   const DivArgs<T>& a = args[i];
   const int local = blockIdx.x - boff[i];
-  k_div_fftx_body<T, MB>(a.g, a.f, a.L, a.stage, a.px, a.rtw, a.ck_dt, a.pi, a.rhs_in, local % a.gx, local / a.gx, boff[i + 1] - boff[i]);
+  k_div_fftx_body<T, MB>(a.g, a.f, a.L, a.stage, a.px, a.rtw, a.ck_dt, a.pi, a.rhs_in, a.ll, local % a.gx, local / a.gx, boff[i + 1] - boff[i]);
 }
 
 // ---------------------------------------------------------------------------------------
-// fftz: complex FFT along z of the half spectrum, W consecutive x modes per block.
+// fftz: complex FFT along z of the half spectrum, W columns (one x mode m of one plane j)
+// per block.  The first blocks take W consecutive modes of one plane; the mh mod W modes
+// left over at the end of every plane are gathered, W at a time, into the last blocks, so
+// that no block transforms padding columns.
 // ---------------------------------------------------------------------------------------
 template <typename T, int MB>
 __device__ __forceinline__ void k_fftz_body(GridParams g, cplx<T>* __restrict__ spec, FFTPlan pz, int sign,
-                                             int W, int bid_x, int bid_y, int nblk) {
+                                             int W, int b) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem_raw);
-  const int nz = g.nz, mh = g.mh;
+  const int nz = g.nz, mh = g.mh, mhs = g.mhs;
   cplx<T>* tw = A + nz * W;
   load_twiddles<T>(tw, pz, threadIdx.x, blockDim.x);
-  const int j = bid_y;
-  const int m0 = bid_x * W;
-  cplx<T>* base = spec + (size_t)j * nz * mh;
-  for (int e = threadIdx.x; e < nz * W; e += blockDim.x) {
-    const int kz = e / W, w = e - kz * W, m = m0 + w;
-    A[e] = (m < mh) ? base[kz * mh + m] : cplx<T>{T(0), T(0)};
+  const int lw = __ffs(W) - 1;   // W is a power of two
+  const int w = threadIdx.x & (W - 1), lane = threadIdx.x >> lw, nl = blockDim.x >> lw;
+  const int gxf = mh >> lw, nfull = gxf * g.ny1, rem = mh - (gxf << lw);
+  // this thread's column (plane j, mode m)
+  int j = 0, m = 0;
+  bool ok = true;
+  if (b < nfull) {
+    j = b / gxf;
+    m = ((b - j * gxf) << lw) + w;
+  } else {
+    const int idx = ((b - nfull) << lw) + w;
+    ok = rem > 0 && idx < rem * g.ny1;
+    if (ok) {
+      j = idx / rem;
+      m = (gxf << lw) + idx - j * rem;
+    }
   }
+  cplx<T>* col = spec + (size_t)j * g.splane + m;   // element kz at col[kz * mhs]
+  for (int kz = lane; kz < nz; kz += nl) A[(kz << lw) + w] = ok ? col[(size_t)kz * mhs] : cplx<T>{T(0), T(0)};
   __syncthreads();
-  const int w = threadIdx.x % W, lane = threadIdx.x / W, nl = blockDim.x / W;
-  fft_lds<T, MB>(A + w, W, pz, tw, sign, lane, nl);
-  const cplx<T>* R = A;
-  for (int e = threadIdx.x; e < nz * W; e += blockDim.x) {
-    const int kz = e / W, ww = e - kz * W, m = m0 + ww;
-    if (m < mh) base[kz * mh + m] = R[e];
-  }
+  fft_lds<T, MB>(A + w, lw, pz, tw, sign, lane, nl);
+  if (ok)
+    for (int kz = lane; kz < nz; kz += nl) col[(size_t)kz * mhs] = A[(kz << lw) + w];
+}
+
+// Blocks of one z-FFT launch: full blocks plus the gathered remainder columns.
+__host__ __device__ inline int fftz_blocks(int mh, int ny1, int W) {
+  const int gxf = mh / W, rem = mh - gxf * W;
+  return gxf * ny1 + (rem * ny1 + W - 1) / W;
 }
 
 template <typename T, int MB>
 __global__ __launch_bounds__(512) void k_fftz(GridParams g, cplx<T>* __restrict__ spec, FFTPlan pz, int sign,
                                              int W) {
-  k_fftz_body<T, MB>(g, spec, pz, sign, W, blockIdx.x, blockIdx.y, gridDim.x);
+  k_fftz_body<T, MB>(g, spec, pz, sign, W, blockIdx.x);
 }
 
 // The same for a batch of independent grids in one launch (block ranges boff).
@@ -486,7 +508,7 @@ __global__ __launch_bounds__(512) void k_fftz_b(const FftzArgs<T>* __restrict__ 
   const int i = batch_instance(boff, ninst, blockIdx.x);
   const FftzArgs<T>& a = args[i];
   const int local = blockIdx.x - boff[i];
-  k_fftz_body<T, MB>(a.g, a.spec, a.pz, a.sign, a.W, local % a.gx, local / a.gx, boff[i + 1] - boff[i]);
+  k_fftz_body<T, MB>(a.g, a.spec, a.pz, a.sign, a.W, local);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -511,37 +533,35 @@ __device__ __forceinline__ void k_tri_body(GridParams g, cplx<T>* __restrict__ s
                                             int P, int W, double* __restrict__ mean_out, int bid_x, int bid_y, int nblk) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* lds = reinterpret_cast<double*>(smem_raw);
-  const int n = g.ny1, Q = g.nmodes;
+  const int n = g.ny1;
   const int tid = threadIdx.x;
-  const int w = tid % W, p = tid / W;
+  const int p = tid / W, w = tid - p * W;
   const bool active = p < P;
-  const int q = bid_x * W + w;
-  const bool valid = active && q < Q;
-  const int r0 = (int)(((int64_t)p * n) / P);
-  const int r1 = active ? (int)(((int64_t)(p + 1) * n) / P) : r0;
+  // modes in spectrum order (kz*mhs + m, padding included, so that the W modes of a
+  // block are one aligned run); padding modes m >= mh are skipped
+  const int qa = bid_x * W + w;
+  const int kz = qa / g.mhs, m = qa - kz * g.mhs;
+  const bool valid = active && kz < g.nz && m < g.mh;
+  const int r0 = (p * n) / P;   // p n < 2^31 (p <= 256, n < 2049)
+  const int r1 = active ? ((p + 1) * n) / P : r0;
   const int L = r1 - r0;
   const double a = g.idy2;
   const double norm = 1.0 / ((double)g.nx * (double)g.nz);
   const int N2 = 2 * P;
-  double* Rl = lds;                 // [2P][W] reduced system (mode fastest)
-  double* Rd = Rl + W * N2;
-  double* Ru = Rd + W * N2;
+  double* Rl = lds;                 // [2P][W] reduced system (mode fastest), unit diagonal
+  double* Ru = Rl + W * N2;
   double* Rr = Ru + W * N2;
   double* Ri = Rr + W * N2;
   double* red = Ri + W * N2;        // [2P] sums of the (0,0) mode
-  double K2 = 0.0;
-  if (valid) {
-    const int kz = q / g.mh, m = q - kz * g.mh;
-    K2 = kx2[m] + kz2[kz];
-  }
-  const bool zmode = valid && q == 0;
+  const double K2 = valid ? kx2[m] + kz2[kz] : 0.0;
+  const bool zmode = valid && qa == 0;
   double dr[LM], di[LM];
 #pragma unroll
   for (int t = 0; t < LM; ++t) {
     dr[t] = 0.0;
     di[t] = 0.0;
     if (valid && t < L) {
-      const cplx<T> v = spec[(size_t)(r0 + t) * Q + q];
+      const cplx<T> v = spec[(size_t)(r0 + t) * g.splane + qa];
       dr[t] = (double)v.x;
       di[t] = (double)v.y;
     }
@@ -582,19 +602,20 @@ __device__ __forceinline__ void k_tri_body(GridParams g, cplx<T>* __restrict__ s
     di[t] = (di[t] - mi) * norm;
   }
   if (zmode && r0 == 0) { dr[0] = 0.0; di[0] = 0.0; }
-  // downward elimination: rows t >= 1 become al[t] x0 + be[t] x_t + up x_{t+1} = d_t
-  double al[LM], be[LM], ga[LM];
+  // downward elimination: rows t >= 1 become al[t] x0 + be[t] x_t + up x_{t+1} = d_t;
+  // ib[t] = 1 / be[t] also serves the upward sweep and the back substitution
+  double al[LM], ib[LM], ga[LM];
 #pragma unroll
-  for (int t = 0; t < LM; ++t) { al[t] = 0.0; be[t] = 1.0; ga[t] = 0.0; }
+  for (int t = 0; t < LM; ++t) { al[t] = 0.0; ib[t] = 1.0; ga[t] = 0.0; }
   if (valid) {
     al[1] = lo_of(r0 + 1);
-    be[1] = di_of(r0 + 1);
+    ib[1] = 1.0 / di_of(r0 + 1);
 #pragma unroll
     for (int t = 2; t < LM; ++t) {
       if (t < L) {
-        const double m = lo_of(r0 + t) / be[t - 1];
+        const double m = lo_of(r0 + t) * ib[t - 1];
         al[t] = -m * al[t - 1];
-        be[t] = di_of(r0 + t) - m * up_of(r0 + t - 1);
+        ib[t] = 1.0 / (di_of(r0 + t) - m * up_of(r0 + t - 1));
         dr[t] -= m * dr[t - 1];
         di[t] -= m * di[t - 1];
       }
@@ -607,7 +628,7 @@ __device__ __forceinline__ void k_tri_body(GridParams g, cplx<T>* __restrict__ s
 #pragma unroll
       for (int t = LM - 3; t >= 1; --t) {
         if (t <= L - 3) {
-          const double m = up_of(r0 + t) / be[t + 1];
+          const double m = up_of(r0 + t) * ib[t + 1];
           al[t] -= m * al[t + 1];
           ga[t] = -m * ga[t + 1];
           dr[t] -= m * dr[t + 1];
@@ -615,64 +636,60 @@ __device__ __forceinline__ void k_tri_body(GridParams g, cplx<T>* __restrict__ s
         }
       }
     }
-    // reduced equations of F = x_0 and E = x_{L-1}
+    // reduced equations of F = x_0 and E = x_{L-1} (segments hold L >= 2 rows), each
+    // divided by its diagonal
     const int eF = (2 * p) * W + w, eE = eF + W;
-    double dL = dr[0], dLi = di[0];
+    double dL = dr[0], dLi = di[0], alL = 0.0, ibL = 1.0;
 #pragma unroll
     for (int t = 1; t < LM; ++t)
-      if (t == L - 1) { dL = dr[t]; dLi = di[t]; }
-    double alL = 0.0, beL = 1.0;
-#pragma unroll
-    for (int t = 1; t < LM; ++t)
-      if (t == L - 1) { alL = al[t]; beL = be[t]; }
-    Rl[eE] = alL;
-    Rd[eE] = beL;
-    Ru[eE] = up_of(r1 - 1);
-    Rr[eE] = dL;
-    Ri[eE] = dLi;
-    Rl[eF] = lo_of(r0);
+      if (t == L - 1) { dL = dr[t]; dLi = di[t]; alL = al[t]; ibL = ib[t]; }
+    Rl[eE] = alL * ibL;
+    Ru[eE] = up_of(r1 - 1) * ibL;
+    Rr[eE] = dL * ibL;
+    Ri[eE] = dLi * ibL;
+    double dF = di_of(r0), uF = up_of(r0), rF = dr[0], iF = di[0];
     if (L >= 3) {
-      const double m = up_of(r0) / be[1];
-      Rd[eF] = di_of(r0) - m * al[1];
-      Ru[eF] = -m * ga[1];
-      Rr[eF] = dr[0] - m * dr[1];
-      Ri[eF] = di[0] - m * di[1];
-    } else {
-      Rd[eF] = di_of(r0);
-      Ru[eF] = up_of(r0);
-      Rr[eF] = dr[0];
-      Ri[eF] = di[0];
+      const double m = uF * ib[1];
+      dF -= m * al[1];
+      uF = -m * ga[1];
+      rF -= m * dr[1];
+      iF -= m * di[1];
     }
+    const double idF = 1.0 / dF;
+    Rl[eF] = lo_of(r0) * idF;
+    Ru[eF] = uF * idF;
+    Rr[eF] = rF * idF;
+    Ri[eF] = iF * idF;
   }
   __syncthreads();
   // Parallel cyclic reduction of the reduced system: each thread owns rows 2p and 2p+1 of
-  // its mode; at stride s every row eliminates its couplings to rows e-s and e+s.
+  // its mode; at stride s every row eliminates its couplings to rows e-s and e+s and is
+  // divided by its new diagonal, so the right-hand side ends as the solution.
   for (int st = 1; st < N2; st <<= 1) {
-    double nl[2], nd[2], nu[2], nr[2], ni[2];
+    double nl[2], nu[2], nr[2], ni[2];
     if (valid) {
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int e = 2 * p + h;
         const int ie = e * W + w;
-        double l = Rl[ie], d = Rd[ie], u = Ru[ie], r = Rr[ie], im = Ri[ie];
-        double l2 = 0.0, u2 = 0.0;
+        const double l = Rl[ie], u = Ru[ie];
+        double r = Rr[ie], im = Ri[ie], d = 1.0, l2 = 0.0, u2 = 0.0;
         if (e - st >= 0) {
           const int j = (e - st) * W + w;
-          const double k1 = l / Rd[j];
-          l2 = -Rl[j] * k1;
-          d -= Ru[j] * k1;
-          r -= Rr[j] * k1;
-          im -= Ri[j] * k1;
+          l2 = -l * Rl[j];
+          d -= l * Ru[j];
+          r -= l * Rr[j];
+          im -= l * Ri[j];
         }
         if (e + st < N2) {
           const int j = (e + st) * W + w;
-          const double k2 = u / Rd[j];
-          u2 = -Ru[j] * k2;
-          d -= Rl[j] * k2;
-          r -= Rr[j] * k2;
-          im -= Ri[j] * k2;
+          u2 = -u * Ru[j];
+          d -= u * Rl[j];
+          r -= u * Rr[j];
+          im -= u * Ri[j];
         }
-        nl[h] = l2; nd[h] = d; nu[h] = u2; nr[h] = r; ni[h] = im;
+        const double id = 1.0 / d;
+        nl[h] = l2 * id; nu[h] = u2 * id; nr[h] = r * id; ni[h] = im * id;
       }
     }
     __syncthreads();
@@ -680,7 +697,7 @@ __device__ __forceinline__ void k_tri_body(GridParams g, cplx<T>* __restrict__ s
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int ie = (2 * p + h) * W + w;
-        Rl[ie] = nl[h]; Rd[ie] = nd[h]; Ru[ie] = nu[h]; Rr[ie] = nr[h]; Ri[ie] = ni[h];
+        Rl[ie] = nl[h]; Ru[ie] = nu[h]; Rr[ie] = nr[h]; Ri[ie] = ni[h];
       }
     }
     __syncthreads();
@@ -688,11 +705,11 @@ __device__ __forceinline__ void k_tri_body(GridParams g, cplx<T>* __restrict__ s
   double xr_[LM], xi_[LM];
   if (valid) {
     const int eF = (2 * p) * W + w, eE = eF + W;
-    const double Fr = Rr[eF] / Rd[eF], Fi = Ri[eF] / Rd[eF], Er = Rr[eE] / Rd[eE], Ei = Ri[eE] / Rd[eE];
+    const double Fr = Rr[eF], Fi = Ri[eF], Er = Rr[eE], Ei = Ri[eE];
 #pragma unroll
     for (int t = 0; t < LM; ++t) {
-      xr_[t] = (dr[t] - al[t] * Fr - ga[t] * Er) / be[t];
-      xi_[t] = (di[t] - al[t] * Fi - ga[t] * Ei) / be[t];
+      xr_[t] = (dr[t] - al[t] * Fr - ga[t] * Er) * ib[t];
+      xi_[t] = (di[t] - al[t] * Fi - ga[t] * Ei) * ib[t];
       if (t == 0) { xr_[t] = Fr; xi_[t] = Fi; }
       if (t == L - 1) { xr_[t] = Er; xi_[t] = Ei; }
     }
@@ -721,7 +738,7 @@ __device__ __forceinline__ void k_tri_body(GridParams g, cplx<T>* __restrict__ s
   if (valid) {
 #pragma unroll
     for (int t = 0; t < LM; ++t)
-      if (t < L) spec[(size_t)(r0 + t) * Q + q] = cplx<T>{T(xr_[t]), T(xi_[t])};
+      if (t < L) spec[(size_t)(r0 + t) * g.splane + qa] = cplx<T>{T(xr_[t]), T(xi_[t])};
   }
 }
 
@@ -749,19 +766,22 @@ __global__ __launch_bounds__(256) void k_tri_b(const TriArgs<T>* __restrict__ ar
 // ---------------------------------------------------------------------------------------
 template <typename T, int MB>
 __device__ __forceinline__ void k_ifftx_body(GridParams g, const cplx<T>* __restrict__ spec, T* __restrict__ out,
-                                              FFTPlan px, const double2* __restrict__ rtw, int bid_x, int bid_y, int nblk) {
+                                              FFTPlan px, const double2* __restrict__ rtw, int ll, int bid_x, int bid_y, int nblk) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* sm = reinterpret_cast<cplx<T>*>(smem_raw);
   const int N = g.nhalf;
-  const int grp = threadIdx.x / IBM_WAVE, lane = threadIdx.x % IBM_WAVE;
-  const int row = bid_x * 4 + grp;
+  const int RB = blockDim.x >> ll;             // rows per block
+  const int NL = 1 << ll;                      // lanes per row
+  const int grp = threadIdx.x >> ll, lane = threadIdx.x & (NL - 1);
+  const int row = bid_x * RB + grp;
   cplx<T>* A = sm + grp * N;
-  cplx<T>* tw = sm + 4 * N;
+  cplx<T>* tw = sm + RB * N;
   load_twiddles<T>(tw, px, threadIdx.x, blockDim.x);
   const bool valid = row < g.nrows;
   if (valid) {
-    const cplx<T>* in = spec + (size_t)row * g.mh;
-    for (int m = lane; m < N; m += IBM_WAVE) {
+    const int jr = row / g.nz;
+    const cplx<T>* in = spec + (size_t)jr * g.splane + (size_t)(row - jr * g.nz) * g.mhs;
+    for (int m = lane; m < N; m += NL) {
       const cplx<T> X = in[m];
       const cplx<T> Xc = cconj(in[N - m]);
       const cplx<T> s1 = cadd(X, Xc), d1 = csub(X, Xc);
@@ -772,18 +792,18 @@ __device__ __forceinline__ void k_ifftx_body(GridParams g, const cplx<T>* __rest
     }
   }
   __syncthreads();
-  fft_lds<T, MB>(A, 1, px, tw, +1, lane, IBM_WAVE);
+  fft_lds<T, MB>(A, 0, px, tw, +1, lane, NL);
   const cplx<T>* R = A;
   if (valid) {
     const T* Rr = reinterpret_cast<const T*>(R);
-    for (int i = lane; i < g.nx; i += IBM_WAVE) out[(size_t)row * g.nx + i] = Rr[i];
+    for (int i = lane; i < g.nx; i += NL) out[(size_t)row * g.nx + i] = Rr[i];
   }
 }
 
 template <typename T, int MB>
 __global__ __launch_bounds__(256) void k_ifftx(GridParams g, const cplx<T>* __restrict__ spec, T* __restrict__ out,
-                                              FFTPlan px, const double2* __restrict__ rtw) {
-  k_ifftx_body<T, MB>(g, spec, out, px, rtw, blockIdx.x, blockIdx.y, gridDim.x);
+                                              FFTPlan px, const double2* __restrict__ rtw, int ll) {
+  k_ifftx_body<T, MB>(g, spec, out, px, rtw, ll, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
 // The same for a batch of independent grids in one launch (block ranges boff).
@@ -793,7 +813,7 @@ __global__ __launch_bounds__(256) void k_ifftx_b(const IfftxArgs<T>* __restrict_
   const int i = batch_instance(boff, ninst, blockIdx.x);
   const IfftxArgs<T>& a = args[i];
   const int local = blockIdx.x - boff[i];
-  k_ifftx_body<T, MB>(a.g, a.spec, a.out, a.px, a.rtw, local % a.gx, local / a.gx, boff[i + 1] - boff[i]);
+  k_ifftx_body<T, MB>(a.g, a.spec, a.out, a.px, a.rtw, a.ll, local % a.gx, local / a.gx, boff[i + 1] - boff[i]);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -879,17 +899,41 @@ hipError_t launch_cfr_pi(const Fields<T>& f, const IbmLists& L, int stage, doubl
   return hipGetLastError();
 }
 
+// Row geometry of the x transforms (div_fftx, ifftx): 2^ll lanes per row, the fewest (a
+// power of two from 4 to a wavefront) that keep every stage at one butterfly per lane;
+// 256 threads per block, so 256 >> ll rows per block.
+struct XfftShape {
+  int ll, rows, mb;
+  size_t lds;
+};
+template <typename T>
+static XfftShape xfft_shape(const GridParams& g, const FFTPlan& px) {
+  int l = IBM_WAVE;
+  while (l > 4 && fft_max_bfly(px, l / 2) == 1) l >>= 1;
+  XfftShape s;
+  s.ll = __builtin_ctz((unsigned)l);
+  s.rows = 256 / l;
+  s.mb = fft_max_bfly(px, l);
+  s.lds = (size_t)(s.rows + 1) * g.nhalf * sizeof(cplx<T>);   // rows plus the twiddle table
+  return s;
+}
+
 template <typename T>
 hipError_t launch_div_fftx(const GridParams& g, const Fields<T>& f, const IbmLists& L, int stage,
                            const FFTPlan& px, const double2* rtw, double ck_dt, const double* pi, const T* rhs_in,
                            hipStream_t st) {
-  const int RB = 4;
-  const size_t lds = (RB + 1) * (size_t)g.nhalf * sizeof(cplx<T>);
-  const int mb = fft_max_bfly(px, IBM_WAVE);
-  const dim3 grid((g.nrows + RB - 1) / RB), blk(64 * RB);
-  if (mb == 1) hipLaunchKernelGGL((k_div_fftx<T, 1>), grid, blk, lds, st, g, f, L, stage, px, rtw, ck_dt, pi, rhs_in);
-  else if (mb == 2) hipLaunchKernelGGL((k_div_fftx<T, 2>), grid, blk, lds, st, g, f, L, stage, px, rtw, ck_dt, pi, rhs_in);
-  else hipLaunchKernelGGL((k_div_fftx<T, 4>), grid, blk, lds, st, g, f, L, stage, px, rtw, ck_dt, pi, rhs_in);
+  const XfftShape x = xfft_shape<T>(g, px);
+  const int mb = x.mb, ll = x.ll;
+  const size_t lds = x.lds;
+  const void* k = mb == 1 ? (const void*)k_div_fftx<T, 1> : (mb == 2 ? (const void*)k_div_fftx<T, 2> : (const void*)k_div_fftx<T, 4>);
+  if (lds > 65536) {
+    const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  const dim3 grid((g.nrows + x.rows - 1) / x.rows), blk(256);
+  if (mb == 1) hipLaunchKernelGGL((k_div_fftx<T, 1>), grid, blk, lds, st, g, f, L, stage, px, rtw, ck_dt, pi, rhs_in, ll);
+  else if (mb == 2) hipLaunchKernelGGL((k_div_fftx<T, 2>), grid, blk, lds, st, g, f, L, stage, px, rtw, ck_dt, pi, rhs_in, ll);
+  else hipLaunchKernelGGL((k_div_fftx<T, 4>), grid, blk, lds, st, g, f, L, stage, px, rtw, ck_dt, pi, rhs_in, ll);
   return hipGetLastError();
 }
 
@@ -938,7 +982,7 @@ hipError_t launch_fftz(const GridParams& g, cplx<T>* spec, const FFTPlan& pz, in
   const int nt = fftz_threads(pz, W);
   const size_t lds = ((size_t)W + 1) * g.nz * sizeof(cplx<T>);
   const int mb = fft_max_bfly(pz, nt / W);
-  const dim3 grid((g.mh + W - 1) / W, g.ny1);
+  const dim3 grid(fftz_blocks(g.mh, g.ny1, W));
   const void* kfn = mb == 1 ? (const void*)k_fftz<T, 1> : (mb == 2 ? (const void*)k_fftz<T, 2> : (const void*)k_fftz<T, 4>);
   if (lds > 65536) {
     const hipError_t e = hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -959,8 +1003,8 @@ hipError_t launch_tri(const GridParams& g, cplx<T>* spec, const double* kx2, con
   if (P > n / 2) P = n / 2 > 0 ? n / 2 : 1;  // ... and at least 2
   if (P > 256) P = 256;
   const int W = 256 / P;                     // modes per block
-  const size_t lds = (size_t)(5 * W * 2 * P + 2 * P) * sizeof(double);
-  const dim3 grid((g.nmodes + W - 1) / W);
+  const size_t lds = (size_t)(4 * W * 2 * P + 2 * P) * sizeof(double);
+  const dim3 grid((g.nz * g.mhs + W - 1) / W);
   if (L == 4 && (n + P - 1) / P <= 4)
     hipLaunchKernelGGL((k_tri<T, 4>), grid, dim3(256), lds, st, g, spec, kx2, kz2, P, W, mean_out);
   else
@@ -971,12 +1015,18 @@ hipError_t launch_tri(const GridParams& g, cplx<T>* spec, const double* kx2, con
 template <typename T>
 hipError_t launch_ifftx(const GridParams& g, const cplx<T>* spec, T* out, const FFTPlan& px, const double2* rtw,
                         hipStream_t st) {
-  const size_t lds = (4 + 1) * (size_t)g.nhalf * sizeof(cplx<T>);
-  const int mb = fft_max_bfly(px, IBM_WAVE);
-  const dim3 grid((g.nrows + 3) / 4);
-  if (mb == 1) hipLaunchKernelGGL((k_ifftx<T, 1>), grid, dim3(256), lds, st, g, spec, out, px, rtw);
-  else if (mb == 2) hipLaunchKernelGGL((k_ifftx<T, 2>), grid, dim3(256), lds, st, g, spec, out, px, rtw);
-  else hipLaunchKernelGGL((k_ifftx<T, 4>), grid, dim3(256), lds, st, g, spec, out, px, rtw);
+  const XfftShape x = xfft_shape<T>(g, px);
+  const int mb = x.mb, ll = x.ll;
+  const size_t lds = x.lds;
+  const void* k = mb == 1 ? (const void*)k_ifftx<T, 1> : (mb == 2 ? (const void*)k_ifftx<T, 2> : (const void*)k_ifftx<T, 4>);
+  if (lds > 65536) {
+    const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  const dim3 grid((g.nrows + x.rows - 1) / x.rows);
+  if (mb == 1) hipLaunchKernelGGL((k_ifftx<T, 1>), grid, dim3(256), lds, st, g, spec, out, px, rtw, ll);
+  else if (mb == 2) hipLaunchKernelGGL((k_ifftx<T, 2>), grid, dim3(256), lds, st, g, spec, out, px, rtw, ll);
+  else hipLaunchKernelGGL((k_ifftx<T, 4>), grid, dim3(256), lds, st, g, spec, out, px, rtw, ll);
   return hipGetLastError();
 }
 
@@ -1025,11 +1075,11 @@ int plan_cfr_pi(const Fields<T>& f, const IbmLists& L, int stage, double ck_dt, 
 template <typename T>
 int plan_div_fftx(const GridParams& g, const Fields<T>& f, const IbmLists& L, int stage, const FFTPlan& px,
                   const double2* rtw, double ck_dt, const double* pi, DivArgs<T>* a, int* mb, size_t* lds) {
-  const int RB = 4;
-  const int nb = (g.nrows + RB - 1) / RB;
-  *a = DivArgs<T>{g, f, L, stage, px, rtw, ck_dt, pi, (const T*)nullptr, nb};
-  *mb = fft_max_bfly(px, IBM_WAVE);
-  *lds = (RB + 1) * (size_t)g.nhalf * sizeof(cplx<T>);
+  const XfftShape x = xfft_shape<T>(g, px);
+  const int nb = (g.nrows + x.rows - 1) / x.rows;
+  *a = DivArgs<T>{g, f, L, stage, px, rtw, ck_dt, pi, (const T*)nullptr, x.ll, nb};
+  *mb = x.mb;
+  *lds = x.lds;
   return nb;
 }
 
@@ -1038,12 +1088,12 @@ int plan_fftz(const GridParams& g, cplx<T>* spec, const FFTPlan& pz, int sign, c
               int* mb, size_t* lds, int* threads) {
   const int W = fftz_width<T>(g, pz, tu);
   const int nt = fftz_threads(pz, W);
-  const int gx = (g.mh + W - 1) / W;
-  *a = FftzArgs<T>{g, spec, pz, sign, W, gx};
+  const int nb = fftz_blocks(g.mh, g.ny1, W);
+  *a = FftzArgs<T>{g, spec, pz, sign, W, nb};
   *mb = fft_max_bfly(pz, nt / W);
   *lds = ((size_t)W + 1) * g.nz * sizeof(cplx<T>);
   *threads = nt;
-  return gx * g.ny1;
+  return nb;
 }
 
 template <typename T>
@@ -1055,20 +1105,21 @@ int plan_tri(const GridParams& g, cplx<T>* spec, const double* kx2, const double
   if (P > n / 2) P = n / 2 > 0 ? n / 2 : 1;
   if (P > 256) P = 256;
   const int W = 256 / P;
-  const int nb = (g.nmodes + W - 1) / W;
+  const int nb = (g.nz * g.mhs + W - 1) / W;
   *a = TriArgs<T>{g, spec, kx2, kz2, P, W, mean_out, nb};
   *lm = (L == 4 && (n + P - 1) / P <= 4) ? 4 : 8;
-  *lds = (size_t)(5 * W * 2 * P + 2 * P) * sizeof(double);
+  *lds = (size_t)(4 * W * 2 * P + 2 * P) * sizeof(double);
   return nb;
 }
 
 template <typename T>
 int plan_ifftx(const GridParams& g, const cplx<T>* spec, T* out, const FFTPlan& px, const double2* rtw,
                IfftxArgs<T>* a, int* mb, size_t* lds) {
-  const int nb = (g.nrows + 3) / 4;
-  *a = IfftxArgs<T>{g, spec, out, px, rtw, nb};
-  *mb = fft_max_bfly(px, IBM_WAVE);
-  *lds = (4 + 1) * (size_t)g.nhalf * sizeof(cplx<T>);
+  const XfftShape x = xfft_shape<T>(g, px);
+  const int nb = (g.nrows + x.rows - 1) / x.rows;
+  *a = IfftxArgs<T>{g, spec, out, px, rtw, x.ll, nb};
+  *mb = x.mb;
+  *lds = x.lds;
   return nb;
 }
 
