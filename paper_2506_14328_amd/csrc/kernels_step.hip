@@ -527,6 +527,20 @@ __global__ __launch_bounds__(512) void k_fftz_b(const FftzArgs<T>* __restrict__ 
 // in LDS; each thread then recovers its interior rows.  The spectrum is read once
 // and written once.  W = 256/P modes per block, lane = p * W + w.
 // ---------------------------------------------------------------------------------------
+// 1/x (x normal, not tiny): the hardware reciprocal estimate refined by two Newton steps,
+// each of which squares the relative error, to full FP64 accuracy.
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+
+// Row stride (in doubles) of the reduced-system arrays: W padded so that the four
+// segment groups of a wavefront fall into alternate halves of the LDS banks.
+__host__ __device__ inline int tri_rs(int W) { return W + ((8 - W % 16) + 16) % 16; }
+
 template <typename T, int LM>
 __device__ __forceinline__ void k_tri_body(GridParams g, cplx<T>* __restrict__ spec,
                                             const double* __restrict__ kx2, const double* __restrict__ kz2,
@@ -548,11 +562,12 @@ __device__ __forceinline__ void k_tri_body(GridParams g, cplx<T>* __restrict__ s
   const double a = g.idy2;
   const double norm = 1.0 / ((double)g.nx * (double)g.nz);
   const int N2 = 2 * P;
-  double* Rl = lds;                 // [2P][W] reduced system (mode fastest), unit diagonal
-  double* Ru = Rl + W * N2;
-  double* Rr = Ru + W * N2;
-  double* Ri = Rr + W * N2;
-  double* red = Ri + W * N2;        // [2P] sums of the (0,0) mode
+  const int RS = tri_rs(W);
+  double* Rl = lds;                 // [2P][RS] reduced system (mode fastest), unit diagonal
+  double* Ru = Rl + RS * N2;
+  double* Rr = Ru + RS * N2;
+  double* Ri = Rr + RS * N2;
+  double* red = Ri + RS * N2;       // [2P] sums of the (0,0) mode
   const double K2 = valid ? kx2[m] + kz2[kz] : 0.0;
   const bool zmode = valid && qa == 0;
   double dr[LM], di[LM];
@@ -609,13 +624,13 @@ __device__ __forceinline__ void k_tri_body(GridParams g, cplx<T>* __restrict__ s
   for (int t = 0; t < LM; ++t) { al[t] = 0.0; ib[t] = 1.0; ga[t] = 0.0; }
   if (valid) {
     al[1] = lo_of(r0 + 1);
-    ib[1] = 1.0 / di_of(r0 + 1);
+    ib[1] = recip(di_of(r0 + 1));
 #pragma unroll
     for (int t = 2; t < LM; ++t) {
       if (t < L) {
         const double m = lo_of(r0 + t) * ib[t - 1];
         al[t] = -m * al[t - 1];
-        ib[t] = 1.0 / (di_of(r0 + t) - m * up_of(r0 + t - 1));
+        ib[t] = recip(di_of(r0 + t) - m * up_of(r0 + t - 1));
         dr[t] -= m * dr[t - 1];
         di[t] -= m * di[t - 1];
       }
@@ -638,7 +653,7 @@ __device__ __forceinline__ void k_tri_body(GridParams g, cplx<T>* __restrict__ s
     }
     // reduced equations of F = x_0 and E = x_{L-1} (segments hold L >= 2 rows), each
     // divided by its diagonal
-    const int eF = (2 * p) * W + w, eE = eF + W;
+    const int eF = (2 * p) * RS + w, eE = eF + RS;
     double dL = dr[0], dLi = di[0], alL = 0.0, ibL = 1.0;
 #pragma unroll
     for (int t = 1; t < LM; ++t)
@@ -655,7 +670,7 @@ __device__ __forceinline__ void k_tri_body(GridParams g, cplx<T>* __restrict__ s
       rF -= m * dr[1];
       iF -= m * di[1];
     }
-    const double idF = 1.0 / dF;
+    const double idF = recip(dF);
     Rl[eF] = lo_of(r0) * idF;
     Ru[eF] = uF * idF;
     Rr[eF] = rF * idF;
@@ -671,24 +686,24 @@ __device__ __forceinline__ void k_tri_body(GridParams g, cplx<T>* __restrict__ s
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int e = 2 * p + h;
-        const int ie = e * W + w;
+        const int ie = e * RS + w;
         const double l = Rl[ie], u = Ru[ie];
         double r = Rr[ie], im = Ri[ie], d = 1.0, l2 = 0.0, u2 = 0.0;
         if (e - st >= 0) {
-          const int j = (e - st) * W + w;
+          const int j = (e - st) * RS + w;
           l2 = -l * Rl[j];
           d -= l * Ru[j];
           r -= l * Rr[j];
           im -= l * Ri[j];
         }
         if (e + st < N2) {
-          const int j = (e + st) * W + w;
+          const int j = (e + st) * RS + w;
           u2 = -u * Ru[j];
           d -= u * Rl[j];
           r -= u * Rr[j];
           im -= u * Ri[j];
         }
-        const double id = 1.0 / d;
+        const double id = recip(d);
         nl[h] = l2 * id; nu[h] = u2 * id; nr[h] = r * id; ni[h] = im * id;
       }
     }
@@ -696,7 +711,7 @@ __device__ __forceinline__ void k_tri_body(GridParams g, cplx<T>* __restrict__ s
     if (valid) {
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        const int ie = (2 * p + h) * W + w;
+        const int ie = (2 * p + h) * RS + w;
         Rl[ie] = nl[h]; Ru[ie] = nu[h]; Rr[ie] = nr[h]; Ri[ie] = ni[h];
       }
     }
@@ -704,7 +719,7 @@ __device__ __forceinline__ void k_tri_body(GridParams g, cplx<T>* __restrict__ s
   }
   double xr_[LM], xi_[LM];
   if (valid) {
-    const int eF = (2 * p) * W + w, eE = eF + W;
+    const int eF = (2 * p) * RS + w, eE = eF + RS;
     const double Fr = Rr[eF], Fi = Ri[eF], Er = Rr[eE], Ei = Ri[eE];
 #pragma unroll
     for (int t = 0; t < LM; ++t) {
@@ -1003,7 +1018,7 @@ hipError_t launch_tri(const GridParams& g, cplx<T>* spec, const double* kx2, con
   if (P > n / 2) P = n / 2 > 0 ? n / 2 : 1;  // ... and at least 2
   if (P > 256) P = 256;
   const int W = 256 / P;                     // modes per block
-  const size_t lds = (size_t)(4 * W * 2 * P + 2 * P) * sizeof(double);
+  const size_t lds = (size_t)(4 * tri_rs(W) * 2 * P + 2 * P) * sizeof(double);
   const dim3 grid((g.nz * g.mhs + W - 1) / W);
   if (L == 4 && (n + P - 1) / P <= 4)
     hipLaunchKernelGGL((k_tri<T, 4>), grid, dim3(256), lds, st, g, spec, kx2, kz2, P, W, mean_out);
@@ -1108,7 +1123,7 @@ int plan_tri(const GridParams& g, cplx<T>* spec, const double* kx2, const double
   const int nb = (g.nz * g.mhs + W - 1) / W;
   *a = TriArgs<T>{g, spec, kx2, kz2, P, W, mean_out, nb};
   *lm = (L == 4 && (n + P - 1) / P <= 4) ? 4 : 8;
-  *lds = (size_t)(4 * W * 2 * P + 2 * P) * sizeof(double);
+  *lds = (size_t)(4 * tri_rs(W) * 2 * P + 2 * P) * sizeof(double);
   return nb;
 }
 
