@@ -43,20 +43,31 @@ __device__ __forceinline__ int batch_instance(const int* __restrict__ boff, int 
 //
 // A block owns a 64 x 4 (x, z) column of cells and marches through a chunk of y
 // planes.  u, v, w, p live in a ring of four LDS planes (j-1, j, j+1 and the one being
-// filled) with a one-cell halo in x and z.  The loads of plane j+2 are issued before the arithmetic of plane j
-// and their corrected values written to the ring slot of plane j-1 afterwards.  Planes
-// outside the box (ghost rows, the north wall face of v) are zero.
+// filled) with a halo of one row in z and two columns in x (so that the tile is made of
+// whole, aligned pairs of x-adjacent values: every thread loads one pair of each field
+// with one vector load).  The loads of plane j+2 are issued before the arithmetic of
+// plane j and their corrected values written to the ring slot of plane j-2 afterwards.
+// Planes outside the box (ghost rows, the north wall face of v) are zero.
 // ---------------------------------------------------------------------------------------
 constexpr int MX = 64, MZ = 4;
-constexpr int MHX = MX + 2, MHZ = MZ + 2, MTILE = MHX * MHZ;   // 396 values per plane tile
-constexpr int MLOADS = (MTILE + 255) / 256;                     // tile values per thread
+constexpr int MHX = MX + 4, MHZ = MZ + 2, MTILE = MHX * MHZ;   // 408 values per plane tile
+constexpr int MPAIRS = MTILE / 2;                               // 204 pairs, one per thread
+static_assert(MPAIRS <= MX * MZ, "one tile pair per thread");
 
-// Loaded inputs of one tile value: previous predictor, previous pressure, phi and its
-// west, back and south neighbours, tag.
+template <typename T>
+struct alignas(2 * sizeof(T)) Pair {
+  T x, y;
+};
+template <typename T>
+__device__ __forceinline__ Pair<T> ld_pair(const T* p) { return *reinterpret_cast<const Pair<T>*>(p); }
+
+// Loaded inputs of one pair of x-adjacent tile values (x, x+1): previous predictor,
+// previous pressure, phi, phi at x-2 and x-1 (the west neighbours), phi of the back row
+// and of the plane below, the two tags (x in the low byte).
 template <typename T>
 struct TileRaw {
-  T us, vs, ws, pp, ph, phx, phz, phy;
-  uint8_t tg;
+  Pair<T> us, vs, ws, pp, ph, phw, phz, phy;
+  uint16_t tg;
 };
 
 // The 1-D grid's blocks are dealt round-robin to the 8 XCDs (block b to XCD b mod 8, each
@@ -71,7 +82,7 @@ template <typename T>
 __device__ __forceinline__ void k_momentum_body(GridParams g, Fields<T> f, IbmLists L, StageConsts s, int jc,
                                                  int ntx, int ntz, int xcd_order, const double* __restrict__ pi_prev,
                                                  double ckdt_prev, double* __restrict__ qpart, int bid_x, int bid_y, int nblk) {
-  __shared__ T ring[4][4][MTILE];   // [field u,v,w,p][slot][tile]
+  __shared__ __align__(16) T ring[4][4][MTILE];   // [field u,v,w,p][slot][tile]
   __shared__ double red[4];
   const int tx = threadIdx.x, tz = threadIdx.y, tid = tz * MX + tx;
   const int nx = g.nx, nz = g.nz, ny1 = g.ny1, plane = nx * nz;
@@ -89,69 +100,83 @@ __device__ __forceinline__ void k_momentum_body(GridParams g, Fields<T> f, IbmLi
   const int j1 = min(j0 + jc, ny1);
   const int i = i0 + tx, k = k0 + tz;
   const bool act = (i < nx) && (k < nz);
-  // tile element -> offsets inside a plane (periodic wrap in x and z) of itself and of
-  // its west (x-1) and back (z-1) neighbours
-  int off[MLOADS];
-  bool has[MLOADS], wx0[MLOADS], wz0[MLOADS];   // tile value exists; its x (z) index is 0
-#pragma unroll
-  for (int r = 0; r < MLOADS; ++r) {
-    const int e = tid + 256 * r;
-    has[r] = e < MTILE;
-    const int lz = e / MHX, lx = e - lz * MHX;
+  // this thread's tile pair -> offsets inside a plane (periodic wrap in x and z) of itself,
+  // of the pair west of it and of the pair in the back row; threads past the tile repeat
+  // the last pair's loads (cache hits) and write nothing
+  const bool has = tid < MPAIRS;
+  int off, offw, offb;
+  {
+    const int pidx = has ? tid : MPAIRS - 1;
+    const int lz = pidx / (MHX / 2), lx = 2 * (pidx - lz * (MHX / 2));
     int gz = (k0 - 1 + lz) % nz;
     if (gz < 0) gz += nz;
-    int gx = (i0 - 1 + lx) % nx;
+    int gx = (i0 - 2 + lx) % nx;   // even: nx is even
     if (gx < 0) gx += nx;
-    off[r] = gz * nx + gx;
-    wx0[r] = gx == 0;
-    wz0[r] = gz == 0;
+    off = gz * nx + gx;
+    offw = gz * nx + (gx == 0 ? nx - 2 : gx - 2);
+    offb = (gz == 0 ? nz - 1 : gz - 1) * nx + gx;
   }
   const T pick = T(pi_prev[0] * ckdt_prev), ckp = T(ckdt_prev);
   const T idx = T(g.idx), idy = T(g.idy), idz = T(g.idz);
-  // phi of the plane below each of this thread's tile values (the v correction's
-  // south neighbour) is kept from the previous plane instead of being loaded again;
-  // only the first plane of the prologue loads it (with_phy).
-  T phprev[MLOADS];
-  auto fetch = [&](int jj, TileRaw<T>* q, bool with_phy) {
-#pragma unroll
-    for (int r = 0; r < MLOADS; ++r) {
-      q[r] = TileRaw<T>{T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0), 0};
-      if (has[r] && jj >= 0 && jj < ny1) {
-        const int b = jj * plane;
-        q[r].us = f.usp[b + off[r]];
-        q[r].vs = f.vsp[b + off[r]];
-        q[r].ws = f.wsp[b + off[r]];
-        q[r].pp = f.pp[b + off[r]];
-        q[r].ph = f.phi[b + off[r]];
-        q[r].phx = f.phi[b + off[r] + (wx0[r] ? nx - 1 : -1)];
-        q[r].phz = f.phi[b + off[r] + (wz0[r] ? plane - nx : -nx)];
-        if (with_phy) q[r].phy = jj > 0 ? f.phi[b - plane + off[r]] : T(0);
-        q[r].tg = f.tag[b + off[r]];
-      }
-    }
+  // phi of the plane below this thread's pair (the v correction's south neighbour) is
+  // kept from the previous plane instead of being loaded again; only the first plane of
+  // the prologue loads it (with_phy).
+  Pair<T> phprev = {T(0), T(0)};
+  // The loads are unconditional (a plane outside the box reads the nearest one and a zero
+  // tag then zeroes the values): without branches around them the compiler can count
+  // them, so that waiting for loads issued earlier does not wait for these.
+  auto fetch = [&](int jj, TileRaw<T>& q, bool with_phy) {
+    const bool inb = jj >= 0 && jj < ny1;
+    const int b = (jj < 0 ? 0 : (jj < ny1 ? jj : ny1 - 1)) * plane;
+    q.us = ld_pair(f.usp + b + off);
+    q.vs = ld_pair(f.vsp + b + off);
+    q.ws = ld_pair(f.wsp + b + off);
+    q.pp = ld_pair(f.pp + b + off);
+    q.ph = ld_pair(f.phi + b + off);
+    q.phw = ld_pair(f.phi + b + offw);
+    q.phz = ld_pair(f.phi + b + offb);
+    q.phy = Pair<T>{T(0), T(0)};
+    if (with_phy && inb && jj > 0) q.phy = ld_pair(f.phi + b - plane + off);
+    const uint16_t t = *reinterpret_cast<const uint16_t*>(f.tag + b + off);
+    q.tg = inb ? t : uint16_t(0);
   };
-  // corrected state of the fetched values into ring slot sl
-  auto put = [&](int sl, const TileRaw<T>* q, bool with_phy) {
-#pragma unroll
-    for (int r = 0; r < MLOADS; ++r)
-      if (has[r]) {
-        const TileRaw<T>& a = q[r];
-        const int e = tid + 256 * r;
-        const T phy = with_phy ? a.phy : phprev[r];
-        const T pk = ((a.tg & (TAG_U | TAG_UI)) == TAG_U) ? pick : T(0);
-        ring[0][sl][e] = (a.tg & TAG_U) ? a.us - pk - ckp * ((a.ph - a.phx) * idx) : T(0);
-        ring[1][sl][e] = (a.tg & TAG_V) ? a.vs - ckp * ((a.ph - phy) * idy) : T(0);
-        ring[2][sl][e] = (a.tg & TAG_W) ? a.ws - ckp * ((a.ph - a.phz) * idz) : T(0);
-        ring[3][sl][e] = (a.tg & TAG_P) ? a.pp + a.ph : T(0);
-        phprev[r] = a.ph;
-      }
+  // corrected state of one fetched value (tag tg, its phi and west/back/south phi)
+  auto corr = [&](int fld, uint8_t tg, T val, T ph, T phx, T phz, T phy) -> T {
+    if (fld == 0) {
+      const T pk = ((tg & (TAG_U | TAG_UI)) == TAG_U) ? pick : T(0);
+      return (tg & TAG_U) ? val - pk - ckp * ((ph - phx) * idx) : T(0);
+    }
+    if (fld == 1) return (tg & TAG_V) ? val - ckp * ((ph - phy) * idy) : T(0);
+    if (fld == 2) return (tg & TAG_W) ? val - ckp * ((ph - phz) * idz) : T(0);
+    return (tg & TAG_P) ? val + ph : T(0);
+  };
+  // corrected state of the fetched pair into ring slot sl
+  auto put = [&](int sl, const TileRaw<T>& a, bool with_phy) {
+    if (has) {
+      const int e = 2 * tid;   // tile index of the pair's first value
+      const Pair<T> phy = with_phy ? a.phy : phprev;   // a plane outside the box has tag 0
+      const uint8_t t0 = uint8_t(a.tg & 0xff), t1 = uint8_t(a.tg >> 8);
+      const Pair<T> cu = {corr(0, t0, a.us.x, a.ph.x, a.phw.y, a.phz.x, phy.x),
+                          corr(0, t1, a.us.y, a.ph.y, a.ph.x, a.phz.y, phy.y)};
+      const Pair<T> cv = {corr(1, t0, a.vs.x, a.ph.x, a.phw.y, a.phz.x, phy.x),
+                          corr(1, t1, a.vs.y, a.ph.y, a.ph.x, a.phz.y, phy.y)};
+      const Pair<T> cw = {corr(2, t0, a.ws.x, a.ph.x, a.phw.y, a.phz.x, phy.x),
+                          corr(2, t1, a.ws.y, a.ph.y, a.ph.x, a.phz.y, phy.y)};
+      const Pair<T> cp = {corr(3, t0, a.pp.x, a.ph.x, a.phw.y, a.phz.x, phy.x),
+                          corr(3, t1, a.pp.y, a.ph.y, a.ph.x, a.phz.y, phy.y)};
+      *reinterpret_cast<Pair<T>*>(&ring[0][sl][e]) = cu;
+      *reinterpret_cast<Pair<T>*>(&ring[1][sl][e]) = cv;
+      *reinterpret_cast<Pair<T>*>(&ring[2][sl][e]) = cw;
+      *reinterpret_cast<Pair<T>*>(&ring[3][sl][e]) = cp;
+      phprev = a.ph;
+    }
   };
   // four slots: plane j+2 goes to the slot of plane j-2, which no wave reads any more
   // once the barrier closing the previous plane has passed, so one barrier per plane
   auto slot = [](int jj) { return (jj + 4) & 3; };
   // prologue: planes j0-1, j0, j0+1
   {
-    TileRaw<T> q0[MLOADS], q1[MLOADS], q2[MLOADS];
+    TileRaw<T> q0, q1, q2;
     fetch(j0 - 1, q0, true);
     fetch(j0, q1, false);
     fetch(j0 + 1, q2, false);
@@ -159,7 +184,7 @@ __device__ __forceinline__ void k_momentum_body(GridParams g, Fields<T> f, IbmLi
     put(slot(j0), q1, false);
     put(slot(j0 + 1), q2, false);
   }
-  const int cc = (tz + 1) * MHX + (tx + 1);   // centre inside a tile
+  const int cc = (tz + 1) * MHX + (tx + 2);   // centre inside a tile
   __syncthreads();
 
   const T h = T(0.5), two = T(2), zero = T(0);
@@ -168,11 +193,13 @@ __device__ __forceinline__ void k_momentum_body(GridParams g, Fields<T> f, IbmLi
   double qloc = 0.0;
 
   for (int j = j0; j < j1; ++j) {
-    // prefetch plane j+2
-    TileRaw<T> nq[MLOADS];
-    fetch(j + 2, nq, false);
+    // this point's own loads first: loads complete in issue order, so waiting for these
+    // does not wait for the prefetch issued after them.  The tag and the list offsets of
+    // the immersed-boundary points of this 64-wide row chunk are loaded unconditionally
+    // (clamped into the box), so that the loads after them can be counted.
     const int c = j * plane + k * nx + i;
-    const uint8_t tg = act ? f.tag[c] : 0;
+    const int kc = k < nz ? k : nz - 1;
+    const uint8_t tgl = f.tag[j * plane + kc * nx + (i < nx ? i : nx - 1)];
     T hu = zero, hv = zero, hw = zero;
     if (act) {
       if (s.use_hold) {
@@ -181,6 +208,13 @@ __device__ __forceinline__ void k_momentum_body(GridParams g, Fields<T> f, IbmLi
         hw = f.Hw[c];
       }
     }
+    const int ch = (j * nz + kc) * L.cpr + bx;
+    const int chu = L.choff_u[ch], chv = L.choff_v[ch], chw = L.choff_w[ch];
+    __builtin_amdgcn_sched_barrier(0);   // keep the loads above ahead of the prefetch
+    // prefetch plane j+2
+    TileRaw<T> nq;
+    fetch(j + 2, nq, false);
+    const uint8_t tg = act ? tgl : uint8_t(0);
     const T* U0 = ring[0][slot(j)];
     const T* Um = ring[0][slot(j - 1)];
     const T* Up = ring[0][slot(j + 1)];
@@ -253,20 +287,15 @@ __device__ __forceinline__ void k_momentum_body(GridParams g, Fields<T> f, IbmLi
       if (tg & TAG_V) sv = vc + rv;
       if (tg & TAG_W) sw = wc + rw;
       if (tg & (TAG_UI | TAG_VI | TAG_WI)) {
-        const int ch = (j * nz + k) * L.cpr + bx;
+        // the three coefficient loads are issued together: one wait for all of them
         const size_t cb = (size_t)s.stage * L.n_total;
-        if (tg & TAG_UI) {
-          const double2 cf = L.coef[cb + L.choff_u[ch] + lanes_below(mu, tx)];
-          su = T((cf.x * (double)uc + (double)ru) * cf.y);
-        }
-        if (tg & TAG_VI) {
-          const double2 cf = L.coef[cb + L.n_u + L.choff_v[ch] + lanes_below(mv, tx)];
-          sv = T((cf.x * (double)vc + (double)rv) * cf.y);
-        }
-        if (tg & TAG_WI) {
-          const double2 cf = L.coef[cb + L.n_u + L.n_v + L.choff_w[ch] + lanes_below(mw, tx)];
-          sw = T((cf.x * (double)wc + (double)rw) * cf.y);
-        }
+        double2 cfu = {0.0, 0.0}, cfv = {0.0, 0.0}, cfw = {0.0, 0.0};
+        if (tg & TAG_UI) cfu = L.coef[cb + chu + lanes_below(mu, tx)];
+        if (tg & TAG_VI) cfv = L.coef[cb + L.n_u + chv + lanes_below(mv, tx)];
+        if (tg & TAG_WI) cfw = L.coef[cb + L.n_u + L.n_v + chw + lanes_below(mw, tx)];
+        if (tg & TAG_UI) su = T((cfu.x * (double)uc + (double)ru) * cfu.y);
+        if (tg & TAG_VI) sv = T((cfv.x * (double)vc + (double)rv) * cfv.y);
+        if (tg & TAG_WI) sw = T((cfw.x * (double)wc + (double)rw) * cfw.y);
       }
       f.us[c] = su;
       f.vs[c] = sv;
