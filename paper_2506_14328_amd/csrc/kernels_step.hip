@@ -192,14 +192,32 @@ __device__ __forceinline__ void k_momentum_body(GridParams g, Fields<T> f, IbmLi
   const T akdt = T(s.ak_dt), bkdt = T(s.bk_dt), ckdt = T(s.ck_dt);
   double qloc = 0.0;
 
+  // This point's tag and the list offsets of the immersed-boundary points of its 64-wide
+  // row chunk are loaded one plane ahead (clamped into the box), so that the coefficient
+  // loads of a plane can be issued before its prefetch: loads complete in issue order, and
+  // waiting for loads issued before the prefetch does not wait for the prefetch.
+  const int kc = k < nz ? k : nz - 1, icl = i < nx ? i : nx - 1;
+  uint8_t tgn = f.tag[j0 * plane + kc * nx + icl];
+  int chn_u, chn_v, chn_w;
+  {
+    const int ch = (j0 * nz + kc) * L.cpr + bx;
+    chn_u = L.choff_u[ch];
+    chn_v = L.choff_v[ch];
+    chn_w = L.choff_w[ch];
+  }
   for (int j = j0; j < j1; ++j) {
-    // this point's own loads first: loads complete in issue order, so waiting for these
-    // does not wait for the prefetch issued after them.  The tag and the list offsets of
-    // the immersed-boundary points of this 64-wide row chunk are loaded unconditionally
-    // (clamped into the box), so that the loads after them can be counted.
     const int c = j * plane + k * nx + i;
-    const int kc = k < nz ? k : nz - 1;
-    const uint8_t tgl = f.tag[j * plane + kc * nx + (i < nx ? i : nx - 1)];
+    const uint8_t tg = act ? tgn : uint8_t(0);
+    // immersed-boundary points: list index = chunk offset + flagged lanes below (the
+    // wavefront is the 64-wide chunk bx of row j*nz + k); (B, 1/A) of this point
+    const uint64_t mu = __ballot((tg & TAG_UI) != 0);
+    const uint64_t mv = __ballot((tg & TAG_VI) != 0);
+    const uint64_t mw = __ballot((tg & TAG_WI) != 0);
+    const size_t cb = (size_t)s.stage * L.n_total;
+    double2 cfu = {0.0, 0.0}, cfv = {0.0, 0.0}, cfw = {0.0, 0.0};
+    if (tg & TAG_UI) cfu = L.coef[cb + chn_u + lanes_below(mu, tx)];
+    if (tg & TAG_VI) cfv = L.coef[cb + L.n_u + chn_v + lanes_below(mv, tx)];
+    if (tg & TAG_WI) cfw = L.coef[cb + L.n_u + L.n_v + chn_w + lanes_below(mw, tx)];
     T hu = zero, hv = zero, hw = zero;
     if (act) {
       if (s.use_hold) {
@@ -208,13 +226,18 @@ __device__ __forceinline__ void k_momentum_body(GridParams g, Fields<T> f, IbmLi
         hw = f.Hw[c];
       }
     }
-    const int ch = (j * nz + kc) * L.cpr + bx;
-    const int chu = L.choff_u[ch], chv = L.choff_v[ch], chw = L.choff_w[ch];
     __builtin_amdgcn_sched_barrier(0);   // keep the loads above ahead of the prefetch
     // prefetch plane j+2
     TileRaw<T> nq;
     fetch(j + 2, nq, false);
-    const uint8_t tg = act ? tgl : uint8_t(0);
+    {
+      const int jn = j + 1 < ny1 ? j + 1 : ny1 - 1;
+      tgn = f.tag[jn * plane + kc * nx + icl];
+      const int ch = (jn * nz + kc) * L.cpr + bx;
+      chn_u = L.choff_u[ch];
+      chn_v = L.choff_v[ch];
+      chn_w = L.choff_w[ch];
+    }
     const T* U0 = ring[0][slot(j)];
     const T* Um = ring[0][slot(j - 1)];
     const T* Up = ring[0][slot(j + 1)];
@@ -271,11 +294,6 @@ __device__ __forceinline__ void k_momentum_body(GridParams g, Fields<T> f, IbmLi
       rw = akdt * Hw - ckdt * ((pc - pb) * idz);
       if (s.use_hold) rw += bkdt * hw;
     }
-    // immersed-boundary points: list index = chunk offset + flagged lanes below (the
-    // wavefront is the 64-wide chunk bx of row j*nz + k)
-    const uint64_t mu = __ballot((tg & TAG_UI) != 0);
-    const uint64_t mv = __ballot((tg & TAG_VI) != 0);
-    const uint64_t mw = __ballot((tg & TAG_WI) != 0);
     if (act) {
       if (s.write_h) {
         f.Hu[c] = Hu;
@@ -286,17 +304,9 @@ __device__ __forceinline__ void k_momentum_body(GridParams g, Fields<T> f, IbmLi
       if (tg & TAG_U) su = uc + ru;
       if (tg & TAG_V) sv = vc + rv;
       if (tg & TAG_W) sw = wc + rw;
-      if (tg & (TAG_UI | TAG_VI | TAG_WI)) {
-        // the three coefficient loads are issued together: one wait for all of them
-        const size_t cb = (size_t)s.stage * L.n_total;
-        double2 cfu = {0.0, 0.0}, cfv = {0.0, 0.0}, cfw = {0.0, 0.0};
-        if (tg & TAG_UI) cfu = L.coef[cb + chu + lanes_below(mu, tx)];
-        if (tg & TAG_VI) cfv = L.coef[cb + L.n_u + chv + lanes_below(mv, tx)];
-        if (tg & TAG_WI) cfw = L.coef[cb + L.n_u + L.n_v + chw + lanes_below(mw, tx)];
-        if (tg & TAG_UI) su = T((cfu.x * (double)uc + (double)ru) * cfu.y);
-        if (tg & TAG_VI) sv = T((cfv.x * (double)vc + (double)rv) * cfv.y);
-        if (tg & TAG_WI) sw = T((cfw.x * (double)wc + (double)rw) * cfw.y);
-      }
+      if (tg & TAG_UI) su = T((cfu.x * (double)uc + (double)ru) * cfu.y);
+      if (tg & TAG_VI) sv = T((cfv.x * (double)vc + (double)rv) * cfv.y);
+      if (tg & TAG_WI) sw = T((cfw.x * (double)wc + (double)rw) * cfw.y);
       f.us[c] = su;
       f.vs[c] = sv;
       f.ws[c] = sw;
@@ -342,6 +352,16 @@ __device__ __forceinline__ void k_cfr_pi_body(Fields<T> f, IbmLists L, int stage
                                                double* __restrict__ pi_out, double* __restrict__ pi_hist, int bid_x, int bid_y, int nblk) {
   __shared__ double red[4];
   __shared__ double pi_s;
+  // this thread's immersed-boundary u face and its u* are loaded first, so that their
+  // latency overlaps the reduction
+  const int g = bid_x * blockDim.x + threadIdx.x;
+  int id = 0;
+  double inva = 0.0, usv = 0.0;
+  if (g < L.n_u) {
+    id = L.idx[g];
+    inva = L.coef[(size_t)stage * L.n_total + g].y;
+    usv = (double)f.us[id];
+  }
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   const int stride = blockDim.x * 8;
   for (int base = threadIdx.x; base < nq; base += stride) {
@@ -364,12 +384,7 @@ __device__ __forceinline__ void k_cfr_pi_body(Fields<T> f, IbmLists L, int stage
     }
   }
   __syncthreads();
-  const int g = bid_x * blockDim.x + threadIdx.x;
-  if (g < L.n_u) {
-    const int id = L.idx[g];
-    const double inva = L.coef[(size_t)stage * L.n_total + g].y;
-    f.us[id] = T((double)f.us[id] - pi_s * ck_dt * inva);
-  }
+  if (g < L.n_u) f.us[id] = T(usv - pi_s * ck_dt * inva);
 }
 
 template <typename T>
@@ -390,18 +405,11 @@ __global__ __launch_bounds__(256) void k_cfr_pi_b(const CfrArgs<T>* __restrict__
   k_cfr_pi_body<T>(a.f, a.L, a.stage, a.ck_dt, a.qpart, a.nq, a.scale, a.forcing, a.qt, a.S3, a.pi_out, a.pi_hist, local % a.gx, local / a.gx, boff[i + 1] - boff[i]);
 }
 
-// u* on a u face: internal non-IBM faces still owe -Pi c_k dt (= pick).
-template <typename T>
-__device__ __forceinline__ T ustar_at(const Fields<T>& f, int c, T pick) {
-  const uint8_t tg = f.tag[c];
-  return f.us[c] - (((tg & (TAG_U | TAG_UI)) == TAG_U) ? pick : T(0));
-}
-
 // ---------------------------------------------------------------------------------------
 // div_fftx: rhs = D u* / (c_k dt) on every cell, then the real FFT along x of each
 // (j, k) row: the nx reals are packed as nx/2 complex numbers z_n = x_{2n} + i x_{2n+1},
 // transformed, and unpacked to X_m, m = 0..nx/2.  2^ll lanes per row (as few as keep
-// every FFT stage at <= 2 butterflies per lane), blockDim.x >> ll rows per block.
+// every FFT stage at one butterfly per lane), blockDim.x >> ll rows per block.
 // If rhs_in is given, it replaces the divergence (stand-alone Poisson solve).
 // ---------------------------------------------------------------------------------------
 template <typename T, int MB>
@@ -422,9 +430,11 @@ __device__ __forceinline__ void k_div_fftx_body(GridParams g, Fields<T> f, IbmLi
   load_twiddles<T>(tw, px, threadIdx.x, blockDim.x);
   const bool valid = row < g.nrows;
   if (valid) {
-    T* Ar = reinterpret_cast<T*>(A);   // interleaved (re, im) == packed reals
-    if (rhs_in) {
-      for (int i = lane; i < nx; i += NL) Ar[i] = rhs_in[row * nx + i];
+    // each lane takes pairs of x-adjacent points (one vector load per field), which are
+    // also the packed complex values z_n = x_{2n} + i x_{2n+1}
+    const int rb = row * nx;
+    if (rhs_in) {   // a caller's array: element loads, no alignment assumed
+      for (int n = lane; n < N; n += NL) A[n] = cplx<T>{rhs_in[rb + 2 * n], rhs_in[rb + 2 * n + 1]};
     } else {
       const int j = row / g.nz, k = row - (row / g.nz) * g.nz;
       const int kp = wrap_p(k, g.nz);
@@ -433,13 +443,22 @@ __device__ __forceinline__ void k_div_fftx_body(GridParams g, Fields<T> f, IbmLi
       const T idx = T(g.idx), idy = T(g.idy), idz = T(g.idz);
       const bool hasN = (j + 1 < g.ny1);
       const int plane = nx * g.nz;
-      for (int i = lane; i < nx; i += NL) {
-        const int c = row * nx + i;
-        const int ip = wrap_p(i, nx);
-        const T ue = ustar_at(f, c - i + ip, pick), uc = ustar_at(f, c, pick);
-        const T vn = hasN ? f.vs[c + plane] : T(0), vc = f.vs[c];
-        const T wt = f.ws[c + (kp - k) * nx], wc = f.ws[c];
-        Ar[i] = ((ue - uc) * idx + (vn - vc) * idy + (wt - wc) * idz) * inv;
+      // u* on a u face: internal non-IBM faces still owe -Pi c_k dt (= pick)
+      auto ust = [&](T u, uint8_t tg) { return u - (((tg & (TAG_U | TAG_UI)) == TAG_U) ? pick : T(0)); };
+      for (int n = lane; n < N; n += NL) {
+        const int c = rb + 2 * n;
+        const int ie = rb + (2 * n + 2 == nx ? 0 : 2 * n + 2);   // east of the pair's second point
+        const Pair<T> u2 = ld_pair(f.us + c);
+        const T u3 = f.us[ie];
+        const uint16_t t2 = *reinterpret_cast<const uint16_t*>(f.tag + c);
+        const uint8_t t3 = f.tag[ie];
+        const Pair<T> vc2 = ld_pair(f.vs + c);
+        const Pair<T> vn2 = hasN ? ld_pair(f.vs + c + plane) : Pair<T>{T(0), T(0)};
+        const Pair<T> wc2 = ld_pair(f.ws + c);
+        const Pair<T> wt2 = ld_pair(f.ws + c + (kp - k) * nx);
+        const T a0 = ust(u2.x, uint8_t(t2 & 0xff)), a1 = ust(u2.y, uint8_t(t2 >> 8)), a2 = ust(u3, t3);
+        A[n] = cplx<T>{((a1 - a0) * idx + (vn2.x - vc2.x) * idy + (wt2.x - wc2.x) * idz) * inv,
+                       ((a2 - a1) * idx + (vn2.y - vc2.y) * idy + (wt2.y - wc2.y) * idz) * inv};
       }
     }
   }
@@ -839,8 +858,16 @@ __device__ __forceinline__ void k_ifftx_body(GridParams g, const cplx<T>* __rest
   fft_lds<T, MB>(A, 0, px, tw, +1, lane, NL);
   const cplx<T>* R = A;
   if (valid) {
-    const T* Rr = reinterpret_cast<const T*>(R);
-    for (int i = lane; i < g.nx; i += NL) out[(size_t)row * g.nx + i] = Rr[i];
+    T* orow = out + (size_t)row * g.nx;   // x_{2n}, x_{2n+1} = Re, Im z_n
+    if ((reinterpret_cast<uintptr_t>(out) & (2 * sizeof(T) - 1)) == 0) {   // one vector store per pair
+      Pair<T>* o2 = reinterpret_cast<Pair<T>*>(orow);
+      for (int n = lane; n < N; n += NL) o2[n] = Pair<T>{R[n].x, R[n].y};
+    } else {   // a caller's array that is not pair-aligned
+      for (int n = lane; n < N; n += NL) {
+        orow[2 * n] = R[n].x;
+        orow[2 * n + 1] = R[n].y;
+      }
+    }
   }
 }
 
