@@ -500,13 +500,15 @@ __global__ __launch_bounds__(256) void k_div_fftx_b(const DivArgs<T>* __restrict
 
 // ---------------------------------------------------------------------------------------
 // fftz: complex FFT along z of the half spectrum, W columns (one x mode m of one plane j)
-// per block.  The first blocks take W consecutive modes of one plane; the mh mod W modes
-// left over at the end of every plane are gathered, W at a time, into the last blocks, so
-// that no block transforms padding columns.
+// at a time per block.  The first blocks take W consecutive modes of NJ consecutive
+// planes, one plane after the other; with RP > 0 the next plane's columns are loaded into
+// registers (RP values per thread) while the current one is transformed and stored.  The
+// mh mod W modes left over at the end of every plane are gathered, W at a time, into the
+// last blocks (one plane each), so that no block transforms padding columns.
 // ---------------------------------------------------------------------------------------
-template <typename T, int MB>
+template <typename T, int MB, int RP>
 __device__ __forceinline__ void k_fftz_body(GridParams g, cplx<T>* __restrict__ spec, FFTPlan pz, int sign,
-                                             int W, int b) {
+                                             int W, int NJ, int b) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem_raw);
   const int nz = g.nz, mh = g.mh, mhs = g.mhs;
@@ -514,20 +516,65 @@ __device__ __forceinline__ void k_fftz_body(GridParams g, cplx<T>* __restrict__ 
   load_twiddles<T>(tw, pz, threadIdx.x, blockDim.x);
   const int lw = __ffs(W) - 1;   // W is a power of two
   const int w = threadIdx.x & (W - 1), lane = threadIdx.x >> lw, nl = blockDim.x >> lw;
-  const int gxf = mh >> lw, nfull = gxf * g.ny1, rem = mh - (gxf << lw);
-  // this thread's column (plane j, mode m)
-  int j = 0, m = 0;
-  bool ok = true;
+  const int gxf = mh >> lw, rem = mh - (gxf << lw);
+  const int nfull = gxf * ((g.ny1 + NJ - 1) / NJ);
   if (b < nfull) {
-    j = b / gxf;
-    m = ((b - j * gxf) << lw) + w;
-  } else {
-    const int idx = ((b - nfull) << lw) + w;
-    ok = rem > 0 && idx < rem * g.ny1;
-    if (ok) {
-      j = idx / rem;
-      m = (gxf << lw) + idx - j * rem;
+    const int jb = b / gxf;
+    const int m = ((b - jb * gxf) << lw) + w;
+    const int ja = jb * NJ, je = min(ja + NJ, g.ny1);
+    if (RP > 0) {
+      T prx[RP > 0 ? RP : 1], pry[RP > 0 ? RP : 1];   // next plane's values (re, im)
+      {
+        const cplx<T>* col = spec + (size_t)ja * g.splane + m;
+#pragma unroll
+        for (int r = 0; r < RP; ++r) {
+          const int kz = min(lane + r * nl, nz - 1);   // clamped: a repeated load is never stored
+          const cplx<T> v = col[(size_t)kz * mhs];
+          prx[r] = v.x;
+          pry[r] = v.y;
+        }
+      }
+      for (int j = ja; j < je; ++j) {
+#pragma unroll
+        for (int r = 0; r < RP; ++r) {
+          const int kz = lane + r * nl;
+          if (kz < nz) A[(kz << lw) + w] = cplx<T>{prx[r], pry[r]};
+        }
+        __syncthreads();
+        if (j + 1 < je) {   // the next plane's loads are in flight during this plane's transform and store
+          const cplx<T>* col = spec + (size_t)(j + 1) * g.splane + m;
+#pragma unroll
+          for (int r = 0; r < RP; ++r) {
+            const int kz = min(lane + r * nl, nz - 1);
+            const cplx<T> v = col[(size_t)kz * mhs];
+            prx[r] = v.x;
+            pry[r] = v.y;
+          }
+        }
+        fft_lds<T, MB>(A + w, lw, pz, tw, sign, lane, nl);
+        cplx<T>* col = spec + (size_t)j * g.splane + m;
+        for (int kz = lane; kz < nz; kz += nl) col[(size_t)kz * mhs] = A[(kz << lw) + w];
+        __syncthreads();   // the next plane overwrites A
+      }
+    } else {
+      for (int j = ja; j < je; ++j) {
+        cplx<T>* col = spec + (size_t)j * g.splane + m;   // element kz at col[kz * mhs]
+        for (int kz = lane; kz < nz; kz += nl) A[(kz << lw) + w] = col[(size_t)kz * mhs];
+        __syncthreads();
+        fft_lds<T, MB>(A + w, lw, pz, tw, sign, lane, nl);
+        for (int kz = lane; kz < nz; kz += nl) col[(size_t)kz * mhs] = A[(kz << lw) + w];
+        __syncthreads();
+      }
     }
+    return;
+  }
+  // a remainder block: this thread's column (plane j, mode m)
+  const int idx = ((b - nfull) << lw) + w;
+  const bool ok = rem > 0 && idx < rem * g.ny1;
+  int j = 0, m = 0;
+  if (ok) {
+    j = idx / rem;
+    m = (gxf << lw) + idx - j * rem;
   }
   cplx<T>* col = spec + (size_t)j * g.splane + m;   // element kz at col[kz * mhs]
   for (int kz = lane; kz < nz; kz += nl) A[(kz << lw) + w] = ok ? col[(size_t)kz * mhs] : cplx<T>{T(0), T(0)};
@@ -537,26 +584,28 @@ __device__ __forceinline__ void k_fftz_body(GridParams g, cplx<T>* __restrict__ 
     for (int kz = lane; kz < nz; kz += nl) col[(size_t)kz * mhs] = A[(kz << lw) + w];
 }
 
-// Blocks of one z-FFT launch: full blocks plus the gathered remainder columns.
-__host__ __device__ inline int fftz_blocks(int mh, int ny1, int W) {
+// Blocks of one z-FFT launch: full blocks (NJ planes each) plus the gathered remainder
+// columns.
+__host__ __device__ inline int fftz_blocks(int mh, int ny1, int W, int NJ) {
   const int gxf = mh / W, rem = mh - gxf * W;
-  return gxf * ny1 + (rem * ny1 + W - 1) / W;
+  return gxf * ((ny1 + NJ - 1) / NJ) + (rem * ny1 + W - 1) / W;
 }
 
-template <typename T, int MB>
+template <typename T, int MB, int RP>
 __global__ __launch_bounds__(512) void k_fftz(GridParams g, cplx<T>* __restrict__ spec, FFTPlan pz, int sign,
-                                             int W) {
-  k_fftz_body<T, MB>(g, spec, pz, sign, W, blockIdx.x);
+                                             int W, int NJ) {
+  k_fftz_body<T, MB, RP>(g, spec, pz, sign, W, NJ, blockIdx.x);
 }
 
-// The same for a batch of independent grids in one launch (block ranges boff).
+// The same for a batch of independent grids in one launch (block ranges boff), one plane
+// per block.
 template <typename T, int MB>
 __global__ __launch_bounds__(512) void k_fftz_b(const FftzArgs<T>* __restrict__ args,
     const int* __restrict__ boff, int ninst) {
   const int i = batch_instance(boff, ninst, blockIdx.x);
   const FftzArgs<T>& a = args[i];
   const int local = blockIdx.x - boff[i];
-  k_fftz_body<T, MB>(a.g, a.spec, a.pz, a.sign, a.W, local);
+  k_fftz_body<T, MB, 0>(a.g, a.spec, a.pz, a.sign, a.W, 1, local);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1046,6 +1095,19 @@ static int fftz_width(const GridParams& g, const FFTPlan& pz, const Tuning& tu) 
   return W;
 }
 
+template <typename T, int MB, int RP>
+static hipError_t launch_fftz_v(const GridParams& g, cplx<T>* spec, const FFTPlan& pz, int sign, int W, int NJ,
+                                int nt, size_t lds, hipStream_t st) {
+  const void* kfn = (const void*)k_fftz<T, MB, RP>;
+  if (lds > 65536) {
+    const hipError_t e = hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((k_fftz<T, MB, RP>), dim3(fftz_blocks(g.mh, g.ny1, W, NJ)), dim3(nt), lds, st, g, spec, pz,
+                     sign, W, NJ);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_fftz(const GridParams& g, cplx<T>* spec, const FFTPlan& pz, int sign, const Tuning& tu,
                        hipStream_t st) {
@@ -1053,16 +1115,24 @@ hipError_t launch_fftz(const GridParams& g, cplx<T>* spec, const FFTPlan& pz, in
   const int nt = fftz_threads(pz, W);
   const size_t lds = ((size_t)W + 1) * g.nz * sizeof(cplx<T>);
   const int mb = fft_max_bfly(pz, nt / W);
-  const dim3 grid(fftz_blocks(g.mh, g.ny1, W));
-  const void* kfn = mb == 1 ? (const void*)k_fftz<T, 1> : (mb == 2 ? (const void*)k_fftz<T, 2> : (const void*)k_fftz<T, 4>);
-  if (lds > 65536) {
-    const hipError_t e = hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
+  // planes per block: two, with the next plane's columns held in registers, when a
+  // thread's share of a column (ceil(nz / lanes)) fits 4 or 8 registers
+  const int per = (g.nz + nt / W - 1) / (nt / W);
+  const int rp = per <= 4 ? 4 : (per <= 8 ? 8 : 0);
+  const int nj = rp ? 2 : 1;
+  if (mb == 1) {
+    if (rp == 4) return launch_fftz_v<T, 1, 4>(g, spec, pz, sign, W, nj, nt, lds, st);
+    if (rp == 8) return launch_fftz_v<T, 1, 8>(g, spec, pz, sign, W, nj, nt, lds, st);
+    return launch_fftz_v<T, 1, 0>(g, spec, pz, sign, W, nj, nt, lds, st);
   }
-  if (mb == 1) hipLaunchKernelGGL((k_fftz<T, 1>), grid, dim3(nt), lds, st, g, spec, pz, sign, W);
-  else if (mb == 2) hipLaunchKernelGGL((k_fftz<T, 2>), grid, dim3(nt), lds, st, g, spec, pz, sign, W);
-  else hipLaunchKernelGGL((k_fftz<T, 4>), grid, dim3(nt), lds, st, g, spec, pz, sign, W);
-  return hipGetLastError();
+  if (mb == 2) {
+    if (rp == 4) return launch_fftz_v<T, 2, 4>(g, spec, pz, sign, W, nj, nt, lds, st);
+    if (rp == 8) return launch_fftz_v<T, 2, 8>(g, spec, pz, sign, W, nj, nt, lds, st);
+    return launch_fftz_v<T, 2, 0>(g, spec, pz, sign, W, nj, nt, lds, st);
+  }
+  if (rp == 4) return launch_fftz_v<T, 4, 4>(g, spec, pz, sign, W, nj, nt, lds, st);
+  if (rp == 8) return launch_fftz_v<T, 4, 8>(g, spec, pz, sign, W, nj, nt, lds, st);
+  return launch_fftz_v<T, 4, 0>(g, spec, pz, sign, W, nj, nt, lds, st);
 }
 
 template <typename T>
@@ -1159,7 +1229,7 @@ int plan_fftz(const GridParams& g, cplx<T>* spec, const FFTPlan& pz, int sign, c
               int* mb, size_t* lds, int* threads) {
   const int W = fftz_width<T>(g, pz, tu);
   const int nt = fftz_threads(pz, W);
-  const int nb = fftz_blocks(g.mh, g.ny1, W);
+  const int nb = fftz_blocks(g.mh, g.ny1, W, 1);
   *a = FftzArgs<T>{g, spec, pz, sign, W, nb};
   *mb = fft_max_bfly(pz, nt / W);
   *lds = ((size_t)W + 1) * g.nz * sizeof(cplx<T>);
