@@ -698,16 +698,13 @@ __device__ __forceinline__ void k_tri_body(GridParams g, cplx<T>* __restrict__ s
     }
     __syncthreads();
   }
-  // row coefficients of global row r
-  auto lo_of = [&](int r) { return r == 0 ? 0.0 : a; };
-  auto up_of = [&](int r) { return (r == n - 1 || (zmode && r == 0)) ? 0.0 : a; };
-  auto di_of = [&](int r) {
-    if (zmode && r == 0) return 1.0;
-    double b = -2.0 * a - K2;
-    if (r == 0) b += a;
-    if (r == n - 1) b += a;
-    return b;
-  };
+  // Row coefficients: interior rows have (a, -2a - K2, a).  The box's first row has no
+  // lower coefficient and a diagonal raised by a (for the (0,0) mode it becomes phi_0 = 0:
+  // diagonal 1, no upper coefficient); the box's last row has no upper coefficient and a
+  // diagonal raised by a.  Segments hold L >= 2 rows, so the first row can only be a
+  // segment's row 0 and the last row only its row L-1.
+  const bool first = r0 == 0, last = r1 == n;
+  const double dI = -2.0 * a - K2, dLast = dI + a;
 #pragma unroll
   for (int t = 0; t < LM; ++t) {
     dr[t] = (dr[t] - mr) * norm;
@@ -720,14 +717,14 @@ __device__ __forceinline__ void k_tri_body(GridParams g, cplx<T>* __restrict__ s
 #pragma unroll
   for (int t = 0; t < LM; ++t) { al[t] = 0.0; ib[t] = 1.0; ga[t] = 0.0; }
   if (valid) {
-    al[1] = lo_of(r0 + 1);
-    ib[1] = recip(di_of(r0 + 1));
+    al[1] = a;
+    ib[1] = recip((last && L == 2) ? dLast : dI);
 #pragma unroll
     for (int t = 2; t < LM; ++t) {
       if (t < L) {
-        const double m = lo_of(r0 + t) * ib[t - 1];
+        const double m = a * ib[t - 1];
         al[t] = -m * al[t - 1];
-        ib[t] = recip(di_of(r0 + t) - m * up_of(r0 + t - 1));
+        ib[t] = recip(((last && t == L - 1) ? dLast : dI) - m * a);
         dr[t] -= m * dr[t - 1];
         di[t] -= m * di[t - 1];
       }
@@ -736,11 +733,11 @@ __device__ __forceinline__ void k_tri_body(GridParams g, cplx<T>* __restrict__ s
     if (L >= 3) {
 #pragma unroll
       for (int t = 1; t < LM; ++t)
-        if (t == L - 2) ga[t] = up_of(r0 + t);
+        if (t == L - 2) ga[t] = a;
 #pragma unroll
       for (int t = LM - 3; t >= 1; --t) {
         if (t <= L - 3) {
-          const double m = up_of(r0 + t) * ib[t + 1];
+          const double m = a * ib[t + 1];
           al[t] -= m * al[t + 1];
           ga[t] = -m * ga[t + 1];
           dr[t] -= m * dr[t + 1];
@@ -756,10 +753,11 @@ __device__ __forceinline__ void k_tri_body(GridParams g, cplx<T>* __restrict__ s
     for (int t = 1; t < LM; ++t)
       if (t == L - 1) { dL = dr[t]; dLi = di[t]; alL = al[t]; ibL = ib[t]; }
     Rl[eE] = alL * ibL;
-    Ru[eE] = up_of(r1 - 1) * ibL;
+    Ru[eE] = last ? 0.0 : a * ibL;
     Rr[eE] = dL * ibL;
     Ri[eE] = dLi * ibL;
-    double dF = di_of(r0), uF = up_of(r0), rF = dr[0], iF = di[0];
+    const bool pin = zmode && first;   // phi_0 = 0 of the (0,0) mode
+    double dF = pin ? 1.0 : (first ? dI + a : dI), uF = pin ? 0.0 : a, rF = dr[0], iF = di[0];
     if (L >= 3) {
       const double m = uF * ib[1];
       dF -= m * al[1];
@@ -768,7 +766,7 @@ __device__ __forceinline__ void k_tri_body(GridParams g, cplx<T>* __restrict__ s
       iF -= m * di[1];
     }
     const double idF = recip(dF);
-    Rl[eF] = lo_of(r0) * idF;
+    Rl[eF] = first ? 0.0 : a * idF;
     Ru[eF] = uF * idF;
     Rr[eF] = rF * idF;
     Ri[eF] = iF * idF;
@@ -1143,13 +1141,16 @@ hipError_t launch_tri(const GridParams& g, cplx<T>* spec, const double* kx2, con
   int P = (n + L - 1) / L;                   // segments of at most L rows ...
   if (P > n / 2) P = n / 2 > 0 ? n / 2 : 1;  // ... and at least 2
   if (P > 256) P = 256;
-  const int W = 256 / P;                     // modes per block
+  // 128-thread blocks while their modes still fill whole 128-byte lines of every row read:
+  // twice the blocks of 256 threads spread more evenly over the compute units
+  const int TB = (128 / P) * (int)sizeof(cplx<T>) >= 128 ? 128 : 256;
+  const int W = TB / P;                      // modes per block
   const size_t lds = (size_t)(4 * tri_rs(W) * 2 * P + 2 * P) * sizeof(double);
   const dim3 grid((g.nz * g.mhs + W - 1) / W);
   if (L == 4 && (n + P - 1) / P <= 4)
-    hipLaunchKernelGGL((k_tri<T, 4>), grid, dim3(256), lds, st, g, spec, kx2, kz2, P, W, mean_out);
+    hipLaunchKernelGGL((k_tri<T, 4>), grid, dim3(TB), lds, st, g, spec, kx2, kz2, P, W, mean_out);
   else
-    hipLaunchKernelGGL((k_tri<T, 8>), grid, dim3(256), lds, st, g, spec, kx2, kz2, P, W, mean_out);
+    hipLaunchKernelGGL((k_tri<T, 8>), grid, dim3(TB), lds, st, g, spec, kx2, kz2, P, W, mean_out);
   return hipGetLastError();
 }
 
