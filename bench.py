@@ -31,7 +31,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="wavy", help="wavy | wavy_large | poiseuille")
+    ap.add_argument("--workload", default="wavy", help="wavy | wavy_large | wavy_open | ellipsoids | poiseuille")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the extra forms (FP32, large grid, IBM off)")
@@ -371,6 +371,11 @@ def main():
             forms.append(dict(_form(re_, prec), ibm_point_fraction=round(re_["ibm_fraction"], 4)))
         del sdf_e, st_e, inp_e
         torch.cuda.empty_cache()
+        # open channel over an undulated bottom, free-slip top (192 x 65 x 160), 300 steps
+        inp_o = build_inputs("wavy_open")
+        ro = measure("wavy_open", "fp64", 300, 3, inputs=inp_o)
+        forms.append(dict(_form(ro, "fp64"), top="free-slip", ibm_point_fraction=round(ro["ibm_fraction"], 4)))
+        del inp_o
         forms.append(measure_ensemble())
         out["forms"] = forms
     print(json.dumps(out), flush=True)

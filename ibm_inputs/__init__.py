@@ -58,6 +58,7 @@ class Case:
     seed: int = 0
     geometry: str = "flat"
     geo_params: Tuple = ()
+    top: int = 0       # 0 = no-slip north box face, 1 = free-slip north face (open channel)
 
     @property
     def dx(self) -> float:
@@ -124,6 +125,20 @@ def sdf_wavy(c: Case, amp: float, lam: float, top: float = 1.0):
         yw = -1.0 + amp * np.sin(k * X)
         dyw = amp * k * np.cos(k * X)
         return np.minimum((Y - yw) / np.sqrt(1.0 + dyw * dyw), top - Y)
+    return _sample(c, fn)
+
+
+def wavy_open_wall(x, eps: float, alpha: float):
+    """Undulated bottom y_w(x) = eps (1 + cos(alpha x)) of the open channel, and its slope."""
+    return eps * (1.0 + np.cos(alpha * x)), -eps * alpha * np.sin(alpha * x)
+
+
+def sdf_wavy_open(c: Case, eps: float, alpha: float):
+    """Open channel over the undulated bottom y_w(x) = eps (1 + cos alpha x): only the bottom
+    is a wall (the north box face is free-slip), s = (y - y_w)/sqrt(1 + y_w'^2)."""
+    def fn(X, Y, Z):
+        yw, dyw = wavy_open_wall(X, eps, alpha)
+        return (Y - yw) / np.sqrt(1.0 + dyw * dyw)
     return _sample(c, fn)
 
 
@@ -237,10 +252,21 @@ def laminar_plus_noise(c: Case, seed: int, amp: float = 1e-3):
     return random_fields(c, seed, amp)
 
 
+def open_channel_profile(c: Case, eps: float, alpha: float, ub: float = 1.0) -> np.ndarray:
+    """Laminar open-channel profile 1.5 ub (2 eta - eta^2), eta = (y - y_w)/(y_hi - y_w),
+    on the u grid (zero below the wall): bulk velocity ub over every column."""
+    g = coords(c)
+    X, Y, _ = _mesh(g["yc"], g["zc"], g["xf"])
+    yw, _ = wavy_open_wall(X, eps, alpha)
+    eta = np.clip((Y - yw) / (c.y_hi - yw), 0.0, 1.0)
+    return 1.5 * ub * (2.0 * eta - eta * eta)
+
+
 def laminar_plus_solenoidal(c: Case, sdfs, seed: int, amp: float = 0.1, ub: float = 1.0,
-                            env_width: Optional[float] = None):
-    """Laminar 1.5*ub*(1-y^2) streamwise profile plus a solenoidal perturbation with
-    max |u'| = amp*ub, both faded to zero in the solid by a smooth SDF envelope."""
+                            env_width: Optional[float] = None, profile: Optional[np.ndarray] = None):
+    """Laminar 1.5*ub*(1-y^2) streamwise profile (or the given one on the u grid) plus a
+    solenoidal perturbation with max |u'| = amp*ub, both faded to zero in the solid by a
+    smooth SDF envelope."""
     g = coords(c)
     su, sv, sw = sdfs
     width = env_width if env_width is not None else 2.0 * c.dy
@@ -251,7 +277,7 @@ def laminar_plus_solenoidal(c: Case, sdfs, seed: int, amp: float = 0.1, ub: floa
     m = max(np.abs(up).max(), np.abs(vp).max(), np.abs(wp).max(), 1e-300)
     sc = amp * ub / m
     yc = g["yc"][:, None, None]
-    lam = 1.5 * ub * np.clip(1.0 - yc * yc, 0.0, None)
+    lam = 1.5 * ub * np.clip(1.0 - yc * yc, 0.0, None) if profile is None else profile
     u = (lam + sc * up) * eu
     v = (sc * vp) * ev
     w = (sc * wp) * ew
@@ -275,6 +301,13 @@ WORKLOADS: Dict[str, Case] = {
     "wavy_large": Case(nx=512, ny=257, nz=256, lx=2 * math.pi, lz=math.pi, y_lo=-1.2, y_hi=1.0,
                        nu=1.0 / 2800.0, dt=0.003, forcing=0, q_target_or_pi=2.0 * math.pi,
                        name="wavy_512x257x256", seed=3, geometry="wavy", geo_params=(0.1, math.pi / 2)),
+    # Open channel over an undulated bottom y_w = eps (1 + cos alpha x), eps = 0.05,
+    # alpha = 1/2 (Lx = 4 pi), spanwise 2 pi, free-slip at y = 1, Re_b = 2800: the
+    # coarsest grid of the convergence study (192 x 160 x 64, uniform here)
+    "wavy_open": Case(nx=192, ny=65, nz=160, lx=4 * math.pi, lz=2 * math.pi, y_lo=0.0, y_hi=1.0,
+                      nu=1.0 / 2800.0, dt=0.008, forcing=0, q_target_or_pi=2 * math.pi * 0.95,
+                      name="wavy_open_192x65x160", seed=6, geometry="wavy_open", geo_params=(0.05, 0.5),
+                      top=1),
     # Union of 64 seeded ellipsoids, 384x193x192
     "ellipsoids": Case(nx=384, ny=193, nz=192, lx=2 * math.pi, lz=math.pi, y_lo=-1.0, y_hi=1.0,
                        nu=1.0 / 1000.0, dt=0.004, forcing=0, q_target_or_pi=2.0 * math.pi,
@@ -293,12 +326,17 @@ def make_sdf(c: Case):
         return sdf_wavy(c, c.geo_params[0], c.geo_params[1])
     if c.geometry == "ellipsoids":
         return sdf_ellipsoids(c, int(c.geo_params[0]), seed=c.seed)
+    if c.geometry == "wavy_open":
+        return sdf_wavy_open(c, c.geo_params[0], c.geo_params[1])
     raise ValueError(c.geometry)
 
 
 def make_initial(c: Case, sdfs):
     if c.geometry == "flat":
         return laminar_plus_noise(c, c.seed, 1e-3)
+    if c.geometry == "wavy_open":
+        prof = open_channel_profile(c, c.geo_params[0], c.geo_params[1])
+        return laminar_plus_solenoidal(c, sdfs, c.seed, amp=0.1, profile=prof)
     return laminar_plus_solenoidal(c, sdfs, c.seed, amp=0.1)
 
 

@@ -58,6 +58,7 @@ enum {
 enum { IBM_FP64 = 0, IBM_FP32_STORAGE = 1 };
 enum { IBM_CFR = 0, IBM_CPG = 1 };               /* constant flow rate / pressure gradient */
 enum { IBM_B_EXP = 0, IBM_B_EULER = 1, IBM_B_TAYLOR2 = 2 };
+enum { IBM_TOP_WALL = 0, IBM_TOP_FREE_SLIP = 1 };   /* condition at the north box face y_hi */
 
 typedef struct ibm_ctx* ibm_handle;
 
@@ -74,6 +75,10 @@ typedef struct {
   double lx, lz, y_lo, y_hi;
   double nu, dt;        /* kinematic viscosity (1/Re_bulk), fixed time step */
   double q_target_or_pi;
+  int32_t top;          /* IBM_TOP_WALL: no-slip wall on the north box face (as on the south
+                           one); IBM_TOP_FREE_SLIP: free-slip surface there (v = 0,
+                           du/dy = dw/dy = 0: the row above mirrors the top row of u and w),
+                           the open channel of Sec. 4.2 */
 } ibm_grid_desc;
 
 typedef struct {

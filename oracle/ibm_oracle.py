@@ -20,7 +20,10 @@ z spanwise (periodic).  Arrays are indexed [j, k, i] (x fastest):
                                                              box wall: implicit zero)
   w   back faces            (x_c[i], y_c[j], k*dz)
 Ghost rows of u and w at j = -1 and j = ny-1 lie outside the box; they are
-always external (value 0) and only carry SDF samples.
+external (value 0) and only carry SDF samples, except that with a free-slip north
+face (top = 1, the open channel of Sec. 4.2) the ghost row j = ny-1 mirrors the top
+row of u and w (du/dy = dw/dy = 0 on the face) and that face is not a wall for lambda
+(reading R16).
 Pi is the mean streamwise pressure gradient, entering the u-momentum
 equation as -Pi (the paper's notation in Sec. 2.5, Eq. (18)).
 """
@@ -56,6 +59,7 @@ class OGrid:
     forcing: int = CFR
     q_target_or_pi: float = 0.0
     b_mode: int = B_EXP
+    top: int = 0          # 0: no-slip north box face; 1: free-slip north face
 
     @property
     def dx(self):
@@ -76,7 +80,7 @@ class OGrid:
     @classmethod
     def from_case(cls, c) -> "OGrid":
         return cls(c.nx, c.ny, c.nz, c.lx, c.lz, c.y_lo, c.y_hi, c.nu, c.dt,
-                   c.forcing, c.q_target_or_pi, c.b_mode)
+                   c.forcing, c.q_target_or_pi, c.b_mode, int(getattr(c, "top", 0)))
 
 
 # --------------------------------------------------------------------------------------
@@ -157,11 +161,12 @@ def wall_lambda(g: OGrid, sdf_full: np.ndarray, comp: str, internal: np.ndarray)
         ext_dn = s_dn <= 0.0
         ext_up = s_up <= 0.0
         ext_dn[0] = True              # ghost rows are outside the box
-        ext_up[-1] = True
         box_dn = np.full(s.shape, np.inf)
         box_up = np.full(s.shape, np.inf)
         box_dn[0] = 0.5 * g.dy        # u, w of row 0 sit dy/2 above the south box wall
-        box_up[-1] = 0.5 * g.dy
+        if g.top == 0:                # a north box wall dy/2 above the top row
+            ext_up[-1] = True
+            box_up[-1] = 0.5 * g.dy
     else:  # v: faces 0..ny-1 are all stored in sdf_full; face 0 and ny-1 are box walls
         s = sdf_full[:-1]
         s_dn = np.zeros_like(s)
@@ -247,14 +252,19 @@ def convection(g: OGrid, u, v, w):
     return Nu, Nv, Nw
 
 
-def laplacian(g: OGrid, f):
+def laplacian(g: OGrid, f, mirror_top: bool = False):
     """Seven-point Laplacian, Eq. (3), with external/ghost neighbours equal to zero.
 
     Sec. 2.4: as long as external values are zero and the right-hand side is
     explicit, the unmodified Laplacian is used; the wall enters through lambda.
+    mirror_top: the ghost row above the top row equals the top row (free-slip face,
+    reading R16).
     """
+    up = sy(f, 1)
+    if mirror_top:
+        up[-1] = f[-1]
     return ((sx(f, 1) - 2.0 * f + sx(f, -1)) / g.dx ** 2
-            + (sy(f, 1) - 2.0 * f + sy(f, -1)) / g.dy ** 2
+            + (up - 2.0 * f + sy(f, -1)) / g.dy ** 2
             + (sz(f, 1) - 2.0 * f + sz(f, -1)) / g.dz ** 2)
 
 
@@ -272,9 +282,10 @@ def divergence(g: OGrid, u, v, w):
 def explicit_rhs(g: OGrid, u, v, w, tags):
     """H = -N(u) + nu L(u) at internal points (Sec. 2.4, Eq. (9)); zero elsewhere."""
     Nu, Nv, Nw = convection(g, u, v, w)
-    Hu = np.where(tags["u"], -Nu + g.nu * laplacian(g, u), 0.0)
+    fs = g.top == 1
+    Hu = np.where(tags["u"], -Nu + g.nu * laplacian(g, u, fs), 0.0)
     Hv = np.where(tags["v"], -Nv + g.nu * laplacian(g, v), 0.0)
-    Hw = np.where(tags["w"], -Nw + g.nu * laplacian(g, w), 0.0)
+    Hw = np.where(tags["w"], -Nw + g.nu * laplacian(g, w, fs), 0.0)
     return Hu, Hv, Hw
 
 

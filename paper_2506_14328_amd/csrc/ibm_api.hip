@@ -195,6 +195,7 @@ int validate(ibm_ctx* c, const ibm_grid_desc& d) {
   if (!(d.lx > 0.0) || !(d.lz > 0.0) || !(d.y_hi > d.y_lo)) return fail(c, IBM_ERR_ARG, "invalid box extents");
   if (d.forcing != IBM_CFR && d.forcing != IBM_CPG) return fail(c, IBM_ERR_ARG, "invalid forcing");
   if (d.b_mode < 0 || d.b_mode > 2) return fail(c, IBM_ERR_ARG, "invalid b_mode");
+  if (d.top != IBM_TOP_WALL && d.top != IBM_TOP_FREE_SLIP) return fail(c, IBM_ERR_ARG, "invalid top");
   return IBM_OK;
 }
 
@@ -220,6 +221,7 @@ int init_instance(ibm_ctx* c, Instance& I, const ibm_grid_desc& d) {
   g.idz2 = 1.0 / (g.dz * g.dz);
   g.nu = d.nu;
   g.dt = d.dt;
+  g.top_fs = d.top == IBM_TOP_FREE_SLIP ? 1 : 0;
   const size_t ts = (c->precision == IBM_FP64) ? sizeof(double) : sizeof(float);
   // spectrum rows start on 128-byte lines (8 FP64 or 16 FP32 complex values per line);
   // a plane spans an odd number of lines, so that the rows of one mode in successive

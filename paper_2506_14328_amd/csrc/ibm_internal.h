@@ -38,6 +38,7 @@ struct GridParams {
   int nmodes;           // nz*mh Fourier modes per y plane
   int mhs;              // spectrum row stride: mh rounded up to whole 128-byte lines
   int splane;           // spectrum elements per y plane (nz*mhs, plus one line if even)
+  int top_fs;           // 1: free-slip north box face (u, w mirrored above the top row)
   int64_t ncell;        // nx*ny1*nz
   double dx, dy, dz;
   double idx, idy, idz;

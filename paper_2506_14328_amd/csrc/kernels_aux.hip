@@ -47,7 +47,8 @@ __global__ __launch_bounds__(256) void k_geom_lambda(GridParams g, const double*
       const double sxm = s[o + im], sxp = s[o + ip];
       const double szm = s[o + (km - k) * nx + i], szp = s[o + (kp - k) * nx + i];
       const double sdn = s[o - plane + i], sup = s[o + plane + i];
-      const bool gdn = (j == 0), gup = (j == ny1 - 1);
+      // the south box face is a wall; so is the north one unless it is free-slip
+      const bool gdn = (j == 0), gup = (j == ny1 - 1) && !g.top_fs;
       lam += arm(nu, dx, sP, sxm, sxm <= 0.0, INFINITY);
       lam += arm(nu, dx, sP, sxp, sxp <= 0.0, INFINITY);
       lam += arm(nu, dz, sP, szm, szm <= 0.0, INFINITY);

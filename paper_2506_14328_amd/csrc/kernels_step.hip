@@ -138,7 +138,10 @@ __device__ __forceinline__ void k_momentum_body(GridParams g, Fields<T> f, IbmLi
     q.phy = Pair<T>{T(0), T(0)};
     if (with_phy && inb && jj > 0) q.phy = ld_pair(f.phi + b - plane + off);
     const uint16_t t = *reinterpret_cast<const uint16_t*>(f.tag + b + off);
-    q.tg = inb ? t : uint16_t(0);
+    // above a free-slip north face the row mirrors the top row's u and w (the clamped
+    // load is that row); v on the face and p are zero there
+    const uint16_t keep = (g.top_fs && jj == ny1) ? uint16_t(~((TAG_V | TAG_VI | TAG_P) * 0x0101u)) : uint16_t(0);
+    q.tg = inb ? t : uint16_t(t & keep);
   };
   // corrected state of one fetched value (tag tg, its phi and west/back/south phi)
   auto corr = [&](int fld, uint8_t tg, T val, T ph, T phx, T phz, T phy) -> T {

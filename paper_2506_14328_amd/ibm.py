@@ -38,7 +38,7 @@ class IbmGridDesc(ctypes.Structure):
     _fields_ = [("nx", c_int32), ("ny", c_int32), ("nz", c_int32), ("forcing", c_int32),
                 ("b_mode", c_int32), ("ibm", c_int32),
                 ("lx", c_double), ("lz", c_double), ("y_lo", c_double), ("y_hi", c_double),
-                ("nu", c_double), ("dt", c_double), ("q_target_or_pi", c_double)]
+                ("nu", c_double), ("dt", c_double), ("q_target_or_pi", c_double), ("top", c_int32)]
 
 
 class IbmStats(ctypes.Structure):
@@ -104,7 +104,7 @@ def _ptr(t: torch.Tensor) -> int:
 
 def _desc(c, ibm: bool) -> IbmGridDesc:
     return IbmGridDesc(c.nx, c.ny, c.nz, c.forcing, c.b_mode, 1 if ibm else 0, c.lx, c.lz, c.y_lo, c.y_hi, c.nu,
-                       c.dt, c.q_target_or_pi)
+                       c.dt, c.q_target_or_pi, int(getattr(c, "top", 0)))
 
 
 class IbmGrid:

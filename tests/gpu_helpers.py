@@ -38,6 +38,9 @@ def case(name, **kw):
         wavy_160=dict(nx=160, ny=9, nz=20, lx=2 * math.pi, lz=math.pi, y_lo=-1.2, y_hi=1.0, nu=1 / 1000.0,
                       dt=0.004, q_target_or_pi=2 * math.pi, seed=5, geometry="wavy",
                       geo_params=(0.12, math.pi / 2)),
+        open_small=dict(nx=32, ny=17, nz=20, lx=4 * math.pi, lz=2 * math.pi, y_lo=0.0, y_hi=1.0, nu=1 / 500.0,
+                        dt=0.01, q_target_or_pi=2 * math.pi * 0.95, seed=12, geometry="wavy_open",
+                        geo_params=(0.05, 0.5), top=1),
     )[name]
     base.update(kw)
     return I.Case(name=name, **base)

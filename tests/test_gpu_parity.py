@@ -28,7 +28,7 @@ def _oracle_tags(o):
     return t
 
 
-@pytest.mark.parametrize("name", ["wavy_small", "flat_small", "ellip_small", "minimal", "wavy_160"])
+@pytest.mark.parametrize("name", ["wavy_small", "flat_small", "ellip_small", "minimal", "wavy_160", "open_small"])
 @pytest.mark.parametrize("b_mode", [0, 1, 2])
 def test_geometry_parity(name, b_mode):
     c = case(name, b_mode=b_mode)
@@ -101,7 +101,7 @@ def test_solve_pressure_unaligned_buffers(precision):
 
 
 @pytest.mark.parametrize("name,nsteps", [("wavy_small", 1), ("wavy_small", 4), ("flat_small", 3),
-                                         ("ellip_small", 2), ("minimal", 5), ("wavy_160", 2)])
+                                         ("ellip_small", 2), ("minimal", 5), ("wavy_160", 2), ("open_small", 4)])
 def test_step_parity_fp64(name, nsteps):
     c = case(name)
     o, sdf, st = oracle_run(c, nsteps)
@@ -228,6 +228,9 @@ def test_error_paths():
     with pytest.raises(ValueError):
         g.set_state(*[torch.zeros((3, 3, 3), dtype=torch.float64, device=device())] * 4)
     g.close()
+    with pytest.raises(IbmError) as e:
+        IbmGrid.from_case(case("open_small", top=2))   # neither a wall nor free-slip
+    assert e.value.code == -1
 
 
 def test_nan_detected():
@@ -267,7 +270,7 @@ def test_autotune_keeps_trajectory():
 
 def _ensemble_members():
     return [case("wavy_small"), case("flat_small"), case("ellip_small"), case("wavy_160", nu=1 / 700.0),
-            case("minimal")]
+            case("minimal"), case("open_small")]
 
 
 @pytest.mark.parametrize("graph,batch", [(False, False), (True, False), (False, True), (True, True)])

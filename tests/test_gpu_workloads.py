@@ -259,6 +259,23 @@ def test_large_grid_one_step_oracle(large_inputs):
 # ---------------------------------------------------------------------------------------
 # 64 ellipsoids 384x193x192
 # ---------------------------------------------------------------------------------------
+def test_open_channel_full_size_parity():
+    """The open channel over the undulated bottom with a free-slip top (192x65x160, FP64),
+    full arrays, 2 steps in the autotuned launch configuration, against the oracle."""
+    from tests.gpu_helpers import oracle_run
+    c = I.make_case("wavy_open")
+    _say("oracle 2 steps ...")
+    o, sdf, st = oracle_run(c, 2)
+    g = gpu_grid(c, sdf, st)
+    g.autotune(1)
+    g.step(2)
+    u, v, w, p = [t.cpu().numpy() for t in g.get_state()]
+    for a, b in ((u, o.u), (v, o.v), (w, o.w)):
+        assert rel_err(a, b) < 1e-12
+    assert g.stats()["n_ibm"][0] > 0
+    g.close()
+
+
 def test_ellipsoids_full_size_one_step_parity():
     """Complex geometry at full size: tags and IBM counts exactly, every velocity and the
     pressure after one step within 1e-12 of the oracle; the IBM-point fraction is reported."""
