@@ -497,3 +497,83 @@ def gradient_full(g: OGrid, phi):
 def solve_pressure(g: OGrid, rhs: np.ndarray):
     """Stand-alone Poisson solve, the operation behind the library's solve-pressure call."""
     return poisson_solve(g, np.asarray(rhs, dtype=np.float64))
+
+
+# --------------------------------------------------------------------------------------
+# Wall-shear stress of the undulated bottom and its Fourier components (Sec. 4.2)
+# --------------------------------------------------------------------------------------
+def south_wall_points(g: OGrid, sdf_u: np.ndarray, ibm: bool = True):
+    """Lowest internal u point of every (k, i) column and its distance to the wall below.
+
+    Reading R17: the wall under the lowest internal point of a column is located as the
+    immersed boundary locates it (Sec. 2.2 and reading R8): the linear zero crossing of
+    the signed distance between the point and the external point below it, or the south
+    box wall dy/2 below row 0 when that is nearer.  Without the immersed-boundary
+    correction the staircase puts the wall at the external point itself (distance dy).
+    Returns (j1, d1): j1 = -1 and d1 = 0 where a column holds no internal u point.
+    sdf_u: (ny+1, nz, nx) with row j+1 holding row j (ghost rows 0 and ny).
+    """
+    s = sdf_u[1:-1]
+    internal = s > 0.0
+    has = internal.any(axis=0)
+    j1 = np.argmax(internal, axis=0)
+    kk, ii = np.meshgrid(np.arange(g.nz), np.arange(g.nx), indexing="ij")
+    sP = s[j1, kk, ii]
+    s_dn = sdf_u[j1, kk, ii]                 # row j1 - 1 (the ghost row for j1 = 0)
+    d1 = np.full(j1.shape, g.dy)
+    if ibm:
+        with np.errstate(divide="ignore", invalid="ignore"):
+            cross = np.where(s_dn <= 0.0, g.dy * sP / (sP - s_dn), np.inf)
+        box = np.where(j1 == 0, 0.5 * g.dy, np.inf)
+        d1 = np.minimum(cross, box)
+    j1 = np.where(has, j1, -1)
+    d1 = np.where(has, d1, 0.0)
+    return j1, d1
+
+
+def wall_shear_profile(g: OGrid, u: np.ndarray, sdf_u: np.ndarray, ibm: bool = True) -> np.ndarray:
+    """Spanwise-averaged wall-shear stress tau(x_i) along the south wall (Sec. 4.2).
+
+    Reading R17: tau = nu du/dy at the wall, from the parabola through the no-slip wall
+    value (0 at distance 0), u1 at the lowest internal point (distance d1) and u2 at the
+    point above it (distance d1 + dy):
+        tau = nu (u1 d2^2 - u2 d1^2) / (d1 d2 (d2 - d1)),  d2 = d1 + dy,
+    exact for velocity profiles quadratic in the wall distance; where the point above is
+    not internal (or outside the box) the straight line through the wall and u1 is used,
+    tau = nu u1 / d1.  Columns without internal u points add zero; the mean is over all
+    nz columns of each x_i = i dx.
+    """
+    internal = sdf_u[1:-1] > 0.0
+    j1, d1 = south_wall_points(g, sdf_u, ibm)
+    ny1 = g.ny - 1
+    tau = np.zeros((g.nz, g.nx))
+    for k in range(g.nz):
+        for i in range(g.nx):
+            j = int(j1[k, i])
+            if j < 0:
+                continue
+            a = float(d1[k, i])
+            u1 = float(u[j, k, i])
+            if j + 1 < ny1 and internal[j + 1, k, i]:
+                b = a + g.dy
+                u2 = float(u[j + 1, k, i])
+                tau[k, i] = g.nu * (u1 * b * b - u2 * a * a) / (a * b * (b - a))
+            else:
+                tau[k, i] = g.nu * u1 / a
+    return tau.mean(axis=0)
+
+
+def wall_shear_modes(g: OGrid, tau_x: np.ndarray) -> Tuple[float, float, float]:
+    """Mean and first Fourier components of tau(x) over the box length (Sec. 4.2).
+
+    tau_1c and tau_1s are (2/L_x) times the integrals of tau(x) cos(2 pi x/L_x) and
+    tau(x) sin(2 pi x/L_x) over one box length; on the uniform periodic grid of u points
+    x_i = i dx the integrals are the rectangle sums, exact for trigonometric polynomials
+    of degree below nx.  tau_0 is the plain mean.
+    """
+    x = np.arange(g.nx) * g.dx
+    th = 2.0 * math.pi * x / g.lx
+    t0 = float(np.sum(tau_x) * g.dx / g.lx)
+    t1c = float(2.0 / g.lx * np.sum(tau_x * np.cos(th)) * g.dx)
+    t1s = float(2.0 / g.lx * np.sum(tau_x * np.sin(th)) * g.dx)
+    return t0, t1c, t1s
