@@ -42,6 +42,10 @@ struct Instance {
   int32_t* itotal = nullptr;
   double2* rtw = nullptr;
   double *kx2 = nullptr, *kz2 = nullptr;
+  // south-wall point per (k, i) column (row, distance) and wall-shear output [nx + 3]
+  int32_t* wall_j = nullptr;
+  double* wall_d = nullptr;
+  double* wall_tau = nullptr;
   // immersed-boundary lists
   DevBuf ibm_idx, ibm_coef, ibm_lam, ibm_choff;
   IbmLists L{};
@@ -254,6 +258,10 @@ int init_instance(ibm_ctx* c, Instance& I, const ibm_grid_desc& d) {
   if ((rc = dalloc(c, I, (void**)&I.small, 32 * sizeof(double)))) return rc;
   HIPCHK(c, hipMemsetAsync(I.small, 0, 32 * sizeof(double), c->stream));
   if ((rc = dalloc(c, I, (void**)&I.itotal, 16 * sizeof(int32_t)))) return rc;
+  const size_t ncol = (size_t)g.nx * g.nz;
+  if ((rc = dalloc(c, I, (void**)&I.wall_j, ncol * sizeof(int32_t)))) return rc;
+  if ((rc = dalloc(c, I, (void**)&I.wall_d, ncol * sizeof(double)))) return rc;
+  if ((rc = dalloc(c, I, (void**)&I.wall_tau, (g.nx + 3) * sizeof(double)))) return rc;
   // real-FFT unpacking twiddles e^{-2 pi i m/nx}, m = 0..nx/2, and modified wavenumbers
   std::vector<double2> rt(g.mh);
   for (int m = 0; m < g.mh; ++m) {
@@ -448,6 +456,7 @@ int set_geometry_impl(ibm_ctx* c, Instance& I, const double* su, const double* s
       return launch_geom_lambda(g, su, sv, sw, I.d.ibm, I.tag, lam_u, lam_v, lam_w, st);
     });
     if (e == hipSuccess) e = launch_geom_ptag(g, I.tag, st);
+    if (e == hipSuccess) e = launch_geom_south_wall(g, su, I.d.ibm, I.wall_j, I.wall_d, st);
     if (e != hipSuccess) { rc = fail(c, IBM_ERR_DEVICE, std::string("geometry: ") + hipGetErrorString(e)); break; }
     const uint8_t imask[3] = {TAG_U, TAG_V, TAG_W};
     const uint8_t bmask[3] = {TAG_UI, TAG_VI, TAG_WI};
@@ -891,6 +900,29 @@ int ibm_set_diagnostics(ibm_handle h, int32_t on) {
   return IBM_OK;
 }
 
+int ibm_wall_shear(ibm_handle h, int32_t inst, double* tau_x, double* modes) {
+  int rc = check_inst(h, inst);
+  if (rc) return rc;
+  Instance& I = h->inst[inst];
+  if (!I.geom_ready) return fail(h, IBM_ERR_STATE, "ibm_wall_shear before ibm_set_geometry");
+  if ((rc = materialize(h, I))) return rc;
+  const GridParams& g = I.g;
+  double* tx = tau_x ? tau_x : I.wall_tau;
+  double* md = modes ? I.wall_tau + g.nx : nullptr;
+  if (h->precision == IBM_FP64) {
+    RUNK(h, K_WALL_SHEAR,
+         launch_wall_shear<double>(g, (const double*)I.u, I.tag, I.wall_j, I.wall_d, tx, md, h->stream));
+  } else {
+    RUNK(h, K_WALL_SHEAR,
+         launch_wall_shear<float>(g, (const float*)I.u, I.tag, I.wall_j, I.wall_d, tx, md, h->stream));
+  }
+  if (modes) {
+    HIPCHK(h, hipMemcpyAsync(modes, md, 3 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+  }
+  return IBM_OK;
+}
+
 int ibm_stats(ibm_handle h, int32_t inst, ibm_stats_t* out) {
   int rc = check_inst(h, inst);
   if (rc) return rc;
@@ -1174,7 +1206,8 @@ int ibm_profile_read(ibm_handle h, double* total_ms, int64_t* launches, int32_t 
 
 const char* ibm_kernel_name(int32_t id) {
   static const char* names[K_NUM_KERNELS] = {"momentum", "cfr_pi", "div_fftx", "fftz_fwd", "tri", "fftz_inv",
-                                             "ifftx", "correct", "diag", "stats", "geom"};
+                                             "ifftx", "correct", "diag", "stats", "geom",
+                                             "wall_shear"};
   if (id < 0 || id >= K_NUM_KERNELS) return "unknown";
   return names[id];
 }

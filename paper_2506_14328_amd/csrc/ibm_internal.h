@@ -21,7 +21,7 @@ enum : uint8_t {
 // Kernel ids (profiling).
 enum KernelId {
   K_MOMENTUM = 0, K_CFR_PI, K_DIV_FFTX, K_FFTZ_FWD, K_TRI, K_FFTZ_INV, K_IFFTX, K_CORRECT, K_DIAG, K_STATS,
-  K_GEOM, K_NUM_KERNELS
+  K_GEOM, K_WALL_SHEAR, K_NUM_KERNELS
 };
 
 template <typename T>
@@ -326,6 +326,12 @@ hipError_t launch_geom_lambda(const GridParams& g, const double* su, const doubl
                               int ibm_on, uint8_t* tag, double* lam_u, double* lam_v, double* lam_w,
                               hipStream_t st);
 hipError_t launch_geom_ptag(const GridParams& g, uint8_t* tag, hipStream_t st);
+hipError_t launch_geom_south_wall(const GridParams& g, const double* su, int ibm_on, int32_t* wj, double* wd,
+                                  hipStream_t st);
+// tau_x[nx] and, if modes is not null, modes[3] = (tau_0, tau_1c, tau_1s)
+template <typename T>
+hipError_t launch_wall_shear(const GridParams& g, const T* u, const uint8_t* tag, const int32_t* wj,
+                             const double* wd, double* tau_x, double* modes, hipStream_t st);
 hipError_t launch_count_flags(const uint8_t* tag, int64_t n, uint8_t mask, int32_t* blk_counts,
                               int nblk, hipStream_t st);
 hipError_t launch_scan_counts(int32_t* blk_counts, int nblk, int32_t* total, hipStream_t st);

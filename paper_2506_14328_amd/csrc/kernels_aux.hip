@@ -102,6 +102,42 @@ __global__ __launch_bounds__(256) void k_geom_ptag(GridParams g, uint8_t* __rest
   if (pin) tag[c] = t | TAG_P;
 }
 
+// South-wall point of every (k, i) column of u points: the lowest internal u row j1 and
+// its distance d1 to the wall below, located as the immersed boundary locates it (the
+// linear zero crossing of the signed distance towards the external point below, or the
+// south box wall dy/2 below row 0 when nearer); without the correction the staircase
+// wall is at the external point (dy).  j1 = -1, d1 = 0 for a column with no internal u.
+__global__ __launch_bounds__(256) void k_geom_south_wall(GridParams g, const double* __restrict__ su, int ibm_on,
+                                                        int32_t* __restrict__ wj, double* __restrict__ wd) {
+  const int i = blockIdx.x * BX + threadIdx.x;
+  const int k = blockIdx.y * BZ + threadIdx.y;
+  if (i >= g.nx || k >= g.nz) return;
+  const size_t plane = (size_t)g.nx * g.nz;
+  const int col = k * g.nx + i;
+  int j1 = -1;
+  double sP = 0.0;
+  for (int j = 0; j < g.ny1; ++j) {
+    const double sj = su[(size_t)(j + 1) * plane + col];   // row j is SDF row j + 1
+    if (sj > 0.0) {
+      j1 = j;
+      sP = sj;
+      break;
+    }
+  }
+  double d = 0.0;
+  if (j1 >= 0) {
+    if (ibm_on) {
+      const double sdn = su[(size_t)j1 * plane + col];
+      d = (sdn <= 0.0) ? g.dy * sP / (sP - sdn) : INFINITY;
+      if (j1 == 0) d = fmin(d, 0.5 * g.dy);
+    } else {
+      d = g.dy;
+    }
+  }
+  wj[col] = j1;
+  wd[col] = d;
+}
+
 // Count cells whose tag has `mask` set, per block of 256 cells.
 __global__ __launch_bounds__(256) void k_count_flags(const uint8_t* __restrict__ tag, int64_t n, uint8_t mask,
                                                     int32_t* __restrict__ counts) {
@@ -378,6 +414,71 @@ __global__ __launch_bounds__(256) void k_reduce_final(const double* __restrict__
   if (threadIdx.x == 0) out[col] = r;
 }
 
+// Spanwise-averaged wall-shear stress tau(x_i) = nu du/dy at the south wall (Sec. 4.2):
+// per column the parabola through the wall (0 at distance 0), u1 at d1 and u2 one row
+// above (d1 + dy), or the straight line through the wall and u1 where that row is not
+// internal.  Block (64, 16): x lanes, 16 rows of z columns summed in a fixed order.
+constexpr int WS_Z = 16;
+template <typename T>
+__global__ __launch_bounds__(BX * WS_Z) void k_wall_shear(GridParams g, const T* __restrict__ u,
+                                                         const uint8_t* __restrict__ tag,
+                                                         const int32_t* __restrict__ wj,
+                                                         const double* __restrict__ wd, double* __restrict__ tau_x) {
+  __shared__ double red[WS_Z][BX];
+  const int i = blockIdx.x * BX + threadIdx.x;
+  const size_t plane = (size_t)g.nx * g.nz;
+  double acc = 0.0;
+  if (i < g.nx) {
+    for (int k = threadIdx.y; k < g.nz; k += WS_Z) {
+      const int col = k * g.nx + i;
+      const int j1 = wj[col];
+      if (j1 < 0) continue;
+      const double a = wd[col];
+      const size_t c = (size_t)j1 * plane + col;
+      const double u1 = (double)u[c];
+      if (j1 + 1 < g.ny1 && (tag[c + plane] & TAG_U)) {
+        const double b = a + g.dy, u2 = (double)u[c + plane];
+        acc += (u1 * b * b - u2 * a * a) / (a * b * (b - a));
+      } else {
+        acc += u1 / a;
+      }
+    }
+  }
+  red[threadIdx.y][threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.y == 0 && i < g.nx) {
+    double sum = 0.0;
+    for (int r = 0; r < WS_Z; ++r) sum += red[r][threadIdx.x];
+    tau_x[i] = g.nu * sum / g.nz;
+  }
+}
+
+// Mean and first Fourier components over the box length of tau(x_i), x_i = i dx:
+// out = (sum tau / nx, (2/nx) sum tau cos(2 pi i/nx), (2/nx) sum tau sin(2 pi i/nx)).
+__global__ __launch_bounds__(256) void k_tau_modes(const double* __restrict__ tau_x, int nx,
+                                                  double* __restrict__ out) {
+  __shared__ double red[4];
+  double s0 = 0.0, sc = 0.0, ss = 0.0;
+  for (int i = threadIdx.x; i < nx; i += blockDim.x) {
+    double sn, cs;
+    sincospi(2.0 * (double)i / (double)nx, &sn, &cs);
+    const double t = tau_x[i];
+    s0 += t;
+    sc += t * cs;
+    ss += t * sn;
+  }
+  const double r0 = block_reduce<false>(s0, red);
+  __syncthreads();
+  const double rc = block_reduce<false>(sc, red);
+  __syncthreads();
+  const double rs = block_reduce<false>(ss, red);
+  if (threadIdx.x == 0) {
+    out[0] = r0 / nx;
+    out[1] = 2.0 * rc / nx;
+    out[2] = 2.0 * rs / nx;
+  }
+}
+
 }  // namespace
 
 static inline dim3 cell_grid(const GridParams& g) {
@@ -396,6 +497,26 @@ hipError_t launch_geom_ptag(const GridParams& g, uint8_t* tag, hipStream_t st) {
   hipLaunchKernelGGL(k_geom_ptag, cell_grid(g), dim3(BX, BZ), 0, st, g, tag);
   return hipGetLastError();
 }
+
+hipError_t launch_geom_south_wall(const GridParams& g, const double* su, int ibm_on, int32_t* wj, double* wd,
+                                  hipStream_t st) {
+  const dim3 grid((g.nx + BX - 1) / BX, (g.nz + BZ - 1) / BZ, 1);
+  hipLaunchKernelGGL(k_geom_south_wall, grid, dim3(BX, BZ), 0, st, g, su, ibm_on, wj, wd);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_wall_shear(const GridParams& g, const T* u, const uint8_t* tag, const int32_t* wj,
+                             const double* wd, double* tau_x, double* modes, hipStream_t st) {
+  hipLaunchKernelGGL(k_wall_shear<T>, dim3((g.nx + BX - 1) / BX), dim3(BX, WS_Z), 0, st, g, u, tag, wj, wd,
+                     tau_x);
+  if (modes) hipLaunchKernelGGL(k_tau_modes, dim3(1), dim3(256), 0, st, tau_x, g.nx, modes);
+  return hipGetLastError();
+}
+template hipError_t launch_wall_shear<double>(const GridParams&, const double*, const uint8_t*, const int32_t*,
+                                              const double*, double*, double*, hipStream_t);
+template hipError_t launch_wall_shear<float>(const GridParams&, const float*, const uint8_t*, const int32_t*,
+                                             const double*, double*, double*, hipStream_t);
 
 hipError_t launch_count_flags(const uint8_t* tag, int64_t n, uint8_t mask, int32_t* blk_counts, int nblk,
                               hipStream_t st) {

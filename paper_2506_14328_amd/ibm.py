@@ -28,7 +28,7 @@ EXPORTED = [
     "ibm_create_grid", "ibm_set_geometry", "ibm_set_state", "ibm_get_state", "ibm_step",
     "ibm_solve_pressure", "ibm_stats", "ibm_set_diagnostics", "ibm_get_geometry", "ibm_get_ibm_list",
     "ibm_profile", "ibm_profile_read", "ibm_kernel_name", "ibm_num_kernels", "ibm_device_bytes",
-    "ibm_destroy", "ibm_last_error", "ibm_tune_set", "ibm_tune_get", "ibm_autotune",
+    "ibm_destroy", "ibm_last_error", "ibm_tune_set", "ibm_tune_get", "ibm_autotune", "ibm_wall_shear",
 ]
 TUNE_PARAMS = {"momentum_planes": 0, "fftz_width": 1, "tri_rows": 2, "graph": 3, "graph_branches": 4,
                "tile_order": 5, "batch": 6}
@@ -76,6 +76,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "ibm_step": (c_int32, [h, c_int32]),
         "ibm_solve_pressure": (c_int32, [h, c_int32, c_void_p, c_void_p]),
         "ibm_stats": (c_int32, [h, c_int32, POINTER(IbmStats)]),
+        "ibm_wall_shear": (c_int32, [h, c_int32, c_void_p, POINTER(c_double)]),
         "ibm_set_diagnostics": (c_int32, [h, c_int32]),
         "ibm_get_geometry": (c_int32, [h, c_int32, c_void_p, POINTER(c_int64)]),
         "ibm_get_ibm_list": (c_int32, [h, c_int32, c_int32, c_void_p, c_void_p, c_void_p]),
@@ -210,6 +211,14 @@ class IbmGrid:
         d["n_ibm"] = list(s.n_ibm)
         d["unstable"] = rc == IBM_ERR_UNSTABLE
         return d
+
+    def wall_shear(self, inst: int = 0) -> Tuple[torch.Tensor, Tuple[float, float, float]]:
+        """Spanwise-averaged south-wall shear stress tau(x_i) (device, float64) and
+        (tau_0, tau_1c, tau_1s) of the current state (ibm_wall_shear)."""
+        tau = torch.empty(self.shape_of(inst)[2], dtype=torch.float64, device=self.device)
+        modes = (c_double * 3)()
+        self._check(self.lib.ibm_wall_shear(self._h, inst, _ptr(tau), modes))
+        return tau, (modes[0], modes[1], modes[2])
 
     def geometry(self, inst: int = 0) -> Tuple[torch.Tensor, list]:
         tags = torch.empty(self.shape_of(inst), dtype=torch.uint8, device=self.device)

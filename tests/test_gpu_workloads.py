@@ -273,7 +273,72 @@ def test_open_channel_full_size_parity():
     for a, b in ((u, o.u), (v, o.v), (w, o.w)):
         assert rel_err(a, b) < 1e-12
     assert g.stats()["n_ibm"][0] > 0
+    # wall-shear profile of the undulated bottom and its modes tau_0, tau_1c, tau_1s
+    from oracle.ibm_oracle import wall_shear_modes, wall_shear_profile
+    from tests.test_gpu_wall_shear import _tau_tol
+    tau, modes = g.wall_shear()
+    ref = wall_shear_profile(o.g, o.u, sdf[0])
+    tol = _tau_tol(o.g, sdf[0], 1e-12 * np.abs(o.u).max()) + 1e-14 * np.abs(ref).max()
+    e = np.abs(tau.cpu().numpy() - ref).max()
+    _say(f"tau(x): max err {e:.2e} (bound {tol:.2e}); modes {modes} vs {wall_shear_modes(o.g, ref)}")
+    assert e <= tol
+    for got, want in zip(modes, wall_shear_modes(o.g, ref)):
+        assert abs(got - want) <= 2 * tol
     g.close()
+
+
+def _open_steady(n, ibm, nu=0.02):
+    """Steady laminar open channel over the undulated bottom of Sec. 4.2 (eps 0.05,
+    alpha 1/2, L_x = 4 pi, free-slip top at 1; Re_b = 1/nu) with dx ~ dy = 1/n and two
+    spanwise points: (tau_0, tau_1c, tau_1s), Pi and the steps taken."""
+    from paper_2506_14328_amd import IbmGrid
+    nx = {16: 200, 32: 400, 64: 800}[n]
+    dt = 0.16 / n
+    c = I.Case(nx=nx, ny=n + 1, nz=2, lx=4 * math.pi, lz=0.5, y_lo=0.0, y_hi=1.0, nu=nu, dt=dt, forcing=0,
+               q_target_or_pi=0.95 * 0.5, name=f"open_laminar_{n}", seed=1, geometry="wavy_open",
+               geo_params=(0.05, 0.5), top=1)
+    sdf = I.make_sdf(c)
+    u0, v0, w0 = I.laminar_plus_solenoidal(c, sdf, 1, amp=0.0, profile=I.open_channel_profile(c, 0.05, 0.5))
+    g = IbmGrid.from_case(c, ibm=ibm)
+    g.set_geometry(*[to_dev(a) for a in sdf])
+    g.set_state(*[to_dev(a) for a in (u0, v0, w0, np.zeros_like(u0))])
+    chunk = int(round(20.0 / dt))
+    prev, change = None, None
+    for _ in range(40):
+        g.step(chunk)
+        _, m = g.wall_shear()
+        if prev is not None:
+            change = max(abs(a - b) for a, b in zip(m, prev))
+            if change < 1e-12:
+                break
+        prev = m
+    s = g.stats()
+    g.close()
+    assert s["nan_flag"] == 0
+    return m, s["pi_last"], s["step"], change
+
+
+@pytest.mark.parametrize("ibm", [True, False])
+def test_open_channel_wall_shear_refinement_trend(ibm):
+    """Wall-shear modes of the steady laminar open channel on three grids refined by 2 in
+    every direction (dy = 1/16, 1/32, 1/64).  Each run reaches a steady state (modes
+    unchanged to 1e-12 over 20 time units); the differences between successive grids of
+    tau_0 (and, with the immersed boundary, of tau_1s and Pi) shrink.  The observed orders
+    are printed; no order is asserted (the paper's order 1.9 is for the turbulent average)."""
+    res = []
+    for n in (16, 32, 64):
+        m, pi, steps, change = _open_steady(n, ibm)
+        _say(f"[ibm={ibm}] dy=1/{n}: tau_0 {m[0]:.8e} tau_1c {m[1]:.8e} tau_1s {m[2]:.8e} Pi {pi:.8e} "
+             f"({steps} steps, last change {change:.1e})")
+        assert change < 1e-12
+        res.append((m[0], m[1], m[2], pi))
+    names = ("tau_0", "tau_1c", "tau_1s", "Pi")
+    for q, name in enumerate(names):
+        d1, d2 = res[0][q] - res[1][q], res[1][q] - res[2][q]
+        _say(f"[ibm={ibm}] {name}: differences {d1:.3e} {d2:.3e}, observed order {math.log2(abs(d1 / d2)):.2f}")
+    checked = (0, 2, 3) if ibm else (0,)
+    for q in checked:
+        assert abs(res[1][q] - res[2][q]) < abs(res[0][q] - res[1][q]), names[q]
 
 
 def test_ellipsoids_full_size_one_step_parity():
