@@ -59,6 +59,7 @@ class Case:
     geometry: str = "flat"
     geo_params: Tuple = ()
     top: int = 0       # 0 = no-slip north box face, 1 = free-slip north face (open channel)
+    projection: int = 0  # 0 = full-box pressure projection, 1 = masked (internal cells only)
 
     @property
     def dx(self) -> float:

@@ -60,6 +60,7 @@ class OGrid:
     q_target_or_pi: float = 0.0
     b_mode: int = B_EXP
     top: int = 0          # 0: no-slip north box face; 1: free-slip north face
+    projection: int = 0   # 0: full-box projection (reading R6); 1: masked (reading R18)
 
     @property
     def dx(self):
@@ -80,7 +81,8 @@ class OGrid:
     @classmethod
     def from_case(cls, c) -> "OGrid":
         return cls(c.nx, c.ny, c.nz, c.lx, c.lz, c.y_lo, c.y_hi, c.nu, c.dt,
-                   c.forcing, c.q_target_or_pi, c.b_mode, int(getattr(c, "top", 0)))
+                   c.forcing, c.q_target_or_pi, c.b_mode, int(getattr(c, "top", 0)),
+                   int(getattr(c, "projection", 0)))
 
 
 # --------------------------------------------------------------------------------------
@@ -352,6 +354,71 @@ def poisson_solve(g: OGrid, rhs: np.ndarray) -> Tuple[np.ndarray, float]:
     return phi, float(mean00.real) / (g.nx * g.nz)
 
 
+def masked_laplacian(g: OGrid, tags) -> Tuple["scipy.sparse.csr_matrix", np.ndarray]:
+    """D M G restricted to the internal pressure cells (reading R18).
+
+    M keeps the gradient only on internal velocity faces (the external ones are never
+    corrected, Sec. 3.3), so each internal face couples the two pressure cells it
+    separates with weight 1/h^2 (an internal face always lies between two internal
+    cells).  Returns the sparse matrix over the internal cells (in C order of the
+    (j, k, i) cell array) and the flat indices of those cells.
+    """
+    import scipy.sparse as sp
+    pin = tags["p"]
+    cells = np.flatnonzero(pin.ravel())
+    pos = -np.ones(pin.size, dtype=np.int64)
+    pos[cells] = np.arange(cells.size)
+    ny1, nz, nx = pin.shape
+    jj, kk, ii = np.meshgrid(np.arange(ny1), np.arange(nz), np.arange(nx), indexing="ij")
+    lin = (jj * nz + kk) * nx + ii
+    rows, cols, vals = [], [], []
+    # u face i of cell (j, k, i) joins cells i-1 and i; v face j joins rows j-1 and j
+    # (face 0 is the south box wall, never internal); w face k joins k-1 and k
+    for face, other, h in ((tags["u"], (jj * nz + kk) * nx + (ii - 1) % nx, g.dx),
+                           (tags["v"], ((jj - 1) * nz + kk) * nx + ii, g.dy),
+                           (tags["w"], (jj * nz + (kk - 1) % nz) * nx + ii, g.dz)):
+        a = pos[lin[face]]
+        b = pos[other[face]]
+        if (a < 0).any() or (b < 0).any():
+            raise ValueError("internal face next to an external pressure cell")
+        wgt = 1.0 / (h * h)
+        rows += [a, b, a, b]
+        cols += [b, a, a, b]
+        vals += [np.full(a.size, wgt), np.full(a.size, wgt), np.full(a.size, -wgt), np.full(a.size, -wgt)]
+    L = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(cells.size, cells.size))
+    return L, cells
+
+
+def masked_poisson_solve(g: OGrid, rhs: np.ndarray, tags) -> Tuple[np.ndarray, float]:
+    """Solve D M G phi = rhs on the internal pressure cells only (reading R18).
+
+    The operator is singular (constants); the solution with zero sum over the internal
+    cells is taken, from the augmented system [L 1; 1^T 0][phi; mu] = [rhs; 0] solved
+    by a sparse direct factorisation (mu absorbs the rounding-level inconsistency of
+    rhs).  The internal cells must form one connected set through internal faces.
+    Returns phi (zero outside the internal cells) and the relative residual
+    ||L phi - rhs|| / ||rhs|| (2-norms over the internal cells).
+    """
+    import scipy.sparse as sp
+    import scipy.sparse.csgraph as csg
+    import scipy.sparse.linalg as spla
+    L, cells = masked_laplacian(g, tags)
+    n = cells.size
+    ncomp, _ = csg.connected_components(L != 0, directed=False)
+    if ncomp != 1:
+        raise ValueError(f"internal pressure cells form {ncomp} disconnected sets")
+    ones = np.ones((n, 1))
+    K = sp.bmat([[L, sp.csr_matrix(ones)], [sp.csr_matrix(ones.T), None]], format="csc")
+    b = rhs.ravel()[cells]
+    sol = spla.spsolve(K, np.concatenate([b, [0.0]]))
+    x = sol[:n]
+    phi = np.zeros(rhs.size)
+    phi[cells] = x
+    res = float(np.linalg.norm(L @ x - b) / max(np.linalg.norm(b), 1e-300))
+    return phi.reshape(rhs.shape), res
+
+
 # --------------------------------------------------------------------------------------
 # Solver state and the RK3 substep (Sec. 2.4, Eq. (16); Sec. 2.1 projection)
 # --------------------------------------------------------------------------------------
@@ -434,19 +501,29 @@ class Oracle:
         self.pi_last = pi
         # projection (Sec. 2.1; continuity on the full box, Sec. 3.3, reading R6)
         rhs = divergence(g, us, vs, ws) / (ck * dt)
-        phi, mean_removed = poisson_solve(g, rhs)
-        Gx, Gy, Gz = gradient(g, phi)
-        un = us - ck * dt * Gx
-        vn = vs - ck * dt * Gy
-        vn[0] = 0.0                                                     # south box wall
-        wn = ws - ck * dt * Gz
-        div_full = divergence(g, un, vn, wn)
-        resid = divergence(g, *gradient_full(g, phi)) - (rhs - mean_removed)
-        self.diag = {
-            "div_max_fullbox": float(np.abs(div_full).max()),
-            "poisson_rel_residual": float(np.abs(resid).max() / max(np.abs(rhs).max(), 1e-300)),
-            "rhs_mean_removed": mean_removed,
-        }
+        if g.projection == 1:
+            # masked projection (reading R18): continuity on the internal cells only
+            phi, res = masked_poisson_solve(g, rhs, t)
+            Gx, Gy, Gz = gradient(g, phi)
+            un = us - ck * dt * Gx
+            vn = vs - ck * dt * Gy
+            vn[0] = 0.0
+            wn = ws - ck * dt * Gz
+            self.diag = {"div_max_fullbox": 0.0, "poisson_rel_residual": res, "rhs_mean_removed": 0.0}
+        else:
+            phi, mean_removed = poisson_solve(g, rhs)
+            Gx, Gy, Gz = gradient(g, phi)
+            un = us - ck * dt * Gx
+            vn = vs - ck * dt * Gy
+            vn[0] = 0.0                                                     # south box wall
+            wn = ws - ck * dt * Gz
+            div_full = divergence(g, un, vn, wn)
+            resid = divergence(g, *gradient_full(g, phi)) - (rhs - mean_removed)
+            self.diag = {
+                "div_max_fullbox": float(np.abs(div_full).max()),
+                "poisson_rel_residual": float(np.abs(resid).max() / max(np.abs(rhs).max(), 1e-300)),
+                "rhs_mean_removed": mean_removed,
+            }
         # external faces back to zero (Sec. 3.3); only internal pressure is updated
         self.u = np.where(t["u"], un, 0.0)
         self.v = np.where(t["v"], vn, 0.0)
