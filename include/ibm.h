@@ -59,6 +59,7 @@ enum { IBM_FP64 = 0, IBM_FP32_STORAGE = 1 };
 enum { IBM_CFR = 0, IBM_CPG = 1 };               /* constant flow rate / pressure gradient */
 enum { IBM_B_EXP = 0, IBM_B_EULER = 1, IBM_B_TAYLOR2 = 2 };
 enum { IBM_TOP_WALL = 0, IBM_TOP_FREE_SLIP = 1 };   /* condition at the north box face y_hi */
+enum { IBM_PROJ_FULL_BOX = 0, IBM_PROJ_MASKED = 1 }; /* pressure projection, see ibm_grid_desc */
 
 typedef struct ibm_ctx* ibm_handle;
 
@@ -79,6 +80,21 @@ typedef struct {
                            one); IBM_TOP_FREE_SLIP: free-slip surface there (v = 0,
                            du/dy = dw/dy = 0: the row above mirrors the top row of u and w),
                            the open channel of Sec. 4.2 */
+  int32_t projection;   /* IBM_PROJ_FULL_BOX: continuity on every cell of the box, one
+                           FFT/tridiagonal solve per substep, external faces reset to zero
+                           afterwards (Sec. 2.1, Sec. 3.3);
+                           IBM_PROJ_MASKED: continuity on the internal pressure cells only,
+                           D M G phi = D u_p / (c_k dt) (u_p the predictor) with M keeping the internal faces (the
+                           external ones are never corrected, Sec. 3.3 read strictly), solved
+                           by conjugate gradients preconditioned with the full-box solve and
+                           started from its solution; phi has zero mean over the internal
+                           cells.  IBM_FP64 only; ibm_step then launches eagerly (no graph)
+                           and synchronises once per iteration; IBM_ERR_UNSTABLE if the
+                           iteration cap is reached.  The internal pressure cells must be
+                           connected through internal faces. */
+  int32_t pcg_max_iter; /* masked: iteration cap per solve (<= 0: 500) */
+  double pcg_tol;       /* masked: stop at ||r||_2 <= pcg_tol ||b||_2 over the internal cells,
+                           b = D u_p / (c_k dt) (<= 0: 1e-13) */
 } ibm_grid_desc;
 
 typedef struct {
@@ -89,7 +105,9 @@ typedef struct {
   double div_max_fullbox;       /* max |D u| after the last projection, before external
                                    faces are reset (needs ibm_set_diagnostics(h, 1)) */
   double div_max_internal_leak; /* max |D u| over internal pressure cells, current state */
-  double poisson_rel_residual;  /* ||D G phi - (rhs - mean)||_inf / ||rhs||_inf (diagnostics on) */
+  double poisson_rel_residual;  /* ||D G phi - (rhs - mean)||_inf / ||rhs||_inf (diagnostics on);
+                                   masked projection: ||r||_2 / ||b||_2 at the end of the last
+                                   conjugate-gradient solve */
   double rhs_mean_removed;      /* mean of the Poisson right-hand side removed by the gauge */
   double ke;                    /* 1/2 sum |u|^2 dx dy dz */
   double cfl_max;               /* max (|u|/dx + |v|/dy + |w|/dz) dt */
@@ -97,7 +115,7 @@ typedef struct {
   int64_t n_ibm[3];             /* points with lambda > 0 per component */
   int64_t n_p_internal;         /* internal pressure cells */
   int32_t nan_flag;             /* 1 if any field holds NaN/Inf */
-  int32_t reserved;
+  int32_t pcg_iters;            /* masked projection: iterations of the last solve; else 0 */
 } ibm_stats_t;
 
 /* Create n_inst independent channel instances (an ensemble of ragged sizes is

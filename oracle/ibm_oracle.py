@@ -393,10 +393,14 @@ def masked_laplacian(g: OGrid, tags) -> Tuple["scipy.sparse.csr_matrix", np.ndar
 def masked_poisson_solve(g: OGrid, rhs: np.ndarray, tags) -> Tuple[np.ndarray, float]:
     """Solve D M G phi = rhs on the internal pressure cells only (reading R18).
 
-    The operator is singular (constants); the solution with zero sum over the internal
-    cells is taken, from the augmented system [L 1; 1^T 0][phi; mu] = [rhs; 0] solved
-    by a sparse direct factorisation (mu absorbs the rounding-level inconsistency of
-    rhs).  The internal cells must form one connected set through internal faces.
+    The operator is singular (constants) and rhs sums to zero over the internal cells
+    (every boundary face of the set carries no flux), so the system is consistent.  The
+    solution with zero sum over the internal cells is taken: the rounding-level mean of
+    rhs over the internal cells is removed (the least-squares reading of the system),
+    the first internal cell is pinned to zero and its equation, implied by the others,
+    dropped; the remaining nonsingular system is solved by a sparse direct factorisation
+    and the mean over the internal cells removed.  The internal cells must form one
+    connected set through internal faces.
     Returns phi (zero outside the internal cells) and the relative residual
     ||L phi - rhs|| / ||rhs|| (2-norms over the internal cells).
     """
@@ -408,11 +412,12 @@ def masked_poisson_solve(g: OGrid, rhs: np.ndarray, tags) -> Tuple[np.ndarray, f
     ncomp, _ = csg.connected_components(L != 0, directed=False)
     if ncomp != 1:
         raise ValueError(f"internal pressure cells form {ncomp} disconnected sets")
-    ones = np.ones((n, 1))
-    K = sp.bmat([[L, sp.csr_matrix(ones)], [sp.csr_matrix(ones.T), None]], format="csc")
     b = rhs.ravel()[cells]
-    sol = spla.spsolve(K, np.concatenate([b, [0.0]]))
-    x = sol[:n]
+    bc = b - b.mean()
+    x = np.zeros(n)
+    if n > 1:
+        x[1:] = spla.spsolve(sp.csc_matrix(L[1:, 1:]), bc[1:])
+    x -= x.mean()
     phi = np.zeros(rhs.size)
     phi[cells] = x
     res = float(np.linalg.norm(L @ x - b) / max(np.linalg.norm(b), 1e-300))

@@ -38,10 +38,15 @@ struct Instance {
   uint8_t* tag = nullptr;
   double* qpart = nullptr;
   double* red_part = nullptr;
-  double* small = nullptr;         // S3[3] pi[1] pi_hist[2] mean[1] red_out[8] diag_out[4]
+  double* small = nullptr;         // S3[3] pi[1] pi_hist[2] mean[1] red_out[8] diag_out[4] .. pcg[8]
   int32_t* itotal = nullptr;
   double2* rtw = nullptr;
   double *kx2 = nullptr, *kz2 = nullptr;
+  // masked projection: conjugate-gradient vectors r, z, p, A p and partial sums
+  double* pcg_v[4] = {};
+  double* pcg_part = nullptr;
+  int pcg_iters = 0;        // iterations of the last masked solve
+  double pcg_res = 0.0;     // its final |r| / |b|
   // south-wall point per (k, i) column (row, distance) and wall-shear output [nx + 3]
   int32_t* wall_j = nullptr;
   double* wall_d = nullptr;
@@ -62,6 +67,7 @@ struct Instance {
   double* mean() { return small + 6; }
   double* red_out() { return small + 7; }
   double* diag_out() { return small + 15; }
+  double* pcg_sc() { return small + 20; }   // rho[2] |b|^2 saved-mean |r|^2
 };
 
 }  // namespace
@@ -200,6 +206,10 @@ int validate(ibm_ctx* c, const ibm_grid_desc& d) {
   if (d.forcing != IBM_CFR && d.forcing != IBM_CPG) return fail(c, IBM_ERR_ARG, "invalid forcing");
   if (d.b_mode < 0 || d.b_mode > 2) return fail(c, IBM_ERR_ARG, "invalid b_mode");
   if (d.top != IBM_TOP_WALL && d.top != IBM_TOP_FREE_SLIP) return fail(c, IBM_ERR_ARG, "invalid top");
+  if (d.projection != IBM_PROJ_FULL_BOX && d.projection != IBM_PROJ_MASKED)
+    return fail(c, IBM_ERR_ARG, "invalid projection");
+  if (d.projection == IBM_PROJ_MASKED && c->precision != IBM_FP64)
+    return fail(c, IBM_ERR_ARG, "the masked projection needs IBM_FP64");
   return IBM_OK;
 }
 
@@ -258,6 +268,11 @@ int init_instance(ibm_ctx* c, Instance& I, const ibm_grid_desc& d) {
   if ((rc = dalloc(c, I, (void**)&I.small, 32 * sizeof(double)))) return rc;
   HIPCHK(c, hipMemsetAsync(I.small, 0, 32 * sizeof(double), c->stream));
   if ((rc = dalloc(c, I, (void**)&I.itotal, 16 * sizeof(int32_t)))) return rc;
+  if (d.projection == IBM_PROJ_MASKED) {
+    for (int q = 0; q < 4; ++q)
+      if ((rc = dalloc(c, I, (void**)&I.pcg_v[q], (size_t)g.ncell * sizeof(double)))) return rc;
+    if ((rc = dalloc(c, I, (void**)&I.pcg_part, (size_t)PCG_NSLOT * PCG_NPART * sizeof(double)))) return rc;
+  }
   const size_t ncol = (size_t)g.nx * g.nz;
   if ((rc = dalloc(c, I, (void**)&I.wall_j, ncol * sizeof(int32_t)))) return rc;
   if ((rc = dalloc(c, I, (void**)&I.wall_d, ncol * sizeof(double)))) return rc;
@@ -343,6 +358,49 @@ int poisson(ibm_ctx* c, Instance& I, Fields<T>& f, T* phi_out, hipStream_t st) {
   return IBM_OK;
 }
 
+// Masked projection of the current substep: f.phi holds the full-box solution, which
+// starts the conjugate gradients and is replaced by the masked one (zero mean over the
+// internal cells, zero elsewhere).  The residual norm is read back after every
+// iteration, so this synchronises the stream.
+int pcg_project(ibm_ctx* c, Instance& I, Fields<double>& f, hipStream_t st) {
+  const GridParams& g = I.g;
+  double* x = f.phi;
+  double *r = I.pcg_v[0], *z = I.pcg_v[1], *p = I.pcg_v[2], *ap = I.pcg_v[3];
+  double* part = I.pcg_part;
+  double* sc = I.pcg_sc();
+  const double tol = I.d.pcg_tol > 0.0 ? I.d.pcg_tol : 1e-13;
+  const int max_iter = I.d.pcg_max_iter > 0 ? I.d.pcg_max_iter : 500;
+  HIPCHK(c, hipMemcpyAsync(sc + 3, I.mean(), sizeof(double), hipMemcpyDeviceToDevice, st));
+  RUNK(c, K_PCG, launch_pcg_init(g, I.tag, x, sc + 3, r, part, st));
+  RUNK(c, K_PCG, launch_pcg_total(g, part, PCG_B, sc + 2, st));
+  RUNK(c, K_PCG, launch_pcg_total(g, part, PCG_R2, sc + 4, st));
+  double host[3];
+  HIPCHK(c, hipMemcpyAsync(host, sc + 2, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(c, hipStreamSynchronize(st));
+  const double bb = host[0];
+  double rr = host[2];
+  int it = 0;
+  while (rr > tol * tol * bb && it < max_iter) {
+    RUNK(c, K_DIV_FFTX, launch_div_fftx<double>(g, f, I.L, 0, I.px, I.rtw, 1.0, I.pi(), r, st));
+    int rc = poisson<double>(c, I, f, z, st);
+    if (rc) return rc;
+    RUNK(c, K_PCG, launch_pcg_rz(g, r, z, part, st));
+    RUNK(c, K_PCG, launch_pcg_dir(g, I.tag, z, p, part, sc, it, st));
+    RUNK(c, K_PCG, launch_pcg_apply(g, I.tag, p, ap, part, st));
+    RUNK(c, K_PCG, launch_pcg_step(g, I.tag, x, r, p, ap, part, sc, it, st));
+    RUNK(c, K_PCG, launch_pcg_total(g, part, PCG_R2, sc + 4, st));
+    HIPCHK(c, hipMemcpyAsync(&rr, sc + 4, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    ++it;
+  }
+  RUNK(c, K_PCG, launch_pcg_finish(g, I.tag, x, part, I.n_pint, st));
+  HIPCHK(c, hipMemcpyAsync(I.mean(), sc + 3, sizeof(double), hipMemcpyDeviceToDevice, st));
+  I.pcg_iters = it;
+  I.pcg_res = bb > 0.0 ? std::sqrt(rr / bb) : 0.0;
+  if (!(rr <= tol * tol * bb)) return fail(c, IBM_ERR_UNSTABLE, "masked projection did not converge");
+  return IBM_OK;
+}
+
 // nsteps RK3 steps of one instance, launched on st.  count: advance the step/time
 // counters (false while the launches are only being captured into a graph).
 template <typename T>
@@ -373,7 +431,11 @@ int run_steps(ibm_ctx* c, Instance& I, int nsteps, hipStream_t st, bool count = 
       RUNK(c, K_DIV_FFTX, launch_div_fftx<T>(g, f, I.L, k, I.px, I.rtw, sc.ck_dt, I.pi(), (const T*)nullptr, st));
       int rc = poisson<T>(c, I, f, f.phi, st);
       if (rc) return rc;
-      if (c->diag && s == nsteps - 1 && k == 2) {
+      const bool masked = I.d.projection == IBM_PROJ_MASKED;
+      if constexpr (std::is_same<T, double>::value) {
+        if (masked && (rc = pcg_project(c, I, f, st))) return rc;
+      }
+      if (c->diag && s == nsteps - 1 && k == 2 && !masked) {
         int np = 0;
         RUNK(c, K_DIAG, launch_diag<T>(g, f, I.L, k, sc.ck_dt, I.pi(), I.mean(), I.red_part, &np, st));
         RUNK(c, K_DIAG, launch_reduce_final(I.red_part, np, 0, 3, I.diag_out(), st));
@@ -845,8 +907,10 @@ int ibm_step(ibm_handle h, int32_t nsteps) {
   if (nsteps < 0) return fail(h, IBM_ERR_ARG, "nsteps < 0");
   for (Instance& I : h->inst)
     if (!I.geom_ready) return fail(h, IBM_ERR_STATE, "ibm_step before ibm_set_geometry");
-  const bool batched = h->use_batch && h->inst.size() > 1 && !h->diag && !h->prof;
-  if (h->use_graph && !h->diag && !h->prof && nsteps > 0) {
+  bool masked = false;
+  for (Instance& I : h->inst) masked = masked || I.d.projection == IBM_PROJ_MASKED;
+  const bool batched = h->use_batch && h->inst.size() > 1 && !h->diag && !h->prof && !masked;
+  if (h->use_graph && !h->diag && !h->prof && !masked && nsteps > 0) {
     if (!h->gexec || (batched && !batch_current(h))) {
       const int rc = (h->precision == IBM_FP64) ? build_graph<double>(h) : build_graph<float>(h);
       if (rc) return rc;
@@ -952,7 +1016,11 @@ int ibm_stats(ibm_handle h, int32_t inst, ibm_stats_t* out) {
   out->cfl_max = ro[3];
   out->div_max_internal_leak = ro[4];
   out->rhs_mean_removed = host[6];
-  if (I.diag_valid) {
+  if (I.d.projection == IBM_PROJ_MASKED) {
+    out->div_max_fullbox = -1.0;
+    out->poisson_rel_residual = I.step > 0 ? I.pcg_res : -1.0;
+    out->pcg_iters = I.pcg_iters;
+  } else if (I.diag_valid) {
     out->div_max_fullbox = dg[0];
     out->poisson_rel_residual = dg[2] > 0.0 ? dg[1] / dg[2] : 0.0;
   } else {
@@ -1207,7 +1275,7 @@ int ibm_profile_read(ibm_handle h, double* total_ms, int64_t* launches, int32_t 
 const char* ibm_kernel_name(int32_t id) {
   static const char* names[K_NUM_KERNELS] = {"momentum", "cfr_pi", "div_fftx", "fftz_fwd", "tri", "fftz_inv",
                                              "ifftx", "correct", "diag", "stats", "geom",
-                                             "wall_shear"};
+                                             "wall_shear", "pcg"};
   if (id < 0 || id >= K_NUM_KERNELS) return "unknown";
   return names[id];
 }

@@ -21,7 +21,7 @@ enum : uint8_t {
 // Kernel ids (profiling).
 enum KernelId {
   K_MOMENTUM = 0, K_CFR_PI, K_DIV_FFTX, K_FFTZ_FWD, K_TRI, K_FFTZ_INV, K_IFFTX, K_CORRECT, K_DIAG, K_STATS,
-  K_GEOM, K_WALL_SHEAR, K_NUM_KERNELS
+  K_GEOM, K_WALL_SHEAR, K_PCG, K_NUM_KERNELS
 };
 
 template <typename T>
@@ -328,6 +328,23 @@ hipError_t launch_geom_lambda(const GridParams& g, const double* su, const doubl
 hipError_t launch_geom_ptag(const GridParams& g, uint8_t* tag, hipStream_t st);
 hipError_t launch_geom_south_wall(const GridParams& g, const double* su, int ibm_on, int32_t* wj, double* wd,
                                   hipStream_t st);
+// masked projection (conjugate gradients on the internal pressure cells): partial-sum
+// slots of PCG_NPART doubles each
+constexpr int PCG_NPART = 1024;
+enum { PCG_B = 0, PCG_R2, PCG_X, PCG_RZ, PCG_PAP, PCG_NSLOT };
+int pcg_blocks(const GridParams& g);
+hipError_t launch_pcg_init(const GridParams& g, const uint8_t* tag, const double* x, const double* mean, double* r,
+                           double* part, hipStream_t st);
+hipError_t launch_pcg_rz(const GridParams& g, const double* r, const double* z, double* part, hipStream_t st);
+hipError_t launch_pcg_dir(const GridParams& g, const uint8_t* tag, const double* z, double* p, double* part,
+                          double* sc, int it, hipStream_t st);
+hipError_t launch_pcg_apply(const GridParams& g, const uint8_t* tag, const double* p, double* ap, double* part,
+                            hipStream_t st);
+hipError_t launch_pcg_step(const GridParams& g, const uint8_t* tag, double* x, double* r, const double* p,
+                           const double* ap, double* part, const double* sc, int it, hipStream_t st);
+hipError_t launch_pcg_total(const GridParams& g, const double* part, int slot, double* out, hipStream_t st);
+hipError_t launch_pcg_finish(const GridParams& g, const uint8_t* tag, double* x, const double* part,
+                             int64_t n_internal, hipStream_t st);
 // tau_x[nx] and, if modes is not null, modes[3] = (tau_0, tau_1c, tau_1s)
 template <typename T>
 hipError_t launch_wall_shear(const GridParams& g, const T* u, const uint8_t* tag, const int32_t* wj,

@@ -1,0 +1,243 @@
+// Masked pressure projection: continuity enforced on the internal pressure cells only,
+// with the external velocity faces never corrected (Sec. 3.3 read strictly).  The
+// singular system D M G phi = D u* / (c_k dt) over the internal cells (M keeps the
+// internal faces) is solved by preconditioned conjugate gradients, the preconditioner
+// being the full-box FFT/tridiagonal solve of the projection itself; the full-box
+// solution is the starting point.  FP64 only.
+//
+// Vectors live on the full cell array; r and p are zero outside the internal cells.
+// Every reduction writes one partial per block (at most PCG_NPART blocks, grid-stride
+// loops); the kernel that needs the total re-adds the partials in the same fixed order
+// in every block, so no extra launch and no atomics are needed and the result is
+// deterministic.
+#include "ibm_internal.h"
+
+namespace {
+
+constexpr int PT = 256;
+
+__device__ __forceinline__ void decode(const GridParams& g, int c, int& j, int& k, int& i) {
+  i = c % g.nx;
+  const int r = c / g.nx;
+  k = r % g.nz;
+  j = r / g.nz;
+}
+
+// (D M G x) at cell c with MASKED, else the full-box D G x (every face but the box walls).
+template <bool MASKED>
+__device__ __forceinline__ double lap(const GridParams& g, const uint8_t* __restrict__ tag,
+                                      const double* __restrict__ x, int c, int j, int k, int i) {
+  const int nx = g.nx, nz = g.nz, plane = nx * nz;
+  const int cw = c - i + (i == 0 ? nx - 1 : i - 1);
+  const int ce = c - i + (i + 1 == nx ? 0 : i + 1);
+  const int cb = c + ((k == 0 ? nz - 1 : k - 1) - k) * nx;
+  const int cf = c + ((k + 1 == nz ? 0 : k + 1) - k) * nx;
+  bool fw, fe, fs, fn, fb, ff;
+  if (MASKED) {
+    const uint8_t t = tag[c];
+    fw = (t & TAG_U) != 0;
+    fe = (tag[ce] & TAG_U) != 0;
+    fs = (t & TAG_V) != 0;
+    fn = (j + 1 < g.ny1) && (tag[c + plane] & TAG_V);
+    fb = (t & TAG_W) != 0;
+    ff = (tag[cf] & TAG_W) != 0;
+  } else {
+    fw = fe = fb = ff = true;
+    fs = j > 0;
+    fn = j + 1 < g.ny1;
+  }
+  const double xc = x[c];
+  double s = 0.0;
+  if (fw) s += (x[cw] - xc) * g.idx2;
+  if (fe) s += (x[ce] - xc) * g.idx2;
+  if (fs) s += (x[c - plane] - xc) * g.idy2;
+  if (fn) s += (x[c + plane] - xc) * g.idy2;
+  if (fb) s += (x[cb] - xc) * g.idz2;
+  if (ff) s += (x[cf] - xc) * g.idz2;
+  return s;
+}
+
+// Sum of the nb partials, the same order in every block; every thread gets it.
+__device__ __forceinline__ double sum_partials(const double* __restrict__ part, int nb, double* smem) {
+  double s = 0.0;
+  for (int e = threadIdx.x; e < nb; e += blockDim.x) s += part[e];
+  const double r = block_reduce<false>(s, smem);
+  __syncthreads();
+  if (threadIdx.x == 0) smem[7] = r;
+  __syncthreads();
+  return smem[7];
+}
+
+__device__ __forceinline__ void put_partial(double v, double* smem, double* __restrict__ part) {
+  const double r = block_reduce<false>(v, smem);
+  if (threadIdx.x == 0) part[blockIdx.x] = r;
+  __syncthreads();
+}
+
+// r0 = b - D M G x0 with b = D G x0 + mean (the right-hand side the full-box solve x0
+// answered, the removed mean added back); partials of |b|^2, |r0|^2 and sum x0.
+__global__ __launch_bounds__(PT) void k_pcg_init(GridParams g, const uint8_t* __restrict__ tag,
+                                                const double* __restrict__ x, const double* __restrict__ mean,
+                                                double* __restrict__ r, double* __restrict__ pb,
+                                                double* __restrict__ pr, double* __restrict__ px) {
+  __shared__ double smem[8];
+  const double m = mean[0];
+  double ab = 0.0, ar = 0.0, ax = 0.0;
+  for (int c = blockIdx.x * PT + threadIdx.x; c < g.ncell; c += gridDim.x * PT) {
+    double rv = 0.0;
+    if (tag[c] & TAG_P) {
+      int j, k, i;
+      decode(g, c, j, k, i);
+      const double b = lap<false>(g, tag, x, c, j, k, i) + m;
+      rv = b - lap<true>(g, tag, x, c, j, k, i);
+      ab += b * b;
+      ar += rv * rv;
+      ax += x[c];
+    }
+    r[c] = rv;
+  }
+  put_partial(ab, smem, pb);
+  put_partial(ar, smem, pr);
+  put_partial(ax, smem, px);
+}
+
+// partials of r . z (r is zero outside the internal cells)
+__global__ __launch_bounds__(PT) void k_pcg_rz(GridParams g, const double* __restrict__ r,
+                                              const double* __restrict__ z, double* __restrict__ part) {
+  __shared__ double smem[8];
+  double a = 0.0;
+  for (int c = blockIdx.x * PT + threadIdx.x; c < g.ncell; c += gridDim.x * PT) a += r[c] * z[c];
+  put_partial(a, smem, part);
+}
+
+// rho = r . z; p = z + (rho / rho_prev) p on the internal cells (p = z at it = 0), 0
+// elsewhere; rho goes to sc[it & 1], rho_prev is read from the other slot.
+__global__ __launch_bounds__(PT) void k_pcg_dir(GridParams g, const uint8_t* __restrict__ tag,
+                                               const double* __restrict__ z, double* __restrict__ p,
+                                               const double* __restrict__ prz, int nb, double* __restrict__ sc,
+                                               int it) {
+  __shared__ double smem[8];
+  const double rho = sum_partials(prz, nb, smem);
+  const double beta = it > 0 ? rho / sc[(it + 1) & 1] : 0.0;
+  for (int c = blockIdx.x * PT + threadIdx.x; c < g.ncell; c += gridDim.x * PT) {
+    const bool in = (tag[c] & TAG_P) != 0;
+    p[c] = in ? (it > 0 ? z[c] + beta * p[c] : z[c]) : 0.0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc[it & 1] = rho;
+}
+
+// ap = D M G p on the internal cells (0 elsewhere); partials of p . ap
+__global__ __launch_bounds__(PT) void k_pcg_apply(GridParams g, const uint8_t* __restrict__ tag,
+                                                 const double* __restrict__ p, double* __restrict__ ap,
+                                                 double* __restrict__ part) {
+  __shared__ double smem[8];
+  double a = 0.0;
+  for (int c = blockIdx.x * PT + threadIdx.x; c < g.ncell; c += gridDim.x * PT) {
+    double y = 0.0;
+    if (tag[c] & TAG_P) {
+      int j, k, i;
+      decode(g, c, j, k, i);
+      y = lap<true>(g, tag, p, c, j, k, i);
+      a += p[c] * y;
+    }
+    ap[c] = y;
+  }
+  put_partial(a, smem, part);
+}
+
+// alpha = rho / (p . ap); x += alpha p, r -= alpha ap on the internal cells; partials of
+// |r|^2 and sum x there.
+__global__ __launch_bounds__(PT) void k_pcg_step(GridParams g, const uint8_t* __restrict__ tag,
+                                                double* __restrict__ x, double* __restrict__ r,
+                                                const double* __restrict__ p, const double* __restrict__ ap,
+                                                const double* __restrict__ ppap, int nb,
+                                                const double* __restrict__ sc, int it, double* __restrict__ pr,
+                                                double* __restrict__ px) {
+  __shared__ double smem[8];
+  const double pap = sum_partials(ppap, nb, smem);
+  const double alpha = pap != 0.0 ? sc[it & 1] / pap : 0.0;
+  double ar = 0.0, ax = 0.0;
+  for (int c = blockIdx.x * PT + threadIdx.x; c < g.ncell; c += gridDim.x * PT) {
+    if (tag[c] & TAG_P) {
+      const double xv = x[c] + alpha * p[c];
+      const double rv = r[c] - alpha * ap[c];
+      x[c] = xv;
+      r[c] = rv;
+      ar += rv * rv;
+      ax += xv;
+    }
+  }
+  put_partial(ar, smem, pr);
+  put_partial(ax, smem, px);
+}
+
+// out[0] = sum of the nb partials (one block)
+__global__ __launch_bounds__(PT) void k_pcg_total(const double* __restrict__ part, int nb, double* __restrict__ out) {
+  __shared__ double smem[8];
+  const double s = sum_partials(part, nb, smem);
+  if (threadIdx.x == 0) out[0] = s;
+}
+
+// gauge: phi = x - mean of x over the internal cells there, 0 elsewhere
+__global__ __launch_bounds__(PT) void k_pcg_finish(GridParams g, const uint8_t* __restrict__ tag,
+                                                  double* __restrict__ x, const double* __restrict__ px, int nb,
+                                                  double n_internal) {
+  __shared__ double smem[8];
+  const double mean = sum_partials(px, nb, smem) / n_internal;
+  for (int c = blockIdx.x * PT + threadIdx.x; c < g.ncell; c += gridDim.x * PT)
+    x[c] = (tag[c] & TAG_P) ? x[c] - mean : 0.0;
+}
+
+}  // namespace
+
+int pcg_blocks(const GridParams& g) {
+  const int64_t nb = (g.ncell + PT - 1) / PT;
+  return (int)(nb < PCG_NPART ? nb : PCG_NPART);
+}
+
+hipError_t launch_pcg_init(const GridParams& g, const uint8_t* tag, const double* x, const double* mean, double* r,
+                           double* part, hipStream_t st) {
+  const int nb = pcg_blocks(g);
+  hipLaunchKernelGGL(k_pcg_init, dim3(nb), dim3(PT), 0, st, g, tag, x, mean, r, part + PCG_B * PCG_NPART,
+                     part + PCG_R2 * PCG_NPART, part + PCG_X * PCG_NPART);
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_rz(const GridParams& g, const double* r, const double* z, double* part, hipStream_t st) {
+  hipLaunchKernelGGL(k_pcg_rz, dim3(pcg_blocks(g)), dim3(PT), 0, st, g, r, z, part + PCG_RZ * PCG_NPART);
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_dir(const GridParams& g, const uint8_t* tag, const double* z, double* p, double* part,
+                          double* sc, int it, hipStream_t st) {
+  const int nb = pcg_blocks(g);
+  hipLaunchKernelGGL(k_pcg_dir, dim3(nb), dim3(PT), 0, st, g, tag, z, p, part + PCG_RZ * PCG_NPART, nb, sc, it);
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_apply(const GridParams& g, const uint8_t* tag, const double* p, double* ap, double* part,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_pcg_apply, dim3(pcg_blocks(g)), dim3(PT), 0, st, g, tag, p, ap, part + PCG_PAP * PCG_NPART);
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_step(const GridParams& g, const uint8_t* tag, double* x, double* r, const double* p,
+                           const double* ap, double* part, const double* sc, int it, hipStream_t st) {
+  const int nb = pcg_blocks(g);
+  hipLaunchKernelGGL(k_pcg_step, dim3(nb), dim3(PT), 0, st, g, tag, x, r, p, ap, part + PCG_PAP * PCG_NPART, nb,
+                     sc, it, part + PCG_R2 * PCG_NPART, part + PCG_X * PCG_NPART);
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_total(const GridParams& g, const double* part, int slot, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_pcg_total, dim3(1), dim3(PT), 0, st, part + slot * PCG_NPART, pcg_blocks(g), out);
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_finish(const GridParams& g, const uint8_t* tag, double* x, const double* part,
+                             int64_t n_internal, hipStream_t st) {
+  const int nb = pcg_blocks(g);
+  hipLaunchKernelGGL(k_pcg_finish, dim3(nb), dim3(PT), 0, st, g, tag, x, part + PCG_X * PCG_NPART, nb,
+                     (double)n_internal);
+  return hipGetLastError();
+}

@@ -38,7 +38,8 @@ class IbmGridDesc(ctypes.Structure):
     _fields_ = [("nx", c_int32), ("ny", c_int32), ("nz", c_int32), ("forcing", c_int32),
                 ("b_mode", c_int32), ("ibm", c_int32),
                 ("lx", c_double), ("lz", c_double), ("y_lo", c_double), ("y_hi", c_double),
-                ("nu", c_double), ("dt", c_double), ("q_target_or_pi", c_double), ("top", c_int32)]
+                ("nu", c_double), ("dt", c_double), ("q_target_or_pi", c_double), ("top", c_int32),
+                ("projection", c_int32), ("pcg_max_iter", c_int32), ("pcg_tol", c_double)]
 
 
 class IbmStats(ctypes.Structure):
@@ -46,7 +47,7 @@ class IbmStats(ctypes.Structure):
                 ("div_max_fullbox", c_double), ("div_max_internal_leak", c_double),
                 ("poisson_rel_residual", c_double), ("rhs_mean_removed", c_double), ("ke", c_double),
                 ("cfl_max", c_double), ("n_internal", c_int64 * 3), ("n_ibm", c_int64 * 3),
-                ("n_p_internal", c_int64), ("nan_flag", c_int32), ("reserved", c_int32)]
+                ("n_p_internal", c_int64), ("nan_flag", c_int32), ("pcg_iters", c_int32)]
 
 
 class IbmError(RuntimeError):
@@ -105,7 +106,8 @@ def _ptr(t: torch.Tensor) -> int:
 
 def _desc(c, ibm: bool) -> IbmGridDesc:
     return IbmGridDesc(c.nx, c.ny, c.nz, c.forcing, c.b_mode, 1 if ibm else 0, c.lx, c.lz, c.y_lo, c.y_hi, c.nu,
-                       c.dt, c.q_target_or_pi, int(getattr(c, "top", 0)))
+                       c.dt, c.q_target_or_pi, int(getattr(c, "top", 0)), int(getattr(c, "projection", 0)),
+                       int(getattr(c, "pcg_max_iter", 0)), float(getattr(c, "pcg_tol", 0.0)))
 
 
 class IbmGrid:
@@ -206,7 +208,7 @@ class IbmGrid:
         rc = self.lib.ibm_stats(self._h, inst, ctypes.byref(s))
         if rc != IBM_OK and (rc != IBM_ERR_UNSTABLE or raise_unstable):
             self._check(rc)
-        d = {f: getattr(s, f) for f, _ in IbmStats._fields_ if f not in ("n_internal", "n_ibm", "reserved")}
+        d = {f: getattr(s, f) for f, _ in IbmStats._fields_ if f not in ("n_internal", "n_ibm")}
         d["n_internal"] = list(s.n_internal)
         d["n_ibm"] = list(s.n_ibm)
         d["unstable"] = rc == IBM_ERR_UNSTABLE
