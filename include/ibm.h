@@ -166,16 +166,16 @@ int ibm_stats(ibm_handle h, int32_t inst, ibm_stats_t* out);
 
 /* Wall-shear stress of the current state along the south wall, the undulated bottom
  * of the open channel (Sec. 4.2), and its Fourier components tau_1c, tau_1s defined
- * there.  Per (z_k, x_i) column of u points: the lowest internal u point, at distance
- * d1 above the wall located as the immersed boundary locates it (the linear zero
- * crossing of the u signed distance towards the external point below it, or the south
- * box wall when nearer; the external point itself without the correction), and
- * tau = nu du/dy at the wall from the parabola through the wall (velocity 0), u1 at d1
- * and u2 one row above at d1 + dy; where that row is not internal, tau = nu u1/d1.
- * tau_x[i] = mean over the nz columns at x_i = i dx (a column with no internal u point
- * adds 0).  modes = (tau_0, tau_1c, tau_1s): the mean and (2/nx) sum_i tau_x[i]
- * cos|sin(2 pi i/nx), the box length being one period.  The paper's time average is
- * the caller's mean over calls.
+ * there.  Per (z_k, x_i) column of u points: the lowest internal u point, u1, at
+ * distance d1 above the wall located as the immersed boundary locates it (the linear
+ * zero crossing of the u signed distance towards the external point below it, or the
+ * south box wall when nearer; the external point itself without the correction), and
+ * tau = nu u1 / d1, the viscous flux the discretisation exchanges with the wall through
+ * that stencil arm (its ghost value is the linear extrapolation through zero at the
+ * wall, Sec. 2.2 Eqs. (5)-(7)).  tau_x[i] = mean over the nz columns at x_i = i dx (a
+ * column with no internal u point adds 0).  modes = (tau_0, tau_1c, tau_1s): the mean
+ * and (2/nx) sum_i tau_x[i] cos|sin(2 pi i/nx), the box length being one period.  The
+ * paper's time average is the caller's mean over calls.
  * tau_x: device double[nx] or NULL; modes: host double[3] or NULL (then the call does
  * not synchronise the stream).  IBM_ERR_STATE before ibm_set_geometry. */
 int ibm_wall_shear(ibm_handle h, int32_t inst, double* tau_x, double* modes);

@@ -616,32 +616,23 @@ def south_wall_points(g: OGrid, sdf_u: np.ndarray, ibm: bool = True):
 def wall_shear_profile(g: OGrid, u: np.ndarray, sdf_u: np.ndarray, ibm: bool = True) -> np.ndarray:
     """Spanwise-averaged wall-shear stress tau(x_i) along the south wall (Sec. 4.2).
 
-    Reading R17: tau = nu du/dy at the wall, from the parabola through the no-slip wall
-    value (0 at distance 0), u1 at the lowest internal point (distance d1) and u2 at the
-    point above it (distance d1 + dy):
-        tau = nu (u1 d2^2 - u2 d1^2) / (d1 d2 (d2 - d1)),  d2 = d1 + dy,
-    exact for velocity profiles quadratic in the wall distance; where the point above is
-    not internal (or outside the box) the straight line through the wall and u1 is used,
-    tau = nu u1 / d1.  Columns without internal u points add zero; the mean is over all
-    nz columns of each x_i = i dx.
+    Reading R17: tau is the viscous flux the discretisation itself exchanges with the
+    wall.  The ghost value below the lowest internal point is the linear extrapolation
+    through zero at the wall (Sec. 2.2, Eqs. (5)-(7)), so the flux through that stencil
+    arm is nu (u1 - u_ghost)/dy = nu u1/d1, d1 the wall distance the correction uses
+    (with the bare staircase the wall is at the external point, d1 = dy).  Summed over
+    the walls this is exactly the discrete momentum balance of a steady flow (pinned).
+    Columns without internal u points add zero; the mean is over all nz columns of each
+    x_i = i dx.
     """
-    internal = sdf_u[1:-1] > 0.0
     j1, d1 = south_wall_points(g, sdf_u, ibm)
-    ny1 = g.ny - 1
     tau = np.zeros((g.nz, g.nx))
     for k in range(g.nz):
         for i in range(g.nx):
             j = int(j1[k, i])
             if j < 0:
                 continue
-            a = float(d1[k, i])
-            u1 = float(u[j, k, i])
-            if j + 1 < ny1 and internal[j + 1, k, i]:
-                b = a + g.dy
-                u2 = float(u[j + 1, k, i])
-                tau[k, i] = g.nu * (u1 * b * b - u2 * a * a) / (a * b * (b - a))
-            else:
-                tau[k, i] = g.nu * u1 / a
+            tau[k, i] = g.nu * float(u[j, k, i]) / float(d1[k, i])
     return tau.mean(axis=0)
 
 

@@ -360,8 +360,10 @@ int poisson(ibm_ctx* c, Instance& I, Fields<T>& f, T* phi_out, hipStream_t st) {
 
 // Masked projection of the current substep: f.phi holds the full-box solution, which
 // starts the conjugate gradients and is replaced by the masked one (zero mean over the
-// internal cells, zero elsewhere).  The residual norm is read back after every
-// iteration, so this synchronises the stream.
+// internal cells, zero elsewhere).  The residual norm is read back every PCG_CHECK
+// iterations (a host synchronisation each time); up to PCG_CHECK - 1 iterations beyond
+// the tolerance only refine the solution.
+constexpr int PCG_CHECK = 4;
 int pcg_project(ibm_ctx* c, Instance& I, Fields<double>& f, hipStream_t st) {
   const GridParams& g = I.g;
   double* x = f.phi;
@@ -371,7 +373,7 @@ int pcg_project(ibm_ctx* c, Instance& I, Fields<double>& f, hipStream_t st) {
   const double tol = I.d.pcg_tol > 0.0 ? I.d.pcg_tol : 1e-13;
   const int max_iter = I.d.pcg_max_iter > 0 ? I.d.pcg_max_iter : 500;
   HIPCHK(c, hipMemcpyAsync(sc + 3, I.mean(), sizeof(double), hipMemcpyDeviceToDevice, st));
-  RUNK(c, K_PCG, launch_pcg_init(g, I.tag, x, sc + 3, r, part, st));
+  RUNK(c, K_PCG, launch_pcg_init(g, I.tag, x, sc + 3, r, part, I.n_pint, st));
   RUNK(c, K_PCG, launch_pcg_total(g, part, PCG_B, sc + 2, st));
   RUNK(c, K_PCG, launch_pcg_total(g, part, PCG_R2, sc + 4, st));
   double host[3];
@@ -388,10 +390,12 @@ int pcg_project(ibm_ctx* c, Instance& I, Fields<double>& f, hipStream_t st) {
     RUNK(c, K_PCG, launch_pcg_dir(g, I.tag, z, p, part, sc, it, st));
     RUNK(c, K_PCG, launch_pcg_apply(g, I.tag, p, ap, part, st));
     RUNK(c, K_PCG, launch_pcg_step(g, I.tag, x, r, p, ap, part, sc, it, st));
-    RUNK(c, K_PCG, launch_pcg_total(g, part, PCG_R2, sc + 4, st));
-    HIPCHK(c, hipMemcpyAsync(&rr, sc + 4, sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(c, hipStreamSynchronize(st));
     ++it;
+    if (it % PCG_CHECK == 0 || it == max_iter) {
+      RUNK(c, K_PCG, launch_pcg_total(g, part, PCG_R2, sc + 4, st));
+      HIPCHK(c, hipMemcpyAsync(&rr, sc + 4, sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(c, hipStreamSynchronize(st));
+    }
   }
   RUNK(c, K_PCG, launch_pcg_finish(g, I.tag, x, part, I.n_pint, st));
   HIPCHK(c, hipMemcpyAsync(I.mean(), sc + 3, sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -975,10 +979,10 @@ int ibm_wall_shear(ibm_handle h, int32_t inst, double* tau_x, double* modes) {
   double* md = modes ? I.wall_tau + g.nx : nullptr;
   if (h->precision == IBM_FP64) {
     RUNK(h, K_WALL_SHEAR,
-         launch_wall_shear<double>(g, (const double*)I.u, I.tag, I.wall_j, I.wall_d, tx, md, h->stream));
+         launch_wall_shear<double>(g, (const double*)I.u, I.wall_j, I.wall_d, tx, md, h->stream));
   } else {
     RUNK(h, K_WALL_SHEAR,
-         launch_wall_shear<float>(g, (const float*)I.u, I.tag, I.wall_j, I.wall_d, tx, md, h->stream));
+         launch_wall_shear<float>(g, (const float*)I.u, I.wall_j, I.wall_d, tx, md, h->stream));
   }
   if (modes) {
     HIPCHK(h, hipMemcpyAsync(modes, md, 3 * sizeof(double), hipMemcpyDeviceToHost, h->stream));

@@ -331,10 +331,10 @@ hipError_t launch_geom_south_wall(const GridParams& g, const double* su, int ibm
 // masked projection (conjugate gradients on the internal pressure cells): partial-sum
 // slots of PCG_NPART doubles each
 constexpr int PCG_NPART = 1024;
-enum { PCG_B = 0, PCG_R2, PCG_X, PCG_RZ, PCG_PAP, PCG_NSLOT };
+enum { PCG_B = 0, PCG_R2, PCG_X, PCG_RZ, PCG_PAP, PCG_RS, PCG_NSLOT };
 int pcg_blocks(const GridParams& g);
 hipError_t launch_pcg_init(const GridParams& g, const uint8_t* tag, const double* x, const double* mean, double* r,
-                           double* part, hipStream_t st);
+                           double* part, int64_t n_internal, hipStream_t st);
 hipError_t launch_pcg_rz(const GridParams& g, const double* r, const double* z, double* part, hipStream_t st);
 hipError_t launch_pcg_dir(const GridParams& g, const uint8_t* tag, const double* z, double* p, double* part,
                           double* sc, int it, hipStream_t st);
@@ -347,8 +347,8 @@ hipError_t launch_pcg_finish(const GridParams& g, const uint8_t* tag, double* x,
                              int64_t n_internal, hipStream_t st);
 // tau_x[nx] and, if modes is not null, modes[3] = (tau_0, tau_1c, tau_1s)
 template <typename T>
-hipError_t launch_wall_shear(const GridParams& g, const T* u, const uint8_t* tag, const int32_t* wj,
-                             const double* wd, double* tau_x, double* modes, hipStream_t st);
+hipError_t launch_wall_shear(const GridParams& g, const T* u, const int32_t* wj, const double* wd, double* tau_x,
+                             double* modes, hipStream_t st);
 hipError_t launch_count_flags(const uint8_t* tag, int64_t n, uint8_t mask, int32_t* blk_counts,
                               int nblk, hipStream_t st);
 hipError_t launch_scan_counts(int32_t* blk_counts, int nblk, int32_t* total, hipStream_t st);

@@ -414,14 +414,14 @@ __global__ __launch_bounds__(256) void k_reduce_final(const double* __restrict__
   if (threadIdx.x == 0) out[col] = r;
 }
 
-// Spanwise-averaged wall-shear stress tau(x_i) = nu du/dy at the south wall (Sec. 4.2):
-// per column the parabola through the wall (0 at distance 0), u1 at d1 and u2 one row
-// above (d1 + dy), or the straight line through the wall and u1 where that row is not
-// internal.  Block (64, 16): x lanes, 16 rows of z columns summed in a fixed order.
+// Spanwise-averaged wall-shear stress tau(x_i) at the south wall (Sec. 4.2): the viscous
+// flux the discretisation exchanges with the wall through the cut stencil arm below the
+// lowest internal point, nu u1 / d1 (the ghost value is the linear extrapolation through
+// zero at the wall, Eqs. (5)-(7)).  Block (64, 16): x lanes, 16 rows of z columns summed
+// in a fixed order.
 constexpr int WS_Z = 16;
 template <typename T>
 __global__ __launch_bounds__(BX * WS_Z) void k_wall_shear(GridParams g, const T* __restrict__ u,
-                                                         const uint8_t* __restrict__ tag,
                                                          const int32_t* __restrict__ wj,
                                                          const double* __restrict__ wd, double* __restrict__ tau_x) {
   __shared__ double red[WS_Z][BX];
@@ -432,16 +432,7 @@ __global__ __launch_bounds__(BX * WS_Z) void k_wall_shear(GridParams g, const T*
     for (int k = threadIdx.y; k < g.nz; k += WS_Z) {
       const int col = k * g.nx + i;
       const int j1 = wj[col];
-      if (j1 < 0) continue;
-      const double a = wd[col];
-      const size_t c = (size_t)j1 * plane + col;
-      const double u1 = (double)u[c];
-      if (j1 + 1 < g.ny1 && (tag[c + plane] & TAG_U)) {
-        const double b = a + g.dy, u2 = (double)u[c + plane];
-        acc += (u1 * b * b - u2 * a * a) / (a * b * (b - a));
-      } else {
-        acc += u1 / a;
-      }
+      if (j1 >= 0) acc += (double)u[(size_t)j1 * plane + col] / wd[col];
     }
   }
   red[threadIdx.y][threadIdx.x] = acc;
@@ -506,17 +497,16 @@ hipError_t launch_geom_south_wall(const GridParams& g, const double* su, int ibm
 }
 
 template <typename T>
-hipError_t launch_wall_shear(const GridParams& g, const T* u, const uint8_t* tag, const int32_t* wj,
-                             const double* wd, double* tau_x, double* modes, hipStream_t st) {
-  hipLaunchKernelGGL(k_wall_shear<T>, dim3((g.nx + BX - 1) / BX), dim3(BX, WS_Z), 0, st, g, u, tag, wj, wd,
-                     tau_x);
+hipError_t launch_wall_shear(const GridParams& g, const T* u, const int32_t* wj, const double* wd, double* tau_x,
+                             double* modes, hipStream_t st) {
+  hipLaunchKernelGGL(k_wall_shear<T>, dim3((g.nx + BX - 1) / BX), dim3(BX, WS_Z), 0, st, g, u, wj, wd, tau_x);
   if (modes) hipLaunchKernelGGL(k_tau_modes, dim3(1), dim3(256), 0, st, tau_x, g.nx, modes);
   return hipGetLastError();
 }
-template hipError_t launch_wall_shear<double>(const GridParams&, const double*, const uint8_t*, const int32_t*,
-                                              const double*, double*, double*, hipStream_t);
-template hipError_t launch_wall_shear<float>(const GridParams&, const float*, const uint8_t*, const int32_t*,
-                                             const double*, double*, double*, hipStream_t);
+template hipError_t launch_wall_shear<double>(const GridParams&, const double*, const int32_t*, const double*,
+                                              double*, double*, hipStream_t);
+template hipError_t launch_wall_shear<float>(const GridParams&, const float*, const int32_t*, const double*,
+                                             double*, double*, hipStream_t);
 
 hipError_t launch_count_flags(const uint8_t* tag, int64_t n, uint8_t mask, int32_t* blk_counts, int nblk,
                               hipStream_t st) {

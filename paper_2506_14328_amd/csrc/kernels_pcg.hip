@@ -24,6 +24,9 @@ __device__ __forceinline__ void decode(const GridParams& g, int c, int& j, int& 
 }
 
 // (D M G x) at cell c with MASKED, else the full-box D G x (every face but the box walls).
+// Branch-free: every neighbour is loaded (a neighbour beyond a box wall is replaced by the
+// cell itself) and a face that does not count is weighted by 0, so that the loads of
+// several cells can be in flight together.
 template <bool MASKED>
 __device__ __forceinline__ double lap(const GridParams& g, const uint8_t* __restrict__ tag,
                                       const double* __restrict__ x, int c, int j, int k, int i) {
@@ -32,29 +35,21 @@ __device__ __forceinline__ double lap(const GridParams& g, const uint8_t* __rest
   const int ce = c - i + (i + 1 == nx ? 0 : i + 1);
   const int cb = c + ((k == 0 ? nz - 1 : k - 1) - k) * nx;
   const int cf = c + ((k + 1 == nz ? 0 : k + 1) - k) * nx;
-  bool fw, fe, fs, fn, fb, ff;
+  const bool has_s = j > 0, has_n = j + 1 < g.ny1;
+  const int cs = has_s ? c - plane : c, cn = has_n ? c + plane : c;
+  double fw = 1.0, fe = 1.0, fs = has_s ? 1.0 : 0.0, fn = has_n ? 1.0 : 0.0, fb = 1.0, ff = 1.0;
   if (MASKED) {
-    const uint8_t t = tag[c];
-    fw = (t & TAG_U) != 0;
-    fe = (tag[ce] & TAG_U) != 0;
-    fs = (t & TAG_V) != 0;
-    fn = (j + 1 < g.ny1) && (tag[c + plane] & TAG_V);
-    fb = (t & TAG_W) != 0;
-    ff = (tag[cf] & TAG_W) != 0;
-  } else {
-    fw = fe = fb = ff = true;
-    fs = j > 0;
-    fn = j + 1 < g.ny1;
+    const uint8_t t = tag[c], te = tag[ce], tn = tag[cn], tf = tag[cf];
+    fw = (t & TAG_U) ? 1.0 : 0.0;
+    fe = (te & TAG_U) ? 1.0 : 0.0;
+    fs = (t & TAG_V) ? 1.0 : 0.0;             // v face 0 (the south box wall) is never internal
+    fn = (has_n && (tn & TAG_V)) ? 1.0 : 0.0;
+    fb = (t & TAG_W) ? 1.0 : 0.0;
+    ff = (tf & TAG_W) ? 1.0 : 0.0;
   }
   const double xc = x[c];
-  double s = 0.0;
-  if (fw) s += (x[cw] - xc) * g.idx2;
-  if (fe) s += (x[ce] - xc) * g.idx2;
-  if (fs) s += (x[c - plane] - xc) * g.idy2;
-  if (fn) s += (x[c + plane] - xc) * g.idy2;
-  if (fb) s += (x[cb] - xc) * g.idz2;
-  if (ff) s += (x[cf] - xc) * g.idz2;
-  return s;
+  return (fw * (x[cw] - xc) + fe * (x[ce] - xc)) * g.idx2 + (fs * (x[cs] - xc) + fn * (x[cn] - xc)) * g.idy2 +
+         (fb * (x[cb] - xc) + ff * (x[cf] - xc)) * g.idz2;
 }
 
 // Sum of the nb partials, the same order in every block; every thread gets it.
@@ -75,14 +70,14 @@ __device__ __forceinline__ void put_partial(double v, double* smem, double* __re
 }
 
 // r0 = b - D M G x0 with b = D G x0 + mean (the right-hand side the full-box solve x0
-// answered, the removed mean added back); partials of |b|^2, |r0|^2 and sum x0.
+// answered, the removed mean added back); partials of |b|^2, sum r0 and sum x0.
 __global__ __launch_bounds__(PT) void k_pcg_init(GridParams g, const uint8_t* __restrict__ tag,
                                                 const double* __restrict__ x, const double* __restrict__ mean,
                                                 double* __restrict__ r, double* __restrict__ pb,
-                                                double* __restrict__ pr, double* __restrict__ px) {
+                                                double* __restrict__ prs, double* __restrict__ px) {
   __shared__ double smem[8];
   const double m = mean[0];
-  double ab = 0.0, ar = 0.0, ax = 0.0;
+  double ab = 0.0, ars = 0.0, ax = 0.0;
   for (int c = blockIdx.x * PT + threadIdx.x; c < g.ncell; c += gridDim.x * PT) {
     double rv = 0.0;
     if (tag[c] & TAG_P) {
@@ -91,14 +86,33 @@ __global__ __launch_bounds__(PT) void k_pcg_init(GridParams g, const uint8_t* __
       const double b = lap<false>(g, tag, x, c, j, k, i) + m;
       rv = b - lap<true>(g, tag, x, c, j, k, i);
       ab += b * b;
-      ar += rv * rv;
+      ars += rv;
       ax += x[c];
     }
     r[c] = rv;
   }
   put_partial(ab, smem, pb);
-  put_partial(ar, smem, pr);
+  put_partial(ars, smem, prs);
   put_partial(ax, smem, px);
+}
+
+// The operator's range is orthogonal to the constant on the internal cells, and no
+// iteration changes the sum of r: its rounding-level mean (from b, which only matches
+// the divergence to the full-box solve's accuracy) is removed here.  Partials of |r0|^2.
+__global__ __launch_bounds__(PT) void k_pcg_center(GridParams g, const uint8_t* __restrict__ tag,
+                                                  double* __restrict__ r, const double* __restrict__ prs, int nb,
+                                                  double n_internal, double* __restrict__ pr) {
+  __shared__ double smem[8];
+  const double mean = sum_partials(prs, nb, smem) / n_internal;
+  double ar = 0.0;
+  for (int c = blockIdx.x * PT + threadIdx.x; c < g.ncell; c += gridDim.x * PT) {
+    if (tag[c] & TAG_P) {
+      const double rv = r[c] - mean;
+      r[c] = rv;
+      ar += rv * rv;
+    }
+  }
+  put_partial(ar, smem, pr);
 }
 
 // partials of r . z (r is zero outside the internal cells)
@@ -118,7 +132,8 @@ __global__ __launch_bounds__(PT) void k_pcg_dir(GridParams g, const uint8_t* __r
                                                int it) {
   __shared__ double smem[8];
   const double rho = sum_partials(prz, nb, smem);
-  const double beta = it > 0 ? rho / sc[(it + 1) & 1] : 0.0;
+  const double rho_prev = it > 0 ? sc[(it + 1) & 1] : 0.0;
+  const double beta = rho_prev != 0.0 ? rho / rho_prev : 0.0;
   for (int c = blockIdx.x * PT + threadIdx.x; c < g.ncell; c += gridDim.x * PT) {
     const bool in = (tag[c] & TAG_P) != 0;
     p[c] = in ? (it > 0 ? z[c] + beta * p[c] : z[c]) : 0.0;
@@ -126,21 +141,30 @@ __global__ __launch_bounds__(PT) void k_pcg_dir(GridParams g, const uint8_t* __r
   if (blockIdx.x == 0 && threadIdx.x == 0) sc[it & 1] = rho;
 }
 
-// ap = D M G p on the internal cells (0 elsewhere); partials of p . ap
+// ap = D M G p on the internal cells (0 elsewhere); partials of p . ap.  Two cells per
+// trip, evaluated without branches (p is 0 outside the internal cells).
 __global__ __launch_bounds__(PT) void k_pcg_apply(GridParams g, const uint8_t* __restrict__ tag,
                                                  const double* __restrict__ p, double* __restrict__ ap,
                                                  double* __restrict__ part) {
   __shared__ double smem[8];
   double a = 0.0;
-  for (int c = blockIdx.x * PT + threadIdx.x; c < g.ncell; c += gridDim.x * PT) {
-    double y = 0.0;
-    if (tag[c] & TAG_P) {
-      int j, k, i;
-      decode(g, c, j, k, i);
-      y = lap<true>(g, tag, p, c, j, k, i);
-      a += p[c] * y;
+  const int stride = gridDim.x * PT;
+  const int last = (int)g.ncell - 1;
+  for (int c0 = blockIdx.x * PT + threadIdx.x; c0 < g.ncell; c0 += 2 * stride) {
+    const int c1 = c0 + stride;
+    const int c1c = c1 < g.ncell ? c1 : last;
+    int j0, k0, i0, j1, k1, i1;
+    decode(g, c0, j0, k0, i0);
+    decode(g, c1c, j1, k1, i1);
+    const double in0 = (tag[c0] & TAG_P) ? 1.0 : 0.0, in1 = (tag[c1c] & TAG_P) ? 1.0 : 0.0;
+    const double y0 = in0 * lap<true>(g, tag, p, c0, j0, k0, i0);
+    const double y1 = in1 * lap<true>(g, tag, p, c1c, j1, k1, i1);
+    a += p[c0] * y0;
+    ap[c0] = y0;
+    if (c1 < g.ncell) {
+      a += p[c1] * y1;
+      ap[c1] = y1;
     }
-    ap[c] = y;
   }
   put_partial(a, smem, part);
 }
@@ -196,10 +220,12 @@ int pcg_blocks(const GridParams& g) {
 }
 
 hipError_t launch_pcg_init(const GridParams& g, const uint8_t* tag, const double* x, const double* mean, double* r,
-                           double* part, hipStream_t st) {
+                           double* part, int64_t n_internal, hipStream_t st) {
   const int nb = pcg_blocks(g);
   hipLaunchKernelGGL(k_pcg_init, dim3(nb), dim3(PT), 0, st, g, tag, x, mean, r, part + PCG_B * PCG_NPART,
-                     part + PCG_R2 * PCG_NPART, part + PCG_X * PCG_NPART);
+                     part + PCG_RS * PCG_NPART, part + PCG_X * PCG_NPART);
+  hipLaunchKernelGGL(k_pcg_center, dim3(nb), dim3(PT), 0, st, g, tag, r, part + PCG_RS * PCG_NPART, nb,
+                     (double)n_internal, part + PCG_R2 * PCG_NPART);
   return hipGetLastError();
 }
 

@@ -336,7 +336,7 @@ def test_open_channel_wall_shear_refinement_trend(ibm):
     for q, name in enumerate(names):
         d1, d2 = res[0][q] - res[1][q], res[1][q] - res[2][q]
         _say(f"[ibm={ibm}] {name}: differences {d1:.3e} {d2:.3e}, observed order {math.log2(abs(d1 / d2)):.2f}")
-    checked = (0, 2, 3) if ibm else (0,)
+    checked = (0, 1, 2, 3) if ibm else (0,)
     for q in checked:
         assert abs(res[1][q] - res[2][q]) < abs(res[0][q] - res[1][q]), names[q]
 
