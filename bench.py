@@ -33,6 +33,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="wavy", help="wavy | wavy_large | wavy_open | ellipsoids | poiseuille")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--projection", default="full", choices=["full", "masked"],
+                    help="pressure projection of the main workload (masked: FP64, conjugate gradients)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the extra forms (FP32, large grid, IBM off)")
     ap.add_argument("--profile-only", action="store_true",
@@ -144,7 +146,7 @@ def timed_run(g, steps, warmup, profile_kernel=None):
 
 def dominant_kernel(g, nsteps=3):
     """The kernel with the largest total time, each kernel timed in a pass of its own."""
-    names = [n for n in g.kernel_names() if n not in ("diag", "stats", "geom", "wall_shear")]
+    names = [n for n in g.kernel_names() if n not in ("diag", "stats", "geom", "wall_shear", "pcg")]
     tot = {}
     for n in names:
         g.profile([n])
@@ -355,6 +357,9 @@ def main():
               flush=True)
 
     inputs = build_inputs(a.workload)
+    if a.projection == "masked":
+        import dataclasses
+        inputs = (dataclasses.replace(inputs[0], projection=1),) + tuple(inputs[1:])
     fixed = {k: int(v) for k, v in (kv.split("=") for kv in a.tuning.split(",") if kv)} if a.tuning else None
     r = measure(a.workload, a.precision, a.steps, a.warmup, inputs=inputs, tuning=fixed)
     if a.profile_only:
@@ -374,6 +379,7 @@ def main():
            "vs_baseline": None, "dtype": "f64" if a.precision == "fp64" else "f32",
            "data": "synthetic (seeded sinusoidal-wall channel, laminar + solenoidal perturbation)",
            "config": {"workload": c.name, "grid_faces": [c.nx, c.ny, c.nz], "cells": r["cells"],
+                      "projection": "masked" if c.projection == 1 else "full box",
                       "precision": a.precision, "Re_bulk": round(1.0 / c.nu), "dt": c.dt,
                       "forcing": "constant flow rate", "ibm_point_fraction": round(r["ibm_fraction"], 4)},
            "roofline": roof, "kernel_time_share_pct": r["shares"], "tuning": r["tuning"]}
