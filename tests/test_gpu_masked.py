@@ -94,3 +94,32 @@ def test_masked_open_channel_full_size_property():
         g.close()
     assert leaks[1] < 1e-12
     assert leaks[0] > 1e3 * leaks[1]
+
+
+def test_masked_and_full_box_instances_in_one_ensemble():
+    """An ensemble holding a masked-projection instance and a full-box one steps eagerly
+    (the graph knob is ignored while a masked instance is present) and both instances
+    match their own oracle runs; the wall shear is read per instance."""
+    from paper_2506_14328_amd import IbmGrid
+    from oracle.ibm_oracle import wall_shear_profile
+    from tests.test_gpu_wall_shear import _tau_tol
+    cases = [case("open_small", projection=1), case("wavy_small")]
+    runs = [oracle_run(c, 2) for c in cases]
+    g = IbmGrid.ensemble(cases, precision="fp64")
+    for i, (o, sdf, st) in enumerate(runs):
+        g.set_geometry(*[torch.from_numpy(np.ascontiguousarray(a)).to(device()) for a in sdf], inst=i)
+        g.set_state(*[torch.from_numpy(np.ascontiguousarray(a)).to(device()) for a in st], inst=i)
+    g.tune(graph=1, batch=1)
+    g.step(2)
+    for i, (o, sdf, st) in enumerate(runs):
+        u, v, w, p = [t.cpu().numpy() for t in g.get_state(inst=i)]
+        scale = max(np.abs(o.u).max(), np.abs(o.v).max(), np.abs(o.w).max())
+        errs = [np.abs(a - b).max() / scale for a, b in ((u, o.u), (v, o.v), (w, o.w))]
+        _say(f"instance {i} ({cases[i].name}, projection {cases[i].projection}): {['%.1e' % e for e in errs]}")
+        assert max(errs) < 1e-11
+        tau, _ = g.wall_shear(inst=i)
+        ref = wall_shear_profile(o.g, o.u, sdf[0])
+        tol = _tau_tol(o.g, sdf[0], 1e-11 * scale) + 1e-14 * np.abs(ref).max()
+        assert np.abs(tau.cpu().numpy() - ref).max() <= tol
+    assert g.stats(inst=0)["pcg_iters"] > 0 and g.stats(inst=1)["pcg_iters"] == 0
+    g.close()
