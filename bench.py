@@ -284,6 +284,45 @@ def measure_masked(steps=20, warmup=2):
     return out
 
 
+def measure_shard_shapes(steps=20, warmup=3):
+    """One GPU's share of the 512 x 257 x 256 channel split over 8 GPUs: the 512 x 257 x 32
+    z-slab that the stencil kernels would see, and a 64 x 257 x 256 grid whose 33 x-modes
+    are the wave-number slab that the z-FFT and the wall-normal solve would see (one wave
+    of the wall over its length, so that the geometry stays periodic).  Per-kernel averages
+    from the library's HIP-event timing, FP64."""
+    import math
+    import numpy as np
+    import torch
+    import ibm_inputs as I
+    out = []
+    for label, over in (("z-slab of 8", dict(nz=32, lz=math.pi / 8, q_target_or_pi=2.0 * math.pi / 8,
+                                            name="wavy_zslab_512x257x32")),
+                        ("kx-slab of 8", dict(nx=64, lx=math.pi / 4, q_target_or_pi=2.0 * math.pi,
+                                             geo_params=(0.1, math.pi / 4), name="wavy_kxslab_64x257x256"))):
+        import dataclasses
+        c = dataclasses.replace(I.make_case("wavy_large"), **over)
+        sdf = I.make_sdf(c)
+        u, v, w = I.make_initial(c, sdf)
+        g = make_grid(c, sdf, (u, v, w, np.zeros_like(u)), "fp64")
+        tuned = g.autotune(3)
+        g.step(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.step(steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        g.profile(True)
+        g.step(5)
+        prof = g.profile_read()
+        g.profile(False)
+        g.close()
+        C = c.nx * (c.ny - 1) * c.nz
+        out.append({"workload": c.name, "share": label, "precision": "fp64", "cells": C,
+                    "value": C * 3 * steps / el, "ms_per_step": el / steps * 1e3,
+                    "kernel_avg_us": {k: round(v[0] / v[1] * 1e3, 2) for k, v in prof.items()}, "tuning": tuned})
+    return out
+
+
 def cpu_baseline(name, target_s=12.0):
     """The FP64 oracle, as it stands, on the same workload: 1 untimed step, then as many
     whole steps as fit in about target_s seconds (at least 1)."""
@@ -422,6 +461,7 @@ def main():
         forms.append(dict(_form(ro, "fp64"), top="free-slip", ibm_point_fraction=round(ro["ibm_fraction"], 4)))
         del inp_o
         forms.append(measure_masked())
+        forms.extend(measure_shard_shapes())
         forms.append(measure_ensemble())
         out["forms"] = forms
     print(json.dumps(out), flush=True)
