@@ -83,15 +83,18 @@ typedef struct {
   int32_t projection;   /* IBM_PROJ_FULL_BOX: continuity on every cell of the box, one
                            FFT/tridiagonal solve per substep, external faces reset to zero
                            afterwards (Sec. 2.1, Sec. 3.3);
-                           IBM_PROJ_MASKED: continuity on the internal pressure cells only,
-                           D M G phi = D u_p / (c_k dt) (u_p the predictor) with M keeping the internal faces (the
-                           external ones are never corrected, Sec. 3.3 read strictly), solved
-                           by conjugate gradients preconditioned with the full-box solve and
-                           started from its solution; phi has zero mean over the internal
-                           cells.  IBM_FP64 only; ibm_step then launches eagerly (no graph)
-                           and synchronises once per iteration; IBM_ERR_UNSTABLE if the
-                           iteration cap is reached.  The internal pressure cells must be
-                           connected through internal faces. */
+                           IBM_PROJ_MASKED: continuity on the internal pressure cells
+                           only, D M G phi = D u_p / (c_k dt) (u_p the predictor) with M
+                           keeping the internal faces (the external ones are never
+                           corrected, Sec. 3.3 read strictly), solved by conjugate gradients
+                           preconditioned with the full-box solve and started from its
+                           solution; phi has zero mean over the internal cells.  IBM_FP64
+                           only; ibm_step then launches eagerly (no graph) and synchronises
+                           every 4 iterations to test the residual (up to 3 iterations past
+                           the tolerance only refine the solution); IBM_ERR_UNSTABLE if the
+                           iteration cap is reached, the state then holding the last
+                           iterate.  The internal pressure cells must be connected through
+                           internal faces. */
   int32_t pcg_max_iter; /* masked: iteration cap per solve (<= 0: 500) */
   double pcg_tol;       /* masked: stop at ||r||_2 <= pcg_tol ||b||_2 over the internal cells,
                            b = D u_p / (c_k dt) (<= 0: 1e-13) */
