@@ -56,7 +56,10 @@ def test_geometry_parity(name, b_mode):
 
 
 POISSON_SHAPES = [(4, 5, 4), (6, 9, 6), (10, 7, 5), (20, 5, 10), (160, 5, 4), (2, 3, 1), (80, 13, 10),
-                  (96, 33, 96), (192, 9, 3), (512, 5, 16), (32, 33, 16), (40, 17, 25)]
+                  (96, 33, 96), (192, 9, 3), (512, 5, 16), (32, 33, 16), (40, 17, 25),
+                  # the largest accepted sizes: x and z transforms of 512 / 1024 points (radix 2
+                  # and radix 5), the longest wall-normal line (2048 cells)
+                  (1024, 5, 8), (8, 5, 1024), (1000, 5, 6), (6, 5, 750), (4, 2049, 2)]
 
 
 @pytest.mark.parametrize("shape", POISSON_SHAPES)
@@ -69,7 +72,10 @@ def test_solve_pressure_parity(shape):
     from paper_2506_14328_amd import IbmGrid
     g = IbmGrid.from_case(c)
     phi = g.solve_pressure(to_dev(rhs)).cpu().numpy()
-    assert rel_err(phi, phi_ref) < 1e-12
+    # two stable solvers agree to about cond * eps; the wall-normal Neumann line of n cells
+    # has a condition number growing as n^2, which passes 1e-12 / eps beyond 256 cells
+    tol = 1e-12 * max(1.0, ((ny - 1) / 256.0) ** 2)
+    assert rel_err(phi, phi_ref) < tol
     s = g.stats()
     assert abs(s["rhs_mean_removed"] - mean_ref) < 1e-13
     g.close()
@@ -100,10 +106,15 @@ def test_solve_pressure_unaligned_buffers(precision):
     g.close()
 
 
-@pytest.mark.parametrize("name,nsteps", [("wavy_small", 1), ("wavy_small", 4), ("flat_small", 3),
-                                         ("ellip_small", 2), ("minimal", 5), ("wavy_160", 2), ("open_small", 4)])
-def test_step_parity_fp64(name, nsteps):
-    c = case(name)
+@pytest.mark.parametrize("name,nsteps,over", [("wavy_small", 1, {}), ("wavy_small", 4, {}), ("flat_small", 3, {}),
+                                              ("ellip_small", 2, {}), ("minimal", 5, {}), ("wavy_160", 2, {}),
+                                              ("open_small", 4, {}),
+                                              # the largest accepted x and z sizes, a ragged 1000
+                                              ("wavy_small", 1, dict(nx=1024, nz=4, dt=0.002)),
+                                              ("wavy_small", 1, dict(nx=8, nz=1024, dt=0.002)),
+                                              ("wavy_small", 1, dict(nx=1000, nz=6, dt=0.002))])
+def test_step_parity_fp64(name, nsteps, over):
+    c = case(name, **over)
     o, sdf, st = oracle_run(c, nsteps)
     g = gpu_grid(c, sdf, st)
     g.set_diagnostics(True)
@@ -116,7 +127,9 @@ def test_step_parity_fp64(name, nsteps):
     assert np.abs(p - o.p).max() <= 1e-11 * max(np.abs(o.p).max(), scale * scale)
     s = g.stats()
     os_ = o.stats()
-    assert math.isclose(s["pi_last"], o.pi_last, rel_tol=1e-10, abs_tol=1e-14)
+    # Pi is the flow-rate defect (a difference of two close flow rates, summed over all u
+    # faces in different orders) over S_k: compare the defects, S_k Pi, against Q_target
+    assert abs(s["pi_last"] - o.pi_last) * o.S[2] <= 1e-13 * abs(c.q_target_or_pi)
     assert math.isclose(s["q"], os_["q"], rel_tol=1e-12)
     div_tol = 1e-12 * scale / min(o.g.dx, o.g.dy, o.g.dz)
     assert s["div_max_fullbox"] <= div_tol
