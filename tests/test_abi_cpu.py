@@ -93,3 +93,39 @@ def test_invalid_descriptor_rejected(bad):
     rc = lib.ibm_create_grid(ctypes.byref(desc), 1, precision, None, ctypes.byref(h))
     assert rc == IBM_ERR_ARG
     assert not h.value
+
+
+@needs_lib
+def test_c_program_links_and_validates():
+    """A C program built against include/ibm.h and linked with the library (no Python in
+    between) names the kernels and gets IBM_ERR_ARG, with a message, for a descriptor the
+    library rejects before any device work."""
+    src = r'''
+#include <stdio.h>
+#include <string.h>
+#include "ibm.h"
+int main(void) {
+  int n = ibm_num_kernels();
+  if (n < 8 || strcmp(ibm_kernel_name(0), "momentum") != 0) return 1;
+  ibm_grid_desc d;
+  memset(&d, 0, sizeof d);
+  d.nx = 7; d.ny = 5; d.nz = 4; d.lx = 1.0; d.lz = 1.0; d.y_lo = -1.0; d.y_hi = 1.0;
+  d.nu = 0.01; d.dt = 0.01; d.ibm = 1;
+  ibm_handle h = 0;
+  int rc = ibm_create_grid(&d, 1, IBM_FP64, NULL, &h);
+  if (rc != IBM_ERR_ARG || h != NULL) return 2;
+  if (strlen(ibm_last_error(NULL)) == 0) return 3;
+  printf("%d %s\n", n, ibm_last_error(NULL));
+  return 0;
+}
+'''
+    libdir = os.path.dirname(LIB)
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        exe = os.path.join(d, "t")
+        open(c, "w").write(src)
+        subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe, "-L", libdir, "-libm",
+                               "-Wl,-rpath," + libdir])
+        r = subprocess.run([exe], capture_output=True, text=True)
+    assert r.returncode == 0, (r.returncode, r.stdout, r.stderr)
+    assert "nx" in r.stdout
