@@ -226,12 +226,16 @@ def measure_ensemble(n=96, steps=200, warmup=3, seed=5):
     torch.cuda.synchronize()
     cells = sum(c.nx * (c.ny - 1) * c.nz for c in cases)
     res = {}
+    tunings = {}
     for mode in ("sequential", "graph", "batched"):
-        # instances run side by side in a graph or a batched launch: 16 y planes per
-        # momentum block (fewer, longer blocks per instance) instead of the single-grid
-        # choice of about 2048 blocks per grid, which the one-after-another runs keep
+        # the graph and batched runs take the joint ensemble autotuner's choice (y planes
+        # per momentum block and tile order, one value for all instances); the runs one
+        # after another keep the single-grid automatic choices
         g.tune(graph=0 if mode == "sequential" else 1, batch=1 if mode == "batched" else 0,
-               momentum_planes=0 if mode == "sequential" else 16)
+               momentum_planes=0, tile_order=0)
+        if mode != "sequential":
+            ch = g.autotune(2)
+            tunings[mode] = {"momentum_planes": ch["momentum_planes"], "tile_order": ch["tile_order"]}
         for i, st in enumerate(states):
             g.set_state(*st, inst=i)
         g.step(warmup)
@@ -247,7 +251,7 @@ def measure_ensemble(n=96, steps=200, warmup=3, seed=5):
             "steps": steps, "value": res["graph"]["value"], "ms_per_step": res["graph"]["ms_per_step"],
             "sequential_value": res["sequential"]["value"], "batched_graph_value": res["batched"]["value"],
             "graph_speedup": res["graph"]["value"] / res["sequential"]["value"], "instances_with_nan": bad,
-            "tuning": {"momentum_planes": "16 in the graph and batched runs, automatic one after another"}}
+            "tuning": tunings}
 
 
 def measure_masked(steps=20, warmup=2):

@@ -234,11 +234,15 @@ int ibm_tune_get(ibm_handle h, int32_t param, int32_t* value);
 
 /* Autotuner: for each knob in turn, time steps_per_trial RK3 steps (after one
  * warm-up step, best of two runs) from the current state for every candidate value
- * with HIP events, and keep the fastest.  The state (u, v, w, p, step count, time) is saved before
- * and restored after, so the trajectory is unchanged.  chosen (may be NULL)
- * receives the 4 selected values (momentum planes, z-FFT width, tridiagonal rows,
- * tile order).  Synchronises the stream.  IBM_ERR_STATE
- * before ibm_set_geometry. */
+ * with HIP events, and keep the fastest.  Each instance is tuned on its own, except
+ * for an ensemble launched together (IBM_TUNE_GRAPH or IBM_TUNE_BATCH on): there the
+ * momentum planes and the tile order are tuned jointly, one value for every instance,
+ * timing whole ensemble steps in that launch mode (the other knobs keep their values).
+ * The state (u, v, w, p, step count, time) of every instance is saved before and
+ * restored after, so the trajectory is unchanged.  chosen (may be NULL) receives the 4
+ * selected values (momentum planes, z-FFT width, tridiagonal rows, tile order; for an
+ * ensemble, those of the last instance tuned on its own or of instance 0).
+ * Synchronises the stream.  IBM_ERR_STATE before ibm_set_geometry. */
 int ibm_autotune(ibm_handle h, int32_t steps_per_trial, int32_t* chosen);
 
 /* Bytes of device memory the library holds for this handle. */

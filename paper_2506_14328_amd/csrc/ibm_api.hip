@@ -1226,6 +1226,114 @@ int autotune_impl(ibm_ctx* c, Instance& I, int steps, int32_t* chosen) {
   cleanup();
   return rc;
 }
+
+// Ensembles launched together (graph branches or one launch per kernel for all): the
+// knobs that decide how the instances share the GPU (y planes per momentum block, tile
+// order) are tuned jointly by timing whole ensemble steps in that launch mode, the same
+// value for every instance; the other knobs keep their per-grid values.  The state of
+// every instance is saved and restored.
+template <typename T>
+int autotune_ensemble(ibm_ctx* c, int steps, int32_t* chosen) {
+  const size_t ni = c->inst.size();
+  std::vector<void*> save(4 * ni, nullptr);
+  std::vector<int64_t> step0(ni);
+  std::vector<double> time0(ni);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const bool prof = c->prof, diag = c->diag;
+  c->prof = false;
+  c->diag = false;
+  auto cleanup = [&]() {
+    for (void* p : save)
+      if (p) (void)hipFree(p);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    c->prof = prof;
+    c->diag = diag;
+  };
+  int rc = IBM_OK;
+  for (size_t i = 0; i < ni && !rc; ++i) {
+    Instance& I = c->inst[i];
+    step0[i] = I.step;
+    time0[i] = I.time;
+    const size_t fb = (size_t)I.g.ncell * sizeof(T);
+    void* fld[4] = {I.u, I.v, I.w, I.p};
+    rc = materialize(c, I);
+    for (int q = 0; q < 4 && !rc; ++q) {
+      if (hipMalloc(&save[4 * i + q], fb) != hipSuccess)
+        rc = fail(c, IBM_ERR_OOM, "autotune state copy");
+      else if (hipMemcpyAsync(save[4 * i + q], fld[q], fb, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+        rc = fail(c, IBM_ERR_DEVICE, "autotune save");
+    }
+  }
+  if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+    rc = fail(c, IBM_ERR_DEVICE, "autotune events");
+  auto restore = [&]() -> int {
+    for (size_t i = 0; i < ni; ++i) {
+      Instance& I = c->inst[i];
+      const size_t fb = (size_t)I.g.ncell * sizeof(T);
+      void* fld[4] = {I.u, I.v, I.w, I.p};
+      for (int q = 0; q < 4; ++q)
+        if (hipMemcpyAsync(fld[q], save[4 * i + q], fb, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+          return fail(c, IBM_ERR_DEVICE, "autotune restore");
+      const int r = seed_pending(c, I);
+      if (r) return r;
+      I.step = step0[i];
+      I.time = time0[i];
+      I.diag_valid = false;
+    }
+    return IBM_OK;
+  };
+  // `steps` ensemble steps in the current launch mode from the saved states, after one
+  // step that builds the graph or the batched arguments (best of two runs)
+  auto trial = [&](float* ms) -> int {
+    *ms = 1e30f;
+    drop_graph(c);
+    for (int rep = 0; rep < 2; ++rep) {
+      int r = restore();
+      if (!r) r = ibm_step(c, 1);
+      if (r) return r;
+      if (hipEventRecord(e0, c->stream) != hipSuccess) return fail(c, IBM_ERR_DEVICE, "event");
+      r = ibm_step(c, steps);
+      if (r) return r;
+      float t = 0.f;
+      if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&t, e0, e1) != hipSuccess)
+        return fail(c, IBM_ERR_DEVICE, "autotune timing");
+      if (t < *ms) *ms = t;
+    }
+    return IBM_OK;
+  };
+  const std::vector<int> jc = {0, 8, 16, 24, 32, 48};
+  const std::vector<int> to = {1, 2};
+  const std::vector<int>* cand[2] = {&jc, &to};
+  const int slot[2] = {0, 3};
+  for (int kq = 0; kq < 2 && !rc; ++kq) {
+    float best = 1e30f;
+    int bestv = kq == 0 ? c->inst[0].tu.mom_jc : c->inst[0].tu.tile_order;
+    for (int v : *cand[kq]) {
+      for (Instance& I : c->inst) (kq == 0 ? I.tu.mom_jc : I.tu.tile_order) = v;
+      float ms = 0.f;
+      rc = trial(&ms);
+      if (rc) break;
+      if (ms < best) {
+        best = ms;
+        bestv = v;
+      }
+    }
+    for (Instance& I : c->inst) (kq == 0 ? I.tu.mom_jc : I.tu.tile_order) = bestv;
+    if (chosen) chosen[slot[kq]] = bestv;
+  }
+  if (chosen && !rc) {
+    chosen[1] = c->inst[0].tu.fftz_w;
+    chosen[2] = c->inst[0].tu.tri_rows;
+  }
+  if (!rc) rc = restore();
+  if (!rc && hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(c, IBM_ERR_DEVICE, "autotune sync");
+  drop_graph(c);
+  cleanup();
+  return rc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1234,6 +1342,11 @@ int ibm_autotune(ibm_handle h, int32_t steps_per_trial, int32_t* chosen) {
   if (!h) return fail(nullptr, IBM_ERR_ARG, "null handle");
   if (steps_per_trial < 1) return fail(h, IBM_ERR_ARG, "steps_per_trial must be >= 1");
   drop_graph(h);
+  for (Instance& I : h->inst)
+    if (!I.geom_ready) return fail(h, IBM_ERR_STATE, "autotune before ibm_set_geometry");
+  if (h->inst.size() > 1 && (h->use_graph || h->use_batch))
+    return (h->precision == IBM_FP64) ? autotune_ensemble<double>(h, steps_per_trial, chosen)
+                                      : autotune_ensemble<float>(h, steps_per_trial, chosen);
   for (Instance& I : h->inst) {
     if (!I.geom_ready) return fail(h, IBM_ERR_STATE, "autotune before ibm_set_geometry");
     const int rc = (h->precision == IBM_FP64) ? autotune_impl<double>(h, I, steps_per_trial, chosen)
