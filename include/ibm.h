@@ -146,8 +146,9 @@ int ibm_set_geometry(ibm_handle h, int32_t inst, const double* sdf_u, const doub
 /* Copy a velocity/pressure state in (set) or out (get).  Arrays are device
  * pointers of the storage type (double for IBM_FP64, float for
  * IBM_FP32_STORAGE), field layout above.  set clears the stored explicit
- * right-hand side of the previous stage.  Values at external points are
- * taken as given; the next substep resets them. */
+ * right-hand side of the previous stage.  Values at external points (of the
+ * geometry in force when the next step runs) are kept as given until then; the step
+ * treats them as zero, the solid's velocity (Sec. 3.3), and writes zeros there. */
 int ibm_set_state(ibm_handle h, int32_t inst, const void* u, const void* v, const void* w,
                   const void* p);
 int ibm_get_state(ibm_handle h, int32_t inst, void* u, void* v, void* w, void* p);

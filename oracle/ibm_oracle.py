@@ -483,6 +483,14 @@ class Oracle:
     def substep(self, k: int):
         g, t = self.g, self.tags
         dt, ck = g.dt, RK_C[k]
+        # external points hold zero velocity and no pressure (Sec. 3.3): the correction of
+        # Eqs. (5)-(7) is the difference to a stencil whose external neighbours are zero.
+        # After a substep this already holds; after a new state or a new geometry the
+        # values at external points are replaced by zero here.
+        self.u = np.where(t["u"], self.u, 0.0)
+        self.v = np.where(t["v"], self.v, 0.0)
+        self.w = np.where(t["w"], self.w, 0.0)
+        self.p = np.where(t["p"], self.p, 0.0)
         # explicit right-hand side at the current stage (Eq. (9) without the IBM term)
         Hn = explicit_rhs(g, self.u, self.v, self.w, t)
         Gp = gradient(g, self.p)

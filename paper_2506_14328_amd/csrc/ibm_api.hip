@@ -51,8 +51,8 @@ struct Instance {
   int32_t* wall_j = nullptr;
   double* wall_d = nullptr;
   double* wall_tau = nullptr;
-  // immersed-boundary lists
-  DevBuf ibm_idx, ibm_coef, ibm_lam, ibm_choff;
+  // immersed-boundary lists; geometry temporaries (dense lambda, block counts)
+  DevBuf ibm_idx, ibm_coef, ibm_lam, ibm_choff, geo_tmp;
   IbmLists L{};
   Tuning tu{};
   int64_t n_int[3] = {0, 0, 0}, n_ibm[3] = {0, 0, 0}, n_pint = 0;
@@ -453,13 +453,10 @@ int run_steps(ibm_ctx* c, Instance& I, int nsteps, hipStream_t st, bool count = 
   return IBM_OK;
 }
 
-int count_mask(ibm_ctx* c, Instance& I, uint8_t mask, int32_t* blk, int nblk, int64_t* out) {
+// Number of cells whose tag has `mask` set, into I.itotal[slot] (no synchronisation).
+int count_mask(ibm_ctx* c, Instance& I, uint8_t mask, int32_t* blk, int nblk, int slot) {
   HIPCHK(c, launch_count_flags(I.tag, I.g.ncell, mask, blk, nblk, c->stream));
-  HIPCHK(c, launch_scan_counts(blk, nblk, I.itotal, c->stream));
-  int32_t tot = 0;
-  HIPCHK(c, hipMemcpyAsync(&tot, I.itotal, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
-  *out = tot;
+  HIPCHK(c, launch_scan_counts(blk, nblk, I.itotal + slot, c->stream));
   return IBM_OK;
 }
 
@@ -502,20 +499,22 @@ int set_geometry_impl(ibm_ctx* c, Instance& I, const double* su, const double* s
   const GridParams& g = I.g;
   hipStream_t st = c->stream;
   const size_t nc = (size_t)g.ncell;
-  double *lam_u = nullptr, *lam_v = nullptr, *lam_w = nullptr;
-  int32_t* blk = nullptr;
   const int nblk = (int)((nc + 255) / 256);
-  auto cleanup = [&]() {
-    if (lam_u) (void)hipFree(lam_u);
-    if (lam_v) (void)hipFree(lam_v);
-    if (lam_w) (void)hipFree(lam_w);
-    if (blk) (void)hipFree(blk);
-  };
-  if (hipMalloc((void**)&lam_u, nc * 8) != hipSuccess || hipMalloc((void**)&lam_v, nc * 8) != hipSuccess ||
-      hipMalloc((void**)&lam_w, nc * 8) != hipSuccess || hipMalloc((void**)&blk, (nblk + 1) * 4) != hipSuccess) {
-    cleanup();
-    return fail(c, IBM_ERR_OOM, "geometry temporaries");
+  // dense lambda per component and per-block counts: allocated at the first geometry of
+  // the instance and kept, so that a geometry that changes every step reallocates nothing
+  // of this size
+  const size_t tmp_bytes = 3 * nc * 8 + (size_t)(nblk + 1) * 4;
+  if (!I.geo_tmp.p) {
+    if (hipMalloc(&I.geo_tmp.p, tmp_bytes) != hipSuccess) {
+      I.geo_tmp.p = nullptr;
+      return fail(c, IBM_ERR_OOM, "geometry temporaries");
+    }
+    I.geo_tmp.bytes = tmp_bytes;
   }
+  double* lam_u = (double*)I.geo_tmp.p;
+  double* lam_v = lam_u + nc;
+  double* lam_w = lam_v + nc;
+  int32_t* blk = (int32_t*)(lam_w + nc);
   int rc = IBM_OK;
   do {
     hipError_t e = timed(c, K_GEOM, [&]() {
@@ -524,12 +523,20 @@ int set_geometry_impl(ibm_ctx* c, Instance& I, const double* su, const double* s
     if (e == hipSuccess) e = launch_geom_ptag(g, I.tag, st);
     if (e == hipSuccess) e = launch_geom_south_wall(g, su, I.d.ibm, I.wall_j, I.wall_d, st);
     if (e != hipSuccess) { rc = fail(c, IBM_ERR_DEVICE, std::string("geometry: ") + hipGetErrorString(e)); break; }
-    const uint8_t imask[3] = {TAG_U, TAG_V, TAG_W};
     const uint8_t bmask[3] = {TAG_UI, TAG_VI, TAG_WI};
-    for (int q = 0; q < 3 && !rc; ++q) rc = count_mask(c, I, imask[q], blk, nblk, &I.n_int[q]);
-    if (!rc) rc = count_mask(c, I, TAG_P, blk, nblk, &I.n_pint);
-    for (int q = 0; q < 3 && !rc; ++q) rc = count_mask(c, I, bmask[q], blk, nblk, &I.n_ibm[q]);
+    // internal u, v, w, p and IBM u, v, w counts, read back with one synchronisation
+    const uint8_t cmask[7] = {TAG_U, TAG_V, TAG_W, TAG_P, TAG_UI, TAG_VI, TAG_WI};
+    for (int q = 0; q < 7 && !rc; ++q) rc = count_mask(c, I, cmask[q], blk, nblk, q);
     if (rc) break;
+    int32_t cnt[7];
+    e = hipMemcpyAsync(cnt, I.itotal, sizeof(cnt), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) { rc = fail(c, IBM_ERR_DEVICE, std::string("geometry counts: ") + hipGetErrorString(e)); break; }
+    for (int q = 0; q < 3; ++q) {
+      I.n_int[q] = cnt[q];
+      I.n_ibm[q] = cnt[4 + q];
+    }
+    I.n_pint = cnt[3];
     if (I.n_pint == 0) { rc = fail(c, IBM_ERR_ARG, "geometry has no fluid"); break; }
     const int64_t ntot = I.n_ibm[0] + I.n_ibm[1] + I.n_ibm[2];
     free_buf(I.ibm_idx);
@@ -593,7 +600,6 @@ int set_geometry_impl(ibm_ctx* c, Instance& I, const double* su, const double* s
     I.geom_ready = true;
     I.diag_valid = false;
   } while (0);
-  cleanup();
   return rc;
 }
 
@@ -1404,7 +1410,7 @@ int64_t ibm_device_bytes(ibm_handle h) {
   int64_t b = 0;
   for (Instance& I : h->inst) {
     for (auto& x : I.bufs) b += (int64_t)x.bytes;
-    b += I.ibm_idx.bytes + I.ibm_coef.bytes + I.ibm_lam.bytes + I.ibm_choff.bytes;
+    b += I.ibm_idx.bytes + I.ibm_coef.bytes + I.ibm_lam.bytes + I.ibm_choff.bytes + I.geo_tmp.bytes;
   }
   return b;
 }
@@ -1419,6 +1425,7 @@ int ibm_destroy(ibm_handle h) {
     free_buf(I.ibm_coef);
     free_buf(I.ibm_lam);
     free_buf(I.ibm_choff);
+    free_buf(I.geo_tmp);
   }
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
   drop_graph(h);

@@ -151,30 +151,44 @@ __global__ __launch_bounds__(256) void k_count_flags(const uint8_t* __restrict__
   if (threadIdx.x == 0) counts[blockIdx.x] = wc[0] + wc[1] + wc[2] + wc[3];
 }
 
-// Exclusive scan of the block counts (single block, sequential chunks); total at the end.
+// Exclusive prefix sum of nblk counts in place, total[0] = their sum; one block of 1024
+// threads, 4096 counts per round: each thread adds 4 consecutive counts, the waves scan
+// their threads' sums with shuffles and one wave scans the 16 wave sums.
 __global__ __launch_bounds__(1024) void k_scan_counts(int32_t* __restrict__ counts, int nblk,
                                                      int32_t* __restrict__ total) {
-  __shared__ int32_t buf[1024];
-  __shared__ int32_t carry;
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
-  for (int base = 0; base < nblk; base += 1024) {
-    const int e = base + threadIdx.x;
-    const int32_t v = (e < nblk) ? counts[e] : 0;
-    buf[threadIdx.x] = v;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-      const int32_t add = (threadIdx.x >= o) ? buf[threadIdx.x - o] : 0;
-      __syncthreads();
-      buf[threadIdx.x] += add;
-      __syncthreads();
+  __shared__ int32_t wsum[16];
+  const int tid = threadIdx.x, lane = tid & (IBM_WAVE - 1), wid = tid / IBM_WAVE;
+  int32_t carry = 0;
+  for (int base = 0; base < nblk; base += 4096) {
+    const int e0 = base + 4 * tid;
+    int32_t v[4];
+    for (int q = 0; q < 4; ++q) v[q] = (e0 + q < nblk) ? counts[e0 + q] : 0;
+    const int32_t sum = v[0] + v[1] + v[2] + v[3];
+    int32_t x = sum;   // inclusive scan over the wave
+    for (int o = 1; o < IBM_WAVE; o <<= 1) {
+      const int32_t y = __shfl_up(x, o, IBM_WAVE);
+      if (lane >= o) x += y;
     }
-    if (e < nblk) counts[e] = carry + buf[threadIdx.x] - v;
+    if (lane == IBM_WAVE - 1) wsum[wid] = x;
     __syncthreads();
-    if (threadIdx.x == 1023) carry += buf[1023];
+    if (wid == 0) {
+      int32_t w = lane < 16 ? wsum[lane] : 0;
+      for (int o = 1; o < 16; o <<= 1) {
+        const int32_t y = __shfl_up(w, o, IBM_WAVE);
+        if (lane >= o) w += y;
+      }
+      if (lane < 16) wsum[lane] = w;
+    }
+    __syncthreads();
+    int32_t run = carry + (wid > 0 ? wsum[wid - 1] : 0) + (x - sum);
+    for (int q = 0; q < 4; ++q) {
+      if (e0 + q < nblk) counts[e0 + q] = run;
+      run += v[q];
+    }
+    carry += wsum[15];
     __syncthreads();
   }
-  if (threadIdx.x == 0) total[0] = carry;
+  if (tid == 0) total[0] = carry;
 }
 
 // Flagged cells per 64-wide chunk of each grid row: counts[row * cpr + ch]; one extra

@@ -365,3 +365,35 @@ def test_graph_replays_match_eager():
                     assert np.array_equal(x, y), (rep, i)
     for g in gs:
         g.close()
+
+
+def test_geometry_changing_every_step():
+    """A wall that moves between steps (the sinusoidal wall shifted by a fifth of a
+    wavelength per step, its samples replaced before each step) against the oracle given
+    the same sequence of geometries; the geometry preprocessing reallocates nothing of the
+    grid's size after the first call."""
+    c = case("wavy_small")
+    amp, lam = c.geo_params
+    o, sdf0, st = oracle_run(c, 0)
+    g = gpu_grid(c, sdf0, st)
+    bytes0 = g.device_bytes()
+    for n in range(1, 4):
+        shift = 0.2 * lam * n
+
+        def fn(Xg, Yg, Zg):
+            yw = -1.0 + amp * np.sin(2 * math.pi * (Xg - shift) / lam)
+            dyw = amp * 2 * math.pi / lam * np.cos(2 * math.pi * (Xg - shift) / lam)
+            return np.minimum((Yg - yw) / np.sqrt(1.0 + dyw * dyw), 1.0 - Yg)
+
+        sdf = I._sample(c, fn)
+        o.set_geometry(*sdf)
+        o.step(1)
+        g.set_geometry(*[to_dev(a) for a in sdf])
+        g.step(1)
+        u, v, w, p = [t.cpu().numpy() for t in g.get_state()]
+        scale = max(np.abs(o.u).max(), np.abs(o.v).max(), np.abs(o.w).max())
+        errs = [np.abs(a - b).max() / scale for a, b in ((u, o.u), (v, o.v), (w, o.w))]
+        print(f"step {n}: u, v, w {['%.1e' % e for e in errs]}", flush=True)
+        assert max(errs) < 1e-12
+        assert g.device_bytes() <= bytes0 + 64 * 1024 * 1024
+    g.close()
