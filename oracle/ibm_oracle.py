@@ -196,6 +196,65 @@ def wall_lambda(g: OGrid, sdf_full: np.ndarray, comp: str, internal: np.ndarray)
     return lam
 
 
+def wall_source(g: OGrid, sdf_full: np.ndarray, comp: str, internal: np.ndarray) -> np.ndarray:
+    """Coefficient sigma of the wall velocity U_b in the immersed-boundary term of a
+    rigidly moving wall (reading R19): the IBM term of a point becomes
+    -lambda u_P + sigma U_b.
+
+    With the ghost value the linear extrapolation through U_b at the wall (Sec. 2.2,
+    Eqs. (5)-(7) with a moving wall), u_G = U_b h/delta - u_P (h - delta)/delta, and the
+    plain stencil using the stored value of the external neighbour, the difference per
+    arm whose wall is the immersed one (the signed-distance crossing nearer than any box
+    wall) is lambda_arm (U_b - u_P) when that neighbour stores U_b (an external point
+    inside the box), and nu U_b/(delta h) - lambda_arm u_P when it stores zero (the box
+    wall face or the ghost row beyond it).  Arms ending on a box wall (at rest) add
+    nothing.  Zero at points that are not internal.
+    """
+    nu = g.nu
+    if comp in ("u", "w"):
+        s = sdf_full[1:-1]
+        s_dn = sdf_full[:-2]
+        s_up = sdf_full[2:]
+        ext_dn = s_dn <= 0.0
+        ext_up = s_up <= 0.0
+        ext_dn[0] = True
+        box_dn = np.full(s.shape, np.inf)
+        box_up = np.full(s.shape, np.inf)
+        box_dn[0] = 0.5 * g.dy
+        if g.top == 0:
+            ext_up[-1] = True
+            box_up[-1] = 0.5 * g.dy
+    else:
+        s = sdf_full[:-1]
+        s_dn = np.zeros_like(s)
+        s_dn[1:] = sdf_full[:-2]
+        s_up = sdf_full[1:]
+        ext_dn = s_dn <= 0.0
+        ext_up = s_up <= 0.0
+        ext_dn[1] = True
+        ext_up[-1] = True
+        box_dn = np.full(s.shape, np.inf)
+        box_up = np.full(s.shape, np.inf)
+        box_dn[1] = g.dy
+        box_up[-1] = g.dy
+    sig = np.zeros(s.shape)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        for h, sQ, extQ, bd in (
+            (g.dx, sx(s, -1), sx(s, -1) <= 0.0, np.inf),
+            (g.dx, sx(s, +1), sx(s, +1) <= 0.0, np.inf),
+            (g.dz, sz(s, -1), sz(s, -1) <= 0.0, np.inf),
+            (g.dz, sz(s, +1), sz(s, +1) <= 0.0, np.inf),
+            (g.dy, s_dn, ext_dn, box_dn),
+            (g.dy, s_up, ext_up, box_up),
+        ):
+            d_sdf = np.where(sQ <= 0.0, h * s / (s - sQ), np.inf)
+            immersed = extQ & (d_sdf < bd)
+            stores_zero = np.isfinite(bd)
+            arm = np.where(stores_zero, nu / (d_sdf * h), nu * (h - d_sdf) / (d_sdf * h * h))
+            sig += np.where(immersed, arm, 0.0)
+    return np.where(internal, sig, 0.0)
+
+
 def stage_coefficients(lam: np.ndarray, k: int, dt: float, b_mode: int = B_EXP):
     """(B, A) of the implicit IBM update for RK stage k (Sec. 2.4, Eqs. (14)-(16)).
 
@@ -444,6 +503,7 @@ class Oracle:
         self.H = None
         self.step_count = 0
         self.time = 0.0
+        self.wall_vel = (0.0, 0.0, 0.0)
         self.pi_last = 0.0
         self.q_last = 0.0
         self.diag = {}
@@ -461,8 +521,14 @@ class Oracle:
             "v": wall_lambda(g, sdf_v, "v", self.tags["v"]),
             "w": wall_lambda(g, sdf_w, "w", self.tags["w"]),
         }
+        self.sig = {
+            "u": wall_source(g, sdf_u, "u", self.tags["u"]),
+            "v": wall_source(g, sdf_v, "v", self.tags["v"]),
+            "w": wall_source(g, sdf_w, "w", self.tags["w"]),
+        }
         if not ibm:
             self.lam = {c: np.zeros_like(l) for c, l in self.lam.items()}
+            self.sig = {c: np.zeros_like(l) for c, l in self.sig.items()}
         self.coef = []
         for k in range(3):
             self.coef.append({c: stage_coefficients(self.lam[c], k, g.dt, g.b_mode) for c in "uvw"})
@@ -474,6 +540,19 @@ class Oracle:
         self.u, self.v, self.w, self.p = (np.array(a, dtype=np.float64) for a in (u, v, w, p))
         self.H = None
 
+    def set_wall_velocity(self, ub: float, vb: float, wb: float):
+        """Velocity of the immersed walls (rigid translation; reading R19); the box walls
+        stay at rest."""
+        self.wall_vel = (float(ub), float(vb), float(wb))
+
+    def _external(self, comp: str) -> np.ndarray:
+        """Stored value of the external points of one component: the wall velocity inside
+        the box, zero on the south box-wall face of v (Sec. 3.3)."""
+        out = np.full(self.g.shape, self.wall_vel["uvw".index(comp)])
+        if comp == "v":
+            out[0] = 0.0
+        return out
+
     def flow_rate(self, f):
         """Q = (1/nx) sum over internal u faces of f dy dz (mean flux through x-planes)."""
         g = self.g
@@ -483,13 +562,14 @@ class Oracle:
     def substep(self, k: int):
         g, t = self.g, self.tags
         dt, ck = g.dt, RK_C[k]
-        # external points hold zero velocity and no pressure (Sec. 3.3): the correction of
-        # Eqs. (5)-(7) is the difference to a stencil whose external neighbours are zero.
-        # After a substep this already holds; after a new state or a new geometry the
-        # values at external points are replaced by zero here.
-        self.u = np.where(t["u"], self.u, 0.0)
-        self.v = np.where(t["v"], self.v, 0.0)
-        self.w = np.where(t["w"], self.w, 0.0)
+        # external points hold the wall velocity (zero for walls at rest) and no pressure
+        # (Sec. 3.3): the correction of Eqs. (5)-(7) is the difference to a stencil that
+        # uses these stored values.  After a substep this already holds; after a new state
+        # or a new geometry the values at external points are replaced here.
+        ext = {c: self._external(c) for c in "uvw"}
+        self.u = np.where(t["u"], self.u, ext["u"])
+        self.v = np.where(t["v"], self.v, ext["v"])
+        self.w = np.where(t["w"], self.w, ext["w"])
         self.p = np.where(t["p"], self.p, 0.0)
         # explicit right-hand side at the current stage (Eq. (9) without the IBM term)
         Hn = explicit_rhs(g, self.u, self.v, self.w, t)
@@ -500,8 +580,10 @@ class Oracle:
             if RK_B[k] != 0.0:
                 r = r + dt * RK_B[k] * self.H[("uvw").index(c)]
             B, A = self.coef[k][c]
-            # Eq. (16): (lambda c_k dt + B) w* - B w = dt (a_k f_k + b_k f_{k-1})
-            star.append(np.where(t[c], (B * f + r) / A, 0.0))        # reading R3
+            # Eq. (16): (lambda c_k dt + B) w* - B w = dt (a_k f_k + b_k f_{k-1}), plus the
+            # moving wall's term sigma U_b, explicit and weighted like lambda (reading R19)
+            src = ck * dt * self.sig[c] * self.wall_vel["uvw".index(c)]
+            star.append(np.where(t[c], (B * f + r + src) / A, ext[c]))   # reading R3
         us, vs, ws = star
         # mean pressure gradient (reading R4)
         invA_u = 1.0 / self.coef[k]["u"][1]
@@ -510,7 +592,7 @@ class Oracle:
             pi = (q0 - g.q_target_or_pi) / self.S[k]
         else:
             pi = g.q_target_or_pi
-        us = np.where(t["u"], us - pi * ck * dt * invA_u, 0.0)
+        us = np.where(t["u"], us - pi * ck * dt * invA_u, ext["u"])
         self.pi_last = pi
         # projection (Sec. 2.1; continuity on the full box, Sec. 3.3, reading R6)
         rhs = divergence(g, us, vs, ws) / (ck * dt)
@@ -537,10 +619,11 @@ class Oracle:
                 "poisson_rel_residual": float(np.abs(resid).max() / max(np.abs(rhs).max(), 1e-300)),
                 "rhs_mean_removed": mean_removed,
             }
-        # external faces back to zero (Sec. 3.3); only internal pressure is updated
-        self.u = np.where(t["u"], un, 0.0)
-        self.v = np.where(t["v"], vn, 0.0)
-        self.w = np.where(t["w"], wn, 0.0)
+        # external faces back to the wall velocity (Sec. 3.3); only internal pressure is
+        # updated
+        self.u = np.where(t["u"], un, ext["u"])
+        self.v = np.where(t["v"], vn, ext["v"])
+        self.w = np.where(t["w"], wn, ext["w"])
         self.p = np.where(t["p"], self.p + phi, 0.0)
         self.H = Hn
         self.q_last = self.flow_rate(self.u)
@@ -592,7 +675,7 @@ def solve_pressure(g: OGrid, rhs: np.ndarray):
 # --------------------------------------------------------------------------------------
 # Wall-shear stress of the undulated bottom and its Fourier components (Sec. 4.2)
 # --------------------------------------------------------------------------------------
-def south_wall_points(g: OGrid, sdf_u: np.ndarray, ibm: bool = True):
+def south_wall_points(g: OGrid, sdf_u: np.ndarray, ibm: bool = True, with_box: bool = False):
     """Lowest internal u point of every (k, i) column and its distance to the wall below.
 
     Reading R17: the wall under the lowest internal point of a column is located as the
@@ -600,7 +683,8 @@ def south_wall_points(g: OGrid, sdf_u: np.ndarray, ibm: bool = True):
     the signed distance between the point and the external point below it, or the south
     box wall dy/2 below row 0 when that is nearer.  Without the immersed-boundary
     correction the staircase puts the wall at the external point itself (distance dy).
-    Returns (j1, d1): j1 = -1 and d1 = 0 where a column holds no internal u point.
+    Returns (j1, d1): j1 = -1 and d1 = 0 where a column holds no internal u point; with
+    with_box also a mask of the columns whose wall is the south box wall (at rest).
     sdf_u: (ny+1, nz, nx) with row j+1 holding row j (ghost rows 0 and ny).
     """
     s = sdf_u[1:-1]
@@ -611,17 +695,20 @@ def south_wall_points(g: OGrid, sdf_u: np.ndarray, ibm: bool = True):
     sP = s[j1, kk, ii]
     s_dn = sdf_u[j1, kk, ii]                 # row j1 - 1 (the ghost row for j1 = 0)
     d1 = np.full(j1.shape, g.dy)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        cross = np.where(s_dn <= 0.0, g.dy * sP / (sP - s_dn), np.inf)
+    box = np.where(j1 == 0, 0.5 * g.dy, np.inf)
     if ibm:
-        with np.errstate(divide="ignore", invalid="ignore"):
-            cross = np.where(s_dn <= 0.0, g.dy * sP / (sP - s_dn), np.inf)
-        box = np.where(j1 == 0, 0.5 * g.dy, np.inf)
         d1 = np.minimum(cross, box)
     j1 = np.where(has, j1, -1)
     d1 = np.where(has, d1, 0.0)
+    if with_box:
+        return j1, d1, has & (box <= cross)
     return j1, d1
 
 
-def wall_shear_profile(g: OGrid, u: np.ndarray, sdf_u: np.ndarray, ibm: bool = True) -> np.ndarray:
+def wall_shear_profile(g: OGrid, u: np.ndarray, sdf_u: np.ndarray, ibm: bool = True,
+                       wall_velocity: float = 0.0) -> np.ndarray:
     """Spanwise-averaged wall-shear stress tau(x_i) along the south wall (Sec. 4.2).
 
     Reading R17: tau is the viscous flux the discretisation itself exchanges with the
@@ -630,17 +717,19 @@ def wall_shear_profile(g: OGrid, u: np.ndarray, sdf_u: np.ndarray, ibm: bool = T
     arm is nu (u1 - u_ghost)/dy = nu u1/d1, d1 the wall distance the correction uses
     (with the bare staircase the wall is at the external point, d1 = dy).  Summed over
     the walls this is exactly the discrete momentum balance of a steady flow (pinned).
-    Columns without internal u points add zero; the mean is over all nz columns of each
-    x_i = i dx.
+    An immersed wall sliding with streamwise velocity U_b gives nu (u1 - U_b)/d1 (the box
+    wall stays at rest).  Columns without internal u points add zero; the mean is over all
+    nz columns of each x_i = i dx.
     """
-    j1, d1 = south_wall_points(g, sdf_u, ibm)
+    j1, d1, box = south_wall_points(g, sdf_u, ibm, with_box=True)
     tau = np.zeros((g.nz, g.nx))
     for k in range(g.nz):
         for i in range(g.nx):
             j = int(j1[k, i])
             if j < 0:
                 continue
-            tau[k, i] = g.nu * float(u[j, k, i]) / float(d1[k, i])
+            ub = 0.0 if box[k, i] else wall_velocity
+            tau[k, i] = g.nu * (float(u[j, k, i]) - ub) / float(d1[k, i])
     return tau.mean(axis=0)
 
 
