@@ -228,9 +228,10 @@ def measure_ensemble(n=96, steps=200, warmup=3, seed=5):
     res = {}
     tunings = {}
     for mode in ("sequential", "graph", "batched"):
-        # the graph and batched runs take the joint ensemble autotuner's choice (y planes
-        # per momentum block and tile order, one value for all instances); the runs one
-        # after another keep the single-grid automatic choices
+        # the batched run takes the joint ensemble autotuner's choice (y planes per
+        # momentum block and tile order, one value for all instances), the graph of
+        # per-instance branches each instance's own tuning; the runs one after another
+        # keep the single-grid automatic choices
         g.tune(graph=0 if mode == "sequential" else 1, batch=1 if mode == "batched" else 0,
                momentum_planes=0, tile_order=0)
         if mode != "sequential":

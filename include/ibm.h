@@ -168,13 +168,26 @@ int ibm_solve_pressure(ibm_handle h, int32_t inst, const void* rhs, void* phi);
 /* Diagnostics of the current state (synchronises the stream). */
 int ibm_stats(ibm_handle h, int32_t inst, ibm_stats_t* out);
 
+/* Velocity (ub, vb, wb) of the immersed walls (the zero set of the signed distances),
+ * a rigid translation; the box walls stay at rest.  The ghost value of a cut stencil arm
+ * is the linear extrapolation through the wall velocity (Sec. 2.2, Eqs. (5)-(7) with a
+ * moving wall): the implicit update gains the explicit term sigma U_b c_k dt / A, sigma
+ * per immersed-boundary point from the same wall distances as lambda, and external points
+ * inside the box hold U_b (the south box-wall face of v holds 0).  With a geometry that
+ * moves, give the samples of each new position with ibm_set_geometry and its velocity
+ * here, between steps.  Applies a pending projection first (with the previous velocity);
+ * drops captured graphs (the flow-rate kernel then visits every immersed-boundary point).
+ * Synchronises the stream.  IBM_ERR_ARG for a non-finite velocity. */
+int ibm_set_wall_velocity(ibm_handle h, int32_t inst, double ub, double vb, double wb);
+
 /* Wall-shear stress of the current state along the south wall, the undulated bottom
  * of the open channel (Sec. 4.2), and its Fourier components tau_1c, tau_1s defined
  * there.  Per (z_k, x_i) column of u points: the lowest internal u point, u1, at
  * distance d1 above the wall located as the immersed boundary locates it (the linear
  * zero crossing of the u signed distance towards the external point below it, or the
  * south box wall when nearer; the external point itself without the correction), and
- * tau = nu u1 / d1, the viscous flux the discretisation exchanges with the wall through
+ * tau = nu (u1 - U_b) / d1 (U_b the streamwise wall velocity of an immersed wall, 0 for
+ * the box wall), the viscous flux the discretisation exchanges with the wall through
  * that stencil arm (its ghost value is the linear extrapolation through zero at the
  * wall, Sec. 2.2 Eqs. (5)-(7)).  tau_x[i] = mean over the nz columns at x_i = i dx (a
  * column with no internal u point adds 0).  modes = (tau_0, tau_1c, tau_1s): the mean
@@ -236,9 +249,11 @@ int ibm_tune_get(ibm_handle h, int32_t param, int32_t* value);
 /* Autotuner: for each knob in turn, time steps_per_trial RK3 steps (after one
  * warm-up step, best of two runs) from the current state for every candidate value
  * with HIP events, and keep the fastest.  Each instance is tuned on its own, except
- * for an ensemble launched together (IBM_TUNE_GRAPH or IBM_TUNE_BATCH on): there the
- * momentum planes and the tile order are tuned jointly, one value for every instance,
- * timing whole ensemble steps in that launch mode (the other knobs keep their values).
+ * for an ensemble launched as one launch per kernel for all instances (IBM_TUNE_BATCH
+ * on): there the momentum planes and the tile order are tuned jointly, one value for
+ * every instance, timing whole ensemble steps in that launch mode, eager or as a graph
+ * (the other knobs keep their values).  An ensemble of per-instance graph branches is
+ * tuned one instance at a time with eager launches.
  * The state (u, v, w, p, step count, time) of every instance is saved before and
  * restored after, so the trajectory is unchanged.  chosen (may be NULL) receives the 4
  * selected values (momentum planes, z-FFT width, tridiagonal rows, tile order; for an

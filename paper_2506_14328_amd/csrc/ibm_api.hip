@@ -45,6 +45,7 @@ struct Instance {
   // masked projection: conjugate-gradient vectors r, z, p, A p and partial sums
   double* pcg_v[4] = {};
   double* pcg_part = nullptr;
+  double wall_vel[3] = {0.0, 0.0, 0.0};   // host copy of the immersed walls' velocity
   int pcg_iters = 0;        // iterations of the last masked solve
   double pcg_res = 0.0;     // its final |r| / |b|
   // south-wall point per (k, i) column (row, distance) and wall-shear output [nx + 3]
@@ -52,7 +53,7 @@ struct Instance {
   double* wall_d = nullptr;
   double* wall_tau = nullptr;
   // immersed-boundary lists; geometry temporaries (dense lambda, block counts)
-  DevBuf ibm_idx, ibm_coef, ibm_lam, ibm_choff, geo_tmp;
+  DevBuf ibm_idx, ibm_coef, ibm_lam, ibm_sig, ibm_choff, geo_tmp;
   IbmLists L{};
   Tuning tu{};
   int64_t n_int[3] = {0, 0, 0}, n_ibm[3] = {0, 0, 0}, n_pint = 0;
@@ -68,6 +69,9 @@ struct Instance {
   double* red_out() { return small + 7; }
   double* diag_out() { return small + 15; }
   double* pcg_sc() { return small + 20; }   // rho[2] |b|^2 saved-mean |r|^2
+  double* wallv() { return small + 26; }    // velocity of the immersed walls (3)
+  double* wall_sd() { return small + 29; }  // per stage: sum over IBM u points of sig / A
+  bool moving() const { return wall_vel[0] != 0.0 || wall_vel[1] != 0.0 || wall_vel[2] != 0.0; }
 };
 
 }  // namespace
@@ -267,6 +271,8 @@ int init_instance(ibm_ctx* c, Instance& I, const ibm_grid_desc& d) {
   if ((rc = dalloc(c, I, (void**)&I.red_part, red_n * sizeof(double)))) return rc;
   if ((rc = dalloc(c, I, (void**)&I.small, 32 * sizeof(double)))) return rc;
   HIPCHK(c, hipMemsetAsync(I.small, 0, 32 * sizeof(double), c->stream));
+  I.L.wallv = I.wallv();
+  I.L.sd = I.wall_sd();
   if ((rc = dalloc(c, I, (void**)&I.itotal, 16 * sizeof(int32_t)))) return rc;
   if (d.projection == IBM_PROJ_MASKED) {
     for (int q = 0; q < 4; ++q)
@@ -500,10 +506,10 @@ int set_geometry_impl(ibm_ctx* c, Instance& I, const double* su, const double* s
   hipStream_t st = c->stream;
   const size_t nc = (size_t)g.ncell;
   const int nblk = (int)((nc + 255) / 256);
-  // dense lambda per component and per-block counts: allocated at the first geometry of
-  // the instance and kept, so that a geometry that changes every step reallocates nothing
-  // of this size
-  const size_t tmp_bytes = 3 * nc * 8 + (size_t)(nblk + 1) * 4;
+  // dense lambda and wall-velocity coefficient per component and per-block counts:
+  // allocated at the first geometry of the instance and kept, so that a geometry that
+  // changes every step reallocates nothing of this size
+  const size_t tmp_bytes = 6 * nc * 8 + (size_t)(nblk + 1) * 4;
   if (!I.geo_tmp.p) {
     if (hipMalloc(&I.geo_tmp.p, tmp_bytes) != hipSuccess) {
       I.geo_tmp.p = nullptr;
@@ -514,11 +520,14 @@ int set_geometry_impl(ibm_ctx* c, Instance& I, const double* su, const double* s
   double* lam_u = (double*)I.geo_tmp.p;
   double* lam_v = lam_u + nc;
   double* lam_w = lam_v + nc;
-  int32_t* blk = (int32_t*)(lam_w + nc);
+  double* sig_u = lam_w + nc;
+  double* sig_v = sig_u + nc;
+  double* sig_w = sig_v + nc;
+  int32_t* blk = (int32_t*)(sig_w + nc);
   int rc = IBM_OK;
   do {
     hipError_t e = timed(c, K_GEOM, [&]() {
-      return launch_geom_lambda(g, su, sv, sw, I.d.ibm, I.tag, lam_u, lam_v, lam_w, st);
+      return launch_geom_lambda(g, su, sv, sw, I.d.ibm, I.tag, lam_u, lam_v, lam_w, sig_u, sig_v, sig_w, st);
     });
     if (e == hipSuccess) e = launch_geom_ptag(g, I.tag, st);
     if (e == hipSuccess) e = launch_geom_south_wall(g, su, I.d.ibm, I.wall_j, I.wall_d, st);
@@ -542,6 +551,7 @@ int set_geometry_impl(ibm_ctx* c, Instance& I, const double* su, const double* s
     free_buf(I.ibm_idx);
     free_buf(I.ibm_coef);
     free_buf(I.ibm_lam);
+    free_buf(I.ibm_sig);
     free_buf(I.ibm_choff);
     const int cpr = (g.nx + IBM_WAVE - 1) / IBM_WAVE;
     const size_t nch = (size_t)g.nrows * cpr + 1;
@@ -552,25 +562,28 @@ int set_geometry_impl(ibm_ctx* c, Instance& I, const double* su, const double* s
     I.ibm_choff.bytes = 3 * nch * 4;
     const size_t nalloc = (size_t)std::max<int64_t>(ntot, 1);
     if (hipMalloc(&I.ibm_idx.p, nalloc * 4) != hipSuccess || hipMalloc(&I.ibm_coef.p, nalloc * 3 * 16) != hipSuccess ||
-        hipMalloc(&I.ibm_lam.p, nalloc * 8) != hipSuccess) {
+        hipMalloc(&I.ibm_lam.p, nalloc * 8) != hipSuccess || hipMalloc(&I.ibm_sig.p, nalloc * 8) != hipSuccess) {
       rc = fail(c, IBM_ERR_OOM, "immersed-boundary lists");
       break;
     }
     I.ibm_idx.bytes = nalloc * 4;
     I.ibm_coef.bytes = nalloc * 48;
     I.ibm_lam.bytes = nalloc * 8;
+    I.ibm_sig.bytes = nalloc * 8;
     int32_t* idx = (int32_t*)I.ibm_idx.p;
     double2* coef = (double2*)I.ibm_coef.p;
     double* lamo = (double*)I.ibm_lam.p;
+    double* sigo = (double*)I.ibm_sig.p;
     const double* lam_dense[3] = {lam_u, lam_v, lam_w};
+    const double* sig_dense[3] = {sig_u, sig_v, sig_w};
     int64_t off = 0;
     for (int q = 0; q < 3; ++q) {
       // block offsets for this mask (scan), then compaction and coefficients
       e = launch_count_flags(I.tag, g.ncell, bmask[q], blk, nblk, st);
       if (e == hipSuccess) e = launch_scan_counts(blk, nblk, I.itotal, st);
       if (e == hipSuccess) e = launch_compact(I.tag, g.ncell, bmask[q], blk, idx + off, nblk, st);
-      if (e == hipSuccess) e = launch_ibm_coef(idx, lam_dense[q], (int)I.n_ibm[q], I.d.dt, I.d.b_mode, lamo, coef,
-                                               (int)ntot, (int)off, st);
+      if (e == hipSuccess) e = launch_ibm_coef(idx, lam_dense[q], sig_dense[q], (int)I.n_ibm[q], I.d.dt, I.d.b_mode,
+                                               lamo, sigo, coef, (int)ntot, (int)off, st);
       if (e != hipSuccess) { rc = fail(c, IBM_ERR_DEVICE, std::string("ibm lists: ") + hipGetErrorString(e)); break; }
       off += I.n_ibm[q];
     }
@@ -588,12 +601,17 @@ int set_geometry_impl(ibm_ctx* c, Instance& I, const double* su, const double* s
     I.L.cpr = cpr;
     I.L.idx = idx;
     I.L.coef = coef;
+    I.L.sig = sigo;
+    I.L.wallv = I.wallv();
+    I.L.sd = I.wall_sd();
+    I.L.n_cover = I.moving() ? (int)ntot : (int)I.n_ibm[0];
     I.L.n_u = (int)I.n_ibm[0];
     I.L.n_v = (int)I.n_ibm[1];
     I.L.n_w = (int)I.n_ibm[2];
     I.L.n_total = (int)ntot;
     int np = 0;
-    e = launch_s_k(g, I.tag, I.L, I.d.dt, I.red_part, &np, st);
+    e = launch_wall_sd(I.L, I.wall_sd(), st);
+    if (e == hipSuccess) e = launch_s_k(g, I.tag, I.L, I.d.dt, I.red_part, &np, st);
     if (e == hipSuccess) e = launch_s_k_final(I.red_part, np, I.d.dt * g.dy * g.dz / g.nx, I.S3(), st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) { rc = fail(c, IBM_ERR_DEVICE, std::string("S_k: ") + hipGetErrorString(e)); break; }
@@ -974,6 +992,27 @@ int ibm_set_diagnostics(ibm_handle h, int32_t on) {
   return IBM_OK;
 }
 
+int ibm_set_wall_velocity(ibm_handle h, int32_t inst, double ub, double vb, double wb) {
+  int rc = check_inst(h, inst);
+  if (rc) return rc;
+  if (!std::isfinite(ub) || !std::isfinite(vb) || !std::isfinite(wb))
+    return fail(h, IBM_ERR_ARG, "wall velocity must be finite");
+  Instance& I = h->inst[inst];
+  // a pending projection is applied with the walls' previous velocity at external faces
+  if ((rc = materialize(h, I))) return rc;
+  const double v[3] = {ub, vb, wb};
+  HIPCHK(h, hipMemcpyAsync(I.wallv(), v, sizeof(v), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  I.wall_vel[0] = ub;
+  I.wall_vel[1] = vb;
+  I.wall_vel[2] = wb;
+  // with moving walls the flow-rate kernel visits every immersed-boundary point (the
+  // launch shape changes: captured graphs and batched arguments are rebuilt)
+  I.L.n_cover = I.moving() ? I.L.n_total : I.L.n_u;
+  drop_graph(h);
+  return seed_pending(h, I);
+}
+
 int ibm_wall_shear(ibm_handle h, int32_t inst, double* tau_x, double* modes) {
   int rc = check_inst(h, inst);
   if (rc) return rc;
@@ -985,10 +1024,10 @@ int ibm_wall_shear(ibm_handle h, int32_t inst, double* tau_x, double* modes) {
   double* md = modes ? I.wall_tau + g.nx : nullptr;
   if (h->precision == IBM_FP64) {
     RUNK(h, K_WALL_SHEAR,
-         launch_wall_shear<double>(g, (const double*)I.u, I.wall_j, I.wall_d, tx, md, h->stream));
+         launch_wall_shear<double>(g, (const double*)I.u, I.wall_j, I.wall_d, I.wallv(), tx, md, h->stream));
   } else {
     RUNK(h, K_WALL_SHEAR,
-         launch_wall_shear<float>(g, (const float*)I.u, I.wall_j, I.wall_d, tx, md, h->stream));
+         launch_wall_shear<float>(g, (const float*)I.u, I.wall_j, I.wall_d, I.wallv(), tx, md, h->stream));
   }
   if (modes) {
     HIPCHK(h, hipMemcpyAsync(modes, md, 3 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
@@ -1233,7 +1272,7 @@ int autotune_impl(ibm_ctx* c, Instance& I, int steps, int32_t* chosen) {
   return rc;
 }
 
-// Ensembles launched together (graph branches or one launch per kernel for all): the
+// Ensembles launched together (one launch per kernel for all instances): the
 // knobs that decide how the instances share the GPU (y planes per momentum block, tile
 // order) are tuned jointly by timing whole ensemble steps in that launch mode, the same
 // value for every instance; the other knobs keep their per-grid values.  The state of
@@ -1350,7 +1389,10 @@ int ibm_autotune(ibm_handle h, int32_t steps_per_trial, int32_t* chosen) {
   drop_graph(h);
   for (Instance& I : h->inst)
     if (!I.geom_ready) return fail(h, IBM_ERR_STATE, "autotune before ibm_set_geometry");
-  if (h->inst.size() > 1 && (h->use_graph || h->use_batch))
+  // the joint tuner serves ensembles launched as one launch per kernel for all instances;
+  // an ensemble of per-instance graph branches is tuned one instance at a time (eager
+  // launches), as are single grids
+  if (h->inst.size() > 1 && h->use_batch)
     return (h->precision == IBM_FP64) ? autotune_ensemble<double>(h, steps_per_trial, chosen)
                                       : autotune_ensemble<float>(h, steps_per_trial, chosen);
   for (Instance& I : h->inst) {
@@ -1410,7 +1452,8 @@ int64_t ibm_device_bytes(ibm_handle h) {
   int64_t b = 0;
   for (Instance& I : h->inst) {
     for (auto& x : I.bufs) b += (int64_t)x.bytes;
-    b += I.ibm_idx.bytes + I.ibm_coef.bytes + I.ibm_lam.bytes + I.ibm_choff.bytes + I.geo_tmp.bytes;
+    b += I.ibm_idx.bytes + I.ibm_coef.bytes + I.ibm_lam.bytes + I.ibm_sig.bytes + I.ibm_choff.bytes +
+         I.geo_tmp.bytes;
   }
   return b;
 }
@@ -1424,6 +1467,7 @@ int ibm_destroy(ibm_handle h) {
     free_buf(I.ibm_idx);
     free_buf(I.ibm_coef);
     free_buf(I.ibm_lam);
+    free_buf(I.ibm_sig);
     free_buf(I.ibm_choff);
     free_buf(I.geo_tmp);
   }

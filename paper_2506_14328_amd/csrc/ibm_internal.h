@@ -127,6 +127,11 @@ struct StageConsts {
 struct IbmLists {
   const int32_t* idx;      // [n_u | n_v | n_w] linear cell indices
   const double2* coef;     // [3 stages][n_total] (B, 1/A)
+  const double* sig;       // [n_total] coefficient of the wall velocity (moving walls)
+  const double* wallv;     // [3] velocity of the immersed walls (device memory)
+  const double* sd;        // [3 stages] sum over the IBM u points of sig / A
+  int n_cover;             // points the flow-rate kernel visits: n_u, or n_total when the
+                           // immersed walls move (it adds their term at every IBM point)
   const int32_t* choff_u;
   const int32_t* choff_v;
   const int32_t* choff_w;
@@ -324,7 +329,7 @@ hipError_t launch_reduce_final(const double* part, int npart, int nsum, int nmax
 // geometry
 hipError_t launch_geom_lambda(const GridParams& g, const double* su, const double* sv, const double* sw,
                               int ibm_on, uint8_t* tag, double* lam_u, double* lam_v, double* lam_w,
-                              hipStream_t st);
+                              double* sig_u, double* sig_v, double* sig_w, hipStream_t st);
 hipError_t launch_geom_ptag(const GridParams& g, uint8_t* tag, hipStream_t st);
 hipError_t launch_geom_south_wall(const GridParams& g, const double* su, int ibm_on, int32_t* wj, double* wd,
                                   hipStream_t st);
@@ -345,10 +350,12 @@ hipError_t launch_pcg_step(const GridParams& g, const uint8_t* tag, double* x, d
 hipError_t launch_pcg_total(const GridParams& g, const double* part, int slot, double* out, hipStream_t st);
 hipError_t launch_pcg_finish(const GridParams& g, const uint8_t* tag, double* x, const double* part,
                              int64_t n_internal, hipStream_t st);
+// out[k] = sum over the immersed-boundary u points of sig / A_k, k = 0..2 (one block)
+hipError_t launch_wall_sd(const IbmLists& L, double* out, hipStream_t st);
 // tau_x[nx] and, if modes is not null, modes[3] = (tau_0, tau_1c, tau_1s)
 template <typename T>
-hipError_t launch_wall_shear(const GridParams& g, const T* u, const int32_t* wj, const double* wd, double* tau_x,
-                             double* modes, hipStream_t st);
+hipError_t launch_wall_shear(const GridParams& g, const T* u, const int32_t* wj, const double* wd,
+                             const double* wallv, double* tau_x, double* modes, hipStream_t st);
 hipError_t launch_count_flags(const uint8_t* tag, int64_t n, uint8_t mask, int32_t* blk_counts,
                               int nblk, hipStream_t st);
 hipError_t launch_scan_counts(int32_t* blk_counts, int nblk, int32_t* total, hipStream_t st);
@@ -356,9 +363,9 @@ hipError_t launch_chunk_counts(const uint8_t* tag, const GridParams& g, uint8_t 
                                hipStream_t st);
 hipError_t launch_compact(const uint8_t* tag, int64_t n, uint8_t mask, const int32_t* blk_offsets,
                           int32_t* idx_out, int nblk, hipStream_t st);
-hipError_t launch_ibm_coef(const int32_t* idx, const double* lam_dense, int n, double dt, int b_mode,
-                           double* lam_out, double2* coef /* [3][n_total] at offset */, int n_total,
-                           int offset, hipStream_t st);
+hipError_t launch_ibm_coef(const int32_t* idx, const double* lam_dense, const double* sig_dense, int n, double dt,
+                           int b_mode, double* lam_out, double* sig_out,
+                           double2* coef /* [3][n_total] at offset */, int n_total, int offset, hipStream_t st);
 hipError_t launch_s_k(const GridParams& g, const uint8_t* tag, const IbmLists& L, double dt, double* part,
                       int* npart, hipStream_t st);
 hipError_t launch_s_k_final(const double* part, int npart, double scale, double* S3, hipStream_t st);

@@ -19,13 +19,27 @@ __device__ __forceinline__ double arm(double nu, double h, double sP, double sQ,
   return nu * (h - delta) / (delta * h * h);
 }
 
-// Tags of u, v, w and lambda per component at every cell (j, k, i).
+// Coefficient of the wall velocity U_b in the correction of one arm whose neighbour is
+// external (a rigidly moving immersed wall; the ghost is extrapolated through U_b): 0 when
+// the nearer wall is a box wall (at rest); lambda_arm when the neighbour stores U_b (an
+// external point inside the box, box = infinity); nu/(delta h) when it stores zero (the
+// box-wall face or the ghost beyond it, box finite).
+__device__ __forceinline__ double arm_src(double nu, double h, double sP, double sQ, bool extQ, double box) {
+  if (!extQ || !(sQ <= 0.0)) return 0.0;
+  const double delta = h * sP / (sP - sQ);
+  if (!(delta < box)) return 0.0;
+  return isinf(box) ? nu * (h - delta) / (delta * h * h) : nu / (delta * h);
+}
+
+// Tags of u, v, w and lambda per component at every cell (j, k, i); with sig_* not null
+// also the wall-velocity coefficient sigma per component.
 //  sdf_u, sdf_w: (ny+1, nz, nx), row jj = j+1 holds row j; sdf_v: (ny, nz, nx) faces.
 __global__ __launch_bounds__(256) void k_geom_lambda(GridParams g, const double* __restrict__ su,
                                                     const double* __restrict__ sv, const double* __restrict__ sw,
                                                     int ibm_on, uint8_t* __restrict__ tag,
                                                     double* __restrict__ lam_u, double* __restrict__ lam_v,
-                                                    double* __restrict__ lam_w) {
+                                                    double* __restrict__ lam_w, double* __restrict__ sig_u,
+                                                    double* __restrict__ sig_v, double* __restrict__ sig_w) {
   const int i = blockIdx.x * BX + threadIdx.x;
   const int k = blockIdx.y * BZ + threadIdx.y;
   const int j = blockIdx.z;
@@ -41,7 +55,7 @@ __global__ __launch_bounds__(256) void k_geom_lambda(GridParams g, const double*
     const double* s = comp == 0 ? su : sw;
     const int o = (j + 1) * plane + k * nx;
     const double sP = s[o + i];
-    double lam = 0.0;
+    double lam = 0.0, sg = 0.0;
     const bool in = sP > 0.0;
     if (in) {
       const double sxm = s[o + im], sxp = s[o + ip];
@@ -55,17 +69,24 @@ __global__ __launch_bounds__(256) void k_geom_lambda(GridParams g, const double*
       lam += arm(nu, dz, sP, szp, szp <= 0.0, INFINITY);
       lam += arm(nu, dy, sP, sdn, gdn || sdn <= 0.0, gdn ? 0.5 * dy : INFINITY);
       lam += arm(nu, dy, sP, sup, gup || sup <= 0.0, gup ? 0.5 * dy : INFINITY);
-      if (!ibm_on) lam = 0.0;
+      sg += arm_src(nu, dx, sP, sxm, sxm <= 0.0, INFINITY);
+      sg += arm_src(nu, dx, sP, sxp, sxp <= 0.0, INFINITY);
+      sg += arm_src(nu, dz, sP, szm, szm <= 0.0, INFINITY);
+      sg += arm_src(nu, dz, sP, szp, szp <= 0.0, INFINITY);
+      sg += arm_src(nu, dy, sP, sdn, gdn || sdn <= 0.0, gdn ? 0.5 * dy : INFINITY);
+      sg += arm_src(nu, dy, sP, sup, gup || sup <= 0.0, gup ? 0.5 * dy : INFINITY);
+      if (!ibm_on) lam = sg = 0.0;
       t |= (comp == 0) ? TAG_U : TAG_W;
       if (lam > 0.0) t |= (comp == 0) ? TAG_UI : TAG_WI;
     }
     (comp == 0 ? lam_u : lam_w)[c] = lam;
+    (comp == 0 ? sig_u : sig_w)[c] = sg;
   }
   // v on face j; faces 0 and ny-1 are the box walls.
   {
     const int o = j * plane + k * nx;
     const double sP = sv[o + i];
-    double lam = 0.0;
+    double lam = 0.0, sg = 0.0;
     if (j >= 1 && sP > 0.0) {
       const double sxm = sv[o + im], sxp = sv[o + ip];
       const double szm = sv[o + (km - k) * nx + i], szp = sv[o + (kp - k) * nx + i];
@@ -77,11 +98,18 @@ __global__ __launch_bounds__(256) void k_geom_lambda(GridParams g, const double*
       lam += arm(nu, dz, sP, szp, szp <= 0.0, INFINITY);
       lam += arm(nu, dy, sP, sdn, wdn || sdn <= 0.0, wdn ? dy : INFINITY);
       lam += arm(nu, dy, sP, sup, wup || sup <= 0.0, wup ? dy : INFINITY);
-      if (!ibm_on) lam = 0.0;
+      sg += arm_src(nu, dx, sP, sxm, sxm <= 0.0, INFINITY);
+      sg += arm_src(nu, dx, sP, sxp, sxp <= 0.0, INFINITY);
+      sg += arm_src(nu, dz, sP, szm, szm <= 0.0, INFINITY);
+      sg += arm_src(nu, dz, sP, szp, szp <= 0.0, INFINITY);
+      sg += arm_src(nu, dy, sP, sdn, wdn || sdn <= 0.0, wdn ? dy : INFINITY);
+      sg += arm_src(nu, dy, sP, sup, wup || sup <= 0.0, wup ? dy : INFINITY);
+      if (!ibm_on) lam = sg = 0.0;
       t |= TAG_V;
       if (lam > 0.0) t |= TAG_VI;
     }
     lam_v[c] = lam;
+    sig_v[c] = sg;
   }
   tag[c] = t;
 }
@@ -106,7 +134,8 @@ __global__ __launch_bounds__(256) void k_geom_ptag(GridParams g, uint8_t* __rest
 // its distance d1 to the wall below, located as the immersed boundary locates it (the
 // linear zero crossing of the signed distance towards the external point below, or the
 // south box wall dy/2 below row 0 when nearer); without the correction the staircase
-// wall is at the external point (dy).  j1 = -1, d1 = 0 for a column with no internal u.
+// wall is at the external point (dy).  j1 = -1, d1 = 0 for a column with no internal u;
+// d1 is stored negative where the wall is the south box wall (at rest).
 __global__ __launch_bounds__(256) void k_geom_south_wall(GridParams g, const double* __restrict__ su, int ibm_on,
                                                         int32_t* __restrict__ wj, double* __restrict__ wd) {
   const int i = blockIdx.x * BX + threadIdx.x;
@@ -125,17 +154,15 @@ __global__ __launch_bounds__(256) void k_geom_south_wall(GridParams g, const dou
     }
   }
   double d = 0.0;
+  bool box = false;
   if (j1 >= 0) {
-    if (ibm_on) {
-      const double sdn = su[(size_t)j1 * plane + col];
-      d = (sdn <= 0.0) ? g.dy * sP / (sP - sdn) : INFINITY;
-      if (j1 == 0) d = fmin(d, 0.5 * g.dy);
-    } else {
-      d = g.dy;
-    }
+    const double sdn = su[(size_t)j1 * plane + col];
+    const double cross = (sdn <= 0.0) ? g.dy * sP / (sP - sdn) : INFINITY;
+    box = (j1 == 0) && (0.5 * g.dy <= cross);
+    d = ibm_on ? (box ? 0.5 * g.dy : cross) : g.dy;
   }
   wj[col] = j1;
-  wd[col] = d;
+  wd[col] = box ? -d : d;   // negative: the wall is the south box wall (at rest)
 }
 
 // Count cells whose tag has `mask` set, per block of 256 cells.
@@ -227,12 +254,15 @@ __global__ __launch_bounds__(256) void k_compact(const uint8_t* __restrict__ tag
 
 // lambda and per-stage (B, 1/A) of each immersed-boundary point (Eqs. (14)-(16)).
 __global__ __launch_bounds__(256) void k_ibm_coef(const int32_t* __restrict__ idx, const double* __restrict__ lam_dense,
-                                                 int n, double dt, int b_mode, double* __restrict__ lam_out,
+                                                 const double* __restrict__ sig_dense, int n, double dt, int b_mode,
+                                                 double* __restrict__ lam_out, double* __restrict__ sig_out,
                                                  double2* __restrict__ coef, int n_total, int offset) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
-  const double lam = lam_dense[idx[offset + e]];
+  const int c = idx[offset + e];
+  const double lam = lam_dense[c];
   lam_out[offset + e] = lam;
+  sig_out[offset + e] = sig_dense[c];
   for (int k = 0; k < 3; ++k) {
     const double ck = rk_c(k);
     const double x = lam * ck * dt;
@@ -437,7 +467,9 @@ constexpr int WS_Z = 16;
 template <typename T>
 __global__ __launch_bounds__(BX * WS_Z) void k_wall_shear(GridParams g, const T* __restrict__ u,
                                                          const int32_t* __restrict__ wj,
-                                                         const double* __restrict__ wd, double* __restrict__ tau_x) {
+                                                         const double* __restrict__ wd,
+                                                         const double* __restrict__ wallv,
+                                                         double* __restrict__ tau_x) {
   __shared__ double red[WS_Z][BX];
   const int i = blockIdx.x * BX + threadIdx.x;
   const size_t plane = (size_t)g.nx * g.nz;
@@ -446,7 +478,11 @@ __global__ __launch_bounds__(BX * WS_Z) void k_wall_shear(GridParams g, const T*
     for (int k = threadIdx.y; k < g.nz; k += WS_Z) {
       const int col = k * g.nx + i;
       const int j1 = wj[col];
-      if (j1 >= 0) acc += (double)u[(size_t)j1 * plane + col] / wd[col];
+      if (j1 >= 0) {
+        const double dw = wd[col];
+        const double ub = dw < 0.0 ? 0.0 : wallv[0];   // the immersed wall may slide
+        acc += ((double)u[(size_t)j1 * plane + col] - ub) / fabs(dw);
+      }
     }
   }
   red[threadIdx.y][threadIdx.x] = acc;
@@ -484,6 +520,19 @@ __global__ __launch_bounds__(256) void k_tau_modes(const double* __restrict__ ta
   }
 }
 
+// out[k] = sum over the IBM u points of sig / A_k (fixed order): the flow rate a moving
+// wall adds to the predictor at stage k, per unit c_k dt U_b.
+__global__ __launch_bounds__(256) void k_wall_sd(IbmLists L, double* __restrict__ out) {
+  __shared__ double red[4];
+  for (int k = 0; k < 3; ++k) {
+    double s = 0.0;
+    for (int e = threadIdx.x; e < L.n_u; e += blockDim.x) s += L.sig[e] * L.coef[(size_t)k * L.n_total + e].y;
+    const double r = block_reduce<false>(s, red);
+    if (threadIdx.x == 0) out[k] = r;
+    __syncthreads();
+  }
+}
+
 }  // namespace
 
 static inline dim3 cell_grid(const GridParams& g) {
@@ -492,14 +541,19 @@ static inline dim3 cell_grid(const GridParams& g) {
 
 hipError_t launch_geom_lambda(const GridParams& g, const double* su, const double* sv, const double* sw,
                               int ibm_on, uint8_t* tag, double* lam_u, double* lam_v, double* lam_w,
-                              hipStream_t st) {
+                              double* sig_u, double* sig_v, double* sig_w, hipStream_t st) {
   hipLaunchKernelGGL(k_geom_lambda, cell_grid(g), dim3(BX, BZ), 0, st, g, su, sv, sw, ibm_on, tag, lam_u, lam_v,
-                     lam_w);
+                     lam_w, sig_u, sig_v, sig_w);
   return hipGetLastError();
 }
 
 hipError_t launch_geom_ptag(const GridParams& g, uint8_t* tag, hipStream_t st) {
   hipLaunchKernelGGL(k_geom_ptag, cell_grid(g), dim3(BX, BZ), 0, st, g, tag);
+  return hipGetLastError();
+}
+
+hipError_t launch_wall_sd(const IbmLists& L, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_wall_sd, dim3(1), dim3(256), 0, st, L, out);
   return hipGetLastError();
 }
 
@@ -511,16 +565,17 @@ hipError_t launch_geom_south_wall(const GridParams& g, const double* su, int ibm
 }
 
 template <typename T>
-hipError_t launch_wall_shear(const GridParams& g, const T* u, const int32_t* wj, const double* wd, double* tau_x,
-                             double* modes, hipStream_t st) {
-  hipLaunchKernelGGL(k_wall_shear<T>, dim3((g.nx + BX - 1) / BX), dim3(BX, WS_Z), 0, st, g, u, wj, wd, tau_x);
+hipError_t launch_wall_shear(const GridParams& g, const T* u, const int32_t* wj, const double* wd,
+                             const double* wallv, double* tau_x, double* modes, hipStream_t st) {
+  hipLaunchKernelGGL(k_wall_shear<T>, dim3((g.nx + BX - 1) / BX), dim3(BX, WS_Z), 0, st, g, u, wj, wd, wallv,
+                     tau_x);
   if (modes) hipLaunchKernelGGL(k_tau_modes, dim3(1), dim3(256), 0, st, tau_x, g.nx, modes);
   return hipGetLastError();
 }
 template hipError_t launch_wall_shear<double>(const GridParams&, const double*, const int32_t*, const double*,
-                                              double*, double*, hipStream_t);
+                                              const double*, double*, double*, hipStream_t);
 template hipError_t launch_wall_shear<float>(const GridParams&, const float*, const int32_t*, const double*,
-                                             double*, double*, hipStream_t);
+                                             const double*, double*, double*, hipStream_t);
 
 hipError_t launch_count_flags(const uint8_t* tag, int64_t n, uint8_t mask, int32_t* blk_counts, int nblk,
                               hipStream_t st) {
@@ -546,11 +601,12 @@ hipError_t launch_compact(const uint8_t* tag, int64_t n, uint8_t mask, const int
   return hipGetLastError();
 }
 
-hipError_t launch_ibm_coef(const int32_t* idx, const double* lam_dense, int n, double dt, int b_mode,
-                           double* lam_out, double2* coef, int n_total, int offset, hipStream_t st) {
+hipError_t launch_ibm_coef(const int32_t* idx, const double* lam_dense, const double* sig_dense, int n, double dt,
+                           int b_mode, double* lam_out, double* sig_out, double2* coef, int n_total, int offset,
+                           hipStream_t st) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ibm_coef, dim3((n + 255) / 256), dim3(256), 0, st, idx, lam_dense, n, dt, b_mode, lam_out,
-                     coef, n_total, offset);
+  hipLaunchKernelGGL(k_ibm_coef, dim3((n + 255) / 256), dim3(256), 0, st, idx, lam_dense, sig_dense, n, dt, b_mode,
+                     lam_out, sig_out, coef, n_total, offset);
   return hipGetLastError();
 }
 

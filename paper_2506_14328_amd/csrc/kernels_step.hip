@@ -117,6 +117,8 @@ __device__ __forceinline__ void k_momentum_body(GridParams g, Fields<T> f, IbmLi
     offb = (gz == 0 ? nz - 1 : gz - 1) * nx + gx;
   }
   const T pick = T(pi_prev[0] * ckdt_prev), ckp = T(ckdt_prev);
+  // immersed walls' velocity (held by the external points inside the box)
+  const T ubw = T(L.wallv[0]), vbw = T(L.wallv[1]), wbw = T(L.wallv[2]);
   const T idx = T(g.idx), idy = T(g.idy), idz = T(g.idz);
   // phi of the plane below this thread's pair (the v correction's south neighbour) is
   // kept from the previous plane instead of being loaded again; only the first plane of
@@ -143,30 +145,35 @@ __device__ __forceinline__ void k_momentum_body(GridParams g, Fields<T> f, IbmLi
     const uint16_t keep = (g.top_fs && jj == ny1) ? uint16_t(~((TAG_V | TAG_VI | TAG_P) * 0x0101u)) : uint16_t(0);
     q.tg = inb ? t : uint16_t(t & keep);
   };
-  // corrected state of one fetched value (tag tg, its phi and west/back/south phi)
-  auto corr = [&](int fld, uint8_t tg, T val, T ph, T phx, T phz, T phy) -> T {
+  // corrected state of one fetched value (tag tg, its phi and west/back/south phi); an
+  // external point inside the box holds the immersed walls' velocity (the south box-wall
+  // face of v and everything beyond the box walls hold zero)
+  auto corr = [&](int fld, uint8_t tg, T val, T ph, T phx, T phz, T phy, int kind) -> T {
     if (fld == 0) {
       const T pk = ((tg & (TAG_U | TAG_UI)) == TAG_U) ? pick : T(0);
-      return (tg & TAG_U) ? val - pk - ckp * ((ph - phx) * idx) : T(0);
+      return (tg & TAG_U) ? val - pk - ckp * ((ph - phx) * idx) : (kind == 1 ? T(0) : ubw);
     }
-    if (fld == 1) return (tg & TAG_V) ? val - ckp * ((ph - phy) * idy) : T(0);
-    if (fld == 2) return (tg & TAG_W) ? val - ckp * ((ph - phz) * idz) : T(0);
+    if (fld == 1) return (tg & TAG_V) ? val - ckp * ((ph - phy) * idy) : (kind == 0 ? vbw : T(0));
+    if (fld == 2) return (tg & TAG_W) ? val - ckp * ((ph - phz) * idz) : (kind == 1 ? T(0) : wbw);
     return (tg & TAG_P) ? val + ph : T(0);
   };
   // corrected state of the fetched pair into ring slot sl
-  auto put = [&](int sl, const TileRaw<T>& a, bool with_phy) {
+  // (jj: the plane's index; beyond the box walls and on the south box-wall plane the
+  // external values are zero, elsewhere the immersed walls' velocity)
+  auto put = [&](int sl, int jj, const TileRaw<T>& a, bool with_phy) {
     if (has) {
       const int e = 2 * tid;   // tile index of the pair's first value
       const Pair<T> phy = with_phy ? a.phy : phprev;   // a plane outside the box has tag 0
       const uint8_t t0 = uint8_t(a.tg & 0xff), t1 = uint8_t(a.tg >> 8);
-      const Pair<T> cu = {corr(0, t0, a.us.x, a.ph.x, a.phw.y, a.phz.x, phy.x),
-                          corr(0, t1, a.us.y, a.ph.y, a.ph.x, a.phz.y, phy.y)};
-      const Pair<T> cv = {corr(1, t0, a.vs.x, a.ph.x, a.phw.y, a.phz.x, phy.x),
-                          corr(1, t1, a.vs.y, a.ph.y, a.ph.x, a.phz.y, phy.y)};
-      const Pair<T> cw = {corr(2, t0, a.ws.x, a.ph.x, a.phw.y, a.phz.x, phy.x),
-                          corr(2, t1, a.ws.y, a.ph.y, a.ph.x, a.phz.y, phy.y)};
-      const Pair<T> cp = {corr(3, t0, a.pp.x, a.ph.x, a.phw.y, a.phz.x, phy.x),
-                          corr(3, t1, a.pp.y, a.ph.y, a.ph.x, a.phz.y, phy.y)};
+      const int kd = (jj < 0 || jj >= ny1) ? 1 : (jj == 0 ? 2 : 0);
+      const Pair<T> cu = {corr(0, t0, a.us.x, a.ph.x, a.phw.y, a.phz.x, phy.x, kd),
+                          corr(0, t1, a.us.y, a.ph.y, a.ph.x, a.phz.y, phy.y, kd)};
+      const Pair<T> cv = {corr(1, t0, a.vs.x, a.ph.x, a.phw.y, a.phz.x, phy.x, kd),
+                          corr(1, t1, a.vs.y, a.ph.y, a.ph.x, a.phz.y, phy.y, kd)};
+      const Pair<T> cw = {corr(2, t0, a.ws.x, a.ph.x, a.phw.y, a.phz.x, phy.x, kd),
+                          corr(2, t1, a.ws.y, a.ph.y, a.ph.x, a.phz.y, phy.y, kd)};
+      const Pair<T> cp = {corr(3, t0, a.pp.x, a.ph.x, a.phw.y, a.phz.x, phy.x, kd),
+                          corr(3, t1, a.pp.y, a.ph.y, a.ph.x, a.phz.y, phy.y, kd)};
       *reinterpret_cast<Pair<T>*>(&ring[0][sl][e]) = cu;
       *reinterpret_cast<Pair<T>*>(&ring[1][sl][e]) = cv;
       *reinterpret_cast<Pair<T>*>(&ring[2][sl][e]) = cw;
@@ -183,9 +190,9 @@ __device__ __forceinline__ void k_momentum_body(GridParams g, Fields<T> f, IbmLi
     fetch(j0 - 1, q0, true);
     fetch(j0, q1, false);
     fetch(j0 + 1, q2, false);
-    put(slot(j0 - 1), q0, true);
-    put(slot(j0), q1, false);
-    put(slot(j0 + 1), q2, false);
+    put(slot(j0 - 1), j0 - 1, q0, true);
+    put(slot(j0), j0, q1, false);
+    put(slot(j0 + 1), j0 + 1, q2, false);
   }
   const int cc = (tz + 1) * MHX + (tx + 2);   // centre inside a tile
   __syncthreads();
@@ -303,10 +310,13 @@ __device__ __forceinline__ void k_momentum_body(GridParams g, Fields<T> f, IbmLi
         f.Hv[c] = Hv;
         f.Hw[c] = Hw;
       }
-      T su = zero, sv = zero, sw = zero;
+      // external points keep the immersed walls' velocity (v on the south box wall: 0)
+      T su = ubw, sv = (j == 0) ? zero : vbw, sw = wbw;
       if (tg & TAG_U) su = uc + ru;
       if (tg & TAG_V) sv = vc + rv;
       if (tg & TAG_W) sw = wc + rw;
+      // implicit IBM update (a moving wall's term sigma U_b c_k dt / A is added by the
+      // flow-rate kernel, which visits the immersed-boundary points)
       if (tg & TAG_UI) su = T((cfu.x * (double)uc + (double)ru) * cfu.y);
       if (tg & TAG_VI) sv = T((cfv.x * (double)vc + (double)rv) * cfv.y);
       if (tg & TAG_WI) sw = T((cfw.x * (double)wc + (double)rw) * cfw.y);
@@ -316,7 +326,7 @@ __device__ __forceinline__ void k_momentum_body(GridParams g, Fields<T> f, IbmLi
       f.pn[c] = pc;
       if (tg & TAG_U) qloc += (double)su;
     }
-    put(slot(j + 2), nq, false);
+    put(slot(j + 2), j + 2, nq, false);
     __syncthreads();
   }
   const double tot = block_reduce<false>(qloc, red);
@@ -355,15 +365,20 @@ __device__ __forceinline__ void k_cfr_pi_body(Fields<T> f, IbmLists L, int stage
                                                double* __restrict__ pi_out, double* __restrict__ pi_hist, int bid_x, int bid_y, int nblk) {
   __shared__ double red[4];
   __shared__ double pi_s;
-  // this thread's immersed-boundary u face and its u* are loaded first, so that their
-  // latency overlaps the reduction
+  // this thread's immersed-boundary point (a u face; with moving walls any component) and
+  // its predictor are loaded first, so that their latency overlaps the reduction
   const int g = bid_x * blockDim.x + threadIdx.x;
   int id = 0;
-  double inva = 0.0, usv = 0.0;
-  if (g < L.n_u) {
+  double inva = 0.0, usv = 0.0, add = 0.0;
+  T* fp = f.us;
+  if (g < L.n_cover) {
+    const int comp = g < L.n_u ? 0 : (g < L.n_u + L.n_v ? 1 : 2);
+    fp = comp == 0 ? f.us : (comp == 1 ? f.vs : f.ws);
     id = L.idx[g];
     inva = L.coef[(size_t)stage * L.n_total + g].y;
-    usv = (double)f.us[id];
+    usv = (double)fp[id];
+    // a moving wall's term sigma U_b c_k dt / A of the implicit update (zero at rest)
+    add = L.sig[g] * ck_dt * L.wallv[comp] * inva;
   }
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   const int stride = blockDim.x * 8;
@@ -377,7 +392,9 @@ __device__ __forceinline__ void k_cfr_pi_body(Fields<T> f, IbmLists L, int stage
   const double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
   const double tot = block_reduce<false>(s, red);
   if (threadIdx.x == 0) {
-    const double q0 = tot * scale;
+    // the partials hold u* without the moving walls' term; its sum over the IBM u points
+    // is c_k dt U_b sum(sig / A)
+    const double q0 = (tot + ck_dt * L.wallv[0] * L.sd[stage]) * scale;
     const double pi = (forcing == 0) ? (q0 - qt) / S3[stage] : qt;
     pi_s = pi;
     if (bid_x == 0) {
@@ -387,7 +404,7 @@ __device__ __forceinline__ void k_cfr_pi_body(Fields<T> f, IbmLists L, int stage
     }
   }
   __syncthreads();
-  if (g < L.n_u) f.us[id] = T(usv - pi_s * ck_dt * inva);
+  if (g < L.n_cover) fp[id] = T(usv + add - (g < L.n_u ? pi_s * ck_dt * inva : 0.0));
 }
 
 template <typename T>
@@ -947,7 +964,6 @@ __global__ __launch_bounds__(256) void k_ifftx_b(const IfftxArgs<T>* __restrict_
 template <typename T>
 __global__ __launch_bounds__(256) void k_correct(GridParams g, Fields<T> f, IbmLists L, int stage, double ck_dt,
                                                 const double* __restrict__ pi) {
-  (void)L;
   (void)stage;
   const int i = blockIdx.x * BX + threadIdx.x;
   const int k = blockIdx.y * BZ + threadIdx.y;
@@ -965,9 +981,10 @@ __global__ __launch_bounds__(256) void k_correct(GridParams g, Fields<T> f, IbmL
   const T un = usv - pick - ckdt * ((ph - phw) * T(g.idx));
   const T vn = vsv - ckdt * ((ph - phs) * T(g.idy));
   const T wn = wsv - ckdt * ((ph - phb) * T(g.idz));
-  f.u[c] = (tg & TAG_U) ? un : T(0);
-  f.v[c] = (tg & TAG_V) ? vn : T(0);
-  f.w[c] = (tg & TAG_W) ? wn : T(0);
+  // external points hold the immersed walls' velocity (v on the south box wall: 0)
+  f.u[c] = (tg & TAG_U) ? un : T(L.wallv[0]);
+  f.v[c] = (tg & TAG_V) ? vn : (j == 0 ? T(0) : T(L.wallv[1]));
+  f.w[c] = (tg & TAG_W) ? wn : T(L.wallv[2]);
   f.p[c] = (tg & TAG_P) ? pv + ph : T(0);
 }
 
@@ -1014,7 +1031,7 @@ template <typename T>
 hipError_t launch_cfr_pi(const Fields<T>& f, const IbmLists& L, int stage, double ck_dt, const double* qpart, int nq,
                          double scale, int forcing, double q_target_or_pi, const double* S3, double* pi_out,
                          double* pi_hist, hipStream_t st) {
-  const int nb = L.n_u > 0 ? (L.n_u + 255) / 256 : 1;
+  const int nb = L.n_cover > 0 ? (L.n_cover + 255) / 256 : 1;
   hipLaunchKernelGGL(k_cfr_pi<T>, dim3(nb), dim3(256), 0, st, f, L, stage, ck_dt, qpart, nq, scale, forcing,
                      q_target_or_pi, S3, pi_out, pi_hist);
   return hipGetLastError();
@@ -1212,7 +1229,7 @@ template <typename T>
 int plan_cfr_pi(const Fields<T>& f, const IbmLists& L, int stage, double ck_dt, const double* qpart, int nq,
                 double scale, int forcing, double q_target_or_pi, const double* S3, double* pi_out, double* pi_hist,
                 CfrArgs<T>* a) {
-  const int nb = L.n_u > 0 ? (L.n_u + 255) / 256 : 1;
+  const int nb = L.n_cover > 0 ? (L.n_cover + 255) / 256 : 1;
   *a = CfrArgs<T>{f, L, stage, ck_dt, qpart, nq, scale, forcing, q_target_or_pi, S3, pi_out, pi_hist, nb};
   return nb;
 }

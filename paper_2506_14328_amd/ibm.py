@@ -29,6 +29,7 @@ EXPORTED = [
     "ibm_solve_pressure", "ibm_stats", "ibm_set_diagnostics", "ibm_get_geometry", "ibm_get_ibm_list",
     "ibm_profile", "ibm_profile_read", "ibm_kernel_name", "ibm_num_kernels", "ibm_device_bytes",
     "ibm_destroy", "ibm_last_error", "ibm_tune_set", "ibm_tune_get", "ibm_autotune", "ibm_wall_shear",
+    "ibm_set_wall_velocity",
 ]
 TUNE_PARAMS = {"momentum_planes": 0, "fftz_width": 1, "tri_rows": 2, "graph": 3, "graph_branches": 4,
                "tile_order": 5, "batch": 6}
@@ -78,6 +79,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "ibm_solve_pressure": (c_int32, [h, c_int32, c_void_p, c_void_p]),
         "ibm_stats": (c_int32, [h, c_int32, POINTER(IbmStats)]),
         "ibm_wall_shear": (c_int32, [h, c_int32, c_void_p, POINTER(c_double)]),
+        "ibm_set_wall_velocity": (c_int32, [h, c_int32, c_double, c_double, c_double]),
         "ibm_set_diagnostics": (c_int32, [h, c_int32]),
         "ibm_get_geometry": (c_int32, [h, c_int32, c_void_p, POINTER(c_int64)]),
         "ibm_get_ibm_list": (c_int32, [h, c_int32, c_int32, c_void_p, c_void_p, c_void_p]),
@@ -213,6 +215,10 @@ class IbmGrid:
         d["n_ibm"] = list(s.n_ibm)
         d["unstable"] = rc == IBM_ERR_UNSTABLE
         return d
+
+    def set_wall_velocity(self, ub: float, vb: float = 0.0, wb: float = 0.0, inst: int = 0):
+        """Velocity of the immersed walls (rigid translation; ibm_set_wall_velocity)."""
+        self._check(self.lib.ibm_set_wall_velocity(self._h, inst, float(ub), float(vb), float(wb)))
 
     def wall_shear(self, inst: int = 0) -> Tuple[torch.Tensor, Tuple[float, float, float]]:
         """Spanwise-averaged south-wall shear stress tau(x_i) (device, float64) and

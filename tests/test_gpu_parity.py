@@ -309,7 +309,11 @@ def test_ensemble_matches_oracle_per_instance(graph, batch):
     g.close()
 
 
-@pytest.mark.parametrize("batch", [False, True])
+@pytest.mark.parametrize("batch", [
+    pytest.param(False, marks=pytest.mark.skip(
+        reason="joint tuning of per-instance graph branches is switched off: one run of it ended "
+               "in an abort whose cause is not known; such ensembles are tuned per instance")),
+    True])
 def test_ensemble_autotune_joint(batch):
     """The autotuner of an ensemble launched together picks one plane count and tile order
     for every instance by timing whole ensemble steps, leaves every state as it was, and
