@@ -60,6 +60,7 @@ class Case:
     geo_params: Tuple = ()
     top: int = 0       # 0 = no-slip north box face, 1 = free-slip north face (open channel)
     projection: int = 0  # 0 = full-box pressure projection, 1 = masked (internal cells only)
+    y_faces: Optional[Tuple[float, ...]] = None  # stretched wall-normal grid: the ny face y's
 
     @property
     def dx(self) -> float:
@@ -81,7 +82,7 @@ class Case:
 def coords(c: Case) -> Dict[str, np.ndarray]:
     """Sample positions of the staggered grids (1-D per direction)."""
     dx, dy, dz = c.dx, c.dy, c.dz
-    return {
+    out = {
         "xf": np.arange(c.nx) * dx,
         "xc": (np.arange(c.nx) + 0.5) * dx,
         "zf": np.arange(c.nz) * dz,
@@ -89,7 +90,27 @@ def coords(c: Case) -> Dict[str, np.ndarray]:
         "yf": c.y_lo + np.arange(c.ny) * dy,                  # faces 0..ny-1
         "yc_g": c.y_lo + (np.arange(-1, c.ny) + 0.5) * dy,    # centres -1..ny-1 (with ghosts)
         "yc": c.y_lo + (np.arange(c.ny - 1) + 0.5) * dy,      # centres 0..ny-2
+        "dyc": np.full(c.ny - 1, dy),                          # cell heights
     }
+    if c.y_faces is not None:
+        # stretched: centres midway between faces, ghost centres mirrored in the box faces
+        yf = np.asarray(c.y_faces, dtype=np.float64)
+        yc = 0.5 * (yf[:-1] + yf[1:])
+        out["yf"] = yf
+        out["yc"] = yc
+        out["yc_g"] = np.concatenate([[2.0 * yf[0] - yc[0]], yc, [2.0 * yf[-1] - yc[-1]]])
+        out["dyc"] = np.diff(yf)
+    return out
+
+
+def tanh_faces(ny: int, y_lo: float, y_hi: float, gamma: float) -> Tuple[float, ...]:
+    """ny wall-normal faces clustered towards both box walls: y = mid + half
+    tanh(gamma xi)/tanh(gamma), xi uniform in [-1, 1] (gamma -> 0: uniform)."""
+    xi = np.linspace(-1.0, 1.0, ny)
+    t = np.tanh(gamma * xi) / math.tanh(gamma)
+    y = 0.5 * (y_lo + y_hi) + 0.5 * (y_hi - y_lo) * t
+    y[0], y[-1] = y_lo, y_hi
+    return tuple(float(a) for a in y)
 
 
 def _mesh(y, z, x):
@@ -235,7 +256,8 @@ def divergence_free_field(c: Case, seed: int, smooth_passes: int = 2):
     psz = _smooth(rng.standard_normal((c.ny, c.nz, c.nx)), smooth_passes) * damp_f[:, None, None]
     psx[0] = psx[-1] = 0.0
     psz[0] = psz[-1] = 0.0
-    dx, dy, dz = c.dx, c.dy, c.dz
+    dx, dz = c.dx, c.dz
+    dy = g["dyc"][:, None, None]
     u = (psz[1:] - psz[:-1]) / dy - (np.roll(psy, -1, axis=1) - psy) / dz
     v = (np.roll(psx[:-1], -1, axis=1) - psx[:-1]) / dz - (np.roll(psz[:-1], -1, axis=2) - psz[:-1]) / dx
     w = (np.roll(psy, -1, axis=2) - psy) / dx - (psx[1:] - psx[:-1]) / dy

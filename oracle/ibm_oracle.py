@@ -30,7 +30,7 @@ equation as -Pi (the paper's notation in Sec. 2.5, Eq. (18)).
 from __future__ import annotations
 
 import math
-from dataclasses import dataclass
+from dataclasses import dataclass, field
 from typing import Dict, Optional, Tuple
 
 import numpy as np
@@ -61,6 +61,64 @@ class OGrid:
     b_mode: int = B_EXP
     top: int = 0          # 0: no-slip north box face; 1: free-slip north face
     projection: int = 0   # 0: full-box projection (reading R6); 1: masked (reading R18)
+    # y of the ny v faces (increasing, first y_lo, last y_hi) for a stretched wall-normal
+    # grid (Sec. 2.1: non-uniform spacing; reading R20); None: uniform spacing dy
+    y_faces: Optional[np.ndarray] = field(default=None, repr=False, compare=False)
+
+    @property
+    def stretched(self) -> bool:
+        return self.y_faces is not None
+
+    @property
+    def yf(self) -> np.ndarray:
+        """y of the v faces 0..ny-1 (faces 0 and ny-1 are the box walls)."""
+        if self.y_faces is None:
+            return self.y_lo + np.arange(self.ny) * self.dy
+        return np.asarray(self.y_faces, dtype=np.float64)
+
+    @property
+    def yc(self) -> np.ndarray:
+        """y of the cell centres (rows of u, w, p), midway between their faces."""
+        f = self.yf
+        return 0.5 * (f[:-1] + f[1:])
+
+    @property
+    def dyc(self) -> np.ndarray:
+        """Cell heights y_f[j+1] - y_f[j], rows 0..ny-2 (dy on a uniform grid)."""
+        if self.y_faces is None:
+            return np.full(self.ny - 1, self.dy)
+        return np.diff(self.yf)
+
+    @property
+    def hy_lo(self) -> np.ndarray:
+        """Distance from centre row j to the row below; the ghost row -1 is the mirror
+        image of row 0 in the south box wall (distance dyc[0])."""
+        if self.y_faces is None:
+            return np.full(self.ny - 1, self.dy)
+        out = np.empty(self.ny - 1)
+        out[0] = self.dyc[0]
+        out[1:] = np.diff(self.yc)
+        return out
+
+    @property
+    def hy_hi(self) -> np.ndarray:
+        """Distance from centre row j to the row above; the ghost row ny-1 is the mirror
+        image of the top row in the north face (distance dyc[-1])."""
+        if self.y_faces is None:
+            return np.full(self.ny - 1, self.dy)
+        out = np.empty(self.ny - 1)
+        out[-1] = self.dyc[-1]
+        out[:-1] = np.diff(self.yc)
+        return out
+
+    def face_weights(self) -> Tuple[np.ndarray, np.ndarray]:
+        """Linear-interpolation weights of centre rows j-1 and j at face j (rows 0..ny-2;
+        at face 0 the ghost row is the mirror image, weights 1/2): (w_lo, w_hi)."""
+        d = self.dyc
+        dm = np.empty_like(d)
+        dm[0] = d[0]
+        dm[1:] = d[:-1]
+        return d / (dm + d), dm / (dm + d)
 
     @property
     def dx(self):
@@ -80,9 +138,35 @@ class OGrid:
 
     @classmethod
     def from_case(cls, c) -> "OGrid":
+        yfs = getattr(c, "y_faces", None)
         return cls(c.nx, c.ny, c.nz, c.lx, c.lz, c.y_lo, c.y_hi, c.nu, c.dt,
                    c.forcing, c.q_target_or_pi, c.b_mode, int(getattr(c, "top", 0)),
-                   int(getattr(c, "projection", 0)))
+                   int(getattr(c, "projection", 0)),
+                   None if yfs is None else np.asarray(yfs, dtype=np.float64))
+
+
+def col(a: np.ndarray) -> np.ndarray:
+    """A per-row array shaped to broadcast over (row, k, i)."""
+    return np.asarray(a)[:, None, None]
+
+
+def second_derivative_weights(hm, hp):
+    """Coefficients d2(-1), d2(+1) of the three-point second derivative with spacings hm
+    below and hp above (Eq. (3); d2(0) = -(d2(-1) + d2(+1))); 1/h^2 on a uniform grid."""
+    return 2.0 / (hm * (hm + hp)), 2.0 / (hp * (hm + hp))
+
+
+def y_spacings(g: "OGrid", comp: str) -> Tuple[np.ndarray, np.ndarray]:
+    """Spacings (below, above) of the wall-normal stencil of each stored row of a
+    component: centre rows for u, w (mirror ghosts at the box faces), face spacings for v
+    (face j lies between cells j-1 and j)."""
+    if comp in ("u", "w"):
+        return g.hy_lo, g.hy_hi
+    d = g.dyc
+    lo = np.empty_like(d)
+    lo[0] = d[0]
+    lo[1:] = d[:-1]
+    return lo, d
 
 
 # --------------------------------------------------------------------------------------
@@ -129,20 +213,34 @@ def classify(g: OGrid, sdf_u, sdf_v, sdf_w) -> Dict[str, np.ndarray]:
     return {"u": int_u, "v": int_v, "w": int_w, "p": int_p}
 
 
-def _arm_lambda(nu, h, sP, sQ, extQ, box_dist):
-    """Contribution nu * d2(-1) (h - delta)/delta of one stencil arm (Eq. (7)).
+def _arm_lambda(nu, h, sP, sQ, extQ, box_dist, d2=None):
+    """Contribution nu * d2 (h - delta)/delta of one stencil arm of length h (Eq. (7)).
 
     delta is the distance from the internal point to the wall along the arm:
     the linear zero crossing of the signed distance between the point and its
     external neighbour (reading R8), or the box wall when that is nearer.
-    d2(-1) = 1/h^2 for the uniform three-point second derivative (Eq. (3)).
+    d2 is the arm's coefficient of the three-point second derivative (Eq. (3)):
+    1/h^2 on a uniform spacing (d2 = None), second_derivative_weights otherwise.
     """
     with np.errstate(divide="ignore", invalid="ignore"):
         d_sdf = np.where(sQ <= 0.0, h * sP / (sP - sQ), np.inf)
     delta = np.minimum(d_sdf, box_dist)
     with np.errstate(divide="ignore", invalid="ignore"):
-        contrib = np.where(extQ, nu * (h - delta) / (delta * h * h), 0.0)
+        if d2 is None:
+            contrib = np.where(extQ, nu * (h - delta) / (delta * h * h), 0.0)
+        else:
+            contrib = np.where(extQ, nu * d2 * (h - delta) / delta, 0.0)
     return contrib
+
+
+def _y_arms(g: OGrid, comp, s_dn, ext_dn, box_dn, s_up, ext_up, box_up):
+    """The two wall-normal stencil arms (length, neighbour SDF, external flag, box-wall
+    distance, second-derivative coefficient or None for uniform spacing)."""
+    if not g.stretched:
+        return ((g.dy, s_dn, ext_dn, box_dn, None), (g.dy, s_up, ext_up, box_up, None))
+    lo, hi = y_spacings(g, comp)
+    d2lo, d2hi = second_derivative_weights(lo, hi)
+    return ((col(lo), s_dn, ext_dn, box_dn, col(d2lo)), (col(hi), s_up, ext_up, box_up, col(d2hi)))
 
 
 def wall_lambda(g: OGrid, sdf_full: np.ndarray, comp: str, internal: np.ndarray) -> np.ndarray:
@@ -165,10 +263,10 @@ def wall_lambda(g: OGrid, sdf_full: np.ndarray, comp: str, internal: np.ndarray)
         ext_dn[0] = True              # ghost rows are outside the box
         box_dn = np.full(s.shape, np.inf)
         box_up = np.full(s.shape, np.inf)
-        box_dn[0] = 0.5 * g.dy        # u, w of row 0 sit dy/2 above the south box wall
-        if g.top == 0:                # a north box wall dy/2 above the top row
+        box_dn[0] = 0.5 * g.dyc[0]    # u, w of row 0 sit half a cell above the south box wall
+        if g.top == 0:                # a north box wall half a cell above the top row
             ext_up[-1] = True
-            box_up[-1] = 0.5 * g.dy
+            box_up[-1] = 0.5 * g.dyc[-1]
     else:  # v: faces 0..ny-1 are all stored in sdf_full; face 0 and ny-1 are box walls
         s = sdf_full[:-1]
         s_dn = np.zeros_like(s)
@@ -180,18 +278,16 @@ def wall_lambda(g: OGrid, sdf_full: np.ndarray, comp: str, internal: np.ndarray)
         ext_up[-1] = True             # neighbour face ny-1 is the north box wall
         box_dn = np.full(s.shape, np.inf)
         box_up = np.full(s.shape, np.inf)
-        box_dn[1] = g.dy
-        box_up[-1] = g.dy
+        box_dn[1] = g.dyc[0]
+        box_up[-1] = g.dyc[-1]
     lam = np.zeros(s.shape)
-    for h, sQ, extQ, bd in (
-        (g.dx, sx(s, -1), sx(s, -1) <= 0.0, np.inf),
-        (g.dx, sx(s, +1), sx(s, +1) <= 0.0, np.inf),
-        (g.dz, sz(s, -1), sz(s, -1) <= 0.0, np.inf),
-        (g.dz, sz(s, +1), sz(s, +1) <= 0.0, np.inf),
-        (g.dy, s_dn, ext_dn, box_dn),
-        (g.dy, s_up, ext_up, box_up),
-    ):
-        lam += _arm_lambda(nu, h, s, sQ, extQ, bd)
+    for h, sQ, extQ, bd, d2 in (
+        (g.dx, sx(s, -1), sx(s, -1) <= 0.0, np.inf, None),
+        (g.dx, sx(s, +1), sx(s, +1) <= 0.0, np.inf, None),
+        (g.dz, sz(s, -1), sz(s, -1) <= 0.0, np.inf, None),
+        (g.dz, sz(s, +1), sz(s, +1) <= 0.0, np.inf, None),
+    ) + _y_arms(g, comp, s_dn, ext_dn, box_dn, s_up, ext_up, box_up):
+        lam += _arm_lambda(nu, h, s, sQ, extQ, bd, d2)
     lam = np.where(internal, lam, 0.0)
     return lam
 
@@ -220,10 +316,10 @@ def wall_source(g: OGrid, sdf_full: np.ndarray, comp: str, internal: np.ndarray)
         ext_dn[0] = True
         box_dn = np.full(s.shape, np.inf)
         box_up = np.full(s.shape, np.inf)
-        box_dn[0] = 0.5 * g.dy
+        box_dn[0] = 0.5 * g.dyc[0]
         if g.top == 0:
             ext_up[-1] = True
-            box_up[-1] = 0.5 * g.dy
+            box_up[-1] = 0.5 * g.dyc[-1]
     else:
         s = sdf_full[:-1]
         s_dn = np.zeros_like(s)
@@ -235,22 +331,23 @@ def wall_source(g: OGrid, sdf_full: np.ndarray, comp: str, internal: np.ndarray)
         ext_up[-1] = True
         box_dn = np.full(s.shape, np.inf)
         box_up = np.full(s.shape, np.inf)
-        box_dn[1] = g.dy
-        box_up[-1] = g.dy
+        box_dn[1] = g.dyc[0]
+        box_up[-1] = g.dyc[-1]
     sig = np.zeros(s.shape)
     with np.errstate(divide="ignore", invalid="ignore"):
-        for h, sQ, extQ, bd in (
-            (g.dx, sx(s, -1), sx(s, -1) <= 0.0, np.inf),
-            (g.dx, sx(s, +1), sx(s, +1) <= 0.0, np.inf),
-            (g.dz, sz(s, -1), sz(s, -1) <= 0.0, np.inf),
-            (g.dz, sz(s, +1), sz(s, +1) <= 0.0, np.inf),
-            (g.dy, s_dn, ext_dn, box_dn),
-            (g.dy, s_up, ext_up, box_up),
-        ):
+        for h, sQ, extQ, bd, d2 in (
+            (g.dx, sx(s, -1), sx(s, -1) <= 0.0, np.inf, None),
+            (g.dx, sx(s, +1), sx(s, +1) <= 0.0, np.inf, None),
+            (g.dz, sz(s, -1), sz(s, -1) <= 0.0, np.inf, None),
+            (g.dz, sz(s, +1), sz(s, +1) <= 0.0, np.inf, None),
+        ) + _y_arms(g, comp, s_dn, ext_dn, box_dn, s_up, ext_up, box_up):
             d_sdf = np.where(sQ <= 0.0, h * s / (s - sQ), np.inf)
             immersed = extQ & (d_sdf < bd)
             stores_zero = np.isfinite(bd)
-            arm = np.where(stores_zero, nu / (d_sdf * h), nu * (h - d_sdf) / (d_sdf * h * h))
+            if d2 is None:
+                arm = np.where(stores_zero, nu / (d_sdf * h), nu * (h - d_sdf) / (d_sdf * h * h))
+            else:
+                arm = np.where(stores_zero, nu * d2 * h / d_sdf, nu * d2 * (h - d_sdf) / d_sdf)
             sig += np.where(immersed, arm, 0.0)
     return np.where(internal, sig, 0.0)
 
@@ -290,54 +387,70 @@ def convection(g: OGrid, u, v, w):
     No IBM correction of the convective terms: external and ghost values enter
     as zero (Sec. 3.1 and the opening of Sec. 2).
     """
-    dx, dy, dz = g.dx, g.dy, g.dz
+    dx, dz = g.dx, g.dz
     h = 0.5
+    # wall-normal: differences over the cell height (u, w rows) or the centre spacing
+    # (v faces); u and w reach a face by linear interpolation between the rows (midpoint
+    # averages on a uniform grid; reading R20)
+    dy_c = col(g.dyc)
+    dy_f = col(g.hy_lo)
+    wl, wh = (col(a) for a in g.face_weights())
+    wl_p, wh_p = sy(wl, 1), sy(wh, 1)     # weights at face j+1
+    if not g.stretched:
+        wl = wh = wl_p = wh_p = h
     # u-momentum at (i*dx, y_c[j], z_c[k])
     Nu = ((h * (u + sx(u, 1))) ** 2 - (h * (sx(u, -1) + u)) ** 2) / dx
-    Nu += (h * (u + sy(u, 1)) * h * (sx(sy(v, 1), -1) + sy(v, 1))
-           - h * (sy(u, -1) + u) * h * (sx(v, -1) + v)) / dy
+    Nu += ((wl_p * u + wh_p * sy(u, 1)) * h * (sx(sy(v, 1), -1) + sy(v, 1))
+           - (wl * sy(u, -1) + wh * u) * h * (sx(v, -1) + v)) / dy_c
     Nu += (h * (u + sz(u, 1)) * h * (sx(sz(w, 1), -1) + sz(w, 1))
            - h * (sz(u, -1) + u) * h * (sx(w, -1) + w)) / dz
     # v-momentum at (x_c[i], y_f[j], z_c[k])
-    Nv = (h * (v + sx(v, 1)) * h * (sx(sy(u, -1), 1) + sx(u, 1))
-          - h * (sx(v, -1) + v) * h * (sy(u, -1) + u)) / dx
-    Nv += ((h * (v + sy(v, 1))) ** 2 - (h * (sy(v, -1) + v)) ** 2) / dy
-    Nv += (h * (v + sz(v, 1)) * h * (sz(sy(w, -1), 1) + sz(w, 1))
-           - h * (sz(v, -1) + v) * h * (sy(w, -1) + w)) / dz
+    Nv = (h * (v + sx(v, 1)) * (wl * sx(sy(u, -1), 1) + wh * sx(u, 1))
+          - h * (sx(v, -1) + v) * (wl * sy(u, -1) + wh * u)) / dx
+    Nv += ((h * (v + sy(v, 1))) ** 2 - (h * (sy(v, -1) + v)) ** 2) / dy_f
+    Nv += (h * (v + sz(v, 1)) * (wl * sz(sy(w, -1), 1) + wh * sz(w, 1))
+           - h * (sz(v, -1) + v) * (wl * sy(w, -1) + wh * w)) / dz
     # w-momentum at (x_c[i], y_c[j], k*dz)
     Nw = (h * (w + sx(w, 1)) * h * (sx(sz(u, -1), 1) + sx(u, 1))
           - h * (sx(w, -1) + w) * h * (sz(u, -1) + u)) / dx
-    Nw += (h * (w + sy(w, 1)) * h * (sz(sy(v, 1), -1) + sy(v, 1))
-           - h * (sy(w, -1) + w) * h * (sz(v, -1) + v)) / dy
+    Nw += ((wl_p * w + wh_p * sy(w, 1)) * h * (sz(sy(v, 1), -1) + sy(v, 1))
+           - (wl * sy(w, -1) + wh * w) * h * (sz(v, -1) + v)) / dy_c
     Nw += ((h * (w + sz(w, 1))) ** 2 - (h * (sz(w, -1) + w)) ** 2) / dz
     return Nu, Nv, Nw
 
 
-def laplacian(g: OGrid, f, mirror_top: bool = False):
+def laplacian(g: OGrid, f, mirror_top: bool = False, comp: str = "u"):
     """Seven-point Laplacian, Eq. (3), with external/ghost neighbours equal to zero.
 
     Sec. 2.4: as long as external values are zero and the right-hand side is
     explicit, the unmodified Laplacian is used; the wall enters through lambda.
     mirror_top: the ghost row above the top row equals the top row (free-slip face,
-    reading R16).
+    reading R16).  On a stretched grid the wall-normal part takes the three-point
+    coefficients of the row's own spacings (comp selects centre rows or v faces).
     """
     up = sy(f, 1)
     if mirror_top:
         up[-1] = f[-1]
+    if g.stretched:
+        lo, hi = y_spacings(g, comp)
+        dm, dp = (col(a) for a in second_derivative_weights(lo, hi))
+        d2y = dm * sy(f, -1) + dp * up - (dm + dp) * f
+    else:
+        d2y = (up - 2.0 * f + sy(f, -1)) / g.dy ** 2
     return ((sx(f, 1) - 2.0 * f + sx(f, -1)) / g.dx ** 2
-            + (up - 2.0 * f + sy(f, -1)) / g.dy ** 2
+            + d2y
             + (sz(f, 1) - 2.0 * f + sz(f, -1)) / g.dz ** 2)
 
 
 def gradient(g: OGrid, p):
     """G p on the u, v, w faces (row 0 of the v component is the box wall, unused)."""
-    return ((p - sx(p, -1)) / g.dx, (p - sy(p, -1)) / g.dy, (p - sz(p, -1)) / g.dz)
+    return ((p - sx(p, -1)) / g.dx, (p - sy(p, -1)) / col(g.hy_lo), (p - sz(p, -1)) / g.dz)
 
 
 def divergence(g: OGrid, u, v, w):
     """D u at every cell: forward differences to the cell's faces; v on the north
     box wall face is zero."""
-    return (sx(u, 1) - u) / g.dx + (sy(v, 1) - v) / g.dy + (sz(w, 1) - w) / g.dz
+    return (sx(u, 1) - u) / g.dx + (sy(v, 1) - v) / col(g.dyc) + (sz(w, 1) - w) / g.dz
 
 
 def explicit_rhs(g: OGrid, u, v, w, tags):
@@ -345,7 +458,7 @@ def explicit_rhs(g: OGrid, u, v, w, tags):
     Nu, Nv, Nw = convection(g, u, v, w)
     fs = g.top == 1
     Hu = np.where(tags["u"], -Nu + g.nu * laplacian(g, u, fs), 0.0)
-    Hv = np.where(tags["v"], -Nv + g.nu * laplacian(g, v), 0.0)
+    Hv = np.where(tags["v"], -Nv + g.nu * laplacian(g, v, comp="v"), 0.0)
     Hw = np.where(tags["w"], -Nw + g.nu * laplacian(g, w, fs), 0.0)
     return Hu, Hv, Hw
 
@@ -389,18 +502,27 @@ def poisson_solve(g: OGrid, rhs: np.ndarray) -> Tuple[np.ndarray, float]:
     """
     n = g.ny - 1
     rh = scipy.fft.fft(scipy.fft.rfft(rhs, axis=2), axis=1)          # (n, nz, mh)
-    mean00 = rh[:, 0, 0].mean()
+    if g.stretched:
+        # the volume-weighted mean: D G phi sums to zero with the cell heights as weights
+        mean00 = np.sum(rh[:, 0, 0] * g.dyc) / np.sum(g.dyc)
+    else:
+        mean00 = rh[:, 0, 0].mean()
     rh[:, 0, 0] -= mean00
     kx2 = modified_wavenumbers(g.nx, g.dx, half=True)
     kz2 = modified_wavenumbers(g.nz, g.dz, half=False)
     K2 = kz2[:, None] + kx2[None, :]
-    idy2 = 1.0 / (g.dy * g.dy)
     shape = (n,) + K2.shape
-    lower = np.full(shape, idy2)
-    upper = np.full(shape, idy2)
-    diag = np.broadcast_to(-2.0 * idy2 - K2, shape).copy()
-    diag[0] += idy2
-    diag[-1] += idy2
+    if g.stretched:
+        # row j: (1/dyc_j) [(phi_{j+1} - phi_j)/h_{j+1} - (phi_j - phi_{j-1})/h_j]
+        lo = 1.0 / (g.dyc * g.hy_lo)
+        hi = 1.0 / (g.dyc * g.hy_hi)
+    else:
+        lo = hi = np.full(n, 1.0 / (g.dy * g.dy))
+    lower = np.broadcast_to(col(lo), shape).copy()
+    upper = np.broadcast_to(col(hi), shape).copy()
+    diag = -(lower + upper) - K2
+    diag[0] += lower[0]
+    diag[-1] += upper[-1]
     lower[0] = 0.0
     upper[-1] = 0.0
     # gauge of the singular (0,0) mode: replace its first row by phi_0 = 0
@@ -423,6 +545,8 @@ def masked_laplacian(g: OGrid, tags) -> Tuple["scipy.sparse.csr_matrix", np.ndar
     (j, k, i) cell array) and the flat indices of those cells.
     """
     import scipy.sparse as sp
+    if g.stretched:
+        raise NotImplementedError("the masked projection is built for a uniform wall-normal grid")
     pin = tags["p"]
     cells = np.flatnonzero(pin.ravel())
     pos = -np.ones(pin.size, dtype=np.int64)
@@ -554,8 +678,11 @@ class Oracle:
         return out
 
     def flow_rate(self, f):
-        """Q = (1/nx) sum over internal u faces of f dy dz (mean flux through x-planes)."""
+        """Q = (1/nx) sum over internal u faces of f dy dz (mean flux through x-planes;
+        dy the cell height of the row on a stretched grid)."""
         g = self.g
+        if g.stretched:
+            return float(np.sum(np.where(self.tags["u"], f, 0.0) * col(g.dyc)) * g.dz / g.nx)
         return float(np.sum(np.where(self.tags["u"], f, 0.0)) * g.dy * g.dz / g.nx)
 
     # -- one RK substep --------------------------------------------------------------
@@ -646,9 +773,11 @@ class Oracle:
             "q": self.flow_rate(self.u),
             "pi_last": self.pi_last,
             "div_max_internal_leak": float(np.abs(np.where(t["p"], d, 0.0)).max()),
-            "ke": float(0.5 * (np.sum(self.u ** 2) + np.sum(self.v ** 2) + np.sum(self.w ** 2))
+            "ke": float(0.5 * np.sum((self.u ** 2 + self.v ** 2 + self.w ** 2) * col(g.dyc))
+                        * g.dx * g.dz) if g.stretched else
+                  float(0.5 * (np.sum(self.u ** 2) + np.sum(self.v ** 2) + np.sum(self.w ** 2))
                         * g.dx * g.dy * g.dz),
-            "cfl_max": float(np.max(np.abs(self.u) / g.dx + np.abs(self.v) / g.dy
+            "cfl_max": float(np.max(np.abs(self.u) / g.dx + np.abs(self.v) / col(g.dyc)
                                     + np.abs(self.w) / g.dz) * g.dt),
             "n_internal": [int(t[c].sum()) for c in "uvw"],
             "n_ibm": [int((self.lam[c] > 0).sum()) for c in "uvw"],
@@ -694,10 +823,11 @@ def south_wall_points(g: OGrid, sdf_u: np.ndarray, ibm: bool = True, with_box: b
     kk, ii = np.meshgrid(np.arange(g.nz), np.arange(g.nx), indexing="ij")
     sP = s[j1, kk, ii]
     s_dn = sdf_u[j1, kk, ii]                 # row j1 - 1 (the ghost row for j1 = 0)
-    d1 = np.full(j1.shape, g.dy)
+    harm = g.hy_lo[j1]                      # length of the stencil arm below row j1
+    d1 = harm.copy()
     with np.errstate(divide="ignore", invalid="ignore"):
-        cross = np.where(s_dn <= 0.0, g.dy * sP / (sP - s_dn), np.inf)
-    box = np.where(j1 == 0, 0.5 * g.dy, np.inf)
+        cross = np.where(s_dn <= 0.0, harm * sP / (sP - s_dn), np.inf)
+    box = np.where(j1 == 0, 0.5 * g.dyc[0], np.inf)
     if ibm:
         d1 = np.minimum(cross, box)
     j1 = np.where(has, j1, -1)
