@@ -180,6 +180,20 @@ int ibm_stats(ibm_handle h, int32_t inst, ibm_stats_t* out);
  * Synchronises the stream.  IBM_ERR_ARG for a non-finite velocity. */
 int ibm_set_wall_velocity(ibm_handle h, int32_t inst, double ub, double vb, double wb);
 
+/* Stretched wall-normal grid (Sec. 2.1 allows non-uniform spacing): y_faces (host, ny
+ * doubles, strictly increasing, the first y_lo and the last y_hi of the descriptor) are
+ * the positions of the v faces; cell centres lie midway between their faces.  Every
+ * wall-normal operator takes the spacings of its row: the three-point second derivative
+ * with its non-uniform coefficient triple (Eq. (3)), lambda and sigma from the arm's own
+ * coefficient and length (Eqs. (5)-(7)), u and w carried to the faces by linear
+ * interpolation, the divergence and the pressure Poisson rows with the cell heights,
+ * the flow rate and S_k weighted by them.  The immersed-boundary data depend on the
+ * spacing: call ibm_set_geometry afterwards (IBM_ERR_STATE until then).  Applies a
+ * pending projection first and drops captured graphs.  Synchronises the stream.
+ * IBM_ERR_ARG for a masked-projection instance, non-finite or non-increasing faces or
+ * end points other than y_lo, y_hi (relative tolerance 1e-12). */
+int ibm_set_y_faces(ibm_handle h, int32_t inst, const double* y_faces);
+
 /* Wall-shear stress of the current state along the south wall, the undulated bottom
  * of the open channel (Sec. 4.2), and its Fourier components tau_1c, tau_1s defined
  * there.  Per (z_k, x_i) column of u points: the lowest internal u point, u1, at

@@ -115,6 +115,7 @@ struct ibm_ctx {
     int n_mom = 0, n_cfr = 0, n_div = 0, n_fz = 0, n_tri = 0, n_ifx = 0;
     int mb_div = 1, mb_fz = 1, mb_ifx = 1, lm_tri = 4, th_fz = 256;
     size_t lds_div = 0, lds_fz = 0, lds_tri = 0, lds_ifx = 0;
+    bool stretched = false;   // some instance has a stretched wall-normal grid
   } batch;
 };
 
@@ -158,6 +159,50 @@ bool factor_235(int n, int* radix, int* nst) {
   *nst = k;
   return n == 1;
 }
+
+// Per-row wall-normal tables (the YTable layout) of the faces yf[0..ny1]: the same
+// arithmetic as the definitions of the spacings (cell heights, centre spacings with the
+// ghost centres mirrored in the box faces).
+std::vector<double> y_tables(const double* yf, int ny1) {
+  const int ys = ny1 + 1;
+  std::vector<double> t((size_t)YT_NF * ys, 0.0);
+  std::vector<double> dyc(ny1), yc(ny1), h(ny1 + 1);
+  for (int j = 0; j < ny1; ++j) {
+    dyc[j] = yf[j + 1] - yf[j];
+    yc[j] = 0.5 * (yf[j] + yf[j + 1]);
+  }
+  h[0] = dyc[0];
+  for (int j = 1; j < ny1; ++j) h[j] = yc[j] - yc[j - 1];
+  h[ny1] = dyc[ny1 - 1];
+  double box = 0.0;
+  for (int j = 0; j < ny1; ++j) box += dyc[j];
+  auto at = [&](int f, int j) -> double& { return t[(size_t)f * ys + j]; };
+  for (int j = 0; j < ny1; ++j) {
+    const double dm = j > 0 ? dyc[j - 1] : dyc[0];
+    at(YT_IDYC, j) = 1.0 / dyc[j];
+    at(YT_DCM, j) = 2.0 / (h[j] * (h[j] + h[j + 1]));
+    at(YT_DCP, j) = 2.0 / (h[j + 1] * (h[j] + h[j + 1]));
+    at(YT_DFM, j) = 2.0 / (dm * (dm + dyc[j]));
+    at(YT_DFP, j) = 2.0 / (dyc[j] * (dm + dyc[j]));
+    at(YT_WLO, j) = dyc[j] / (dm + dyc[j]);
+    at(YT_WHI, j) = dm / (dm + dyc[j]);
+    at(YT_DYC, j) = dyc[j];
+    at(YT_TLO, j) = 1.0 / (dyc[j] * h[j]);
+    at(YT_THI, j) = 1.0 / (dyc[j] * h[j + 1]);
+  }
+  for (int j = 0; j <= ny1; ++j) {
+    at(YT_IDYF, j) = 1.0 / h[j];
+    at(YT_HC, j) = h[j];
+  }
+  at(YT_WLO, ny1) = 0.5;
+  at(YT_WHI, ny1) = 0.5;
+  at(YT_DYC, ny1) = box;
+  return t;
+}
+
+// dy in the flow-rate and volume scale factors: the kernels already weight each row by
+// its cell height on a stretched grid
+inline double y_scale(const GridParams& g) { return g.stretched ? 1.0 : g.dy; }
 
 int dalloc(ibm_ctx* c, Instance& I, void** out, size_t bytes) {
   if (bytes == 0) bytes = 16;
@@ -250,6 +295,19 @@ int init_instance(ibm_ctx* c, Instance& I, const ibm_grid_desc& d) {
   if ((g.splane / line) % 2 == 0) g.splane += line;
   int rc;
   if ((rc = make_plan(c, I, g.nhalf, &I.px))) return rc;
+  {
+    // wall-normal tables (uniform values until ibm_set_y_faces)
+    std::vector<double> yf(d.ny);
+    for (int j = 0; j < d.ny; ++j) yf[j] = d.y_lo + j * g.dy;
+    const std::vector<double> tab = y_tables(yf.data(), g.ny1);
+    double* yt = nullptr;
+    if ((rc = dalloc(c, I, (void**)&yt, tab.size() * sizeof(double)))) return rc;
+    HIPCHK(c, hipMemcpyAsync(yt, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    g.ytab = yt;
+    g.ystr = g.ny1 + 1;
+    g.stretched = 0;
+  }
   if ((rc = make_plan(c, I, g.nz, &I.pz))) return rc;
   const size_t fb = (size_t)g.ncell * ts;
   void** fields[] = {&I.u, &I.v, &I.w, &I.p, &I.S[0][0], &I.S[0][1], &I.S[0][2], &I.S[1][0], &I.S[1][1],
@@ -416,7 +474,7 @@ int pcg_project(ibm_ctx* c, Instance& I, Fields<double>& f, hipStream_t st) {
 template <typename T>
 int run_steps(ibm_ctx* c, Instance& I, int nsteps, hipStream_t st, bool count = true) {
   const GridParams& g = I.g;
-  const double scale = g.dy * g.dz / g.nx;
+  const double scale = y_scale(g) * g.dz / g.nx;
   for (int s = 0; s < nsteps; ++s) {
     for (int k = 0; k < 3; ++k) {
       StageConsts sc;
@@ -610,9 +668,8 @@ int set_geometry_impl(ibm_ctx* c, Instance& I, const double* su, const double* s
     I.L.n_w = (int)I.n_ibm[2];
     I.L.n_total = (int)ntot;
     int np = 0;
-    e = launch_wall_sd(I.L, I.wall_sd(), st);
-    if (e == hipSuccess) e = launch_s_k(g, I.tag, I.L, I.d.dt, I.red_part, &np, st);
-    if (e == hipSuccess) e = launch_s_k_final(I.red_part, np, I.d.dt * g.dy * g.dz / g.nx, I.S3(), st);
+    e = launch_s_k(g, I.tag, I.L, I.d.dt, I.red_part, &np, I.wall_sd(), st);
+    if (e == hipSuccess) e = launch_s_k_final(I.red_part, np, I.d.dt * y_scale(g) * g.dz / g.nx, I.S3(), st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) { rc = fail(c, IBM_ERR_DEVICE, std::string("S_k: ") + hipGetErrorString(e)); break; }
     I.geom_ready = true;
@@ -664,8 +721,9 @@ int build_batch(ibm_ctx* c) {
   for (int i = 0; i < n; ++i) {
     Instance& I = c->inst[i];
     const GridParams& g = I.g;
-    const double scale = g.dy * g.dz / g.nx;
+    const double scale = y_scale(g) * g.dz / g.nx;
     b.cur0[i] = I.cur;
+    b.stretched = b.stretched || I.g.stretched;
     int nq = 0, mb = 1, th = 256, lm = 4;
     size_t lds = 0;
     for (int k = 0; k < 3; ++k) {
@@ -763,7 +821,7 @@ int run_steps_batched(ibm_ctx* c, int nsteps, hipStream_t st, bool count = true)
   const int n = (int)c->inst.size();
   for (int s = 0; s < nsteps; ++s) {
     for (int k = 0; k < 3; ++k) {
-      RUNK(c, K_MOMENTUM, launch_momentum_b<T>((const MomArgs<T>*)b.mom[k], b.bo_mom, n, b.n_mom, st));
+      RUNK(c, K_MOMENTUM, launch_momentum_b<T>((const MomArgs<T>*)b.mom[k], b.bo_mom, n, b.n_mom, b.stretched, st));
       for (Instance& I : c->inst) {
         I.cur = (I.cur + 1) % 3;
         I.fresh = false;
@@ -1013,6 +1071,33 @@ int ibm_set_wall_velocity(ibm_handle h, int32_t inst, double ub, double vb, doub
   return seed_pending(h, I);
 }
 
+int ibm_set_y_faces(ibm_handle h, int32_t inst, const double* y_faces) {
+  int rc = check_inst(h, inst);
+  if (rc) return rc;
+  if (!y_faces) return fail(h, IBM_ERR_ARG, "null y_faces");
+  Instance& I = h->inst[inst];
+  if (I.d.projection == IBM_PROJ_MASKED)
+    return fail(h, IBM_ERR_ARG, "the masked projection needs a uniform wall-normal grid");
+  const int ny = I.g.ny1 + 1;
+  const double H = I.d.y_hi - I.d.y_lo;
+  for (int j = 0; j < ny; ++j)
+    if (!std::isfinite(y_faces[j])) return fail(h, IBM_ERR_ARG, "y_faces must be finite");
+  if (std::fabs(y_faces[0] - I.d.y_lo) > 1e-12 * H || std::fabs(y_faces[ny - 1] - I.d.y_hi) > 1e-12 * H)
+    return fail(h, IBM_ERR_ARG, "y_faces must start at y_lo and end at y_hi");
+  for (int j = 0; j + 1 < ny; ++j)
+    if (!(y_faces[j + 1] > y_faces[j])) return fail(h, IBM_ERR_ARG, "y_faces must increase strictly");
+  drop_graph(h);
+  if ((rc = materialize(h, I))) return rc;
+  const std::vector<double> tab = y_tables(y_faces, I.g.ny1);
+  HIPCHK(h, hipMemcpyAsync((void*)I.g.ytab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice,
+                           h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  I.g.stretched = 1;
+  // lambda, sigma, the wall distances and S_k depend on the spacing: a geometry is needed
+  I.geom_ready = false;
+  return IBM_OK;
+}
+
 int ibm_wall_shear(ibm_handle h, int32_t inst, double* tau_x, double* modes) {
   int rc = check_inst(h, inst);
   if (rc) return rc;
@@ -1058,9 +1143,9 @@ int ibm_stats(ibm_handle h, int32_t inst, ibm_stats_t* out) {
   memset(out, 0, sizeof(*out));
   out->step = I.step;
   out->time = I.time;
-  out->q = ro[0] * g.dy * g.dz / g.nx;
+  out->q = ro[0] * y_scale(g) * g.dz / g.nx;
   out->pi_last = host[4];
-  out->ke = 0.5 * ro[1] * g.dx * g.dy * g.dz;
+  out->ke = 0.5 * ro[1] * g.dx * y_scale(g) * g.dz;
   out->nan_flag = ro[2] > 0.0 ? 1 : 0;
   out->cfl_max = ro[3];
   out->div_max_internal_leak = ro[4];

@@ -44,6 +44,32 @@ struct GridParams {
   double idx, idy, idz;
   double idx2, idy2, idz2;
   double nu, dt;
+  // stretched wall-normal grid: stretched = 1 and ytab holds YT_NF per-row tables of
+  // ystr = ny1 + 1 doubles each (table f of row j at ytab[f * ystr + j]); a uniform grid
+  // has stretched = 0 and a table with the uniform values (used only by batched launches
+  // that mix both kinds)
+  int stretched;
+  int ystr;
+  const double* ytab;
+};
+
+// Per-row tables of a stretched wall-normal grid (rows j = 0..ny1-1; entry ny1 is padding).
+// Cell heights dyc_j = y_f[j+1] - y_f[j]; centre spacings h_j = y_c[j] - y_c[j-1] with the
+// ghost centres mirrored in the box faces (h_0 = dyc_0, h_ny1 = dyc_{ny1-1}).
+enum YTable {
+  YT_IDYC = 0,   // 1 / dyc_j (differences across cell j: divergence, fluxes of u and w rows)
+  YT_IDYF,       // 1 / h_j (differences across face j: gradient, flux of v)
+  YT_DCM,        // second-derivative weights of centre row j: below 2/(h_j (h_j + h_{j+1}))
+  YT_DCP,        //   above 2/(h_{j+1} (h_j + h_{j+1}))
+  YT_DFM,        // second-derivative weights of face j: below 2/(dyc_{j-1} (dyc_{j-1} + dyc_j))
+  YT_DFP,        //   above 2/(dyc_j (dyc_{j-1} + dyc_j))  (dyc_{-1} = dyc_0)
+  YT_WLO,        // interpolation to face j: weight of row j-1, dyc_j / (dyc_{j-1} + dyc_j)
+  YT_WHI,        //   weight of row j, dyc_{j-1} / (dyc_{j-1} + dyc_j)
+  YT_DYC,        // dyc_j (flow-rate and volume weights); entry ny1: the box height
+  YT_TLO,        // pressure Poisson row j: lower coefficient 1/(dyc_j h_j)
+  YT_THI,        //   upper coefficient 1/(dyc_j h_{j+1})
+  YT_HC,         // h_j (j = 0..ny1: the mirrored ends included)
+  YT_NF
 };
 
 // Twiddle/stage description of one complex FFT length, resident on the device.
@@ -271,7 +297,8 @@ int plan_ifftx(const GridParams& g, const cplx<T>* spec, T* out, const FFTPlan& 
                IfftxArgs<T>* a, int* mb, size_t* lds);
 // Batched launches: args and boff (ninst + 1 block offsets) in device memory; ntot blocks.
 template <typename T>
-hipError_t launch_momentum_b(const MomArgs<T>* args, const int* boff, int ninst, int ntot, hipStream_t st);
+hipError_t launch_momentum_b(const MomArgs<T>* args, const int* boff, int ninst, int ntot, bool stretched,
+                             hipStream_t st);
 template <typename T>
 hipError_t launch_cfr_pi_b(const CfrArgs<T>* args, const int* boff, int ninst, int ntot, hipStream_t st);
 template <typename T>
@@ -350,8 +377,6 @@ hipError_t launch_pcg_step(const GridParams& g, const uint8_t* tag, double* x, d
 hipError_t launch_pcg_total(const GridParams& g, const double* part, int slot, double* out, hipStream_t st);
 hipError_t launch_pcg_finish(const GridParams& g, const uint8_t* tag, double* x, const double* part,
                              int64_t n_internal, hipStream_t st);
-// out[k] = sum over the immersed-boundary u points of sig / A_k, k = 0..2 (one block)
-hipError_t launch_wall_sd(const IbmLists& L, double* out, hipStream_t st);
 // tau_x[nx] and, if modes is not null, modes[3] = (tau_0, tau_1c, tau_1s)
 template <typename T>
 hipError_t launch_wall_shear(const GridParams& g, const T* u, const int32_t* wj, const double* wd,
@@ -366,8 +391,10 @@ hipError_t launch_compact(const uint8_t* tag, int64_t n, uint8_t mask, const int
 hipError_t launch_ibm_coef(const int32_t* idx, const double* lam_dense, const double* sig_dense, int n, double dt,
                            int b_mode, double* lam_out, double* sig_out,
                            double2* coef /* [3][n_total] at offset */, int n_total, int offset, hipStream_t st);
+// partial sums for S_k into part[0 .. 4 npart); sd_out[k] = sum over the IBM u points of
+// sig / A_k (its partials after those of S_k: part needs 4 (npart + n_u/256 + 1) doubles)
 hipError_t launch_s_k(const GridParams& g, const uint8_t* tag, const IbmLists& L, double dt, double* part,
-                      int* npart, hipStream_t st);
+                      int* npart, double* sd_out, hipStream_t st);
 hipError_t launch_s_k_final(const double* part, int npart, double scale, double* S3, hipStream_t st);
 
 // state copy helpers

@@ -19,6 +19,16 @@ __device__ __forceinline__ double arm(double nu, double h, double sP, double sQ,
   return nu * (h - delta) / (delta * h * h);
 }
 
+// The same with the arm's own second-derivative coefficient d2 (stretched wall-normal
+// arms): nu d2 (h - delta)/delta.
+__device__ __forceinline__ double arm_w(double nu, double h, double d2, double sP, double sQ, bool extQ,
+                                        double box) {
+  if (!extQ) return 0.0;
+  double delta = (sQ <= 0.0) ? h * sP / (sP - sQ) : INFINITY;
+  delta = fmin(delta, box);
+  return nu * d2 * (h - delta) / delta;
+}
+
 // Coefficient of the wall velocity U_b in the correction of one arm whose neighbour is
 // external (a rigidly moving immersed wall; the ghost is extrapolated through U_b): 0 when
 // the nearer wall is a box wall (at rest); lambda_arm when the neighbour stores U_b (an
@@ -29,6 +39,13 @@ __device__ __forceinline__ double arm_src(double nu, double h, double sP, double
   const double delta = h * sP / (sP - sQ);
   if (!(delta < box)) return 0.0;
   return isinf(box) ? nu * (h - delta) / (delta * h * h) : nu / (delta * h);
+}
+__device__ __forceinline__ double arm_src_w(double nu, double h, double d2, double sP, double sQ, bool extQ,
+                                            double box) {
+  if (!extQ || !(sQ <= 0.0)) return 0.0;
+  const double delta = h * sP / (sP - sQ);
+  if (!(delta < box)) return 0.0;
+  return isinf(box) ? nu * d2 * (h - delta) / delta : nu * d2 * h / delta;
 }
 
 // Tags of u, v, w and lambda per component at every cell (j, k, i); with sig_* not null
@@ -49,6 +66,16 @@ __global__ __launch_bounds__(256) void k_geom_lambda(GridParams g, const double*
   const int plane = nx * nz;
   const int c = (j * nz + k) * nx + i;
   const double nu = g.nu, dx = g.dx, dy = g.dy, dz = g.dz;
+  const bool sy = g.stretched != 0;
+  const double* yt = g.ytab;
+  const int ys = g.ystr;
+  // wall-normal arms: uniform spacing dy, or the row's own spacing and coefficient
+  auto yarm = [&](double h, double d2, double sP, double sQ, bool ext, double box) {
+    return sy ? arm_w(nu, h, d2, sP, sQ, ext, box) : arm(nu, h, sP, sQ, ext, box);
+  };
+  auto ysrc = [&](double h, double d2, double sP, double sQ, bool ext, double box) {
+    return sy ? arm_src_w(nu, h, d2, sP, sQ, ext, box) : arm_src(nu, h, sP, sQ, ext, box);
+  };
   uint8_t t = 0;
   // u and w: sample row jj = j + 1; ghost rows jj = 0 and jj = ny are outside the box.
   for (int comp = 0; comp < 3; comp += 2) {
@@ -63,18 +90,27 @@ __global__ __launch_bounds__(256) void k_geom_lambda(GridParams g, const double*
       const double sdn = s[o - plane + i], sup = s[o + plane + i];
       // the south box face is a wall; so is the north one unless it is free-slip
       const bool gdn = (j == 0), gup = (j == ny1 - 1) && !g.top_fs;
+      double hdn = dy, hup = dy, cdn = 0.0, cup = 0.0, bdn = 0.5 * dy, bup = 0.5 * dy;
+      if (sy) {
+        hdn = yt[YT_HC * ys + j];
+        hup = yt[YT_HC * ys + j + 1];
+        cdn = yt[YT_DCM * ys + j];
+        cup = yt[YT_DCP * ys + j];
+        bdn = 0.5 * yt[YT_DYC * ys];
+        bup = 0.5 * yt[YT_DYC * ys + ny1 - 1];
+      }
       lam += arm(nu, dx, sP, sxm, sxm <= 0.0, INFINITY);
       lam += arm(nu, dx, sP, sxp, sxp <= 0.0, INFINITY);
       lam += arm(nu, dz, sP, szm, szm <= 0.0, INFINITY);
       lam += arm(nu, dz, sP, szp, szp <= 0.0, INFINITY);
-      lam += arm(nu, dy, sP, sdn, gdn || sdn <= 0.0, gdn ? 0.5 * dy : INFINITY);
-      lam += arm(nu, dy, sP, sup, gup || sup <= 0.0, gup ? 0.5 * dy : INFINITY);
+      lam += yarm(hdn, cdn, sP, sdn, gdn || sdn <= 0.0, gdn ? bdn : INFINITY);
+      lam += yarm(hup, cup, sP, sup, gup || sup <= 0.0, gup ? bup : INFINITY);
       sg += arm_src(nu, dx, sP, sxm, sxm <= 0.0, INFINITY);
       sg += arm_src(nu, dx, sP, sxp, sxp <= 0.0, INFINITY);
       sg += arm_src(nu, dz, sP, szm, szm <= 0.0, INFINITY);
       sg += arm_src(nu, dz, sP, szp, szp <= 0.0, INFINITY);
-      sg += arm_src(nu, dy, sP, sdn, gdn || sdn <= 0.0, gdn ? 0.5 * dy : INFINITY);
-      sg += arm_src(nu, dy, sP, sup, gup || sup <= 0.0, gup ? 0.5 * dy : INFINITY);
+      sg += ysrc(hdn, cdn, sP, sdn, gdn || sdn <= 0.0, gdn ? bdn : INFINITY);
+      sg += ysrc(hup, cup, sP, sup, gup || sup <= 0.0, gup ? bup : INFINITY);
       if (!ibm_on) lam = sg = 0.0;
       t |= (comp == 0) ? TAG_U : TAG_W;
       if (lam > 0.0) t |= (comp == 0) ? TAG_UI : TAG_WI;
@@ -92,18 +128,26 @@ __global__ __launch_bounds__(256) void k_geom_lambda(GridParams g, const double*
       const double szm = sv[o + (km - k) * nx + i], szp = sv[o + (kp - k) * nx + i];
       const double sdn = sv[o - plane + i], sup = sv[o + plane + i];
       const bool wdn = (j - 1 == 0), wup = (j + 1 == ny1);
+      // face j lies between cells j-1 and j
+      double hdn = dy, hup = dy, cdn = 0.0, cup = 0.0;
+      if (sy) {
+        hdn = yt[YT_DYC * ys + j - 1];
+        hup = yt[YT_DYC * ys + j];
+        cdn = yt[YT_DFM * ys + j];
+        cup = yt[YT_DFP * ys + j];
+      }
       lam += arm(nu, dx, sP, sxm, sxm <= 0.0, INFINITY);
       lam += arm(nu, dx, sP, sxp, sxp <= 0.0, INFINITY);
       lam += arm(nu, dz, sP, szm, szm <= 0.0, INFINITY);
       lam += arm(nu, dz, sP, szp, szp <= 0.0, INFINITY);
-      lam += arm(nu, dy, sP, sdn, wdn || sdn <= 0.0, wdn ? dy : INFINITY);
-      lam += arm(nu, dy, sP, sup, wup || sup <= 0.0, wup ? dy : INFINITY);
+      lam += yarm(hdn, cdn, sP, sdn, wdn || sdn <= 0.0, wdn ? hdn : INFINITY);
+      lam += yarm(hup, cup, sP, sup, wup || sup <= 0.0, wup ? hup : INFINITY);
       sg += arm_src(nu, dx, sP, sxm, sxm <= 0.0, INFINITY);
       sg += arm_src(nu, dx, sP, sxp, sxp <= 0.0, INFINITY);
       sg += arm_src(nu, dz, sP, szm, szm <= 0.0, INFINITY);
       sg += arm_src(nu, dz, sP, szp, szp <= 0.0, INFINITY);
-      sg += arm_src(nu, dy, sP, sdn, wdn || sdn <= 0.0, wdn ? dy : INFINITY);
-      sg += arm_src(nu, dy, sP, sup, wup || sup <= 0.0, wup ? dy : INFINITY);
+      sg += ysrc(hdn, cdn, sP, sdn, wdn || sdn <= 0.0, wdn ? hdn : INFINITY);
+      sg += ysrc(hup, cup, sP, sup, wup || sup <= 0.0, wup ? hup : INFINITY);
       if (!ibm_on) lam = sg = 0.0;
       t |= TAG_V;
       if (lam > 0.0) t |= TAG_VI;
@@ -157,9 +201,12 @@ __global__ __launch_bounds__(256) void k_geom_south_wall(GridParams g, const dou
   bool box = false;
   if (j1 >= 0) {
     const double sdn = su[(size_t)j1 * plane + col];
-    const double cross = (sdn <= 0.0) ? g.dy * sP / (sP - sdn) : INFINITY;
-    box = (j1 == 0) && (0.5 * g.dy <= cross);
-    d = ibm_on ? (box ? 0.5 * g.dy : cross) : g.dy;
+    // length of the stencil arm below row j1 and half the first cell
+    const double harm = g.stretched ? g.ytab[YT_HC * g.ystr + j1] : g.dy;
+    const double half = g.stretched ? 0.5 * g.ytab[YT_DYC * g.ystr] : 0.5 * g.dy;
+    const double cross = (sdn <= 0.0) ? harm * sP / (sP - sdn) : INFINITY;
+    box = (j1 == 0) && (half <= cross);
+    d = ibm_on ? (box ? half : cross) : harm;
   }
   wj[col] = j1;
   wd[col] = box ? -d : d;   // negative: the wall is the south box wall (at rest)
@@ -289,6 +336,8 @@ __global__ __launch_bounds__(256) void k_s_cells(GridParams g, const uint8_t* __
   const int64_t e = blockIdx.x * 256ll + threadIdx.x;
   double c = 0.0;
   if (e < g.ncell) c = ((tag[e] & (TAG_U | TAG_UI)) == TAG_U) ? 1.0 : 0.0;
+  // a stretched grid weights each row by its cell height
+  if (g.stretched && e < g.ncell) c *= g.ytab[YT_DYC * g.ystr + (int)(e / ((int64_t)g.nx * g.nz))];
   const double tot = block_reduce<false>(c, red);
   if (threadIdx.x == 0) {
     part[blockIdx.x * 4 + 0] = tot;
@@ -297,16 +346,43 @@ __global__ __launch_bounds__(256) void k_s_cells(GridParams g, const uint8_t* __
     part[blockIdx.x * 4 + 3] = 0.0;
   }
 }
-__global__ __launch_bounds__(256) void k_s_list(IbmLists L, double* __restrict__ part) {
+// Per block of IBM u points and stage k: sum of 1/A_k into part, and sum of sigma/A_k (the
+// flow rate a moving wall adds, per unit c_k dt U_b) into part_sd.
+__global__ __launch_bounds__(256) void k_s_list(GridParams g, IbmLists L, double* __restrict__ part,
+                                               double* __restrict__ part_sd) {
   __shared__ double red[4];
   const int e = blockIdx.x * 256 + threadIdx.x;
+  const double sg = (e < L.n_u) ? L.sig[e] : 0.0;
+  // a stretched grid weights each point by the cell height of its row
+  const double wy = (g.stretched && e < L.n_u) ? g.ytab[YT_DYC * g.ystr + L.idx[e] / (g.nx * g.nz)] : 1.0;
   for (int k = 0; k < 3; ++k) {
-    const double v = (e < L.n_u) ? L.coef[(size_t)k * L.n_total + e].y : 0.0;
+    double v = (e < L.n_u) ? L.coef[(size_t)k * L.n_total + e].y : 0.0;
+    if (g.stretched) v *= wy;
     const double tot = block_reduce<false>(v, red);
-    if (threadIdx.x == 0) part[blockIdx.x * 4 + 1 + k] = tot;
+    __syncthreads();
+    const double tsd = block_reduce<false>(sg * v, red);
+    if (threadIdx.x == 0) {
+      part[blockIdx.x * 4 + 1 + k] = tot;
+      part_sd[blockIdx.x * 4 + k] = tsd;
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) part[blockIdx.x * 4] = 0.0;
+  if (threadIdx.x == 0) {
+    part[blockIdx.x * 4] = 0.0;
+    part_sd[blockIdx.x * 4 + 3] = 0.0;
+  }
+}
+// out[k] = sum of the npart partials of stage k (fixed order; zero for no partials)
+__global__ __launch_bounds__(1024) void k_sd_final(const double* __restrict__ part, int npart,
+                                                  double* __restrict__ out) {
+  __shared__ double red[16];
+  for (int k = 0; k < 3; ++k) {
+    double s = 0.0;
+    for (int e = threadIdx.x; e < npart; e += blockDim.x) s += part[e * 4 + k];
+    const double r = block_reduce<false>(s, red);
+    if (threadIdx.x == 0) out[k] = r;
+    __syncthreads();
+  }
 }
 __global__ __launch_bounds__(1024) void k_s_final(const double* __restrict__ part, int npart, double scale,
                                                  double* __restrict__ S3) {
@@ -371,13 +447,20 @@ __global__ __launch_bounds__(256) void k_diag(GridParams g, Fields<T> f, IbmList
     const double phn = hasN ? fval(f.phi, c + plane) : 0.0, phs = hasS ? fval(f.phi, c - plane) : 0.0;
     const double vs = fval(f.vs, c), vn = hasN ? fval(f.vs, c + plane) : 0.0;
     const double wb = fval(f.ws, c), wt = fval(f.ws, c + (kp - k) * nx);
-    // gradients of phi on the faces (no flux through the box walls)
+    // gradients of phi on the faces (no flux through the box walls); a stretched grid
+    // takes the spacings of face j, face j+1 and cell j
+    double iys = g.idy, iyn = g.idy, iyc = g.idy;
+    if (g.stretched) {
+      iys = g.ytab[YT_IDYF * g.ystr + j];
+      iyn = g.ytab[YT_IDYF * g.ystr + j + 1];
+      iyc = g.ytab[YT_IDYC * g.ystr + j];
+    }
     const double gxw = (ph - phw) * g.idx, gxe = (phe - ph) * g.idx;
-    const double gys = hasS ? (ph - phs) * g.idy : 0.0, gyn = hasN ? (phn - ph) * g.idy : 0.0;
+    const double gys = hasS ? (ph - phs) * iys : 0.0, gyn = hasN ? (phn - ph) * iyn : 0.0;
     const double gzb = (ph - phb) * g.idz, gzt = (pht - ph) * g.idz;
-    const double divs = (ue - uw) * g.idx + (vn - vs) * g.idy + (wt - wb) * g.idz;
+    const double divs = (ue - uw) * g.idx + (vn - vs) * iyc + (wt - wb) * g.idz;
     const double rhs = divs / ck_dt;
-    const double dg = (gxe - gxw) * g.idx + (gyn - gys) * g.idy + (gzt - gzb) * g.idz;
+    const double dg = (gxe - gxw) * g.idx + (gyn - gys) * iyc + (gzt - gzb) * g.idz;
     dmax = fabs(divs - ck_dt * dg);
     rmax = fabs(dg - (rhs - mean[0]));
     hmax = fabs(rhs);
@@ -410,15 +493,19 @@ __global__ __launch_bounds__(256) void k_stats(GridParams g, Fields<T> f, double
     const int c = (j * nz + k) * nx + i;
     const uint8_t t = f.tag[c];
     const double u = fval(f.u, c), v = fval(f.v, c), w = fval(f.w, c), p = fval(f.p, c);
-    if (t & TAG_U) qs = u;
+    // a stretched grid weights the sums by the cell height and takes it as the spacing
+    const double iyc = g.stretched ? g.ytab[YT_IDYC * g.ystr + j] : g.idy;
+    const double wy = g.stretched ? g.ytab[YT_DYC * g.ystr + j] : 1.0;
+    if (t & TAG_U) qs = g.stretched ? u * wy : u;
     ke = u * u + v * v + w * w;
+    if (g.stretched) ke *= wy;
     nan = (isfinite(u) && isfinite(v) && isfinite(w) && isfinite(p)) ? 0.0 : 1.0;
-    cfl = (fabs(u) * g.idx + fabs(v) * g.idy + fabs(w) * g.idz) * g.dt;
+    cfl = (fabs(u) * g.idx + fabs(v) * iyc + fabs(w) * g.idz) * g.dt;
     if (t & TAG_P) {
       const double ue = fval(f.u, c - i + ip);
       const double vn = (j + 1 < g.ny1) ? fval(f.v, c + plane) : 0.0;
       const double wt = fval(f.w, c + (kp - k) * nx);
-      leak = fabs((ue - u) * g.idx + (vn - v) * g.idy + (wt - w) * g.idz);
+      leak = fabs((ue - u) * g.idx + (vn - v) * iyc + (wt - w) * g.idz);
     }
   }
   const double a = block_reduce<false>(qs, red);
@@ -520,19 +607,6 @@ __global__ __launch_bounds__(256) void k_tau_modes(const double* __restrict__ ta
   }
 }
 
-// out[k] = sum over the IBM u points of sig / A_k (fixed order): the flow rate a moving
-// wall adds to the predictor at stage k, per unit c_k dt U_b.
-__global__ __launch_bounds__(256) void k_wall_sd(IbmLists L, double* __restrict__ out) {
-  __shared__ double red[4];
-  for (int k = 0; k < 3; ++k) {
-    double s = 0.0;
-    for (int e = threadIdx.x; e < L.n_u; e += blockDim.x) s += L.sig[e] * L.coef[(size_t)k * L.n_total + e].y;
-    const double r = block_reduce<false>(s, red);
-    if (threadIdx.x == 0) out[k] = r;
-    __syncthreads();
-  }
-}
-
 }  // namespace
 
 static inline dim3 cell_grid(const GridParams& g) {
@@ -549,11 +623,6 @@ hipError_t launch_geom_lambda(const GridParams& g, const double* su, const doubl
 
 hipError_t launch_geom_ptag(const GridParams& g, uint8_t* tag, hipStream_t st) {
   hipLaunchKernelGGL(k_geom_ptag, cell_grid(g), dim3(BX, BZ), 0, st, g, tag);
-  return hipGetLastError();
-}
-
-hipError_t launch_wall_sd(const IbmLists& L, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_wall_sd, dim3(1), dim3(256), 0, st, L, out);
   return hipGetLastError();
 }
 
@@ -611,12 +680,14 @@ hipError_t launch_ibm_coef(const int32_t* idx, const double* lam_dense, const do
 }
 
 hipError_t launch_s_k(const GridParams& g, const uint8_t* tag, const IbmLists& L, double dt, double* part,
-                      int* npart, hipStream_t st) {
+                      int* npart, double* sd_out, hipStream_t st) {
   (void)dt;
   const int nb1 = (int)((g.ncell + 255) / 256);
   const int nb2 = (L.n_u + 255) / 256;
+  double* part_sd = part + (size_t)(nb1 + nb2) * 4;
   hipLaunchKernelGGL(k_s_cells, dim3(nb1), dim3(256), 0, st, g, tag, part);
-  if (nb2 > 0) hipLaunchKernelGGL(k_s_list, dim3(nb2), dim3(256), 0, st, L, part + (size_t)nb1 * 4);
+  if (nb2 > 0) hipLaunchKernelGGL(k_s_list, dim3(nb2), dim3(256), 0, st, g, L, part + (size_t)nb1 * 4, part_sd);
+  hipLaunchKernelGGL(k_sd_final, dim3(1), dim3(1024), 0, st, part_sd, nb2, sd_out);
   *npart = nb1 + nb2;
   return hipGetLastError();
 }

@@ -78,7 +78,7 @@ struct TileRaw {
 // concurrent HBM accesses close together).
 constexpr int NXCD = 8;
 
-template <typename T>
+template <typename T, bool SY>
 __device__ __forceinline__ void k_momentum_body(GridParams g, Fields<T> f, IbmLists L, StageConsts s, int jc,
                                                  int ntx, int ntz, int xcd_order, const double* __restrict__ pi_prev,
                                                  double ckdt_prev, double* __restrict__ qpart, int bid_x, int bid_y, int nblk) {
@@ -148,12 +148,12 @@ __device__ __forceinline__ void k_momentum_body(GridParams g, Fields<T> f, IbmLi
   // corrected state of one fetched value (tag tg, its phi and west/back/south phi); an
   // external point inside the box holds the immersed walls' velocity (the south box-wall
   // face of v and everything beyond the box walls hold zero)
-  auto corr = [&](int fld, uint8_t tg, T val, T ph, T phx, T phz, T phy, int kind) -> T {
+  auto corr = [&](int fld, uint8_t tg, T val, T ph, T phx, T phz, T phy, int kind, T iyf) -> T {
     if (fld == 0) {
       const T pk = ((tg & (TAG_U | TAG_UI)) == TAG_U) ? pick : T(0);
       return (tg & TAG_U) ? val - pk - ckp * ((ph - phx) * idx) : (kind == 1 ? T(0) : ubw);
     }
-    if (fld == 1) return (tg & TAG_V) ? val - ckp * ((ph - phy) * idy) : (kind == 0 ? vbw : T(0));
+    if (fld == 1) return (tg & TAG_V) ? val - ckp * ((ph - phy) * iyf) : (kind == 0 ? vbw : T(0));
     if (fld == 2) return (tg & TAG_W) ? val - ckp * ((ph - phz) * idz) : (kind == 1 ? T(0) : wbw);
     return (tg & TAG_P) ? val + ph : T(0);
   };
@@ -166,14 +166,16 @@ __device__ __forceinline__ void k_momentum_body(GridParams g, Fields<T> f, IbmLi
       const Pair<T> phy = with_phy ? a.phy : phprev;   // a plane outside the box has tag 0
       const uint8_t t0 = uint8_t(a.tg & 0xff), t1 = uint8_t(a.tg >> 8);
       const int kd = (jj < 0 || jj >= ny1) ? 1 : (jj == 0 ? 2 : 0);
-      const Pair<T> cu = {corr(0, t0, a.us.x, a.ph.x, a.phw.y, a.phz.x, phy.x, kd),
-                          corr(0, t1, a.us.y, a.ph.y, a.ph.x, a.phz.y, phy.y, kd)};
-      const Pair<T> cv = {corr(1, t0, a.vs.x, a.ph.x, a.phw.y, a.phz.x, phy.x, kd),
-                          corr(1, t1, a.vs.y, a.ph.y, a.ph.x, a.phz.y, phy.y, kd)};
-      const Pair<T> cw = {corr(2, t0, a.ws.x, a.ph.x, a.phw.y, a.phz.x, phy.x, kd),
-                          corr(2, t1, a.ws.y, a.ph.y, a.ph.x, a.phz.y, phy.y, kd)};
-      const Pair<T> cp = {corr(3, t0, a.pp.x, a.ph.x, a.phw.y, a.phz.x, phy.x, kd),
-                          corr(3, t1, a.pp.y, a.ph.y, a.ph.x, a.phz.y, phy.y, kd)};
+      T iyf = idy;
+      if constexpr (SY) iyf = T(g.ytab[YT_IDYF * g.ystr + min(max(jj, 0), ny1 - 1)]);
+      const Pair<T> cu = {corr(0, t0, a.us.x, a.ph.x, a.phw.y, a.phz.x, phy.x, kd, iyf),
+                          corr(0, t1, a.us.y, a.ph.y, a.ph.x, a.phz.y, phy.y, kd, iyf)};
+      const Pair<T> cv = {corr(1, t0, a.vs.x, a.ph.x, a.phw.y, a.phz.x, phy.x, kd, iyf),
+                          corr(1, t1, a.vs.y, a.ph.y, a.ph.x, a.phz.y, phy.y, kd, iyf)};
+      const Pair<T> cw = {corr(2, t0, a.ws.x, a.ph.x, a.phw.y, a.phz.x, phy.x, kd, iyf),
+                          corr(2, t1, a.ws.y, a.ph.y, a.ph.x, a.phz.y, phy.y, kd, iyf)};
+      const Pair<T> cp = {corr(3, t0, a.pp.x, a.ph.x, a.phw.y, a.phz.x, phy.x, kd, iyf),
+                          corr(3, t1, a.pp.y, a.ph.y, a.ph.x, a.phz.y, phy.y, kd, iyf)};
       *reinterpret_cast<Pair<T>*>(&ring[0][sl][e]) = cu;
       *reinterpret_cast<Pair<T>*>(&ring[1][sl][e]) = cv;
       *reinterpret_cast<Pair<T>*>(&ring[2][sl][e]) = cw;
@@ -267,42 +269,85 @@ __device__ __forceinline__ void k_momentum_body(GridParams g, Fields<T> f, IbmLi
     const T wn = Wp[cc], wsb = Wm[cc], w_kp_im = W0[cc + MHX - 1], w_kp_s = Wm[cc + MHX];
     const T pc = P0[cc], pw = P0[cc - 1], pb = P0[cc - MHX], ps = Pm[cc];
 
-
-    // u-momentum at (i dx, y_c[j], z_c[k])
-    T Hu, ru;
-    {
-      const T a1 = h * (uc + ue), a0 = h * (uw + uc);
-      const T N = (a1 * a1 - a0 * a0) * idx +
-                  (h * (uc + un) * h * (v_im_n + vn) - h * (usb + uc) * h * (vw + vc)) * idy +
-                  (h * (uc + ut) * h * (w_kp_im + wt) - h * (ub + uc) * h * (ww + wc)) * idz;
-      const T L = (ue - two * uc + uw) * idx2 + (un - two * uc + usb) * idy2 + (ut - two * uc + ub) * idz2;
-      Hu = -N + nu * L;
-      ru = akdt * Hu - ckdt * ((pc - pw) * idx);
-      if (s.use_hold) ru += bkdt * hu;
-    }
-    // v-momentum at (x_c[i], y_f[j], z_c[k]); only stored where v is internal (j >= 1)
-    T Hv, rv;
-    {
-      const T b1 = h * (vc + vn), b0 = h * (vs0 + vc);
-      const T N = (h * (vc + ve) * h * (u_ip_s + ue) - h * (vw + vc) * h * (usb + uc)) * idx +
-                  (b1 * b1 - b0 * b0) * idy +
-                  (h * (vc + vt) * h * (w_kp_s + wt) - h * (vb + vc) * h * (wsb + wc)) * idz;
-      const T L = (ve - two * vc + vw) * idx2 + (vn - two * vc + vs0) * idy2 + (vt - two * vc + vb) * idz2;
-      Hv = -N + nu * L;
-      rv = akdt * Hv - ckdt * ((pc - ps) * idy);
-      if (s.use_hold) rv += bkdt * hv;
-    }
-    // w-momentum at (x_c[i], y_c[j], k dz)
-    T Hw, rw;
-    {
-      const T c1 = h * (wc + wt), c0 = h * (wb + wc);
-      const T N = (h * (wc + we) * h * (u_ip_km + ue) - h * (ww + wc) * h * (ub + uc)) * idx +
-                  (h * (wc + wn) * h * (v_km_n + vn) - h * (wsb + wc) * h * (vb + vc)) * idy +
-                  (c1 * c1 - c0 * c0) * idz;
-      const T L = (we - two * wc + ww) * idx2 + (wn - two * wc + wsb) * idy2 + (wt - two * wc + wb) * idz2;
-      Hw = -N + nu * L;
-      rw = akdt * Hw - ckdt * ((pc - pb) * idz);
-      if (s.use_hold) rw += bkdt * hw;
+    T Hu, ru, Hv, rv, Hw, rw;
+    if constexpr (!SY) {
+      // u-momentum at (i dx, y_c[j], z_c[k])
+      {
+        const T a1 = h * (uc + ue), a0 = h * (uw + uc);
+        const T N = (a1 * a1 - a0 * a0) * idx +
+                    (h * (uc + un) * h * (v_im_n + vn) - h * (usb + uc) * h * (vw + vc)) * idy +
+                    (h * (uc + ut) * h * (w_kp_im + wt) - h * (ub + uc) * h * (ww + wc)) * idz;
+        const T L = (ue - two * uc + uw) * idx2 + (un - two * uc + usb) * idy2 + (ut - two * uc + ub) * idz2;
+        Hu = -N + nu * L;
+        ru = akdt * Hu - ckdt * ((pc - pw) * idx);
+        if (s.use_hold) ru += bkdt * hu;
+      }
+      // v-momentum at (x_c[i], y_f[j], z_c[k]); only stored where v is internal (j >= 1)
+      {
+        const T b1 = h * (vc + vn), b0 = h * (vs0 + vc);
+        const T N = (h * (vc + ve) * h * (u_ip_s + ue) - h * (vw + vc) * h * (usb + uc)) * idx +
+                    (b1 * b1 - b0 * b0) * idy +
+                    (h * (vc + vt) * h * (w_kp_s + wt) - h * (vb + vc) * h * (wsb + wc)) * idz;
+        const T L = (ve - two * vc + vw) * idx2 + (vn - two * vc + vs0) * idy2 + (vt - two * vc + vb) * idz2;
+        Hv = -N + nu * L;
+        rv = akdt * Hv - ckdt * ((pc - ps) * idy);
+        if (s.use_hold) rv += bkdt * hv;
+      }
+      // w-momentum at (x_c[i], y_c[j], k dz)
+      {
+        const T c1 = h * (wc + wt), c0 = h * (wb + wc);
+        const T N = (h * (wc + we) * h * (u_ip_km + ue) - h * (ww + wc) * h * (ub + uc)) * idx +
+                    (h * (wc + wn) * h * (v_km_n + vn) - h * (wsb + wc) * h * (vb + vc)) * idy +
+                    (c1 * c1 - c0 * c0) * idz;
+        const T L = (we - two * wc + ww) * idx2 + (wn - two * wc + wsb) * idy2 + (wt - two * wc + wb) * idz2;
+        Hw = -N + nu * L;
+        rw = akdt * Hw - ckdt * ((pc - pb) * idz);
+        if (s.use_hold) rw += bkdt * hw;
+      }
+    } else {
+      // stretched wall-normal grid: per-row spacings (uniform over the block's plane),
+      // three-point second derivatives with the row's own weights, u and w carried to the
+      // faces by linear interpolation
+      const double* yt = g.ytab;
+      const int ys = g.ystr;
+      const T iyc = T(yt[YT_IDYC * ys + j]), iyf = T(yt[YT_IDYF * ys + j]);
+      const T dcm = T(yt[YT_DCM * ys + j]), dcp = T(yt[YT_DCP * ys + j]);
+      const T dfm = T(yt[YT_DFM * ys + j]), dfp = T(yt[YT_DFP * ys + j]);
+      const T wl0 = T(yt[YT_WLO * ys + j]), wh0 = T(yt[YT_WHI * ys + j]);
+      const T wl1 = T(yt[YT_WLO * ys + j + 1]), wh1 = T(yt[YT_WHI * ys + j + 1]);
+      {
+        const T a1 = h * (uc + ue), a0 = h * (uw + uc);
+        const T N = (a1 * a1 - a0 * a0) * idx +
+                    ((wl1 * uc + wh1 * un) * h * (v_im_n + vn) - (wl0 * usb + wh0 * uc) * h * (vw + vc)) * iyc +
+                    (h * (uc + ut) * h * (w_kp_im + wt) - h * (ub + uc) * h * (ww + wc)) * idz;
+        const T L = (ue - two * uc + uw) * idx2 + (dcm * usb + dcp * un - (dcm + dcp) * uc) +
+                    (ut - two * uc + ub) * idz2;
+        Hu = -N + nu * L;
+        ru = akdt * Hu - ckdt * ((pc - pw) * idx);
+        if (s.use_hold) ru += bkdt * hu;
+      }
+      {
+        const T b1 = h * (vc + vn), b0 = h * (vs0 + vc);
+        const T N = (h * (vc + ve) * (wl0 * u_ip_s + wh0 * ue) - h * (vw + vc) * (wl0 * usb + wh0 * uc)) * idx +
+                    (b1 * b1 - b0 * b0) * iyf +
+                    (h * (vc + vt) * (wl0 * w_kp_s + wh0 * wt) - h * (vb + vc) * (wl0 * wsb + wh0 * wc)) * idz;
+        const T L = (ve - two * vc + vw) * idx2 + (dfm * vs0 + dfp * vn - (dfm + dfp) * vc) +
+                    (vt - two * vc + vb) * idz2;
+        Hv = -N + nu * L;
+        rv = akdt * Hv - ckdt * ((pc - ps) * iyf);
+        if (s.use_hold) rv += bkdt * hv;
+      }
+      {
+        const T c1 = h * (wc + wt), c0 = h * (wb + wc);
+        const T N = (h * (wc + we) * h * (u_ip_km + ue) - h * (ww + wc) * h * (ub + uc)) * idx +
+                    ((wl1 * wc + wh1 * wn) * h * (v_km_n + vn) - (wl0 * wsb + wh0 * wc) * h * (vb + vc)) * iyc +
+                    (c1 * c1 - c0 * c0) * idz;
+        const T L = (we - two * wc + ww) * idx2 + (dcm * wsb + dcp * wn - (dcm + dcp) * wc) +
+                    (wt - two * wc + wb) * idz2;
+        Hw = -N + nu * L;
+        rw = akdt * Hw - ckdt * ((pc - pb) * idz);
+        if (s.use_hold) rw += bkdt * hw;
+      }
     }
     if (act) {
       if (s.write_h) {
@@ -324,7 +369,13 @@ __device__ __forceinline__ void k_momentum_body(GridParams g, Fields<T> f, IbmLi
       f.vs[c] = sv;
       f.ws[c] = sw;
       f.pn[c] = pc;
-      if (tg & TAG_U) qloc += (double)su;
+      if constexpr (SY) {
+        // (a uniform grid in a batched launch with stretched ones: unweighted, like its
+        // flow-rate scale factor)
+        if (tg & TAG_U) qloc += g.stretched ? (double)su * g.ytab[YT_DYC * g.ystr + j] : (double)su;
+      } else {
+        if (tg & TAG_U) qloc += (double)su;
+      }
     }
     put(slot(j + 2), j + 2, nq, false);
     __syncthreads();
@@ -333,21 +384,21 @@ __device__ __forceinline__ void k_momentum_body(GridParams g, Fields<T> f, IbmLi
   if (tid == 0) qpart[bid_x] = tot;
 }
 
-template <typename T>
+template <typename T, bool SY>
 __global__ __launch_bounds__(256) void k_momentum(GridParams g, Fields<T> f, IbmLists L, StageConsts s, int jc,
                                                  int ntx, int ntz, int xcd_order, const double* __restrict__ pi_prev,
                                                  double ckdt_prev, double* __restrict__ qpart) {
-  k_momentum_body<T>(g, f, L, s, jc, ntx, ntz, xcd_order, pi_prev, ckdt_prev, qpart, blockIdx.x, blockIdx.y, gridDim.x);
+  k_momentum_body<T, SY>(g, f, L, s, jc, ntx, ntz, xcd_order, pi_prev, ckdt_prev, qpart, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
 // The same for a batch of independent grids in one launch (block ranges boff).
-template <typename T>
+template <typename T, bool SY>
 __global__ __launch_bounds__(256) void k_momentum_b(const MomArgs<T>* __restrict__ args,
     const int* __restrict__ boff, int ninst) {
   const int i = batch_instance(boff, ninst, blockIdx.x);
   const MomArgs<T>& a = args[i];
   const int local = blockIdx.x - boff[i];
-  k_momentum_body<T>(a.g, a.f, a.L, a.s, a.jc, a.ntx, a.ntz, a.xcd_order, a.pi_prev, a.ckdt_prev, a.qpart, local % a.gx, local / a.gx, boff[i + 1] - boff[i]);
+  k_momentum_body<T, SY>(a.g, a.f, a.L, a.s, a.jc, a.ntx, a.ntz, a.xcd_order, a.pi_prev, a.ckdt_prev, a.qpart, local % a.gx, local / a.gx, boff[i + 1] - boff[i]);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -460,7 +511,8 @@ __device__ __forceinline__ void k_div_fftx_body(GridParams g, Fields<T> f, IbmLi
       const int kp = wrap_p(k, g.nz);
       const T pick = T(pi[0] * ck_dt);
       const T inv = T(1.0 / ck_dt);
-      const T idx = T(g.idx), idy = T(g.idy), idz = T(g.idz);
+      const T idx = T(g.idx), idz = T(g.idz);
+      const T idy = T(g.stretched ? g.ytab[YT_IDYC * g.ystr + j] : g.idy);
       const bool hasN = (j + 1 < g.ny1);
       const int plane = nx * g.nz;
       // u* on a u face: internal non-IBM faces still owe -Pi c_k dt (= pick)
@@ -698,22 +750,31 @@ __device__ __forceinline__ void k_tri_body(GridParams g, cplx<T>* __restrict__ s
       di[t] = (double)v.y;
     }
   }
-  // mean of the (0,0) mode over j (only block 0 holds it, at w = 0)
+  // mean of the (0,0) mode over j (only block 0 holds it, at w = 0); on a stretched grid
+  // weighted by the cell heights (entry ny1 of their table holds the box height)
+  const bool sy = g.stretched != 0;
+  const double* yt = g.ytab;
+  const int ys = g.ystr;
   double mr = 0.0, mi = 0.0;
   if (bid_x == 0) {
     if (w == 0 && active) {
       double sr = 0.0, si = 0.0;
 #pragma unroll
       for (int t = 0; t < LM; ++t)
-        if (t < L) { sr += dr[t]; si += di[t]; }
+        if (t < L) {
+          const double wt = sy ? yt[YT_DYC * ys + r0 + t] : 1.0;
+          sr += sy ? dr[t] * wt : dr[t];
+          si += sy ? di[t] * wt : di[t];
+        }
       red[p] = sr;
       red[P + p] = si;
     }
     __syncthreads();
     if (w == 0) {
       for (int pp = 0; pp < P; ++pp) { mr += red[pp]; mi += red[P + pp]; }
-      mr /= n;
-      mi /= n;
+      const double den = sy ? yt[YT_DYC * ys + n] : (double)n;
+      mr /= den;
+      mi /= den;
       if (tid == 0) mean_out[0] = mr * norm;
     }
     __syncthreads();
@@ -725,6 +786,14 @@ __device__ __forceinline__ void k_tri_body(GridParams g, cplx<T>* __restrict__ s
   // segment's row 0 and the last row only its row L-1.
   const bool first = r0 == 0, last = r1 == n;
   const double dI = -2.0 * a - K2, dLast = dI + a;
+  // coefficients of segment row t: lower, upper and (t >= 1) diagonal; a stretched grid
+  // takes its per-row values (the box's last row has no upper coefficient)
+  auto lo_ = [&](int t) -> double { return sy ? yt[YT_TLO * ys + r0 + t] : a; };
+  auto hi_ = [&](int t) -> double { return sy ? yt[YT_THI * ys + r0 + t] : a; };
+  auto dg_ = [&](int t, bool boxlast) -> double {
+    if (sy) return boxlast ? -lo_(t) - K2 : -(lo_(t) + hi_(t)) - K2;
+    return boxlast ? dLast : dI;
+  };
 #pragma unroll
   for (int t = 0; t < LM; ++t) {
     dr[t] = (dr[t] - mr) * norm;
@@ -737,14 +806,14 @@ __device__ __forceinline__ void k_tri_body(GridParams g, cplx<T>* __restrict__ s
 #pragma unroll
   for (int t = 0; t < LM; ++t) { al[t] = 0.0; ib[t] = 1.0; ga[t] = 0.0; }
   if (valid) {
-    al[1] = a;
-    ib[1] = recip((last && L == 2) ? dLast : dI);
+    al[1] = lo_(1);
+    ib[1] = recip(dg_(1, last && L == 2));
 #pragma unroll
     for (int t = 2; t < LM; ++t) {
       if (t < L) {
-        const double m = a * ib[t - 1];
+        const double m = lo_(t) * ib[t - 1];
         al[t] = -m * al[t - 1];
-        ib[t] = recip(((last && t == L - 1) ? dLast : dI) - m * a);
+        ib[t] = recip(dg_(t, last && t == L - 1) - m * hi_(t - 1));
         dr[t] -= m * dr[t - 1];
         di[t] -= m * di[t - 1];
       }
@@ -753,11 +822,11 @@ __device__ __forceinline__ void k_tri_body(GridParams g, cplx<T>* __restrict__ s
     if (L >= 3) {
 #pragma unroll
       for (int t = 1; t < LM; ++t)
-        if (t == L - 2) ga[t] = a;
+        if (t == L - 2) ga[t] = hi_(t);
 #pragma unroll
       for (int t = LM - 3; t >= 1; --t) {
         if (t <= L - 3) {
-          const double m = a * ib[t + 1];
+          const double m = hi_(t) * ib[t + 1];
           al[t] -= m * al[t + 1];
           ga[t] = -m * ga[t + 1];
           dr[t] -= m * dr[t + 1];
@@ -768,16 +837,17 @@ __device__ __forceinline__ void k_tri_body(GridParams g, cplx<T>* __restrict__ s
     // reduced equations of F = x_0 and E = x_{L-1} (segments hold L >= 2 rows), each
     // divided by its diagonal
     const int eF = (2 * p) * RS + w, eE = eF + RS;
-    double dL = dr[0], dLi = di[0], alL = 0.0, ibL = 1.0;
+    double dL = dr[0], dLi = di[0], alL = 0.0, ibL = 1.0, hiL = a;
 #pragma unroll
     for (int t = 1; t < LM; ++t)
-      if (t == L - 1) { dL = dr[t]; dLi = di[t]; alL = al[t]; ibL = ib[t]; }
+      if (t == L - 1) { dL = dr[t]; dLi = di[t]; alL = al[t]; ibL = ib[t]; hiL = hi_(t); }
     Rl[eE] = alL * ibL;
-    Ru[eE] = last ? 0.0 : a * ibL;
+    Ru[eE] = last ? 0.0 : hiL * ibL;
     Rr[eE] = dL * ibL;
     Ri[eE] = dLi * ibL;
     const bool pin = zmode && first;   // phi_0 = 0 of the (0,0) mode
-    double dF = pin ? 1.0 : (first ? dI + a : dI), uF = pin ? 0.0 : a, rF = dr[0], iF = di[0];
+    double dF = pin ? 1.0 : (sy ? (first ? -hi_(0) - K2 : -(lo_(0) + hi_(0)) - K2) : (first ? dI + a : dI));
+    double uF = pin ? 0.0 : hi_(0), rF = dr[0], iF = di[0];
     if (L >= 3) {
       const double m = uF * ib[1];
       dF -= m * al[1];
@@ -786,7 +856,7 @@ __device__ __forceinline__ void k_tri_body(GridParams g, cplx<T>* __restrict__ s
       iF -= m * di[1];
     }
     const double idF = recip(dF);
-    Rl[eF] = first ? 0.0 : a * idF;
+    Rl[eF] = first ? 0.0 : lo_(0) * idF;
     Ru[eF] = uF * idF;
     Rr[eF] = rF * idF;
     Ri[eF] = iF * idF;
@@ -979,7 +1049,7 @@ __global__ __launch_bounds__(256) void k_correct(GridParams g, Fields<T> f, IbmL
   const T ckdt = T(ck_dt);
   const T pick = ((tg & (TAG_U | TAG_UI)) == TAG_U) ? T(pi[0] * ck_dt) : T(0);
   const T un = usv - pick - ckdt * ((ph - phw) * T(g.idx));
-  const T vn = vsv - ckdt * ((ph - phs) * T(g.idy));
+  const T vn = vsv - ckdt * ((ph - phs) * T(g.stretched ? g.ytab[YT_IDYF * g.ystr + j] : g.idy));
   const T wn = wsv - ckdt * ((ph - phb) * T(g.idz));
   // external points hold the immersed walls' velocity (v on the south box wall: 0)
   f.u[c] = (tg & TAG_U) ? un : T(L.wallv[0]);
@@ -1021,8 +1091,12 @@ hipError_t launch_momentum(const GridParams& g, const Fields<T>& f, const IbmLis
   const int ntx = (g.nx + MX - 1) / MX, ntz = (g.nz + MZ - 1) / MZ, nty = (g.ny1 + jc - 1) / jc;
   const int nb = ntx * ntz * nty;
   const int xo = tu.tile_order == 2 ? 0 : 1;
-  hipLaunchKernelGGL(k_momentum<T>, dim3(nb), dim3(MX, MZ), 0, st, g, f, L, s, jc, ntx, ntz, xo, pi_prev,
-                     ckdt_prev, qpart);
+  if (g.stretched)
+    hipLaunchKernelGGL((k_momentum<T, true>), dim3(nb), dim3(MX, MZ), 0, st, g, f, L, s, jc, ntx, ntz, xo, pi_prev,
+                       ckdt_prev, qpart);
+  else
+    hipLaunchKernelGGL((k_momentum<T, false>), dim3(nb), dim3(MX, MZ), 0, st, g, f, L, s, jc, ntx, ntz, xo, pi_prev,
+                       ckdt_prev, qpart);
   *nqpart = nb;
   return hipGetLastError();
 }
@@ -1292,8 +1366,12 @@ static hipError_t allow_lds(const void* kfn, size_t lds) {
 }
 
 template <typename T>
-hipError_t launch_momentum_b(const MomArgs<T>* args, const int* boff, int ninst, int ntot, hipStream_t st) {
-  hipLaunchKernelGGL(k_momentum_b<T>, dim3(ntot), dim3(MX, MZ), 0, st, args, boff, ninst);
+hipError_t launch_momentum_b(const MomArgs<T>* args, const int* boff, int ninst, int ntot, bool stretched,
+                             hipStream_t st) {
+  if (stretched)
+    hipLaunchKernelGGL((k_momentum_b<T, true>), dim3(ntot), dim3(MX, MZ), 0, st, args, boff, ninst);
+  else
+    hipLaunchKernelGGL((k_momentum_b<T, false>), dim3(ntot), dim3(MX, MZ), 0, st, args, boff, ninst);
   return hipGetLastError();
 }
 
@@ -1363,7 +1441,7 @@ hipError_t launch_ifftx_b(const IfftxArgs<T>* args, const int* boff, int ninst, 
                            TriArgs<T>*, int*, size_t*);                                                         \
   template int plan_ifftx<T>(const GridParams&, const cplx<T>*, T*, const FFTPlan&, const double2*,             \
                              IfftxArgs<T>*, int*, size_t*);                                                     \
-  template hipError_t launch_momentum_b<T>(const MomArgs<T>*, const int*, int, int, hipStream_t);               \
+  template hipError_t launch_momentum_b<T>(const MomArgs<T>*, const int*, int, int, bool, hipStream_t);               \
   template hipError_t launch_cfr_pi_b<T>(const CfrArgs<T>*, const int*, int, int, hipStream_t);                 \
   template hipError_t launch_div_fftx_b<T>(const DivArgs<T>*, const int*, int, int, int, size_t, hipStream_t);  \
   template hipError_t launch_fftz_b<T>(const FftzArgs<T>*, const int*, int, int, int, size_t, int,              \

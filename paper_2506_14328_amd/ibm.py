@@ -29,7 +29,7 @@ EXPORTED = [
     "ibm_solve_pressure", "ibm_stats", "ibm_set_diagnostics", "ibm_get_geometry", "ibm_get_ibm_list",
     "ibm_profile", "ibm_profile_read", "ibm_kernel_name", "ibm_num_kernels", "ibm_device_bytes",
     "ibm_destroy", "ibm_last_error", "ibm_tune_set", "ibm_tune_get", "ibm_autotune", "ibm_wall_shear",
-    "ibm_set_wall_velocity",
+    "ibm_set_wall_velocity", "ibm_set_y_faces",
 ]
 TUNE_PARAMS = {"momentum_planes": 0, "fftz_width": 1, "tri_rows": 2, "graph": 3, "graph_branches": 4,
                "tile_order": 5, "batch": 6}
@@ -80,6 +80,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "ibm_stats": (c_int32, [h, c_int32, POINTER(IbmStats)]),
         "ibm_wall_shear": (c_int32, [h, c_int32, c_void_p, POINTER(c_double)]),
         "ibm_set_wall_velocity": (c_int32, [h, c_int32, c_double, c_double, c_double]),
+        "ibm_set_y_faces": (c_int32, [h, c_int32, c_void_p]),
         "ibm_set_diagnostics": (c_int32, [h, c_int32]),
         "ibm_get_geometry": (c_int32, [h, c_int32, c_void_p, POINTER(c_int64)]),
         "ibm_get_ibm_list": (c_int32, [h, c_int32, c_int32, c_void_p, c_void_p, c_void_p]),
@@ -143,12 +144,19 @@ class IbmGrid:
 
     @classmethod
     def from_case(cls, c, precision: str = "fp64", ibm: bool = True, **kw) -> "IbmGrid":
-        return cls(0, 0, 0, 0, 0, 0, 0, 0, 0, precision=precision, _descs=[_desc(c, ibm)], **kw)
+        g = cls(0, 0, 0, 0, 0, 0, 0, 0, 0, precision=precision, _descs=[_desc(c, ibm)], **kw)
+        if getattr(c, "y_faces", None) is not None:
+            g.set_y_faces(c.y_faces)
+        return g
 
     @classmethod
     def ensemble(cls, cases, precision: str = "fp32", ibm: bool = True, **kw) -> "IbmGrid":
         """Independent instances of ragged sizes advanced together by step()."""
-        return cls(0, 0, 0, 0, 0, 0, 0, 0, 0, precision=precision, _descs=[_desc(c, ibm) for c in cases], **kw)
+        g = cls(0, 0, 0, 0, 0, 0, 0, 0, 0, precision=precision, _descs=[_desc(c, ibm) for c in cases], **kw)
+        for i, c in enumerate(cases):
+            if getattr(c, "y_faces", None) is not None:
+                g.set_y_faces(c.y_faces, inst=i)
+        return g
 
     def shape_of(self, inst: int = 0):
         nx, ny, nz = self.dims[inst]
@@ -215,6 +223,15 @@ class IbmGrid:
         d["n_ibm"] = list(s.n_ibm)
         d["unstable"] = rc == IBM_ERR_UNSTABLE
         return d
+
+    def set_y_faces(self, y_faces, inst: int = 0):
+        """Stretched wall-normal grid: the ny face positions, increasing from y_lo to y_hi
+        (ibm_set_y_faces; a geometry must be given afterwards)."""
+        import numpy as np
+        a = np.ascontiguousarray(np.asarray(y_faces, dtype=np.float64))
+        if a.shape != (self.dims[inst][1],):
+            raise ValueError(f"y_faces must hold {self.dims[inst][1]} values, got shape {a.shape}")
+        self._check(self.lib.ibm_set_y_faces(self._h, inst, c_void_p(a.ctypes.data)))
 
     def set_wall_velocity(self, ub: float, vb: float = 0.0, wb: float = 0.0, inst: int = 0):
         """Velocity of the immersed walls (rigid translation; ibm_set_wall_velocity)."""

@@ -1,0 +1,155 @@
+"""Stretched wall-normal grids (ibm_set_y_faces) through the C ABI against the oracle on
+the same tanh-clustered faces: geometry (tags, lists, lambda, B, 1/A), the stand-alone
+pressure solve, full steps in FP64 and FP32 storage, a batched graph ensemble mixing a
+stretched and a uniform instance, the wall shear, and the argument checks."""
+import numpy as np
+import pytest
+import torch
+
+import ibm_inputs as I
+from oracle.ibm_oracle import OGrid, solve_pressure, wall_shear_profile
+from tests.gpu_helpers import case, device, gpu_grid, oracle_run, rel_err, to_dev
+from paper_2506_14328_amd.ibm import IbmError
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _need_gpu():
+    device()
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def stretched(name, gamma=1.2, **kw):
+    c = case(name, **kw)
+    import dataclasses
+    return dataclasses.replace(c, y_faces=I.tanh_faces(c.ny, c.y_lo, c.y_hi, gamma))
+
+
+@pytest.mark.parametrize("name", ["wavy_small", "flat_small", "open_small", "ellip_small"])
+def test_geometry_parity_stretched(name):
+    c = stretched(name)
+    o, sdf, st = oracle_run(c, 0)
+    g = gpu_grid(c, sdf, st)
+    for comp, cn in enumerate("uvw"):
+        idx, lam, coef = g.ibm_list(comp)
+        ref_idx = np.flatnonzero(o.lam[cn].ravel() > 0)
+        assert np.array_equal(idx.cpu().numpy(), ref_idx)
+        if ref_idx.size:
+            ref_lam = o.lam[cn].ravel()[ref_idx]
+            assert np.abs(lam.cpu().numpy() - ref_lam).max() <= 1e-13 * ref_lam.max()
+            cf = coef.cpu().numpy()
+            for k in range(3):
+                B, A = o.coef[k][cn]
+                assert np.abs(cf[k, :, 0] - B.ravel()[ref_idx]).max() <= 1e-13
+                assert np.abs(cf[k, :, 1] - 1.0 / A.ravel()[ref_idx]).max() <= 1e-13
+    g.close()
+
+
+@pytest.mark.parametrize("shape,top", [((16, 13, 8), 0), ((32, 33, 16), 1), ((6, 9, 6), 0)])
+def test_solve_pressure_parity_stretched(shape, top):
+    from paper_2506_14328_amd import IbmGrid
+    nx, ny, nz = shape
+    c = I.Case(nx=nx, ny=ny, nz=nz, lx=2.0, lz=1.0, y_lo=-1.0, y_hi=1.0, nu=0.01, dt=0.01, top=top,
+               y_faces=I.tanh_faces(ny, -1.0, 1.0, 1.5))
+    rng = np.random.default_rng(3)
+    rhs = rng.standard_normal((ny - 1, nz, nx))
+    ref, _ = solve_pressure(OGrid.from_case(c), rhs)
+    g = IbmGrid.from_case(c)
+    phi = g.solve_pressure(to_dev(rhs)).cpu().numpy()
+    err = rel_err(phi, ref)
+    _say(f"poisson {shape} top={top}: {err:.2e}")
+    assert err < 1e-12
+    g.close()
+
+
+@pytest.mark.parametrize("name,steps", [("wavy_small", 3), ("flat_small", 3), ("open_small", 2), ("ellip_small", 2)])
+def test_step_parity_stretched_fp64(name, steps):
+    c = stretched(name)
+    o, sdf, st = oracle_run(c, steps)
+    g = gpu_grid(c, sdf, st)
+    g.step(steps)
+    u, v, w, p = [t.cpu().numpy() for t in g.get_state()]
+    errs = [rel_err(a, b) for a, b in ((u, o.u), (v, o.v), (w, o.w))]
+    _say(f"{name} stretched, {steps} steps: {['%.1e' % e for e in errs]}")
+    assert max(errs) < 1e-12
+    s = g.stats()
+    assert abs(s["q"] - o.flow_rate(o.u)) < 1e-12 * abs(o.flow_rate(o.u))
+    g.close()
+
+
+def test_step_stretched_fp32_storage():
+    c = stretched("wavy_small")
+    o, sdf, st = oracle_run(c, 3)
+    g = gpu_grid(c, sdf, st, precision="fp32")
+    g.step(3)
+    u, v, w, p = [t.double().cpu().numpy() for t in g.get_state()]
+    scale = np.abs(o.u).max()
+    assert max(np.abs(a - b).max() for a, b in ((u, o.u), (v, o.v), (w, o.w))) < 1e-5 * scale
+    g.close()
+
+
+def test_stretched_and_uniform_in_a_batched_graph_ensemble():
+    from paper_2506_14328_amd import IbmGrid
+    cs = [stretched("wavy_small"), case("flat_small")]
+    runs = [oracle_run(x, 2) for x in cs]
+    g = IbmGrid.ensemble(cs, precision="fp64")
+    for i, (o, sdf, st) in enumerate(runs):
+        g.set_geometry(*[to_dev(a) for a in sdf], inst=i)
+        g.set_state(*[to_dev(a) for a in st], inst=i)
+    g.tune(graph=1, batch=1)
+    g.step(1)
+    g.step(1)
+    for i, (o, sdf, st) in enumerate(runs):
+        u, v, w, p = [t.cpu().numpy() for t in g.get_state(inst=i)]
+        errs = [rel_err(a, b) for a, b in ((u, o.u), (v, o.v), (w, o.w))]
+        _say(f"instance {i}: {['%.1e' % e for e in errs]}")
+        assert max(errs) < 1e-12
+    g.close()
+
+
+def test_wall_shear_stretched():
+    c = stretched("open_small")
+    o, sdf, st = oracle_run(c, 2)
+    g = gpu_grid(c, sdf, st)
+    g.step(2)
+    tau, modes = g.wall_shear()
+    ref = wall_shear_profile(o.g, o.u, sdf[0])
+    err = np.abs(tau.cpu().numpy() - ref).max() / np.abs(ref).max()
+    _say(f"wall shear stretched: {err:.1e}")
+    assert err < 1e-10
+    g.close()
+
+
+def test_y_faces_argument_checks():
+    from paper_2506_14328_amd import IbmGrid
+    c = case("flat_small")
+    g = IbmGrid.from_case(c)
+    yf = np.asarray(I.tanh_faces(c.ny, c.y_lo, c.y_hi, 1.0))
+    bad = yf.copy()
+    bad[5], bad[6] = bad[6], bad[5]
+    with pytest.raises(IbmError):
+        g.set_y_faces(bad)
+    bad = yf.copy()
+    bad[0] -= 0.1
+    with pytest.raises(IbmError):
+        g.set_y_faces(bad)
+    bad = yf.copy()
+    bad[3] = np.nan
+    with pytest.raises(IbmError):
+        g.set_y_faces(bad)
+    # after new faces a geometry is needed before stepping
+    sdf = I.make_sdf(c)
+    g.set_geometry(*[to_dev(a) for a in sdf])
+    g.set_y_faces(yf)
+    with pytest.raises(IbmError):
+        g.step(1)
+    g.close()
+    import dataclasses
+    m = IbmGrid.from_case(dataclasses.replace(c, projection=1))
+    with pytest.raises(IbmError):
+        m.set_y_faces(yf)
+    m.close()
