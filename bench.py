@@ -465,6 +465,22 @@ def main():
         ro = measure("wavy_open", "fp64", 300, 3, inputs=inp_o)
         forms.append(dict(_form(ro, "fp64"), top="free-slip", ibm_point_fraction=round(ro["ibm_fraction"], 4)))
         del inp_o
+        # the wavy channel on a stretched wall-normal grid (faces clustered towards both box
+        # walls, tanh with gamma 1.2: spacing ratio 3.3), FP64, 300 steps
+        import dataclasses
+        import numpy as np
+        import ibm_inputs as I
+        cw = I.make_case("wavy")
+        cs = dataclasses.replace(cw, y_faces=I.tanh_faces(cw.ny, cw.y_lo, cw.y_hi, 1.2),
+                                 name="wavy_stretched_192x129x96")
+        sdf_s = I.make_sdf(cs)
+        us_, vs_, ws_ = I.make_initial(cs, sdf_s)
+        rs = measure("wavy", "fp64", 300, 3, inputs=(cs, sdf_s, (us_, vs_, ws_, np.zeros_like(us_))))
+        dyc = np.diff(np.asarray(cs.y_faces))
+        forms.append(dict(_form(rs, "fp64"), y_faces="tanh, gamma 1.2",
+                          spacing_ratio=round(float(dyc.max() / dyc.min()), 2),
+                          ibm_point_fraction=round(rs["ibm_fraction"], 4)))
+        del sdf_s, us_, vs_, ws_
         forms.append(measure_masked())
         forms.extend(measure_shard_shapes())
         forms.append(measure_ensemble())
