@@ -832,7 +832,7 @@ int run_steps_batched(ibm_ctx* c, int nsteps, hipStream_t st, bool count = true)
                                                b.lds_div, st));
       RUNK(c, K_FFTZ_FWD, launch_fftz_b<T>((const FftzArgs<T>*)b.fzf, b.bo_fz, n, b.n_fz, b.mb_fz, b.lds_fz,
                                            b.th_fz, st));
-      RUNK(c, K_TRI, launch_tri_b<T>((const TriArgs<T>*)b.tri, b.bo_tri, n, b.n_tri, b.lm_tri, b.lds_tri, st));
+      RUNK(c, K_TRI, launch_tri_b<T>((const TriArgs<T>*)b.tri, b.bo_tri, n, b.n_tri, b.lm_tri, b.lds_tri, b.stretched, st));
       RUNK(c, K_FFTZ_INV, launch_fftz_b<T>((const FftzArgs<T>*)b.fzi, b.bo_fz, n, b.n_fz, b.mb_fz, b.lds_fz,
                                            b.th_fz, st));
       RUNK(c, K_IFFTX, launch_ifftx_b<T>((const IfftxArgs<T>*)b.ifx, b.bo_ifx, n, b.n_ifx, b.mb_ifx, b.lds_ifx,

@@ -309,7 +309,7 @@ hipError_t launch_fftz_b(const FftzArgs<T>* args, const int* boff, int ninst, in
                          int threads, hipStream_t st);
 template <typename T>
 hipError_t launch_tri_b(const TriArgs<T>* args, const int* boff, int ninst, int ntot, int lm, size_t lds,
-                        hipStream_t st);
+                        bool stretched, hipStream_t st);
 template <typename T>
 hipError_t launch_ifftx_b(const IfftxArgs<T>* args, const int* boff, int ninst, int ntot, int mb, size_t lds,
                           hipStream_t st);

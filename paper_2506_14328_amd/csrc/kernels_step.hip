@@ -710,7 +710,7 @@ __device__ __forceinline__ double recip(double x) {
 // segment groups of a wavefront fall into alternate halves of the LDS banks.
 __host__ __device__ inline int tri_rs(int W) { return W + ((8 - W % 16) + 16) % 16; }
 
-template <typename T, int LM>
+template <typename T, int LM, bool SY>
 __device__ __forceinline__ void k_tri_body(GridParams g, cplx<T>* __restrict__ spec,
                                             const double* __restrict__ kx2, const double* __restrict__ kz2,
                                             int P, int W, double* __restrict__ mean_out, int bid_x, int bid_y, int nblk) {
@@ -752,7 +752,7 @@ __device__ __forceinline__ void k_tri_body(GridParams g, cplx<T>* __restrict__ s
   }
   // mean of the (0,0) mode over j (only block 0 holds it, at w = 0); on a stretched grid
   // weighted by the cell heights (entry ny1 of their table holds the box height)
-  const bool sy = g.stretched != 0;
+  constexpr bool sy = SY;
   const double* yt = g.ytab;
   const int ys = g.ystr;
   double mr = 0.0, mi = 0.0;
@@ -942,21 +942,21 @@ __device__ __forceinline__ void k_tri_body(GridParams g, cplx<T>* __restrict__ s
   }
 }
 
-template <typename T, int LM>
+template <typename T, int LM, bool SY>
 __global__ __launch_bounds__(256) void k_tri(GridParams g, cplx<T>* __restrict__ spec,
                                             const double* __restrict__ kx2, const double* __restrict__ kz2,
                                             int P, int W, double* __restrict__ mean_out) {
-  k_tri_body<T, LM>(g, spec, kx2, kz2, P, W, mean_out, blockIdx.x, blockIdx.y, gridDim.x);
+  k_tri_body<T, LM, SY>(g, spec, kx2, kz2, P, W, mean_out, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
 // The same for a batch of independent grids in one launch (block ranges boff).
-template <typename T, int LM>
+template <typename T, int LM, bool SY>
 __global__ __launch_bounds__(256) void k_tri_b(const TriArgs<T>* __restrict__ args,
     const int* __restrict__ boff, int ninst) {
   const int i = batch_instance(boff, ninst, blockIdx.x);
   const TriArgs<T>& a = args[i];
   const int local = blockIdx.x - boff[i];
-  k_tri_body<T, LM>(a.g, a.spec, a.kx2, a.kz2, a.P, a.W, a.mean_out, local % a.gx, local / a.gx, boff[i + 1] - boff[i]);
+  k_tri_body<T, LM, SY>(a.g, a.spec, a.kx2, a.kz2, a.P, a.W, a.mean_out, local % a.gx, local / a.gx, boff[i + 1] - boff[i]);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1241,10 +1241,14 @@ hipError_t launch_tri(const GridParams& g, cplx<T>* spec, const double* kx2, con
   const int W = TB / P;                      // modes per block
   const size_t lds = (size_t)(4 * tri_rs(W) * 2 * P + 2 * P) * sizeof(double);
   const dim3 grid((g.nz * g.mhs + W - 1) / W);
-  if (L == 4 && (n + P - 1) / P <= 4)
-    hipLaunchKernelGGL((k_tri<T, 4>), grid, dim3(TB), lds, st, g, spec, kx2, kz2, P, W, mean_out);
-  else
-    hipLaunchKernelGGL((k_tri<T, 8>), grid, dim3(TB), lds, st, g, spec, kx2, kz2, P, W, mean_out);
+  const bool l4 = L == 4 && (n + P - 1) / P <= 4;
+  if (g.stretched) {
+    if (l4) hipLaunchKernelGGL((k_tri<T, 4, true>), grid, dim3(TB), lds, st, g, spec, kx2, kz2, P, W, mean_out);
+    else hipLaunchKernelGGL((k_tri<T, 8, true>), grid, dim3(TB), lds, st, g, spec, kx2, kz2, P, W, mean_out);
+  } else {
+    if (l4) hipLaunchKernelGGL((k_tri<T, 4, false>), grid, dim3(TB), lds, st, g, spec, kx2, kz2, P, W, mean_out);
+    else hipLaunchKernelGGL((k_tri<T, 8, false>), grid, dim3(TB), lds, st, g, spec, kx2, kz2, P, W, mean_out);
+  }
   return hipGetLastError();
 }
 
@@ -1407,12 +1411,18 @@ hipError_t launch_fftz_b(const FftzArgs<T>* args, const int* boff, int ninst, in
 
 template <typename T>
 hipError_t launch_tri_b(const TriArgs<T>* args, const int* boff, int ninst, int ntot, int lm, size_t lds,
-                        hipStream_t st) {
-  const void* k = lm == 4 ? (const void*)k_tri_b<T, 4> : (const void*)k_tri_b<T, 8>;
+                        bool stretched, hipStream_t st) {
+  const void* k = stretched ? (lm == 4 ? (const void*)k_tri_b<T, 4, true> : (const void*)k_tri_b<T, 8, true>)
+                            : (lm == 4 ? (const void*)k_tri_b<T, 4, false> : (const void*)k_tri_b<T, 8, false>);
   hipError_t e = allow_lds(k, lds);
   if (e != hipSuccess) return e;
-  if (lm == 4) hipLaunchKernelGGL((k_tri_b<T, 4>), dim3(ntot), dim3(256), lds, st, args, boff, ninst);
-  else hipLaunchKernelGGL((k_tri_b<T, 8>), dim3(ntot), dim3(256), lds, st, args, boff, ninst);
+  if (stretched) {
+    if (lm == 4) hipLaunchKernelGGL((k_tri_b<T, 4, true>), dim3(ntot), dim3(256), lds, st, args, boff, ninst);
+    else hipLaunchKernelGGL((k_tri_b<T, 8, true>), dim3(ntot), dim3(256), lds, st, args, boff, ninst);
+  } else {
+    if (lm == 4) hipLaunchKernelGGL((k_tri_b<T, 4, false>), dim3(ntot), dim3(256), lds, st, args, boff, ninst);
+    else hipLaunchKernelGGL((k_tri_b<T, 8, false>), dim3(ntot), dim3(256), lds, st, args, boff, ninst);
+  }
   return hipGetLastError();
 }
 
@@ -1446,7 +1456,7 @@ hipError_t launch_ifftx_b(const IfftxArgs<T>* args, const int* boff, int ninst, 
   template hipError_t launch_div_fftx_b<T>(const DivArgs<T>*, const int*, int, int, int, size_t, hipStream_t);  \
   template hipError_t launch_fftz_b<T>(const FftzArgs<T>*, const int*, int, int, int, size_t, int,              \
                                        hipStream_t);                                                            \
-  template hipError_t launch_tri_b<T>(const TriArgs<T>*, const int*, int, int, int, size_t, hipStream_t);       \
+  template hipError_t launch_tri_b<T>(const TriArgs<T>*, const int*, int, int, int, size_t, bool, hipStream_t);       \
   template hipError_t launch_ifftx_b<T>(const IfftxArgs<T>*, const int*, int, int, int, size_t, hipStream_t);
 
 IBM_BATCH_INST(double)
