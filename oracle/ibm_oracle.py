@@ -8,7 +8,7 @@ with the GPU library and never calls it.
 
 Every function cites the passage of the paper (arXiv 2506.14328) it follows.
 Where the paper is silent the reading taken is stated in the docstring
-(readings R1..R13; the same list is kept with the design notes).
+(readings R1..R20; the same list is kept with the design notes).
 
 Conventions
 -----------
