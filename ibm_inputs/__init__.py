@@ -35,7 +35,7 @@ import numpy as np
 __all__ = [
     "Case", "coords", "sdf_flat_channel", "sdf_wavy", "sdf_ellipsoids",
     "laminar_plus_noise", "laminar_plus_solenoidal", "random_fields",
-    "divergence_free_field", "make_case", "WORKLOADS", "ensemble_cases",
+    "divergence_free_field", "make_case", "WORKLOADS", "ensemble_cases", "tanh_faces", "bottom_tanh_faces",
 ]
 
 
@@ -111,6 +111,31 @@ def tanh_faces(ny: int, y_lo: float, y_hi: float, gamma: float) -> Tuple[float, 
     y = 0.5 * (y_lo + y_hi) + 0.5 * (y_hi - y_lo) * t
     y[0], y[-1] = y_lo, y_hi
     return tuple(float(a) for a in y)
+
+
+def bottom_tanh_faces(ny: int, y_lo: float, y_hi: float, ratio: float) -> Tuple[float, ...]:
+    """ny wall-normal faces clustered towards the bottom y_lo only: y = y_hi - (y_hi - y_lo)
+    tanh(gamma (1 - xi))/tanh(gamma), xi uniform in [0, 1], with gamma chosen (bisection)
+    so that the largest spacing (at the top) is `ratio` times the smallest (at the bottom)."""
+    xi = np.linspace(0.0, 1.0, ny)
+
+    def faces(gm):
+        y = y_hi - (y_hi - y_lo) * np.tanh(gm * (1.0 - xi)) / math.tanh(gm)
+        y[0], y[-1] = y_lo, y_hi
+        return y
+
+    def spread(gm):
+        d = np.diff(faces(gm))
+        return d.max() / d.min()
+
+    lo, hi = 1e-6, 10.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if spread(mid) < ratio:
+            lo = mid
+        else:
+            hi = mid
+    return tuple(float(a) for a in faces(0.5 * (lo + hi)))
 
 
 def _mesh(y, z, x):

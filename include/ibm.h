@@ -123,10 +123,17 @@ typedef struct {
 
 /* Create n_inst independent channel instances (an ensemble of ragged sizes is
  * allowed; desc points to n_inst descriptors) at the given precision, all work on
- * hip_stream (a hipStream_t; NULL = default stream).  Instances are addressed by
- * their index in the per-instance calls; ibm_step advances all of them.
- * Validates the descriptor (IBM_ERR_ARG), allocates device fields and the FFT
- * and tridiagonal plans (IBM_ERR_OOM).  Fields start at zero. */
+ * hip_stream (a hipStream_t; NULL = default stream).  The grid is the staggered
+ * second-order Cartesian grid of Sec. 2.1 (pressure at cell centres, each velocity
+ * component on the faces normal to it), periodic in x and z, bounded by walls (or a
+ * free-slip face) in y; the time step is the fixed dt of Sec. 2.4's RK3 integration.
+ * Instances are addressed by their index in the per-instance calls; ibm_step advances
+ * all of them.  Validates the descriptors (IBM_ERR_ARG: nx odd, nx/2 or nz with a prime
+ * factor outside {2,3,5}, nx or nz above 1024, ny outside 3..2049, more than 2e9/3
+ * cells, dt <= 0, nu <= 0, an empty box, an unknown forcing, b_mode, top, projection or
+ * precision, the masked projection without IBM_FP64, n_inst outside 1..65536 or a null
+ * pointer), allocates device fields and the FFT and tridiagonal plans (IBM_ERR_OOM;
+ * IBM_ERR_DEVICE if a HIP call fails).  Fields start at zero. */
 int ibm_create_grid(const ibm_grid_desc* desc, int32_t n_inst, int32_t precision,
                     void* hip_stream, ibm_handle* out);
 
@@ -159,13 +166,25 @@ int ibm_get_state(ibm_handle h, int32_t inst, void* u, void* v, void* w, void* p
  * ibm_set_geometry. */
 int ibm_step(ibm_handle h, int32_t nsteps);
 
-/* Stand-alone pressure solve on the full box: D G phi = rhs - mean(rhs),
- * zero-mean phi (periodic x, z; homogeneous Neumann at the y box walls).
- * rhs, phi: device arrays of the storage type, cell layout.  The removed
- * mean is reported by the next ibm_stats(). */
+/* Stand-alone pressure solve on the full box, the Poisson equation of the projection
+ * of Sec. 2.1 (D G phi = D u_p / (c_k dt) there, u_p the predictor) solved exactly as Sec. 2.1 allows, with
+ * the continuity equation imposed on every cell as Sec. 3.3 describes:
+ * D G phi = rhs - mean(rhs), zero-mean phi (periodic x, z; homogeneous Neumann at the y
+ * box walls), by real FFT in x, complex FFT in z and an FP64 tridiagonal solve per
+ * Fourier mode in y.  rhs, phi: device arrays of the storage type, cell layout (no
+ * alignment needed beyond that of the type); rhs is not modified; they may alias only
+ * if identical.  The removed mean is reported by the next ibm_stats().  Stream-ordered,
+ * no synchronisation.  IBM_ERR_ARG for a bad instance or null pointer. */
 int ibm_solve_pressure(ibm_handle h, int32_t inst, const void* rhs, void* phi);
 
-/* Diagnostics of the current state (synchronises the stream). */
+/* Diagnostics of the current state (synchronises the stream): the flow rate and mean
+ * pressure gradient of the constant-flow-rate control (Sec. 2.5, Eq. (18) notation),
+ * the divergence left by the projection of Sec. 2.1 on the full box and on the internal
+ * pressure cells (Sec. 3.3), the Poisson residual, kinetic energy, CFL number and a
+ * NaN/Inf flag, and the point counts of the staircase classification (Sec. 3.3) and of
+ * the immersed-boundary lists (Sec. 2.2).  Fields as in ibm_stats_t; *out is fully
+ * written on IBM_OK and on IBM_ERR_UNSTABLE (NaN/Inf or CFL above sqrt(3), the values
+ * still reported).  IBM_ERR_ARG for a bad instance or null out. */
 int ibm_stats(ibm_handle h, int32_t inst, ibm_stats_t* out);
 
 /* Velocity (ub, vb, wb) of the immersed walls (the zero set of the signed distances),
@@ -253,10 +272,18 @@ enum { IBM_TUNE_MOMENTUM_PLANES = 0, IBM_TUNE_FFTZ_WIDTH = 1, IBM_TUNE_TRI_ROWS 
                                          or profiling are on. */
        IBM_TUNE_GRAPH_BRANCHES = 4,   /* capture streams for the graph (0 = up to 8) */
        IBM_TUNE_TILE_ORDER = 5,
-       IBM_TUNE_BATCH = 6 };          /* 1: an ensemble is advanced with one launch per kernel for
+       IBM_TUNE_BATCH = 6,            /* 1: an ensemble is advanced with one launch per kernel for
                                          all instances (each instance's blocks a contiguous range of
                                          the grid), also inside the graph.  Ignored for a single
                                          instance and while diagnostics or profiling are on. */
+       IBM_TUNE_MOMENTUM_CACHE = 7,   /* cache policy of the momentum kernel's single-use
+                                         accesses, 1 + bits: bit 0 streaming (non-temporal)
+                                         stores of u*, p and H, bit 1 streaming loads of H_prev
+                                         (0 = automatic: plain accesses) */
+       IBM_TUNE_MOMENTUM_TILE = 8 };  /* (x, z) tile of one momentum block: 0 or 1 = 64 x 4,
+                                         2 = 128 x 4, 3 = 64 x 8, 4 = 256 x 4 and 5 = 128 x 8
+                                         (FP32 storage only; FP64 takes 64 x 4 for these);
+                                         stretched grids and batched launches take 64 x 4 */
 int ibm_tune_set(ibm_handle h, int32_t param, int32_t value);
 int ibm_tune_get(ibm_handle h, int32_t param, int32_t* value);
 
@@ -277,6 +304,15 @@ int ibm_autotune(ibm_handle h, int32_t steps_per_trial, int32_t* chosen);
 
 /* Bytes of device memory the library holds for this handle. */
 int64_t ibm_device_bytes(ibm_handle h);
+
+/* Streaming device copy of `bytes` bytes from src to dst (device pointers, both 16-byte
+ * aligned, bytes a multiple of 16, the ranges not overlapping), enqueued on hip_stream
+ * (a hipStream_t; NULL = the default stream): 16-byte vector loads and stores over the
+ * whole GPU.  It is the measured practical HBM ceiling against which the step kernels'
+ * bandwidth is compared (it reads and writes every byte once).  No handle; the library
+ * keeps nothing.  IBM_ERR_ARG for null pointers, misalignment, a size that is not a
+ * multiple of 16 or overlapping ranges; IBM_ERR_DEVICE if the launch fails. */
+int ibm_stream_copy(void* dst, const void* src, int64_t bytes, void* hip_stream);
 
 int ibm_destroy(ibm_handle h);
 const char* ibm_last_error(ibm_handle h);

@@ -1229,6 +1229,14 @@ int ibm_tune_set(ibm_handle h, int32_t param, int32_t value) {
         if (value > 2) return fail(h, IBM_ERR_ARG, "tile order must be 0, 1 or 2");
         I.tu.tile_order = value;
         break;
+      case IBM_TUNE_MOMENTUM_TILE:
+        if (value > 5) return fail(h, IBM_ERR_ARG, "momentum tile must be 0..5");
+        I.tu.mom_tile = value;
+        break;
+      case IBM_TUNE_MOMENTUM_CACHE:
+        if (value > 4) return fail(h, IBM_ERR_ARG, "momentum cache policy must be 0..4");
+        I.tu.mom_cache = value;
+        break;
       case IBM_TUNE_FFTZ_WIDTH: I.tu.fftz_w = value; break;
       case IBM_TUNE_TRI_ROWS:
         if (value != 0 && value != 4 && value != 8) return fail(h, IBM_ERR_ARG, "tri rows must be 0, 4 or 8");
@@ -1246,6 +1254,8 @@ int ibm_tune_get(ibm_handle h, int32_t param, int32_t* value) {
   switch (param) {
     case IBM_TUNE_MOMENTUM_PLANES: *value = t.mom_jc; break;
     case IBM_TUNE_TILE_ORDER: *value = t.tile_order; break;
+    case IBM_TUNE_MOMENTUM_CACHE: *value = t.mom_cache; break;
+    case IBM_TUNE_MOMENTUM_TILE: *value = t.mom_tile; break;
     case IBM_TUNE_FFTZ_WIDTH: *value = t.fftz_w; break;
     case IBM_TUNE_TRI_ROWS: *value = t.tri_rows; break;
     case IBM_TUNE_GRAPH: *value = h->use_graph ? 1 : 0; break;
@@ -1541,6 +1551,18 @@ int64_t ibm_device_bytes(ibm_handle h) {
          I.geo_tmp.bytes;
   }
   return b;
+}
+
+int ibm_stream_copy(void* dst, const void* src, int64_t bytes, void* hip_stream) {
+  if (!dst || !src) return fail(nullptr, IBM_ERR_ARG, "null pointer");
+  if (((uintptr_t)dst | (uintptr_t)src) % 16 != 0) return fail(nullptr, IBM_ERR_ARG, "pointers must be 16-byte aligned");
+  if (bytes < 0 || bytes % 16 != 0) return fail(nullptr, IBM_ERR_ARG, "bytes must be a non-negative multiple of 16");
+  const uintptr_t d = (uintptr_t)dst, s = (uintptr_t)src;
+  if (d < s + (uintptr_t)bytes && s < d + (uintptr_t)bytes && bytes > 0)
+    return fail(nullptr, IBM_ERR_ARG, "source and destination overlap");
+  const hipError_t e = launch_stream_copy(src, dst, bytes / 16, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return fail(nullptr, IBM_ERR_DEVICE, std::string("stream copy: ") + hipGetErrorString(e));
+  return IBM_OK;
 }
 
 int ibm_destroy(ibm_handle h) {

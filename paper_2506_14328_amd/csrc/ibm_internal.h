@@ -191,7 +191,13 @@ struct Tuning {
   int fftz_w = 0;     // x modes per z-FFT block
   int tri_rows = 0;   // rows per thread of the tridiagonal partition solver (4 or 8)
   int tile_order = 0; // momentum tiles: 1 contiguous per XCD (default), 2 interleaved
+  int mom_cache = 0;  // 1 + bits: bit 0 streaming stores, bit 1 streaming single-use loads
+  int mom_tile = 0;   // momentum tile: 0/1 64x4, 2 128x4, 3 64x8, 4 256x4 (FP32), 5 128x8 (FP32)
 };
+
+// Flags of the momentum kernel's `order` argument: the tile order (bit 0: contiguous runs
+// per XCD) and the cache policy of its single-use accesses.
+enum : int { MOM_XCD_CONTIG = 1, MOM_NT_STORE = 2, MOM_NT_LOAD = 4 };
 
 // Arguments of one grid's step kernels, for the batched launches that advance a whole
 // ensemble of independent grids with one launch per kernel (block ranges per grid).
@@ -400,6 +406,8 @@ hipError_t launch_s_k_final(const double* part, int npart, double scale, double*
 // state copy helpers
 template <typename T>
 hipError_t launch_copy(const T* src, T* dst, int64_t n, hipStream_t st);
+// nvec 16-byte vectors from src to dst (16-byte aligned)
+hipError_t launch_stream_copy(const void* src, void* dst, int64_t nvec, hipStream_t st);
 
 // RK3 constants (Sec. 2.4, Eq. (17)); c_k = a_k + b_k.
 static const double RK_A[3] = {64.0 / 120.0, 50.0 / 120.0, 90.0 / 120.0};

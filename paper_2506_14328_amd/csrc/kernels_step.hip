@@ -41,18 +41,23 @@ __device__ __forceinline__ int batch_instance(const int* __restrict__ boff, int 
 // pressure p' as the planes are loaded (c' = c_{k-1}, Pi' = Pi_{k-1}); p is also written
 // out (f.pn) for the next substep.
 //
-// A block owns a 64 x 4 (x, z) column of cells and marches through a chunk of y
-// planes.  u, v, w, p live in a ring of four LDS planes (j-1, j, j+1 and the one being
+// A block owns an MX x MZ (x, z) column of cells (64 x 4 by default; a wavefront is one
+// 64-wide row chunk) and marches through a chunk of y planes.  u, v, w, p live in a ring of four LDS planes (j-1, j, j+1 and the one being
 // filled) with a halo of one row in z and two columns in x (so that the tile is made of
 // whole, aligned pairs of x-adjacent values: every thread loads one pair of each field
 // with one vector load).  The loads of plane j+2 are issued before the arithmetic of
 // plane j and their corrected values written to the ring slot of plane j-2 afterwards.
 // Planes outside the box (ghost rows, the north wall face of v) are zero.
 // ---------------------------------------------------------------------------------------
-constexpr int MX = 64, MZ = 4;
-constexpr int MHX = MX + 4, MHZ = MZ + 2, MTILE = MHX * MHZ;   // 408 values per plane tile
-constexpr int MPAIRS = MTILE / 2;                               // 204 pairs, one per thread
-static_assert(MPAIRS <= MX * MZ, "one tile pair per thread");
+constexpr int MX = 64, MZ = 4;   // default tile (and the batched launches' tile)
+template <int TX, int TZ>
+struct MomTile {
+  static constexpr int HX = TX + 4, HZ = TZ + 2, TILE = HX * HZ;   // 408 values at 64 x 4
+  static constexpr int PAIRS = TILE / 2;                           // 204 pairs, one per thread
+  static constexpr int THREADS = TX * TZ;
+  static_assert(PAIRS <= THREADS, "one tile pair per thread");
+  static_assert(TX % 64 == 0, "whole 64-wide row chunks per block row");
+};
 
 template <typename T>
 struct alignas(2 * sizeof(T)) Pair {
@@ -78,24 +83,28 @@ struct TileRaw {
 // concurrent HBM accesses close together).
 constexpr int NXCD = 8;
 
-template <typename T, bool SY>
+template <typename T, bool SY, int MXT = MX, int MZT = MZ>
 __device__ __forceinline__ void k_momentum_body(GridParams g, Fields<T> f, IbmLists L, StageConsts s, int jc,
                                                  int ntx, int ntz, int xcd_order, const double* __restrict__ pi_prev,
                                                  double ckdt_prev, double* __restrict__ qpart, int bid_x, int bid_y, int nblk) {
+  using TL = MomTile<MXT, MZT>;
+  constexpr int MHX = TL::HX, MTILE = TL::TILE, MPAIRS = TL::PAIRS;
   __shared__ __align__(16) T ring[4][4][MTILE];   // [field u,v,w,p][slot][tile]
-  __shared__ double red[4];
-  const int tx = threadIdx.x, tz = threadIdx.y, tid = tz * MX + tx;
+  __shared__ double red[TL::THREADS / 64];
+  const int tx = threadIdx.x, tz = threadIdx.y, tid = tz * MXT + tx;
+  const int lane = tx & 63;
   const int nx = g.nx, nz = g.nz, ny1 = g.ny1, plane = nx * nz;
   int bx, bz, by;
   {
     const int nb = nblk, b = bid_x;
     const int xcd = b % NXCD, q = nb / NXCD, rem = nb % NXCD;
-    const int t = xcd_order ? xcd * q + min(xcd, rem) + b / NXCD : b;
+    const int t = (xcd_order & MOM_XCD_CONTIG) ? xcd * q + min(xcd, rem) + b / NXCD : b;
     bx = t % ntx;
     bz = (t / ntx) % ntz;
     by = t / (ntx * ntz);
   }
-  const int i0 = bx * MX, k0 = bz * MZ;
+  const int i0 = bx * MXT, k0 = bz * MZT;
+  const int chk = (i0 + tx) >> 6;   // this wavefront's 64-wide chunk of the row
   const int j0 = by * jc;
   const int j1 = min(j0 + jc, ny1);
   const int i = i0 + tx, k = k0 + tz;
@@ -212,7 +221,7 @@ __device__ __forceinline__ void k_momentum_body(GridParams g, Fields<T> f, IbmLi
   uint8_t tgn = f.tag[j0 * plane + kc * nx + icl];
   int chn_u, chn_v, chn_w;
   {
-    const int ch = (j0 * nz + kc) * L.cpr + bx;
+    const int ch = (j0 * nz + kc) * L.cpr + chk;
     chn_u = L.choff_u[ch];
     chn_v = L.choff_v[ch];
     chn_w = L.choff_w[ch];
@@ -221,21 +230,27 @@ __device__ __forceinline__ void k_momentum_body(GridParams g, Fields<T> f, IbmLi
     const int c = j * plane + k * nx + i;
     const uint8_t tg = act ? tgn : uint8_t(0);
     // immersed-boundary points: list index = chunk offset + flagged lanes below (the
-    // wavefront is the 64-wide chunk bx of row j*nz + k); (B, 1/A) of this point
+    // wavefront is the 64-wide chunk chk of row j*nz + k); (B, 1/A) of this point
     const uint64_t mu = __ballot((tg & TAG_UI) != 0);
     const uint64_t mv = __ballot((tg & TAG_VI) != 0);
     const uint64_t mw = __ballot((tg & TAG_WI) != 0);
     const size_t cb = (size_t)s.stage * L.n_total;
     double2 cfu = {0.0, 0.0}, cfv = {0.0, 0.0}, cfw = {0.0, 0.0};
-    if (tg & TAG_UI) cfu = L.coef[cb + chn_u + lanes_below(mu, tx)];
-    if (tg & TAG_VI) cfv = L.coef[cb + L.n_u + chn_v + lanes_below(mv, tx)];
-    if (tg & TAG_WI) cfw = L.coef[cb + L.n_u + L.n_v + chn_w + lanes_below(mw, tx)];
+    if (tg & TAG_UI) cfu = L.coef[cb + chn_u + lanes_below(mu, lane)];
+    if (tg & TAG_VI) cfv = L.coef[cb + L.n_u + chn_v + lanes_below(mv, lane)];
+    if (tg & TAG_WI) cfw = L.coef[cb + L.n_u + L.n_v + chn_w + lanes_below(mw, lane)];
     T hu = zero, hv = zero, hw = zero;
     if (act) {
       if (s.use_hold) {
-        hu = f.Hu[c];
-        hv = f.Hv[c];
-        hw = f.Hw[c];
+        if (xcd_order & MOM_NT_LOAD) {
+          hu = __builtin_nontemporal_load(f.Hu + c);
+          hv = __builtin_nontemporal_load(f.Hv + c);
+          hw = __builtin_nontemporal_load(f.Hw + c);
+        } else {
+          hu = f.Hu[c];
+          hv = f.Hv[c];
+          hw = f.Hw[c];
+        }
       }
     }
     __builtin_amdgcn_sched_barrier(0);   // keep the loads above ahead of the prefetch
@@ -245,7 +260,7 @@ __device__ __forceinline__ void k_momentum_body(GridParams g, Fields<T> f, IbmLi
     {
       const int jn = j + 1 < ny1 ? j + 1 : ny1 - 1;
       tgn = f.tag[jn * plane + kc * nx + icl];
-      const int ch = (jn * nz + kc) * L.cpr + bx;
+      const int ch = (jn * nz + kc) * L.cpr + chk;
       chn_u = L.choff_u[ch];
       chn_v = L.choff_v[ch];
       chn_w = L.choff_w[ch];
@@ -349,11 +364,17 @@ __device__ __forceinline__ void k_momentum_body(GridParams g, Fields<T> f, IbmLi
         if (s.use_hold) rw += bkdt * hw;
       }
     }
+    // single-use outputs: optionally streamed past the caches, so that the L2 keeps the
+    // tile rows that neighbouring blocks load as their halos
+    auto st_out = [&](T* ptr, T val) {
+      if (xcd_order & MOM_NT_STORE) __builtin_nontemporal_store(val, ptr);
+      else *ptr = val;
+    };
     if (act) {
       if (s.write_h) {
-        f.Hu[c] = Hu;
-        f.Hv[c] = Hv;
-        f.Hw[c] = Hw;
+        st_out(f.Hu + c, Hu);
+        st_out(f.Hv + c, Hv);
+        st_out(f.Hw + c, Hw);
       }
       // external points keep the immersed walls' velocity (v on the south box wall: 0)
       T su = ubw, sv = (j == 0) ? zero : vbw, sw = wbw;
@@ -365,10 +386,10 @@ __device__ __forceinline__ void k_momentum_body(GridParams g, Fields<T> f, IbmLi
       if (tg & TAG_UI) su = T((cfu.x * (double)uc + (double)ru) * cfu.y);
       if (tg & TAG_VI) sv = T((cfv.x * (double)vc + (double)rv) * cfv.y);
       if (tg & TAG_WI) sw = T((cfw.x * (double)wc + (double)rw) * cfw.y);
-      f.us[c] = su;
-      f.vs[c] = sv;
-      f.ws[c] = sw;
-      f.pn[c] = pc;
+      st_out(f.us + c, su);
+      st_out(f.vs + c, sv);
+      st_out(f.ws + c, sw);
+      st_out(f.pn + c, pc);
       if constexpr (SY) {
         // (a uniform grid in a batched launch with stretched ones: unweighted, like its
         // flow-rate scale factor)
@@ -384,11 +405,12 @@ __device__ __forceinline__ void k_momentum_body(GridParams g, Fields<T> f, IbmLi
   if (tid == 0) qpart[bid_x] = tot;
 }
 
-template <typename T, bool SY>
-__global__ __launch_bounds__(256) void k_momentum(GridParams g, Fields<T> f, IbmLists L, StageConsts s, int jc,
+template <typename T, bool SY, int MXT, int MZT>
+__global__ __launch_bounds__(MXT * MZT) void k_momentum(GridParams g, Fields<T> f, IbmLists L, StageConsts s, int jc,
                                                  int ntx, int ntz, int xcd_order, const double* __restrict__ pi_prev,
                                                  double ckdt_prev, double* __restrict__ qpart) {
-  k_momentum_body<T, SY>(g, f, L, s, jc, ntx, ntz, xcd_order, pi_prev, ckdt_prev, qpart, blockIdx.x, blockIdx.y, gridDim.x);
+  k_momentum_body<T, SY, MXT, MZT>(g, f, L, s, jc, ntx, ntz, xcd_order, pi_prev, ckdt_prev, qpart, blockIdx.x,
+                                   blockIdx.y, gridDim.x);
 }
 
 // The same for a batch of independent grids in one launch (block ranges boff).
@@ -1064,7 +1086,36 @@ __global__ __launch_bounds__(256) void k_copy(const T* __restrict__ src, T* __re
     dst[e] = src[e];
 }
 
+// Streaming copy of n 16-byte vectors (the practical HBM ceiling of a kernel that reads and
+// writes each byte once): every thread moves 4 vectors per trip, all four loads issued
+// before the stores, with the blocks striding over the whole array.
+__global__ __launch_bounds__(256) void k_stream_copy(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                                                      int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * 1024;
+  for (int64_t b = (int64_t)blockIdx.x * 1024 + threadIdx.x; b < n; b += stride) {
+    uint4 v[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t e = b + r * 256;
+      if (e < n) v[r] = src[e];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t e = b + r * 256;
+      if (e < n) dst[e] = v[r];
+    }
+  }
+}
+
 }  // namespace
+
+hipError_t launch_stream_copy(const void* src, void* dst, int64_t nvec, hipStream_t st) {
+  if (nvec <= 0) return hipSuccess;
+  int64_t nb = (nvec + 1023) / 1024;
+  if (nb > 8192) nb = 8192;   // 32 blocks per CU, then grid-stride
+  hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)nb), dim3(256), 0, st, (const uint4*)src, (uint4*)dst, nvec);
+  return hipGetLastError();
+}
 
 // =======================================================================================
 // Launchers
@@ -1073,9 +1124,19 @@ static inline dim3 cell_grid(const GridParams& g) {
   return dim3((g.nx + BX - 1) / BX, (g.nz + BZ - 1) / BZ, g.ny1);
 }
 
+// Momentum tile (x, z) of a tuning: 64 x 4 (automatic), 128 x 4, 64 x 8, 256 x 4, 128 x 8.
+static void momentum_tile(const Tuning& tu, int* tx, int* tz) {
+  static const int TXS[6] = {64, 64, 128, 64, 256, 128}, TZS[6] = {4, 4, 4, 8, 4, 8};
+  const int t = (tu.mom_tile >= 0 && tu.mom_tile < 6) ? tu.mom_tile : 0;
+  *tx = TXS[t];
+  *tz = TZS[t];
+}
+
 // y planes per momentum block: about 2048 blocks, 4..64 planes each, unless tuned.
 static int momentum_chunk(const GridParams& g, const Tuning& tu) {
   if (tu.mom_jc > 0) return tu.mom_jc < g.ny1 ? tu.mom_jc : g.ny1;
+  int MX, MZ;
+  momentum_tile(tu, &MX, &MZ);
   const long cols = (long)((g.nx + MX - 1) / MX) * ((g.nz + MZ - 1) / MZ);
   long jc = (g.ny1 * cols + 2047) / 2048;
   if (jc < 4) jc = 4;
@@ -1088,15 +1149,38 @@ hipError_t launch_momentum(const GridParams& g, const Fields<T>& f, const IbmLis
                            const double* pi_prev, double ckdt_prev, const Tuning& tu, double* qpart, int* nqpart,
                            hipStream_t st) {
   const int jc = momentum_chunk(g, tu);
-  const int ntx = (g.nx + MX - 1) / MX, ntz = (g.nz + MZ - 1) / MZ, nty = (g.ny1 + jc - 1) / jc;
+  int tx, tz;
+  momentum_tile(tu, &tx, &tz);
+  const int ntx = (g.nx + tx - 1) / tx, ntz = (g.nz + tz - 1) / tz, nty = (g.ny1 + jc - 1) / jc;
   const int nb = ntx * ntz * nty;
-  const int xo = tu.tile_order == 2 ? 0 : 1;
-  if (g.stretched)
-    hipLaunchKernelGGL((k_momentum<T, true>), dim3(nb), dim3(MX, MZ), 0, st, g, f, L, s, jc, ntx, ntz, xo, pi_prev,
-                       ckdt_prev, qpart);
-  else
-    hipLaunchKernelGGL((k_momentum<T, false>), dim3(nb), dim3(MX, MZ), 0, st, g, f, L, s, jc, ntx, ntz, xo, pi_prev,
-                       ckdt_prev, qpart);
+  const int cache = tu.mom_cache > 0 ? tu.mom_cache - 1 : 0;
+  const int xo = (tu.tile_order == 2 ? 0 : MOM_XCD_CONTIG) | ((cache & 1) ? MOM_NT_STORE : 0) |
+                 ((cache & 2) ? MOM_NT_LOAD : 0);
+#define IBM_LAUNCH_MOM(SYV, TXV, TZV)                                                                   \
+  hipLaunchKernelGGL((k_momentum<T, SYV, TXV, TZV>), dim3(nb), dim3(TXV, TZV), 0, st, g, f, L, s, jc, ntx, ntz, xo, \
+                     pi_prev, ckdt_prev, qpart)
+  bool done = false;
+  if (g.stretched) {
+    IBM_LAUNCH_MOM(true, 64, 4);
+    done = true;
+  } else if (tx == 128 && tz == 4) {
+    IBM_LAUNCH_MOM(false, 128, 4);
+    done = true;
+  } else if (tx == 64 && tz == 8) {
+    IBM_LAUNCH_MOM(false, 64, 8);
+    done = true;
+  }
+  if constexpr (sizeof(T) == 4) {   // the larger tiles fit the LDS only in FP32
+    if (!done && tx == 256 && tz == 4) {
+      IBM_LAUNCH_MOM(false, 256, 4);
+      done = true;
+    } else if (!done && tx == 128 && tz == 8) {
+      IBM_LAUNCH_MOM(false, 128, 8);
+      done = true;
+    }
+  }
+  if (!done) IBM_LAUNCH_MOM(false, 64, 4);
+#undef IBM_LAUNCH_MOM
   *nqpart = nb;
   return hipGetLastError();
 }
@@ -1295,7 +1379,9 @@ hipError_t launch_copy(const T* src, T* dst, int64_t n, hipStream_t st) {
 // =======================================================================================
 template <typename T>
 int plan_momentum(const GridParams& g, const Fields<T>& f, const IbmLists& L, const StageConsts& s,
-                  const double* pi_prev, double ckdt_prev, const Tuning& tu, double* qpart, MomArgs<T>* a) {
+                  const double* pi_prev, double ckdt_prev, const Tuning& tu0, double* qpart, MomArgs<T>* a) {
+  Tuning tu = tu0;
+  tu.mom_tile = 0;   // batched launches use the default tile
   const int jc = momentum_chunk(g, tu);
   const int ntx = (g.nx + MX - 1) / MX, ntz = (g.nz + MZ - 1) / MZ, nty = (g.ny1 + jc - 1) / jc;
   const int nb = ntx * ntz * nty;

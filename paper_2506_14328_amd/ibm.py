@@ -29,10 +29,11 @@ EXPORTED = [
     "ibm_solve_pressure", "ibm_stats", "ibm_set_diagnostics", "ibm_get_geometry", "ibm_get_ibm_list",
     "ibm_profile", "ibm_profile_read", "ibm_kernel_name", "ibm_num_kernels", "ibm_device_bytes",
     "ibm_destroy", "ibm_last_error", "ibm_tune_set", "ibm_tune_get", "ibm_autotune", "ibm_wall_shear",
-    "ibm_set_wall_velocity", "ibm_set_y_faces",
+    "ibm_set_wall_velocity", "ibm_set_y_faces", "ibm_stream_copy",
 ]
 TUNE_PARAMS = {"momentum_planes": 0, "fftz_width": 1, "tri_rows": 2, "graph": 3, "graph_branches": 4,
-               "tile_order": 5, "batch": 6}
+               "tile_order": 5, "batch": 6, "momentum_cache": 7,
+               "momentum_tile": 8}
 
 
 class IbmGridDesc(ctypes.Structure):
@@ -94,6 +95,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "ibm_autotune": (c_int32, [h, c_int32, POINTER(c_int32)]),
         "ibm_destroy": (c_int32, [h]),
         "ibm_last_error": (ctypes.c_char_p, [h]),
+        "ibm_stream_copy": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -105,6 +107,21 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
 
 def _ptr(t: torch.Tensor) -> int:
     return t.data_ptr()
+
+
+def stream_copy(dst: torch.Tensor, src: torch.Tensor, stream: Optional[torch.cuda.Stream] = None):
+    """dst <- src with the library's streaming copy kernel (ibm_stream_copy): contiguous
+    device tensors of the same size in bytes (a multiple of 16), on torch's current stream."""
+    lib = load_library()
+    if dst.device.type != "cuda" or src.device.type != "cuda" or not dst.is_contiguous() or not src.is_contiguous():
+        raise TypeError("expected contiguous GPU tensors")
+    nb = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nb:
+        raise ValueError("dst and src differ in size")
+    st = stream if stream is not None else torch.cuda.current_stream(src.device)
+    rc = lib.ibm_stream_copy(c_void_p(_ptr(dst)), c_void_p(_ptr(src)), nb, c_void_p(st.cuda_stream))
+    if rc != IBM_OK:
+        raise IbmError(rc, lib.ibm_last_error(None).decode())
 
 
 def _desc(c, ibm: bool) -> IbmGridDesc:

@@ -187,6 +187,39 @@ def test_full_size_stretched_step_properties():
     assert s["nan_flag"] == 0 and s["step"] == 3
     assert s["div_max_fullbox"] * hmin < 1e-12
     assert s["poisson_rel_residual"] < 1e-13
-    assert abs(s["q"] / c.q_target_or_pi - 1.0) < 1e-3
+    assert abs(s["q"] / c.q_target_or_pi - 1.0) < 1e-4
     assert math.isfinite(s["div_max_internal_leak"])
+    g.close()
+
+
+def test_open_channel_stretched_full_size_parity():
+    """The open channel of Sec. 4.2 (192x65x160, free-slip top) on a mildly stretched
+    wall-normal grid clustered towards the undulated bottom (largest/smallest spacing 5.6,
+    the ratio of the paper's 64-point grid), two steps in the autotuned configuration
+    against the oracle on the same faces, every element, and the wall-shear profile."""
+    import dataclasses
+    from oracle.ibm_oracle import wall_shear_modes
+    from tests.test_gpu_wall_shear import _tau_tol
+    c0 = I.make_case("wavy_open")
+    c = dataclasses.replace(c0, y_faces=I.bottom_tanh_faces(c0.ny, c0.y_lo, c0.y_hi, 5.6),
+                            name="wavy_open_stretched_192x65x160")
+    _say("oracle 2 steps ...")
+    o, sdf, st = oracle_run(c, 2)
+    g = gpu_grid(c, sdf, st)
+    tuned = g.autotune(1)
+    g.set_state(*[to_dev(a) for a in st])
+    g.step(2)
+    u, v, w, p = [t.cpu().numpy() for t in g.get_state()]
+    scale = max(np.abs(o.u).max(), np.abs(o.v).max(), np.abs(o.w).max())
+    errs = [np.abs(a - b).max() / scale for a, b in ((u, o.u), (v, o.v), (w, o.w))]
+    ep = np.abs(p - o.p).max() / max(np.abs(o.p).max(), scale * scale)
+    _say(f"tuning {tuned}: u v w {errs}, p {ep:.2e}")
+    assert max(errs) <= 1e-12
+    assert ep <= 1e-11
+    tau, modes = g.wall_shear()
+    ref = wall_shear_profile(o.g, o.u, sdf[0])
+    tol = _tau_tol(o.g, sdf[0], 1e-12 * np.abs(o.u).max()) + 1e-14 * np.abs(ref).max()
+    e = np.abs(tau.cpu().numpy() - ref).max()
+    _say(f"tau(x): max err {e:.2e} (bound {tol:.2e}); modes {modes} vs {wall_shear_modes(o.g, ref)}")
+    assert e <= tol
     g.close()
