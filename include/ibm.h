@@ -314,6 +314,29 @@ int64_t ibm_device_bytes(ibm_handle h);
  * multiple of 16 or overlapping ranges; IBM_ERR_DEVICE if the launch fails. */
 int ibm_stream_copy(void* dst, const void* src, int64_t bytes, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the full-box pressure solve of
+ * ibm_solve_pressure without a handle.  The grid is desc's (uniform wall-normal
+ * spacing; only nx, ny, nz, lx, lz, y_lo and y_hi are read), the precision IBM_FP64 or
+ * IBM_FP32_STORAGE, rhs and phi device arrays of that storage type in the cell layout
+ * (as for ibm_solve_pressure, same kernels, same result up to the last-bit rounding of
+ * the device-computed twiddle tables); mean_removed: NULL or a device double that
+ * receives the mean of rhs removed by the gauge.  Work area: a fixed array of
+ * IBM_NOALLOC_SCRATCH_BYTES inside the library, one per GPU (held until the process
+ * ends, its device address looked up once per device on the first call there); the call
+ * allocates nothing, calls no hipMalloc, hipFree or hipMemset, and only enqueues kernels
+ * on hip_stream (a hipStream_t; NULL = the default stream), so it may be captured into a
+ * HIP graph.  Every call on a GPU uses that GPU's one work area: calls that may run
+ * concurrently on one GPU (different streams, or graphs replayed concurrently) race and
+ * must be ordered by the caller.  IBM_ERR_ARG for a null argument, a grid the kernels do
+ * not accept (as ibm_create_grid) or one whose half spectrum and tables exceed the work
+ * area (about ny nz (nx/2 + 8) 16 bytes in FP64, half that in FP32: for example
+ * 256 x 129 x 128 in FP64); IBM_ERR_DEVICE if a launch fails.  ibm_last_error(NULL)
+ * gives the message. */
+#define IBM_NOALLOC_SCRATCH_BYTES (64ll << 20)
+int ibm_solve_pressure_noalloc(const ibm_grid_desc* desc, int32_t precision, const void* rhs, void* phi,
+                               double* mean_removed, void* hip_stream);
+
 int ibm_destroy(ibm_handle h);
 const char* ibm_last_error(ibm_handle h);
 

@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libibm.so")
-SOURCES = ["ibm_api.hip", "kernels_step.hip", "kernels_aux.hip", "kernels_pcg.hip"]
+SOURCES = ["ibm_api.hip", "kernels_step.hip", "kernels_aux.hip", "kernels_pcg.hip", "ibm_noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",

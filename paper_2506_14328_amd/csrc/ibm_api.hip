@@ -149,6 +149,10 @@ hipError_t timed(ibm_ctx* c, int kid, F&& launch) {
   return launch();
 }
 
+}  // namespace
+
+void set_last_error(const char* msg) { g_last_error = msg; }
+
 bool factor_235(int n, int* radix, int* nst) {
   int k = 0;
   while (n % 8 == 0 && k < 20) { radix[k++] = 8; n /= 8; }
@@ -159,6 +163,8 @@ bool factor_235(int n, int* radix, int* nst) {
   *nst = k;
   return n == 1;
 }
+
+namespace {
 
 // Per-row wall-normal tables (the YTable layout) of the faces yf[0..ny1]: the same
 // arithmetic as the definitions of the spacings (cell heights, centre spacings with the
@@ -265,34 +271,9 @@ int validate(ibm_ctx* c, const ibm_grid_desc& d) {
 int init_instance(ibm_ctx* c, Instance& I, const ibm_grid_desc& d) {
   I.d = d;
   GridParams& g = I.g;
-  g.nx = d.nx;
-  g.ny1 = d.ny - 1;
-  g.nz = d.nz;
-  g.nhalf = d.nx / 2;
-  g.mh = d.nx / 2 + 1;
-  g.nrows = g.ny1 * g.nz;
-  g.nmodes = g.nz * g.mh;
-  g.ncell = (int64_t)g.nx * g.ny1 * g.nz;
-  g.dx = d.lx / d.nx;
-  g.dz = d.lz / d.nz;
-  g.dy = (d.y_hi - d.y_lo) / (d.ny - 1);
-  g.idx = 1.0 / g.dx;
-  g.idy = 1.0 / g.dy;
-  g.idz = 1.0 / g.dz;
-  g.idx2 = 1.0 / (g.dx * g.dx);
-  g.idy2 = 1.0 / (g.dy * g.dy);
-  g.idz2 = 1.0 / (g.dz * g.dz);
-  g.nu = d.nu;
-  g.dt = d.dt;
-  g.top_fs = d.top == IBM_TOP_FREE_SLIP ? 1 : 0;
   const size_t ts = (c->precision == IBM_FP64) ? sizeof(double) : sizeof(float);
-  // spectrum rows start on 128-byte lines (8 FP64 or 16 FP32 complex values per line);
-  // a plane spans an odd number of lines, so that the rows of one mode in successive
-  // planes do not all fall on the same memory channels
-  const int line = (int)(128 / (2 * ts));
-  g.mhs = (g.mh + line - 1) / line * line;
-  g.splane = g.nz * g.mhs;
-  if ((g.splane / line) % 2 == 0) g.splane += line;
+  grid_params_uniform(d.nx, d.ny, d.nz, d.lx, d.lz, d.y_lo, d.y_hi, d.nu, d.dt,
+                      d.top == IBM_TOP_FREE_SLIP ? 1 : 0, ts, &g);
   int rc;
   if ((rc = make_plan(c, I, g.nhalf, &I.px))) return rc;
   {

@@ -72,6 +72,50 @@ enum YTable {
   YT_NF
 };
 
+// Uniform-grid parameters of one descriptor (nx, ny1, nz, spacings, spectrum strides) for
+// storage values of ts bytes; ytab, ystr and stretched are left for the caller.
+// Spectrum rows start on 128-byte lines (8 FP64 or 16 FP32 complex values per line); a
+// plane spans an odd number of lines, so that the rows of one mode in successive planes
+// do not all fall on the same memory channels.
+inline void grid_params_uniform(int nx, int ny, int nz, double lx, double lz, double y_lo, double y_hi, double nu,
+                                double dt, int top_fs, size_t ts, GridParams* out) {
+  GridParams& g = *out;
+  g.nx = nx;
+  g.ny1 = ny - 1;
+  g.nz = nz;
+  g.nhalf = nx / 2;
+  g.mh = nx / 2 + 1;
+  g.nrows = g.ny1 * g.nz;
+  g.nmodes = g.nz * g.mh;
+  g.ncell = (int64_t)g.nx * g.ny1 * g.nz;
+  g.dx = lx / nx;
+  g.dz = lz / nz;
+  g.dy = (y_hi - y_lo) / (ny - 1);
+  g.idx = 1.0 / g.dx;
+  g.idy = 1.0 / g.dy;
+  g.idz = 1.0 / g.dz;
+  g.idx2 = 1.0 / (g.dx * g.dx);
+  g.idy2 = 1.0 / (g.dy * g.dy);
+  g.idz2 = 1.0 / (g.dz * g.dz);
+  g.nu = nu;
+  g.dt = dt;
+  g.top_fs = top_fs;
+  const int line = (int)(128 / (2 * ts));
+  g.mhs = (g.mh + line - 1) / line * line;
+  g.splane = g.nz * g.mhs;
+  if ((g.splane / line) % 2 == 0) g.splane += line;
+  g.stretched = 0;
+  g.ystr = g.ny1 + 1;
+  g.ytab = nullptr;
+}
+
+// Factors of an FFT length into radix-8/4/2/3/5 stages (host): false if n has another
+// prime factor.
+bool factor_235(int n, int* radix, int* nst);
+
+// The message ibm_last_error(NULL) returns on this thread (calls without a handle).
+void set_last_error(const char* msg);
+
 // Twiddle/stage description of one complex FFT length, resident on the device.
 struct FFTPlan {
   int n;                // transform length

@@ -29,7 +29,7 @@ EXPORTED = [
     "ibm_solve_pressure", "ibm_stats", "ibm_set_diagnostics", "ibm_get_geometry", "ibm_get_ibm_list",
     "ibm_profile", "ibm_profile_read", "ibm_kernel_name", "ibm_num_kernels", "ibm_device_bytes",
     "ibm_destroy", "ibm_last_error", "ibm_tune_set", "ibm_tune_get", "ibm_autotune", "ibm_wall_shear",
-    "ibm_set_wall_velocity", "ibm_set_y_faces", "ibm_stream_copy",
+    "ibm_set_wall_velocity", "ibm_set_y_faces", "ibm_stream_copy", "ibm_solve_pressure_noalloc",
 ]
 TUNE_PARAMS = {"momentum_planes": 0, "fftz_width": 1, "tri_rows": 2, "graph": 3, "graph_branches": 4,
                "tile_order": 5, "batch": 6, "momentum_cache": 7,
@@ -96,6 +96,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "ibm_destroy": (c_int32, [h]),
         "ibm_last_error": (ctypes.c_char_p, [h]),
         "ibm_stream_copy": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p]),
+        "ibm_solve_pressure_noalloc": (c_int32, [POINTER(IbmGridDesc), c_int32, c_void_p, c_void_p, c_void_p,
+                                                 c_void_p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -122,6 +124,40 @@ def stream_copy(dst: torch.Tensor, src: torch.Tensor, stream: Optional[torch.cud
     rc = lib.ibm_stream_copy(c_void_p(_ptr(dst)), c_void_p(_ptr(src)), nb, c_void_p(st.cuda_stream))
     if rc != IBM_OK:
         raise IbmError(rc, lib.ibm_last_error(None).decode())
+
+
+def solve_pressure_noalloc(c, rhs: torch.Tensor, phi: Optional[torch.Tensor] = None,
+                           mean_removed: Optional[torch.Tensor] = None,
+                           stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+    """ibm_solve_pressure_noalloc: the full-box pressure solve of the grid of case c
+    (uniform wall-normal spacing) with the library's fixed work area.  rhs (and phi, if
+    given) are contiguous GPU tensors of shape (ny-1, nz, nx) in float64 or float32 (the
+    precision follows their dtype); mean_removed, if given, a GPU float64 tensor of one
+    element.  Enqueued on torch's current stream; allocates no device memory in the library
+    (phi is allocated here by torch when not given)."""
+    lib = load_library()
+    shape = (c.ny - 1, c.nz, c.nx)
+    if rhs.device.type != "cuda" or tuple(rhs.shape) != shape or not rhs.is_contiguous():
+        raise ValueError(f"rhs must be a contiguous GPU tensor of shape {shape}")
+    if rhs.dtype not in (torch.float64, torch.float32):
+        raise TypeError("rhs must be float64 or float32")
+    if phi is None:
+        phi = torch.empty_like(rhs)
+    if phi.device.type != "cuda" or tuple(phi.shape) != shape or phi.dtype != rhs.dtype or not phi.is_contiguous():
+        raise ValueError("phi must match rhs")
+    mp = None
+    if mean_removed is not None:
+        if mean_removed.device.type != "cuda" or mean_removed.dtype != torch.float64 or mean_removed.numel() < 1:
+            raise ValueError("mean_removed must be a GPU float64 tensor")
+        mp = c_void_p(_ptr(mean_removed))
+    prec = IBM_FP64 if rhs.dtype == torch.float64 else IBM_FP32_STORAGE
+    st = stream if stream is not None else torch.cuda.current_stream(rhs.device)
+    d = _desc(c, True)
+    rc = lib.ibm_solve_pressure_noalloc(ctypes.byref(d), prec, c_void_p(_ptr(rhs)), c_void_p(_ptr(phi)), mp,
+                                        c_void_p(st.cuda_stream))
+    if rc != IBM_OK:
+        raise IbmError(rc, lib.ibm_last_error(None).decode())
+    return phi
 
 
 def _desc(c, ibm: bool) -> IbmGridDesc:
