@@ -263,7 +263,12 @@ int32_t ibm_num_kernels(void);
  *   IBM_TUNE_TRI_ROWS         rows per thread of the tridiagonal solver: 4 or 8
  *   IBM_TUNE_TILE_ORDER       momentum tiles: 1 = each XCD takes a contiguous run of
  *                             tiles (neighbours share an L2), 2 = tiles interleaved
- *                             over the XCDs */
+ *                             over the XCDs, 3..8 = super-tiles of 2x2, 4x2, 2x4, 4x4,
+ *                             8x2 and 8x4 tiles (x by z) dealt round-robin to the XCDs,
+ *                             the tiles of one super-tile consecutive blocks of one XCD
+ *                             (they share halo lines through its L2); a grid whose tile
+ *                             counts do not split into whole super-tiles dealt evenly to
+ *                             the 8 XCDs takes order 2 instead */
 enum { IBM_TUNE_MOMENTUM_PLANES = 0, IBM_TUNE_FFTZ_WIDTH = 1, IBM_TUNE_TRI_ROWS = 2,
        IBM_TUNE_GRAPH = 3,            /* 1: ibm_step replays a HIP graph of one RK3 step of all
                                          instances (captured on first use, rebuilt after any

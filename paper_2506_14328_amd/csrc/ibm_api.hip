@@ -1207,7 +1207,7 @@ int ibm_tune_set(ibm_handle h, int32_t param, int32_t value) {
     switch (param) {
       case IBM_TUNE_MOMENTUM_PLANES: I.tu.mom_jc = value; break;
       case IBM_TUNE_TILE_ORDER:
-        if (value > 2) return fail(h, IBM_ERR_ARG, "tile order must be 0, 1 or 2");
+        if (value > 8) return fail(h, IBM_ERR_ARG, "tile order must be 0..8");
         I.tu.tile_order = value;
         break;
       case IBM_TUNE_MOMENTUM_TILE:
@@ -1307,7 +1307,7 @@ int autotune_impl(ibm_ctx* c, Instance& I, int steps, int32_t* chosen) {
     return IBM_OK;
   };
   // candidates per knob, searched one knob at a time
-  std::vector<int> to = {1, 2};
+  std::vector<int> to = {1, 2, 3, 4, 5, 6, 7, 8};
   std::vector<int> jc = {0, 2, 4, 6, 8, 10, 12, 14, 16, 20, 24, 32, 48, 64};
   int wv[8];
   const int nw = fftz_widths<T>(g, I.pz, wv, 8);

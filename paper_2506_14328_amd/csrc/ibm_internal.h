@@ -234,14 +234,17 @@ struct Tuning {
   int mom_jc = 0;     // y planes per momentum block
   int fftz_w = 0;     // x modes per z-FFT block
   int tri_rows = 0;   // rows per thread of the tridiagonal partition solver (4 or 8)
-  int tile_order = 0; // momentum tiles: 1 contiguous per XCD (default), 2 interleaved
+  int tile_order = 0; // momentum tiles: 1 contiguous per XCD (default), 2 interleaved,
+                      // 3..8 super-tiles of 2x2, 4x2, 2x4, 4x4, 8x2, 8x4 tiles per XCD
   int mom_cache = 0;  // 1 + bits: bit 0 streaming stores, bit 1 streaming single-use loads
   int mom_tile = 0;   // momentum tile: 0/1 64x4, 2 128x4, 3 64x8, 4 256x4 (FP32), 5 128x8 (FP32)
 };
 
 // Flags of the momentum kernel's `order` argument: the tile order (bit 0: contiguous runs
 // per XCD) and the cache policy of its single-use accesses.
-enum : int { MOM_XCD_CONTIG = 1, MOM_NT_STORE = 2, MOM_NT_LOAD = 4 };
+// Bits MOM_SUPER_SHIFT.. hold log2 of the super-tile's width and depth in tiles (two bits
+// each; 0 and 0: no super-tiles).
+enum : int { MOM_XCD_CONTIG = 1, MOM_NT_STORE = 2, MOM_NT_LOAD = 4, MOM_SUPER_SHIFT = 4 };
 
 // Arguments of one grid's step kernels, for the batched launches that advance a whole
 // ensemble of independent grids with one launch per kernel (block ranges per grid).
