@@ -60,6 +60,8 @@ class Case:
     geo_params: Tuple = ()
     top: int = 0       # 0 = no-slip north box face, 1 = free-slip north face (open channel)
     projection: int = 0  # 0 = full-box pressure projection, 1 = masked (internal cells only)
+    pcg_max_iter: int = 0  # masked: iteration cap per solve (0 = the library's default)
+    pcg_tol: float = 0.0   # masked: relative residual tolerance (0 = the library's default)
     y_faces: Optional[Tuple[float, ...]] = None  # stretched wall-normal grid: the ny face y's
 
     @property

@@ -89,12 +89,20 @@ typedef struct {
                            corrected, Sec. 3.3 read strictly), solved by conjugate gradients
                            preconditioned with the full-box solve and started from its
                            solution; phi has zero mean over the internal cells.  IBM_FP64
-                           only; ibm_step then launches eagerly (no graph) and synchronises
-                           every 4 iterations to test the residual (up to 3 iterations past
-                           the tolerance only refine the solution); IBM_ERR_UNSTABLE if the
-                           iteration cap is reached, the state then holding the last
-                           iterate.  The internal pressure cells must be connected through
-                           internal faces. */
+                           only.  Convergence is tested on the device after every iteration
+                           and, once reached, the solve's remaining kernels return at once.
+                           Eager steps read that flag back every 4 iterations to stop
+                           launching (a host synchronisation each time) and return
+                           IBM_ERR_UNSTABLE when pcg_max_iter is reached, the state then
+                           holding the last iterate.  With IBM_TUNE_GRAPH on, a first step
+                           runs eagerly and the captured graph then runs a fixed budget per
+                           solve: the most iterations a solve has needed so far (eager, or
+                           captured as read by ibm_stats) plus a quarter, at least 4 more (a
+                           multiple of 4, at least 8, at most pcg_max_iter; a larger need
+                           rebuilds the graph at the next ibm_step), with no host access; a
+                           solve that does not converge within it makes the next ibm_stats
+                           return IBM_ERR_UNSTABLE.  The internal pressure cells must be connected
+                           through internal faces. */
   int32_t pcg_max_iter; /* masked: iteration cap per solve (<= 0: 500) */
   double pcg_tol;       /* masked: stop at ||r||_2 <= pcg_tol ||b||_2 over the internal cells,
                            b = D u_p / (c_k dt) (<= 0: 1e-13) */

@@ -48,6 +48,10 @@ struct Instance {
   double wall_vel[3] = {0.0, 0.0, 0.0};   // host copy of the immersed walls' velocity
   int pcg_iters = 0;        // iterations of the last masked solve
   double pcg_res = 0.0;     // its final |r| / |b|
+  int pcg_iters_max = 0;    // most iterations of an eager masked solve so far
+  bool pcg_seen = false;    // an eager masked solve has run
+  int pcg_budget = 0;       // iterations per solve captured in the graph
+  int32_t* pcg_stat = nullptr;   // device: PCG_NSTAT int32 slots, then |r|^2 (double)
   // south-wall point per (k, i) column (row, distance) and wall-shear output [nx + 3]
   int32_t* wall_j = nullptr;
   double* wall_d = nullptr;
@@ -132,6 +136,38 @@ int fail(ibm_ctx* c, int code, const std::string& msg) {
     hipError_t _e = (expr);                                                                      \
     if (_e != hipSuccess)                                                                        \
       return fail(ctx, IBM_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(_e));       \
+  } while (0)
+
+// Synchronises st, after checking that neither st nor the library's own capture stream is
+// being captured into a graph (a synchronising call inside a capture is refused with
+// IBM_ERR_STATE instead of being left to the runtime).
+int sync_stream(ibm_ctx* c, hipStream_t st) {
+  // (a query that fails says nothing about a capture: the synchronisation then decides)
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+    return fail(c, IBM_ERR_STATE, "a synchronising call on a stream that is being captured");
+  cs = hipStreamCaptureStatusNone;
+  if (c && c->cap && hipStreamIsCapturing(c->cap, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+    return fail(c, IBM_ERR_STATE, "a synchronising call while the library's graph capture is active");
+  const hipError_t e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return fail(c, IBM_ERR_DEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+  return IBM_OK;
+}
+
+// IBM_ERR_STATE when the library's stream is being captured into a graph by the caller:
+// entry points that synchronise refuse before they enqueue anything, so that the state
+// they would leave half-updated stays as it was.
+int refuse_capture(ibm_ctx* c) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(c->stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+    return fail(c, IBM_ERR_STATE, "this call synchronises the stream, which is being captured into a graph");
+  return IBM_OK;
+}
+
+#define SYNCHK(ctx, st)                   \
+  do {                                    \
+    const int _r = sync_stream(ctx, st);  \
+    if (_r) return _r;                    \
   } while (0)
 
 template <class F>
@@ -284,7 +320,7 @@ int init_instance(ibm_ctx* c, Instance& I, const ibm_grid_desc& d) {
     double* yt = nullptr;
     if ((rc = dalloc(c, I, (void**)&yt, tab.size() * sizeof(double)))) return rc;
     HIPCHK(c, hipMemcpyAsync(yt, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    SYNCHK(c, c->stream);
     g.ytab = yt;
     g.ystr = g.ny1 + 1;
     g.stretched = 0;
@@ -317,6 +353,8 @@ int init_instance(ibm_ctx* c, Instance& I, const ibm_grid_desc& d) {
     for (int q = 0; q < 4; ++q)
       if ((rc = dalloc(c, I, (void**)&I.pcg_v[q], (size_t)g.ncell * sizeof(double)))) return rc;
     if ((rc = dalloc(c, I, (void**)&I.pcg_part, (size_t)PCG_NSLOT * PCG_NPART * sizeof(double)))) return rc;
+    if ((rc = dalloc(c, I, (void**)&I.pcg_stat, PCG_NSTAT * sizeof(int32_t) + 2 * sizeof(double)))) return rc;
+    HIPCHK(c, hipMemsetAsync(I.pcg_stat, 0, PCG_NSTAT * sizeof(int32_t) + 2 * sizeof(double), c->stream));
   }
   const size_t ncol = (size_t)g.nx * g.nz;
   if ((rc = dalloc(c, I, (void**)&I.wall_j, ncol * sizeof(int32_t)))) return rc;
@@ -392,10 +430,10 @@ StageConsts stage_consts(const GridParams& g, int k) {
       return fail(ctx, IBM_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(_e));       \
   } while (0)
 
-// Pressure solve of the current right-hand side: forward FFTs, tridiagonal, inverse FFTs.
+// Pressure solve of the current right-hand side: forward FFTs, tridiagonal, inverse FFTs
+// (g: the instance's parameters, with the masked solve's skip flag inside its iterations).
 template <typename T>
-int poisson(ibm_ctx* c, Instance& I, Fields<T>& f, T* phi_out, hipStream_t st) {
-  const GridParams& g = I.g;
+int poisson(ibm_ctx* c, Instance& I, const GridParams& g, Fields<T>& f, T* phi_out, hipStream_t st) {
   RUNK(c, K_FFTZ_FWD, launch_fftz<T>(g, f.spec, I.pz, -1, I.tu, st));
   RUNK(c, K_TRI, launch_tri<T>(g, f.spec, I.kx2, I.kz2, I.mean(), I.tu, st));
   RUNK(c, K_FFTZ_INV, launch_fftz<T>(g, f.spec, I.pz, +1, I.tu, st));
@@ -405,49 +443,72 @@ int poisson(ibm_ctx* c, Instance& I, Fields<T>& f, T* phi_out, hipStream_t st) {
 
 // Masked projection of the current substep: f.phi holds the full-box solution, which
 // starts the conjugate gradients and is replaced by the masked one (zero mean over the
-// internal cells, zero elsewhere).  The residual norm is read back every PCG_CHECK
-// iterations (a host synchronisation each time); up to PCG_CHECK - 1 iterations beyond
-// the tolerance only refine the solution.
+// internal cells, zero elsewhere).  Convergence is tested on the device after every
+// iteration (k_pcg_check); once it holds, every later kernel of the solve returns at once
+// (the skip flag in the kernels' grid parameters), so the iterate stops exactly there.
+// Eager (capture false): up to pcg_max_iter iterations, the flag read back every
+// PCG_CHECK iterations to stop launching (a host synchronisation each time).  Captured
+// into a graph (capture true): a fixed budget of I.pcg_budget iterations and no host
+// access; a solve that has not converged within the budget is reported by ibm_stats.
 constexpr int PCG_CHECK = 4;
-int pcg_project(ibm_ctx* c, Instance& I, Fields<double>& f, hipStream_t st) {
-  const GridParams& g = I.g;
+int pcg_project(ibm_ctx* c, Instance& I, Fields<double>& f, hipStream_t st, bool capture) {
+  const GridParams& g0 = I.g;
+  GridParams g = g0;
+  g.skip = I.pcg_stat + PCG_DONE;
   double* x = f.phi;
   double *r = I.pcg_v[0], *z = I.pcg_v[1], *p = I.pcg_v[2], *ap = I.pcg_v[3];
   double* part = I.pcg_part;
   double* sc = I.pcg_sc();
+  double* rr_dev = reinterpret_cast<double*>(I.pcg_stat + PCG_NSTAT);
   const double tol = I.d.pcg_tol > 0.0 ? I.d.pcg_tol : 1e-13;
   const int max_iter = I.d.pcg_max_iter > 0 ? I.d.pcg_max_iter : 500;
-  HIPCHK(c, hipMemcpyAsync(sc + 3, I.mean(), sizeof(double), hipMemcpyDeviceToDevice, st));
-  RUNK(c, K_PCG, launch_pcg_init(g, I.tag, x, sc + 3, r, part, I.n_pint, st));
-  RUNK(c, K_PCG, launch_pcg_total(g, part, PCG_B, sc + 2, st));
-  RUNK(c, K_PCG, launch_pcg_total(g, part, PCG_R2, sc + 4, st));
-  double host[3];
-  HIPCHK(c, hipMemcpyAsync(host, sc + 2, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
-  HIPCHK(c, hipStreamSynchronize(st));
-  const double bb = host[0];
-  double rr = host[2];
-  int it = 0;
-  while (rr > tol * tol * bb && it < max_iter) {
+  const int budget = capture ? I.pcg_budget : max_iter;
+  RUNK(c, K_PCG, launch_pcg_prep(I.mean(), sc, I.pcg_stat, st));
+  RUNK(c, K_PCG, launch_pcg_init(g0, I.tag, x, sc + 3, r, part, I.n_pint, st));
+  RUNK(c, K_PCG, launch_pcg_total(g0, part, PCG_B, sc + 2, st));
+  RUNK(c, K_PCG, launch_pcg_check(g0, part, sc, tol * tol, 0, I.pcg_stat, rr_dev, st));
+  for (int it = 0; it < budget; ++it) {
+    if (!capture && it % PCG_CHECK == 0) {
+      int32_t done = 0;
+      HIPCHK(c, hipMemcpyAsync(&done, I.pcg_stat + PCG_DONE, sizeof(done), hipMemcpyDeviceToHost, st));
+      SYNCHK(c, st);
+      if (done) break;
+    }
     RUNK(c, K_DIV_FFTX, launch_div_fftx<double>(g, f, I.L, 0, I.px, I.rtw, 1.0, I.pi(), r, st));
-    int rc = poisson<double>(c, I, f, z, st);
+    int rc = poisson<double>(c, I, g, f, z, st);
     if (rc) return rc;
     RUNK(c, K_PCG, launch_pcg_rz(g, r, z, part, st));
     RUNK(c, K_PCG, launch_pcg_dir(g, I.tag, z, p, part, sc, it, st));
     RUNK(c, K_PCG, launch_pcg_apply(g, I.tag, p, ap, part, st));
     RUNK(c, K_PCG, launch_pcg_step(g, I.tag, x, r, p, ap, part, sc, it, st));
-    ++it;
-    if (it % PCG_CHECK == 0 || it == max_iter) {
-      RUNK(c, K_PCG, launch_pcg_total(g, part, PCG_R2, sc + 4, st));
-      HIPCHK(c, hipMemcpyAsync(&rr, sc + 4, sizeof(double), hipMemcpyDeviceToHost, st));
-      HIPCHK(c, hipStreamSynchronize(st));
-    }
+    RUNK(c, K_PCG, launch_pcg_check(g0, part, sc, tol * tol, it + 1, I.pcg_stat, rr_dev, st));
   }
-  RUNK(c, K_PCG, launch_pcg_finish(g, I.tag, x, part, I.n_pint, st));
-  HIPCHK(c, hipMemcpyAsync(I.mean(), sc + 3, sizeof(double), hipMemcpyDeviceToDevice, st));
-  I.pcg_iters = it;
+  RUNK(c, K_PCG, launch_pcg_finish(g0, I.tag, x, part, I.n_pint, st));
+  RUNK(c, K_PCG, launch_pcg_post(I.mean(), sc, st));
+  if (capture) return IBM_OK;
+  int32_t stat[PCG_NSTAT];
+  double rr = 0.0, bb = 0.0;
+  HIPCHK(c, hipMemcpyAsync(stat, I.pcg_stat, sizeof(stat), hipMemcpyDeviceToHost, st));
+  HIPCHK(c, hipMemcpyAsync(&rr, rr_dev, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(c, hipMemcpyAsync(&bb, sc + 2, sizeof(double), hipMemcpyDeviceToHost, st));
+  SYNCHK(c, st);
+  I.pcg_iters = stat[PCG_ITERS];
   I.pcg_res = bb > 0.0 ? std::sqrt(rr / bb) : 0.0;
-  if (!(rr <= tol * tol * bb)) return fail(c, IBM_ERR_UNSTABLE, "masked projection did not converge");
+  I.pcg_iters_max = std::max(I.pcg_iters_max, I.pcg_iters);
+  I.pcg_seen = true;
+  if (!stat[PCG_DONE]) return fail(c, IBM_ERR_UNSTABLE, "masked projection did not converge");
   return IBM_OK;
+}
+
+// Iterations per masked solve captured into a graph: the most a solve has needed so far
+// (eager solves, and captured ones as read by ibm_stats) plus a quarter (at least 4), a
+// multiple of PCG_CHECK, at least 8 and at most pcg_max_iter.  Iterations past
+// convergence cost only their launches (every kernel returns at once).
+int pcg_capture_budget(const Instance& I) {
+  const int max_iter = I.d.pcg_max_iter > 0 ? I.d.pcg_max_iter : 500;
+  int b = std::max(8, I.pcg_iters_max + std::max(4, I.pcg_iters_max / 4));
+  b = (b + PCG_CHECK - 1) / PCG_CHECK * PCG_CHECK;
+  return std::min(b, max_iter);
 }
 
 // nsteps RK3 steps of one instance, launched on st.  count: advance the step/time
@@ -478,11 +539,11 @@ int run_steps(ibm_ctx* c, Instance& I, int nsteps, hipStream_t st, bool count = 
       RUNK(c, K_CFR_PI, launch_cfr_pi<T>(f, I.L, k, sc.ck_dt, I.qpart, nq, scale, I.d.forcing, I.d.q_target_or_pi,
                                          I.S3(), I.pi(), I.pi_hist(), st));
       RUNK(c, K_DIV_FFTX, launch_div_fftx<T>(g, f, I.L, k, I.px, I.rtw, sc.ck_dt, I.pi(), (const T*)nullptr, st));
-      int rc = poisson<T>(c, I, f, f.phi, st);
+      int rc = poisson<T>(c, I, I.g, f, f.phi, st);
       if (rc) return rc;
       const bool masked = I.d.projection == IBM_PROJ_MASKED;
       if constexpr (std::is_same<T, double>::value) {
-        if (masked && (rc = pcg_project(c, I, f, st))) return rc;
+        if (masked && (rc = pcg_project(c, I, f, st, !count))) return rc;
       }
       if (c->diag && s == nsteps - 1 && k == 2 && !masked) {
         int np = 0;
@@ -578,8 +639,8 @@ int set_geometry_impl(ibm_ctx* c, Instance& I, const double* su, const double* s
     if (rc) break;
     int32_t cnt[7];
     e = hipMemcpyAsync(cnt, I.itotal, sizeof(cnt), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) { rc = fail(c, IBM_ERR_DEVICE, std::string("geometry counts: ") + hipGetErrorString(e)); break; }
+    if ((rc = sync_stream(c, st))) break;
     for (int q = 0; q < 3; ++q) {
       I.n_int[q] = cnt[q];
       I.n_ibm[q] = cnt[4 + q];
@@ -651,8 +712,8 @@ int set_geometry_impl(ibm_ctx* c, Instance& I, const double* su, const double* s
     int np = 0;
     e = launch_s_k(g, I.tag, I.L, I.d.dt, I.red_part, &np, I.wall_sd(), st);
     if (e == hipSuccess) e = launch_s_k_final(I.red_part, np, I.d.dt * y_scale(g) * g.dz / g.nx, I.S3(), st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) { rc = fail(c, IBM_ERR_DEVICE, std::string("S_k: ") + hipGetErrorString(e)); break; }
+    if ((rc = sync_stream(c, st))) break;
     I.geom_ready = true;
     I.diag_valid = false;
   } while (0);
@@ -834,7 +895,11 @@ int run_steps_batched(ibm_ctx* c, int nsteps, hipStream_t st, bool count = true)
 template <typename T>
 int build_graph(ibm_ctx* c) {
   drop_graph(c);
-  if (c->use_batch && c->inst.size() > 1) {
+  bool masked = false;
+  for (Instance& I : c->inst) masked = masked || I.d.projection == IBM_PROJ_MASKED;
+  // batched launches have no masked projection: an ensemble with a masked instance is
+  // captured as per-instance branches
+  if (c->use_batch && c->inst.size() > 1 && !masked) {
     // the batched launches on one stream: seven nodes per substep for the whole ensemble
     int rc = build_batch<T>(c);
     if (rc) return rc;
@@ -917,10 +982,7 @@ int ibm_create_grid(const ibm_grid_desc* desc, int32_t n_inst, int32_t precision
     c->inst.resize(n_inst);
     for (int i = 0; i < n_inst && !rc; ++i) rc = init_instance(c, c->inst[i], desc[i]);
   }
-  if (!rc) {
-    hipError_t e = hipStreamSynchronize(c->stream);
-    if (e != hipSuccess) rc = fail(c, IBM_ERR_DEVICE, hipGetErrorString(e));
-  }
+  if (!rc) rc = sync_stream(c, c->stream);
   if (rc) {
     ibm_destroy(c);
     return rc;
@@ -933,6 +995,7 @@ int ibm_set_geometry(ibm_handle h, int32_t inst, const double* sdf_u, const doub
   int rc = check_inst(h, inst);
   if (rc) return rc;
   if (!sdf_u || !sdf_v || !sdf_w) return fail(h, IBM_ERR_ARG, "null SDF pointer");
+  if ((rc = refuse_capture(h))) return rc;
   drop_graph(h);
   Instance& I = h->inst[inst];
   if ((rc = materialize(h, I))) return rc;   // a pending projection belongs to the old geometry
@@ -957,6 +1020,7 @@ int ibm_set_state(ibm_handle h, int32_t inst, const void* u, const void* v, cons
 int ibm_get_state(ibm_handle h, int32_t inst, void* u, void* v, void* w, void* p) {
   int rc = check_inst(h, inst);
   if (rc) return rc;
+  if ((rc = refuse_capture(h))) return rc;
   Instance& I = h->inst[inst];
   const size_t fb = (size_t)I.g.ncell * (h->precision == IBM_FP64 ? 8 : 4);
   if ((rc = materialize(h, I))) return rc;
@@ -976,8 +1040,37 @@ int ibm_step(ibm_handle h, int32_t nsteps) {
     if (!I.geom_ready) return fail(h, IBM_ERR_STATE, "ibm_step before ibm_set_geometry");
   bool masked = false;
   for (Instance& I : h->inst) masked = masked || I.d.projection == IBM_PROJ_MASKED;
+  // a masked solve synchronises in eager steps and a graph is built by a capture of the
+  // library's own: neither inside the caller's capture of the stream
+  if (masked || h->use_graph) {
+    const int rc = refuse_capture(h);
+    if (rc) return rc;
+  }
   const bool batched = h->use_batch && h->inst.size() > 1 && !h->diag && !h->prof && !masked;
-  if (h->use_graph && !h->diag && !h->prof && !masked && nsteps > 0) {
+  if (h->use_graph && !h->diag && !h->prof && masked && nsteps > 0) {
+    // a masked instance's iteration budget in the graph comes from its eager solves: a
+    // first step runs eagerly when none has been made yet; the graph is rebuilt when a
+    // budget changes
+    bool need = false;
+    for (Instance& I : h->inst) need = need || (I.d.projection == IBM_PROJ_MASKED && !I.pcg_seen);
+    if (need) {
+      for (Instance& I : h->inst) {
+        const int rc = (h->precision == IBM_FP64) ? run_steps<double>(h, I, 1, h->stream)
+                                                  : run_steps<float>(h, I, 1, h->stream);
+        if (rc) return rc;
+      }
+      if (--nsteps == 0) return IBM_OK;
+    }
+    for (Instance& I : h->inst) {
+      if (I.d.projection != IBM_PROJ_MASKED) continue;
+      const int b = pcg_capture_budget(I);
+      if (b != I.pcg_budget) {
+        I.pcg_budget = b;
+        drop_graph(h);
+      }
+    }
+  }
+  if (h->use_graph && !h->diag && !h->prof && nsteps > 0) {
     if (!h->gexec || (batched && !batch_current(h))) {
       const int rc = (h->precision == IBM_FP64) ? build_graph<double>(h) : build_graph<float>(h);
       if (rc) return rc;
@@ -1016,12 +1109,12 @@ int ibm_solve_pressure(ibm_handle h, int32_t inst, const void* rhs, void* phi) {
     Fields<double> f = fields_of<double>(I);
     RUNK(h, K_DIV_FFTX, launch_div_fftx<double>(I.g, f, I.L, 0, I.px, I.rtw, 1.0, I.pi(), (const double*)rhs,
                                                  h->stream));
-    return poisson<double>(h, I, f, (double*)phi, h->stream);
+    return poisson<double>(h, I, I.g, f, (double*)phi, h->stream);
   }
   Fields<float> f = fields_of<float>(I);
   RUNK(h, K_DIV_FFTX, launch_div_fftx<float>(I.g, f, I.L, 0, I.px, I.rtw, 1.0, I.pi(), (const float*)rhs,
                                               h->stream));
-  return poisson<float>(h, I, f, (float*)phi, h->stream);
+  return poisson<float>(h, I, I.g, f, (float*)phi, h->stream);
 }
 
 int ibm_set_diagnostics(ibm_handle h, int32_t on) {
@@ -1036,12 +1129,13 @@ int ibm_set_wall_velocity(ibm_handle h, int32_t inst, double ub, double vb, doub
   if (rc) return rc;
   if (!std::isfinite(ub) || !std::isfinite(vb) || !std::isfinite(wb))
     return fail(h, IBM_ERR_ARG, "wall velocity must be finite");
+  if ((rc = refuse_capture(h))) return rc;
   Instance& I = h->inst[inst];
   // a pending projection is applied with the walls' previous velocity at external faces
   if ((rc = materialize(h, I))) return rc;
   const double v[3] = {ub, vb, wb};
   HIPCHK(h, hipMemcpyAsync(I.wallv(), v, sizeof(v), hipMemcpyHostToDevice, h->stream));
-  HIPCHK(h, hipStreamSynchronize(h->stream));
+  SYNCHK(h, h->stream);
   I.wall_vel[0] = ub;
   I.wall_vel[1] = vb;
   I.wall_vel[2] = wb;
@@ -1056,6 +1150,7 @@ int ibm_set_y_faces(ibm_handle h, int32_t inst, const double* y_faces) {
   int rc = check_inst(h, inst);
   if (rc) return rc;
   if (!y_faces) return fail(h, IBM_ERR_ARG, "null y_faces");
+  if ((rc = refuse_capture(h))) return rc;
   Instance& I = h->inst[inst];
   if (I.d.projection == IBM_PROJ_MASKED)
     return fail(h, IBM_ERR_ARG, "the masked projection needs a uniform wall-normal grid");
@@ -1072,7 +1167,7 @@ int ibm_set_y_faces(ibm_handle h, int32_t inst, const double* y_faces) {
   const std::vector<double> tab = y_tables(y_faces, I.g.ny1);
   HIPCHK(h, hipMemcpyAsync((void*)I.g.ytab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice,
                            h->stream));
-  HIPCHK(h, hipStreamSynchronize(h->stream));
+  SYNCHK(h, h->stream);
   I.g.stretched = 1;
   // lambda, sigma, the wall distances and S_k depend on the spacing: a geometry is needed
   I.geom_ready = false;
@@ -1084,6 +1179,7 @@ int ibm_wall_shear(ibm_handle h, int32_t inst, double* tau_x, double* modes) {
   if (rc) return rc;
   Instance& I = h->inst[inst];
   if (!I.geom_ready) return fail(h, IBM_ERR_STATE, "ibm_wall_shear before ibm_set_geometry");
+  if (modes && (rc = refuse_capture(h))) return rc;
   if ((rc = materialize(h, I))) return rc;
   const GridParams& g = I.g;
   double* tx = tau_x ? tau_x : I.wall_tau;
@@ -1097,7 +1193,7 @@ int ibm_wall_shear(ibm_handle h, int32_t inst, double* tau_x, double* modes) {
   }
   if (modes) {
     HIPCHK(h, hipMemcpyAsync(modes, md, 3 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(h, hipStreamSynchronize(h->stream));
+    SYNCHK(h, h->stream);
   }
   return IBM_OK;
 }
@@ -1106,6 +1202,7 @@ int ibm_stats(ibm_handle h, int32_t inst, ibm_stats_t* out) {
   int rc = check_inst(h, inst);
   if (rc) return rc;
   if (!out) return fail(h, IBM_ERR_ARG, "null output");
+  if ((rc = refuse_capture(h))) return rc;
   Instance& I = h->inst[inst];
   const GridParams& g = I.g;
   if ((rc = materialize(h, I))) return rc;
@@ -1118,7 +1215,15 @@ int ibm_stats(ibm_handle h, int32_t inst, ibm_stats_t* out) {
   RUNK(h, K_STATS, launch_reduce_final(I.red_part, np, 3, 3, I.red_out(), h->stream));
   double host[32];
   HIPCHK(h, hipMemcpyAsync(host, I.small, sizeof(host), hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(h, hipStreamSynchronize(h->stream));
+  // the masked solve's device status: converged flag, iterations, |r|^2
+  int32_t pstat[PCG_NSTAT] = {1, 0, 0, 0};
+  double prr = 0.0;
+  const bool masked = I.d.projection == IBM_PROJ_MASKED;
+  if (masked) {
+    HIPCHK(h, hipMemcpyAsync(pstat, I.pcg_stat, sizeof(pstat), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(&prr, I.pcg_stat + PCG_NSTAT, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  }
+  SYNCHK(h, h->stream);
   const double* ro = host + 7;
   const double* dg = host + 15;
   memset(out, 0, sizeof(*out));
@@ -1131,10 +1236,13 @@ int ibm_stats(ibm_handle h, int32_t inst, ibm_stats_t* out) {
   out->cfl_max = ro[3];
   out->div_max_internal_leak = ro[4];
   out->rhs_mean_removed = host[6];
-  if (I.d.projection == IBM_PROJ_MASKED) {
+  if (masked) {
+    // |b|^2 of the last solve is in pcg_sc()[2] = small[22]
+    const double bb = host[22];
     out->div_max_fullbox = -1.0;
-    out->poisson_rel_residual = I.step > 0 ? I.pcg_res : -1.0;
-    out->pcg_iters = I.pcg_iters;
+    out->poisson_rel_residual = I.step > 0 ? (bb > 0.0 ? std::sqrt(prr / bb) : 0.0) : -1.0;
+    out->pcg_iters = pstat[PCG_ITERS];
+    if (pstat[PCG_DONE]) I.pcg_iters_max = std::max(I.pcg_iters_max, (int)pstat[PCG_ITERS]);
   } else if (I.diag_valid) {
     out->div_max_fullbox = dg[0];
     out->poisson_rel_residual = dg[2] > 0.0 ? dg[1] / dg[2] : 0.0;
@@ -1148,6 +1256,11 @@ int ibm_stats(ibm_handle h, int32_t inst, ibm_stats_t* out) {
   }
   out->n_p_internal = I.n_pint;
   if (out->nan_flag) return fail(h, IBM_ERR_UNSTABLE, "NaN/Inf in the state");
+  if (masked && I.step > 0 && !pstat[PCG_DONE])
+    return fail(h, IBM_ERR_UNSTABLE,
+                I.pcg_budget > 0 ? "masked projection did not converge within the iterations captured (" +
+                                       std::to_string(I.pcg_budget) + " per solve)"
+                                 : std::string("masked projection did not converge"));
   if (out->cfl_max > std::sqrt(3.0)) return fail(h, IBM_ERR_UNSTABLE, "CFL above sqrt(3)");
   return IBM_OK;
 }
@@ -1157,8 +1270,9 @@ int ibm_get_geometry(ibm_handle h, int32_t inst, uint8_t* tags, int64_t* n_ibm3)
   if (rc) return rc;
   Instance& I = h->inst[inst];
   if (!I.geom_ready) return fail(h, IBM_ERR_STATE, "no geometry");
+  if ((rc = refuse_capture(h))) return rc;
   if (tags) HIPCHK(h, hipMemcpyAsync(tags, I.tag, (size_t)I.g.ncell, hipMemcpyDeviceToDevice, h->stream));
-  HIPCHK(h, hipStreamSynchronize(h->stream));
+  SYNCHK(h, h->stream);
   if (n_ibm3)
     for (int q = 0; q < 3; ++q) n_ibm3[q] = I.n_ibm[q];
   return IBM_OK;
@@ -1169,6 +1283,7 @@ int ibm_get_ibm_list(ibm_handle h, int32_t inst, int32_t comp, int32_t* idx, dou
   if (rc) return rc;
   Instance& I = h->inst[inst];
   if (!I.geom_ready) return fail(h, IBM_ERR_STATE, "no geometry");
+  if ((rc = refuse_capture(h))) return rc;
   if (comp < 0 || comp > 2) return fail(h, IBM_ERR_ARG, "comp must be 0, 1 or 2");
   const int64_t off = (comp >= 1 ? I.n_ibm[0] : 0) + (comp >= 2 ? I.n_ibm[1] : 0);
   const int64_t n = I.n_ibm[comp];
@@ -1183,7 +1298,7 @@ int ibm_get_ibm_list(ibm_handle h, int32_t inst, int32_t comp, int32_t* idx, dou
         HIPCHK(h, hipMemcpyAsync(coef + (size_t)k * n * 2, (double2*)I.ibm_coef.p + k * ntot + off, n * 16,
                                  hipMemcpyDeviceToDevice, h->stream));
   }
-  HIPCHK(h, hipStreamSynchronize(h->stream));
+  SYNCHK(h, h->stream);
   return IBM_OK;
 }
 
@@ -1340,7 +1455,7 @@ int autotune_impl(ibm_ctx* c, Instance& I, int steps, int32_t* chosen) {
     if (hipMemcpyAsync(fld[q], save[q], fb, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
       rc = fail(c, IBM_ERR_DEVICE, "autotune restore");
   if (!rc) rc = seed_pending(c, I);
-  if (!rc && hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(c, IBM_ERR_DEVICE, "autotune sync");
+  if (!rc) rc = sync_stream(c, c->stream);
   I.step = step0;
   I.time = time0;
   I.diag_valid = false;
@@ -1449,7 +1564,7 @@ int autotune_ensemble(ibm_ctx* c, int steps, int32_t* chosen) {
     chosen[2] = c->inst[0].tu.tri_rows;
   }
   if (!rc) rc = restore();
-  if (!rc && hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(c, IBM_ERR_DEVICE, "autotune sync");
+  if (!rc) rc = sync_stream(c, c->stream);
   drop_graph(c);
   cleanup();
   return rc;
@@ -1462,6 +1577,8 @@ extern "C" {
 int ibm_autotune(ibm_handle h, int32_t steps_per_trial, int32_t* chosen) {
   if (!h) return fail(nullptr, IBM_ERR_ARG, "null handle");
   if (steps_per_trial < 1) return fail(h, IBM_ERR_ARG, "steps_per_trial must be >= 1");
+  int rc0 = refuse_capture(h);
+  if (rc0) return rc0;
   drop_graph(h);
   for (Instance& I : h->inst)
     if (!I.geom_ready) return fail(h, IBM_ERR_STATE, "autotune before ibm_set_geometry");
@@ -1495,7 +1612,7 @@ int ibm_profile(ibm_handle h, int32_t on) {
 
 int ibm_profile_read(ibm_handle h, double* total_ms, int64_t* launches, int32_t max) {
   if (!h) return fail(nullptr, IBM_ERR_ARG, "null handle");
-  HIPCHK(h, hipStreamSynchronize(h->stream));
+  SYNCHK(h, h->stream);
   for (size_t e = 0; e + 1 < h->ev_used; e += 2) {
     float ms = 0.f;
     HIPCHK(h, hipEventElapsedTime(&ms, h->ev[e], h->ev[e + 1]));

@@ -51,6 +51,9 @@ struct GridParams {
   int stretched;
   int ystr;
   const double* ytab;
+  // when set and *skip != 0, the projection kernels (x, z transforms, tridiagonal solve)
+  // and the conjugate-gradient kernels return at once: the masked solve has converged
+  const int* skip;
 };
 
 // Per-row tables of a stretched wall-normal grid (rows j = 0..ny1-1; entry ny1 is padding).
@@ -107,6 +110,7 @@ inline void grid_params_uniform(int nx, int ny, int nz, double lx, double lz, do
   g.stretched = 0;
   g.ystr = g.ny1 + 1;
   g.ytab = nullptr;
+  g.skip = nullptr;
 }
 
 // Factors of an FFT length into radix-8/4/2/3/5 stages (host): false if n has another
@@ -417,6 +421,18 @@ hipError_t launch_geom_south_wall(const GridParams& g, const double* su, int ibm
 // slots of PCG_NPART doubles each
 constexpr int PCG_NPART = 1024;
 enum { PCG_B = 0, PCG_R2, PCG_X, PCG_RZ, PCG_PAP, PCG_RS, PCG_NSLOT };
+// Device status of the last masked solve (int32 slots): converged flag, iterations, and
+// the iteration budget it ran under (0: unbounded eager solve); its final |r|^2 is kept
+// as a double in the status's second half.
+enum { PCG_DONE = 0, PCG_ITERS, PCG_BUDGET, PCG_NSTAT = 4 };
+// sc[3] <- mean[0], the converged flag cleared (a kernel: the solve may be captured)
+hipError_t launch_pcg_prep(const double* mean, double* sc, int32_t* stat, hipStream_t st);
+// convergence test after `it` iterations: sums the |r|^2 partials; unless already
+// converged, records it and |r|^2 and sets the flag when |r|^2 <= tol2 |b|^2
+hipError_t launch_pcg_check(const GridParams& g, const double* part, const double* sc, double tol2, int it,
+                            int32_t* stat, double* rr_out, hipStream_t st);
+// mean[0] <- sc[3] (the removed mean restored for the diagnostics)
+hipError_t launch_pcg_post(double* mean, const double* sc, hipStream_t st);
 int pcg_blocks(const GridParams& g);
 hipError_t launch_pcg_init(const GridParams& g, const uint8_t* tag, const double* x, const double* mean, double* r,
                            double* part, int64_t n_internal, hipStream_t st);

@@ -118,6 +118,7 @@ __global__ __launch_bounds__(PT) void k_pcg_center(GridParams g, const uint8_t* 
 // partials of r . z (r is zero outside the internal cells)
 __global__ __launch_bounds__(PT) void k_pcg_rz(GridParams g, const double* __restrict__ r,
                                               const double* __restrict__ z, double* __restrict__ part) {
+  if (g.skip && *g.skip) return;
   __shared__ double smem[8];
   double a = 0.0;
   for (int c = blockIdx.x * PT + threadIdx.x; c < g.ncell; c += gridDim.x * PT) a += r[c] * z[c];
@@ -130,6 +131,7 @@ __global__ __launch_bounds__(PT) void k_pcg_dir(GridParams g, const uint8_t* __r
                                                const double* __restrict__ z, double* __restrict__ p,
                                                const double* __restrict__ prz, int nb, double* __restrict__ sc,
                                                int it) {
+  if (g.skip && *g.skip) return;
   __shared__ double smem[8];
   const double rho = sum_partials(prz, nb, smem);
   const double rho_prev = it > 0 ? sc[(it + 1) & 1] : 0.0;
@@ -146,6 +148,7 @@ __global__ __launch_bounds__(PT) void k_pcg_dir(GridParams g, const uint8_t* __r
 __global__ __launch_bounds__(PT) void k_pcg_apply(GridParams g, const uint8_t* __restrict__ tag,
                                                  const double* __restrict__ p, double* __restrict__ ap,
                                                  double* __restrict__ part) {
+  if (g.skip && *g.skip) return;
   __shared__ double smem[8];
   double a = 0.0;
   const int stride = gridDim.x * PT;
@@ -177,6 +180,7 @@ __global__ __launch_bounds__(PT) void k_pcg_step(GridParams g, const uint8_t* __
                                                 const double* __restrict__ ppap, int nb,
                                                 const double* __restrict__ sc, int it, double* __restrict__ pr,
                                                 double* __restrict__ px) {
+  if (g.skip && *g.skip) return;
   __shared__ double smem[8];
   const double pap = sum_partials(ppap, nb, smem);
   const double alpha = pap != 0.0 ? sc[it & 1] / pap : 0.0;
@@ -200,6 +204,37 @@ __global__ __launch_bounds__(PT) void k_pcg_total(const double* __restrict__ par
   __shared__ double smem[8];
   const double s = sum_partials(part, nb, smem);
   if (threadIdx.x == 0) out[0] = s;
+}
+
+// sc[3] <- mean[0]; converged flag cleared (one thread)
+__global__ void k_pcg_prep(const double* __restrict__ mean, double* __restrict__ sc, int32_t* __restrict__ stat) {
+  if (threadIdx.x == 0) {
+    sc[3] = mean[0];
+    stat[PCG_DONE] = 0;
+    stat[PCG_ITERS] = 0;
+  }
+}
+
+// Convergence test after `it` iterations (one block): |r|^2 from the partials of the last
+// update; unless the solve has already converged, `it` and |r|^2 are recorded and the
+// flag set once |r|^2 <= tol2 |b|^2 (|b|^2 in sc[2]).  Every later kernel of the solve
+// then returns at once, so the iterate stops exactly at convergence.
+__global__ __launch_bounds__(PT) void k_pcg_check(const double* __restrict__ part, int nb,
+                                                 const double* __restrict__ sc, double tol2, int it,
+                                                 int32_t* __restrict__ stat, double* __restrict__ rr_out) {
+  __shared__ double smem[8];
+  if (stat[PCG_DONE]) return;
+  const double rr = sum_partials(part, nb, smem);
+  if (threadIdx.x == 0) {
+    stat[PCG_ITERS] = it;
+    rr_out[0] = rr;
+    if (rr <= tol2 * sc[2]) stat[PCG_DONE] = 1;
+  }
+}
+
+// mean[0] <- sc[3]
+__global__ void k_pcg_post(double* __restrict__ mean, const double* __restrict__ sc) {
+  if (threadIdx.x == 0) mean[0] = sc[3];
 }
 
 // gauge: phi = x - mean of x over the internal cells there, 0 elsewhere
@@ -257,6 +292,23 @@ hipError_t launch_pcg_step(const GridParams& g, const uint8_t* tag, double* x, d
 
 hipError_t launch_pcg_total(const GridParams& g, const double* part, int slot, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_pcg_total, dim3(1), dim3(PT), 0, st, part + slot * PCG_NPART, pcg_blocks(g), out);
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_prep(const double* mean, double* sc, int32_t* stat, hipStream_t st) {
+  hipLaunchKernelGGL(k_pcg_prep, dim3(1), dim3(64), 0, st, mean, sc, stat);
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_check(const GridParams& g, const double* part, const double* sc, double tol2, int it,
+                            int32_t* stat, double* rr_out, hipStream_t st) {
+  hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(PT), 0, st, part + PCG_R2 * PCG_NPART, pcg_blocks(g), sc, tol2, it,
+                     stat, rr_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_post(double* mean, const double* sc, hipStream_t st) {
+  hipLaunchKernelGGL(k_pcg_post, dim3(1), dim3(64), 0, st, mean, sc);
   return hipGetLastError();
 }
 

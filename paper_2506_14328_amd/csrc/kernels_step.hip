@@ -525,6 +525,7 @@ __device__ __forceinline__ void k_div_fftx_body(GridParams g, Fields<T> f, IbmLi
                                                  const double2* __restrict__ rtw, double ck_dt,
                                                  const double* __restrict__ pi, const T* __restrict__ rhs_in, int ll,
                                                  int bid_x, int bid_y, int nblk) {
+  if (g.skip && *g.skip) return;   // a converged masked solve: nothing left to do
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* sm = reinterpret_cast<cplx<T>*>(smem_raw);
   const int N = g.nhalf;
@@ -618,6 +619,7 @@ __global__ __launch_bounds__(256) void k_div_fftx_b(const DivArgs<T>* __restrict
 template <typename T, int MB, int RP>
 __device__ __forceinline__ void k_fftz_body(GridParams g, cplx<T>* __restrict__ spec, FFTPlan pz, int sign,
                                              int W, int NJ, int b) {
+  if (g.skip && *g.skip) return;   // a converged masked solve: nothing left to do
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem_raw);
   const int nz = g.nz, mh = g.mh, mhs = g.mhs;
@@ -751,6 +753,7 @@ template <typename T, int LM, bool SY>
 __device__ __forceinline__ void k_tri_body(GridParams g, cplx<T>* __restrict__ spec,
                                             const double* __restrict__ kx2, const double* __restrict__ kz2,
                                             int P, int W, double* __restrict__ mean_out, int bid_x, int bid_y, int nblk) {
+  if (g.skip && *g.skip) return;   // a converged masked solve: nothing left to do
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* lds = reinterpret_cast<double*>(smem_raw);
   const int n = g.ny1;
@@ -1004,6 +1007,7 @@ __global__ __launch_bounds__(256) void k_tri_b(const TriArgs<T>* __restrict__ ar
 template <typename T, int MB>
 __device__ __forceinline__ void k_ifftx_body(GridParams g, const cplx<T>* __restrict__ spec, T* __restrict__ out,
                                               FFTPlan px, const double2* __restrict__ rtw, int ll, int bid_x, int bid_y, int nblk) {
+  if (g.skip && *g.skip) return;   // a converged masked solve: nothing left to do
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* sm = reinterpret_cast<cplx<T>*>(smem_raw);
   const int N = g.nhalf;

@@ -39,9 +39,51 @@ def test_masked_step_parity(name, nsteps):
          f"u,v,w {['%.1e' % e for e in errs]} p {ep:.1e}; internal divergence * h / U {leak:.1e}")
     assert s["pcg_iters"] > 0 or name == "flat_small"
     assert 0.0 <= s["poisson_rel_residual"] <= 1e-13
-    assert max(errs) < 1e-11
-    assert ep < 1e-10
+    # the velocity to the 1e-12 FP64 target; the pressure, a sum of increments each solved
+    # to the residual tolerance 1e-13, against its dynamic scale U^2 as in the other steps
+    assert max(errs) <= 1e-12
+    assert ep <= 1e-10
     assert leak < 1e-12
+    g.close()
+
+
+@pytest.mark.parametrize("name", ["open_small", "wavy_small"])
+def test_masked_graph_equals_eager(name):
+    """The masked projection inside a captured graph (fixed iteration budget, convergence
+    tested on the device, no host access) gives bit for bit the eager result: the device
+    flag stops the iterate at the same iteration in both."""
+    c = case(name, projection=1)
+    sdf = I.make_sdf(c)
+    u0, v0, w0 = I.make_initial(c, sdf)
+    st = (u0, v0, w0, np.zeros_like(u0))
+    out = []
+    for graph in (0, 1):
+        g = gpu_grid(c, sdf, st)
+        g.tune(graph=graph)
+        g.step(4)
+        s = g.stats()
+        out.append(([t.cpu().numpy() for t in g.get_state()], s["pcg_iters"], s["poisson_rel_residual"]))
+        g.close()
+    _say(f"{name}: iterations eager {out[0][1]} graph {out[1][1]}, residual {out[1][2]:.1e}")
+    assert out[0][1] == out[1][1] and out[1][1] > 0
+    assert out[1][2] <= 1e-13
+    for a, b in zip(out[0][0], out[1][0]):
+        assert np.array_equal(a, b)
+
+
+def test_masked_iteration_cap_is_reported():
+    """A solve that reaches pcg_max_iter without converging (the device flag unset) makes
+    ibm_step return IBM_ERR_UNSTABLE, also with the graph requested (its first step is
+    eager)."""
+    from paper_2506_14328_amd.ibm import IbmError
+    import dataclasses
+    c = dataclasses.replace(case("wavy_small", projection=1), pcg_max_iter=8)
+    sdf = I.make_sdf(c)
+    u0, v0, w0 = I.make_initial(c, sdf)
+    g = gpu_grid(c, sdf, (u0, v0, w0, np.zeros_like(u0)))
+    g.tune(graph=1)
+    with pytest.raises(IbmError):
+        g.step(3)          # the first, eager step stops at pcg_max_iter and reports it
     g.close()
 
 

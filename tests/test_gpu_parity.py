@@ -404,3 +404,37 @@ def test_geometry_changing_every_step():
         assert max(errs) < 1e-12
         assert g.device_bytes() <= bytes0 + 64 * 1024 * 1024
     g.close()
+
+
+def test_synchronising_calls_refused_inside_a_capture():
+    """While the caller captures the library's stream into a HIP graph, the entry points
+    that synchronise (ibm_stats, ibm_get_state) return IBM_ERR_STATE before enqueuing
+    anything, and the grid works normally once the capture has ended."""
+    import ctypes
+    from paper_2506_14328_amd.ibm import IBM_ERR_STATE, IbmError
+    c = case("wavy_small")
+    sdf = I.make_sdf(c)
+    u0, v0, w0 = I.make_initial(c, sdf)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        g = gpu_grid(c, sdf, (u0, v0, w0, np.zeros_like(u0)))
+    s.synchronize()
+    hip = ctypes.CDLL("libamdhip64.so")
+    graph = ctypes.c_void_p()
+    assert hip.hipStreamBeginCapture(ctypes.c_void_p(s.cuda_stream), 1) == 0   # thread-local mode
+    try:
+        with pytest.raises(IbmError) as e1:
+            g.stats()
+        with pytest.raises(IbmError) as e2:
+            g.get_state()
+    finally:
+        rc = hip.hipStreamEndCapture(ctypes.c_void_p(s.cuda_stream), ctypes.byref(graph))
+        if graph.value:
+            hip.hipGraphDestroy(graph)
+    assert rc == 0
+    assert e1.value.code == IBM_ERR_STATE and e2.value.code == IBM_ERR_STATE
+    with torch.cuda.stream(s):
+        g.step(1)
+        st = g.stats()
+    assert st["step"] == 1 and st["nan_flag"] == 0
+    g.close()
