@@ -314,6 +314,50 @@ def measure_masked(steps=20, warmup=2):
     return out
 
 
+def measure_moving_geometry(steps=50):
+    """The 192x129x96 wavy channel whose wall translates along x (two positions half a
+    cell apart, alternated): the cost of replacing the geometry before every step
+    (ibm_set_geometry: tags, wall distances, lists and coefficients, S_k, all on the stream
+    with no host read-back), with the library's graph replaying the steps, against the
+    same steps with the geometry fixed.  FP64."""
+    import numpy as np
+    import torch
+    import ibm_inputs as I
+    c, sdf, st = build_inputs("wavy")
+    g = make_grid(c, sdf, st, "fp64")
+    g.autotune(2)
+    g.tune(graph=1)
+    # the wall moved by half a cell: sample the same wall at x - dx/2
+    k = 2.0 * math.pi / c.geo_params[1]
+    amp = c.geo_params[0]
+
+    def wall(X, Y, Z):
+        yw = -1.0 + amp * np.sin(k * (X - 0.5 * c.dx))
+        dyw = amp * k * np.cos(k * (X - 0.5 * c.dx))
+        return np.minimum((Y - yw) / np.sqrt(1.0 + dyw * dyw), 1.0 - Y)
+    shifted = I._sample(c, wall)
+    pos = [[torch.as_tensor(a).to("cuda") for a in sdf], [torch.as_tensor(a).to("cuda") for a in shifted]]
+    g.set_geometry(*pos[1])
+    g.set_geometry(*pos[0])
+    g.step(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.step(steps)
+    torch.cuda.synchronize()
+    t_fixed = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for n in range(steps):
+        g.set_geometry(*pos[(n + 1) % 2])
+        g.step(1)
+    torch.cuda.synchronize()
+    t_moving = time.perf_counter() - t0
+    s = g.stats()
+    g.close()
+    return {"workload": "wavy_192x129x96_translating_wall", "precision": "fp64", "graph": True,
+            "ms_per_step_fixed_geometry": t_fixed / steps * 1e3, "ms_per_step_moving_geometry": t_moving / steps * 1e3,
+            "geometry_update_ms": (t_moving - t_fixed) / steps * 1e3, "nan_flag": s["nan_flag"]}
+
+
 def measure_shard_shapes(steps=20, warmup=3):
     """One GPU's share of the 512 x 257 x 256 channel split over 8 GPUs: the 512 x 257 x 32
     z-slab that the stencil kernels would see, and a 64 x 257 x 256 grid whose 33 x-modes
@@ -538,6 +582,7 @@ def main():
                           ibm_point_fraction=round(rs["ibm_fraction"], 4)))
         del sdf_s, us_, vs_, ws_
         forms.append(measure_masked())
+        forms.append(measure_moving_geometry())
         forms.extend(measure_shard_shapes())
         forms.append(measure_ensemble())
         out["forms"] = forms

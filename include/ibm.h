@@ -14,8 +14,11 @@
  *   library copies what it keeps and never frees caller memory.  Internal
  *   fields live in device memory the library allocates at create time.
  * Stream: all work is enqueued on the hipStream_t given at create, in stream
- *   order.  Only ibm_stats(), ibm_get_geometry()/ibm_get_ibm_list(),
- *   ibm_profile_read() and ibm_set_geometry() synchronise that stream.
+ *   order.  Only ibm_stats(), ibm_get_state(), ibm_get_geometry()/ibm_get_ibm_list(),
+ *   ibm_profile_read(), ibm_autotune(), ibm_set_wall_velocity(), ibm_set_y_faces(),
+ *   ibm_wall_shear() with modes, eager steps of a masked projection and the first
+ *   ibm_set_geometry() of an instance synchronise that stream; while the caller captures
+ *   the stream into a graph they return IBM_ERR_STATE before enqueuing anything.
  * Precision: fixed at create.  IBM_FP64 stores and computes everything in
  *   double.  IBM_FP32_STORAGE stores velocity, pressure and spectra as float
  *   and evaluates stencils and FFTs in float; the wall-normal tridiagonal
@@ -153,8 +156,17 @@ int ibm_create_grid(const ibm_grid_desc* desc, int32_t n_inst, int32_t precision
  * the arms whose neighbour is external, delta being the linear zero crossing
  * of s along the arm (or the box wall when nearer); per RK stage k,
  * x = lambda c_k dt, B(x) per b_mode, A = x + B.  sdf_* are FP64 device
- * arrays in the SDF layout above; they may be freed on return.  Returns
- * IBM_ERR_ARG if no pressure cell is internal.  Synchronises the stream. */
+ * arrays in the SDF layout above, read in stream order (they may be freed or refilled
+ * once the work enqueued so far has run).  The first geometry of an instance reads the
+ * point counts back, sizes the immersed-boundary lists with room to spare (the counts
+ * plus a quarter, at least 1024 more per component), synchronises the stream, and returns
+ * IBM_ERR_ARG if no pressure cell is internal.  A later geometry (a moving body) runs on
+ * the stream only: no host read-back, no allocation, no memset, no synchronisation, the
+ * library's captured graph kept, so that a caller may also capture it, with ibm_step,
+ * into a graph of its own (host-side step counters then advance at capture only); its
+ * counts reach the host at the next ibm_stats, which returns IBM_ERR_STATE if it left no
+ * fluid or had more points than the lists hold (the next ibm_set_geometry then resizes
+ * them, synchronously). */
 int ibm_set_geometry(ibm_handle h, int32_t inst, const double* sdf_u, const double* sdf_v,
                      const double* sdf_w);
 

@@ -33,7 +33,6 @@ struct Instance {
   void* P[3] = {};
   int cur = 0;
   bool fresh = true;       // u, v, w, p hold the state as set (no step since ibm_set_state)
-  bool mat_valid = true;   // u, v, w, p hold the current state
   void *Hu = nullptr, *Hv = nullptr, *Hw = nullptr, *phi = nullptr, *spec = nullptr;
   uint8_t* tag = nullptr;
   double* qpart = nullptr;
@@ -61,6 +60,9 @@ struct Instance {
   IbmLists L{};
   Tuning tu{};
   int64_t n_int[3] = {0, 0, 0}, n_ibm[3] = {0, 0, 0}, n_pint = 0;
+  int cap[3] = {0, 0, 0};        // immersed-boundary list capacities per component
+  bool counts_fresh = true;      // the host counts match the device's
+  bool lists_overflowed = false; // a geometry had more points than the capacities
   bool geom_ready = false;
   bool diag_valid = false;
   int64_t step = 0;
@@ -464,7 +466,7 @@ int pcg_project(ibm_ctx* c, Instance& I, Fields<double>& f, hipStream_t st, bool
   const int max_iter = I.d.pcg_max_iter > 0 ? I.d.pcg_max_iter : 500;
   const int budget = capture ? I.pcg_budget : max_iter;
   RUNK(c, K_PCG, launch_pcg_prep(I.mean(), sc, I.pcg_stat, st));
-  RUNK(c, K_PCG, launch_pcg_init(g0, I.tag, x, sc + 3, r, part, I.n_pint, st));
+  RUNK(c, K_PCG, launch_pcg_init(g0, I.tag, x, sc + 3, r, part, I.itotal + 3, st));
   RUNK(c, K_PCG, launch_pcg_total(g0, part, PCG_B, sc + 2, st));
   RUNK(c, K_PCG, launch_pcg_check(g0, part, sc, tol * tol, 0, I.pcg_stat, rr_dev, st));
   for (int it = 0; it < budget; ++it) {
@@ -483,7 +485,7 @@ int pcg_project(ibm_ctx* c, Instance& I, Fields<double>& f, hipStream_t st, bool
     RUNK(c, K_PCG, launch_pcg_step(g, I.tag, x, r, p, ap, part, sc, it, st));
     RUNK(c, K_PCG, launch_pcg_check(g0, part, sc, tol * tol, it + 1, I.pcg_stat, rr_dev, st));
   }
-  RUNK(c, K_PCG, launch_pcg_finish(g0, I.tag, x, part, I.n_pint, st));
+  RUNK(c, K_PCG, launch_pcg_finish(g0, I.tag, x, part, I.itotal + 3, st));
   RUNK(c, K_PCG, launch_pcg_post(I.mean(), sc, st));
   if (capture) return IBM_OK;
   int32_t stat[PCG_NSTAT];
@@ -534,7 +536,6 @@ int run_steps(ibm_ctx* c, Instance& I, int nsteps, hipStream_t st, bool count = 
                                              st));
       I.cur = nxt;
       I.fresh = false;
-      I.mat_valid = false;
       Fields<T> f = fields_of<T>(I);
       RUNK(c, K_CFR_PI, launch_cfr_pi<T>(f, I.L, k, sc.ck_dt, I.qpart, nq, scale, I.d.forcing, I.d.q_target_or_pi,
                                          I.S3(), I.pi(), I.pi_hist(), st));
@@ -559,21 +560,16 @@ int run_steps(ibm_ctx* c, Instance& I, int nsteps, hipStream_t st, bool count = 
   return IBM_OK;
 }
 
-// Number of cells whose tag has `mask` set, into I.itotal[slot] (no synchronisation).
-int count_mask(ibm_ctx* c, Instance& I, uint8_t mask, int32_t* blk, int nblk, int slot) {
-  HIPCHK(c, launch_count_flags(I.tag, I.g.ncell, mask, blk, nblk, c->stream));
-  HIPCHK(c, launch_scan_counts(blk, nblk, I.itotal + slot, c->stream));
-  return IBM_OK;
-}
 
 // Writes the state (u, v, w, p) from the pending projection of the last substep.
 template <typename T>
 int materialize_t(ibm_ctx* c, Instance& I) {
-  if (I.fresh || I.mat_valid) return IBM_OK;
+  // (recomputed even when it was already written: the host cannot see replays of graphs
+  // the caller captured, after which the pending projection is newer than the state)
+  if (I.fresh) return IBM_OK;
   Fields<T> f = fields_of<T>(I);
   f.us = f.usp; f.vs = f.vsp; f.ws = f.wsp;   // the predictor awaiting its projection
   RUNK(c, K_CORRECT, launch_correct<T>(I.g, f, I.L, 2, rk_c(2) * I.g.dt, I.pi(), c->stream));
-  I.mat_valid = true;
   return IBM_OK;
 }
 
@@ -588,10 +584,10 @@ int seed_pending(ibm_ctx* c, Instance& I) {
   const void* src[4] = {I.u, I.v, I.w, I.p};
   void* dst[4] = {I.S[I.cur][0], I.S[I.cur][1], I.S[I.cur][2], I.P[I.cur]};
   for (int q = 0; q < 4; ++q) HIPCHK(c, hipMemcpyAsync(dst[q], src[q], fb, hipMemcpyDeviceToDevice, c->stream));
-  HIPCHK(c, hipMemsetAsync(I.phi, 0, fb, c->stream));
-  HIPCHK(c, hipMemsetAsync(I.pi(), 0, sizeof(double), c->stream));
+  // zeros by kernels, not memsets: a geometry update may be captured into a graph
+  HIPCHK(c, launch_fill_zero(I.phi, (int64_t)fb, c->stream));
+  HIPCHK(c, launch_fill_zero(I.pi(), (int64_t)sizeof(double), c->stream));
   I.fresh = true;
-  I.mat_valid = true;
   return IBM_OK;
 }
 
@@ -601,21 +597,38 @@ void free_buf(DevBuf& b) {
   b.bytes = 0;
 }
 
-int set_geometry_impl(ibm_ctx* c, Instance& I, const double* su, const double* sv, const double* sw) {
+// Geometry preprocessing (staircase tags, wall distances, immersed-boundary lists and
+// coefficients, S_k), all on the stream.  The first geometry of an instance (or the next
+// one after the lists overflowed) reads the point counts back, sizes the lists with room
+// to spare and synchronises; later ones run with no host synchronisation and no
+// allocation, the counts staying on the device (read by ibm_stats), so that a moving
+// body can be advanced between steps at the cost of a few kernels, also inside a graph
+// the caller captures.  *sized: whether the lists were (re)allocated.
+int set_geometry_impl(ibm_ctx* c, Instance& I, const double* su, const double* sv, const double* sw,
+                      bool* sized) {
   const GridParams& g = I.g;
   hipStream_t st = c->stream;
   const size_t nc = (size_t)g.ncell;
   const int nblk = (int)((nc + 255) / 256);
-  // dense lambda and wall-velocity coefficient per component and per-block counts:
-  // allocated at the first geometry of the instance and kept, so that a geometry that
-  // changes every step reallocates nothing of this size
-  const size_t tmp_bytes = 6 * nc * 8 + (size_t)(nblk + 1) * 4;
+  const int cpr = (g.nx + IBM_WAVE - 1) / IBM_WAVE;
+  const size_t nch = (size_t)g.nrows * cpr + 1;
+  *sized = false;
+  // dense lambda and wall-velocity coefficient per component and per-block counts of the
+  // seven tag masks: allocated at the first geometry of the instance and kept
+  const size_t tmp_bytes = 6 * nc * 8 + (size_t)(7 * nblk + 1) * 4;
   if (!I.geo_tmp.p) {
     if (hipMalloc(&I.geo_tmp.p, tmp_bytes) != hipSuccess) {
       I.geo_tmp.p = nullptr;
       return fail(c, IBM_ERR_OOM, "geometry temporaries");
     }
     I.geo_tmp.bytes = tmp_bytes;
+  }
+  if (!I.ibm_choff.p) {
+    if (hipMalloc(&I.ibm_choff.p, 3 * nch * 4) != hipSuccess) {
+      I.ibm_choff.p = nullptr;
+      return fail(c, IBM_ERR_OOM, "immersed-boundary chunk offsets");
+    }
+    I.ibm_choff.bytes = 3 * nch * 4;
   }
   double* lam_u = (double*)I.geo_tmp.p;
   double* lam_v = lam_u + nc;
@@ -624,6 +637,12 @@ int set_geometry_impl(ibm_ctx* c, Instance& I, const double* su, const double* s
   double* sig_v = sig_u + nc;
   double* sig_w = sig_v + nc;
   int32_t* blk = (int32_t*)(sig_w + nc);
+  // I.itotal: [0..6] counts of internal u, v, w, p and immersed-boundary u, v, w points,
+  // [8] the lists' overflow flag, [15] scratch total
+  int32_t* cnt7 = I.itotal;
+  int32_t* overflow = I.itotal + 8;
+  int32_t* scratch_total = I.itotal + 15;
+  const bool first = !I.ibm_idx.p || I.lists_overflowed;
   int rc = IBM_OK;
   do {
     hipError_t e = timed(c, K_GEOM, [&]() {
@@ -631,70 +650,62 @@ int set_geometry_impl(ibm_ctx* c, Instance& I, const double* su, const double* s
     });
     if (e == hipSuccess) e = launch_geom_ptag(g, I.tag, st);
     if (e == hipSuccess) e = launch_geom_south_wall(g, su, I.d.ibm, I.wall_j, I.wall_d, st);
+    // per-block counts of the seven masks, scanned in place (block offsets) with totals
+    const uint64_t masks = (uint64_t)TAG_U | ((uint64_t)TAG_V << 8) | ((uint64_t)TAG_W << 16) |
+                           ((uint64_t)TAG_P << 24) | ((uint64_t)TAG_UI << 32) | ((uint64_t)TAG_VI << 40) |
+                           ((uint64_t)TAG_WI << 48);
+    if (e == hipSuccess) e = launch_count_masks(I.tag, g.ncell, masks, 7, blk, nblk, st);
+    if (e == hipSuccess) e = launch_scan_multi(blk, nblk, nblk, 7, cnt7, st);
     if (e != hipSuccess) { rc = fail(c, IBM_ERR_DEVICE, std::string("geometry: ") + hipGetErrorString(e)); break; }
-    const uint8_t bmask[3] = {TAG_UI, TAG_VI, TAG_WI};
-    // internal u, v, w, p and IBM u, v, w counts, read back with one synchronisation
-    const uint8_t cmask[7] = {TAG_U, TAG_V, TAG_W, TAG_P, TAG_UI, TAG_VI, TAG_WI};
-    for (int q = 0; q < 7 && !rc; ++q) rc = count_mask(c, I, cmask[q], blk, nblk, q);
-    if (rc) break;
-    int32_t cnt[7];
-    e = hipMemcpyAsync(cnt, I.itotal, sizeof(cnt), hipMemcpyDeviceToHost, st);
-    if (e != hipSuccess) { rc = fail(c, IBM_ERR_DEVICE, std::string("geometry counts: ") + hipGetErrorString(e)); break; }
-    if ((rc = sync_stream(c, st))) break;
-    for (int q = 0; q < 3; ++q) {
-      I.n_int[q] = cnt[q];
-      I.n_ibm[q] = cnt[4 + q];
+    if (first) {
+      int32_t cnt[7];
+      e = hipMemcpyAsync(cnt, cnt7, sizeof(cnt), hipMemcpyDeviceToHost, st);
+      if (e != hipSuccess) { rc = fail(c, IBM_ERR_DEVICE, std::string("geometry counts: ") + hipGetErrorString(e)); break; }
+      if ((rc = sync_stream(c, st))) break;
+      for (int q = 0; q < 3; ++q) {
+        I.n_int[q] = cnt[q];
+        I.n_ibm[q] = cnt[4 + q];
+      }
+      I.n_pint = cnt[3];
+      if (I.n_pint == 0) { rc = fail(c, IBM_ERR_ARG, "geometry has no fluid"); break; }
+      // list capacities: the counts plus a quarter (at least 1024 more), at most one per cell
+      for (int q = 0; q < 3; ++q) {
+        const int64_t n = I.n_ibm[q];
+        I.cap[q] = (int)std::min<int64_t>((int64_t)nc, n + std::max<int64_t>(n / 4, 1024));
+      }
+      const int64_t ctot = (int64_t)I.cap[0] + I.cap[1] + I.cap[2];
+      free_buf(I.ibm_idx);
+      free_buf(I.ibm_coef);
+      free_buf(I.ibm_lam);
+      free_buf(I.ibm_sig);
+      if (hipMalloc(&I.ibm_idx.p, ctot * 4) != hipSuccess || hipMalloc(&I.ibm_coef.p, ctot * 3 * 16) != hipSuccess ||
+          hipMalloc(&I.ibm_lam.p, ctot * 8) != hipSuccess || hipMalloc(&I.ibm_sig.p, ctot * 8) != hipSuccess) {
+        rc = fail(c, IBM_ERR_OOM, "immersed-boundary lists");
+        break;
+      }
+      I.ibm_idx.bytes = ctot * 4;
+      I.ibm_coef.bytes = ctot * 48;
+      I.ibm_lam.bytes = ctot * 8;
+      I.ibm_sig.bytes = ctot * 8;
+      I.lists_overflowed = false;
+      I.counts_fresh = true;
+      *sized = true;
+    } else {
+      I.counts_fresh = false;   // the counts are on the device until the next ibm_stats
     }
-    I.n_pint = cnt[3];
-    if (I.n_pint == 0) { rc = fail(c, IBM_ERR_ARG, "geometry has no fluid"); break; }
-    const int64_t ntot = I.n_ibm[0] + I.n_ibm[1] + I.n_ibm[2];
-    free_buf(I.ibm_idx);
-    free_buf(I.ibm_coef);
-    free_buf(I.ibm_lam);
-    free_buf(I.ibm_sig);
-    free_buf(I.ibm_choff);
-    const int cpr = (g.nx + IBM_WAVE - 1) / IBM_WAVE;
-    const size_t nch = (size_t)g.nrows * cpr + 1;
-    if (hipMalloc(&I.ibm_choff.p, 3 * nch * 4) != hipSuccess) {
-      rc = fail(c, IBM_ERR_OOM, "immersed-boundary chunk offsets");
-      break;
-    }
-    I.ibm_choff.bytes = 3 * nch * 4;
-    const size_t nalloc = (size_t)std::max<int64_t>(ntot, 1);
-    if (hipMalloc(&I.ibm_idx.p, nalloc * 4) != hipSuccess || hipMalloc(&I.ibm_coef.p, nalloc * 3 * 16) != hipSuccess ||
-        hipMalloc(&I.ibm_lam.p, nalloc * 8) != hipSuccess || hipMalloc(&I.ibm_sig.p, nalloc * 8) != hipSuccess) {
-      rc = fail(c, IBM_ERR_OOM, "immersed-boundary lists");
-      break;
-    }
-    I.ibm_idx.bytes = nalloc * 4;
-    I.ibm_coef.bytes = nalloc * 48;
-    I.ibm_lam.bytes = nalloc * 8;
-    I.ibm_sig.bytes = nalloc * 8;
     int32_t* idx = (int32_t*)I.ibm_idx.p;
     double2* coef = (double2*)I.ibm_coef.p;
     double* lamo = (double*)I.ibm_lam.p;
     double* sigo = (double*)I.ibm_sig.p;
-    const double* lam_dense[3] = {lam_u, lam_v, lam_w};
-    const double* sig_dense[3] = {sig_u, sig_v, sig_w};
-    int64_t off = 0;
-    for (int q = 0; q < 3; ++q) {
-      // block offsets for this mask (scan), then compaction and coefficients
-      e = launch_count_flags(I.tag, g.ncell, bmask[q], blk, nblk, st);
-      if (e == hipSuccess) e = launch_scan_counts(blk, nblk, I.itotal, st);
-      if (e == hipSuccess) e = launch_compact(I.tag, g.ncell, bmask[q], blk, idx + off, nblk, st);
-      if (e == hipSuccess) e = launch_ibm_coef(idx, lam_dense[q], sig_dense[q], (int)I.n_ibm[q], I.d.dt, I.d.b_mode,
-                                               lamo, sigo, coef, (int)ntot, (int)off, st);
-      if (e != hipSuccess) { rc = fail(c, IBM_ERR_DEVICE, std::string("ibm lists: ") + hipGetErrorString(e)); break; }
-      off += I.n_ibm[q];
-    }
-    if (rc) break;
     int32_t* choff = (int32_t*)I.ibm_choff.p;
-    for (int q = 0; q < 3 && !rc; ++q) {
-      e = launch_chunk_counts(I.tag, g, bmask[q], cpr, choff + q * nch, st);
-      if (e == hipSuccess) e = launch_scan_counts(choff + q * nch, (int)nch, I.itotal, st);
-      if (e != hipSuccess) rc = fail(c, IBM_ERR_DEVICE, std::string("chunk offsets: ") + hipGetErrorString(e));
-    }
-    if (rc) break;
+    e = launch_clear_flag(overflow, st);
+    if (e == hipSuccess) e = launch_compact3(I.tag, g.ncell, blk + 4 * (size_t)nblk, nblk, idx, I.cap, overflow, st);
+    if (e == hipSuccess) e = launch_ibm_coef3(idx, lam_u, sig_u, g.ncell, cnt7 + 4, I.cap, I.d.dt, I.d.b_mode, lamo,
+                                              sigo, coef, st);
+    // per-(row, 64-wide chunk) list offsets of the three components
+    if (e == hipSuccess) e = launch_chunk_counts3(I.tag, g, cpr, choff, st);
+    if (e == hipSuccess) e = launch_scan_multi(choff, (int)nch, (int)nch, 3, scratch_total, st);
+    if (e != hipSuccess) { rc = fail(c, IBM_ERR_DEVICE, std::string("ibm lists: ") + hipGetErrorString(e)); break; }
     I.L.choff_u = choff;
     I.L.choff_v = choff + nch;
     I.L.choff_w = choff + 2 * nch;
@@ -704,20 +715,45 @@ int set_geometry_impl(ibm_ctx* c, Instance& I, const double* su, const double* s
     I.L.sig = sigo;
     I.L.wallv = I.wallv();
     I.L.sd = I.wall_sd();
-    I.L.n_cover = I.moving() ? (int)ntot : (int)I.n_ibm[0];
-    I.L.n_u = (int)I.n_ibm[0];
-    I.L.n_v = (int)I.n_ibm[1];
-    I.L.n_w = (int)I.n_ibm[2];
-    I.L.n_total = (int)ntot;
+    I.L.cnt = cnt7 + 4;
+    I.L.n_u = I.cap[0];
+    I.L.n_v = I.cap[1];
+    I.L.n_w = I.cap[2];
+    I.L.n_total = I.cap[0] + I.cap[1] + I.cap[2];
+    I.L.n_cover = I.moving() ? I.L.n_total : I.L.n_u;
     int np = 0;
     e = launch_s_k(g, I.tag, I.L, I.d.dt, I.red_part, &np, I.wall_sd(), st);
     if (e == hipSuccess) e = launch_s_k_final(I.red_part, np, I.d.dt * y_scale(g) * g.dz / g.nx, I.S3(), st);
     if (e != hipSuccess) { rc = fail(c, IBM_ERR_DEVICE, std::string("S_k: ") + hipGetErrorString(e)); break; }
-    if ((rc = sync_stream(c, st))) break;
+    if (first && (rc = sync_stream(c, st))) break;
     I.geom_ready = true;
     I.diag_valid = false;
   } while (0);
   return rc;
+}
+
+// Host copies of the point counts, refreshed from the device after geometries that ran
+// without a read-back (synchronises); IBM_ERR_STATE if such a geometry overflowed the lists
+// or left no fluid.
+int refresh_counts(ibm_ctx* c, Instance& I) {
+  if (I.counts_fresh || !I.geom_ready) return IBM_OK;
+  int32_t cnt[9];
+  HIPCHK(c, hipMemcpyAsync(cnt, I.itotal, sizeof(cnt), hipMemcpyDeviceToHost, c->stream));
+  SYNCHK(c, c->stream);
+  for (int q = 0; q < 3; ++q) {
+    I.n_int[q] = cnt[q];
+    I.n_ibm[q] = cnt[4 + q];
+  }
+  I.n_pint = cnt[3];
+  I.counts_fresh = true;
+  if (cnt[8]) {
+    I.lists_overflowed = true;
+    return fail(c, IBM_ERR_STATE,
+                "the geometry has more immersed-boundary points than the lists reserved at the first geometry; "
+                "give it again with ibm_set_geometry, which then resizes them");
+  }
+  if (I.n_pint == 0) return fail(c, IBM_ERR_STATE, "the current geometry has no fluid");
+  return IBM_OK;
 }
 
 int check_inst(ibm_ctx* c, int32_t inst) {
@@ -867,7 +903,6 @@ int run_steps_batched(ibm_ctx* c, int nsteps, hipStream_t st, bool count = true)
       for (Instance& I : c->inst) {
         I.cur = (I.cur + 1) % 3;
         I.fresh = false;
-        I.mat_valid = false;
       }
       RUNK(c, K_CFR_PI, launch_cfr_pi_b<T>((const CfrArgs<T>*)b.cfr[k], b.bo_cfr, n, b.n_cfr, st));
       RUNK(c, K_DIV_FFTX, launch_div_fftx_b<T>((const DivArgs<T>*)b.div[k], b.bo_div, n, b.n_div, b.mb_div,
@@ -995,11 +1030,18 @@ int ibm_set_geometry(ibm_handle h, int32_t inst, const double* sdf_u, const doub
   int rc = check_inst(h, inst);
   if (rc) return rc;
   if (!sdf_u || !sdf_v || !sdf_w) return fail(h, IBM_ERR_ARG, "null SDF pointer");
-  if ((rc = refuse_capture(h))) return rc;
-  drop_graph(h);
   Instance& I = h->inst[inst];
+  // the first geometry (or one after the lists overflowed) sizes the lists and
+  // synchronises; later ones only enqueue kernels and keep the captured graph
+  const bool sizing = !I.ibm_idx.p || I.lists_overflowed;
+  if (sizing) {
+    if ((rc = refuse_capture(h))) return rc;
+    drop_graph(h);
+  }
   if ((rc = materialize(h, I))) return rc;   // a pending projection belongs to the old geometry
-  if ((rc = set_geometry_impl(h, I, sdf_u, sdf_v, sdf_w))) return rc;
+  bool sized = false;
+  if ((rc = set_geometry_impl(h, I, sdf_u, sdf_v, sdf_w, &sized))) return rc;
+  if (sized) drop_graph(h);
   return seed_pending(h, I);
 }
 
@@ -1080,7 +1122,6 @@ int ibm_step(ibm_handle h, int32_t nsteps) {
       I.step += nsteps;
       I.time += nsteps * I.g.dt;
       I.fresh = false;
-      I.mat_valid = false;
     }
     return IBM_OK;
   }
@@ -1204,6 +1245,7 @@ int ibm_stats(ibm_handle h, int32_t inst, ibm_stats_t* out) {
   if (!out) return fail(h, IBM_ERR_ARG, "null output");
   if ((rc = refuse_capture(h))) return rc;
   Instance& I = h->inst[inst];
+  if ((rc = refresh_counts(h, I))) return rc;
   const GridParams& g = I.g;
   if ((rc = materialize(h, I))) return rc;
   int np = 0;
@@ -1271,6 +1313,7 @@ int ibm_get_geometry(ibm_handle h, int32_t inst, uint8_t* tags, int64_t* n_ibm3)
   Instance& I = h->inst[inst];
   if (!I.geom_ready) return fail(h, IBM_ERR_STATE, "no geometry");
   if ((rc = refuse_capture(h))) return rc;
+  if ((rc = refresh_counts(h, I))) return rc;
   if (tags) HIPCHK(h, hipMemcpyAsync(tags, I.tag, (size_t)I.g.ncell, hipMemcpyDeviceToDevice, h->stream));
   SYNCHK(h, h->stream);
   if (n_ibm3)
@@ -1285,7 +1328,9 @@ int ibm_get_ibm_list(ibm_handle h, int32_t inst, int32_t comp, int32_t* idx, dou
   if (!I.geom_ready) return fail(h, IBM_ERR_STATE, "no geometry");
   if ((rc = refuse_capture(h))) return rc;
   if (comp < 0 || comp > 2) return fail(h, IBM_ERR_ARG, "comp must be 0, 1 or 2");
-  const int64_t off = (comp >= 1 ? I.n_ibm[0] : 0) + (comp >= 2 ? I.n_ibm[1] : 0);
+  if ((rc = refresh_counts(h, I))) return rc;
+  // the component lists lie end to end at their capacities
+  const int64_t off = (comp >= 1 ? I.cap[0] : 0) + (comp >= 2 ? I.cap[1] : 0);
   const int64_t n = I.n_ibm[comp];
   const int64_t ntot = I.L.n_total;
   if (n > 0) {

@@ -193,8 +193,9 @@ struct StageConsts {
   int write_h;    // H needed by the next stage
 };
 
-// Immersed-boundary points: the three component lists, concatenated in linear cell
-// order.  choff_c[row * cpr + ch] is the number of points of component c that come
+// Immersed-boundary points: the three component lists, each in linear cell order, laid
+// end to end at fixed capacities (so that a new geometry with no more points than the
+// capacities needs no reallocation and no host read-back).  choff_c[row * cpr + ch] is the number of points of component c that come
 // before the 64-wide chunk ch of grid row `row` (row = j * nz + k); a wavefront that
 // covers exactly one such chunk finds a point's list index as that offset plus the
 // number of flagged lanes below it (ballot).
@@ -209,7 +210,10 @@ struct IbmLists {
   const int32_t* choff_u;
   const int32_t* choff_v;
   const int32_t* choff_w;
-  int n_u, n_v, n_w, n_total;
+  int n_u, n_v, n_w, n_total;   // capacities of the three lists (laid end to end: v starts
+                                // at n_u, w at n_u + n_v) and their sum, the stride of coef
+  const int32_t* cnt;      // device: points actually listed per component (<= capacity
+                           // unless the geometry overflowed it, which is reported)
   int cpr;                 // 64-wide chunks per row
 };
 
@@ -434,8 +438,9 @@ hipError_t launch_pcg_check(const GridParams& g, const double* part, const doubl
 // mean[0] <- sc[3] (the removed mean restored for the diagnostics)
 hipError_t launch_pcg_post(double* mean, const double* sc, hipStream_t st);
 int pcg_blocks(const GridParams& g);
+// n_internal: device count of the internal pressure cells
 hipError_t launch_pcg_init(const GridParams& g, const uint8_t* tag, const double* x, const double* mean, double* r,
-                           double* part, int64_t n_internal, hipStream_t st);
+                           double* part, const int32_t* n_internal, hipStream_t st);
 hipError_t launch_pcg_rz(const GridParams& g, const double* r, const double* z, double* part, hipStream_t st);
 hipError_t launch_pcg_dir(const GridParams& g, const uint8_t* tag, const double* z, double* p, double* part,
                           double* sc, int it, hipStream_t st);
@@ -445,21 +450,31 @@ hipError_t launch_pcg_step(const GridParams& g, const uint8_t* tag, double* x, d
                            const double* ap, double* part, const double* sc, int it, hipStream_t st);
 hipError_t launch_pcg_total(const GridParams& g, const double* part, int slot, double* out, hipStream_t st);
 hipError_t launch_pcg_finish(const GridParams& g, const uint8_t* tag, double* x, const double* part,
-                             int64_t n_internal, hipStream_t st);
+                             const int32_t* n_internal, hipStream_t st);
 // tau_x[nx] and, if modes is not null, modes[3] = (tau_0, tau_1c, tau_1s)
 template <typename T>
 hipError_t launch_wall_shear(const GridParams& g, const T* u, const int32_t* wj, const double* wd,
                              const double* wallv, double* tau_x, double* modes, hipStream_t st);
-hipError_t launch_count_flags(const uint8_t* tag, int64_t n, uint8_t mask, int32_t* blk_counts,
-                              int nblk, hipStream_t st);
-hipError_t launch_scan_counts(int32_t* blk_counts, int nblk, int32_t* total, hipStream_t st);
-hipError_t launch_chunk_counts(const uint8_t* tag, const GridParams& g, uint8_t mask, int cpr, int32_t* counts,
-                               hipStream_t st);
-hipError_t launch_compact(const uint8_t* tag, int64_t n, uint8_t mask, const int32_t* blk_offsets,
-                          int32_t* idx_out, int nblk, hipStream_t st);
-hipError_t launch_ibm_coef(const int32_t* idx, const double* lam_dense, const double* sig_dense, int n, double dt,
-                           int b_mode, double* lam_out, double* sig_out,
-                           double2* coef /* [3][n_total] at offset */, int n_total, int offset, hipStream_t st);
+// counts[m * nblk + block] for nm <= 8 masks packed 8 bits each into masks
+hipError_t launch_count_masks(const uint8_t* tag, int64_t n, uint64_t masks, int nm, int32_t* counts, int nblk,
+                              hipStream_t st);
+// exclusive scans of narr arrays of nblk counts (stride apart), their sums into totals
+hipError_t launch_scan_multi(int32_t* counts, int nblk, int stride, int narr, int32_t* totals, hipStream_t st);
+// the u, v, w immersed-boundary lists of capacities cap[] (laid end to end) from the
+// scanned per-block offsets of their masks (offsets[c * nblk + block]); overflow[0] set
+// when a component has more points than its capacity
+hipError_t launch_compact3(const uint8_t* tag, int64_t n, const int32_t* offsets, int nblk, int32_t* idx,
+                           const int cap[3], int32_t* overflow, hipStream_t st);
+// lambda, sigma and (B, 1/A) of the listed points (cnt[c] per component, at most cap[c]);
+// lam_dense, sig_dense: three dense component arrays of ncell values each
+hipError_t launch_ibm_coef3(const int32_t* idx, const double* lam_dense, const double* sig_dense, int64_t ncell,
+                            const int32_t* cnt, const int cap[3], double dt, int b_mode, double* lam_out,
+                            double* sig_out, double2* coef, hipStream_t st);
+// per-(row, 64-chunk) counts of the three immersed-boundary masks, [3][nrows cpr + 1]
+hipError_t launch_chunk_counts3(const uint8_t* tag, const GridParams& g, int cpr, int32_t* counts, hipStream_t st);
+hipError_t launch_clear_flag(int32_t* flag, hipStream_t st);
+hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t st);
+
 // partial sums for S_k into part[0 .. 4 npart); sd_out[k] = sum over the IBM u points of
 // sig / A_k (its partials after those of S_k: part needs 4 (npart + n_u/256 + 1) doubles)
 hipError_t launch_s_k(const GridParams& g, const uint8_t* tag, const IbmLists& L, double dt, double* part,

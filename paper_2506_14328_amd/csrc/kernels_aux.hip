@@ -212,24 +212,11 @@ __global__ __launch_bounds__(256) void k_geom_south_wall(GridParams g, const dou
   wd[col] = box ? -d : d;   // negative: the wall is the south box wall (at rest)
 }
 
-// Count cells whose tag has `mask` set, per block of 256 cells.
-__global__ __launch_bounds__(256) void k_count_flags(const uint8_t* __restrict__ tag, int64_t n, uint8_t mask,
-                                                    int32_t* __restrict__ counts) {
-  __shared__ int32_t wc[4];
-  const int64_t e = blockIdx.x * 256ll + threadIdx.x;
-  const bool f = (e < n) && (tag[e] & mask);
-  const uint64_t b = __ballot(f);
-  const int lane = threadIdx.x % IBM_WAVE, wid = threadIdx.x / IBM_WAVE;
-  if (lane == 0) wc[wid] = __popcll(b);
-  __syncthreads();
-  if (threadIdx.x == 0) counts[blockIdx.x] = wc[0] + wc[1] + wc[2] + wc[3];
-}
-
 // Exclusive prefix sum of nblk counts in place, total[0] = their sum; one block of 1024
 // threads, 4096 counts per round: each thread adds 4 consecutive counts, the waves scan
 // their threads' sums with shuffles and one wave scans the 16 wave sums.
-__global__ __launch_bounds__(1024) void k_scan_counts(int32_t* __restrict__ counts, int nblk,
-                                                     int32_t* __restrict__ total) {
+__device__ __forceinline__ void scan_counts_body(int32_t* __restrict__ counts, int nblk,
+                                                 int32_t* __restrict__ total) {
   __shared__ int32_t wsum[16];
   const int tid = threadIdx.x, lane = tid & (IBM_WAVE - 1), wid = tid / IBM_WAVE;
   int32_t carry = 0;
@@ -265,51 +252,84 @@ __global__ __launch_bounds__(1024) void k_scan_counts(int32_t* __restrict__ coun
   if (tid == 0) total[0] = carry;
 }
 
-// Flagged cells per 64-wide chunk of each grid row: counts[row * cpr + ch]; one extra
-// zero entry at the end, so that the scanned array also holds the total.
-__global__ __launch_bounds__(256) void k_chunk_counts(const uint8_t* __restrict__ tag, int nx, int nrows, int cpr,
-                                                     uint8_t mask, int32_t* __restrict__ counts) {
-  const int e = blockIdx.x * 256 + threadIdx.x;
-  if (e > nrows * cpr) return;
-  if (e == nrows * cpr) {
-    counts[e] = 0;
-    return;
-  }
-  const int row = e / cpr, ch = e - row * cpr;
-  const int a = ch * IBM_WAVE, b = min(a + IBM_WAVE, nx);
-  const uint8_t* t = tag + (size_t)row * nx;
-  int n = 0;
-  for (int i = a; i < b; ++i) n += (t[i] & mask) ? 1 : 0;
-  counts[e] = n;
+// The same for several arrays at once: block m scans counts[m * stride ..] and writes its
+// sum to total[m].
+__global__ __launch_bounds__(1024) void k_scan_multi(int32_t* __restrict__ counts, int nblk, int stride,
+                                                    int32_t* __restrict__ total) {
+  scan_counts_body(counts + (size_t)blockIdx.x * stride, nblk, total + blockIdx.x);
 }
 
-// Write the ascending linear indices of flagged cells at their scanned offsets.
-__global__ __launch_bounds__(256) void k_compact(const uint8_t* __restrict__ tag, int64_t n, uint8_t mask,
-                                                const int32_t* __restrict__ offsets, int32_t* __restrict__ out) {
-  __shared__ int32_t wc[4];
+// Per block of 256 cells, the number of cells with each of nm tag masks set (mask m in
+// bits 8m..8m+7 of masks): counts[m * nblk + block].
+__global__ __launch_bounds__(256) void k_count_masks(const uint8_t* __restrict__ tag, int64_t n, uint64_t masks,
+                                                    int nm, int32_t* __restrict__ counts, int nblk) {
+  __shared__ int32_t wc[8][4];
   const int64_t e = blockIdx.x * 256ll + threadIdx.x;
-  const bool f = (e < n) && (tag[e] & mask);
-  const uint64_t b = __ballot(f);
+  const uint8_t t = (e < n) ? tag[e] : uint8_t(0);
   const int lane = threadIdx.x % IBM_WAVE, wid = threadIdx.x / IBM_WAVE;
-  if (lane == 0) wc[wid] = __popcll(b);
+  for (int m = 0; m < nm; ++m) {
+    const uint8_t mask = uint8_t((masks >> (8 * m)) & 0xffu);
+    const uint64_t b = __ballot((t & mask) != 0);
+    if (lane == 0) wc[m][wid] = __popcll(b);
+  }
   __syncthreads();
-  int base = offsets[blockIdx.x];
-  for (int w = 0; w < wid; ++w) base += wc[w];
-  const uint64_t below = (lane == 0) ? 0ull : (b & ((~0ull) >> (64 - lane)));
-  if (f) out[base + __popcll(below)] = (int32_t)e;
+  if ((int)threadIdx.x < nm) {
+    const int m = threadIdx.x;
+    counts[(size_t)m * nblk + blockIdx.x] = wc[m][0] + wc[m][1] + wc[m][2] + wc[m][3];
+  }
 }
 
-// lambda and per-stage (B, 1/A) of each immersed-boundary point (Eqs. (14)-(16)).
-__global__ __launch_bounds__(256) void k_ibm_coef(const int32_t* __restrict__ idx, const double* __restrict__ lam_dense,
-                                                 const double* __restrict__ sig_dense, int n, double dt, int b_mode,
-                                                 double* __restrict__ lam_out, double* __restrict__ sig_out,
-                                                 double2* __restrict__ coef, int n_total, int offset) {
+// The ascending cell indices of the u, v and w immersed-boundary points (tag bits
+// TAG_UI << c) at their scanned block offsets offsets[c * nblk + block], into the
+// component's list, which starts at list_off[c] and holds cap[c] entries; a point whose
+// rank reaches the capacity is not written and sets overflow[0].
+__global__ __launch_bounds__(256) void k_compact3(const uint8_t* __restrict__ tag, int64_t n,
+                                                 const int32_t* __restrict__ offsets, int nblk,
+                                                 int32_t* __restrict__ idx, int off_v, int off_w, int cap_u,
+                                                 int cap_v, int cap_w, int32_t* __restrict__ overflow) {
+  __shared__ int32_t wc[3][4];
+  const int64_t e = blockIdx.x * 256ll + threadIdx.x;
+  const uint8_t t = (e < n) ? tag[e] : uint8_t(0);
+  const int lane = threadIdx.x % IBM_WAVE, wid = threadIdx.x / IBM_WAVE;
+  uint64_t bal[3];
+  for (int c = 0; c < 3; ++c) {
+    bal[c] = __ballot((t & (TAG_UI << c)) != 0);
+    if (lane == 0) wc[c][wid] = __popcll(bal[c]);
+  }
+  __syncthreads();
+  const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+  for (int c = 0; c < 3; ++c) {
+    if (!(t & (TAG_UI << c))) continue;
+    int base = offsets[(size_t)c * nblk + blockIdx.x];
+    for (int w = 0; w < wid; ++w) base += wc[c][w];
+    const int r = base + __popcll(bal[c] & below);
+    const int cap = c == 0 ? cap_u : (c == 1 ? cap_v : cap_w);
+    const int off = c == 0 ? 0 : (c == 1 ? off_v : off_w);
+    if (r < cap) idx[off + r] = (int32_t)e;
+    else overflow[0] = 1;
+  }
+}
+
+// lambda, sigma and per-stage (B, 1/A) of every immersed-boundary point of the three
+// component lists (Eqs. (14)-(16)); entry e of the capacity-strided lists, component c
+// from the capacities, its points counted by cnt[c] (entries past it are left alone).
+__global__ __launch_bounds__(256) void k_ibm_coef3(const int32_t* __restrict__ idx,
+                                                  const double* __restrict__ lam_dense,
+                                                  const double* __restrict__ sig_dense, int64_t ncell,
+                                                  const int32_t* __restrict__ cnt, int cap_u, int cap_v,
+                                                  int cap_total, double dt, int b_mode,
+                                                  double* __restrict__ lam_out, double* __restrict__ sig_out,
+                                                  double2* __restrict__ coef) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
-  const int c = idx[offset + e];
-  const double lam = lam_dense[c];
-  lam_out[offset + e] = lam;
-  sig_out[offset + e] = sig_dense[c];
+  if (e >= cap_total) return;
+  const int c = e < cap_u ? 0 : (e < cap_u + cap_v ? 1 : 2);
+  const int off = c == 0 ? 0 : (c == 1 ? cap_u : cap_u + cap_v);
+  const int cap = c == 0 ? cap_u : (c == 1 ? cap_v : cap_total - cap_u - cap_v);
+  if (e - off >= min(cnt[c], cap)) return;
+  const int cell = idx[e];
+  const double lam = lam_dense[(size_t)c * ncell + cell];
+  lam_out[e] = lam;
+  sig_out[e] = sig_dense[(size_t)c * ncell + cell];
   for (int k = 0; k < 3; ++k) {
     const double ck = rk_c(k);
     const double x = lam * ck * dt;
@@ -324,8 +344,48 @@ __global__ __launch_bounds__(256) void k_ibm_coef(const int32_t* __restrict__ id
       B = (x > 700.0) ? 0.0 : ((x > 0.0) ? x / expm1(x) : 1.0);
       A = x + B;
     }
-    coef[(size_t)k * n_total + offset + e] = make_double2(B, 1.0 / A);
+    coef[(size_t)k * cap_total + e] = make_double2(B, 1.0 / A);
   }
+}
+
+// Flagged cells per 64-wide chunk of each grid row for the three immersed-boundary masks:
+// counts[c * (nrows cpr + 1) + row * cpr + ch]; one extra zero entry per mask.
+__global__ __launch_bounds__(256) void k_chunk_counts3(const uint8_t* __restrict__ tag, int nx, int nrows, int cpr,
+                                                      int32_t* __restrict__ counts) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  const int nch = nrows * cpr + 1;
+  if (e >= nch) return;
+  if (e == nch - 1) {
+    for (int c = 0; c < 3; ++c) counts[c * nch + e] = 0;
+    return;
+  }
+  const int row = e / cpr, ch = e - row * cpr;
+  const int a = ch * IBM_WAVE, b = min(a + IBM_WAVE, nx);
+  const uint8_t* t = tag + (size_t)row * nx;
+  int n0 = 0, n1 = 0, n2 = 0;
+  for (int i = a; i < b; ++i) {
+    const uint8_t v = t[i];
+    n0 += (v & TAG_UI) ? 1 : 0;
+    n1 += (v & TAG_VI) ? 1 : 0;
+    n2 += (v & TAG_WI) ? 1 : 0;
+  }
+  counts[e] = n0;
+  counts[nch + e] = n1;
+  counts[2 * nch + e] = n2;
+}
+
+// overflow[0] = 0 (a kernel, so that a geometry update can be captured into a graph)
+__global__ void k_clear_flag(int32_t* __restrict__ flag) {
+  if (threadIdx.x == 0) flag[0] = 0;
+}
+
+// bytes zeros from p (a kernel: no memset nodes in captured graphs): nvec 16-byte vectors
+// (p 16-byte aligned, nvec = 0 otherwise), the remaining bytes by thread 0 of block 0
+__global__ __launch_bounds__(256) void k_fill_zero(unsigned char* __restrict__ p, int64_t nvec, int64_t bytes) {
+  const int64_t e = blockIdx.x * 256ll + threadIdx.x;
+  if (e < nvec) reinterpret_cast<uint4*>(p)[e] = make_uint4(0u, 0u, 0u, 0u);
+  if (e == 0)
+    for (int64_t b = nvec * 16; b < bytes; ++b) p[b] = 0;
 }
 
 // S_k partials: number of internal non-IBM u points (column 0) and sum over IBM u points
@@ -352,11 +412,13 @@ __global__ __launch_bounds__(256) void k_s_list(GridParams g, IbmLists L, double
                                                double* __restrict__ part_sd) {
   __shared__ double red[4];
   const int e = blockIdx.x * 256 + threadIdx.x;
-  const double sg = (e < L.n_u) ? L.sig[e] : 0.0;
+  // the u list holds cnt[0] points (at most its capacity n_u)
+  const bool in = e < min(L.cnt[0], L.n_u);
+  const double sg = in ? L.sig[e] : 0.0;
   // a stretched grid weights each point by the cell height of its row
-  const double wy = (g.stretched && e < L.n_u) ? g.ytab[YT_DYC * g.ystr + L.idx[e] / (g.nx * g.nz)] : 1.0;
+  const double wy = (g.stretched && in) ? g.ytab[YT_DYC * g.ystr + L.idx[e] / (g.nx * g.nz)] : 1.0;
   for (int k = 0; k < 3; ++k) {
-    double v = (e < L.n_u) ? L.coef[(size_t)k * L.n_total + e].y : 0.0;
+    double v = in ? L.coef[(size_t)k * L.n_total + e].y : 0.0;
     if (g.stretched) v *= wy;
     const double tot = block_reduce<false>(v, red);
     __syncthreads();
@@ -646,36 +708,50 @@ template hipError_t launch_wall_shear<double>(const GridParams&, const double*, 
 template hipError_t launch_wall_shear<float>(const GridParams&, const float*, const int32_t*, const double*,
                                              const double*, double*, double*, hipStream_t);
 
-hipError_t launch_count_flags(const uint8_t* tag, int64_t n, uint8_t mask, int32_t* blk_counts, int nblk,
+hipError_t launch_count_masks(const uint8_t* tag, int64_t n, uint64_t masks, int nm, int32_t* counts, int nblk,
                               hipStream_t st) {
-  hipLaunchKernelGGL(k_count_flags, dim3(nblk), dim3(256), 0, st, tag, n, mask, blk_counts);
+  hipLaunchKernelGGL(k_count_masks, dim3(nblk), dim3(256), 0, st, tag, n, masks, nm, counts, nblk);
   return hipGetLastError();
 }
 
-hipError_t launch_scan_counts(int32_t* blk_counts, int nblk, int32_t* total, hipStream_t st) {
-  hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, blk_counts, nblk, total);
+hipError_t launch_scan_multi(int32_t* counts, int nblk, int stride, int narr, int32_t* totals, hipStream_t st) {
+  hipLaunchKernelGGL(k_scan_multi, dim3(narr), dim3(1024), 0, st, counts, nblk, stride, totals);
   return hipGetLastError();
 }
 
-hipError_t launch_chunk_counts(const uint8_t* tag, const GridParams& g, uint8_t mask, int cpr, int32_t* counts,
-                               hipStream_t st) {
+hipError_t launch_compact3(const uint8_t* tag, int64_t n, const int32_t* offsets, int nblk, int32_t* idx,
+                           const int cap[3], int32_t* overflow, hipStream_t st) {
+  hipLaunchKernelGGL(k_compact3, dim3(nblk), dim3(256), 0, st, tag, n, offsets, nblk, idx, cap[0], cap[0] + cap[1],
+                     cap[0], cap[1], cap[2], overflow);
+  return hipGetLastError();
+}
+
+hipError_t launch_ibm_coef3(const int32_t* idx, const double* lam_dense, const double* sig_dense, int64_t ncell,
+                            const int32_t* cnt, const int cap[3], double dt, int b_mode, double* lam_out,
+                            double* sig_out, double2* coef, hipStream_t st) {
+  const int ct = cap[0] + cap[1] + cap[2];
+  if (ct == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ibm_coef3, dim3((ct + 255) / 256), dim3(256), 0, st, idx, lam_dense, sig_dense, ncell, cnt,
+                     cap[0], cap[1], ct, dt, b_mode, lam_out, sig_out, coef);
+  return hipGetLastError();
+}
+
+hipError_t launch_chunk_counts3(const uint8_t* tag, const GridParams& g, int cpr, int32_t* counts, hipStream_t st) {
   const int n = g.nrows * cpr + 1;
-  hipLaunchKernelGGL(k_chunk_counts, dim3((n + 255) / 256), dim3(256), 0, st, tag, g.nx, g.nrows, cpr, mask, counts);
+  hipLaunchKernelGGL(k_chunk_counts3, dim3((n + 255) / 256), dim3(256), 0, st, tag, g.nx, g.nrows, cpr, counts);
   return hipGetLastError();
 }
 
-hipError_t launch_compact(const uint8_t* tag, int64_t n, uint8_t mask, const int32_t* blk_offsets,
-                          int32_t* idx_out, int nblk, hipStream_t st) {
-  hipLaunchKernelGGL(k_compact, dim3(nblk), dim3(256), 0, st, tag, n, mask, blk_offsets, idx_out);
+hipError_t launch_clear_flag(int32_t* flag, hipStream_t st) {
+  hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(64), 0, st, flag);
   return hipGetLastError();
 }
 
-hipError_t launch_ibm_coef(const int32_t* idx, const double* lam_dense, const double* sig_dense, int n, double dt,
-                           int b_mode, double* lam_out, double* sig_out, double2* coef, int n_total, int offset,
-                           hipStream_t st) {
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ibm_coef, dim3((n + 255) / 256), dim3(256), 0, st, idx, lam_dense, sig_dense, n, dt, b_mode,
-                     lam_out, sig_out, coef, n_total, offset);
+hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t st) {
+  if (bytes <= 0) return hipSuccess;
+  const int64_t nvec = ((uintptr_t)p % 16 == 0) ? bytes / 16 : 0;
+  const int64_t nb = nvec > 0 ? (nvec + 255) / 256 : 1;
+  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)nb), dim3(256), 0, st, (unsigned char*)p, nvec, bytes);
   return hipGetLastError();
 }
 

@@ -101,9 +101,9 @@ __global__ __launch_bounds__(PT) void k_pcg_init(GridParams g, const uint8_t* __
 // the divergence to the full-box solve's accuracy) is removed here.  Partials of |r0|^2.
 __global__ __launch_bounds__(PT) void k_pcg_center(GridParams g, const uint8_t* __restrict__ tag,
                                                   double* __restrict__ r, const double* __restrict__ prs, int nb,
-                                                  double n_internal, double* __restrict__ pr) {
+                                                  const int32_t* __restrict__ n_internal, double* __restrict__ pr) {
   __shared__ double smem[8];
-  const double mean = sum_partials(prs, nb, smem) / n_internal;
+  const double mean = sum_partials(prs, nb, smem) / (double)n_internal[0];
   double ar = 0.0;
   for (int c = blockIdx.x * PT + threadIdx.x; c < g.ncell; c += gridDim.x * PT) {
     if (tag[c] & TAG_P) {
@@ -240,9 +240,9 @@ __global__ void k_pcg_post(double* __restrict__ mean, const double* __restrict__
 // gauge: phi = x - mean of x over the internal cells there, 0 elsewhere
 __global__ __launch_bounds__(PT) void k_pcg_finish(GridParams g, const uint8_t* __restrict__ tag,
                                                   double* __restrict__ x, const double* __restrict__ px, int nb,
-                                                  double n_internal) {
+                                                  const int32_t* __restrict__ n_internal) {
   __shared__ double smem[8];
-  const double mean = sum_partials(px, nb, smem) / n_internal;
+  const double mean = sum_partials(px, nb, smem) / (double)n_internal[0];
   for (int c = blockIdx.x * PT + threadIdx.x; c < g.ncell; c += gridDim.x * PT)
     x[c] = (tag[c] & TAG_P) ? x[c] - mean : 0.0;
 }
@@ -255,12 +255,12 @@ int pcg_blocks(const GridParams& g) {
 }
 
 hipError_t launch_pcg_init(const GridParams& g, const uint8_t* tag, const double* x, const double* mean, double* r,
-                           double* part, int64_t n_internal, hipStream_t st) {
+                           double* part, const int32_t* n_internal, hipStream_t st) {
   const int nb = pcg_blocks(g);
   hipLaunchKernelGGL(k_pcg_init, dim3(nb), dim3(PT), 0, st, g, tag, x, mean, r, part + PCG_B * PCG_NPART,
                      part + PCG_RS * PCG_NPART, part + PCG_X * PCG_NPART);
   hipLaunchKernelGGL(k_pcg_center, dim3(nb), dim3(PT), 0, st, g, tag, r, part + PCG_RS * PCG_NPART, nb,
-                     (double)n_internal, part + PCG_R2 * PCG_NPART);
+                     n_internal, part + PCG_R2 * PCG_NPART);
   return hipGetLastError();
 }
 
@@ -313,9 +313,9 @@ hipError_t launch_pcg_post(double* mean, const double* sc, hipStream_t st) {
 }
 
 hipError_t launch_pcg_finish(const GridParams& g, const uint8_t* tag, double* x, const double* part,
-                             int64_t n_internal, hipStream_t st) {
+                             const int32_t* n_internal, hipStream_t st) {
   const int nb = pcg_blocks(g);
   hipLaunchKernelGGL(k_pcg_finish, dim3(nb), dim3(PT), 0, st, g, tag, x, part + PCG_X * PCG_NPART, nb,
-                     (double)n_internal);
+                     n_internal);
   return hipGetLastError();
 }

@@ -251,9 +251,11 @@ __device__ __forceinline__ void k_momentum_body(GridParams g, Fields<T> f, IbmLi
     const uint64_t mw = __ballot((tg & TAG_WI) != 0);
     const size_t cb = (size_t)s.stage * L.n_total;
     double2 cfu = {0.0, 0.0}, cfv = {0.0, 0.0}, cfw = {0.0, 0.0};
-    if (tg & TAG_UI) cfu = L.coef[cb + chn_u + lanes_below(mu, lane)];
-    if (tg & TAG_VI) cfv = L.coef[cb + L.n_u + chn_v + lanes_below(mv, lane)];
-    if (tg & TAG_WI) cfw = L.coef[cb + L.n_u + L.n_v + chn_w + lanes_below(mw, lane)];
+    // (clamped to the list capacities: a geometry that overflowed them is reported and
+    // never reads past its lists)
+    if (tg & TAG_UI) cfu = L.coef[cb + min(chn_u + lanes_below(mu, lane), L.n_u - 1)];
+    if (tg & TAG_VI) cfv = L.coef[cb + L.n_u + min(chn_v + lanes_below(mv, lane), L.n_v - 1)];
+    if (tg & TAG_WI) cfw = L.coef[cb + L.n_u + L.n_v + min(chn_w + lanes_below(mw, lane), L.n_w - 1)];
     T hu = zero, hv = zero, hw = zero;
     if (act) {
       if (s.use_hold) {
@@ -459,8 +461,12 @@ __device__ __forceinline__ void k_cfr_pi_body(Fields<T> f, IbmLists L, int stage
   int id = 0;
   double inva = 0.0, usv = 0.0, add = 0.0;
   T* fp = f.us;
-  if (g < L.n_cover) {
-    const int comp = g < L.n_u ? 0 : (g < L.n_u + L.n_v ? 1 : 2);
+  // entry g of the capacity-strided lists holds a point if it is below its component's count
+  const int comp = g < L.n_u ? 0 : (g < L.n_u + L.n_v ? 1 : 2);
+  const int coff = comp == 0 ? 0 : (comp == 1 ? L.n_u : L.n_u + L.n_v);
+  const int ccap = comp == 0 ? L.n_u : (comp == 1 ? L.n_v : L.n_w);
+  const bool pt = g < L.n_cover && g - coff < min(L.cnt[comp], ccap);
+  if (pt) {
     fp = comp == 0 ? f.us : (comp == 1 ? f.vs : f.ws);
     id = L.idx[g];
     inva = L.coef[(size_t)stage * L.n_total + g].y;
@@ -492,7 +498,7 @@ __device__ __forceinline__ void k_cfr_pi_body(Fields<T> f, IbmLists L, int stage
     }
   }
   __syncthreads();
-  if (g < L.n_cover) fp[id] = T(usv + add - (g < L.n_u ? pi_s * ck_dt * inva : 0.0));
+  if (pt) fp[id] = T(usv + add - (g < L.n_u ? pi_s * ck_dt * inva : 0.0));
 }
 
 template <typename T>

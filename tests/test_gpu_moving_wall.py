@@ -207,3 +207,137 @@ def test_translating_body_with_masked_projection():
         o.set_geometry(*sdf)
         g.set_geometry(*[to_dev(a) for a in sdf])
     g.close()
+
+
+def _sphere_case():
+    return I.Case(nx=32, ny=17, nz=16, lx=2.0, lz=1.0, y_lo=-1.0, y_hi=1.0, nu=0.02, dt=0.01, q_target_or_pi=1.0,
+                  seed=9, geometry="flat", geo_params=(0.0,))
+
+
+def test_translating_body_with_the_graph_on():
+    """The translating sphere with the library's HIP graph on: a new geometry with no more
+    immersed-boundary points than the lists hold is processed on the stream without a
+    host read-back and keeps the captured graph, which then replays each step."""
+    c = _sphere_case()
+    vel = (0.6, -0.2, 0.1)
+    centre = np.array([0.6, -0.1, 0.45])
+    sdf = _body_sdf(c, centre, 0.3)
+    u0, v0, w0 = I.laminar_plus_solenoidal(c, sdf, c.seed, amp=0.05)
+    st = (u0, v0, w0, np.zeros_like(u0))
+    o = Oracle(OGrid.from_case(c))
+    o.set_geometry(*sdf)
+    o.set_wall_velocity(*vel)
+    o.set_state(*st)
+    g = gpu_grid(c, sdf, st)
+    g.set_wall_velocity(*vel)
+    g.tune(graph=1)
+    for n in range(4):
+        o.step(1)
+        g.step(1)
+        errs, _ = _errs(g, o)
+        s = g.stats()
+        _say(f"graph, step {n + 1}: {['%.1e' % e for e in errs]}, n_ibm {s['n_ibm']} (oracle "
+             f"{[int((o.lam[k] > 0).sum()) for k in 'uvw']})")
+        assert max(errs) < 1e-12
+        assert s["n_ibm"] == [int((o.lam[k] > 0).sum()) for k in "uvw"]
+        centre = centre + np.array(vel) * c.dt
+        sdf = _body_sdf(c, centre, 0.3)
+        o.set_geometry(*sdf)
+        g.set_geometry(*[to_dev(a) for a in sdf])
+    g.close()
+
+
+def test_translating_body_inside_a_caller_graph():
+    """A caller captures one move of the body and one step (ibm_set_geometry from
+    signed-distance buffers it refills, then ibm_step) into a HIP graph of its own and
+    replays it: the geometry update enqueues kernels and copies only (no synchronisation,
+    allocation or memset), and every replay equals the oracle's step."""
+    import ctypes
+    c = _sphere_case()
+    vel = (0.5, 0.1, -0.2)
+    centre = np.array([0.7, 0.05, 0.4])
+    sdf = _body_sdf(c, centre, 0.3)
+    u0, v0, w0 = I.laminar_plus_solenoidal(c, sdf, c.seed, amp=0.05)
+    st = (u0, v0, w0, np.zeros_like(u0))
+    o = Oracle(OGrid.from_case(c))
+    o.set_geometry(*sdf)
+    o.set_wall_velocity(*vel)
+    o.set_state(*st)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        g = gpu_grid(c, sdf, st)
+        g.set_wall_velocity(*vel)
+        bufs = [to_dev(a) for a in sdf]
+        g.step(1)                      # a pending projection, as before every replay
+    o.step(1)
+    s.synchronize()
+    hip = ctypes.CDLL("libamdhip64.so")
+    graph, gexec = ctypes.c_void_p(), ctypes.c_void_p()
+    assert hip.hipStreamBeginCapture(ctypes.c_void_p(s.cuda_stream), 1) == 0
+    try:
+        g.set_geometry(*bufs)
+        g.step(1)
+    finally:
+        rc = hip.hipStreamEndCapture(ctypes.c_void_p(s.cuda_stream), ctypes.byref(graph))
+    assert rc == 0 and graph.value
+    assert hip.hipGraphInstantiate(ctypes.byref(gexec), graph, None, None, ctypes.c_size_t(0)) == 0
+    try:
+        for n in range(3):
+            centre = centre + np.array(vel) * c.dt
+            sdf = _body_sdf(c, centre, 0.3)
+            o.set_geometry(*sdf)
+            o.step(1)
+            with torch.cuda.stream(s):
+                for b, a in zip(bufs, sdf):
+                    b.copy_(torch.from_numpy(a))
+            assert hip.hipGraphLaunch(gexec, ctypes.c_void_p(s.cuda_stream)) == 0
+            s.synchronize()
+            with torch.cuda.stream(s):
+                errs, _ = _errs(g, o)
+            _say(f"caller graph, replay {n + 1}: {['%.1e' % e for e in errs]}")
+            assert max(errs) < 1e-12
+    finally:
+        hip.hipGraphExecDestroy(gexec)
+        hip.hipGraphDestroy(graph)
+    g.close()
+
+
+def test_geometry_beyond_the_list_capacity():
+    """A geometry with more immersed-boundary points than the lists reserved at the first
+    one is reported by ibm_stats (IBM_ERR_STATE); giving it again resizes the lists, and
+    the step then equals the oracle's."""
+    from paper_2506_14328_amd.ibm import IBM_ERR_STATE, IbmError
+    c = I.Case(nx=32, ny=33, nz=16, lx=2.0, lz=1.0, y_lo=-1.0, y_hi=1.0, nu=0.02, dt=0.01, q_target_or_pi=1.0,
+               seed=9, geometry="flat", geo_params=(0.0,))
+
+    def body(r):
+        def fn(X, Y, Z):
+            dx = X - 1.0
+            dx -= c.lx * np.round(dx / c.lx)
+            dz = Z - 0.5
+            dz -= c.lz * np.round(dz / c.lz)
+            return np.minimum(np.sqrt(dx * dx + Y * Y + dz * dz) - r, 1.0 - np.abs(Y))
+        return I._sample(c, fn)
+
+    small, big = body(0.05), body(0.8)
+    u0, v0, w0 = I.laminar_plus_solenoidal(c, big, c.seed, amp=0.05)
+    st = (u0, v0, w0, np.zeros_like(u0))
+    g = gpu_grid(c, small, st)
+    n_small = g.stats()["n_ibm"]
+    g.set_geometry(*[to_dev(a) for a in big])
+    with pytest.raises(IbmError) as e:
+        g.stats()
+    assert e.value.code == IBM_ERR_STATE
+    g.set_geometry(*[to_dev(a) for a in big])      # resized now
+    g.set_state(*[to_dev(a) for a in st])
+    o = Oracle(OGrid.from_case(c))
+    o.set_geometry(*big)
+    o.set_state(*st)
+    g.step(2)
+    o.step(2)
+    errs, _ = _errs(g, o)
+    s = g.stats()
+    _say(f"capacity: first geometry {n_small}, larger {s['n_ibm']}; after resizing {['%.1e' % x for x in errs]}")
+    assert s["n_ibm"] == [int((o.lam[k] > 0).sum()) for k in "uvw"]
+    assert max(errs) < 1e-12
+    g.close()
