@@ -261,8 +261,19 @@ def measure_ensemble(n=96, steps=200, warmup=3, seed=5):
         el = time.perf_counter() - t0
         res[mode] = {"value": cells * 3 * steps / el, "ms_per_step": el / steps * 1e3}
     bad = sum(1 for i in range(n) if g.stats(inst=i)["nan_flag"])
+    # whole-step fraction of the HBM peak in each mode: algorithmic bytes of one RK3 step
+    # summed over the instances / measured time per step (the library's per-kernel events
+    # see per-instance launches only, so the batched kernels are not timed one by one)
+    n_ibm = [g.stats(inst=i)["n_ibm"] for i in range(n)]
+    nb_step = 0.0
+    for c, ni in zip(cases, n_ibm):
+        C = c.nx * (c.ny - 1) * c.nz
+        M = (c.nx // 2 + 1) * c.nz * (c.ny - 1)
+        nb_step += step_bytes(C, M, 4, sum(ni), ni[0])
+    step_frac = {m: round(nb_step / (r["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) for m, r in res.items()}
     g.close()
     return {"workload": f"ensemble_{n}_wavy_ragged", "precision": "fp32", "instances": n, "cells": cells,
+            "step_algorithmic_GB": round(nb_step / 1e9, 3), "step_frac_hbm": step_frac,
             "steps": steps, "value": res["graph"]["value"], "ms_per_step": res["graph"]["ms_per_step"],
             "sequential_value": res["sequential"]["value"], "batched_graph_value": res["batched"]["value"],
             "graph_speedup": res["graph"]["value"] / res["sequential"]["value"], "instances_with_nan": bad,
