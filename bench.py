@@ -472,6 +472,34 @@ def copy_bandwidth(gib=2.0, reps=10):
     return gbs
 
 
+def stream_mix_bandwidth(cells, elem_bytes, reps=5):
+    """Bytes per second of the library's stream-mix kernel (ibm_stream_mix) with the
+    momentum kernel's stream counts over the three RK3 stages, arrays of one field each:
+    stage 1 reads 5 fields and writes 7, stage 2 reads 8 and writes 7, stage 3 reads 8 and
+    writes 4 (the tag byte left out).  Total bytes / total time of the three: the practical
+    HBM ceiling of a kernel with that mix of read and write streams."""
+    import torch
+    from paper_2506_14328_amd import stream_mix
+    n = cells * elem_bytes // 8
+    arrs = [torch.full((n,), 1.0, dtype=torch.float64, device="cuda") for _ in range(15)]
+    mixes = ((5, 7), (8, 7), (8, 4))
+    for ns, nd in mixes:
+        stream_mix(arrs[8:8 + nd], arrs[:ns])
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        for ns, nd in mixes:
+            stream_mix(arrs[8:8 + nd], arrs[:ns])
+    e1.record()
+    e1.synchronize()
+    nbytes = reps * sum(ns + nd for ns, nd in mixes) * n * 8
+    gbs = nbytes / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    assert bool((arrs[8] == 8.0).all())
+    del arrs
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -514,6 +542,11 @@ def main():
             "algorithmic_bytes_per_launch": int(r["kernel_bytes"]),
             "step_algorithmic_GBs": round(r["step_gbs"], 1)}
     roof["measured_copy_GBs"] = round(copy_bandwidth(), 1)   # practical ceiling on this device
+    if r["kernel"] == "momentum":
+        # the ceiling of a kernel with the momentum kernel's read and write streams
+        mix = stream_mix_bandwidth(r["cells"], 8 if a.precision == "fp64" else 4)
+        roof["measured_stream_mix_GBs"] = round(mix, 1)
+        roof["frac_of_stream_mix"] = round(r["achieved_gbs"] / mix, 4)
     out = {"metric": METRIC, "value": r["value"], "unit": "cell-updates/s", "n_gpus": 1, "steps": a.steps,
            "warmup": a.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64" if a.precision == "fp64" else "f32",

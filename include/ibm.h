@@ -307,7 +307,8 @@ enum { IBM_TUNE_MOMENTUM_PLANES = 0, IBM_TUNE_FFTZ_WIDTH = 1, IBM_TUNE_TRI_ROWS 
                                          (0 = automatic: plain accesses) */
        IBM_TUNE_MOMENTUM_TILE = 8 };  /* (x, z) tile of one momentum block: 0 or 1 = 64 x 4,
                                          2 = 128 x 4, 3 = 64 x 8, 4 = 256 x 4 and 5 = 128 x 8
-                                         (FP32 storage only; FP64 takes 64 x 4 for these);
+                                         (FP32 storage only; FP64 takes 64 x 4 for these),
+                                         6 = 64 x 4 with the loads of two planes in flight;
                                          stretched grids and batched launches take 64 x 4 */
 int ibm_tune_set(ibm_handle h, int32_t param, int32_t value);
 int ibm_tune_get(ibm_handle h, int32_t param, int32_t* value);
@@ -338,6 +339,19 @@ int64_t ibm_device_bytes(ibm_handle h);
  * keeps nothing.  IBM_ERR_ARG for null pointers, misalignment, a size that is not a
  * multiple of 16 or overlapping ranges; IBM_ERR_DEVICE if the launch fails. */
 int ibm_stream_copy(void* dst, const void* src, int64_t bytes, void* hip_stream);
+
+/* Streams nsrc input arrays into ndst output arrays of `bytes` bytes each (1 <= nsrc, ndst
+ * <= 8; dst and src are host arrays of device pointers, each 16-byte aligned; bytes a
+ * multiple of 16): every output receives the element-wise sum of the inputs read as FP64
+ * values, 16-byte vector loads and stores, enqueued on hip_stream (NULL = the default
+ * stream).  It is the measured practical HBM ceiling of a kernel with the same numbers of
+ * read and write streams as a step kernel (the momentum kernel moves 5..8 read and 4..7
+ * write streams at once), the copy being the case of one and one.  No handle; the library
+ * keeps nothing.  IBM_ERR_ARG for null or misaligned pointers, counts outside 1..8, a size
+ * that is not a multiple of 16 or an output overlapping another array; IBM_ERR_DEVICE if
+ * the launch fails. */
+int ibm_stream_mix(void* const* dst, int32_t ndst, const void* const* src, int32_t nsrc, int64_t bytes,
+                   void* hip_stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): the full-box pressure solve of

@@ -6,4 +6,5 @@ The compute path is the HIP library libibm.so (C ABI in include/ibm.h);
 library; creating an `IbmGrid` does, and raises if it has not been built.
 """
 from .ibm import (IBM_B_EULER, IBM_B_EXP, IBM_B_TAYLOR2, IBM_CFR, IBM_CPG, IBM_FP32_STORAGE, IBM_FP64,  # noqa
-                  IbmError, IbmGrid, IbmGridDesc, IbmStats, load_library, LIB_PATH, EXPORTED, stream_copy, solve_pressure_noalloc)
+                  IbmError, IbmGrid, IbmGridDesc, IbmStats, load_library, LIB_PATH, EXPORTED, stream_copy, stream_mix,
+                  solve_pressure_noalloc)

@@ -1371,7 +1371,7 @@ int ibm_tune_set(ibm_handle h, int32_t param, int32_t value) {
         I.tu.tile_order = value;
         break;
       case IBM_TUNE_MOMENTUM_TILE:
-        if (value > 5) return fail(h, IBM_ERR_ARG, "momentum tile must be 0..5");
+        if (value > 6) return fail(h, IBM_ERR_ARG, "momentum tile must be 0..6");
         I.tu.mom_tile = value;
         break;
       case IBM_TUNE_MOMENTUM_CACHE:
@@ -1705,6 +1705,36 @@ int ibm_stream_copy(void* dst, const void* src, int64_t bytes, void* hip_stream)
     return fail(nullptr, IBM_ERR_ARG, "source and destination overlap");
   const hipError_t e = launch_stream_copy(src, dst, bytes / 16, (hipStream_t)hip_stream);
   if (e != hipSuccess) return fail(nullptr, IBM_ERR_DEVICE, std::string("stream copy: ") + hipGetErrorString(e));
+  return IBM_OK;
+}
+
+int ibm_stream_mix(void* const* dst, int32_t ndst, const void* const* src, int32_t nsrc, int64_t bytes,
+                   void* hip_stream) {
+  if (!dst || !src) return fail(nullptr, IBM_ERR_ARG, "null pointer array");
+  if (ndst < 1 || ndst > MIX_MAX || nsrc < 1 || nsrc > MIX_MAX)
+    return fail(nullptr, IBM_ERR_ARG, "ndst and nsrc must be 1..8");
+  if (bytes < 0 || bytes % 16 != 0) return fail(nullptr, IBM_ERR_ARG, "bytes must be a non-negative multiple of 16");
+  MixPtrs p{};
+  for (int q = 0; q < nsrc; ++q) {
+    if (!src[q] || (uintptr_t)src[q] % 16 != 0) return fail(nullptr, IBM_ERR_ARG, "input arrays must be non-null and 16-byte aligned");
+    p.src[q] = (const double2*)src[q];
+  }
+  for (int q = 0; q < ndst; ++q) {
+    if (!dst[q] || (uintptr_t)dst[q] % 16 != 0) return fail(nullptr, IBM_ERR_ARG, "output arrays must be non-null and 16-byte aligned");
+    p.dst[q] = (double2*)dst[q];
+  }
+  // no output may overlap an input or another output
+  for (int a = 0; a < ndst; ++a) {
+    const uintptr_t d = (uintptr_t)dst[a];
+    for (int b = 0; b < nsrc + ndst; ++b) {
+      if (b == nsrc + a) continue;
+      const uintptr_t o = b < nsrc ? (uintptr_t)src[b] : (uintptr_t)dst[b - nsrc];
+      if (bytes > 0 && d < o + (uintptr_t)bytes && o < d + (uintptr_t)bytes)
+        return fail(nullptr, IBM_ERR_ARG, "an output array overlaps another array");
+    }
+  }
+  const hipError_t e = launch_stream_mix(p, nsrc, ndst, bytes / 16, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return fail(nullptr, IBM_ERR_DEVICE, std::string("stream mix: ") + hipGetErrorString(e));
   return IBM_OK;
 }
 

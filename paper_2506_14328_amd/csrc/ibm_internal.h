@@ -245,7 +245,8 @@ struct Tuning {
   int tile_order = 0; // momentum tiles: 1 contiguous per XCD (default), 2 interleaved,
                       // 3..8 super-tiles of 2x2, 4x2, 2x4, 4x4, 8x2, 8x4 tiles per XCD
   int mom_cache = 0;  // 1 + bits: bit 0 streaming stores, bit 1 streaming single-use loads
-  int mom_tile = 0;   // momentum tile: 0/1 64x4, 2 128x4, 3 64x8, 4 256x4 (FP32), 5 128x8 (FP32)
+  int mom_tile = 0;   // momentum tile: 0/1 64x4, 2 128x4, 3 64x8, 4 256x4 (FP32), 5 128x8 (FP32),
+                      // 6 64x4 with two planes of loads in flight
 };
 
 // Flags of the momentum kernel's `order` argument: the tile order (bit 0: contiguous runs
@@ -486,6 +487,12 @@ template <typename T>
 hipError_t launch_copy(const T* src, T* dst, int64_t n, hipStream_t st);
 // nvec 16-byte vectors from src to dst (16-byte aligned)
 hipError_t launch_stream_copy(const void* src, void* dst, int64_t nvec, hipStream_t st);
+constexpr int MIX_MAX = 8;   // most input or output arrays of one stream-mix launch
+struct MixPtrs {
+  const double2* src[MIX_MAX];
+  double2* dst[MIX_MAX];
+};
+hipError_t launch_stream_mix(const MixPtrs& p, int nsrc, int ndst, int64_t nvec, hipStream_t st);
 
 // RK3 constants (Sec. 2.4, Eq. (17)); c_k = a_k + b_k.
 static const double RK_A[3] = {64.0 / 120.0, 50.0 / 120.0, 90.0 / 120.0};

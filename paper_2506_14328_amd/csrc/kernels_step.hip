@@ -72,7 +72,7 @@ __device__ __forceinline__ Pair<T> ld_pair(const T* p) { return *reinterpret_cas
 template <typename T>
 struct TileRaw {
   Pair<T> us, vs, ws, pp, ph, phw, phz, phy;
-  uint16_t tg;
+  uint16_t tg, keep;   // loaded tags; mask applied to them when the pair is stored
 };
 
 // The 1-D grid's blocks are dealt round-robin to the 8 XCDs (block b to XCD b mod 8, each
@@ -83,7 +83,7 @@ struct TileRaw {
 // concurrent HBM accesses close together).
 constexpr int NXCD = 8;
 
-template <typename T, bool SY, int MXT = MX, int MZT = MZ>
+template <typename T, bool SY, int MXT = MX, int MZT = MZ, int PF = 1>
 __device__ __forceinline__ void k_momentum_body(GridParams g, Fields<T> f, IbmLists L, StageConsts s, int jc,
                                                  int ntx, int ntz, int xcd_order, const double* __restrict__ pi_prev,
                                                  double ckdt_prev, double* __restrict__ qpart, int bid_x, int bid_y, int nblk) {
@@ -167,7 +167,15 @@ __device__ __forceinline__ void k_momentum_body(GridParams g, Fields<T> f, IbmLi
     // above a free-slip north face the row mirrors the top row's u and w (the clamped
     // load is that row); v on the face and p are zero there
     const uint16_t keep = (g.top_fs && jj == ny1) ? uint16_t(~((TAG_V | TAG_VI | TAG_P) * 0x0101u)) : uint16_t(0);
-    q.tg = inb ? t : uint16_t(t & keep);
+    // (with loads two planes ahead the mask is applied where the pair is stored: an
+    // operation on the loaded tag here would wait for this plane's loads at once)
+    if constexpr (PF == 2) {
+      q.tg = t;
+      q.keep = inb ? uint16_t(0xffff) : keep;
+    } else {
+      q.tg = inb ? t : uint16_t(t & keep);
+      q.keep = uint16_t(0xffff);
+    }
   };
   // corrected state of one fetched value (tag tg, its phi and west/back/south phi); an
   // external point inside the box holds the immersed walls' velocity (the south box-wall
@@ -188,7 +196,8 @@ __device__ __forceinline__ void k_momentum_body(GridParams g, Fields<T> f, IbmLi
     if (has) {
       const int e = 2 * tid;   // tile index of the pair's first value
       const Pair<T> phy = with_phy ? a.phy : phprev;   // a plane outside the box has tag 0
-      const uint8_t t0 = uint8_t(a.tg & 0xff), t1 = uint8_t(a.tg >> 8);
+      const uint16_t tgm = a.tg & a.keep;
+      const uint8_t t0 = uint8_t(tgm & 0xff), t1 = uint8_t(tgm >> 8);
       const int kd = (jj < 0 || jj >= ny1) ? 1 : (jj == 0 ? 2 : 0);
       T iyf = idy;
       if constexpr (SY) iyf = T(g.ytab[YT_IDYF * g.ystr + min(max(jj, 0), ny1 - 1)]);
@@ -210,7 +219,8 @@ __device__ __forceinline__ void k_momentum_body(GridParams g, Fields<T> f, IbmLi
   // four slots: plane j+2 goes to the slot of plane j-2, which no wave reads any more
   // once the barrier closing the previous plane has passed, so one barrier per plane
   auto slot = [](int jj) { return (jj + 4) & 3; };
-  // prologue: planes j0-1, j0, j0+1
+  // prologue: planes j0-1, j0, j0+1 into the ring
+  TileRaw<T> ha;
   {
     TileRaw<T> q0, q1, q2;
     fetch(j0 - 1, q0, true);
@@ -228,60 +238,88 @@ __device__ __forceinline__ void k_momentum_body(GridParams g, Fields<T> f, IbmLi
   const T akdt = T(s.ak_dt), bkdt = T(s.bk_dt), ckdt = T(s.ck_dt);
   double qloc = 0.0;
 
-  // This point's tag and the list offsets of the immersed-boundary points of its 64-wide
-  // row chunk are loaded one plane ahead (clamped into the box), so that the coefficient
-  // loads of a plane can be issued before its prefetch: loads complete in issue order, and
-  // waiting for loads issued before the prefetch does not wait for the prefetch.
+  // Per point and plane: the tag and the list offsets of the immersed-boundary points of
+  // the point's 64-wide row chunk (Ahead, loaded one plane before the coefficients that
+  // they index), and the point's (B, 1/A) and held right-hand sides (PointIn).  Loads
+  // complete in issue order, so each group is issued before the loads that are waited for
+  // later: waiting for it does not wait for them.  With PF = 1 a plane's coefficients and
+  // tile loads are issued in the plane's own iteration; with PF = 2 one iteration earlier,
+  // so that every load has a whole iteration to arrive.
+  struct Ahead {
+    uint8_t tg;
+    int cu, cv, cw;
+  };
+  struct PointIn {
+    uint8_t tg;
+    double2 cfu, cfv, cfw;
+    T hu, hv, hw;
+  };
   const int kc = k < nz ? k : nz - 1, icl = i < nx ? i : nx - 1;
-  uint8_t tgn = f.tag[j0 * plane + kc * nx + icl];
-  int chn_u, chn_v, chn_w;
-  {
-    const int ch = (j0 * nz + kc) * L.cpr + chk;
-    chn_u = L.choff_u[ch];
-    chn_v = L.choff_v[ch];
-    chn_w = L.choff_w[ch];
-  }
-  for (int j = j0; j < j1; ++j) {
-    const int c = j * plane + k * nx + i;
-    const uint8_t tg = act ? tgn : uint8_t(0);
+  auto load_ahead = [&](int jj, Ahead& a) {
+    const int jn = jj < ny1 ? jj : ny1 - 1;
+    a.tg = f.tag[jn * plane + kc * nx + icl];
+    const int ch = (jn * nz + kc) * L.cpr + chk;
+    a.cu = L.choff_u[ch];
+    a.cv = L.choff_v[ch];
+    a.cw = L.choff_w[ch];
+  };
+  auto load_point = [&](int jj, const Ahead& a, PointIn& q) {
+    const int jn = jj < ny1 ? jj : ny1 - 1;
+    const int c = jn * plane + k * nx + i;
+    const uint8_t tg = act ? a.tg : uint8_t(0);
+    q.tg = tg;
     // immersed-boundary points: list index = chunk offset + flagged lanes below (the
     // wavefront is the 64-wide chunk chk of row j*nz + k); (B, 1/A) of this point
     const uint64_t mu = __ballot((tg & TAG_UI) != 0);
     const uint64_t mv = __ballot((tg & TAG_VI) != 0);
     const uint64_t mw = __ballot((tg & TAG_WI) != 0);
     const size_t cb = (size_t)s.stage * L.n_total;
-    double2 cfu = {0.0, 0.0}, cfv = {0.0, 0.0}, cfw = {0.0, 0.0};
+    q.cfu = q.cfv = q.cfw = double2{0.0, 0.0};
     // (clamped to the list capacities: a geometry that overflowed them is reported and
     // never reads past its lists)
-    if (tg & TAG_UI) cfu = L.coef[cb + min(chn_u + lanes_below(mu, lane), L.n_u - 1)];
-    if (tg & TAG_VI) cfv = L.coef[cb + L.n_u + min(chn_v + lanes_below(mv, lane), L.n_v - 1)];
-    if (tg & TAG_WI) cfw = L.coef[cb + L.n_u + L.n_v + min(chn_w + lanes_below(mw, lane), L.n_w - 1)];
-    T hu = zero, hv = zero, hw = zero;
+    if (tg & TAG_UI) q.cfu = L.coef[cb + min(a.cu + lanes_below(mu, lane), L.n_u - 1)];
+    if (tg & TAG_VI) q.cfv = L.coef[cb + L.n_u + min(a.cv + lanes_below(mv, lane), L.n_v - 1)];
+    if (tg & TAG_WI) q.cfw = L.coef[cb + L.n_u + L.n_v + min(a.cw + lanes_below(mw, lane), L.n_w - 1)];
+    q.hu = q.hv = q.hw = T(0);
     if (act) {
       if (s.use_hold) {
         if (xcd_order & MOM_NT_LOAD) {
-          hu = __builtin_nontemporal_load(f.Hu + c);
-          hv = __builtin_nontemporal_load(f.Hv + c);
-          hw = __builtin_nontemporal_load(f.Hw + c);
+          q.hu = __builtin_nontemporal_load(f.Hu + c);
+          q.hv = __builtin_nontemporal_load(f.Hv + c);
+          q.hw = __builtin_nontemporal_load(f.Hw + c);
         } else {
-          hu = f.Hu[c];
-          hv = f.Hv[c];
-          hw = f.Hw[c];
+          q.hu = f.Hu[c];
+          q.hv = f.Hv[c];
+          q.hw = f.Hw[c];
         }
       }
     }
+  };
+  Ahead ta, tb;
+  PointIn pa, pb;
+  load_ahead(j0, ta);
+  if constexpr (PF == 2) {
+    // the loads a loop iteration finds in flight, in the loop's own issue order
+    load_point(j0, ta, pa);
+    load_ahead(j0 + 1, ta);
+    __builtin_amdgcn_sched_barrier(0);
+    fetch(j0 + 2, ha, false);
+  }
+  // one plane j: the loads of the next planes are issued (point data of plane j (PF = 1)
+  // or j+1 (PF = 2) into nxt with the offsets in use, offsets of the plane after that into
+  // next, tile plane j+1+PF into fill) before the arithmetic of plane j; afterwards plane
+  // j+2 (fill, or with PF = 2 the registers loaded one iteration earlier, hold) goes to the
+  // ring
+  auto plane_step = [&](int j, TileRaw<T>& hold, TileRaw<T>& fill, PointIn& cur, PointIn& nxt, Ahead& use,
+                        Ahead& next) {
+    const int c = j * plane + k * nx + i;
+    load_point(j + PF - 1, use, nxt);
+    load_ahead(j + PF, next);
     __builtin_amdgcn_sched_barrier(0);   // keep the loads above ahead of the prefetch
-    // prefetch plane j+2
-    TileRaw<T> nq;
-    fetch(j + 2, nq, false);
-    {
-      const int jn = j + 1 < ny1 ? j + 1 : ny1 - 1;
-      tgn = f.tag[jn * plane + kc * nx + icl];
-      const int ch = (jn * nz + kc) * L.cpr + chk;
-      chn_u = L.choff_u[ch];
-      chn_v = L.choff_v[ch];
-      chn_w = L.choff_w[ch];
-    }
+    fetch(j + 1 + PF, fill, false);
+    const uint8_t tg = cur.tg;
+    const double2 cfu = cur.cfu, cfv = cur.cfv, cfw = cur.cfw;
+    const T hu = cur.hu, hv = cur.hv, hw = cur.hw;
     const T* U0 = ring[0][slot(j)];
     const T* Um = ring[0][slot(j - 1)];
     const T* Up = ring[0][slot(j + 1)];
@@ -415,18 +453,30 @@ __device__ __forceinline__ void k_momentum_body(GridParams g, Fields<T> f, IbmLi
         if (tg & TAG_U) qloc += (double)su;
       }
     }
-    put(slot(j + 2), j + 2, nq, false);
+    if constexpr (PF == 2) put(slot(j + 2), j + 2, hold, false);
+    else put(slot(j + 2), j + 2, fill, false);
     __syncthreads();
+  };
+  if constexpr (PF == 2) {
+    // two register sets taking turns (no copies between them, which would wait for the
+    // loads in flight)
+    TileRaw<T> hb;
+    for (int j = j0; j < j1; j += 2) {
+      plane_step(j, ha, hb, pa, pb, ta, tb);
+      if (j + 1 < j1) plane_step(j + 1, hb, ha, pb, pa, tb, ta);
+    }
+  } else {
+    for (int j = j0; j < j1; ++j) plane_step(j, ha, ha, pa, pa, ta, ta);
   }
   const double tot = block_reduce<false>(qloc, red);
   if (tid == 0) qpart[bid_x] = tot;
 }
 
-template <typename T, bool SY, int MXT, int MZT>
+template <typename T, bool SY, int MXT, int MZT, int PF = 1>
 __global__ __launch_bounds__(MXT * MZT) void k_momentum(GridParams g, Fields<T> f, IbmLists L, StageConsts s, int jc,
                                                  int ntx, int ntz, int xcd_order, const double* __restrict__ pi_prev,
                                                  double ckdt_prev, double* __restrict__ qpart) {
-  k_momentum_body<T, SY, MXT, MZT>(g, f, L, s, jc, ntx, ntz, xcd_order, pi_prev, ckdt_prev, qpart, blockIdx.x,
+  k_momentum_body<T, SY, MXT, MZT, PF>(g, f, L, s, jc, ntx, ntz, xcd_order, pi_prev, ckdt_prev, qpart, blockIdx.x,
                                    blockIdx.y, gridDim.x);
 }
 
@@ -1121,7 +1171,38 @@ __global__ __launch_bounds__(256) void k_stream_copy(const uint4* __restrict__ s
   if (e < n) dst[e] = src[e];
 }
 
+// Streams nsrc arrays into ndst arrays (each output the element-wise FP64 sum of the
+// inputs), 16-byte vectors, one vector of every array per thread: the practical HBM
+// ceiling of a kernel with the same numbers of read and write streams (a kernel of a
+// step moves 5..8 read and 4..7 write streams at once, against the copy's one and one).
+__global__ __launch_bounds__(256) void k_stream_mix(MixPtrs p, int nsrc, int ndst, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  double2 v[MIX_MAX];
+#pragma unroll
+  for (int q = 0; q < MIX_MAX; ++q)
+    if (q < nsrc) v[q] = p.src[q][e];
+  double2 acc = v[0];
+#pragma unroll
+  for (int q = 1; q < MIX_MAX; ++q)
+    if (q < nsrc) {
+      acc.x += v[q].x;
+      acc.y += v[q].y;
+    }
+#pragma unroll
+  for (int q = 0; q < MIX_MAX; ++q)
+    if (q < ndst) p.dst[q][e] = acc;
+}
+
 }  // namespace
+
+hipError_t launch_stream_mix(const MixPtrs& p, int nsrc, int ndst, int64_t nvec, hipStream_t st) {
+  if (nvec <= 0) return hipSuccess;
+  const int64_t nb = (nvec + 255) / 256;
+  if (nb > 0x7fffffffll) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_stream_mix, dim3((unsigned)nb), dim3(256), 0, st, p, nsrc, ndst, nvec);
+  return hipGetLastError();
+}
 
 hipError_t launch_stream_copy(const void* src, void* dst, int64_t nvec, hipStream_t st) {
   if (nvec <= 0) return hipSuccess;
@@ -1138,19 +1219,26 @@ static inline dim3 cell_grid(const GridParams& g) {
   return dim3((g.nx + BX - 1) / BX, (g.nz + BZ - 1) / BZ, g.ny1);
 }
 
-// Momentum tile (x, z) of a tuning: 64 x 4 (automatic), 128 x 4, 64 x 8, 256 x 4, 128 x 8.
-static void momentum_tile(const Tuning& tu, int* tx, int* tz) {
-  static const int TXS[6] = {64, 64, 128, 64, 256, 128}, TZS[6] = {4, 4, 4, 8, 4, 8};
-  const int t = (tu.mom_tile >= 0 && tu.mom_tile < 6) ? tu.mom_tile : 0;
-  *tx = TXS[t];
-  *tz = TZS[t];
+// Momentum tile variant launched for a tuning: 0 64 x 4 (automatic), 2 128 x 4, 3 64 x 8,
+// 4 256 x 4, 5 128 x 8, 6 64 x 4 with two planes of loads in flight.  The two largest fit
+// the LDS only in FP32 storage, and stretched grids have the 64 x 4 kernel only: those
+// cases launch the 64 x 4 tile (variant 0).
+static int momentum_variant(const GridParams& g, const Tuning& tu, size_t esize) {
+  int t = (tu.mom_tile >= 0 && tu.mom_tile < 7) ? tu.mom_tile : 0;
+  if (t == 1 || g.stretched || (esize != 4 && (t == 4 || t == 5))) t = 0;
+  return t;
+}
+static void momentum_tile(int variant, int* tx, int* tz) {
+  static const int TXS[7] = {64, 64, 128, 64, 256, 128, 64}, TZS[7] = {4, 4, 4, 8, 4, 8, 4};
+  *tx = TXS[variant];
+  *tz = TZS[variant];
 }
 
 // y planes per momentum block: about 2048 blocks, 4..64 planes each, unless tuned.
-static int momentum_chunk(const GridParams& g, const Tuning& tu) {
+static int momentum_chunk(const GridParams& g, const Tuning& tu, size_t esize) {
   if (tu.mom_jc > 0) return tu.mom_jc < g.ny1 ? tu.mom_jc : g.ny1;
   int MX, MZ;
-  momentum_tile(tu, &MX, &MZ);
+  momentum_tile(momentum_variant(g, tu, esize), &MX, &MZ);
   const long cols = (long)((g.nx + MX - 1) / MX) * ((g.nz + MZ - 1) / MZ);
   long jc = (g.ny1 * cols + 2047) / 2048;
   if (jc < 4) jc = 4;
@@ -1162,9 +1250,10 @@ template <typename T>
 hipError_t launch_momentum(const GridParams& g, const Fields<T>& f, const IbmLists& L, const StageConsts& s,
                            const double* pi_prev, double ckdt_prev, const Tuning& tu, double* qpart, int* nqpart,
                            hipStream_t st) {
-  const int jc = momentum_chunk(g, tu);
+  const int var = momentum_variant(g, tu, sizeof(T));
+  const int jc = momentum_chunk(g, tu, sizeof(T));
   int tx, tz;
-  momentum_tile(tu, &tx, &tz);
+  momentum_tile(var, &tx, &tz);
   const int ntx = (g.nx + tx - 1) / tx, ntz = (g.nz + tz - 1) / tz, nty = (g.ny1 + jc - 1) / jc;
   const int nb = ntx * ntz * nty;
   const int cache = tu.mom_cache > 0 ? tu.mom_cache - 1 : 0;
@@ -1184,27 +1273,23 @@ hipError_t launch_momentum(const GridParams& g, const Fields<T>& f, const IbmLis
 #define IBM_LAUNCH_MOM(SYV, TXV, TZV)                                                                   \
   hipLaunchKernelGGL((k_momentum<T, SYV, TXV, TZV>), dim3(nb), dim3(TXV, TZV), 0, st, g, f, L, s, jc, ntx, ntz, xo, \
                      pi_prev, ckdt_prev, qpart)
-  bool done = false;
   if (g.stretched) {
     IBM_LAUNCH_MOM(true, 64, 4);
-    done = true;
-  } else if (tx == 128 && tz == 4) {
+  } else if (var == 6) {
+    hipLaunchKernelGGL((k_momentum<T, false, 64, 4, 2>), dim3(nb), dim3(64, 4), 0, st, g, f, L, s, jc, ntx, ntz, xo,
+                       pi_prev, ckdt_prev, qpart);
+  } else if (var == 2) {
     IBM_LAUNCH_MOM(false, 128, 4);
-    done = true;
-  } else if (tx == 64 && tz == 8) {
+  } else if (var == 3) {
     IBM_LAUNCH_MOM(false, 64, 8);
-    done = true;
-  }
-  if constexpr (sizeof(T) == 4) {   // the larger tiles fit the LDS only in FP32
-    if (!done && tx == 256 && tz == 4) {
-      IBM_LAUNCH_MOM(false, 256, 4);
-      done = true;
-    } else if (!done && tx == 128 && tz == 8) {
-      IBM_LAUNCH_MOM(false, 128, 8);
-      done = true;
+  } else if (var == 4 || var == 5) {
+    if constexpr (sizeof(T) == 4) {   // (momentum_variant gives these in FP32 only)
+      if (var == 4) IBM_LAUNCH_MOM(false, 256, 4);
+      else IBM_LAUNCH_MOM(false, 128, 8);
     }
+  } else {
+    IBM_LAUNCH_MOM(false, 64, 4);
   }
-  if (!done) IBM_LAUNCH_MOM(false, 64, 4);
 #undef IBM_LAUNCH_MOM
   *nqpart = nb;
   return hipGetLastError();
@@ -1407,7 +1492,7 @@ int plan_momentum(const GridParams& g, const Fields<T>& f, const IbmLists& L, co
                   const double* pi_prev, double ckdt_prev, const Tuning& tu0, double* qpart, MomArgs<T>* a) {
   Tuning tu = tu0;
   tu.mom_tile = 0;   // batched launches use the default tile
-  const int jc = momentum_chunk(g, tu);
+  const int jc = momentum_chunk(g, tu, sizeof(T));
   const int ntx = (g.nx + MX - 1) / MX, ntz = (g.nz + MZ - 1) / MZ, nty = (g.ny1 + jc - 1) / jc;
   const int nb = ntx * ntz * nty;
   *a = MomArgs<T>{g, f, L, s, jc, ntx, ntz, 0, pi_prev, ckdt_prev, qpart, nb};

@@ -29,7 +29,7 @@ EXPORTED = [
     "ibm_solve_pressure", "ibm_stats", "ibm_set_diagnostics", "ibm_get_geometry", "ibm_get_ibm_list",
     "ibm_profile", "ibm_profile_read", "ibm_kernel_name", "ibm_num_kernels", "ibm_device_bytes",
     "ibm_destroy", "ibm_last_error", "ibm_tune_set", "ibm_tune_get", "ibm_autotune", "ibm_wall_shear",
-    "ibm_set_wall_velocity", "ibm_set_y_faces", "ibm_stream_copy", "ibm_solve_pressure_noalloc",
+    "ibm_set_wall_velocity", "ibm_set_y_faces", "ibm_stream_copy", "ibm_stream_mix", "ibm_solve_pressure_noalloc",
 ]
 TUNE_PARAMS = {"momentum_planes": 0, "fftz_width": 1, "tri_rows": 2, "graph": 3, "graph_branches": 4,
                "tile_order": 5, "batch": 6, "momentum_cache": 7,
@@ -96,6 +96,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "ibm_destroy": (c_int32, [h]),
         "ibm_last_error": (ctypes.c_char_p, [h]),
         "ibm_stream_copy": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p]),
+        "ibm_stream_mix": (c_int32, [POINTER(c_void_p), c_int32, POINTER(c_void_p), c_int32, c_int64, c_void_p]),
         "ibm_solve_pressure_noalloc": (c_int32, [POINTER(IbmGridDesc), c_int32, c_void_p, c_void_p, c_void_p,
                                                  c_void_p]),
     }
@@ -122,6 +123,25 @@ def stream_copy(dst: torch.Tensor, src: torch.Tensor, stream: Optional[torch.cud
         raise ValueError("dst and src differ in size")
     st = stream if stream is not None else torch.cuda.current_stream(src.device)
     rc = lib.ibm_stream_copy(c_void_p(_ptr(dst)), c_void_p(_ptr(src)), nb, c_void_p(st.cuda_stream))
+    if rc != IBM_OK:
+        raise IbmError(rc, lib.ibm_last_error(None).decode())
+
+
+def stream_mix(dsts, srcs, stream: Optional[torch.cuda.Stream] = None):
+    """Every tensor of dsts <- the element-wise sum of the tensors of srcs (read as FP64)
+    with the library's stream-mix kernel (ibm_stream_mix): 1..8 contiguous GPU tensors on
+    each side, all of the same size in bytes (a multiple of 16), on torch's current stream."""
+    lib = load_library()
+    ts = list(dsts) + list(srcs)
+    if any(t.device.type != "cuda" or not t.is_contiguous() for t in ts):
+        raise TypeError("expected contiguous GPU tensors")
+    nb = ts[0].numel() * ts[0].element_size()
+    if any(t.numel() * t.element_size() != nb for t in ts):
+        raise ValueError("the tensors differ in size")
+    d = (c_void_p * max(1, len(dsts)))(*[_ptr(t) for t in dsts])
+    s = (c_void_p * max(1, len(srcs)))(*[_ptr(t) for t in srcs])
+    st = stream if stream is not None else torch.cuda.current_stream(ts[0].device)
+    rc = lib.ibm_stream_mix(d, len(dsts), s, len(srcs), nb, c_void_p(st.cuda_stream))
     if rc != IBM_OK:
         raise IbmError(rc, lib.ibm_last_error(None).decode())
 

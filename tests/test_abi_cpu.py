@@ -96,6 +96,35 @@ def test_invalid_descriptor_rejected(bad):
 
 
 @needs_lib
+def test_stream_kernels_validate_arguments():
+    """ibm_stream_copy and ibm_stream_mix reject null, misaligned or overlapping arrays,
+    counts outside 1..8 and sizes that are not multiples of 16 before any device work (the
+    addresses below are never dereferenced)."""
+    from paper_2506_14328_amd.ibm import IBM_ERR_ARG
+    lib = ctypes.CDLL(LIB)
+    vp = ctypes.c_void_p
+    lib.ibm_stream_copy.argtypes = [vp, vp, ctypes.c_int64, vp]
+    P = ctypes.POINTER(vp)
+    lib.ibm_stream_mix.argtypes = [P, ctypes.c_int32, P, ctypes.c_int32, ctypes.c_int64, vp]
+    A, B = 0x100000, 0x200000
+    assert lib.ibm_stream_copy(None, vp(A), 64, None) == IBM_ERR_ARG
+    assert lib.ibm_stream_copy(vp(B + 8), vp(A), 64, None) == IBM_ERR_ARG      # misaligned
+    assert lib.ibm_stream_copy(vp(B), vp(A), 40, None) == IBM_ERR_ARG          # not 16k
+    assert lib.ibm_stream_copy(vp(A + 32), vp(A), 64, None) == IBM_ERR_ARG     # overlap
+
+    def arr(*xs):
+        return (vp * len(xs))(*[vp(x) for x in xs])
+    assert lib.ibm_stream_mix(None, 1, arr(A), 1, 64, None) == IBM_ERR_ARG
+    assert lib.ibm_stream_mix(arr(B), 0, arr(A), 1, 64, None) == IBM_ERR_ARG
+    assert lib.ibm_stream_mix(arr(*[B + 0x1000 * q for q in range(9)]), 9, arr(A), 1, 64, None) == IBM_ERR_ARG
+    assert lib.ibm_stream_mix(arr(B), 1, arr(A), 1, 24, None) == IBM_ERR_ARG
+    assert lib.ibm_stream_mix(arr(B + 4), 1, arr(A), 1, 64, None) == IBM_ERR_ARG
+    assert lib.ibm_stream_mix(arr(B), 1, arr(B + 48), 1, 64, None) == IBM_ERR_ARG        # output on input
+    assert lib.ibm_stream_mix(arr(B, B + 32), 2, arr(A), 1, 64, None) == IBM_ERR_ARG     # outputs overlap
+    assert lib.ibm_last_error(None)
+
+
+@needs_lib
 def test_c_program_links_and_validates():
     """A C program built against include/ibm.h and linked with the library (no Python in
     between) names the kernels and gets IBM_ERR_ARG, with a message, for a descriptor the

@@ -284,6 +284,53 @@ def test_autotune_keeps_trajectory():
     g.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_momentum_variants_agree(prec):
+    """Every momentum tile (0..6; the larger ones are FP32-only and fall back to 64 x 4 in
+    FP64), tile order and a plane count that leaves a ragged last chunk (and an odd one, for
+    the variant that takes two planes per loop pass) give the oracle's state after 3 steps;
+    loads two planes ahead (tile 6) change nothing but timing: bitwise the 64 x 4 result."""
+    c = case("wavy_160")
+    o, sdf, st = oracle_run(c, 3)
+    tol = 1e-12 if prec == "fp64" else 1e-5
+    for jc in (5, 6):
+        base = None
+        for tile in range(7):
+            for order in (1, 2, 8):
+                g = gpu_grid(c, sdf, st, prec)
+                g.tune(momentum_tile=tile, tile_order=order, momentum_planes=jc)
+                g.step(3)
+                out = [t.double().cpu().numpy() for t in g.get_state()]
+                g.close()
+                for a, b in zip(out[:3], (o.u, o.v, o.w)):
+                    assert rel_err(a, b) < tol, (tile, order, jc)
+                if tile == 0 and order == 1:
+                    base = out
+                if tile == 6 and order == 1:
+                    assert all(np.array_equal(a, b) for a, b in zip(out, base)), jc
+
+
+def test_stream_mix_sums_its_inputs():
+    """ibm_stream_mix: every output receives the element-wise sum of the inputs, for 1..8
+    arrays on either side, including a size that is not a multiple of the block's 4 KiB."""
+    from paper_2506_14328_amd import stream_copy, stream_mix
+    gen = torch.Generator(device="cpu").manual_seed(3)
+    n = 1000 * 256 + 6   # 16-byte multiple, ragged last block
+    srcs = [torch.randn(n, generator=gen, dtype=torch.float64).to(device()) for _ in range(8)]
+    for ns, nd in ((1, 1), (5, 7), (8, 7), (8, 4), (3, 8)):
+        dsts = [torch.full((n,), -1.0, dtype=torch.float64, device=device()) for _ in range(nd)]
+        stream_mix(dsts, srcs[:ns])
+        # (the kernel adds in input order; so does the reference)
+        acc = srcs[0].clone()
+        for q in range(1, ns):
+            acc += srcs[q]
+        for d in dsts:
+            assert torch.equal(d, acc), (ns, nd)
+    y = torch.empty_like(srcs[0])
+    stream_copy(y, srcs[1])
+    assert torch.equal(y, srcs[1])
+
+
 def _ensemble_members():
     return [case("wavy_small"), case("flat_small"), case("ellip_small"), case("wavy_160", nu=1 / 700.0),
             case("minimal"), case("open_small")]

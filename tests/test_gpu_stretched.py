@@ -87,6 +87,23 @@ def test_step_parity_stretched_fp64(name, steps):
     g.close()
 
 
+def test_stretched_ignores_the_momentum_tile_setting():
+    """Stretched grids have the 64 x 4 momentum kernel only: any tile setting launches it
+    with its own tile geometry, bitwise the default's result."""
+    c = stretched("wavy_small")
+    o, sdf, st = oracle_run(c, 2)
+    outs = []
+    for tile in (0, 2, 3, 6):
+        g = gpu_grid(c, sdf, st)
+        g.tune(momentum_tile=tile)
+        g.step(2)
+        outs.append([t.cpu().numpy() for t in g.get_state()])
+        g.close()
+    assert rel_err(outs[0][0], o.u) < 1e-12
+    for out in outs[1:]:
+        assert all(np.array_equal(a, b) for a, b in zip(out, outs[0]))
+
+
 def test_step_stretched_fp32_storage():
     c = stretched("wavy_small")
     o, sdf, st = oracle_run(c, 3)
