@@ -42,6 +42,12 @@ def parse():
                     help="run warmup + steps without extra forms or baseline (for rocprofv3)")
     ap.add_argument("--tuning", default="",
                     help="fixed tuning knobs instead of the autotuner, e.g. momentum_planes=12,fftz_width=8")
+    ap.add_argument("--only-form", default="", choices=["", "ensemble", "masked", "moving", "shards"],
+                    help="run only this extra form (its own step counts, or --steps for the ensemble), print "
+                         "its JSON and exit (for rocprofv3 traces of the form)")
+    ap.add_argument("--stream-table", action="store_true",
+                    help="print the HBM throughput of the library's stream kernels for several numbers "
+                         "of read and write streams (arrays of one 512x257x256 field) and exit")
     ap.add_argument("--copy-calibration-mb", type=float, default=0.0,
                     help="also run the library's streaming copy of this many MiB three times (PMC counter "
                          "calibration)")
@@ -500,6 +506,39 @@ def stream_mix_bandwidth(cells, elem_bytes, reps=5):
     return gbs
 
 
+def stream_table(cells=512 * 256 * 256, reps=10):
+    """Read + write bytes per second of ibm_stream_copy and of ibm_stream_mix for several
+    (reads, writes) stream counts, FP64 arrays of `cells` values (and FP32-sized arrays for
+    the momentum kernel's mix), HIP events on torch's current stream."""
+    import torch
+    from paper_2506_14328_amd import stream_copy, stream_mix
+    rows = []
+
+    def timed(fn, nbytes):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        return nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    arrs = [torch.full((cells,), 1.0, dtype=torch.float64, device="cuda") for _ in range(16)]
+    gbs = timed(lambda: stream_copy(arrs[8], arrs[0]), 2 * cells * 8)
+    rows.append({"kernel": "stream_copy", "reads": 1, "writes": 1, "GBs": round(gbs, 1)})
+    for ns, nd in ((1, 1), (2, 2), (4, 4), (8, 1), (1, 7), (5, 7), (8, 7), (8, 4)):
+        gbs = timed(lambda: stream_mix(arrs[8:8 + nd], arrs[:ns]), (ns + nd) * cells * 8)
+        rows.append({"kernel": "stream_mix", "reads": ns, "writes": nd, "GBs": round(gbs, 1)})
+    del arrs
+    torch.cuda.empty_cache()
+    for eb in (8, 4):
+        rows.append({"kernel": "stream_mix", "mix": "momentum stages (5+7, 8+7, 8+4)",
+                     "array_bytes": cells * eb, "GBs": round(stream_mix_bandwidth(cells, eb), 1)})
+    for r in rows:
+        r["frac_of_peak"] = round(r["GBs"] / HBM_PEAK_GBS, 4)
+        print(json.dumps(r), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -511,6 +550,20 @@ def main():
         print(json.dumps({"error": "no GPU visible"}), flush=True)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if a.stream_table:
+        stream_table()
+        return
+    if a.only_form:
+        if a.only_form == "ensemble":
+            res = measure_ensemble(steps=a.steps)
+        elif a.only_form == "masked":
+            res = measure_masked()
+        elif a.only_form == "moving":
+            res = measure_moving_geometry()
+        else:
+            res = measure_shard_shapes()
+        print(json.dumps(res), flush=True)
+        return
 
     if a.copy_calibration_mb > 0:
         from paper_2506_14328_amd import stream_copy
