@@ -562,19 +562,28 @@ int run_steps(ibm_ctx* c, Instance& I, int nsteps, hipStream_t st, bool count = 
 
 
 // Writes the state (u, v, w, p) from the pending projection of the last substep.
+// With seed the corrected values also replace the predictor and pressure they came from,
+// and phi and Pi are zeroed: the state becomes the start of the next substep (what
+// seed_pending does with copies, in one pass).
 template <typename T>
-int materialize_t(ibm_ctx* c, Instance& I) {
+int materialize_t(ibm_ctx* c, Instance& I, bool seed) {
   // (recomputed even when it was already written: the host cannot see replays of graphs
   // the caller captured, after which the pending projection is newer than the state)
   if (I.fresh) return IBM_OK;
   Fields<T> f = fields_of<T>(I);
   f.us = f.usp; f.vs = f.vsp; f.ws = f.wsp;   // the predictor awaiting its projection
-  RUNK(c, K_CORRECT, launch_correct<T>(I.g, f, I.L, 2, rk_c(2) * I.g.dt, I.pi(), c->stream));
+  RUNK(c, K_CORRECT, launch_correct<T>(I.g, f, I.L, seed ? 1 : 0, rk_c(2) * I.g.dt, I.pi(), c->stream));
+  if (seed) {
+    // zeros by kernels, not memsets: a geometry update may be captured into a graph
+    HIPCHK(c, launch_fill_zero(I.phi, (int64_t)I.g.ncell * (int64_t)sizeof(T), c->stream));
+    HIPCHK(c, launch_fill_zero(I.pi(), (int64_t)sizeof(double), c->stream));
+    I.fresh = true;
+  }
   return IBM_OK;
 }
 
-int materialize(ibm_ctx* c, Instance& I) {
-  return c->precision == IBM_FP64 ? materialize_t<double>(c, I) : materialize_t<float>(c, I);
+int materialize(ibm_ctx* c, Instance& I, bool seed = false) {
+  return c->precision == IBM_FP64 ? materialize_t<double>(c, I, seed) : materialize_t<float>(c, I, seed);
 }
 
 // Makes the state in u, v, w, p the starting point of the next step: predictor and
@@ -1038,11 +1047,17 @@ int ibm_set_geometry(ibm_handle h, int32_t inst, const double* sdf_u, const doub
     if ((rc = refuse_capture(h))) return rc;
     drop_graph(h);
   }
-  if ((rc = materialize(h, I))) return rc;   // a pending projection belongs to the old geometry
+  // a pending projection belongs to the old geometry: it is applied (with its tags) and
+  // the result made the start of the next substep, which the new tags then act on.  Under
+  // a caller's capture it is recorded even if nothing is pending now, since the replays
+  // follow steps (with nothing pending it only resets the external points)
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(h->stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) I.fresh = false;
+  if ((rc = materialize(h, I, true))) return rc;
   bool sized = false;
   if ((rc = set_geometry_impl(h, I, sdf_u, sdf_v, sdf_w, &sized))) return rc;
   if (sized) drop_graph(h);
-  return seed_pending(h, I);
+  return IBM_OK;
 }
 
 int ibm_set_state(ibm_handle h, int32_t inst, const void* u, const void* v, const void* w, const void* p) {

@@ -403,7 +403,7 @@ template <typename T>
 hipError_t launch_ifftx(const GridParams& g, const cplx<T>* spec, T* out, const FFTPlan& px,
                         const double2* rtw, hipStream_t st);
 template <typename T>
-hipError_t launch_correct(const GridParams& g, const Fields<T>& f, const IbmLists& L, int stage, double ck_dt,
+hipError_t launch_correct(const GridParams& g, const Fields<T>& f, const IbmLists& L, int seed, double ck_dt,
                           const double* pi, hipStream_t st);
 
 // diagnostics

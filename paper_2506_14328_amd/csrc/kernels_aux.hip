@@ -115,8 +115,12 @@ __global__ __launch_bounds__(256) void k_geom_lambda(GridParams g, const double*
       t |= (comp == 0) ? TAG_U : TAG_W;
       if (lam > 0.0) t |= (comp == 0) ? TAG_UI : TAG_WI;
     }
-    (comp == 0 ? lam_u : lam_w)[c] = lam;
-    (comp == 0 ? sig_u : sig_w)[c] = sg;
+    // (stored at immersed-boundary points only: the coefficient kernel reads these arrays
+    // at the points of its lists, and skipping the rest saves most of this kernel's writes)
+    if (lam > 0.0) {
+      (comp == 0 ? lam_u : lam_w)[c] = lam;
+      (comp == 0 ? sig_u : sig_w)[c] = sg;
+    }
   }
   // v on face j; faces 0 and ny-1 are the box walls.
   {
@@ -152,8 +156,10 @@ __global__ __launch_bounds__(256) void k_geom_lambda(GridParams g, const double*
       t |= TAG_V;
       if (lam > 0.0) t |= TAG_VI;
     }
-    lam_v[c] = lam;
-    sig_v[c] = sg;
+    if (lam > 0.0) {
+      lam_v[c] = lam;
+      sig_v[c] = sg;
+    }
   }
   tag[c] = t;
 }

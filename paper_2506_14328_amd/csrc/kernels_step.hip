@@ -1126,12 +1126,13 @@ __global__ __launch_bounds__(256) void k_ifftx_b(const IfftxArgs<T>* __restrict_
 // u = u* - c_k dt G phi on internal faces (the pending -Pi c_k dt included), zero on
 // external faces (Sec. 3.3); p = p' + phi on internal pressure cells only (p' = f.pp).
 // The step itself folds this into the next momentum; this kernel materialises the state
-// on request.
+// on request.  With seed the values are also written back over the predictor and the
+// pressure they were computed from (f.us, f.pp: each point reads only its own), which
+// makes the state the start of the next substep once the caller zeroes phi and Pi.
 // ---------------------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_correct(GridParams g, Fields<T> f, IbmLists L, int stage, double ck_dt,
+__global__ __launch_bounds__(256) void k_correct(GridParams g, Fields<T> f, IbmLists L, int seed, double ck_dt,
                                                 const double* __restrict__ pi) {
-  (void)stage;
   const int i = blockIdx.x * BX + threadIdx.x;
   const int k = blockIdx.y * BZ + threadIdx.y;
   const int j = blockIdx.z;
@@ -1149,10 +1150,20 @@ __global__ __launch_bounds__(256) void k_correct(GridParams g, Fields<T> f, IbmL
   const T vn = vsv - ckdt * ((ph - phs) * T(g.stretched ? g.ytab[YT_IDYF * g.ystr + j] : g.idy));
   const T wn = wsv - ckdt * ((ph - phb) * T(g.idz));
   // external points hold the immersed walls' velocity (v on the south box wall: 0)
-  f.u[c] = (tg & TAG_U) ? un : T(L.wallv[0]);
-  f.v[c] = (tg & TAG_V) ? vn : (j == 0 ? T(0) : T(L.wallv[1]));
-  f.w[c] = (tg & TAG_W) ? wn : T(L.wallv[2]);
-  f.p[c] = (tg & TAG_P) ? pv + ph : T(0);
+  const T uo = (tg & TAG_U) ? un : T(L.wallv[0]);
+  const T vo = (tg & TAG_V) ? vn : (j == 0 ? T(0) : T(L.wallv[1]));
+  const T wo = (tg & TAG_W) ? wn : T(L.wallv[2]);
+  const T po = (tg & TAG_P) ? pv + ph : T(0);
+  f.u[c] = uo;
+  f.v[c] = vo;
+  f.w[c] = wo;
+  f.p[c] = po;
+  if (seed) {
+    f.us[c] = uo;
+    f.vs[c] = vo;
+    f.ws[c] = wo;
+    f.pp[c] = po;
+  }
 }
 
 template <typename T>
@@ -1465,9 +1476,9 @@ hipError_t launch_ifftx(const GridParams& g, const cplx<T>* spec, T* out, const 
 }
 
 template <typename T>
-hipError_t launch_correct(const GridParams& g, const Fields<T>& f, const IbmLists& L, int stage, double ck_dt,
+hipError_t launch_correct(const GridParams& g, const Fields<T>& f, const IbmLists& L, int seed, double ck_dt,
                           const double* pi, hipStream_t st) {
-  hipLaunchKernelGGL(k_correct<T>, cell_grid(g), dim3(BX, BZ), 0, st, g, f, L, stage, ck_dt, pi);
+  hipLaunchKernelGGL(k_correct<T>, cell_grid(g), dim3(BX, BZ), 0, st, g, f, L, seed, ck_dt, pi);
   return hipGetLastError();
 }
 
