@@ -350,7 +350,7 @@ int init_instance(ibm_ctx* c, Instance& I, const ibm_grid_desc& d) {
   HIPCHK(c, hipMemsetAsync(I.small, 0, 32 * sizeof(double), c->stream));
   I.L.wallv = I.wallv();
   I.L.sd = I.wall_sd();
-  if ((rc = dalloc(c, I, (void**)&I.itotal, 16 * sizeof(int32_t)))) return rc;
+  if ((rc = dalloc(c, I, (void**)&I.itotal, 32 * sizeof(int32_t)))) return rc;
   if (d.projection == IBM_PROJ_MASKED) {
     for (int q = 0; q < 4; ++q)
       if ((rc = dalloc(c, I, (void**)&I.pcg_v[q], (size_t)g.ncell * sizeof(double)))) return rc;
@@ -562,8 +562,8 @@ int run_steps(ibm_ctx* c, Instance& I, int nsteps, hipStream_t st, bool count = 
 
 
 // Writes the state (u, v, w, p) from the pending projection of the last substep.
-// With seed the corrected values also replace the predictor and pressure they came from,
-// and phi and Pi are zeroed: the state becomes the start of the next substep (what
+// With seed the corrected values also replace the predictor and pressure they came from:
+// once the caller zeroes phi and Pi, the state is the start of the next substep (what
 // seed_pending does with copies, in one pass).
 template <typename T>
 int materialize_t(ibm_ctx* c, Instance& I, bool seed) {
@@ -573,12 +573,7 @@ int materialize_t(ibm_ctx* c, Instance& I, bool seed) {
   Fields<T> f = fields_of<T>(I);
   f.us = f.usp; f.vs = f.vsp; f.ws = f.wsp;   // the predictor awaiting its projection
   RUNK(c, K_CORRECT, launch_correct<T>(I.g, f, I.L, seed ? 1 : 0, rk_c(2) * I.g.dt, I.pi(), c->stream));
-  if (seed) {
-    // zeros by kernels, not memsets: a geometry update may be captured into a graph
-    HIPCHK(c, launch_fill_zero(I.phi, (int64_t)I.g.ncell * (int64_t)sizeof(T), c->stream));
-    HIPCHK(c, launch_fill_zero(I.pi(), (int64_t)sizeof(double), c->stream));
-    I.fresh = true;
-  }
+  if (seed) I.fresh = true;   // (phi and Pi are zeroed by the caller's next kernel)
   return IBM_OK;
 }
 
@@ -614,7 +609,7 @@ void free_buf(DevBuf& b) {
 // body can be advanced between steps at the cost of a few kernels, also inside a graph
 // the caller captures.  *sized: whether the lists were (re)allocated.
 int set_geometry_impl(ibm_ctx* c, Instance& I, const double* su, const double* sv, const double* sw,
-                      bool* sized) {
+                      bool* sized, bool zero_pending) {
   const GridParams& g = I.g;
   hipStream_t st = c->stream;
   const size_t nc = (size_t)g.ncell;
@@ -647,24 +642,42 @@ int set_geometry_impl(ibm_ctx* c, Instance& I, const double* su, const double* s
   double* sig_w = sig_v + nc;
   int32_t* blk = (int32_t*)(sig_w + nc);
   // I.itotal: [0..6] counts of internal u, v, w, p and immersed-boundary u, v, w points,
-  // [8] the lists' overflow flag, [15] scratch total
+  // [8] the lists' overflow flag, [16..18] totals of the chunk counts (not used)
   int32_t* cnt7 = I.itotal;
   int32_t* overflow = I.itotal + 8;
-  int32_t* scratch_total = I.itotal + 15;
+  int32_t* chunk_totals = I.itotal + 16;
   const bool first = !I.ibm_idx.p || I.lists_overflowed;
   int rc = IBM_OK;
   do {
+    // (a projection applied just before has left phi and Pi to be zeroed: done here)
+    const int esz = c->precision == IBM_FP64 ? 8 : 4;
     hipError_t e = timed(c, K_GEOM, [&]() {
-      return launch_geom_lambda(g, su, sv, sw, I.d.ibm, I.tag, lam_u, lam_v, lam_w, sig_u, sig_v, sig_w, st);
+      return launch_geom_lambda(g, su, sv, sw, I.d.ibm, I.tag, lam_u, lam_v, lam_w, sig_u, sig_v, sig_w,
+                                zero_pending ? I.phi : nullptr, esz, zero_pending ? I.pi() : nullptr, st);
     });
-    if (e == hipSuccess) e = launch_geom_ptag(g, I.tag, st);
     if (e == hipSuccess) e = launch_geom_south_wall(g, su, I.d.ibm, I.wall_j, I.wall_d, st);
-    // per-block counts of the seven masks, scanned in place (block offsets) with totals
+    // pressure tags with the per-block counts of the seven masks (the overflow flag
+    // cleared), and the per-(row, 64-wide chunk) counts of the three immersed-boundary
+    // masks; then all ten count arrays scanned in place (offsets) in one launch
     const uint64_t masks = (uint64_t)TAG_U | ((uint64_t)TAG_V << 8) | ((uint64_t)TAG_W << 16) |
                            ((uint64_t)TAG_P << 24) | ((uint64_t)TAG_UI << 32) | ((uint64_t)TAG_VI << 40) |
                            ((uint64_t)TAG_WI << 48);
-    if (e == hipSuccess) e = launch_count_masks(I.tag, g.ncell, masks, 7, blk, nblk, st);
-    if (e == hipSuccess) e = launch_scan_multi(blk, nblk, nblk, 7, cnt7, st);
+    int32_t* choff = (int32_t*)I.ibm_choff.p;
+    if (e == hipSuccess) e = launch_geom_ptag_counts(g, I.tag, masks, 7, blk, nblk, overflow, st);
+    if (e == hipSuccess) e = launch_chunk_counts3(I.tag, g, cpr, choff, st);
+    ScanSet set{};
+    for (int m = 0; m < 7; ++m) {
+      set.counts[m] = blk + (size_t)m * nblk;
+      set.n[m] = nblk;
+      set.total[m] = cnt7 + m;
+    }
+    for (int m = 0; m < 3; ++m) {
+      set.counts[7 + m] = choff + (size_t)m * nch;
+      set.n[7 + m] = (int)nch;
+      set.total[7 + m] = chunk_totals + m;
+    }
+    set.narr = 10;
+    if (e == hipSuccess) e = launch_scan_multi(set, st);
     if (e != hipSuccess) { rc = fail(c, IBM_ERR_DEVICE, std::string("geometry: ") + hipGetErrorString(e)); break; }
     if (first) {
       int32_t cnt[7];
@@ -706,14 +719,9 @@ int set_geometry_impl(ibm_ctx* c, Instance& I, const double* su, const double* s
     double2* coef = (double2*)I.ibm_coef.p;
     double* lamo = (double*)I.ibm_lam.p;
     double* sigo = (double*)I.ibm_sig.p;
-    int32_t* choff = (int32_t*)I.ibm_choff.p;
-    e = launch_clear_flag(overflow, st);
-    if (e == hipSuccess) e = launch_compact3(I.tag, g.ncell, blk + 4 * (size_t)nblk, nblk, idx, I.cap, overflow, st);
+    e = launch_compact3(I.tag, g.ncell, blk + 4 * (size_t)nblk, nblk, idx, I.cap, overflow, st);
     if (e == hipSuccess) e = launch_ibm_coef3(idx, lam_u, sig_u, g.ncell, cnt7 + 4, I.cap, I.d.dt, I.d.b_mode, lamo,
                                               sigo, coef, st);
-    // per-(row, 64-wide chunk) list offsets of the three components
-    if (e == hipSuccess) e = launch_chunk_counts3(I.tag, g, cpr, choff, st);
-    if (e == hipSuccess) e = launch_scan_multi(choff, (int)nch, (int)nch, 3, scratch_total, st);
     if (e != hipSuccess) { rc = fail(c, IBM_ERR_DEVICE, std::string("ibm lists: ") + hipGetErrorString(e)); break; }
     I.L.choff_u = choff;
     I.L.choff_v = choff + nch;
@@ -731,8 +739,9 @@ int set_geometry_impl(ibm_ctx* c, Instance& I, const double* su, const double* s
     I.L.n_total = I.cap[0] + I.cap[1] + I.cap[2];
     I.L.n_cover = I.moving() ? I.L.n_total : I.L.n_u;
     int np = 0;
-    e = launch_s_k(g, I.tag, I.L, I.d.dt, I.red_part, &np, I.wall_sd(), st);
-    if (e == hipSuccess) e = launch_s_k_final(I.red_part, np, I.d.dt * y_scale(g) * g.dz / g.nx, I.S3(), st);
+    e = launch_s_k(g, I.tag, I.L, I.red_part, &np, st);
+    if (e == hipSuccess)
+      e = launch_s_k_final(I.red_part, np, I.d.dt * y_scale(g) * g.dz / g.nx, I.S3(), g, I.L, I.wall_sd(), st);
     if (e != hipSuccess) { rc = fail(c, IBM_ERR_DEVICE, std::string("S_k: ") + hipGetErrorString(e)); break; }
     if (first && (rc = sync_stream(c, st))) break;
     I.geom_ready = true;
@@ -1053,9 +1062,18 @@ int ibm_set_geometry(ibm_handle h, int32_t inst, const double* sdf_u, const doub
   // follow steps (with nothing pending it only resets the external points)
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(h->stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) I.fresh = false;
+  const bool pending = !I.fresh;
   if ((rc = materialize(h, I, true))) return rc;
   bool sized = false;
-  if ((rc = set_geometry_impl(h, I, sdf_u, sdf_v, sdf_w, &sized))) return rc;
+  if ((rc = set_geometry_impl(h, I, sdf_u, sdf_v, sdf_w, &sized, pending))) {
+    // (an update that failed before zeroing them must not leave phi and Pi to be applied
+    // a second time)
+    if (pending) {
+      (void)launch_fill_zero(I.phi, (int64_t)I.g.ncell * (h->precision == IBM_FP64 ? 8 : 4), h->stream);
+      (void)launch_fill_zero(I.pi(), (int64_t)sizeof(double), h->stream);
+    }
+    return rc;
+  }
   if (sized) drop_graph(h);
   return IBM_OK;
 }

@@ -416,10 +416,16 @@ hipError_t launch_reduce_final(const double* part, int npart, int nsum, int nmax
                                hipStream_t st);
 
 // geometry
+// tags, lambda and sigma (stored at immersed-boundary points only); with zphi, the cell's
+// phi (zelem bytes each) zeroed too, with zpi the mean pressure gradient
 hipError_t launch_geom_lambda(const GridParams& g, const double* su, const double* sv, const double* sw,
                               int ibm_on, uint8_t* tag, double* lam_u, double* lam_v, double* lam_w,
-                              double* sig_u, double* sig_v, double* sig_w, hipStream_t st);
-hipError_t launch_geom_ptag(const GridParams& g, uint8_t* tag, hipStream_t st);
+                              double* sig_u, double* sig_v, double* sig_w, void* zphi, int zelem, double* zpi,
+                              hipStream_t st);
+// pressure tags, then counts[m * nblk + block] of nm <= 8 tag masks (packed 8 bits each
+// into masks) per block of 256 cells (nblk blocks cover the cells); *clear zeroed
+hipError_t launch_geom_ptag_counts(const GridParams& g, uint8_t* tag, uint64_t masks, int nm, int32_t* counts,
+                                   int nblk, int32_t* clear, hipStream_t st);
 hipError_t launch_geom_south_wall(const GridParams& g, const double* su, int ibm_on, int32_t* wj, double* wd,
                                   hipStream_t st);
 // masked projection (conjugate gradients on the internal pressure cells): partial-sum
@@ -456,11 +462,16 @@ hipError_t launch_pcg_finish(const GridParams& g, const uint8_t* tag, double* x,
 template <typename T>
 hipError_t launch_wall_shear(const GridParams& g, const T* u, const int32_t* wj, const double* wd,
                              const double* wallv, double* tau_x, double* modes, hipStream_t st);
-// counts[m * nblk + block] for nm <= 8 masks packed 8 bits each into masks
-hipError_t launch_count_masks(const uint8_t* tag, int64_t n, uint64_t masks, int nm, int32_t* counts, int nblk,
-                              hipStream_t st);
-// exclusive scans of narr arrays of nblk counts (stride apart), their sums into totals
-hipError_t launch_scan_multi(int32_t* counts, int nblk, int stride, int narr, int32_t* totals, hipStream_t st);
+// exclusive scans in place of up to SCAN_MAX count arrays (one block each), their sums
+// into total[m]
+constexpr int SCAN_MAX = 12;
+struct ScanSet {
+  int32_t* counts[SCAN_MAX];
+  int32_t* total[SCAN_MAX];
+  int n[SCAN_MAX];
+  int narr;
+};
+hipError_t launch_scan_multi(const ScanSet& set, hipStream_t st);
 // the u, v, w immersed-boundary lists of capacities cap[] (laid end to end) from the
 // scanned per-block offsets of their masks (offsets[c * nblk + block]); overflow[0] set
 // when a component has more points than its capacity
@@ -473,14 +484,16 @@ hipError_t launch_ibm_coef3(const int32_t* idx, const double* lam_dense, const d
                             double* sig_out, double2* coef, hipStream_t st);
 // per-(row, 64-chunk) counts of the three immersed-boundary masks, [3][nrows cpr + 1]
 hipError_t launch_chunk_counts3(const uint8_t* tag, const GridParams& g, int cpr, int32_t* counts, hipStream_t st);
-hipError_t launch_clear_flag(int32_t* flag, hipStream_t st);
 hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t st);
 
-// partial sums for S_k into part[0 .. 4 npart); sd_out[k] = sum over the IBM u points of
-// sig / A_k (its partials after those of S_k: part needs 4 (npart + n_u/256 + 1) doubles)
-hipError_t launch_s_k(const GridParams& g, const uint8_t* tag, const IbmLists& L, double dt, double* part,
-                      int* npart, double* sd_out, hipStream_t st);
-hipError_t launch_s_k_final(const double* part, int npart, double scale, double* S3, hipStream_t st);
+// partial sums for S_k into part[0 .. 4 npart), then those of the sum over the IBM u
+// points of sig / A_k (part needs 4 (npart + n_u/256 + 1) doubles)
+hipError_t launch_s_k(const GridParams& g, const uint8_t* tag, const IbmLists& L, double* part, int* npart,
+                      hipStream_t st);
+// S3[k] from the partials; sd_out[k] (if not null) from the sigma/A partials launch_s_k
+// wrote after them
+hipError_t launch_s_k_final(const double* part, int npart, double scale, double* S3, const GridParams& g,
+                            const IbmLists& L, double* sd_out, hipStream_t st);
 
 // state copy helpers
 template <typename T>

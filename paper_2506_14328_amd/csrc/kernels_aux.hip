@@ -51,12 +51,16 @@ __device__ __forceinline__ double arm_src_w(double nu, double h, double d2, doub
 // Tags of u, v, w and lambda per component at every cell (j, k, i); with sig_* not null
 // also the wall-velocity coefficient sigma per component.
 //  sdf_u, sdf_w: (ny+1, nz, nx), row jj = j+1 holds row j; sdf_v: (ny, nz, nx) faces.
+// With zphi not null the cell's phi (zelem bytes) is zeroed too, and with zpi the mean
+// pressure gradient: what is pending of a projection that was applied just before.
 __global__ __launch_bounds__(256) void k_geom_lambda(GridParams g, const double* __restrict__ su,
                                                     const double* __restrict__ sv, const double* __restrict__ sw,
                                                     int ibm_on, uint8_t* __restrict__ tag,
                                                     double* __restrict__ lam_u, double* __restrict__ lam_v,
                                                     double* __restrict__ lam_w, double* __restrict__ sig_u,
-                                                    double* __restrict__ sig_v, double* __restrict__ sig_w) {
+                                                    double* __restrict__ sig_v, double* __restrict__ sig_w,
+                                                    unsigned char* __restrict__ zphi, int zelem,
+                                                    double* __restrict__ zpi) {
   const int i = blockIdx.x * BX + threadIdx.x;
   const int k = blockIdx.y * BZ + threadIdx.y;
   const int j = blockIdx.z;
@@ -65,6 +69,11 @@ __global__ __launch_bounds__(256) void k_geom_lambda(GridParams g, const double*
   const int ip = wrap_p(i, nx), im = wrap_m(i, nx), kp = wrap_p(k, nz), km = wrap_m(k, nz);
   const int plane = nx * nz;
   const int c = (j * nz + k) * nx + i;
+  if (zphi) {
+    if (zelem == 8) reinterpret_cast<double*>(zphi)[c] = 0.0;
+    else reinterpret_cast<float*>(zphi)[c] = 0.0f;
+  }
+  if (zpi && c == 0) zpi[0] = 0.0;
   const double nu = g.nu, dx = g.dx, dy = g.dy, dz = g.dz;
   const bool sy = g.stretched != 0;
   const double* yt = g.ytab;
@@ -164,20 +173,42 @@ __global__ __launch_bounds__(256) void k_geom_lambda(GridParams g, const double*
   tag[c] = t;
 }
 
-// Pressure cell internal iff one of its six faces is an internal velocity point.
-__global__ __launch_bounds__(256) void k_geom_ptag(GridParams g, uint8_t* __restrict__ tag) {
-  const int i = blockIdx.x * BX + threadIdx.x;
-  const int k = blockIdx.y * BZ + threadIdx.y;
-  const int j = blockIdx.z;
-  if (i >= g.nx || k >= g.nz) return;
-  const int nx = g.nx, nz = g.nz;
-  const int c = (j * nz + k) * nx + i;
-  const uint8_t t = tag[c];
-  const uint8_t te = tag[c - i + wrap_p(i, nx)] & TAG_U;
-  const uint8_t tn = (j + 1 < g.ny1) ? (tag[c + nx * nz] & TAG_V) : 0;
-  const uint8_t tt = tag[c + (wrap_p(k, nz) - k) * nx] & TAG_W;
-  const bool pin = (t & (TAG_U | TAG_V | TAG_W)) || te || tn || tt;
-  if (pin) tag[c] = t | TAG_P;
+// Pressure cell internal iff one of its six faces is an internal velocity point; then, per
+// block of 256 consecutive cells, the number of cells with each of nm tag masks set (mask
+// m in bits 8m..8m+7 of masks): counts[m * nblk + block]; block 0 also zeroes *clear (the
+// lists' overflow flag, by a kernel so that a geometry update can be captured).  A
+// neighbour's tag may gain its pressure bit while it is read here; only its velocity bits,
+// which no thread changes, are used.
+__global__ __launch_bounds__(256) void k_geom_ptag_counts(GridParams g, uint8_t* __restrict__ tag, uint64_t masks,
+                                                         int nm, int32_t* __restrict__ counts, int nblk,
+                                                         int32_t* __restrict__ clear) {
+  __shared__ int32_t wc[8][4];
+  const int64_t e = blockIdx.x * 256ll + threadIdx.x;
+  uint8_t t = 0;
+  if (e < g.ncell) {
+    const int nx = g.nx, nz = g.nz;
+    const int i = (int)(e % nx), k = (int)((e / nx) % nz), j = (int)(e / ((int64_t)nx * nz));
+    t = tag[e];
+    const uint8_t te = tag[e - i + wrap_p(i, nx)] & TAG_U;
+    const uint8_t tn = (j + 1 < g.ny1) ? (tag[e + (int64_t)nx * nz] & TAG_V) : 0;
+    const uint8_t tt = tag[e + (int64_t)(wrap_p(k, nz) - k) * nx] & TAG_W;
+    if ((t & (TAG_U | TAG_V | TAG_W)) || te || tn || tt) {
+      t |= TAG_P;
+      tag[e] = t;
+    }
+  }
+  if (clear && e == 0) clear[0] = 0;
+  const int lane = threadIdx.x % IBM_WAVE, wid = threadIdx.x / IBM_WAVE;
+  for (int m = 0; m < nm; ++m) {
+    const uint8_t mask = uint8_t((masks >> (8 * m)) & 0xffu);
+    const uint64_t b = __ballot((t & mask) != 0);
+    if (lane == 0) wc[m][wid] = __popcll(b);
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nm) {
+    const int m = threadIdx.x;
+    counts[(size_t)m * nblk + blockIdx.x] = wc[m][0] + wc[m][1] + wc[m][2] + wc[m][3];
+  }
 }
 
 // South-wall point of every (k, i) column of u points: the lowest internal u row j1 and
@@ -258,31 +289,11 @@ __device__ __forceinline__ void scan_counts_body(int32_t* __restrict__ counts, i
   if (tid == 0) total[0] = carry;
 }
 
-// The same for several arrays at once: block m scans counts[m * stride ..] and writes its
-// sum to total[m].
-__global__ __launch_bounds__(1024) void k_scan_multi(int32_t* __restrict__ counts, int nblk, int stride,
-                                                    int32_t* __restrict__ total) {
-  scan_counts_body(counts + (size_t)blockIdx.x * stride, nblk, total + blockIdx.x);
-}
-
-// Per block of 256 cells, the number of cells with each of nm tag masks set (mask m in
-// bits 8m..8m+7 of masks): counts[m * nblk + block].
-__global__ __launch_bounds__(256) void k_count_masks(const uint8_t* __restrict__ tag, int64_t n, uint64_t masks,
-                                                    int nm, int32_t* __restrict__ counts, int nblk) {
-  __shared__ int32_t wc[8][4];
-  const int64_t e = blockIdx.x * 256ll + threadIdx.x;
-  const uint8_t t = (e < n) ? tag[e] : uint8_t(0);
-  const int lane = threadIdx.x % IBM_WAVE, wid = threadIdx.x / IBM_WAVE;
-  for (int m = 0; m < nm; ++m) {
-    const uint8_t mask = uint8_t((masks >> (8 * m)) & 0xffu);
-    const uint64_t b = __ballot((t & mask) != 0);
-    if (lane == 0) wc[m][wid] = __popcll(b);
-  }
-  __syncthreads();
-  if ((int)threadIdx.x < nm) {
-    const int m = threadIdx.x;
-    counts[(size_t)m * nblk + blockIdx.x] = wc[m][0] + wc[m][1] + wc[m][2] + wc[m][3];
-  }
+// The same for several arrays at once: block m scans set.counts[m] (set.n[m] counts) and
+// writes its sum to set.total[m].
+__global__ __launch_bounds__(1024) void k_scan_multi(ScanSet set) {
+  const int m = blockIdx.x;
+  scan_counts_body(set.counts[m], set.n[m], set.total[m]);
 }
 
 // The ascending cell indices of the u, v and w immersed-boundary points (tag bits
@@ -380,11 +391,6 @@ __global__ __launch_bounds__(256) void k_chunk_counts3(const uint8_t* __restrict
   counts[2 * nch + e] = n2;
 }
 
-// overflow[0] = 0 (a kernel, so that a geometry update can be captured into a graph)
-__global__ void k_clear_flag(int32_t* __restrict__ flag) {
-  if (threadIdx.x == 0) flag[0] = 0;
-}
-
 // bytes zeros from p (a kernel: no memset nodes in captured graphs): nvec 16-byte vectors
 // (p 16-byte aligned, nvec = 0 otherwise), the remaining bytes by thread 0 of block 0
 __global__ __launch_bounds__(256) void k_fill_zero(unsigned char* __restrict__ p, int64_t nvec, int64_t bytes) {
@@ -440,20 +446,11 @@ __global__ __launch_bounds__(256) void k_s_list(GridParams g, IbmLists L, double
     part_sd[blockIdx.x * 4 + 3] = 0.0;
   }
 }
-// out[k] = sum of the npart partials of stage k (fixed order; zero for no partials)
-__global__ __launch_bounds__(1024) void k_sd_final(const double* __restrict__ part, int npart,
-                                                  double* __restrict__ out) {
-  __shared__ double red[16];
-  for (int k = 0; k < 3; ++k) {
-    double s = 0.0;
-    for (int e = threadIdx.x; e < npart; e += blockDim.x) s += part[e * 4 + k];
-    const double r = block_reduce<false>(s, red);
-    if (threadIdx.x == 0) out[k] = r;
-    __syncthreads();
-  }
-}
+// S3[k] = S_k from the npart partials of part; with sd_out, sd_out[k] = the sum of the nsd
+// partials of stage k in part_sd (fixed orders; zero for no partials)
 __global__ __launch_bounds__(1024) void k_s_final(const double* __restrict__ part, int npart, double scale,
-                                                 double* __restrict__ S3) {
+                                                 double* __restrict__ S3, const double* __restrict__ part_sd,
+                                                 int nsd, double* __restrict__ sd_out) {
   __shared__ double red[16];
   double acc[4];
   for (int v = 0; v < 4; ++v) {
@@ -467,6 +464,14 @@ __global__ __launch_bounds__(1024) void k_s_final(const double* __restrict__ par
       const double ckdt = rk_c(k) * scale;   // scale carries dt dy dz / nx
       S3[k] = (acc[0] + acc[1 + k]) * ckdt;
     }
+  }
+  if (!sd_out) return;
+  for (int k = 0; k < 3; ++k) {
+    double s = 0.0;
+    for (int e = threadIdx.x; e < nsd; e += blockDim.x) s += part_sd[e * 4 + k];
+    const double r = block_reduce<false>(s, red);
+    if (threadIdx.x == 0) sd_out[k] = r;
+    __syncthreads();
   }
 }
 
@@ -683,14 +688,17 @@ static inline dim3 cell_grid(const GridParams& g) {
 
 hipError_t launch_geom_lambda(const GridParams& g, const double* su, const double* sv, const double* sw,
                               int ibm_on, uint8_t* tag, double* lam_u, double* lam_v, double* lam_w,
-                              double* sig_u, double* sig_v, double* sig_w, hipStream_t st) {
+                              double* sig_u, double* sig_v, double* sig_w, void* zphi, int zelem, double* zpi,
+                              hipStream_t st) {
   hipLaunchKernelGGL(k_geom_lambda, cell_grid(g), dim3(BX, BZ), 0, st, g, su, sv, sw, ibm_on, tag, lam_u, lam_v,
-                     lam_w, sig_u, sig_v, sig_w);
+                     lam_w, sig_u, sig_v, sig_w, (unsigned char*)zphi, zelem, zpi);
   return hipGetLastError();
 }
 
-hipError_t launch_geom_ptag(const GridParams& g, uint8_t* tag, hipStream_t st) {
-  hipLaunchKernelGGL(k_geom_ptag, cell_grid(g), dim3(BX, BZ), 0, st, g, tag);
+hipError_t launch_geom_ptag_counts(const GridParams& g, uint8_t* tag, uint64_t masks, int nm, int32_t* counts,
+                                   int nblk, int32_t* clear, hipStream_t st) {
+  if ((int64_t)nblk * 256 < g.ncell || nm > 8) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_geom_ptag_counts, dim3(nblk), dim3(256), 0, st, g, tag, masks, nm, counts, nblk, clear);
   return hipGetLastError();
 }
 
@@ -714,14 +722,9 @@ template hipError_t launch_wall_shear<double>(const GridParams&, const double*, 
 template hipError_t launch_wall_shear<float>(const GridParams&, const float*, const int32_t*, const double*,
                                              const double*, double*, double*, hipStream_t);
 
-hipError_t launch_count_masks(const uint8_t* tag, int64_t n, uint64_t masks, int nm, int32_t* counts, int nblk,
-                              hipStream_t st) {
-  hipLaunchKernelGGL(k_count_masks, dim3(nblk), dim3(256), 0, st, tag, n, masks, nm, counts, nblk);
-  return hipGetLastError();
-}
-
-hipError_t launch_scan_multi(int32_t* counts, int nblk, int stride, int narr, int32_t* totals, hipStream_t st) {
-  hipLaunchKernelGGL(k_scan_multi, dim3(narr), dim3(1024), 0, st, counts, nblk, stride, totals);
+hipError_t launch_scan_multi(const ScanSet& set, hipStream_t st) {
+  if (set.narr < 1 || set.narr > SCAN_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_scan_multi, dim3(set.narr), dim3(1024), 0, st, set);
   return hipGetLastError();
 }
 
@@ -748,10 +751,6 @@ hipError_t launch_chunk_counts3(const uint8_t* tag, const GridParams& g, int cpr
   return hipGetLastError();
 }
 
-hipError_t launch_clear_flag(int32_t* flag, hipStream_t st) {
-  hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(64), 0, st, flag);
-  return hipGetLastError();
-}
 
 hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t st) {
   if (bytes <= 0) return hipSuccess;
@@ -761,21 +760,23 @@ hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_s_k(const GridParams& g, const uint8_t* tag, const IbmLists& L, double dt, double* part,
-                      int* npart, double* sd_out, hipStream_t st) {
-  (void)dt;
+hipError_t launch_s_k(const GridParams& g, const uint8_t* tag, const IbmLists& L, double* part, int* npart,
+                      hipStream_t st) {
   const int nb1 = (int)((g.ncell + 255) / 256);
   const int nb2 = (L.n_u + 255) / 256;
   double* part_sd = part + (size_t)(nb1 + nb2) * 4;
   hipLaunchKernelGGL(k_s_cells, dim3(nb1), dim3(256), 0, st, g, tag, part);
   if (nb2 > 0) hipLaunchKernelGGL(k_s_list, dim3(nb2), dim3(256), 0, st, g, L, part + (size_t)nb1 * 4, part_sd);
-  hipLaunchKernelGGL(k_sd_final, dim3(1), dim3(1024), 0, st, part_sd, nb2, sd_out);
   *npart = nb1 + nb2;
   return hipGetLastError();
 }
 
-hipError_t launch_s_k_final(const double* part, int npart, double scale, double* S3, hipStream_t st) {
-  hipLaunchKernelGGL(k_s_final, dim3(1), dim3(1024), 0, st, part, npart, scale, S3);
+hipError_t launch_s_k_final(const double* part, int npart, double scale, double* S3, const GridParams& g,
+                            const IbmLists& L, double* sd_out, hipStream_t st) {
+  const int nb1 = (int)((g.ncell + 255) / 256);
+  const int nb2 = (L.n_u + 255) / 256;
+  const double* part_sd = part + (size_t)(nb1 + nb2) * 4;
+  hipLaunchKernelGGL(k_s_final, dim3(1), dim3(1024), 0, st, part, npart, scale, S3, part_sd, nb2, sd_out);
   return hipGetLastError();
 }
 
