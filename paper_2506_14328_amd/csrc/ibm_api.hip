@@ -663,8 +663,10 @@ int set_geometry_impl(ibm_ctx* c, Instance& I, const double* su, const double* s
                            ((uint64_t)TAG_P << 24) | ((uint64_t)TAG_UI << 32) | ((uint64_t)TAG_VI << 40) |
                            ((uint64_t)TAG_WI << 48);
     int32_t* choff = (int32_t*)I.ibm_choff.p;
-    if (e == hipSuccess) e = launch_geom_ptag_counts(g, I.tag, masks, 7, blk, nblk, overflow, st);
-    if (e == hipSuccess) e = launch_chunk_counts3(I.tag, g, cpr, choff, st);
+    const bool whole_chunks = g.nx % IBM_WAVE == 0;
+    if (e == hipSuccess)
+      e = launch_geom_ptag_counts(g, I.tag, masks, 7, blk, nblk, overflow, whole_chunks ? choff : nullptr, st);
+    if (e == hipSuccess && !whole_chunks) e = launch_chunk_counts3(I.tag, g, cpr, choff, st);
     ScanSet set{};
     for (int m = 0; m < 7; ++m) {
       set.counts[m] = blk + (size_t)m * nblk;
@@ -719,9 +721,8 @@ int set_geometry_impl(ibm_ctx* c, Instance& I, const double* su, const double* s
     double2* coef = (double2*)I.ibm_coef.p;
     double* lamo = (double*)I.ibm_lam.p;
     double* sigo = (double*)I.ibm_sig.p;
-    e = launch_compact3(I.tag, g.ncell, blk + 4 * (size_t)nblk, nblk, idx, I.cap, overflow, st);
-    if (e == hipSuccess) e = launch_ibm_coef3(idx, lam_u, sig_u, g.ncell, cnt7 + 4, I.cap, I.d.dt, I.d.b_mode, lamo,
-                                              sigo, coef, st);
+    e = launch_compact3(I.tag, g.ncell, blk + 4 * (size_t)nblk, nblk, idx, I.cap, overflow, lam_u, sig_u, I.d.dt,
+                        I.d.b_mode, lamo, sigo, coef, st);
     if (e != hipSuccess) { rc = fail(c, IBM_ERR_DEVICE, std::string("ibm lists: ") + hipGetErrorString(e)); break; }
     I.L.choff_u = choff;
     I.L.choff_v = choff + nch;
@@ -741,7 +742,8 @@ int set_geometry_impl(ibm_ctx* c, Instance& I, const double* su, const double* s
     int np = 0;
     e = launch_s_k(g, I.tag, I.L, I.red_part, &np, st);
     if (e == hipSuccess)
-      e = launch_s_k_final(I.red_part, np, I.d.dt * y_scale(g) * g.dz / g.nx, I.S3(), g, I.L, I.wall_sd(), st);
+      e = launch_s_k_final(I.red_part, np, I.d.dt * y_scale(g) * g.dz / g.nx, I.S3(), g, I.L, cnt7, I.wall_sd(),
+                           st);
     if (e != hipSuccess) { rc = fail(c, IBM_ERR_DEVICE, std::string("S_k: ") + hipGetErrorString(e)); break; }
     if (first && (rc = sync_stream(c, st))) break;
     I.geom_ready = true;

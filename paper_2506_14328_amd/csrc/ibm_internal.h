@@ -423,9 +423,10 @@ hipError_t launch_geom_lambda(const GridParams& g, const double* su, const doubl
                               double* sig_u, double* sig_v, double* sig_w, void* zphi, int zelem, double* zpi,
                               hipStream_t st);
 // pressure tags, then counts[m * nblk + block] of nm <= 8 tag masks (packed 8 bits each
-// into masks) per block of 256 cells (nblk blocks cover the cells); *clear zeroed
+// into masks) per block of 256 cells (nblk blocks cover the cells); *clear zeroed; with
+// chunks (nx a multiple of 64) the per-(row, 64-chunk) immersed-boundary counts as well
 hipError_t launch_geom_ptag_counts(const GridParams& g, uint8_t* tag, uint64_t masks, int nm, int32_t* counts,
-                                   int nblk, int32_t* clear, hipStream_t st);
+                                   int nblk, int32_t* clear, int32_t* chunks, hipStream_t st);
 hipError_t launch_geom_south_wall(const GridParams& g, const double* su, int ibm_on, int32_t* wj, double* wd,
                                   hipStream_t st);
 // masked projection (conjugate gradients on the internal pressure cells): partial-sum
@@ -473,15 +474,12 @@ struct ScanSet {
 };
 hipError_t launch_scan_multi(const ScanSet& set, hipStream_t st);
 // the u, v, w immersed-boundary lists of capacities cap[] (laid end to end) from the
-// scanned per-block offsets of their masks (offsets[c * nblk + block]); overflow[0] set
-// when a component has more points than its capacity
+// scanned per-block offsets of their masks (offsets[c * nblk + block]), with each point's
+// lambda, sigma (from lam_dense, sig_dense: three dense component arrays of n values) and
+// per-stage (B, 1/A); overflow[0] set when a component has more points than its capacity
 hipError_t launch_compact3(const uint8_t* tag, int64_t n, const int32_t* offsets, int nblk, int32_t* idx,
-                           const int cap[3], int32_t* overflow, hipStream_t st);
-// lambda, sigma and (B, 1/A) of the listed points (cnt[c] per component, at most cap[c]);
-// lam_dense, sig_dense: three dense component arrays of ncell values each
-hipError_t launch_ibm_coef3(const int32_t* idx, const double* lam_dense, const double* sig_dense, int64_t ncell,
-                            const int32_t* cnt, const int cap[3], double dt, int b_mode, double* lam_out,
-                            double* sig_out, double2* coef, hipStream_t st);
+                           const int cap[3], int32_t* overflow, const double* lam_dense, const double* sig_dense,
+                           double dt, int b_mode, double* lam_out, double* sig_out, double2* coef, hipStream_t st);
 // per-(row, 64-chunk) counts of the three immersed-boundary masks, [3][nrows cpr + 1]
 hipError_t launch_chunk_counts3(const uint8_t* tag, const GridParams& g, int cpr, int32_t* counts, hipStream_t st);
 hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t st);
@@ -493,7 +491,7 @@ hipError_t launch_s_k(const GridParams& g, const uint8_t* tag, const IbmLists& L
 // S3[k] from the partials; sd_out[k] (if not null) from the sigma/A partials launch_s_k
 // wrote after them
 hipError_t launch_s_k_final(const double* part, int npart, double scale, double* S3, const GridParams& g,
-                            const IbmLists& L, double* sd_out, hipStream_t st);
+                            const IbmLists& L, const int32_t* cnt7, double* sd_out, hipStream_t st);
 
 // state copy helpers
 template <typename T>

@@ -179,9 +179,12 @@ __global__ __launch_bounds__(256) void k_geom_lambda(GridParams g, const double*
 // lists' overflow flag, by a kernel so that a geometry update can be captured).  A
 // neighbour's tag may gain its pressure bit while it is read here; only its velocity bits,
 // which no thread changes, are used.
+// With chunks not null (rows of whole 64-wide chunks: nx a multiple of 64) it also
+// writes the per-(row, chunk) counts of the three immersed-boundary masks, laid out as
+// k_chunk_counts3 writes them (wave w of block b is chunk 4b + w).
 __global__ __launch_bounds__(256) void k_geom_ptag_counts(GridParams g, uint8_t* __restrict__ tag, uint64_t masks,
                                                          int nm, int32_t* __restrict__ counts, int nblk,
-                                                         int32_t* __restrict__ clear) {
+                                                         int32_t* __restrict__ clear, int32_t* __restrict__ chunks) {
   __shared__ int32_t wc[8][4];
   const int64_t e = blockIdx.x * 256ll + threadIdx.x;
   uint8_t t = 0;
@@ -199,6 +202,15 @@ __global__ __launch_bounds__(256) void k_geom_ptag_counts(GridParams g, uint8_t*
   }
   if (clear && e == 0) clear[0] = 0;
   const int lane = threadIdx.x % IBM_WAVE, wid = threadIdx.x / IBM_WAVE;
+  if (chunks) {
+    const int64_t nch = g.ncell / IBM_WAVE + 1;   // whole chunks, and one zero entry
+    const int64_t ch = e / IBM_WAVE;              // the same for every lane of the wave
+    for (int c = 0; c < 3; ++c) {
+      const uint64_t b = __ballot((t & (TAG_UI << c)) != 0);
+      if (lane == 0 && ch < nch - 1) chunks[c * nch + ch] = __popcll(b);
+      if (e == 0) chunks[c * nch + nch - 1] = 0;
+    }
+  }
   for (int m = 0; m < nm; ++m) {
     const uint8_t mask = uint8_t((masks >> (8 * m)) & 0xffu);
     const uint64_t b = __ballot((t & mask) != 0);
@@ -300,10 +312,33 @@ __global__ __launch_bounds__(1024) void k_scan_multi(ScanSet set) {
 // TAG_UI << c) at their scanned block offsets offsets[c * nblk + block], into the
 // component's list, which starts at list_off[c] and holds cap[c] entries; a point whose
 // rank reaches the capacity is not written and sets overflow[0].
+// Per-stage (B, 1/A) of a point with coefficient lam (Eqs. (14)-(16)): x = lam c_k dt.
+__device__ __forceinline__ double2 ibm_stage_coef(double lam, int k, double dt, int b_mode) {
+  const double x = lam * rk_c(k) * dt;
+  double B, A;
+  if (b_mode == 1) {          // implicit Euler: B = 1
+    B = 1.0;
+    A = 1.0 + x;
+  } else if (b_mode == 2) {   // reciprocal of the second-order Taylor expansion of 1/B
+    B = 1.0 / (1.0 + 0.5 * x);
+    A = x + B;
+  } else {                    // exponential fit B = x / (e^x - 1)
+    B = (x > 700.0) ? 0.0 : ((x > 0.0) ? x / expm1(x) : 1.0);
+    A = x + B;
+  }
+  return make_double2(B, 1.0 / A);
+}
+
+// ... and with each listed point its lambda, sigma (from the dense per-component arrays,
+// component c at c * n) and per-stage (B, 1/A): coef[k * cap_total + entry].
 __global__ __launch_bounds__(256) void k_compact3(const uint8_t* __restrict__ tag, int64_t n,
                                                  const int32_t* __restrict__ offsets, int nblk,
                                                  int32_t* __restrict__ idx, int off_v, int off_w, int cap_u,
-                                                 int cap_v, int cap_w, int32_t* __restrict__ overflow) {
+                                                 int cap_v, int cap_w, int32_t* __restrict__ overflow,
+                                                 const double* __restrict__ lam_dense,
+                                                 const double* __restrict__ sig_dense, double dt, int b_mode,
+                                                 double* __restrict__ lam_out, double* __restrict__ sig_out,
+                                                 double2* __restrict__ coef) {
   __shared__ int32_t wc[3][4];
   const int64_t e = blockIdx.x * 256ll + threadIdx.x;
   const uint8_t t = (e < n) ? tag[e] : uint8_t(0);
@@ -322,46 +357,17 @@ __global__ __launch_bounds__(256) void k_compact3(const uint8_t* __restrict__ ta
     const int r = base + __popcll(bal[c] & below);
     const int cap = c == 0 ? cap_u : (c == 1 ? cap_v : cap_w);
     const int off = c == 0 ? 0 : (c == 1 ? off_v : off_w);
-    if (r < cap) idx[off + r] = (int32_t)e;
-    else overflow[0] = 1;
-  }
-}
-
-// lambda, sigma and per-stage (B, 1/A) of every immersed-boundary point of the three
-// component lists (Eqs. (14)-(16)); entry e of the capacity-strided lists, component c
-// from the capacities, its points counted by cnt[c] (entries past it are left alone).
-__global__ __launch_bounds__(256) void k_ibm_coef3(const int32_t* __restrict__ idx,
-                                                  const double* __restrict__ lam_dense,
-                                                  const double* __restrict__ sig_dense, int64_t ncell,
-                                                  const int32_t* __restrict__ cnt, int cap_u, int cap_v,
-                                                  int cap_total, double dt, int b_mode,
-                                                  double* __restrict__ lam_out, double* __restrict__ sig_out,
-                                                  double2* __restrict__ coef) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= cap_total) return;
-  const int c = e < cap_u ? 0 : (e < cap_u + cap_v ? 1 : 2);
-  const int off = c == 0 ? 0 : (c == 1 ? cap_u : cap_u + cap_v);
-  const int cap = c == 0 ? cap_u : (c == 1 ? cap_v : cap_total - cap_u - cap_v);
-  if (e - off >= min(cnt[c], cap)) return;
-  const int cell = idx[e];
-  const double lam = lam_dense[(size_t)c * ncell + cell];
-  lam_out[e] = lam;
-  sig_out[e] = sig_dense[(size_t)c * ncell + cell];
-  for (int k = 0; k < 3; ++k) {
-    const double ck = rk_c(k);
-    const double x = lam * ck * dt;
-    double B, A;
-    if (b_mode == 1) {          // implicit Euler: B = 1
-      B = 1.0;
-      A = 1.0 + x;
-    } else if (b_mode == 2) {   // reciprocal of the second-order Taylor expansion of 1/B
-      B = 1.0 / (1.0 + 0.5 * x);
-      A = x + B;
-    } else {                    // exponential fit B = x / (e^x - 1)
-      B = (x > 700.0) ? 0.0 : ((x > 0.0) ? x / expm1(x) : 1.0);
-      A = x + B;
+    if (r < cap) {
+      const int q = off + r;
+      idx[q] = (int32_t)e;
+      const double lam = lam_dense[(size_t)c * n + e];
+      lam_out[q] = lam;
+      sig_out[q] = sig_dense[(size_t)c * n + e];
+      const int cap_total = cap_u + cap_v + cap_w;
+      for (int k = 0; k < 3; ++k) coef[(size_t)k * cap_total + q] = ibm_stage_coef(lam, k, dt, b_mode);
+    } else {
+      overflow[0] = 1;
     }
-    coef[(size_t)k * cap_total + e] = make_double2(B, 1.0 / A);
   }
 }
 
@@ -448,9 +454,12 @@ __global__ __launch_bounds__(256) void k_s_list(GridParams g, IbmLists L, double
 }
 // S3[k] = S_k from the npart partials of part; with sd_out, sd_out[k] = the sum of the nsd
 // partials of stage k in part_sd (fixed orders; zero for no partials)
+// With cnt7 (uniform grids) the internal non-IBM u points are its internal u count minus
+// its immersed-boundary u count (every immersed-boundary u point is internal).
 __global__ __launch_bounds__(1024) void k_s_final(const double* __restrict__ part, int npart, double scale,
                                                  double* __restrict__ S3, const double* __restrict__ part_sd,
-                                                 int nsd, double* __restrict__ sd_out) {
+                                                 int nsd, double* __restrict__ sd_out,
+                                                 const int32_t* __restrict__ cnt7) {
   __shared__ double red[16];
   double acc[4];
   for (int v = 0; v < 4; ++v) {
@@ -459,6 +468,7 @@ __global__ __launch_bounds__(1024) void k_s_final(const double* __restrict__ par
     acc[v] = block_reduce<false>(s, red);
     __syncthreads();
   }
+  if (cnt7) acc[0] += (double)(cnt7[0] - cnt7[4]);
   if (threadIdx.x == 0) {
     for (int k = 0; k < 3; ++k) {
       const double ckdt = rk_c(k) * scale;   // scale carries dt dy dz / nx
@@ -696,9 +706,10 @@ hipError_t launch_geom_lambda(const GridParams& g, const double* su, const doubl
 }
 
 hipError_t launch_geom_ptag_counts(const GridParams& g, uint8_t* tag, uint64_t masks, int nm, int32_t* counts,
-                                   int nblk, int32_t* clear, hipStream_t st) {
-  if ((int64_t)nblk * 256 < g.ncell || nm > 8) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_geom_ptag_counts, dim3(nblk), dim3(256), 0, st, g, tag, masks, nm, counts, nblk, clear);
+                                   int nblk, int32_t* clear, int32_t* chunks, hipStream_t st) {
+  if ((int64_t)nblk * 256 < g.ncell || nm > 8 || (chunks && g.nx % IBM_WAVE != 0)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_geom_ptag_counts, dim3(nblk), dim3(256), 0, st, g, tag, masks, nm, counts, nblk, clear,
+                     chunks);
   return hipGetLastError();
 }
 
@@ -729,19 +740,10 @@ hipError_t launch_scan_multi(const ScanSet& set, hipStream_t st) {
 }
 
 hipError_t launch_compact3(const uint8_t* tag, int64_t n, const int32_t* offsets, int nblk, int32_t* idx,
-                           const int cap[3], int32_t* overflow, hipStream_t st) {
+                           const int cap[3], int32_t* overflow, const double* lam_dense, const double* sig_dense,
+                           double dt, int b_mode, double* lam_out, double* sig_out, double2* coef, hipStream_t st) {
   hipLaunchKernelGGL(k_compact3, dim3(nblk), dim3(256), 0, st, tag, n, offsets, nblk, idx, cap[0], cap[0] + cap[1],
-                     cap[0], cap[1], cap[2], overflow);
-  return hipGetLastError();
-}
-
-hipError_t launch_ibm_coef3(const int32_t* idx, const double* lam_dense, const double* sig_dense, int64_t ncell,
-                            const int32_t* cnt, const int cap[3], double dt, int b_mode, double* lam_out,
-                            double* sig_out, double2* coef, hipStream_t st) {
-  const int ct = cap[0] + cap[1] + cap[2];
-  if (ct == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ibm_coef3, dim3((ct + 255) / 256), dim3(256), 0, st, idx, lam_dense, sig_dense, ncell, cnt,
-                     cap[0], cap[1], ct, dt, b_mode, lam_out, sig_out, coef);
+                     cap[0], cap[1], cap[2], overflow, lam_dense, sig_dense, dt, b_mode, lam_out, sig_out, coef);
   return hipGetLastError();
 }
 
@@ -762,21 +764,24 @@ hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t st) {
 
 hipError_t launch_s_k(const GridParams& g, const uint8_t* tag, const IbmLists& L, double* part, int* npart,
                       hipStream_t st) {
-  const int nb1 = (int)((g.ncell + 255) / 256);
+  // (on a uniform grid the internal non-IBM u points are counted by the tag counts, which
+  // k_s_final reads; a stretched grid weights them by row and sums them here)
+  const int nb1 = g.stretched ? (int)((g.ncell + 255) / 256) : 0;
   const int nb2 = (L.n_u + 255) / 256;
   double* part_sd = part + (size_t)(nb1 + nb2) * 4;
-  hipLaunchKernelGGL(k_s_cells, dim3(nb1), dim3(256), 0, st, g, tag, part);
+  if (nb1 > 0) hipLaunchKernelGGL(k_s_cells, dim3(nb1), dim3(256), 0, st, g, tag, part);
   if (nb2 > 0) hipLaunchKernelGGL(k_s_list, dim3(nb2), dim3(256), 0, st, g, L, part + (size_t)nb1 * 4, part_sd);
   *npart = nb1 + nb2;
   return hipGetLastError();
 }
 
 hipError_t launch_s_k_final(const double* part, int npart, double scale, double* S3, const GridParams& g,
-                            const IbmLists& L, double* sd_out, hipStream_t st) {
-  const int nb1 = (int)((g.ncell + 255) / 256);
+                            const IbmLists& L, const int32_t* cnt7, double* sd_out, hipStream_t st) {
+  const int nb1 = g.stretched ? (int)((g.ncell + 255) / 256) : 0;
   const int nb2 = (L.n_u + 255) / 256;
   const double* part_sd = part + (size_t)(nb1 + nb2) * 4;
-  hipLaunchKernelGGL(k_s_final, dim3(1), dim3(1024), 0, st, part, npart, scale, S3, part_sd, nb2, sd_out);
+  hipLaunchKernelGGL(k_s_final, dim3(1), dim3(1024), 0, st, part, npart, scale, S3, part_sd, nb2, sd_out,
+                     g.stretched ? nullptr : cnt7);
   return hipGetLastError();
 }
 
