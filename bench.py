@@ -252,8 +252,12 @@ def measure_ensemble(n=96, steps=200, warmup=3, seed=5):
         # momentum block and tile order, one value for all instances), the graph of
         # per-instance branches each instance's own tuning; the runs one after another
         # keep the single-grid automatic choices
+        # (the batched launches also take the automatic z-FFT width and tridiagonal rows:
+        # one launch runs the largest kernel variant any instance's tuning needs)
         g.tune(graph=0 if mode == "sequential" else 1, batch=1 if mode == "batched" else 0,
                momentum_planes=0, tile_order=0)
+        if mode == "batched":
+            g.tune(fftz_width=0, tri_rows=8)
         if mode != "sequential":
             ch = g.autotune(2)
             tunings[mode] = {"momentum_planes": ch["momentum_planes"], "tile_order": ch["tile_order"]}
