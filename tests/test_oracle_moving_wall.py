@@ -11,6 +11,8 @@ box walls at rest).
   sliding wall leaves v and w at zero.
 * With U_b = 0 the moving-wall terms vanish (sigma U_b = 0) and every external point
   holds zero, as without the option.
+* Galilean pin of sigma on a curved wall: fluid moving with a sphere's velocity stays
+  uniform away from the box walls (a planted slip in sigma is caught).
 """
 import math
 
@@ -94,3 +96,56 @@ def test_wall_shear_of_sliding_wall():
     tau = wall_shear_profile(g, o.u, sdf[0], wall_velocity=uw)
     rows = int(o.tags["u"][:, 0, 0].sum())
     np.testing.assert_allclose(tau, -o.pi_last * rows * g.dy / 2.0, rtol=1e-12)
+
+
+def _uniform_flow_past_moving_sphere(vel, sig_scale=1.0, steps=1):
+    """A sphere (radius 0.35, minimum image in x and z) at least 5 cells from the box walls,
+    moving at vel = (U, 0, W) through fluid that moves with it (u = U, v = 0, w = W
+    everywhere, zero pressure, no forcing), one RK3 step; sig_scale plants a slip in sigma."""
+    c = I.Case(nx=16, ny=17, nz=16, lx=2.0, lz=2.0, y_lo=-1.0, y_hi=1.0, nu=0.02, dt=0.02, forcing=CPG,
+               q_target_or_pi=0.0, geometry="flat", geo_params=(0.0,))
+    g = OGrid.from_case(c)
+
+    def fn(X, Y, Z):
+        dx = X - 1.0
+        dx -= c.lx * np.round(dx / c.lx)
+        dz = Z - 1.0
+        dz -= c.lz * np.round(dz / c.lz)
+        return np.sqrt(dx * dx + Y * Y + dz * dz) - 0.35
+    o = Oracle(g)
+    o.set_geometry(*I._sample(c, fn))
+    for comp in "uvw":
+        o.sig[comp] = o.sig[comp] * sig_scale
+    o.set_wall_velocity(*vel)
+    u = np.full(g.shape, vel[0])
+    w = np.full(g.shape, vel[2])
+    o.set_state(u, 0.0 * u, w, 0.0 * u)
+    o.step(steps)
+    return g, o
+
+
+@pytest.mark.parametrize("vel", [(0.8, 0.0, 0.0), (0.3, 0.0, -0.5)])
+def test_fluid_moving_with_a_curved_body_stays_uniform(vel):
+    """Galilean pin of sigma on a curved wall (reading R19): with the fluid moving at the
+    body's velocity, the ghost value of every cut arm is U_b and the near-wall operator
+    vanishes, so the implicit update returns U_b exactly when sigma = lambda for arms that
+    end at external points inside the box (every arm of a sphere away from the box
+    walls).  The box walls at rest disturb only the rows within one stencil width per
+    substep of them; everywhere else the step leaves u = U and w = W, v = 0 everywhere.  A
+    planted sigma of 0.5 lambda moves the near-wall points by O(U)."""
+    g, o = _uniform_flow_past_moving_sphere(vel)
+    rows = slice(4, g.ny - 1 - 4)            # more than 3 rows from either box wall
+    assert int((o.lam["u"][rows] > 0).sum()) > 0 and int((o.lam["w"][rows] > 0).sum()) > 0
+    for comp in "uw":
+        ibm = o.lam[comp][rows] > 0            # (the box-wall rows have sigma = 0: at rest)
+        assert np.allclose(o.sig[comp][rows][ibm], o.lam[comp][rows][ibm], rtol=1e-14, atol=0.0)
+    U, W = vel[0], vel[2]
+    scale = max(abs(U), abs(W))
+    assert np.abs(o.u[rows] - U).max() <= 1e-14 * scale
+    assert np.abs(o.w[rows] - W).max() <= 1e-14 * scale
+    assert np.abs(o.v).max() <= 1e-14 * scale
+    # the box walls at rest do act on the rows next to them
+    assert np.abs(o.u[0] - U).max() > 1e-3 * scale
+    # a planted slip in sigma is caught
+    g2, o2 = _uniform_flow_past_moving_sphere(vel, sig_scale=0.5)
+    assert np.abs(o2.u[rows] - U).max() > 1e-3 * scale
