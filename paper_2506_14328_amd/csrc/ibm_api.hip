@@ -32,7 +32,9 @@ struct Instance {
   void* S[3][3] = {};
   void* P[3] = {};
   int cur = 0;
-  bool fresh = true;       // u, v, w, p hold the state as set (no step since ibm_set_state)
+  bool fresh = true;       // nothing pending: the state is in u, v, w, p (no step since it was set),
+                           // or only in the predictor slot cur when state_in_slot
+  bool state_in_slot = false;
   void *Hu = nullptr, *Hv = nullptr, *Hw = nullptr, *phi = nullptr, *spec = nullptr;
   uint8_t* tag = nullptr;
   double* qpart = nullptr;
@@ -562,18 +564,31 @@ int run_steps(ibm_ctx* c, Instance& I, int nsteps, hipStream_t st, bool count = 
 
 
 // Writes the state (u, v, w, p) from the pending projection of the last substep.
-// With seed the corrected values also replace the predictor and pressure they came from:
-// once the caller zeroes phi and Pi, the state is the start of the next substep (what
-// seed_pending does with copies, in one pass).
+// With seed the corrected values replace the predictor and pressure they came from
+// instead: once the caller zeroes phi and Pi, the state is the start of the next substep
+// (what seed_pending does with copies, in one pass), held in that slot only until a call
+// that reads u, v, w, p copies it there.
 template <typename T>
 int materialize_t(ibm_ctx* c, Instance& I, bool seed) {
   // (recomputed even when it was already written: the host cannot see replays of graphs
   // the caller captured, after which the pending projection is newer than the state)
-  if (I.fresh) return IBM_OK;
+  if (I.fresh) {
+    if (!seed && I.state_in_slot) {
+      const size_t fb = (size_t)I.g.ncell * sizeof(T);
+      const void* src[4] = {I.S[I.cur][0], I.S[I.cur][1], I.S[I.cur][2], I.P[I.cur]};
+      void* dst[4] = {I.u, I.v, I.w, I.p};
+      for (int q = 0; q < 4; ++q) HIPCHK(c, hipMemcpyAsync(dst[q], src[q], fb, hipMemcpyDeviceToDevice, c->stream));
+      I.state_in_slot = false;
+    }
+    return IBM_OK;
+  }
   Fields<T> f = fields_of<T>(I);
   f.us = f.usp; f.vs = f.vsp; f.ws = f.wsp;   // the predictor awaiting its projection
-  RUNK(c, K_CORRECT, launch_correct<T>(I.g, f, I.L, seed ? 1 : 0, rk_c(2) * I.g.dt, I.pi(), c->stream));
-  if (seed) I.fresh = true;   // (phi and Pi are zeroed by the caller's next kernel)
+  RUNK(c, K_CORRECT, launch_correct<T>(I.g, f, I.L, seed ? 2 : 1, rk_c(2) * I.g.dt, I.pi(), c->stream));
+  if (seed) {
+    I.fresh = true;   // (phi and Pi are zeroed by the caller's next kernel)
+    I.state_in_slot = true;
+  }
   return IBM_OK;
 }
 
@@ -584,6 +599,7 @@ int materialize(ibm_ctx* c, Instance& I, bool seed = false) {
 // Makes the state in u, v, w, p the starting point of the next step: predictor and
 // pressure slot I.cur take copies, phi and Pi are zero (nothing pending).
 int seed_pending(ibm_ctx* c, Instance& I) {
+  I.state_in_slot = false;   // (every caller has just written u, v, w, p or made them current)
   const size_t fb = (size_t)I.g.ncell * (c->precision == IBM_FP64 ? 8 : 4);
   const void* src[4] = {I.u, I.v, I.w, I.p};
   void* dst[4] = {I.S[I.cur][0], I.S[I.cur][1], I.S[I.cur][2], I.P[I.cur]};

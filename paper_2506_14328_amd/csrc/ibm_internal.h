@@ -403,7 +403,8 @@ template <typename T>
 hipError_t launch_ifftx(const GridParams& g, const cplx<T>* spec, T* out, const FFTPlan& px,
                         const double2* rtw, hipStream_t st);
 template <typename T>
-hipError_t launch_correct(const GridParams& g, const Fields<T>& f, const IbmLists& L, int seed, double ck_dt,
+// mode bit 0: the state into f.u..f.p; bit 1: into the predictor slot it came from
+hipError_t launch_correct(const GridParams& g, const Fields<T>& f, const IbmLists& L, int mode, double ck_dt,
                           const double* pi, hipStream_t st);
 
 // diagnostics

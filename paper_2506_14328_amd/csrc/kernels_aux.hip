@@ -262,18 +262,23 @@ __global__ __launch_bounds__(256) void k_geom_south_wall(GridParams g, const dou
 }
 
 // Exclusive prefix sum of nblk counts in place, total[0] = their sum; one block of 1024
-// threads, 4096 counts per round: each thread adds 4 consecutive counts, the waves scan
-// their threads' sums with shuffles and one wave scans the 16 wave sums.
+// threads, SCAN_PER * 1024 counts per round: each thread adds SCAN_PER consecutive counts,
+// the waves scan their threads' sums with shuffles and one wave scans the 16 wave sums.
+constexpr int SCAN_PER = 16;
 __device__ __forceinline__ void scan_counts_body(int32_t* __restrict__ counts, int nblk,
                                                  int32_t* __restrict__ total) {
   __shared__ int32_t wsum[16];
   const int tid = threadIdx.x, lane = tid & (IBM_WAVE - 1), wid = tid / IBM_WAVE;
   int32_t carry = 0;
-  for (int base = 0; base < nblk; base += 4096) {
-    const int e0 = base + 4 * tid;
-    int32_t v[4];
-    for (int q = 0; q < 4; ++q) v[q] = (e0 + q < nblk) ? counts[e0 + q] : 0;
-    const int32_t sum = v[0] + v[1] + v[2] + v[3];
+  for (int base = 0; base < nblk; base += SCAN_PER * 1024) {
+    const int e0 = base + SCAN_PER * tid;
+    int32_t v[SCAN_PER];
+    int32_t sum = 0;
+#pragma unroll
+    for (int q = 0; q < SCAN_PER; ++q) {
+      v[q] = (e0 + q < nblk) ? counts[e0 + q] : 0;
+      sum += v[q];
+    }
     int32_t x = sum;   // inclusive scan over the wave
     for (int o = 1; o < IBM_WAVE; o <<= 1) {
       const int32_t y = __shfl_up(x, o, IBM_WAVE);
@@ -291,7 +296,8 @@ __device__ __forceinline__ void scan_counts_body(int32_t* __restrict__ counts, i
     }
     __syncthreads();
     int32_t run = carry + (wid > 0 ? wsum[wid - 1] : 0) + (x - sum);
-    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+    for (int q = 0; q < SCAN_PER; ++q) {
       if (e0 + q < nblk) counts[e0 + q] = run;
       run += v[q];
     }

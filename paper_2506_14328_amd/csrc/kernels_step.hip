@@ -1126,12 +1126,13 @@ __global__ __launch_bounds__(256) void k_ifftx_b(const IfftxArgs<T>* __restrict_
 // u = u* - c_k dt G phi on internal faces (the pending -Pi c_k dt included), zero on
 // external faces (Sec. 3.3); p = p' + phi on internal pressure cells only (p' = f.pp).
 // The step itself folds this into the next momentum; this kernel materialises the state
-// on request.  With seed the values are also written back over the predictor and the
-// pressure they were computed from (f.us, f.pp: each point reads only its own), which
-// makes the state the start of the next substep once the caller zeroes phi and Pi.
+// on request.  mode bit 0: the state goes to f.u, f.v, f.w, f.p; bit 1: it is written
+// back over the predictor and the pressure it was computed from (f.us, f.pp: each point
+// reads only its own), which makes it the start of the next substep once the caller
+// zeroes phi and Pi.
 // ---------------------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_correct(GridParams g, Fields<T> f, IbmLists L, int seed, double ck_dt,
+__global__ __launch_bounds__(256) void k_correct(GridParams g, Fields<T> f, IbmLists L, int mode, double ck_dt,
                                                 const double* __restrict__ pi) {
   const int i = blockIdx.x * BX + threadIdx.x;
   const int k = blockIdx.y * BZ + threadIdx.y;
@@ -1154,11 +1155,13 @@ __global__ __launch_bounds__(256) void k_correct(GridParams g, Fields<T> f, IbmL
   const T vo = (tg & TAG_V) ? vn : (j == 0 ? T(0) : T(L.wallv[1]));
   const T wo = (tg & TAG_W) ? wn : T(L.wallv[2]);
   const T po = (tg & TAG_P) ? pv + ph : T(0);
-  f.u[c] = uo;
-  f.v[c] = vo;
-  f.w[c] = wo;
-  f.p[c] = po;
-  if (seed) {
+  if (mode & 1) {
+    f.u[c] = uo;
+    f.v[c] = vo;
+    f.w[c] = wo;
+    f.p[c] = po;
+  }
+  if (mode & 2) {
     f.us[c] = uo;
     f.vs[c] = vo;
     f.ws[c] = wo;
@@ -1476,9 +1479,9 @@ hipError_t launch_ifftx(const GridParams& g, const cplx<T>* spec, T* out, const 
 }
 
 template <typename T>
-hipError_t launch_correct(const GridParams& g, const Fields<T>& f, const IbmLists& L, int seed, double ck_dt,
+hipError_t launch_correct(const GridParams& g, const Fields<T>& f, const IbmLists& L, int mode, double ck_dt,
                           const double* pi, hipStream_t st) {
-  hipLaunchKernelGGL(k_correct<T>, cell_grid(g), dim3(BX, BZ), 0, st, g, f, L, seed, ck_dt, pi);
+  hipLaunchKernelGGL(k_correct<T>, cell_grid(g), dim3(BX, BZ), 0, st, g, f, L, mode, ck_dt, pi);
   return hipGetLastError();
 }
 
