@@ -156,6 +156,8 @@ def solve_pressure_noalloc(c, rhs: torch.Tensor, phi: Optional[torch.Tensor] = N
     element.  Enqueued on torch's current stream; allocates no device memory in the library
     (phi is allocated here by torch when not given)."""
     lib = load_library()
+    if getattr(c, "y_faces", None) is not None:
+        raise ValueError("the allocation-free solve takes a uniform wall-normal grid (no y_faces)")
     shape = (c.ny - 1, c.nz, c.nx)
     if rhs.device.type != "cuda" or tuple(rhs.shape) != shape or not rhs.is_contiguous():
         raise ValueError(f"rhs must be a contiguous GPU tensor of shape {shape}")

@@ -158,3 +158,16 @@ int main(void) {
         r = subprocess.run([exe], capture_output=True, text=True)
     assert r.returncode == 0, (r.returncode, r.stdout, r.stderr)
     assert "nx" in r.stdout
+
+
+@needs_lib
+def test_noalloc_binding_rejects_a_stretched_grid():
+    """The allocation-free solve has no wall-normal table: its binding refuses a case with
+    y_faces before touching any tensor."""
+    import torch
+    import ibm_inputs as I
+    from paper_2506_14328_amd import solve_pressure_noalloc
+    c = I.Case(nx=8, ny=9, nz=4, lx=1.0, lz=1.0, y_lo=-1.0, y_hi=1.0, nu=0.01, dt=0.01,
+               y_faces=I.tanh_faces(9, -1.0, 1.0, 1.2))
+    with pytest.raises(ValueError):
+        solve_pressure_noalloc(c, torch.zeros((8, 4, 8), dtype=torch.float64))
