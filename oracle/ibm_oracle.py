@@ -540,13 +540,15 @@ def masked_laplacian(g: OGrid, tags) -> Tuple["scipy.sparse.csr_matrix", np.ndar
 
     M keeps the gradient only on internal velocity faces (the external ones are never
     corrected, Sec. 3.3), so each internal face couples the two pressure cells it
-    separates with weight 1/h^2 (an internal face always lies between two internal
-    cells).  Returns the sparse matrix over the internal cells (in C order of the
-    (j, k, i) cell array) and the flat indices of those cells.
+    separates (an internal face always lies between two internal cells): with weight
+    1/h^2 on a uniform grid; on a stretched one (reading R20) the v face j, at the
+    centre spacing h_j from cell j-1 to cell j, enters the row of cell j with
+    1/(h_j dy_j) and that of cell j-1 with 1/(h_j dy_{j-1}), dy the cell heights (the
+    divergence over the cell height of the gradient over the centre spacing).  Returns
+    the sparse matrix over the internal cells (in C order of the (j, k, i) cell array)
+    and the flat indices of those cells.
     """
     import scipy.sparse as sp
-    if g.stretched:
-        raise NotImplementedError("the masked projection is built for a uniform wall-normal grid")
     pin = tags["p"]
     cells = np.flatnonzero(pin.ravel())
     pos = -np.ones(pin.size, dtype=np.int64)
@@ -557,17 +559,23 @@ def masked_laplacian(g: OGrid, tags) -> Tuple["scipy.sparse.csr_matrix", np.ndar
     rows, cols, vals = [], [], []
     # u face i of cell (j, k, i) joins cells i-1 and i; v face j joins rows j-1 and j
     # (face 0 is the south box wall, never internal); w face k joins k-1 and k
-    for face, other, h in ((tags["u"], (jj * nz + kk) * nx + (ii - 1) % nx, g.dx),
-                           (tags["v"], ((jj - 1) * nz + kk) * nx + ii, g.dy),
-                           (tags["w"], (jj * nz + (kk - 1) % nz) * nx + ii, g.dz)):
+    for comp, face, other, h in (("u", tags["u"], (jj * nz + kk) * nx + (ii - 1) % nx, g.dx),
+                                 ("v", tags["v"], ((jj - 1) * nz + kk) * nx + ii, g.dy),
+                                 ("w", tags["w"], (jj * nz + (kk - 1) % nz) * nx + ii, g.dz)):
         a = pos[lin[face]]
         b = pos[other[face]]
         if (a < 0).any() or (b < 0).any():
             raise ValueError("internal face next to an external pressure cell")
-        wgt = 1.0 / (h * h)
+        if comp == "v" and g.stretched:
+            jf = jj[face]                      # face j: row a is cell j, row b cell j-1
+            hc = g.hy_lo[jf]
+            wa = 1.0 / (hc * g.dyc[jf])
+            wb = 1.0 / (hc * g.dyc[jf - 1])
+        else:
+            wa = wb = np.full(a.size, 1.0 / (h * h))
         rows += [a, b, a, b]
         cols += [b, a, a, b]
-        vals += [np.full(a.size, wgt), np.full(a.size, wgt), np.full(a.size, -wgt), np.full(a.size, -wgt)]
+        vals += [wa, wb, -wa, -wb]
     L = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                       shape=(cells.size, cells.size))
     return L, cells
@@ -576,10 +584,12 @@ def masked_laplacian(g: OGrid, tags) -> Tuple["scipy.sparse.csr_matrix", np.ndar
 def masked_poisson_solve(g: OGrid, rhs: np.ndarray, tags) -> Tuple[np.ndarray, float]:
     """Solve D M G phi = rhs on the internal pressure cells only (reading R18).
 
-    The operator is singular (constants) and rhs sums to zero over the internal cells
-    (every boundary face of the set carries no flux), so the system is consistent.  The
-    solution with zero sum over the internal cells is taken: the rounding-level mean of
-    rhs over the internal cells is removed (the least-squares reading of the system),
+    The operator is singular (constants) and rhs sums to zero over the internal cells,
+    weighted by the cell volumes (every boundary face of the set carries no flux), so the
+    system is consistent.  The solution with zero sum over the internal cells is taken:
+    the rounding-level volume-weighted mean of rhs over the internal cells is removed
+    (the least-squares reading of the system; the weights are the cell heights on a
+    stretched grid, reading R20),
     the first internal cell is pinned to zero and its equation, implied by the others,
     dropped; the remaining nonsingular system is solved by a sparse direct factorisation
     and the mean over the internal cells removed.  The internal cells must form one
@@ -596,7 +606,11 @@ def masked_poisson_solve(g: OGrid, rhs: np.ndarray, tags) -> Tuple[np.ndarray, f
     if ncomp != 1:
         raise ValueError(f"internal pressure cells form {ncomp} disconnected sets")
     b = rhs.ravel()[cells]
-    bc = b - b.mean()
+    if g.stretched:
+        wv = np.broadcast_to(col(g.dyc), g.shape).ravel()[cells]
+        bc = b - np.sum(wv * b) / np.sum(wv)
+    else:
+        bc = b - b.mean()
     x = np.zeros(n)
     if n > 1:
         x[1:] = spla.spsolve(sp.csc_matrix(L[1:, 1:]), bc[1:])

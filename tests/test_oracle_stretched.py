@@ -12,7 +12,6 @@
   D and G the divergence and gradient pinned above.
 * Plane Poiseuille flow between immersed walls on tanh-stretched grids converges to the
   exact parabola at second order (Sec. 2.3's claim, here with non-uniform spacing).
-* The masked projection is not built for a stretched grid and says so.
 """
 import math
 
@@ -21,7 +20,7 @@ import pytest
 
 import ibm_inputs as I
 from oracle.ibm_oracle import (CPG, OGrid, Oracle, convection, divergence, gradient_full, laplacian,
-                               masked_laplacian, poisson_solve)
+                               poisson_solve)
 
 
 def _grid(ny=13, nx=4, nz=3, gamma=1.3, top=0):
@@ -140,10 +139,3 @@ def test_poiseuille_between_immersed_walls_second_order_on_stretched_grids():
     assert errs[-1] < 1e-3
     assert orders[-1] > 1.8, (errs, orders)
 
-
-def test_masked_projection_not_built_for_stretched_grid():
-    g = _grid()
-    tags = {"p": np.ones(g.shape, bool), "u": np.ones(g.shape, bool), "v": np.ones(g.shape, bool),
-            "w": np.ones(g.shape, bool)}
-    with pytest.raises(NotImplementedError):
-        masked_laplacian(g, tags)
