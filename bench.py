@@ -290,13 +290,22 @@ def measure_ensemble(n=96, steps=200, warmup=3, seed=5):
             "tuning": tunings}
 
 
-def measure_masked(steps=20, warmup=2):
+def measure_masked(steps=20, warmup=2, stretched=False):
     """The open channel (192 x 65 x 160, FP64) with the masked projection: continuity on
     the internal cells only, solved by conjugate gradients preconditioned with the
-    full-box solve (launched eagerly, one host synchronisation per iteration)."""
+    full-box solve (launched eagerly, the convergence flag read every 4 iterations; then
+    replayed as a graph).  stretched: on the bottom-clustered grid of spacing ratio 5.6."""
     import dataclasses
+    import numpy as np
     import torch
+    import ibm_inputs as I
     c, sdf, st = build_inputs("wavy_open")
+    if stretched:
+        c = dataclasses.replace(c, y_faces=I.bottom_tanh_faces(c.ny, c.y_lo, c.y_hi, 5.6),
+                                name="wavy_open_stretched_192x65x160")
+        sdf = I.make_sdf(c)
+        u, v, w = I.make_initial(c, sdf)
+        st = (u, v, w, np.zeros_like(u))
     c = dataclasses.replace(c, projection=1)
     g = make_grid(c, sdf, st, "fp64")
     tuned = g.autotune(2)
@@ -683,6 +692,7 @@ def main():
                           ibm_point_fraction=round(rs["ibm_fraction"], 4)))
         del sdf_s, us_, vs_, ws_
         forms.append(measure_masked())
+        forms.append(measure_masked(stretched=True))
         forms.append(measure_moving_geometry())
         forms.extend(measure_shard_shapes())
         forms.append(measure_ensemble())

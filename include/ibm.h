@@ -228,9 +228,11 @@ int ibm_set_wall_velocity(ibm_handle h, int32_t inst, double ub, double vb, doub
  * interpolation, the divergence and the pressure Poisson rows with the cell heights,
  * the flow rate and S_k weighted by them.  The immersed-boundary data depend on the
  * spacing: call ibm_set_geometry afterwards (IBM_ERR_STATE until then).  Applies a
- * pending projection first and drops captured graphs.  Synchronises the stream.
- * IBM_ERR_ARG for a masked-projection instance, non-finite or non-increasing faces or
- * end points other than y_lo, y_hi (relative tolerance 1e-12). */
+ * pending projection first and drops captured graphs.  Synchronises the stream.  A
+ * masked-projection instance solves the symmetric form W D M G phi = W rhs, W the cell
+ * heights (the preconditioner, the full-box solve, takes W^-1 of the residual).
+ * IBM_ERR_ARG for non-finite or non-increasing faces or end points other than y_lo, y_hi
+ * (relative tolerance 1e-12). */
 int ibm_set_y_faces(ibm_handle h, int32_t inst, const double* y_faces);
 
 /* Wall-shear stress of the current state along the south wall, the undulated bottom

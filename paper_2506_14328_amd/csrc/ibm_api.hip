@@ -44,7 +44,7 @@ struct Instance {
   double2* rtw = nullptr;
   double *kx2 = nullptr, *kz2 = nullptr;
   // masked projection: conjugate-gradient vectors r, z, p, A p and partial sums
-  double* pcg_v[4] = {};
+  double* pcg_v[5] = {};   // r, z, p, A p and (stretched grids) W^-1 r
   double* pcg_part = nullptr;
   double wall_vel[3] = {0.0, 0.0, 0.0};   // host copy of the immersed walls' velocity
   int pcg_iters = 0;        // iterations of the last masked solve
@@ -354,7 +354,7 @@ int init_instance(ibm_ctx* c, Instance& I, const ibm_grid_desc& d) {
   I.L.sd = I.wall_sd();
   if ((rc = dalloc(c, I, (void**)&I.itotal, 32 * sizeof(int32_t)))) return rc;
   if (d.projection == IBM_PROJ_MASKED) {
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < 5; ++q)
       if ((rc = dalloc(c, I, (void**)&I.pcg_v[q], (size_t)g.ncell * sizeof(double)))) return rc;
     if ((rc = dalloc(c, I, (void**)&I.pcg_part, (size_t)PCG_NSLOT * PCG_NPART * sizeof(double)))) return rc;
     if ((rc = dalloc(c, I, (void**)&I.pcg_stat, PCG_NSTAT * sizeof(int32_t) + 2 * sizeof(double)))) return rc;
@@ -461,6 +461,9 @@ int pcg_project(ibm_ctx* c, Instance& I, Fields<double>& f, hipStream_t st, bool
   g.skip = I.pcg_stat + PCG_DONE;
   double* x = f.phi;
   double *r = I.pcg_v[0], *z = I.pcg_v[1], *p = I.pcg_v[2], *ap = I.pcg_v[3];
+  // on a stretched grid the residual is W (b - A x) and the preconditioner takes W^-1 r
+  double* rs = g0.stretched ? I.pcg_v[4] : nullptr;
+  const double* pre_in = rs ? rs : r;
   double* part = I.pcg_part;
   double* sc = I.pcg_sc();
   double* rr_dev = reinterpret_cast<double*>(I.pcg_stat + PCG_NSTAT);
@@ -468,7 +471,7 @@ int pcg_project(ibm_ctx* c, Instance& I, Fields<double>& f, hipStream_t st, bool
   const int max_iter = I.d.pcg_max_iter > 0 ? I.d.pcg_max_iter : 500;
   const int budget = capture ? I.pcg_budget : max_iter;
   RUNK(c, K_PCG, launch_pcg_prep(I.mean(), sc, I.pcg_stat, st));
-  RUNK(c, K_PCG, launch_pcg_init(g0, I.tag, x, sc + 3, r, part, I.itotal + 3, st));
+  RUNK(c, K_PCG, launch_pcg_init(g0, I.tag, x, sc + 3, r, part, I.itotal + 3, rs, st));
   RUNK(c, K_PCG, launch_pcg_total(g0, part, PCG_B, sc + 2, st));
   RUNK(c, K_PCG, launch_pcg_check(g0, part, sc, tol * tol, 0, I.pcg_stat, rr_dev, st));
   for (int it = 0; it < budget; ++it) {
@@ -478,13 +481,13 @@ int pcg_project(ibm_ctx* c, Instance& I, Fields<double>& f, hipStream_t st, bool
       SYNCHK(c, st);
       if (done) break;
     }
-    RUNK(c, K_DIV_FFTX, launch_div_fftx<double>(g, f, I.L, 0, I.px, I.rtw, 1.0, I.pi(), r, st));
+    RUNK(c, K_DIV_FFTX, launch_div_fftx<double>(g, f, I.L, 0, I.px, I.rtw, 1.0, I.pi(), pre_in, st));
     int rc = poisson<double>(c, I, g, f, z, st);
     if (rc) return rc;
     RUNK(c, K_PCG, launch_pcg_rz(g, r, z, part, st));
     RUNK(c, K_PCG, launch_pcg_dir(g, I.tag, z, p, part, sc, it, st));
     RUNK(c, K_PCG, launch_pcg_apply(g, I.tag, p, ap, part, st));
-    RUNK(c, K_PCG, launch_pcg_step(g, I.tag, x, r, p, ap, part, sc, it, st));
+    RUNK(c, K_PCG, launch_pcg_step(g, I.tag, x, r, p, ap, part, sc, it, rs, st));
     RUNK(c, K_PCG, launch_pcg_check(g0, part, sc, tol * tol, it + 1, I.pcg_stat, rr_dev, st));
   }
   RUNK(c, K_PCG, launch_pcg_finish(g0, I.tag, x, part, I.itotal + 3, st));
@@ -1244,8 +1247,6 @@ int ibm_set_y_faces(ibm_handle h, int32_t inst, const double* y_faces) {
   if (!y_faces) return fail(h, IBM_ERR_ARG, "null y_faces");
   if ((rc = refuse_capture(h))) return rc;
   Instance& I = h->inst[inst];
-  if (I.d.projection == IBM_PROJ_MASKED)
-    return fail(h, IBM_ERR_ARG, "the masked projection needs a uniform wall-normal grid");
   const int ny = I.g.ny1 + 1;
   const double H = I.d.y_hi - I.d.y_lo;
   for (int j = 0; j < ny; ++j)

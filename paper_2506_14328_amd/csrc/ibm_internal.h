@@ -448,15 +448,16 @@ hipError_t launch_pcg_check(const GridParams& g, const double* part, const doubl
 hipError_t launch_pcg_post(double* mean, const double* sc, hipStream_t st);
 int pcg_blocks(const GridParams& g);
 // n_internal: device count of the internal pressure cells
+// (rs, on stretched grids: W^-1 r, the preconditioner's input; null on uniform grids)
 hipError_t launch_pcg_init(const GridParams& g, const uint8_t* tag, const double* x, const double* mean, double* r,
-                           double* part, const int32_t* n_internal, hipStream_t st);
+                           double* part, const int32_t* n_internal, double* rs, hipStream_t st);
 hipError_t launch_pcg_rz(const GridParams& g, const double* r, const double* z, double* part, hipStream_t st);
 hipError_t launch_pcg_dir(const GridParams& g, const uint8_t* tag, const double* z, double* p, double* part,
                           double* sc, int it, hipStream_t st);
 hipError_t launch_pcg_apply(const GridParams& g, const uint8_t* tag, const double* p, double* ap, double* part,
                             hipStream_t st);
 hipError_t launch_pcg_step(const GridParams& g, const uint8_t* tag, double* x, double* r, const double* p,
-                           const double* ap, double* part, const double* sc, int it, hipStream_t st);
+                           const double* ap, double* part, const double* sc, int it, double* rs, hipStream_t st);
 hipError_t launch_pcg_total(const GridParams& g, const double* part, int slot, double* out, hipStream_t st);
 hipError_t launch_pcg_finish(const GridParams& g, const uint8_t* tag, double* x, const double* part,
                              const int32_t* n_internal, hipStream_t st);

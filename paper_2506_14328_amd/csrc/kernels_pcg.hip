@@ -5,6 +5,11 @@
 // being the full-box FFT/tridiagonal solve of the projection itself; the full-box
 // solution is the starting point.  FP64 only.
 //
+// On a stretched wall-normal grid the operator's rows carry the cell height dy_j in their
+// denominators (not symmetric); the solve is then of the symmetric W A x = W b, W the
+// diagonal of cell heights: r holds W (b - A x), the preconditioner takes W^-1 r (rs,
+// written where r is), and the operator applied to the direction is W A p.
+//
 // Vectors live on the full cell array; r and p are zero outside the internal cells.
 // Every reduction writes one partial per block (at most PCG_NPART blocks, grid-stride
 // loops); the kernel that needs the total re-adds the partials in the same fixed order
@@ -48,8 +53,16 @@ __device__ __forceinline__ double lap(const GridParams& g, const uint8_t* __rest
     ff = (tf & TAG_W) ? 1.0 : 0.0;
   }
   const double xc = x[c];
-  return (fw * (x[cw] - xc) + fe * (x[ce] - xc)) * g.idx2 + (fs * (x[cs] - xc) + fn * (x[cn] - xc)) * g.idy2 +
-         (fb * (x[cb] - xc) + ff * (x[cf] - xc)) * g.idz2;
+  // wall-normal part: idy2 both ways, or the row's own Poisson coefficients
+  const double ys = fs * (x[cs] - xc), yn = fn * (x[cn] - xc);
+  const double yp = g.stretched ? ys * g.ytab[YT_TLO * g.ystr + j] + yn * g.ytab[YT_THI * g.ystr + j]
+                                : (ys + yn) * g.idy2;
+  return (fw * (x[cw] - xc) + fe * (x[ce] - xc)) * g.idx2 + yp + (fb * (x[cb] - xc) + ff * (x[cf] - xc)) * g.idz2;
+}
+
+// The symmetrising row weight of cell row j: the cell height on a stretched grid, else 1.
+__device__ __forceinline__ double row_weight(const GridParams& g, int c) {
+  return g.stretched ? g.ytab[YT_DYC * g.ystr + c / (g.nx * g.nz)] : 1.0;
 }
 
 // Sum of the nb partials, the same order in every block; every thread gets it.
@@ -83,9 +96,10 @@ __global__ __launch_bounds__(PT) void k_pcg_init(GridParams g, const uint8_t* __
     if (tag[c] & TAG_P) {
       int j, k, i;
       decode(g, c, j, k, i);
+      const double wr = row_weight(g, c);
       const double b = lap<false>(g, tag, x, c, j, k, i) + m;
-      rv = b - lap<true>(g, tag, x, c, j, k, i);
-      ab += b * b;
+      rv = wr * (b - lap<true>(g, tag, x, c, j, k, i));
+      ab += (wr * b) * (wr * b);
       ars += rv;
       ax += x[c];
     }
@@ -99,18 +113,22 @@ __global__ __launch_bounds__(PT) void k_pcg_init(GridParams g, const uint8_t* __
 // The operator's range is orthogonal to the constant on the internal cells, and no
 // iteration changes the sum of r: its rounding-level mean (from b, which only matches
 // the divergence to the full-box solve's accuracy) is removed here.  Partials of |r0|^2.
+// With rs (stretched grids) also rs = W^-1 r everywhere (zero outside the internal cells).
 __global__ __launch_bounds__(PT) void k_pcg_center(GridParams g, const uint8_t* __restrict__ tag,
                                                   double* __restrict__ r, const double* __restrict__ prs, int nb,
-                                                  const int32_t* __restrict__ n_internal, double* __restrict__ pr) {
+                                                  const int32_t* __restrict__ n_internal, double* __restrict__ pr,
+                                                  double* __restrict__ rs) {
   __shared__ double smem[8];
   const double mean = sum_partials(prs, nb, smem) / (double)n_internal[0];
   double ar = 0.0;
   for (int c = blockIdx.x * PT + threadIdx.x; c < g.ncell; c += gridDim.x * PT) {
+    double rv = 0.0;
     if (tag[c] & TAG_P) {
-      const double rv = r[c] - mean;
+      rv = r[c] - mean;
       r[c] = rv;
       ar += rv * rv;
     }
+    if (rs) rs[c] = rv / row_weight(g, c);
   }
   put_partial(ar, smem, pr);
 }
@@ -160,8 +178,8 @@ __global__ __launch_bounds__(PT) void k_pcg_apply(GridParams g, const uint8_t* _
     decode(g, c0, j0, k0, i0);
     decode(g, c1c, j1, k1, i1);
     const double in0 = (tag[c0] & TAG_P) ? 1.0 : 0.0, in1 = (tag[c1c] & TAG_P) ? 1.0 : 0.0;
-    const double y0 = in0 * lap<true>(g, tag, p, c0, j0, k0, i0);
-    const double y1 = in1 * lap<true>(g, tag, p, c1c, j1, k1, i1);
+    const double y0 = in0 * row_weight(g, c0) * lap<true>(g, tag, p, c0, j0, k0, i0);
+    const double y1 = in1 * row_weight(g, c1c) * lap<true>(g, tag, p, c1c, j1, k1, i1);
     a += p[c0] * y0;
     ap[c0] = y0;
     if (c1 < g.ncell) {
@@ -179,7 +197,7 @@ __global__ __launch_bounds__(PT) void k_pcg_step(GridParams g, const uint8_t* __
                                                 const double* __restrict__ p, const double* __restrict__ ap,
                                                 const double* __restrict__ ppap, int nb,
                                                 const double* __restrict__ sc, int it, double* __restrict__ pr,
-                                                double* __restrict__ px) {
+                                                double* __restrict__ px, double* __restrict__ rs) {
   if (g.skip && *g.skip) return;
   __shared__ double smem[8];
   const double pap = sum_partials(ppap, nb, smem);
@@ -191,6 +209,7 @@ __global__ __launch_bounds__(PT) void k_pcg_step(GridParams g, const uint8_t* __
       const double rv = r[c] - alpha * ap[c];
       x[c] = xv;
       r[c] = rv;
+      if (rs) rs[c] = rv / row_weight(g, c);
       ar += rv * rv;
       ax += xv;
     }
@@ -255,12 +274,12 @@ int pcg_blocks(const GridParams& g) {
 }
 
 hipError_t launch_pcg_init(const GridParams& g, const uint8_t* tag, const double* x, const double* mean, double* r,
-                           double* part, const int32_t* n_internal, hipStream_t st) {
+                           double* part, const int32_t* n_internal, double* rs, hipStream_t st) {
   const int nb = pcg_blocks(g);
   hipLaunchKernelGGL(k_pcg_init, dim3(nb), dim3(PT), 0, st, g, tag, x, mean, r, part + PCG_B * PCG_NPART,
                      part + PCG_RS * PCG_NPART, part + PCG_X * PCG_NPART);
   hipLaunchKernelGGL(k_pcg_center, dim3(nb), dim3(PT), 0, st, g, tag, r, part + PCG_RS * PCG_NPART, nb,
-                     n_internal, part + PCG_R2 * PCG_NPART);
+                     n_internal, part + PCG_R2 * PCG_NPART, rs);
   return hipGetLastError();
 }
 
@@ -283,10 +302,10 @@ hipError_t launch_pcg_apply(const GridParams& g, const uint8_t* tag, const doubl
 }
 
 hipError_t launch_pcg_step(const GridParams& g, const uint8_t* tag, double* x, double* r, const double* p,
-                           const double* ap, double* part, const double* sc, int it, hipStream_t st) {
+                           const double* ap, double* part, const double* sc, int it, double* rs, hipStream_t st) {
   const int nb = pcg_blocks(g);
   hipLaunchKernelGGL(k_pcg_step, dim3(nb), dim3(PT), 0, st, g, tag, x, r, p, ap, part + PCG_PAP * PCG_NPART, nb,
-                     sc, it, part + PCG_R2 * PCG_NPART, part + PCG_X * PCG_NPART);
+                     sc, it, part + PCG_R2 * PCG_NPART, part + PCG_X * PCG_NPART, rs);
   return hipGetLastError();
 }
 
