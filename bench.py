@@ -290,11 +290,13 @@ def measure_ensemble(n=96, steps=200, warmup=3, seed=5):
             "tuning": tunings}
 
 
-def measure_masked(steps=20, warmup=2, stretched=False):
+def measure_masked(steps=20, warmup=2, stretched=False, precision="fp64"):
     """The open channel (192 x 65 x 160, FP64) with the masked projection: continuity on
     the internal cells only, solved by conjugate gradients preconditioned with the
     full-box solve (launched eagerly, the convergence flag read every 4 iterations; then
-    replayed as a graph).  stretched: on the bottom-clustered grid of spacing ratio 5.6."""
+    replayed as a graph).  stretched: on the bottom-clustered grid of spacing ratio 5.6.
+    precision fp32: FP32 storage (the iteration in FP64, the FP32 full-box solve as
+    preconditioner)."""
     import dataclasses
     import numpy as np
     import torch
@@ -307,7 +309,7 @@ def measure_masked(steps=20, warmup=2, stretched=False):
         u, v, w = I.make_initial(c, sdf)
         st = (u, v, w, np.zeros_like(u))
     c = dataclasses.replace(c, projection=1)
-    g = make_grid(c, sdf, st, "fp64")
+    g = make_grid(c, sdf, st, precision)
     tuned = g.autotune(2)
     g.set_state(*[torch.as_tensor(a).to("cuda", g.dtype) for a in st])
     g.step(warmup)
@@ -333,7 +335,7 @@ def measure_masked(steps=20, warmup=2, stretched=False):
     sg = g.stats()
     tot = sum(v[0] for v in prof.values())
     C = c.nx * (c.ny - 1) * c.nz
-    out = {"workload": c.name, "projection": "masked", "precision": "fp64", "value": C * 3 * steps / el,
+    out = {"workload": c.name, "projection": "masked", "precision": precision, "value": C * 3 * steps / el,
            "ms_per_step": el / steps * 1e3, "ms_per_step_graph": el_g / steps * 1e3,
            "pcg_iterations_last_solve_graph": sg["pcg_iters"], "pcg_iterations_last_solve": s["pcg_iters"],
            "pcg_relative_residual": s["poisson_rel_residual"],
@@ -693,6 +695,7 @@ def main():
         del sdf_s, us_, vs_, ws_
         forms.append(measure_masked())
         forms.append(measure_masked(stretched=True))
+        forms.append(measure_masked(precision="fp32"))
         forms.append(measure_moving_geometry())
         forms.extend(measure_shard_shapes())
         forms.append(measure_ensemble())

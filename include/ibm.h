@@ -91,8 +91,11 @@ typedef struct {
                            keeping the internal faces (the external ones are never
                            corrected, Sec. 3.3 read strictly), solved by conjugate gradients
                            preconditioned with the full-box solve and started from its
-                           solution; phi has zero mean over the internal cells.  IBM_FP64
-                           only.  Convergence is tested on the device after every iteration
+                           solution; phi has zero mean over the internal cells.  With
+                           IBM_FP32_STORAGE the iteration runs in FP64 with the FP32
+                           full-box solve as preconditioner (the flexible Polak-Ribiere
+                           update of the direction) and phi is stored in FP32.
+                           Convergence is tested on the device after every iteration
                            and, once reached, the solve's remaining kernels return at once.
                            Eager steps read that flag back every 4 iterations to stop
                            launching (a host synchronisation each time) and return
@@ -108,7 +111,8 @@ typedef struct {
                            through internal faces. */
   int32_t pcg_max_iter; /* masked: iteration cap per solve (<= 0: 500) */
   double pcg_tol;       /* masked: stop at ||r||_2 <= pcg_tol ||b||_2 over the internal cells,
-                           b = D u_p / (c_k dt) (<= 0: 1e-13) */
+                           b = D u_p / (c_k dt) (<= 0: 1e-13 with IBM_FP64, 1e-9 with
+                           IBM_FP32_STORAGE) */
 } ibm_grid_desc;
 
 typedef struct {
@@ -142,7 +146,7 @@ typedef struct {
  * all of them.  Validates the descriptors (IBM_ERR_ARG: nx odd, nx/2 or nz with a prime
  * factor outside {2,3,5}, nx or nz above 1024, ny outside 3..2049, more than 2e9/3
  * cells, dt <= 0, nu <= 0, an empty box, an unknown forcing, b_mode, top, projection or
- * precision, the masked projection without IBM_FP64, n_inst outside 1..65536 or a null
+ * precision, n_inst outside 1..65536 or a null
  * pointer), allocates device fields and the FFT and tridiagonal plans (IBM_ERR_OOM;
  * IBM_ERR_DEVICE if a HIP call fails).  Fields start at zero. */
 int ibm_create_grid(const ibm_grid_desc* desc, int32_t n_inst, int32_t precision,

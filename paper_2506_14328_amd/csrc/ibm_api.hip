@@ -45,6 +45,11 @@ struct Instance {
   double *kx2 = nullptr, *kz2 = nullptr;
   // masked projection: conjugate-gradient vectors r, z, p, A p and partial sums
   double* pcg_v[5] = {};   // r, z, p, A p and (stretched grids) W^-1 r
+  // FP32 storage: the FP64 iterate x, two FP32 z (the current and the previous one) and the
+  // FP32 preconditioner input
+  double* pcg_x = nullptr;
+  float* pcg_zf[2] = {};
+  float* pcg_rsf = nullptr;
   double* pcg_part = nullptr;
   double wall_vel[3] = {0.0, 0.0, 0.0};   // host copy of the immersed walls' velocity
   int pcg_iters = 0;        // iterations of the last masked solve
@@ -303,8 +308,6 @@ int validate(ibm_ctx* c, const ibm_grid_desc& d) {
   if (d.top != IBM_TOP_WALL && d.top != IBM_TOP_FREE_SLIP) return fail(c, IBM_ERR_ARG, "invalid top");
   if (d.projection != IBM_PROJ_FULL_BOX && d.projection != IBM_PROJ_MASKED)
     return fail(c, IBM_ERR_ARG, "invalid projection");
-  if (d.projection == IBM_PROJ_MASKED && c->precision != IBM_FP64)
-    return fail(c, IBM_ERR_ARG, "the masked projection needs IBM_FP64");
   return IBM_OK;
 }
 
@@ -356,6 +359,12 @@ int init_instance(ibm_ctx* c, Instance& I, const ibm_grid_desc& d) {
   if (d.projection == IBM_PROJ_MASKED) {
     for (int q = 0; q < 5; ++q)
       if ((rc = dalloc(c, I, (void**)&I.pcg_v[q], (size_t)g.ncell * sizeof(double)))) return rc;
+    if (c->precision == IBM_FP32_STORAGE) {
+      if ((rc = dalloc(c, I, (void**)&I.pcg_x, (size_t)g.ncell * sizeof(double)))) return rc;
+      for (int q = 0; q < 2; ++q)
+        if ((rc = dalloc(c, I, (void**)&I.pcg_zf[q], (size_t)g.ncell * sizeof(float)))) return rc;
+      if ((rc = dalloc(c, I, (void**)&I.pcg_rsf, (size_t)g.ncell * sizeof(float)))) return rc;
+    }
     if ((rc = dalloc(c, I, (void**)&I.pcg_part, (size_t)PCG_NSLOT * PCG_NPART * sizeof(double)))) return rc;
     if ((rc = dalloc(c, I, (void**)&I.pcg_stat, PCG_NSTAT * sizeof(int32_t) + 2 * sizeof(double)))) return rc;
     HIPCHK(c, hipMemsetAsync(I.pcg_stat, 0, PCG_NSTAT * sizeof(int32_t) + 2 * sizeof(double), c->stream));
@@ -454,24 +463,38 @@ int poisson(ibm_ctx* c, Instance& I, const GridParams& g, Fields<T>& f, T* phi_o
 // PCG_CHECK iterations to stop launching (a host synchronisation each time).  Captured
 // into a graph (capture true): a fixed budget of I.pcg_budget iterations and no host
 // access; a solve that has not converged within the budget is reported by ibm_stats.
+// FP32 storage: the iteration in FP64 with an FP32 preconditioner (flexible beta), the
+// result stored back into the FP32 phi, default tolerance 1e-9 (phi is stored to about 6e-8).
 constexpr int PCG_CHECK = 4;
-int pcg_project(ibm_ctx* c, Instance& I, Fields<double>& f, hipStream_t st, bool capture) {
+template <typename T>
+int pcg_project(ibm_ctx* c, Instance& I, Fields<T>& f, hipStream_t st, bool capture) {
+  constexpr bool f64 = std::is_same<T, double>::value;
   const GridParams& g0 = I.g;
   GridParams g = g0;
   g.skip = I.pcg_stat + PCG_DONE;
-  double* x = f.phi;
-  double *r = I.pcg_v[0], *z = I.pcg_v[1], *p = I.pcg_v[2], *ap = I.pcg_v[3];
-  // on a stretched grid the residual is W (b - A x) and the preconditioner takes W^-1 r
-  double* rs = g0.stretched ? I.pcg_v[4] : nullptr;
-  const double* pre_in = rs ? rs : r;
+  double* x = f64 ? reinterpret_cast<double*>(f.phi) : I.pcg_x;
+  double *r = I.pcg_v[0], *p = I.pcg_v[2], *ap = I.pcg_v[3];
+  T* zb[2];
+  T* rs;
+  if constexpr (f64) {
+    zb[0] = zb[1] = I.pcg_v[1];
+    // on a stretched grid the residual is W (b - A x) and the preconditioner takes W^-1 r
+    rs = g0.stretched ? I.pcg_v[4] : nullptr;
+  } else {
+    zb[0] = I.pcg_zf[0];
+    zb[1] = I.pcg_zf[1];
+    rs = I.pcg_rsf;   // W^-1 r (W = 1 on a uniform grid), rounded to FP32
+  }
+  const T* pre_in = rs ? rs : reinterpret_cast<const T*>(r);
   double* part = I.pcg_part;
   double* sc = I.pcg_sc();
   double* rr_dev = reinterpret_cast<double*>(I.pcg_stat + PCG_NSTAT);
-  const double tol = I.d.pcg_tol > 0.0 ? I.d.pcg_tol : 1e-13;
+  const double tol = I.d.pcg_tol > 0.0 ? I.d.pcg_tol : (f64 ? 1e-13 : 1e-9);
   const int max_iter = I.d.pcg_max_iter > 0 ? I.d.pcg_max_iter : 500;
   const int budget = capture ? I.pcg_budget : max_iter;
   RUNK(c, K_PCG, launch_pcg_prep(I.mean(), sc, I.pcg_stat, st));
-  RUNK(c, K_PCG, launch_pcg_init(g0, I.tag, x, sc + 3, r, part, I.itotal + 3, rs, st));
+  if constexpr (!f64) RUNK(c, K_PCG, launch_pcg_load(g0, f.phi, x, st));
+  RUNK(c, K_PCG, launch_pcg_init<T>(g0, I.tag, x, sc + 3, r, part, I.itotal + 3, rs, st));
   RUNK(c, K_PCG, launch_pcg_total(g0, part, PCG_B, sc + 2, st));
   RUNK(c, K_PCG, launch_pcg_check(g0, part, sc, tol * tol, 0, I.pcg_stat, rr_dev, st));
   for (int it = 0; it < budget; ++it) {
@@ -481,16 +504,18 @@ int pcg_project(ibm_ctx* c, Instance& I, Fields<double>& f, hipStream_t st, bool
       SYNCHK(c, st);
       if (done) break;
     }
-    RUNK(c, K_DIV_FFTX, launch_div_fftx<double>(g, f, I.L, 0, I.px, I.rtw, 1.0, I.pi(), pre_in, st));
-    int rc = poisson<double>(c, I, g, f, z, st);
+    T* z = zb[it & 1];
+    const T* zo = (!f64 && it > 0) ? zb[(it + 1) & 1] : nullptr;
+    RUNK(c, K_DIV_FFTX, launch_div_fftx<T>(g, f, I.L, 0, I.px, I.rtw, 1.0, I.pi(), pre_in, st));
+    int rc = poisson<T>(c, I, g, f, z, st);
     if (rc) return rc;
-    RUNK(c, K_PCG, launch_pcg_rz(g, r, z, part, st));
-    RUNK(c, K_PCG, launch_pcg_dir(g, I.tag, z, p, part, sc, it, st));
+    RUNK(c, K_PCG, launch_pcg_rz<T>(g, r, z, zo, part, st));
+    RUNK(c, K_PCG, launch_pcg_dir<T>(g, I.tag, z, p, part, sc, it, !f64, st));
     RUNK(c, K_PCG, launch_pcg_apply(g, I.tag, p, ap, part, st));
-    RUNK(c, K_PCG, launch_pcg_step(g, I.tag, x, r, p, ap, part, sc, it, rs, st));
+    RUNK(c, K_PCG, launch_pcg_step<T>(g, I.tag, x, r, p, ap, part, sc, it, rs, st));
     RUNK(c, K_PCG, launch_pcg_check(g0, part, sc, tol * tol, it + 1, I.pcg_stat, rr_dev, st));
   }
-  RUNK(c, K_PCG, launch_pcg_finish(g0, I.tag, x, part, I.itotal + 3, st));
+  RUNK(c, K_PCG, launch_pcg_finish<T>(g0, I.tag, x, part, I.itotal + 3, f.phi, st));
   RUNK(c, K_PCG, launch_pcg_post(I.mean(), sc, st));
   if (capture) return IBM_OK;
   int32_t stat[PCG_NSTAT];
@@ -548,9 +573,7 @@ int run_steps(ibm_ctx* c, Instance& I, int nsteps, hipStream_t st, bool count = 
       int rc = poisson<T>(c, I, I.g, f, f.phi, st);
       if (rc) return rc;
       const bool masked = I.d.projection == IBM_PROJ_MASKED;
-      if constexpr (std::is_same<T, double>::value) {
-        if (masked && (rc = pcg_project(c, I, f, st, !count))) return rc;
-      }
+      if (masked && (rc = pcg_project<T>(c, I, f, st, !count))) return rc;
       if (c->diag && s == nsteps - 1 && k == 2 && !masked) {
         int np = 0;
         RUNK(c, K_DIAG, launch_diag<T>(g, f, I.L, k, sc.ck_dt, I.pi(), I.mean(), I.red_part, &np, st));

@@ -433,7 +433,7 @@ hipError_t launch_geom_south_wall(const GridParams& g, const double* su, int ibm
 // masked projection (conjugate gradients on the internal pressure cells): partial-sum
 // slots of PCG_NPART doubles each
 constexpr int PCG_NPART = 1024;
-enum { PCG_B = 0, PCG_R2, PCG_X, PCG_RZ, PCG_PAP, PCG_RS, PCG_NSLOT };
+enum { PCG_B = 0, PCG_R2, PCG_X, PCG_RZ, PCG_PAP, PCG_RS, PCG_RZO, PCG_NSLOT };
 // Device status of the last masked solve (int32 slots): converged flag, iterations, and
 // the iteration budget it ran under (0: unbounded eager solve); its final |r|^2 is kept
 // as a double in the status's second half.
@@ -448,19 +448,31 @@ hipError_t launch_pcg_check(const GridParams& g, const double* part, const doubl
 hipError_t launch_pcg_post(double* mean, const double* sc, hipStream_t st);
 int pcg_blocks(const GridParams& g);
 // n_internal: device count of the internal pressure cells
-// (rs, on stretched grids: W^-1 r, the preconditioner's input; null on uniform grids)
+// P: the preconditioner's (storage) precision.  rs: W^-1 r in P, the preconditioner's
+// input (stretched grids, FP32 storage; null otherwise: the input is r)
+template <typename P>
 hipError_t launch_pcg_init(const GridParams& g, const uint8_t* tag, const double* x, const double* mean, double* r,
-                           double* part, const int32_t* n_internal, double* rs, hipStream_t st);
-hipError_t launch_pcg_rz(const GridParams& g, const double* r, const double* z, double* part, hipStream_t st);
-hipError_t launch_pcg_dir(const GridParams& g, const uint8_t* tag, const double* z, double* p, double* part,
-                          double* sc, int it, hipStream_t st);
+                           double* part, const int32_t* n_internal, P* rs, hipStream_t st);
+// x = phi (FP32 storage: the starting point into FP64)
+hipError_t launch_pcg_load(const GridParams& g, const float* phi, double* x, hipStream_t st);
+// partials of r . z and (zo not null) r . zo
+template <typename P>
+hipError_t launch_pcg_rz(const GridParams& g, const double* r, const P* z, const P* zo, double* part,
+                         hipStream_t st);
+// flexible: the Polak-Ribiere beta from the r . zo partials
+template <typename P>
+hipError_t launch_pcg_dir(const GridParams& g, const uint8_t* tag, const P* z, double* p, double* part,
+                          double* sc, int it, bool flexible, hipStream_t st);
 hipError_t launch_pcg_apply(const GridParams& g, const uint8_t* tag, const double* p, double* ap, double* part,
                             hipStream_t st);
+template <typename P>
 hipError_t launch_pcg_step(const GridParams& g, const uint8_t* tag, double* x, double* r, const double* p,
-                           const double* ap, double* part, const double* sc, int it, double* rs, hipStream_t st);
+                           const double* ap, double* part, const double* sc, int it, P* rs, hipStream_t st);
 hipError_t launch_pcg_total(const GridParams& g, const double* part, int slot, double* out, hipStream_t st);
-hipError_t launch_pcg_finish(const GridParams& g, const uint8_t* tag, double* x, const double* part,
-                             const int32_t* n_internal, hipStream_t st);
+// the gauged solution (zero mean over the internal cells) into out (x itself in FP64)
+template <typename P>
+hipError_t launch_pcg_finish(const GridParams& g, const uint8_t* tag, const double* x, const double* part,
+                             const int32_t* n_internal, P* out, hipStream_t st);
 // tau_x[nx] and, if modes is not null, modes[3] = (tau_0, tau_1c, tau_1s)
 template <typename T>
 hipError_t launch_wall_shear(const GridParams& g, const T* u, const int32_t* wj, const double* wd,

@@ -10,6 +10,12 @@
 // diagonal of cell heights: r holds W (b - A x), the preconditioner takes W^-1 r (rs,
 // written where r is), and the operator applied to the direction is W A p.
 //
+// FP32 storage: the conjugate-gradient vectors stay FP64; the preconditioner (the
+// full-box solve in the storage precision) takes an FP32 copy of its input (rs) and returns
+// an FP32 z, which is inexact by rounding, so the direction update takes the flexible
+// (Polak-Ribiere) beta = r . (z - z_prev) / rho_prev, for which the iteration tolerates a
+// preconditioner that varies slightly from one application to the next.
+//
 // Vectors live on the full cell array; r and p are zero outside the internal cells.
 // Every reduction writes one partial per block (at most PCG_NPART blocks, grid-stride
 // loops); the kernel that needs the total re-adds the partials in the same fixed order
@@ -113,11 +119,13 @@ __global__ __launch_bounds__(PT) void k_pcg_init(GridParams g, const uint8_t* __
 // The operator's range is orthogonal to the constant on the internal cells, and no
 // iteration changes the sum of r: its rounding-level mean (from b, which only matches
 // the divergence to the full-box solve's accuracy) is removed here.  Partials of |r0|^2.
-// With rs (stretched grids) also rs = W^-1 r everywhere (zero outside the internal cells).
+// With rs (stretched grids, FP32 storage) also rs = W^-1 r in the preconditioner's
+// precision P everywhere (zero outside the internal cells).
+template <typename P>
 __global__ __launch_bounds__(PT) void k_pcg_center(GridParams g, const uint8_t* __restrict__ tag,
                                                   double* __restrict__ r, const double* __restrict__ prs, int nb,
                                                   const int32_t* __restrict__ n_internal, double* __restrict__ pr,
-                                                  double* __restrict__ rs) {
+                                                  P* __restrict__ rs) {
   __shared__ double smem[8];
   const double mean = sum_partials(prs, nb, smem) / (double)n_internal[0];
   double ar = 0.0;
@@ -128,35 +136,52 @@ __global__ __launch_bounds__(PT) void k_pcg_center(GridParams g, const uint8_t* 
       r[c] = rv;
       ar += rv * rv;
     }
-    if (rs) rs[c] = rv / row_weight(g, c);
+    if (rs) rs[c] = P(rv / row_weight(g, c));
   }
   put_partial(ar, smem, pr);
 }
 
-// partials of r . z (r is zero outside the internal cells)
-__global__ __launch_bounds__(PT) void k_pcg_rz(GridParams g, const double* __restrict__ r,
-                                              const double* __restrict__ z, double* __restrict__ part) {
-  if (g.skip && *g.skip) return;
-  __shared__ double smem[8];
-  double a = 0.0;
-  for (int c = blockIdx.x * PT + threadIdx.x; c < g.ncell; c += gridDim.x * PT) a += r[c] * z[c];
-  put_partial(a, smem, part);
+// x = phi (FP32 storage: the full-box solution that starts the iteration, into FP64)
+__global__ __launch_bounds__(PT) void k_pcg_load(GridParams g, const float* __restrict__ phi,
+                                                double* __restrict__ x) {
+  for (int c = blockIdx.x * PT + threadIdx.x; c < g.ncell; c += gridDim.x * PT) x[c] = (double)phi[c];
 }
 
-// rho = r . z; p = z + (rho / rho_prev) p on the internal cells (p = z at it = 0), 0
-// elsewhere; rho goes to sc[it & 1], rho_prev is read from the other slot.
+// partials of r . z (r is zero outside the internal cells)
+// (with zo, the previous z: partials of r . zo too, for the flexible beta)
+template <typename P>
+__global__ __launch_bounds__(PT) void k_pcg_rz(GridParams g, const double* __restrict__ r,
+                                              const P* __restrict__ z, double* __restrict__ part,
+                                              const P* __restrict__ zo, double* __restrict__ part_o) {
+  if (g.skip && *g.skip) return;
+  __shared__ double smem[8];
+  double a = 0.0, ao = 0.0;
+  for (int c = blockIdx.x * PT + threadIdx.x; c < g.ncell; c += gridDim.x * PT) {
+    a += r[c] * (double)z[c];
+    if (zo) ao += r[c] * (double)zo[c];
+  }
+  put_partial(a, smem, part);
+  if (zo) put_partial(ao, smem, part_o);
+}
+
+// rho = r . z; p = z + beta p on the internal cells (p = z at it = 0), 0 elsewhere, with
+// beta = rho / rho_prev, or (flexible, przo not null) (rho - r . z_prev) / rho_prev; rho
+// goes to sc[it & 1], rho_prev is read from the other slot.
+template <typename P>
 __global__ __launch_bounds__(PT) void k_pcg_dir(GridParams g, const uint8_t* __restrict__ tag,
-                                               const double* __restrict__ z, double* __restrict__ p,
-                                               const double* __restrict__ prz, int nb, double* __restrict__ sc,
-                                               int it) {
+                                               const P* __restrict__ z, double* __restrict__ p,
+                                               const double* __restrict__ prz, const double* __restrict__ przo,
+                                               int nb, double* __restrict__ sc, int it) {
   if (g.skip && *g.skip) return;
   __shared__ double smem[8];
   const double rho = sum_partials(prz, nb, smem);
+  const double rho_o = (przo && it > 0) ? sum_partials(przo, nb, smem) : 0.0;
   const double rho_prev = it > 0 ? sc[(it + 1) & 1] : 0.0;
-  const double beta = rho_prev != 0.0 ? rho / rho_prev : 0.0;
+  const double beta = rho_prev != 0.0 ? (przo ? (rho - rho_o) / rho_prev : rho / rho_prev) : 0.0;
   for (int c = blockIdx.x * PT + threadIdx.x; c < g.ncell; c += gridDim.x * PT) {
     const bool in = (tag[c] & TAG_P) != 0;
-    p[c] = in ? (it > 0 ? z[c] + beta * p[c] : z[c]) : 0.0;
+    const double zc = (double)z[c];
+    p[c] = in ? (it > 0 ? zc + beta * p[c] : zc) : 0.0;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) sc[it & 1] = rho;
 }
@@ -192,12 +217,13 @@ __global__ __launch_bounds__(PT) void k_pcg_apply(GridParams g, const uint8_t* _
 
 // alpha = rho / (p . ap); x += alpha p, r -= alpha ap on the internal cells; partials of
 // |r|^2 and sum x there.
+template <typename P>
 __global__ __launch_bounds__(PT) void k_pcg_step(GridParams g, const uint8_t* __restrict__ tag,
                                                 double* __restrict__ x, double* __restrict__ r,
                                                 const double* __restrict__ p, const double* __restrict__ ap,
                                                 const double* __restrict__ ppap, int nb,
                                                 const double* __restrict__ sc, int it, double* __restrict__ pr,
-                                                double* __restrict__ px, double* __restrict__ rs) {
+                                                double* __restrict__ px, P* __restrict__ rs) {
   if (g.skip && *g.skip) return;
   __shared__ double smem[8];
   const double pap = sum_partials(ppap, nb, smem);
@@ -209,7 +235,7 @@ __global__ __launch_bounds__(PT) void k_pcg_step(GridParams g, const uint8_t* __
       const double rv = r[c] - alpha * ap[c];
       x[c] = xv;
       r[c] = rv;
-      if (rs) rs[c] = rv / row_weight(g, c);
+      if (rs) rs[c] = P(rv / row_weight(g, c));
       ar += rv * rv;
       ax += xv;
     }
@@ -257,13 +283,15 @@ __global__ void k_pcg_post(double* __restrict__ mean, const double* __restrict__
 }
 
 // gauge: phi = x - mean of x over the internal cells there, 0 elsewhere
+// (the result into out, in the storage precision: x itself in FP64)
+template <typename P>
 __global__ __launch_bounds__(PT) void k_pcg_finish(GridParams g, const uint8_t* __restrict__ tag,
-                                                  double* __restrict__ x, const double* __restrict__ px, int nb,
-                                                  const int32_t* __restrict__ n_internal) {
+                                                  const double* __restrict__ x, const double* __restrict__ px, int nb,
+                                                  const int32_t* __restrict__ n_internal, P* __restrict__ out) {
   __shared__ double smem[8];
   const double mean = sum_partials(px, nb, smem) / (double)n_internal[0];
   for (int c = blockIdx.x * PT + threadIdx.x; c < g.ncell; c += gridDim.x * PT)
-    x[c] = (tag[c] & TAG_P) ? x[c] - mean : 0.0;
+    out[c] = P((tag[c] & TAG_P) ? x[c] - mean : 0.0);
 }
 
 }  // namespace
@@ -273,25 +301,36 @@ int pcg_blocks(const GridParams& g) {
   return (int)(nb < PCG_NPART ? nb : PCG_NPART);
 }
 
+template <typename P>
 hipError_t launch_pcg_init(const GridParams& g, const uint8_t* tag, const double* x, const double* mean, double* r,
-                           double* part, const int32_t* n_internal, double* rs, hipStream_t st) {
+                           double* part, const int32_t* n_internal, P* rs, hipStream_t st) {
   const int nb = pcg_blocks(g);
   hipLaunchKernelGGL(k_pcg_init, dim3(nb), dim3(PT), 0, st, g, tag, x, mean, r, part + PCG_B * PCG_NPART,
                      part + PCG_RS * PCG_NPART, part + PCG_X * PCG_NPART);
-  hipLaunchKernelGGL(k_pcg_center, dim3(nb), dim3(PT), 0, st, g, tag, r, part + PCG_RS * PCG_NPART, nb,
+  hipLaunchKernelGGL(k_pcg_center<P>, dim3(nb), dim3(PT), 0, st, g, tag, r, part + PCG_RS * PCG_NPART, nb,
                      n_internal, part + PCG_R2 * PCG_NPART, rs);
   return hipGetLastError();
 }
 
-hipError_t launch_pcg_rz(const GridParams& g, const double* r, const double* z, double* part, hipStream_t st) {
-  hipLaunchKernelGGL(k_pcg_rz, dim3(pcg_blocks(g)), dim3(PT), 0, st, g, r, z, part + PCG_RZ * PCG_NPART);
+hipError_t launch_pcg_load(const GridParams& g, const float* phi, double* x, hipStream_t st) {
+  hipLaunchKernelGGL(k_pcg_load, dim3(pcg_blocks(g)), dim3(PT), 0, st, g, phi, x);
   return hipGetLastError();
 }
 
-hipError_t launch_pcg_dir(const GridParams& g, const uint8_t* tag, const double* z, double* p, double* part,
-                          double* sc, int it, hipStream_t st) {
+template <typename P>
+hipError_t launch_pcg_rz(const GridParams& g, const double* r, const P* z, const P* zo, double* part,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_pcg_rz<P>, dim3(pcg_blocks(g)), dim3(PT), 0, st, g, r, z, part + PCG_RZ * PCG_NPART, zo,
+                     part + PCG_RZO * PCG_NPART);
+  return hipGetLastError();
+}
+
+template <typename P>
+hipError_t launch_pcg_dir(const GridParams& g, const uint8_t* tag, const P* z, double* p, double* part,
+                          double* sc, int it, bool flexible, hipStream_t st) {
   const int nb = pcg_blocks(g);
-  hipLaunchKernelGGL(k_pcg_dir, dim3(nb), dim3(PT), 0, st, g, tag, z, p, part + PCG_RZ * PCG_NPART, nb, sc, it);
+  hipLaunchKernelGGL(k_pcg_dir<P>, dim3(nb), dim3(PT), 0, st, g, tag, z, p, part + PCG_RZ * PCG_NPART,
+                     flexible ? part + PCG_RZO * PCG_NPART : nullptr, nb, sc, it);
   return hipGetLastError();
 }
 
@@ -301,10 +340,11 @@ hipError_t launch_pcg_apply(const GridParams& g, const uint8_t* tag, const doubl
   return hipGetLastError();
 }
 
+template <typename P>
 hipError_t launch_pcg_step(const GridParams& g, const uint8_t* tag, double* x, double* r, const double* p,
-                           const double* ap, double* part, const double* sc, int it, double* rs, hipStream_t st) {
+                           const double* ap, double* part, const double* sc, int it, P* rs, hipStream_t st) {
   const int nb = pcg_blocks(g);
-  hipLaunchKernelGGL(k_pcg_step, dim3(nb), dim3(PT), 0, st, g, tag, x, r, p, ap, part + PCG_PAP * PCG_NPART, nb,
+  hipLaunchKernelGGL(k_pcg_step<P>, dim3(nb), dim3(PT), 0, st, g, tag, x, r, p, ap, part + PCG_PAP * PCG_NPART, nb,
                      sc, it, part + PCG_R2 * PCG_NPART, part + PCG_X * PCG_NPART, rs);
   return hipGetLastError();
 }
@@ -331,10 +371,26 @@ hipError_t launch_pcg_post(double* mean, const double* sc, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_pcg_finish(const GridParams& g, const uint8_t* tag, double* x, const double* part,
-                             const int32_t* n_internal, hipStream_t st) {
+template <typename P>
+hipError_t launch_pcg_finish(const GridParams& g, const uint8_t* tag, const double* x, const double* part,
+                             const int32_t* n_internal, P* out, hipStream_t st) {
   const int nb = pcg_blocks(g);
-  hipLaunchKernelGGL(k_pcg_finish, dim3(nb), dim3(PT), 0, st, g, tag, x, part + PCG_X * PCG_NPART, nb,
-                     n_internal);
+  hipLaunchKernelGGL(k_pcg_finish<P>, dim3(nb), dim3(PT), 0, st, g, tag, x, part + PCG_X * PCG_NPART, nb,
+                     n_internal, out);
   return hipGetLastError();
 }
+
+#define IBM_PCG_INST(P)                                                                                          \
+  template hipError_t launch_pcg_init<P>(const GridParams&, const uint8_t*, const double*, const double*,      \
+                                         double*, double*, const int32_t*, P*, hipStream_t);                    \
+  template hipError_t launch_pcg_rz<P>(const GridParams&, const double*, const P*, const P*, double*,           \
+                                       hipStream_t);                                                             \
+  template hipError_t launch_pcg_dir<P>(const GridParams&, const uint8_t*, const P*, double*, double*, double*, \
+                                        int, bool, hipStream_t);                                                 \
+  template hipError_t launch_pcg_step<P>(const GridParams&, const uint8_t*, double*, double*, const double*,   \
+                                         const double*, double*, const double*, int, P*, hipStream_t);         \
+  template hipError_t launch_pcg_finish<P>(const GridParams&, const uint8_t*, const double*, const double*,    \
+                                           const int32_t*, P*, hipStream_t);
+IBM_PCG_INST(double)
+IBM_PCG_INST(float)
+#undef IBM_PCG_INST

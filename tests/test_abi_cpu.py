@@ -76,8 +76,7 @@ int main(void) {
 @needs_lib
 @pytest.mark.parametrize("bad", [
     dict(nx=7), dict(nx=14), dict(nz=7), dict(ny=2), dict(dt=0.0), dict(nu=-1.0), dict(y_hi=-2.0),
-    dict(forcing=3), dict(b_mode=9), dict(nx=2048), dict(top=2), dict(projection=2),
-    dict(projection=1, precision=1),
+    dict(forcing=3), dict(b_mode=9), dict(nx=2048), dict(top=2), dict(projection=2), dict(precision=2),
 ])
 def test_invalid_descriptor_rejected(bad):
     from paper_2506_14328_amd.ibm import IBM_ERR_ARG, IbmGridDesc

@@ -71,6 +71,38 @@ def test_masked_graph_equals_eager(name):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("name,nsteps", [("open_small", 2), ("wavy_small", 2)])
+def test_masked_fp32_storage(name, nsteps):
+    """The masked projection in FP32 storage: the conjugate gradients in FP64 with the FP32
+    full-box solve as preconditioner (flexible beta), phi stored in FP32; against the
+    oracle's FP64 direct solve the velocity is within the FP32-storage bar, 1e-5 of the
+    largest speed component, the solve reaches its tolerance (1e-9) and continuity holds
+    on the internal cells to FP32 rounding.  The captured graph equals the eager steps
+    bit for bit."""
+    c = case(name, projection=1)
+    o, sdf, st = oracle_run(c, nsteps)
+    out = []
+    for graph in (0, 1):
+        g = gpu_grid(c, sdf, st, "fp32")
+        g.tune(graph=graph)
+        g.step(nsteps)
+        s = g.stats()
+        out.append(([t.double().cpu().numpy() for t in g.get_state()], s))
+        g.close()
+    (u, v, w, p), s = out[0]
+    scale = max(np.abs(o.u).max(), np.abs(o.v).max(), np.abs(o.w).max())
+    errs = [np.abs(a - b).max() / scale for a, b in ((u, o.u), (v, o.v), (w, o.w))]
+    leak = s["div_max_internal_leak"] * min(o.g.dx, o.g.dy, o.g.dz) / scale
+    _say(f"{name} fp32: pcg iterations {s['pcg_iters']}, |r|/|b| {s['poisson_rel_residual']:.1e}; "
+         f"u,v,w {['%.1e' % e for e in errs]}; internal divergence * h / U {leak:.1e}")
+    assert s["pcg_iters"] > 0 and 0.0 <= s["poisson_rel_residual"] <= 1e-9
+    assert max(errs) < 1e-5
+    assert leak < 1e-5
+    assert out[1][1]["pcg_iters"] == s["pcg_iters"]
+    for a, b in zip(out[0][0], out[1][0]):
+        assert np.array_equal(a, b)
+
+
 def test_masked_iteration_cap_is_reported():
     """A solve that reaches pcg_max_iter without converging (the device flag unset) makes
     ibm_step return IBM_ERR_UNSTABLE, also with the graph requested (its first step is
