@@ -356,6 +356,7 @@ int init_instance(ibm_ctx* c, Instance& I, const ibm_grid_desc& d) {
   I.L.wallv = I.wallv();
   I.L.sd = I.wall_sd();
   if ((rc = dalloc(c, I, (void**)&I.itotal, 32 * sizeof(int32_t)))) return rc;
+  HIPCHK(c, hipMemsetAsync(I.itotal, 0, 32 * sizeof(int32_t), c->stream));
   if (d.projection == IBM_PROJ_MASKED) {
     for (int q = 0; q < 5; ++q)
       if ((rc = dalloc(c, I, (void**)&I.pcg_v[q], (size_t)g.ncell * sizeof(double)))) return rc;
@@ -643,6 +644,9 @@ void free_buf(DevBuf& b) {
   b.bytes = 0;
 }
 
+// What a geometry update does about a projection left pending by the last step.
+enum { PENDING_NONE = 0, PENDING_APPLIED, PENDING_FUSE };
+
 // Geometry preprocessing (staircase tags, wall distances, immersed-boundary lists and
 // coefficients, S_k), all on the stream.  The first geometry of an instance (or the next
 // one after the lists overflowed) reads the point counts back, sizes the lists with room
@@ -651,7 +655,7 @@ void free_buf(DevBuf& b) {
 // body can be advanced between steps at the cost of a few kernels, also inside a graph
 // the caller captures.  *sized: whether the lists were (re)allocated.
 int set_geometry_impl(ibm_ctx* c, Instance& I, const double* su, const double* sv, const double* sw,
-                      bool* sized, bool zero_pending) {
+                      bool* sized, int pending) {
   const GridParams& g = I.g;
   hipStream_t st = c->stream;
   const size_t nc = (size_t)g.ncell;
@@ -659,9 +663,11 @@ int set_geometry_impl(ibm_ctx* c, Instance& I, const double* su, const double* s
   const int cpr = (g.nx + IBM_WAVE - 1) / IBM_WAVE;
   const size_t nch = (size_t)g.nrows * cpr + 1;
   *sized = false;
-  // dense lambda and wall-velocity coefficient per component and per-block counts of the
-  // seven tag masks: allocated at the first geometry of the instance and kept
-  const size_t tmp_bytes = 6 * nc * 8 + (size_t)(7 * nblk + 1) * 4;
+  // dense lambda and wall-velocity coefficient per component, per-block counts of the
+  // seven tag masks and the scan's tile sums: allocated at the first geometry of the
+  // instance and kept
+  const int ntile = 7 * scan_tiles(nblk) + 3 * scan_tiles((int64_t)nch);
+  const size_t tmp_bytes = 6 * nc * 8 + (size_t)(7 * nblk + 1) * 4 + (size_t)ntile * 4;
   if (!I.geo_tmp.p) {
     if (hipMalloc(&I.geo_tmp.p, tmp_bytes) != hipSuccess) {
       I.geo_tmp.p = nullptr;
@@ -684,20 +690,33 @@ int set_geometry_impl(ibm_ctx* c, Instance& I, const double* su, const double* s
   double* sig_w = sig_v + nc;
   int32_t* blk = (int32_t*)(sig_w + nc);
   // I.itotal: [0..6] counts of internal u, v, w, p and immersed-boundary u, v, w points,
-  // [8] the lists' overflow flag, [16..18] totals of the chunk counts (not used)
+  // [8] the lists' overflow flag, [16..18] totals of the chunk counts (not used), [24] the
+  // S_k blocks' completion counter (zero between launches)
   int32_t* cnt7 = I.itotal;
   int32_t* overflow = I.itotal + 8;
   int32_t* chunk_totals = I.itotal + 16;
+  unsigned* s_done = reinterpret_cast<unsigned*>(I.itotal + 24);
   const bool first = !I.ibm_idx.p || I.lists_overflowed;
   int rc = IBM_OK;
   do {
-    // (a projection applied just before has left phi and Pi to be zeroed: done here)
+    // pending: PENDING_APPLIED, a projection applied just before has left phi and Pi to be
+    // zeroed; PENDING_FUSE, the tag kernel applies it first (with the old tags, over the
+    // predictor slot it came from), phi and Pi zeroed after
     const int esz = c->precision == IBM_FP64 ? 8 : 4;
+    const bool fuse = pending == PENDING_FUSE;
+    const double ck_dt = rk_c(2) * g.dt;
     hipError_t e = timed(c, K_GEOM, [&]() {
-      return launch_geom_lambda(g, su, sv, sw, I.d.ibm, I.tag, lam_u, lam_v, lam_w, sig_u, sig_v, sig_w,
-                                zero_pending ? I.phi : nullptr, esz, zero_pending ? I.pi() : nullptr, st);
+      if (c->precision == IBM_FP64) {
+        Fields<double> f = fields_of<double>(I);
+        f.us = f.usp; f.vs = f.vsp; f.ws = f.wsp;   // the predictor awaiting its projection
+        return launch_geom_lambda<double>(g, su, sv, sw, I.d.ibm, I.tag, lam_u, lam_v, lam_w, sig_u, sig_v, sig_w,
+                                          fuse, f, I.wallv(), ck_dt, I.pi(), I.wall_j, I.wall_d, st);
+      }
+      Fields<float> f = fields_of<float>(I);
+      f.us = f.usp; f.vs = f.vsp; f.ws = f.wsp;
+      return launch_geom_lambda<float>(g, su, sv, sw, I.d.ibm, I.tag, lam_u, lam_v, lam_w, sig_u, sig_v, sig_w,
+                                       fuse, f, I.wallv(), ck_dt, I.pi(), I.wall_j, I.wall_d, st);
     });
-    if (e == hipSuccess) e = launch_geom_south_wall(g, su, I.d.ibm, I.wall_j, I.wall_d, st);
     // pressure tags with the per-block counts of the seven masks (the overflow flag
     // cleared), and the per-(row, 64-wide chunk) counts of the three immersed-boundary
     // masks; then all ten count arrays scanned in place (offsets) in one launch
@@ -707,7 +726,8 @@ int set_geometry_impl(ibm_ctx* c, Instance& I, const double* su, const double* s
     int32_t* choff = (int32_t*)I.ibm_choff.p;
     const bool whole_chunks = g.nx % IBM_WAVE == 0;
     if (e == hipSuccess)
-      e = launch_geom_ptag_counts(g, I.tag, masks, 7, blk, nblk, overflow, whole_chunks ? choff : nullptr, st);
+      e = launch_geom_ptag_counts(g, I.tag, masks, 7, blk, nblk, overflow, whole_chunks ? choff : nullptr,
+                                  pending ? I.phi : nullptr, esz, pending ? I.pi() : nullptr, st);
     if (e == hipSuccess && !whole_chunks) e = launch_chunk_counts3(I.tag, g, cpr, choff, st);
     ScanSet set{};
     for (int m = 0; m < 7; ++m) {
@@ -721,6 +741,8 @@ int set_geometry_impl(ibm_ctx* c, Instance& I, const double* su, const double* s
       set.total[7 + m] = chunk_totals + m;
     }
     set.narr = 10;
+    set.tsum = blk + 7 * (size_t)nblk + 1;
+    set.tsum_cap = ntile;
     if (e == hipSuccess) e = launch_scan_multi(set, st);
     if (e != hipSuccess) { rc = fail(c, IBM_ERR_DEVICE, std::string("geometry: ") + hipGetErrorString(e)); break; }
     if (first) {
@@ -763,8 +785,8 @@ int set_geometry_impl(ibm_ctx* c, Instance& I, const double* su, const double* s
     double2* coef = (double2*)I.ibm_coef.p;
     double* lamo = (double*)I.ibm_lam.p;
     double* sigo = (double*)I.ibm_sig.p;
-    e = launch_compact3(I.tag, g.ncell, blk + 4 * (size_t)nblk, nblk, idx, I.cap, overflow, lam_u, sig_u, I.d.dt,
-                        I.d.b_mode, lamo, sigo, coef, st);
+    e = launch_compact3(I.tag, g.ncell, blk + 4 * (size_t)nblk, nblk, idx, I.cap, overflow, lam_u, sig_u, lamo,
+                        sigo, st);
     if (e != hipSuccess) { rc = fail(c, IBM_ERR_DEVICE, std::string("ibm lists: ") + hipGetErrorString(e)); break; }
     I.L.choff_u = choff;
     I.L.choff_v = choff + nch;
@@ -781,11 +803,9 @@ int set_geometry_impl(ibm_ctx* c, Instance& I, const double* su, const double* s
     I.L.n_w = I.cap[2];
     I.L.n_total = I.cap[0] + I.cap[1] + I.cap[2];
     I.L.n_cover = I.moving() ? I.L.n_total : I.L.n_u;
-    int np = 0;
-    e = launch_s_k(g, I.tag, I.L, I.red_part, &np, st);
-    if (e == hipSuccess)
-      e = launch_s_k_final(I.red_part, np, I.d.dt * y_scale(g) * g.dz / g.nx, I.S3(), g, I.L, cnt7, I.wall_sd(),
-                           st);
+    // (with every listed point's per-stage coefficients)
+    e = launch_s_k(g, I.tag, I.L, lamo, coef, I.d.dt, I.d.b_mode, I.red_part, I.d.dt * y_scale(g) * g.dz / g.nx,
+                   I.S3(), cnt7, I.wall_sd(), s_done, st);
     if (e != hipSuccess) { rc = fail(c, IBM_ERR_DEVICE, std::string("S_k: ") + hipGetErrorString(e)); break; }
     if (first && (rc = sync_stream(c, st))) break;
     I.geom_ready = true;
@@ -1107,9 +1127,18 @@ int ibm_set_geometry(ibm_handle h, int32_t inst, const double* sdf_u, const doub
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(h->stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) I.fresh = false;
   const bool pending = !I.fresh;
-  if ((rc = materialize(h, I, true))) return rc;
+  int how = PENDING_NONE;
+  if (pending && !sizing) {
+    // applied by the geometry's first kernel, as materialize(seed) would have
+    how = PENDING_FUSE;
+    I.fresh = true;
+    I.state_in_slot = true;
+  } else if (pending) {
+    if ((rc = materialize(h, I, true))) return rc;
+    how = PENDING_APPLIED;
+  }
   bool sized = false;
-  if ((rc = set_geometry_impl(h, I, sdf_u, sdf_v, sdf_w, &sized, pending))) {
+  if ((rc = set_geometry_impl(h, I, sdf_u, sdf_v, sdf_w, &sized, how))) {
     // (an update that failed before zeroing them must not leave phi and Pi to be applied
     // a second time)
     if (pending) {

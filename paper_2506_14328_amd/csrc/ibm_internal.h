@@ -156,6 +156,16 @@ __device__ __forceinline__ cplx<float> twiddle<float>(const FFTPlan& p, int m, i
   return {t.x, sign < 0 ? t.y : -t.y};
 }
 
+// 1/x (x normal, not tiny): the hardware reciprocal estimate refined by two Newton steps,
+// each of which squares the relative error, to full FP64 accuracy.
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+
 // Wave-level and block-level reductions (fixed order: deterministic).
 __device__ __forceinline__ double wave_sum(double v) {
   for (int o = IBM_WAVE / 2; o > 0; o >>= 1) v += __shfl_down(v, o, IBM_WAVE);
@@ -236,6 +246,35 @@ struct Fields {
   cplx<T>* spec;             // spectral work array (ny1, nz, mh)
   const uint8_t* tag;
 };
+
+// The state after a projection at point c = (j, k, i) (Sec. 3.3), from its tag tg, its
+// west, south and back neighbours cw, cs, cb (cs = c on the first row, whose v is never
+// internal): u = u* - c_k dt G phi on internal faces, with the pending -Pi c_k dt on
+// internal u faces that carry no immersed-boundary correction; the immersed walls'
+// velocity on external faces (v on the south box wall: 0); p = p' + phi on internal
+// cells, 0 elsewhere.  Each point reads only its own u*, p' and the phi of its neighbours.
+template <typename T>
+struct Corrected {
+  T u, v, w, p;
+};
+template <typename T>
+__device__ __forceinline__ Corrected<T> corrected_point(const GridParams& g, const Fields<T>& f,
+                                                        const double* __restrict__ wallv, uint8_t tg, int j, int c,
+                                                        int cw, int cs, int cb, double ck_dt, double pi0) {
+  const T ph = f.phi[c], phw = f.phi[cw], phs = f.phi[cs], phb = f.phi[cb];
+  const T usv = f.us[c], vsv = f.vs[c], wsv = f.ws[c], pv = f.pp[c];
+  const T ckdt = T(ck_dt);
+  const T pick = ((tg & (TAG_U | TAG_UI)) == TAG_U) ? T(pi0 * ck_dt) : T(0);
+  const T un = usv - pick - ckdt * ((ph - phw) * T(g.idx));
+  const T vn = vsv - ckdt * ((ph - phs) * T(g.stretched ? g.ytab[YT_IDYF * g.ystr + j] : g.idy));
+  const T wn = wsv - ckdt * ((ph - phb) * T(g.idz));
+  Corrected<T> r;
+  r.u = (tg & TAG_U) ? un : T(wallv[0]);
+  r.v = (tg & TAG_V) ? vn : (j == 0 ? T(0) : T(wallv[1]));
+  r.w = (tg & TAG_W) ? wn : T(wallv[2]);
+  r.p = (tg & TAG_P) ? pv + ph : T(0);
+  return r;
+}
 
 // Launch-shape knobs (0 = automatic choice); set directly or by the autotuner.
 struct Tuning {
@@ -417,19 +456,25 @@ hipError_t launch_reduce_final(const double* part, int npart, int nsum, int nmax
                                hipStream_t st);
 
 // geometry
-// tags, lambda and sigma (stored at immersed-boundary points only); with zphi, the cell's
-// phi (zelem bytes each) zeroed too, with zpi the mean pressure gradient
+// tags, lambda and sigma (stored at immersed-boundary points only) and the south-wall
+// point of every (k, i) column of u points: the lowest internal row wj (-1: none) and its
+// distance wd to the wall below, negative where that is the south box wall; with correct,
+// first the pending projection of the old geometry applied at every point with the old
+// tags and written over its predictor and pressure (f.us, f.vs, f.ws, f.pp;
+// corrected_point with c_k dt = ck_dt, Pi = pi[0])
+template <typename T>
 hipError_t launch_geom_lambda(const GridParams& g, const double* su, const double* sv, const double* sw,
                               int ibm_on, uint8_t* tag, double* lam_u, double* lam_v, double* lam_w,
-                              double* sig_u, double* sig_v, double* sig_w, void* zphi, int zelem, double* zpi,
+                              double* sig_u, double* sig_v, double* sig_w, bool correct, const Fields<T>& f,
+                              const double* wallv, double ck_dt, const double* pi, int32_t* wj, double* wd,
                               hipStream_t st);
 // pressure tags, then counts[m * nblk + block] of nm <= 8 tag masks (packed 8 bits each
 // into masks) per block of 256 cells (nblk blocks cover the cells); *clear zeroed; with
-// chunks (nx a multiple of 64) the per-(row, 64-chunk) immersed-boundary counts as well
+// chunks (nx a multiple of 64) the per-(row, 64-chunk) immersed-boundary counts as well;
+// with zphi every cell's phi (zelem bytes each) zeroed, with zpi the mean pressure gradient
 hipError_t launch_geom_ptag_counts(const GridParams& g, uint8_t* tag, uint64_t masks, int nm, int32_t* counts,
-                                   int nblk, int32_t* clear, int32_t* chunks, hipStream_t st);
-hipError_t launch_geom_south_wall(const GridParams& g, const double* su, int ibm_on, int32_t* wj, double* wd,
-                                  hipStream_t st);
+                                   int nblk, int32_t* clear, int32_t* chunks, void* zphi, int zelem, double* zpi,
+                                   hipStream_t st);
 // masked projection (conjugate gradients on the internal pressure cells): partial-sum
 // slots of PCG_NPART doubles each
 constexpr int PCG_NPART = 1024;
@@ -477,35 +522,44 @@ hipError_t launch_pcg_finish(const GridParams& g, const uint8_t* tag, const doub
 template <typename T>
 hipError_t launch_wall_shear(const GridParams& g, const T* u, const int32_t* wj, const double* wd,
                              const double* wallv, double* tau_x, double* modes, hipStream_t st);
-// exclusive scans in place of up to SCAN_MAX count arrays (one block each), their sums
-// into total[m]
+// exclusive scans in place of up to SCAN_MAX count arrays, their sums into total[m]: the
+// arrays are cut into tiles of SCAN_TILE counts, one block per tile; the tiles' sums go to
+// tsum (tsum_cap entries, at least scan_tiles(set)), then each tile is scanned from the
+// sum of the tiles before it.  tile_off is filled by the launcher.
 constexpr int SCAN_MAX = 12;
+constexpr int SCAN_TILE = 4096;
 struct ScanSet {
   int32_t* counts[SCAN_MAX];
   int32_t* total[SCAN_MAX];
   int n[SCAN_MAX];
+  int tile_off[SCAN_MAX + 1];
+  int32_t* tsum;
+  int tsum_cap;
   int narr;
 };
-hipError_t launch_scan_multi(const ScanSet& set, hipStream_t st);
+// tiles of an array of n counts (one tile for an empty array, which writes its zero total)
+inline int scan_tiles(int64_t n) { return n > 0 ? (int)((n + SCAN_TILE - 1) / SCAN_TILE) : 1; }
+hipError_t launch_scan_multi(ScanSet set, hipStream_t st);
 // the u, v, w immersed-boundary lists of capacities cap[] (laid end to end) from the
 // scanned per-block offsets of their masks (offsets[c * nblk + block]), with each point's
-// lambda, sigma (from lam_dense, sig_dense: three dense component arrays of n values) and
-// per-stage (B, 1/A); overflow[0] set when a component has more points than its capacity
+// lambda and sigma (from lam_dense, sig_dense: three dense component arrays of n values);
+// overflow[0] set when a component has more points than its capacity
 hipError_t launch_compact3(const uint8_t* tag, int64_t n, const int32_t* offsets, int nblk, int32_t* idx,
                            const int cap[3], int32_t* overflow, const double* lam_dense, const double* sig_dense,
-                           double dt, int b_mode, double* lam_out, double* sig_out, double2* coef, hipStream_t st);
+                           double* lam_out, double* sig_out, hipStream_t st);
 // per-(row, 64-chunk) counts of the three immersed-boundary masks, [3][nrows cpr + 1]
 hipError_t launch_chunk_counts3(const uint8_t* tag, const GridParams& g, int cpr, int32_t* counts, hipStream_t st);
 hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t st);
 
-// partial sums for S_k into part[0 .. 4 npart), then those of the sum over the IBM u
-// points of sig / A_k (part needs 4 (npart + n_u/256 + 1) doubles)
-hipError_t launch_s_k(const GridParams& g, const uint8_t* tag, const IbmLists& L, double* part, int* npart,
-                      hipStream_t st);
-// S3[k] from the partials; sd_out[k] (if not null) from the sigma/A partials launch_s_k
-// wrote after them
-hipError_t launch_s_k_final(const double* part, int npart, double scale, double* S3, const GridParams& g,
-                            const IbmLists& L, const int32_t* cnt7, double* sd_out, hipStream_t st);
+// every listed point's per-stage (B, 1/A) from its lambda (lam, list order) into coef,
+// and S3[k] = S_k (Sec. 2.4: c_k dt times the internal non-IBM u points plus the sum of
+// 1/A_k over the IBM u points, times scale = dy dz / nx) with sd_out[k] the sum over the
+// IBM u points of sig / A_k; part holds the partial sums (4 (ncell/256 + 2 n_u/256 + 2)
+// doubles), cnt7 the tag counts (uniform grids), done a device counter that is zero
+// between launches
+hipError_t launch_s_k(const GridParams& g, const uint8_t* tag, const IbmLists& L, const double* lam, double2* coef,
+                      double dt, int b_mode, double* part, double scale, double* S3, const int32_t* cnt7,
+                      double* sd_out, unsigned* done, hipStream_t st);
 
 // state copy helpers
 template <typename T>

@@ -9,168 +9,189 @@ constexpr int BZ = 4;
 __device__ __forceinline__ int wrap_p(int i, int n) { return (i + 1 == n) ? 0 : i + 1; }
 __device__ __forceinline__ int wrap_m(int i, int n) { return (i == 0) ? n - 1 : i - 1; }
 
-// Contribution nu (h - delta)/(delta h^2) of one arm whose neighbour is external
-// (Eq. (7) with d2(-1) = 1/h^2); delta = linear zero crossing of the signed distance
-// between the point and the neighbour, or the box wall distance when that is nearer.
-__device__ __forceinline__ double arm(double nu, double h, double sP, double sQ, bool extQ, double box) {
-  if (!extQ) return 0.0;
-  double delta = (sQ <= 0.0) ? h * sP / (sP - sQ) : INFINITY;
-  delta = fmin(delta, box);
-  return nu * (h - delta) / (delta * h * h);
+// One arm of a point P towards its neighbour Q (spacing h, second-derivative coefficient
+// d2: 1/h^2 on uniform arms), Q external (extQ): the wall lies at delta, the linear zero
+// crossing h sP/(sP - sQ) of the signed distance, or at the box wall distance `box` when
+// that is nearer (Eq. (7)).  Adds to lam the arm's share nu d2 (h - delta)/delta of the
+// Laplacian's centre change, and to src the coefficient of the wall velocity U_b in the
+// correction (the ghost extrapolated through U_b): 0 when the nearer wall is a box wall
+// (at rest); the arm's lambda share when Q stores U_b (an external point inside the box,
+// box = infinity); nu d2 h/delta when Q stores zero (the box-wall face or the ghost beyond
+// it, box finite).  delta takes an IEEE division, since delta < h decides whether P
+// carries a correction; 1/delta is refined from the hardware estimate.
+__device__ __forceinline__ void arm_pair(double nu, double h, double d2, double sP, double sQ, bool extQ,
+                                         double box, double& lam, double& src) {
+  if (!extQ) return;
+  const bool cross = sQ <= 0.0;
+  const double delta = cross ? h * sP / (sP - sQ) : INFINITY;
+  const double dl = fmin(delta, box);
+  const double r = dl > 1e-250 ? recip(dl) : 1.0 / dl;
+  const double l = nu * d2 * (h - dl) * r;
+  lam += l;
+  if (cross && delta < box) src += isinf(box) ? l : nu * d2 * h * r;
 }
 
-// The same with the arm's own second-derivative coefficient d2 (stretched wall-normal
-// arms): nu d2 (h - delta)/delta.
-__device__ __forceinline__ double arm_w(double nu, double h, double d2, double sP, double sQ, bool extQ,
-                                        double box) {
-  if (!extQ) return 0.0;
-  double delta = (sQ <= 0.0) ? h * sP / (sP - sQ) : INFINITY;
-  delta = fmin(delta, box);
-  return nu * d2 * (h - delta) / delta;
+// Wall-normal arm data of component q (0 u, 1 v, 2 w) on row j: the arms' spacings, their
+// second-derivative coefficients and whether the neighbour below / above is a box wall,
+// with that wall's distance (u, w: the south box face is a wall, so is the north one
+// unless it is free-slip, half a cell away; v: faces 0 and ny-1 are the walls, one spacing
+// away); INFINITY where the neighbour is not a box wall.
+struct YArms {
+  double hdn, hup, cdn, cup, bdn, bup;
+  bool gdn, gup;
+};
+__device__ __forceinline__ YArms y_arms(const GridParams& g, int q, int j) {
+  const bool sy = g.stretched != 0;
+  const double* yt = g.ytab;
+  const int ys = g.ystr, ny1 = g.ny1;
+  const double dy2 = 1.0 / (g.dy * g.dy);
+  YArms a;
+  a.bdn = a.bup = INFINITY;
+  if (q != 1) {
+    a.gdn = (j == 0);
+    a.gup = (j == ny1 - 1) && !g.top_fs;
+    a.hdn = sy ? yt[YT_HC * ys + j] : g.dy;
+    a.hup = sy ? yt[YT_HC * ys + j + 1] : g.dy;
+    a.cdn = sy ? yt[YT_DCM * ys + j] : dy2;
+    a.cup = sy ? yt[YT_DCP * ys + j] : dy2;
+    if (a.gdn) a.bdn = sy ? 0.5 * yt[YT_DYC * ys] : 0.5 * g.dy;
+    if (a.gup) a.bup = sy ? 0.5 * yt[YT_DYC * ys + ny1 - 1] : 0.5 * g.dy;
+  } else {
+    a.gdn = (j - 1 == 0);
+    a.gup = (j + 1 == ny1);
+    a.hdn = sy ? yt[YT_DYC * ys + j - 1] : g.dy;
+    a.hup = sy ? yt[YT_DYC * ys + j] : g.dy;
+    a.cdn = sy ? yt[YT_DFM * ys + j] : dy2;
+    a.cup = sy ? yt[YT_DFP * ys + j] : dy2;
+    if (a.gdn) a.bdn = a.hdn;
+    if (a.gup) a.bup = a.hup;
+  }
+  return a;
 }
 
-// Coefficient of the wall velocity U_b in the correction of one arm whose neighbour is
-// external (a rigidly moving immersed wall; the ghost is extrapolated through U_b): 0 when
-// the nearer wall is a box wall (at rest); lambda_arm when the neighbour stores U_b (an
-// external point inside the box, box = infinity); nu/(delta h) when it stores zero (the
-// box-wall face or the ghost beyond it, box finite).
-__device__ __forceinline__ double arm_src(double nu, double h, double sP, double sQ, bool extQ, double box) {
-  if (!extQ || !(sQ <= 0.0)) return 0.0;
-  const double delta = h * sP / (sP - sQ);
-  if (!(delta < box)) return 0.0;
-  return isinf(box) ? nu * (h - delta) / (delta * h * h) : nu / (delta * h);
-}
-__device__ __forceinline__ double arm_src_w(double nu, double h, double d2, double sP, double sQ, bool extQ,
-                                            double box) {
-  if (!extQ || !(sQ <= 0.0)) return 0.0;
-  const double delta = h * sP / (sP - sQ);
-  if (!(delta < box)) return 0.0;
-  return isinf(box) ? nu * d2 * (h - delta) / delta : nu * d2 * h / delta;
+// The seven samples (P, x-, x+, z-, z+, y-, y+) of component q at cell (j, k, i): u and w
+// from sample row j + 1 (ghost rows 0 and ny lie outside the box), v on face j (face 0 is
+// never internal; its y- sample is clamped to itself).
+__device__ __forceinline__ void samples7(const GridParams& g, const double* __restrict__ s, int q, int i, int k,
+                                         int j, double* d) {
+  const int nx = g.nx, nz = g.nz, plane = nx * nz;
+  const int im = wrap_m(i, nx), ip = wrap_p(i, nx);
+  const int b = (q == 1 ? j : j + 1) * plane + k * nx;
+  d[0] = s[b + i];
+  d[1] = s[b + im];
+  d[2] = s[b + ip];
+  d[3] = s[b + (wrap_m(k, nz) - k) * nx + i];
+  d[4] = s[b + (wrap_p(k, nz) - k) * nx + i];
+  d[5] = s[(q == 1 && j == 0 ? b : b - plane) + i];
+  d[6] = s[b + plane + i];
 }
 
-// Tags of u, v, w and lambda per component at every cell (j, k, i); with sig_* not null
-// also the wall-velocity coefficient sigma per component.
+// South-wall point of every (k, i) column of u points: the lowest internal u row j1 and
+// its distance d1 to the wall below, located as the immersed boundary locates it (the
+// linear zero crossing of the signed distance towards the external point below, or the
+// south box wall dy/2 below row 0 when nearer); without the correction the staircase
+// wall is at the external point (dy).  j1 = -1, d1 = 0 for a column with no internal u;
+// d1 is stored negative where the wall is the south box wall (at rest).
+__device__ __forceinline__ void south_wall_point(const GridParams& g, const double* __restrict__ su, int ibm_on,
+                                                 int i, int k, int32_t* __restrict__ wj, double* __restrict__ wd) {
+  const size_t plane = (size_t)g.nx * g.nz;
+  const int col = k * g.nx + i;
+  int j1 = -1;
+  double sP = 0.0;
+  // rows in groups of 8 whose loads are issued together (row j is SDF row j + 1)
+  for (int j0 = 0; j0 < g.ny1 && j1 < 0; j0 += 8) {
+    double sj[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) sj[q] = (j0 + q < g.ny1) ? su[(size_t)(j0 + q + 1) * plane + col] : 0.0;
+#pragma unroll
+    for (int q = 7; q >= 0; --q)
+      if (sj[q] > 0.0) {
+        j1 = j0 + q;
+        sP = sj[q];
+      }
+  }
+  double d = 0.0;
+  bool box = false;
+  if (j1 >= 0) {
+    const double sdn = su[(size_t)j1 * plane + col];
+    // length of the stencil arm below row j1 and half the first cell
+    const double harm = g.stretched ? g.ytab[YT_HC * g.ystr + j1] : g.dy;
+    const double half = g.stretched ? 0.5 * g.ytab[YT_DYC * g.ystr] : 0.5 * g.dy;
+    const double cross = (sdn <= 0.0) ? harm * sP / (sP - sdn) : INFINITY;
+    box = (j1 == 0) && (half <= cross);
+    d = ibm_on ? (box ? half : cross) : harm;
+  }
+  wj[col] = j1;
+  wd[col] = box ? -d : d;   // negative: the wall is the south box wall (at rest)
+}
+
+// Tags of u, v, w and lambda per component at every cell (j, k, i), with the
+// wall-velocity coefficient sigma per component (both stored at immersed-boundary points
+// only: the list kernels read these arrays at the points of their lists), and the
+// south-wall point of every column (wj, wd).
 //  sdf_u, sdf_w: (ny+1, nz, nx), row jj = j+1 holds row j; sdf_v: (ny, nz, nx) faces.
-// With zphi not null the cell's phi (zelem bytes) is zeroed too, and with zpi the mean
-// pressure gradient: what is pending of a projection that was applied just before.
+// With `correct`, first the projection left pending by the last step is applied with the
+// cell's old tag and written over its predictor and pressure (f.us, f.vs, f.ws, f.pp):
+// this thread alone reads and writes those and the tag, and phi is only read here.
+template <typename T>
 __global__ __launch_bounds__(256) void k_geom_lambda(GridParams g, const double* __restrict__ su,
                                                     const double* __restrict__ sv, const double* __restrict__ sw,
                                                     int ibm_on, uint8_t* __restrict__ tag,
                                                     double* __restrict__ lam_u, double* __restrict__ lam_v,
                                                     double* __restrict__ lam_w, double* __restrict__ sig_u,
                                                     double* __restrict__ sig_v, double* __restrict__ sig_w,
-                                                    unsigned char* __restrict__ zphi, int zelem,
-                                                    double* __restrict__ zpi) {
+                                                    int correct, Fields<T> f, const double* __restrict__ wallv,
+                                                    double ck_dt, const double* __restrict__ pi,
+                                                    int32_t* __restrict__ wj, double* __restrict__ wd) {
   const int i = blockIdx.x * BX + threadIdx.x;
   const int k = blockIdx.y * BZ + threadIdx.y;
   const int j = blockIdx.z;
   if (i >= g.nx || k >= g.nz) return;
-  const int nx = g.nx, nz = g.nz, ny1 = g.ny1;
-  const int ip = wrap_p(i, nx), im = wrap_m(i, nx), kp = wrap_p(k, nz), km = wrap_m(k, nz);
-  const int plane = nx * nz;
+  const int nx = g.nx, nz = g.nz, plane = nx * nz;
   const int c = (j * nz + k) * nx + i;
-  if (zphi) {
-    if (zelem == 8) reinterpret_cast<double*>(zphi)[c] = 0.0;
-    else reinterpret_cast<float*>(zphi)[c] = 0.0f;
+  // every sample loaded up front
+  double s7[3][7];
+  const double* src[3] = {su, sv, sw};
+#pragma unroll
+  for (int q = 0; q < 3; ++q) samples7(g, src[q], q, i, k, j, s7[q]);
+  if (correct) {
+    const int im = wrap_m(i, nx), km = wrap_m(k, nz);
+    const Corrected<T> r = corrected_point<T>(g, f, wallv, tag[c], j, c, c - i + im, j > 0 ? c - plane : c,
+                                              c + (km - k) * nx, ck_dt, pi[0]);
+    f.us[c] = r.u;
+    f.vs[c] = r.v;
+    f.ws[c] = r.w;
+    f.pp[c] = r.p;
   }
-  if (zpi && c == 0) zpi[0] = 0.0;
-  const double nu = g.nu, dx = g.dx, dy = g.dy, dz = g.dz;
-  const bool sy = g.stretched != 0;
-  const double* yt = g.ytab;
-  const int ys = g.ystr;
-  // wall-normal arms: uniform spacing dy, or the row's own spacing and coefficient
-  auto yarm = [&](double h, double d2, double sP, double sQ, bool ext, double box) {
-    return sy ? arm_w(nu, h, d2, sP, sQ, ext, box) : arm(nu, h, sP, sQ, ext, box);
-  };
-  auto ysrc = [&](double h, double d2, double sP, double sQ, bool ext, double box) {
-    return sy ? arm_src_w(nu, h, d2, sP, sQ, ext, box) : arm_src(nu, h, sP, sQ, ext, box);
-  };
+  const double nu = g.nu;
+  const double dx2 = 1.0 / (g.dx * g.dx), dz2 = 1.0 / (g.dz * g.dz);
   uint8_t t = 0;
-  // u and w: sample row jj = j + 1; ghost rows jj = 0 and jj = ny are outside the box.
-  for (int comp = 0; comp < 3; comp += 2) {
-    const double* s = comp == 0 ? su : sw;
-    const int o = (j + 1) * plane + k * nx;
-    const double sP = s[o + i];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const double* d = s7[q];
+    const bool in = (q == 1) ? (j >= 1 && d[0] > 0.0) : (d[0] > 0.0);
     double lam = 0.0, sg = 0.0;
-    const bool in = sP > 0.0;
     if (in) {
-      const double sxm = s[o + im], sxp = s[o + ip];
-      const double szm = s[o + (km - k) * nx + i], szp = s[o + (kp - k) * nx + i];
-      const double sdn = s[o - plane + i], sup = s[o + plane + i];
-      // the south box face is a wall; so is the north one unless it is free-slip
-      const bool gdn = (j == 0), gup = (j == ny1 - 1) && !g.top_fs;
-      double hdn = dy, hup = dy, cdn = 0.0, cup = 0.0, bdn = 0.5 * dy, bup = 0.5 * dy;
-      if (sy) {
-        hdn = yt[YT_HC * ys + j];
-        hup = yt[YT_HC * ys + j + 1];
-        cdn = yt[YT_DCM * ys + j];
-        cup = yt[YT_DCP * ys + j];
-        bdn = 0.5 * yt[YT_DYC * ys];
-        bup = 0.5 * yt[YT_DYC * ys + ny1 - 1];
-      }
-      lam += arm(nu, dx, sP, sxm, sxm <= 0.0, INFINITY);
-      lam += arm(nu, dx, sP, sxp, sxp <= 0.0, INFINITY);
-      lam += arm(nu, dz, sP, szm, szm <= 0.0, INFINITY);
-      lam += arm(nu, dz, sP, szp, szp <= 0.0, INFINITY);
-      lam += yarm(hdn, cdn, sP, sdn, gdn || sdn <= 0.0, gdn ? bdn : INFINITY);
-      lam += yarm(hup, cup, sP, sup, gup || sup <= 0.0, gup ? bup : INFINITY);
-      sg += arm_src(nu, dx, sP, sxm, sxm <= 0.0, INFINITY);
-      sg += arm_src(nu, dx, sP, sxp, sxp <= 0.0, INFINITY);
-      sg += arm_src(nu, dz, sP, szm, szm <= 0.0, INFINITY);
-      sg += arm_src(nu, dz, sP, szp, szp <= 0.0, INFINITY);
-      sg += ysrc(hdn, cdn, sP, sdn, gdn || sdn <= 0.0, gdn ? bdn : INFINITY);
-      sg += ysrc(hup, cup, sP, sup, gup || sup <= 0.0, gup ? bup : INFINITY);
+      const YArms ya = y_arms(g, q, j);
+      arm_pair(nu, g.dx, dx2, d[0], d[1], d[1] <= 0.0, INFINITY, lam, sg);
+      arm_pair(nu, g.dx, dx2, d[0], d[2], d[2] <= 0.0, INFINITY, lam, sg);
+      arm_pair(nu, g.dz, dz2, d[0], d[3], d[3] <= 0.0, INFINITY, lam, sg);
+      arm_pair(nu, g.dz, dz2, d[0], d[4], d[4] <= 0.0, INFINITY, lam, sg);
+      arm_pair(nu, ya.hdn, ya.cdn, d[0], d[5], ya.gdn || d[5] <= 0.0, ya.bdn, lam, sg);
+      arm_pair(nu, ya.hup, ya.cup, d[0], d[6], ya.gup || d[6] <= 0.0, ya.bup, lam, sg);
       if (!ibm_on) lam = sg = 0.0;
-      t |= (comp == 0) ? TAG_U : TAG_W;
-      if (lam > 0.0) t |= (comp == 0) ? TAG_UI : TAG_WI;
-    }
-    // (stored at immersed-boundary points only: the coefficient kernel reads these arrays
-    // at the points of its lists, and skipping the rest saves most of this kernel's writes)
-    if (lam > 0.0) {
-      (comp == 0 ? lam_u : lam_w)[c] = lam;
-      (comp == 0 ? sig_u : sig_w)[c] = sg;
-    }
-  }
-  // v on face j; faces 0 and ny-1 are the box walls.
-  {
-    const int o = j * plane + k * nx;
-    const double sP = sv[o + i];
-    double lam = 0.0, sg = 0.0;
-    if (j >= 1 && sP > 0.0) {
-      const double sxm = sv[o + im], sxp = sv[o + ip];
-      const double szm = sv[o + (km - k) * nx + i], szp = sv[o + (kp - k) * nx + i];
-      const double sdn = sv[o - plane + i], sup = sv[o + plane + i];
-      const bool wdn = (j - 1 == 0), wup = (j + 1 == ny1);
-      // face j lies between cells j-1 and j
-      double hdn = dy, hup = dy, cdn = 0.0, cup = 0.0;
-      if (sy) {
-        hdn = yt[YT_DYC * ys + j - 1];
-        hup = yt[YT_DYC * ys + j];
-        cdn = yt[YT_DFM * ys + j];
-        cup = yt[YT_DFP * ys + j];
-      }
-      lam += arm(nu, dx, sP, sxm, sxm <= 0.0, INFINITY);
-      lam += arm(nu, dx, sP, sxp, sxp <= 0.0, INFINITY);
-      lam += arm(nu, dz, sP, szm, szm <= 0.0, INFINITY);
-      lam += arm(nu, dz, sP, szp, szp <= 0.0, INFINITY);
-      lam += yarm(hdn, cdn, sP, sdn, wdn || sdn <= 0.0, wdn ? hdn : INFINITY);
-      lam += yarm(hup, cup, sP, sup, wup || sup <= 0.0, wup ? hup : INFINITY);
-      sg += arm_src(nu, dx, sP, sxm, sxm <= 0.0, INFINITY);
-      sg += arm_src(nu, dx, sP, sxp, sxp <= 0.0, INFINITY);
-      sg += arm_src(nu, dz, sP, szm, szm <= 0.0, INFINITY);
-      sg += arm_src(nu, dz, sP, szp, szp <= 0.0, INFINITY);
-      sg += ysrc(hdn, cdn, sP, sdn, wdn || sdn <= 0.0, wdn ? hdn : INFINITY);
-      sg += ysrc(hup, cup, sP, sup, wup || sup <= 0.0, wup ? hup : INFINITY);
-      if (!ibm_on) lam = sg = 0.0;
-      t |= TAG_V;
-      if (lam > 0.0) t |= TAG_VI;
+      t |= (q == 0) ? TAG_U : (q == 1 ? TAG_V : TAG_W);
+      if (lam > 0.0) t |= (q == 0) ? TAG_UI : (q == 1 ? TAG_VI : TAG_WI);
     }
     if (lam > 0.0) {
-      lam_v[c] = lam;
-      sig_v[c] = sg;
+      (q == 0 ? lam_u : (q == 1 ? lam_v : lam_w))[c] = lam;
+      (q == 0 ? sig_u : (q == 1 ? sig_v : sig_w))[c] = sg;
     }
   }
   tag[c] = t;
+  // the threads of row 0 also locate their column's south-wall point (the first blocks
+  // dispatched: their extra loads overlap with the rest of the grid)
+  if (j == 0) south_wall_point(g, su, ibm_on, i, k, wj, wd);
 }
 
 // Pressure cell internal iff one of its six faces is an internal velocity point; then, per
@@ -184,17 +205,25 @@ __global__ __launch_bounds__(256) void k_geom_lambda(GridParams g, const double*
 // k_chunk_counts3 writes them (wave w of block b is chunk 4b + w).
 __global__ __launch_bounds__(256) void k_geom_ptag_counts(GridParams g, uint8_t* __restrict__ tag, uint64_t masks,
                                                          int nm, int32_t* __restrict__ counts, int nblk,
-                                                         int32_t* __restrict__ clear, int32_t* __restrict__ chunks) {
+                                                         int32_t* __restrict__ clear, int32_t* __restrict__ chunks,
+                                                         unsigned char* __restrict__ zphi, int zelem,
+                                                         double* __restrict__ zpi) {
   __shared__ int32_t wc[8][4];
   const int64_t e = blockIdx.x * 256ll + threadIdx.x;
+  if (zphi && e < g.ncell) {
+    if (zelem == 8) reinterpret_cast<double*>(zphi)[e] = 0.0;
+    else reinterpret_cast<float*>(zphi)[e] = 0.0f;
+  }
+  if (zpi && e == 0) zpi[0] = 0.0;
   uint8_t t = 0;
   if (e < g.ncell) {
-    const int nx = g.nx, nz = g.nz;
-    const int i = (int)(e % nx), k = (int)((e / nx) % nz), j = (int)(e / ((int64_t)nx * nz));
+    // (32-bit index arithmetic: the grid holds fewer than 2^31 cells)
+    const unsigned nx = g.nx, nz = g.nz, ue = (unsigned)e;
+    const unsigned row = ue / nx, i = ue - row * nx, j = row / nz, k = row - j * nz;
     t = tag[e];
-    const uint8_t te = tag[e - i + wrap_p(i, nx)] & TAG_U;
-    const uint8_t tn = (j + 1 < g.ny1) ? (tag[e + (int64_t)nx * nz] & TAG_V) : 0;
-    const uint8_t tt = tag[e + (int64_t)(wrap_p(k, nz) - k) * nx] & TAG_W;
+    const uint8_t te = tag[ue - i + (i + 1 == nx ? 0u : i + 1)] & TAG_U;
+    const uint8_t tn = (j + 1 < (unsigned)g.ny1) ? (tag[ue + nx * nz] & TAG_V) : 0;
+    const uint8_t tt = tag[k + 1 == nz ? ue - k * nx : ue + nx] & TAG_W;
     if ((t & (TAG_U | TAG_V | TAG_W)) || te || tn || tt) {
       t |= TAG_P;
       tag[e] = t;
@@ -223,101 +252,101 @@ __global__ __launch_bounds__(256) void k_geom_ptag_counts(GridParams g, uint8_t*
   }
 }
 
-// South-wall point of every (k, i) column of u points: the lowest internal u row j1 and
-// its distance d1 to the wall below, located as the immersed boundary locates it (the
-// linear zero crossing of the signed distance towards the external point below, or the
-// south box wall dy/2 below row 0 when nearer); without the correction the staircase
-// wall is at the external point (dy).  j1 = -1, d1 = 0 for a column with no internal u;
-// d1 is stored negative where the wall is the south box wall (at rest).
-__global__ __launch_bounds__(256) void k_geom_south_wall(GridParams g, const double* __restrict__ su, int ibm_on,
-                                                        int32_t* __restrict__ wj, double* __restrict__ wd) {
-  const int i = blockIdx.x * BX + threadIdx.x;
-  const int k = blockIdx.y * BZ + threadIdx.y;
-  if (i >= g.nx || k >= g.nz) return;
-  const size_t plane = (size_t)g.nx * g.nz;
-  const int col = k * g.nx + i;
-  int j1 = -1;
-  double sP = 0.0;
-  for (int j = 0; j < g.ny1; ++j) {
-    const double sj = su[(size_t)(j + 1) * plane + col];   // row j is SDF row j + 1
-    if (sj > 0.0) {
-      j1 = j;
-      sP = sj;
-      break;
-    }
+// Tiled exclusive scans of several count arrays (ScanSet): block b scans tile
+// b - tile_off[m] of array m.  In a tile thread t holds the 4 counts 4t .. 4t+3 (one
+// 16-byte load when the array is 16-byte aligned), so that a wave's loads and stores are
+// one contiguous kilobyte.
+__device__ __forceinline__ int scan_array_of(const ScanSet& s, int b) {
+  int m = 0;
+  while (m + 1 < s.narr && b >= s.tile_off[m + 1]) ++m;
+  return m;
+}
+__device__ __forceinline__ int4 scan_load4(const int32_t* __restrict__ counts, int n, int e0) {
+  int4 v;
+  if ((reinterpret_cast<uintptr_t>(counts) & 15) == 0 && e0 + 3 < n) {
+    v = *reinterpret_cast<const int4*>(counts + e0);
+  } else {
+    v.x = e0 < n ? counts[e0] : 0;
+    v.y = e0 + 1 < n ? counts[e0 + 1] : 0;
+    v.z = e0 + 2 < n ? counts[e0 + 2] : 0;
+    v.w = e0 + 3 < n ? counts[e0 + 3] : 0;
   }
-  double d = 0.0;
-  bool box = false;
-  if (j1 >= 0) {
-    const double sdn = su[(size_t)j1 * plane + col];
-    // length of the stencil arm below row j1 and half the first cell
-    const double harm = g.stretched ? g.ytab[YT_HC * g.ystr + j1] : g.dy;
-    const double half = g.stretched ? 0.5 * g.ytab[YT_DYC * g.ystr] : 0.5 * g.dy;
-    const double cross = (sdn <= 0.0) ? harm * sP / (sP - sdn) : INFINITY;
-    box = (j1 == 0) && (half <= cross);
-    d = ibm_on ? (box ? half : cross) : harm;
-  }
-  wj[col] = j1;
-  wd[col] = box ? -d : d;   // negative: the wall is the south box wall (at rest)
+  return v;
+}
+__device__ __forceinline__ int32_t wave_isum(int32_t v) {
+  for (int o = IBM_WAVE / 2; o > 0; o >>= 1) v += __shfl_down(v, o, IBM_WAVE);
+  return v;
 }
 
-// Exclusive prefix sum of nblk counts in place, total[0] = their sum; one block of 1024
-// threads, SCAN_PER * 1024 counts per round: each thread adds SCAN_PER consecutive counts,
-// the waves scan their threads' sums with shuffles and one wave scans the 16 wave sums.
-constexpr int SCAN_PER = 16;
-__device__ __forceinline__ void scan_counts_body(int32_t* __restrict__ counts, int nblk,
-                                                 int32_t* __restrict__ total) {
+// Pass 1: the sum of every tile into s.tsum[b].
+__global__ __launch_bounds__(1024) void k_scan_tile_sums(ScanSet s) {
   __shared__ int32_t wsum[16];
+  const int b = blockIdx.x, m = scan_array_of(s, b), t = b - s.tile_off[m];
   const int tid = threadIdx.x, lane = tid & (IBM_WAVE - 1), wid = tid / IBM_WAVE;
-  int32_t carry = 0;
-  for (int base = 0; base < nblk; base += SCAN_PER * 1024) {
-    const int e0 = base + SCAN_PER * tid;
-    int32_t v[SCAN_PER];
-    int32_t sum = 0;
-#pragma unroll
-    for (int q = 0; q < SCAN_PER; ++q) {
-      v[q] = (e0 + q < nblk) ? counts[e0 + q] : 0;
-      sum += v[q];
-    }
-    int32_t x = sum;   // inclusive scan over the wave
-    for (int o = 1; o < IBM_WAVE; o <<= 1) {
-      const int32_t y = __shfl_up(x, o, IBM_WAVE);
-      if (lane >= o) x += y;
-    }
-    if (lane == IBM_WAVE - 1) wsum[wid] = x;
-    __syncthreads();
-    if (wid == 0) {
-      int32_t w = lane < 16 ? wsum[lane] : 0;
-      for (int o = 1; o < 16; o <<= 1) {
-        const int32_t y = __shfl_up(w, o, IBM_WAVE);
-        if (lane >= o) w += y;
-      }
-      if (lane < 16) wsum[lane] = w;
-    }
-    __syncthreads();
-    int32_t run = carry + (wid > 0 ? wsum[wid - 1] : 0) + (x - sum);
-#pragma unroll
-    for (int q = 0; q < SCAN_PER; ++q) {
-      if (e0 + q < nblk) counts[e0 + q] = run;
-      run += v[q];
-    }
-    carry += wsum[15];
-    __syncthreads();
+  const int4 v = scan_load4(s.counts[m], s.n[m], t * SCAN_TILE + 4 * tid);
+  const int32_t w = wave_isum(v.x + v.y + v.z + v.w);
+  if (lane == 0) wsum[wid] = w;
+  __syncthreads();
+  if (tid == 0) {
+    int32_t tot = 0;
+    for (int q = 0; q < 16; ++q) tot += wsum[q];
+    s.tsum[b] = tot;
   }
-  if (tid == 0) total[0] = carry;
 }
 
-// The same for several arrays at once: block m scans set.counts[m] (set.n[m] counts) and
-// writes its sum to set.total[m].
-__global__ __launch_bounds__(1024) void k_scan_multi(ScanSet set) {
-  const int m = blockIdx.x;
-  scan_counts_body(set.counts[m], set.n[m], set.total[m]);
+// Pass 2: each tile scanned in place from the sum of the tiles before it in its array;
+// the array's last tile writes its total.
+__global__ __launch_bounds__(1024) void k_scan_tiles(ScanSet s) {
+  __shared__ int32_t wsum[16];
+  __shared__ int32_t base_sh;
+  const int b = blockIdx.x, m = scan_array_of(s, b), t = b - s.tile_off[m];
+  const int tid = threadIdx.x, lane = tid & (IBM_WAVE - 1), wid = tid / IBM_WAVE;
+  int32_t* counts = s.counts[m];
+  const int n = s.n[m], e0 = t * SCAN_TILE + 4 * tid;
+  const int4 v = scan_load4(counts, n, e0);
+  if (wid == 0) {   // sum of the preceding tiles of this array
+    int32_t c = 0;
+    for (int q = lane; q < t; q += IBM_WAVE) c += s.tsum[s.tile_off[m] + q];
+    c = wave_isum(c);
+    if (lane == 0) base_sh = c;
+  }
+  const int32_t sum = v.x + v.y + v.z + v.w;
+  int32_t x = sum;   // inclusive scan over the wave
+  for (int o = 1; o < IBM_WAVE; o <<= 1) {
+    const int32_t y = __shfl_up(x, o, IBM_WAVE);
+    if (lane >= o) x += y;
+  }
+  if (lane == IBM_WAVE - 1) wsum[wid] = x;
+  __syncthreads();
+  if (wid == 0) {
+    int32_t w = lane < 16 ? wsum[lane] : 0;
+    for (int o = 1; o < 16; o <<= 1) {
+      const int32_t y = __shfl_up(w, o, IBM_WAVE);
+      if (lane >= o) w += y;
+    }
+    if (lane < 16) wsum[lane] = w;
+  }
+  __syncthreads();
+  int32_t run = base_sh + (wid > 0 ? wsum[wid - 1] : 0) + (x - sum);
+  int4 o;
+  o.x = run;
+  run += v.x;
+  o.y = run;
+  run += v.y;
+  o.z = run;
+  run += v.z;
+  o.w = run;
+  if ((reinterpret_cast<uintptr_t>(counts) & 15) == 0 && e0 + 3 < n) {
+    *reinterpret_cast<int4*>(counts + e0) = o;
+  } else {
+    if (e0 < n) counts[e0] = o.x;
+    if (e0 + 1 < n) counts[e0 + 1] = o.y;
+    if (e0 + 2 < n) counts[e0 + 2] = o.z;
+    if (e0 + 3 < n) counts[e0 + 3] = o.w;
+  }
+  if (tid == 0 && b + 1 == s.tile_off[m + 1]) s.total[m][0] = base_sh + wsum[15];
 }
 
-// The ascending cell indices of the u, v and w immersed-boundary points (tag bits
-// TAG_UI << c) at their scanned block offsets offsets[c * nblk + block], into the
-// component's list, which starts at list_off[c] and holds cap[c] entries; a point whose
-// rank reaches the capacity is not written and sets overflow[0].
 // Per-stage (B, 1/A) of a point with coefficient lam (Eqs. (14)-(16)): x = lam c_k dt.
 __device__ __forceinline__ double2 ibm_stage_coef(double lam, int k, double dt, int b_mode) {
   const double x = lam * rk_c(k) * dt;
@@ -335,16 +364,18 @@ __device__ __forceinline__ double2 ibm_stage_coef(double lam, int k, double dt, 
   return make_double2(B, 1.0 / A);
 }
 
-// ... and with each listed point its lambda, sigma (from the dense per-component arrays,
-// component c at c * n) and per-stage (B, 1/A): coef[k * cap_total + entry].
+// The ascending cell indices of the u, v and w immersed-boundary points (tag bits
+// TAG_UI << c) at their scanned block offsets offsets[c * nblk + block], into the
+// component's list, which starts at list_off[c] and holds cap[c] entries, with each
+// listed point's lambda and sigma (from the dense per-component arrays, component c at
+// c * n); a point whose rank reaches the capacity is not written and sets overflow[0].
 __global__ __launch_bounds__(256) void k_compact3(const uint8_t* __restrict__ tag, int64_t n,
                                                  const int32_t* __restrict__ offsets, int nblk,
                                                  int32_t* __restrict__ idx, int off_v, int off_w, int cap_u,
                                                  int cap_v, int cap_w, int32_t* __restrict__ overflow,
                                                  const double* __restrict__ lam_dense,
-                                                 const double* __restrict__ sig_dense, double dt, int b_mode,
-                                                 double* __restrict__ lam_out, double* __restrict__ sig_out,
-                                                 double2* __restrict__ coef) {
+                                                 const double* __restrict__ sig_dense,
+                                                 double* __restrict__ lam_out, double* __restrict__ sig_out) {
   __shared__ int32_t wc[3][4];
   const int64_t e = blockIdx.x * 256ll + threadIdx.x;
   const uint8_t t = (e < n) ? tag[e] : uint8_t(0);
@@ -366,11 +397,8 @@ __global__ __launch_bounds__(256) void k_compact3(const uint8_t* __restrict__ ta
     if (r < cap) {
       const int q = off + r;
       idx[q] = (int32_t)e;
-      const double lam = lam_dense[(size_t)c * n + e];
-      lam_out[q] = lam;
+      lam_out[q] = lam_dense[(size_t)c * n + e];
       sig_out[q] = sig_dense[(size_t)c * n + e];
-      const int cap_total = cap_u + cap_v + cap_w;
-      for (int k = 0; k < 3; ++k) coef[(size_t)k * cap_total + q] = ibm_stage_coef(lam, k, dt, b_mode);
     } else {
       overflow[0] = 1;
     }
@@ -430,67 +458,146 @@ __global__ __launch_bounds__(256) void k_s_cells(GridParams g, const uint8_t* __
     part[blockIdx.x * 4 + 3] = 0.0;
   }
 }
-// Per block of IBM u points and stage k: sum of 1/A_k into part, and sum of sigma/A_k (the
-// flow rate a moving wall adds, per unit c_k dt U_b) into part_sd.
-__global__ __launch_bounds__(256) void k_s_list(GridParams g, IbmLists L, double* __restrict__ part,
-                                               double* __restrict__ part_sd) {
-  __shared__ double red[4];
-  const int e = blockIdx.x * 256 + threadIdx.x;
-  // the u list holds cnt[0] points (at most its capacity n_u)
-  const bool in = e < min(L.cnt[0], L.n_u);
-  const double sg = in ? L.sig[e] : 0.0;
-  // a stretched grid weights each point by the cell height of its row
-  const double wy = (g.stretched && in) ? g.ytab[YT_DYC * g.ystr + L.idx[e] / (g.nx * g.nz)] : 1.0;
-  for (int k = 0; k < 3; ++k) {
-    double v = in ? L.coef[(size_t)k * L.n_total + e].y : 0.0;
-    if (g.stretched) v *= wy;
-    const double tot = block_reduce<false>(v, red);
-    __syncthreads();
-    const double tsd = block_reduce<false>(sg * v, red);
-    if (threadIdx.x == 0) {
-      part[blockIdx.x * 4 + 1 + k] = tot;
-      part_sd[blockIdx.x * 4 + k] = tsd;
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    part[blockIdx.x * 4] = 0.0;
-    part_sd[blockIdx.x * 4 + 3] = 0.0;
-  }
-}
 // S3[k] = S_k from the npart partials of part; with sd_out, sd_out[k] = the sum of the nsd
 // partials of stage k in part_sd (fixed orders; zero for no partials)
 // With cnt7 (uniform grids) the internal non-IBM u points are its internal u count minus
-// its immersed-boundary u count (every immersed-boundary u point is internal).
+// its immersed-boundary u count (every immersed-boundary u point is internal).  The seven
+// sums are accumulated in one pass (all loads issued together), reduced over each wave and
+// then over the block's waves (at most 16) in a fixed order.
+__device__ __forceinline__ void s_final_block(const double* __restrict__ part, int npart, double scale,
+                                              double* __restrict__ S3, const double* __restrict__ part_sd,
+                                              int nsd, double* __restrict__ sd_out,
+                                              const int32_t* __restrict__ cnt7) {
+  __shared__ double wred[16][8];
+  const int lane = threadIdx.x % IBM_WAVE, wid = threadIdx.x / IBM_WAVE, nw = blockDim.x / IBM_WAVE;
+  double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int e = threadIdx.x; e < npart; e += blockDim.x) {
+    const double2 a = reinterpret_cast<const double2*>(part)[2 * e];
+    const double2 b = reinterpret_cast<const double2*>(part)[2 * e + 1];
+    acc[0] += a.x;
+    acc[1] += a.y;
+    acc[2] += b.x;
+    acc[3] += b.y;
+  }
+  if (sd_out)
+    for (int e = threadIdx.x; e < nsd; e += blockDim.x) {
+      const double2 a = reinterpret_cast<const double2*>(part_sd)[2 * e];
+      const double b = part_sd[4 * e + 2];
+      acc[4] += a.x;
+      acc[5] += a.y;
+      acc[6] += b;
+    }
+#pragma unroll
+  for (int q = 0; q < 7; ++q) acc[q] = wave_sum(acc[q]);
+  if (lane == 0)
+#pragma unroll
+    for (int q = 0; q < 7; ++q) wred[wid][q] = acc[q];
+  __syncthreads();
+  if (threadIdx.x < 7) {
+    const int q = threadIdx.x;
+    double t = wred[0][q];
+    for (int w = 1; w < nw; ++w) t += wred[w][q];
+    wred[0][q] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double c0 = wred[0][0];
+    if (cnt7) c0 += (double)(cnt7[0] - cnt7[4]);
+    for (int k = 0; k < 3; ++k) {
+      const double ckdt = rk_c(k) * scale;   // scale carries dt dy dz / nx
+      S3[k] = (c0 + wred[0][1 + k]) * ckdt;
+      if (sd_out) sd_out[k] = wred[0][4 + k];
+    }
+  }
+}
 __global__ __launch_bounds__(1024) void k_s_final(const double* __restrict__ part, int npart, double scale,
                                                  double* __restrict__ S3, const double* __restrict__ part_sd,
                                                  int nsd, double* __restrict__ sd_out,
                                                  const int32_t* __restrict__ cnt7) {
-  __shared__ double red[16];
-  double acc[4];
-  for (int v = 0; v < 4; ++v) {
-    double s = 0.0;
-    for (int e = threadIdx.x; e < npart; e += blockDim.x) s += part[e * 4 + v];
-    acc[v] = block_reduce<false>(s, red);
-    __syncthreads();
-  }
-  if (cnt7) acc[0] += (double)(cnt7[0] - cnt7[4]);
-  if (threadIdx.x == 0) {
-    for (int k = 0; k < 3; ++k) {
-      const double ckdt = rk_c(k) * scale;   // scale carries dt dy dz / nx
-      S3[k] = (acc[0] + acc[1 + k]) * ckdt;
-    }
-  }
-  if (!sd_out) return;
-  for (int k = 0; k < 3; ++k) {
-    double s = 0.0;
-    for (int e = threadIdx.x; e < nsd; e += blockDim.x) s += part_sd[e * 4 + k];
-    const double r = block_reduce<false>(s, red);
-    if (threadIdx.x == 0) sd_out[k] = r;
-    __syncthreads();
-  }
+  s_final_block(part, npart, scale, S3, part_sd, nsd, sd_out, cnt7);
 }
 
+// Per entry of the three immersed-boundary lists (laid end to end: v at n_u, w at
+// n_u + n_v; entries beyond each list's count are skipped): its per-stage (B, 1/A) from
+// its lambda, into coef[k * n_total + entry].  The first nb2 blocks, which hold the whole
+// u list, also write the S_k partials of their u points: per stage the sum of 1/A_k
+// (weighted by the row's cell height on a stretched grid) into part[block * 4 + 1 + k], and
+// of sigma/A_k (the flow rate a moving wall adds, per unit c_k dt U_b) into
+// part_sd[block * 4 + k].
+// With fin.done (uniform grids), the last of those blocks to finish also forms S_k from
+// every partial (s_final_block): each block writes its partials, makes them visible to
+// the device and counts itself in *fin.done; the block that counts last reads them all
+// and sets the counter back to zero for the next launch.
+struct SFinal {
+  unsigned* done;
+  double scale;
+  double* S3;
+  double* sd_out;
+  const int32_t* cnt7;
+};
+__global__ __launch_bounds__(256) void k_list_coef(GridParams g, IbmLists L, const double* __restrict__ lam,
+                                                  double2* __restrict__ coef, double dt, int b_mode, int nb2,
+                                                  double* __restrict__ part, double* __restrict__ part_sd,
+                                                  SFinal fin) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  const int cmp = e < L.n_u ? 0 : (e < L.n_u + L.n_v ? 1 : 2);
+  const int off = cmp == 0 ? 0 : (cmp == 1 ? L.n_u : L.n_u + L.n_v);
+  const int cap = cmp == 0 ? L.n_u : (cmp == 1 ? L.n_v : L.n_w);
+  const bool valid = e < L.n_total && e - off < min(L.cnt[cmp], cap);
+  double2 cf[3];
+  if (valid) {
+    const double l = lam[e];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      cf[k] = ibm_stage_coef(l, k, dt, b_mode);
+      coef[(size_t)k * L.n_total + e] = cf[k];
+    }
+  }
+  if ((int)blockIdx.x >= nb2) return;   // (the whole block)
+  const bool in = valid && cmp == 0;
+  const double sg = in ? L.sig[e] : 0.0;
+  // a stretched grid weights each point by the cell height of its row
+  const double wy = (g.stretched && in) ? g.ytab[YT_DYC * g.ystr + L.idx[e] / (g.nx * g.nz)] : 1.0;
+  double v[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) v[k] = in ? cf[k].y * wy : 0.0;
+  // the six sums reduced over each wave, then over the block's four waves (fixed order)
+  __shared__ double wred[4][6];
+  const int lane = threadIdx.x % IBM_WAVE, wid = threadIdx.x / IBM_WAVE;
+  double r[6];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    r[k] = wave_sum(v[k]);
+    r[3 + k] = wave_sum(sg * v[k]);
+  }
+  if (lane == 0)
+#pragma unroll
+    for (int q = 0; q < 6; ++q) wred[wid][q] = r[q];
+  __syncthreads();
+  __shared__ int last;
+  if (threadIdx.x == 0) {
+    double t[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) t[q] = ((wred[0][q] + wred[1][q]) + wred[2][q]) + wred[3][q];
+    part[blockIdx.x * 4] = 0.0;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      part[blockIdx.x * 4 + 1 + q] = t[q];
+      part_sd[blockIdx.x * 4 + q] = t[3 + q];
+    }
+    part_sd[blockIdx.x * 4 + 3] = 0.0;
+    last = 0;
+    if (fin.done) {
+      __threadfence();   // the partials visible device-wide before the count
+      last = atomicAdd(fin.done, 1u) == (unsigned)(nb2 - 1);
+    }
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();       // every block's partials visible here
+  s_final_block(part, nb2, fin.scale, fin.S3, part_sd, nb2, fin.sd_out, fin.cnt7);
+  if (threadIdx.x == 0) fin.done[0] = 0u;
+}
 // ---------------------------------------------------------------------------------------
 // Diagnostics
 // ---------------------------------------------------------------------------------------
@@ -702,29 +809,36 @@ static inline dim3 cell_grid(const GridParams& g) {
   return dim3((g.nx + BX - 1) / BX, (g.nz + BZ - 1) / BZ, g.ny1);
 }
 
+template <typename T>
 hipError_t launch_geom_lambda(const GridParams& g, const double* su, const double* sv, const double* sw,
                               int ibm_on, uint8_t* tag, double* lam_u, double* lam_v, double* lam_w,
-                              double* sig_u, double* sig_v, double* sig_w, void* zphi, int zelem, double* zpi,
+                              double* sig_u, double* sig_v, double* sig_w, bool correct, const Fields<T>& f,
+                              const double* wallv, double ck_dt, const double* pi, int32_t* wj, double* wd,
                               hipStream_t st) {
-  hipLaunchKernelGGL(k_geom_lambda, cell_grid(g), dim3(BX, BZ), 0, st, g, su, sv, sw, ibm_on, tag, lam_u, lam_v,
-                     lam_w, sig_u, sig_v, sig_w, (unsigned char*)zphi, zelem, zpi);
+  if (correct && (!f.us || !f.vs || !f.ws || !f.pp || !f.phi || !wallv || !pi)) return hipErrorInvalidValue;
+  if (!wj || !wd) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_geom_lambda<T>, cell_grid(g), dim3(BX, BZ), 0, st, g, su, sv, sw, ibm_on, tag, lam_u, lam_v,
+                     lam_w, sig_u, sig_v, sig_w, correct ? 1 : 0, f, wallv, ck_dt, pi, wj, wd);
   return hipGetLastError();
 }
+template hipError_t launch_geom_lambda<double>(const GridParams&, const double*, const double*, const double*, int,
+                                               uint8_t*, double*, double*, double*, double*, double*, double*, bool,
+                                               const Fields<double>&, const double*, double, const double*, int32_t*,
+                                               double*, hipStream_t);
+template hipError_t launch_geom_lambda<float>(const GridParams&, const double*, const double*, const double*, int,
+                                              uint8_t*, double*, double*, double*, double*, double*, double*, bool,
+                                              const Fields<float>&, const double*, double, const double*, int32_t*,
+                                              double*, hipStream_t);
 
 hipError_t launch_geom_ptag_counts(const GridParams& g, uint8_t* tag, uint64_t masks, int nm, int32_t* counts,
-                                   int nblk, int32_t* clear, int32_t* chunks, hipStream_t st) {
+                                   int nblk, int32_t* clear, int32_t* chunks, void* zphi, int zelem, double* zpi,
+                                   hipStream_t st) {
   if ((int64_t)nblk * 256 < g.ncell || nm > 8 || (chunks && g.nx % IBM_WAVE != 0)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_geom_ptag_counts, dim3(nblk), dim3(256), 0, st, g, tag, masks, nm, counts, nblk, clear,
-                     chunks);
+                     chunks, (unsigned char*)zphi, zelem, zpi);
   return hipGetLastError();
 }
 
-hipError_t launch_geom_south_wall(const GridParams& g, const double* su, int ibm_on, int32_t* wj, double* wd,
-                                  hipStream_t st) {
-  const dim3 grid((g.nx + BX - 1) / BX, (g.nz + BZ - 1) / BZ, 1);
-  hipLaunchKernelGGL(k_geom_south_wall, grid, dim3(BX, BZ), 0, st, g, su, ibm_on, wj, wd);
-  return hipGetLastError();
-}
 
 template <typename T>
 hipError_t launch_wall_shear(const GridParams& g, const T* u, const int32_t* wj, const double* wd,
@@ -739,17 +853,25 @@ template hipError_t launch_wall_shear<double>(const GridParams&, const double*, 
 template hipError_t launch_wall_shear<float>(const GridParams&, const float*, const int32_t*, const double*,
                                              const double*, double*, double*, hipStream_t);
 
-hipError_t launch_scan_multi(const ScanSet& set, hipStream_t st) {
-  if (set.narr < 1 || set.narr > SCAN_MAX) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_scan_multi, dim3(set.narr), dim3(1024), 0, st, set);
+hipError_t launch_scan_multi(ScanSet set, hipStream_t st) {
+  if (set.narr < 1 || set.narr > SCAN_MAX || !set.tsum) return hipErrorInvalidValue;
+  set.tile_off[0] = 0;
+  for (int m = 0; m < set.narr; ++m) {
+    if (set.n[m] < 0) return hipErrorInvalidValue;
+    set.tile_off[m + 1] = set.tile_off[m] + scan_tiles(set.n[m]);
+  }
+  const int ntile = set.tile_off[set.narr];
+  if (ntile > set.tsum_cap) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_scan_tile_sums, dim3(ntile), dim3(1024), 0, st, set);
+  hipLaunchKernelGGL(k_scan_tiles, dim3(ntile), dim3(1024), 0, st, set);
   return hipGetLastError();
 }
 
 hipError_t launch_compact3(const uint8_t* tag, int64_t n, const int32_t* offsets, int nblk, int32_t* idx,
                            const int cap[3], int32_t* overflow, const double* lam_dense, const double* sig_dense,
-                           double dt, int b_mode, double* lam_out, double* sig_out, double2* coef, hipStream_t st) {
+                           double* lam_out, double* sig_out, hipStream_t st) {
   hipLaunchKernelGGL(k_compact3, dim3(nblk), dim3(256), 0, st, tag, n, offsets, nblk, idx, cap[0], cap[0] + cap[1],
-                     cap[0], cap[1], cap[2], overflow, lam_dense, sig_dense, dt, b_mode, lam_out, sig_out, coef);
+                     cap[0], cap[1], cap[2], overflow, lam_dense, sig_dense, lam_out, sig_out);
   return hipGetLastError();
 }
 
@@ -768,26 +890,27 @@ hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_s_k(const GridParams& g, const uint8_t* tag, const IbmLists& L, double* part, int* npart,
-                      hipStream_t st) {
+hipError_t launch_s_k(const GridParams& g, const uint8_t* tag, const IbmLists& L, const double* lam, double2* coef,
+                      double dt, int b_mode, double* part, double scale, double* S3, const int32_t* cnt7,
+                      double* sd_out, unsigned* done, hipStream_t st) {
   // (on a uniform grid the internal non-IBM u points are counted by the tag counts, which
-  // k_s_final reads; a stretched grid weights them by row and sums them here)
+  // the final sums read; a stretched grid weights them by row and sums them here)
   const int nb1 = g.stretched ? (int)((g.ncell + 255) / 256) : 0;
   const int nb2 = (L.n_u + 255) / 256;
+  const int nbl = (L.n_total + 255) / 256;
   double* part_sd = part + (size_t)(nb1 + nb2) * 4;
+  // the final sums in the list kernel's last block on a uniform grid with listed u points;
+  // otherwise (the stretched grid's many cell partials, no u list) by a block of their own
+  const bool fused = nb1 == 0 && nb2 > 0 && done;
+  SFinal fin{};
+  if (fused) fin = SFinal{done, scale, S3, sd_out, cnt7};
   if (nb1 > 0) hipLaunchKernelGGL(k_s_cells, dim3(nb1), dim3(256), 0, st, g, tag, part);
-  if (nb2 > 0) hipLaunchKernelGGL(k_s_list, dim3(nb2), dim3(256), 0, st, g, L, part + (size_t)nb1 * 4, part_sd);
-  *npart = nb1 + nb2;
-  return hipGetLastError();
-}
-
-hipError_t launch_s_k_final(const double* part, int npart, double scale, double* S3, const GridParams& g,
-                            const IbmLists& L, const int32_t* cnt7, double* sd_out, hipStream_t st) {
-  const int nb1 = g.stretched ? (int)((g.ncell + 255) / 256) : 0;
-  const int nb2 = (L.n_u + 255) / 256;
-  const double* part_sd = part + (size_t)(nb1 + nb2) * 4;
-  hipLaunchKernelGGL(k_s_final, dim3(1), dim3(1024), 0, st, part, npart, scale, S3, part_sd, nb2, sd_out,
-                     g.stretched ? nullptr : cnt7);
+  if (nbl > 0)
+    hipLaunchKernelGGL(k_list_coef, dim3(nbl), dim3(256), 0, st, g, L, lam, coef, dt, b_mode, nb2,
+                       part + (size_t)nb1 * 4, part_sd, fin);
+  if (!fused)
+    hipLaunchKernelGGL(k_s_final, dim3(1), dim3(1024), 0, st, part, nb1 + nb2, scale, S3, part_sd, nb2, sd_out,
+                       g.stretched ? nullptr : cnt7);
   return hipGetLastError();
 }
 

@@ -791,16 +791,6 @@ __global__ __launch_bounds__(512) void k_fftz_b(const FftzArgs<T>* __restrict__ 
 // in LDS; each thread then recovers its interior rows.  The spectrum is read once
 // and written once.  W = 256/P modes per block, lane = p * W + w.
 // ---------------------------------------------------------------------------------------
-// 1/x (x normal, not tiny): the hardware reciprocal estimate refined by two Newton steps,
-// each of which squares the relative error, to full FP64 accuracy.
-__device__ __forceinline__ double recip(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = __builtin_fma(-x, r, 1.0);
-  r = __builtin_fma(r, e, r);
-  e = __builtin_fma(-x, r, 1.0);
-  return __builtin_fma(r, e, r);
-}
-
 // Row stride (in doubles) of the reduced-system arrays: W padded so that the four
 // segment groups of a wavefront fall into alternate halves of the LDS banks.
 __host__ __device__ inline int tri_rs(int W) { return W + ((8 - W % 16) + 16) % 16; }
@@ -1122,11 +1112,10 @@ __global__ __launch_bounds__(256) void k_ifftx_b(const IfftxArgs<T>* __restrict_
 }
 
 // ---------------------------------------------------------------------------------------
-// correct: the state after a projection, written to f.u, f.v, f.w, f.p:
-// u = u* - c_k dt G phi on internal faces (the pending -Pi c_k dt included), zero on
-// external faces (Sec. 3.3); p = p' + phi on internal pressure cells only (p' = f.pp).
-// The step itself folds this into the next momentum; this kernel materialises the state
-// on request.  mode bit 0: the state goes to f.u, f.v, f.w, f.p; bit 1: it is written
+// correct: the state after a projection (corrected_point: u = u* - c_k dt G phi on
+// internal faces, the pending -Pi c_k dt included, the walls' velocity on external faces;
+// p = p' + phi on internal pressure cells, p' = f.pp).  The step itself folds this into
+// the next momentum; this kernel materialises the state on request.  mode bit 0: the state goes to f.u, f.v, f.w, f.p; bit 1: it is written
 // back over the predictor and the pressure it was computed from (f.us, f.pp: each point
 // reads only its own), which makes it the start of the next substep once the caller
 // zeroes phi and Pi.
@@ -1142,30 +1131,19 @@ __global__ __launch_bounds__(256) void k_correct(GridParams g, Fields<T> f, IbmL
   const int im = wrap_m(i, nx), km = wrap_m(k, nz);
   const int c = (j * nz + k) * nx + i;
   const int ds = (j > 0) ? nx * nz : 0;      // v on face 0 is never internal
-  const uint8_t tg = f.tag[c];
-  const T ph = f.phi[c], phw = f.phi[c - i + im], phs = f.phi[c - ds], phb = f.phi[c + (km - k) * nx];
-  const T usv = f.us[c], vsv = f.vs[c], wsv = f.ws[c], pv = f.pp[c];
-  const T ckdt = T(ck_dt);
-  const T pick = ((tg & (TAG_U | TAG_UI)) == TAG_U) ? T(pi[0] * ck_dt) : T(0);
-  const T un = usv - pick - ckdt * ((ph - phw) * T(g.idx));
-  const T vn = vsv - ckdt * ((ph - phs) * T(g.stretched ? g.ytab[YT_IDYF * g.ystr + j] : g.idy));
-  const T wn = wsv - ckdt * ((ph - phb) * T(g.idz));
-  // external points hold the immersed walls' velocity (v on the south box wall: 0)
-  const T uo = (tg & TAG_U) ? un : T(L.wallv[0]);
-  const T vo = (tg & TAG_V) ? vn : (j == 0 ? T(0) : T(L.wallv[1]));
-  const T wo = (tg & TAG_W) ? wn : T(L.wallv[2]);
-  const T po = (tg & TAG_P) ? pv + ph : T(0);
+  const Corrected<T> r = corrected_point<T>(g, f, L.wallv, f.tag[c], j, c, c - i + im, c - ds,
+                                            c + (km - k) * nx, ck_dt, pi[0]);
   if (mode & 1) {
-    f.u[c] = uo;
-    f.v[c] = vo;
-    f.w[c] = wo;
-    f.p[c] = po;
+    f.u[c] = r.u;
+    f.v[c] = r.v;
+    f.w[c] = r.w;
+    f.p[c] = r.p;
   }
   if (mode & 2) {
-    f.us[c] = uo;
-    f.vs[c] = vo;
-    f.ws[c] = wo;
-    f.pp[c] = po;
+    f.us[c] = r.u;
+    f.vs[c] = r.v;
+    f.ws[c] = r.w;
+    f.pp[c] = r.p;
   }
 }
 

@@ -106,6 +106,50 @@ def test_translating_body_against_oracle(vel):
     g.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_geometry_update_applies_the_pending_projection(precision):
+    """A geometry update right after a step applies the step's pending projection with the
+    old tags in its first kernel: the same, bit for bit, as taking the state out and
+    seeding it back before the update (nothing pending then); and, moving a sphere each
+    step, the oracle's trajectory (FP64 to 1e-12, FP32 storage to 1e-5)."""
+    c = I.Case(nx=32, ny=17, nz=16, lx=2.0, lz=1.0, y_lo=-1.0, y_hi=1.0, nu=0.02, dt=0.01, q_target_or_pi=1.0,
+               seed=9, geometry="flat", geo_params=(0.0,))
+    vel = (0.2, -0.35, 0.15)
+    centre = np.array([0.6, -0.1, 0.45])
+    sdf = _body_sdf(c, centre, 0.3)
+    u0, v0, w0 = I.laminar_plus_solenoidal(c, sdf, c.seed, amp=0.05)
+    st = (u0, v0, w0, np.zeros_like(u0))
+    o = Oracle(OGrid.from_case(c))
+    o.set_geometry(*sdf)
+    o.set_wall_velocity(*vel)
+    o.set_state(*st)
+    a = gpu_grid(c, sdf, st, precision=precision)
+    b = gpu_grid(c, sdf, st, precision=precision)
+    for g in (a, b):
+        g.set_wall_velocity(*vel)
+    for n in range(3):
+        o.step(1)
+        a.step(1)
+        b.step(1)
+        b.set_state(*b.get_state())           # b: the projection applied and seeded back
+        centre = centre + np.array(vel) * c.dt
+        sdf = _body_sdf(c, centre, 0.3)
+        o.set_geometry(*sdf)
+        a.set_geometry(*[to_dev(x) for x in sdf])   # a: applied inside the update
+        b.set_geometry(*[to_dev(x) for x in sdf])
+    o.step(1)
+    a.step(1)
+    b.step(1)
+    sa, sb = a.get_state(), b.get_state()
+    for x, y in zip(sa, sb):
+        assert torch.equal(x, y)
+    errs, _ = _errs(a, o)
+    _say(f"{precision}: after 3 moves {['%.1e' % e for e in errs]}")
+    assert max(errs) < (1e-12 if precision == "fp64" else 1e-5)
+    a.close()
+    b.close()
+
+
 def test_zero_wall_velocity_is_bitwise_the_plain_step():
     c = case("wavy_small")
     o, sdf, st = oracle_run(c, 0)
