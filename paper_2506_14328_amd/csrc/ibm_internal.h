@@ -363,7 +363,8 @@ struct TriArgs {
   int P;
   int W;
   double* mean_out;
-  int gx;   // blocks along x of the instance's grid
+  int gx;       // blocks of the instance
+  int gather;   // modes left over at the end of the z rows gathered into the first blocks
 };
 
 template <typename T>

@@ -798,7 +798,7 @@ __host__ __device__ inline int tri_rs(int W) { return W + ((8 - W % 16) + 16) % 
 template <typename T, int LM, bool SY>
 __device__ __forceinline__ void k_tri_body(GridParams g, cplx<T>* __restrict__ spec,
                                             const double* __restrict__ kx2, const double* __restrict__ kz2,
-                                            int P, int W, double* __restrict__ mean_out, int bid_x, int bid_y, int nblk) {
+                                            int P, int W, double* __restrict__ mean_out, int bid_x, int gather) {
   if (g.skip && *g.skip) return;   // a converged masked solve: nothing left to do
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* lds = reinterpret_cast<double*>(smem_raw);
@@ -806,11 +806,35 @@ __device__ __forceinline__ void k_tri_body(GridParams g, cplx<T>* __restrict__ s
   const int tid = threadIdx.x;
   const int p = tid / W, w = tid - p * W;
   const bool active = p < P;
-  // modes in spectrum order (kz*mhs + m, padding included, so that the W modes of a
-  // block are one aligned run); padding modes m >= mh are skipped
-  const int qa = bid_x * W + w;
-  const int kz = qa / g.mhs, m = qa - kz * g.mhs;
-  const bool valid = active && kz < g.nz && m < g.mh;
+  // modes.  Without gather: W consecutive entries of the spectrum order kz*mhs + m per
+  // block (aligned runs), the rows' padding entries skipped.  With gather (rows with much
+  // padding): the mh mod W modes left over at the end of every z row, W at a time, in the
+  // first blocks (their scattered accesses overlap with the rest of the grid), then W
+  // consecutive modes of one row per block.  zb: the block holding mode (0, 0), at w = 0.
+  int kz, m, zb = 0;
+  bool mode_ok;
+  if (!gather) {
+    const int q = bid_x * W + w;
+    kz = q / g.mhs;
+    m = q - kz * g.mhs;
+    mode_ok = kz < g.nz && m < g.mh;
+  } else {
+    const int gpr = g.mh / W, rem = g.mh - gpr * W, nremb = (rem * g.nz + W - 1) / W;
+    zb = gpr > 0 ? nremb : 0;
+    if (bid_x < nremb) {
+      const int idx = bid_x * W + w;
+      mode_ok = idx < rem * g.nz;
+      kz = mode_ok ? idx / rem : 0;
+      m = gpr * W + (mode_ok ? idx - kz * rem : 0);
+    } else {
+      const int b = bid_x - nremb;
+      kz = b / gpr;
+      m = (b - kz * gpr) * W + w;
+      mode_ok = true;
+    }
+  }
+  const int qa = kz * g.mhs + m;
+  const bool valid = active && mode_ok;
   const int r0 = (p * n) / P;   // p n < 2^31 (p <= 256, n < 2049)
   const int r1 = active ? ((p + 1) * n) / P : r0;
   const int L = r1 - r0;
@@ -836,13 +860,13 @@ __device__ __forceinline__ void k_tri_body(GridParams g, cplx<T>* __restrict__ s
       di[t] = (double)v.y;
     }
   }
-  // mean of the (0,0) mode over j (only block 0 holds it, at w = 0); on a stretched grid
+  // mean of the (0,0) mode over j (only block zb holds it, at w = 0); on a stretched grid
   // weighted by the cell heights (entry ny1 of their table holds the box height)
   constexpr bool sy = SY;
   const double* yt = g.ytab;
   const int ys = g.ystr;
   double mr = 0.0, mi = 0.0;
-  if (bid_x == 0) {
+  if (bid_x == zb) {
     if (w == 0 && active) {
       double sr = 0.0, si = 0.0;
 #pragma unroll
@@ -1001,7 +1025,7 @@ __device__ __forceinline__ void k_tri_body(GridParams g, cplx<T>* __restrict__ s
     }
   }
   // remove the mean of the (0,0) solution
-  if (bid_x == 0) {
+  if (bid_x == zb) {
     __syncthreads();
     if (w == 0 && active) {
       double sr = 0.0, si = 0.0;
@@ -1028,11 +1052,20 @@ __device__ __forceinline__ void k_tri_body(GridParams g, cplx<T>* __restrict__ s
   }
 }
 
+// Whether the tridiagonal blocks gather the modes left over at the end of the z rows
+// (rows with more than 5 % padding), and the blocks of one launch of W modes each.
+__host__ __device__ inline int tri_gather(const GridParams& g) { return (g.mhs - g.mh) * 20 > g.mhs ? 1 : 0; }
+__host__ __device__ inline int tri_blocks(const GridParams& g, int W, int gather) {
+  if (!gather) return (g.nz * g.mhs + W - 1) / W;
+  const int gpr = g.mh / W, rem = g.mh - gpr * W;
+  return gpr * g.nz + (rem * g.nz + W - 1) / W;
+}
+
 template <typename T, int LM, bool SY>
 __global__ __launch_bounds__(256) void k_tri(GridParams g, cplx<T>* __restrict__ spec,
                                             const double* __restrict__ kx2, const double* __restrict__ kz2,
-                                            int P, int W, double* __restrict__ mean_out) {
-  k_tri_body<T, LM, SY>(g, spec, kx2, kz2, P, W, mean_out, blockIdx.x, blockIdx.y, gridDim.x);
+                                            int P, int W, double* __restrict__ mean_out, int gather) {
+  k_tri_body<T, LM, SY>(g, spec, kx2, kz2, P, W, mean_out, blockIdx.x, gather);
 }
 
 // The same for a batch of independent grids in one launch (block ranges boff).
@@ -1042,7 +1075,7 @@ __global__ __launch_bounds__(256) void k_tri_b(const TriArgs<T>* __restrict__ ar
   const int i = batch_instance(boff, ninst, blockIdx.x);
   const TriArgs<T>& a = args[i];
   const int local = blockIdx.x - boff[i];
-  k_tri_body<T, LM, SY>(a.g, a.spec, a.kx2, a.kz2, a.P, a.W, a.mean_out, local % a.gx, local / a.gx, boff[i + 1] - boff[i]);
+  k_tri_body<T, LM, SY>(a.g, a.spec, a.kx2, a.kz2, a.P, a.W, a.mean_out, local, a.gather);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1426,14 +1459,19 @@ hipError_t launch_tri(const GridParams& g, cplx<T>* spec, const double* kx2, con
   const int TB = (128 / P) * (int)sizeof(cplx<T>) >= 128 ? 128 : 256;
   const int W = TB / P;                      // modes per block
   const size_t lds = (size_t)(4 * tri_rs(W) * 2 * P + 2 * P) * sizeof(double);
-  const dim3 grid((g.nz * g.mhs + W - 1) / W);
+  const int gather = tri_gather(g);
+  const dim3 grid(tri_blocks(g, W, gather));
   const bool l4 = L == 4 && (n + P - 1) / P <= 4;
   if (g.stretched) {
-    if (l4) hipLaunchKernelGGL((k_tri<T, 4, true>), grid, dim3(TB), lds, st, g, spec, kx2, kz2, P, W, mean_out);
-    else hipLaunchKernelGGL((k_tri<T, 8, true>), grid, dim3(TB), lds, st, g, spec, kx2, kz2, P, W, mean_out);
+    if (l4) hipLaunchKernelGGL((k_tri<T, 4, true>), grid, dim3(TB), lds, st, g, spec, kx2, kz2, P, W, mean_out,
+                                          gather);
+    else hipLaunchKernelGGL((k_tri<T, 8, true>), grid, dim3(TB), lds, st, g, spec, kx2, kz2, P, W, mean_out,
+                                          gather);
   } else {
-    if (l4) hipLaunchKernelGGL((k_tri<T, 4, false>), grid, dim3(TB), lds, st, g, spec, kx2, kz2, P, W, mean_out);
-    else hipLaunchKernelGGL((k_tri<T, 8, false>), grid, dim3(TB), lds, st, g, spec, kx2, kz2, P, W, mean_out);
+    if (l4) hipLaunchKernelGGL((k_tri<T, 4, false>), grid, dim3(TB), lds, st, g, spec, kx2, kz2, P, W, mean_out,
+                                          gather);
+    else hipLaunchKernelGGL((k_tri<T, 8, false>), grid, dim3(TB), lds, st, g, spec, kx2, kz2, P, W, mean_out,
+                                          gather);
   }
   return hipGetLastError();
 }
@@ -1533,8 +1571,9 @@ int plan_tri(const GridParams& g, cplx<T>* spec, const double* kx2, const double
   if (P > n / 2) P = n / 2 > 0 ? n / 2 : 1;
   if (P > 256) P = 256;
   const int W = 256 / P;
-  const int nb = (g.nz * g.mhs + W - 1) / W;
-  *a = TriArgs<T>{g, spec, kx2, kz2, P, W, mean_out, nb};
+  const int gather = tri_gather(g);
+  const int nb = tri_blocks(g, W, gather);
+  *a = TriArgs<T>{g, spec, kx2, kz2, P, W, mean_out, nb, gather};
   *lm = (L == 4 && (n + P - 1) / P <= 4) ? 4 : 8;
   *lds = (size_t)(4 * tri_rs(W) * 2 * P + 2 * P) * sizeof(double);
   return nb;
