@@ -663,11 +663,10 @@ int set_geometry_impl(ibm_ctx* c, Instance& I, const double* su, const double* s
   const int cpr = (g.nx + IBM_WAVE - 1) / IBM_WAVE;
   const size_t nch = (size_t)g.nrows * cpr + 1;
   *sized = false;
-  // dense lambda and wall-velocity coefficient per component, per-block counts of the
-  // seven tag masks and the scan's tile sums: allocated at the first geometry of the
-  // instance and kept
+  // per-block counts of the seven tag masks and the scan's tile sums: allocated at the
+  // first geometry of the instance and kept
   const int ntile = 7 * scan_tiles(nblk) + 3 * scan_tiles((int64_t)nch);
-  const size_t tmp_bytes = 6 * nc * 8 + (size_t)(7 * nblk + 1) * 4 + (size_t)ntile * 4;
+  const size_t tmp_bytes = (size_t)(7 * nblk + 1) * 4 + (size_t)ntile * 4;
   if (!I.geo_tmp.p) {
     if (hipMalloc(&I.geo_tmp.p, tmp_bytes) != hipSuccess) {
       I.geo_tmp.p = nullptr;
@@ -682,13 +681,7 @@ int set_geometry_impl(ibm_ctx* c, Instance& I, const double* su, const double* s
     }
     I.ibm_choff.bytes = 3 * nch * 4;
   }
-  double* lam_u = (double*)I.geo_tmp.p;
-  double* lam_v = lam_u + nc;
-  double* lam_w = lam_v + nc;
-  double* sig_u = lam_w + nc;
-  double* sig_v = sig_u + nc;
-  double* sig_w = sig_v + nc;
-  int32_t* blk = (int32_t*)(sig_w + nc);
+  int32_t* blk = (int32_t*)I.geo_tmp.p;
   // I.itotal: [0..6] counts of internal u, v, w, p and immersed-boundary u, v, w points,
   // [8] the lists' overflow flag, [16..18] totals of the chunk counts (not used), [24] the
   // S_k blocks' completion counter (zero between launches)
@@ -709,13 +702,13 @@ int set_geometry_impl(ibm_ctx* c, Instance& I, const double* su, const double* s
       if (c->precision == IBM_FP64) {
         Fields<double> f = fields_of<double>(I);
         f.us = f.usp; f.vs = f.vsp; f.ws = f.wsp;   // the predictor awaiting its projection
-        return launch_geom_lambda<double>(g, su, sv, sw, I.d.ibm, I.tag, lam_u, lam_v, lam_w, sig_u, sig_v, sig_w,
-                                          fuse, f, I.wallv(), ck_dt, I.pi(), I.wall_j, I.wall_d, st);
+        return launch_geom_tags<double>(g, su, sv, sw, I.d.ibm, I.tag, fuse, f, I.wallv(), ck_dt, I.pi(), I.wall_j,
+                                        I.wall_d, st);
       }
       Fields<float> f = fields_of<float>(I);
       f.us = f.usp; f.vs = f.vsp; f.ws = f.wsp;
-      return launch_geom_lambda<float>(g, su, sv, sw, I.d.ibm, I.tag, lam_u, lam_v, lam_w, sig_u, sig_v, sig_w,
-                                       fuse, f, I.wallv(), ck_dt, I.pi(), I.wall_j, I.wall_d, st);
+      return launch_geom_tags<float>(g, su, sv, sw, I.d.ibm, I.tag, fuse, f, I.wallv(), ck_dt, I.pi(), I.wall_j,
+                                     I.wall_d, st);
     });
     // pressure tags with the per-block counts of the seven masks (the overflow flag
     // cleared), and the per-(row, 64-wide chunk) counts of the three immersed-boundary
@@ -785,8 +778,7 @@ int set_geometry_impl(ibm_ctx* c, Instance& I, const double* su, const double* s
     double2* coef = (double2*)I.ibm_coef.p;
     double* lamo = (double*)I.ibm_lam.p;
     double* sigo = (double*)I.ibm_sig.p;
-    e = launch_compact3(I.tag, g.ncell, blk + 4 * (size_t)nblk, nblk, idx, I.cap, overflow, lam_u, sig_u, lamo,
-                        sigo, st);
+    e = launch_compact3(I.tag, g.ncell, blk + 4 * (size_t)nblk, nblk, idx, I.cap, overflow, st);
     if (e != hipSuccess) { rc = fail(c, IBM_ERR_DEVICE, std::string("ibm lists: ") + hipGetErrorString(e)); break; }
     I.L.choff_u = choff;
     I.L.choff_v = choff + nch;
@@ -803,9 +795,9 @@ int set_geometry_impl(ibm_ctx* c, Instance& I, const double* su, const double* s
     I.L.n_w = I.cap[2];
     I.L.n_total = I.cap[0] + I.cap[1] + I.cap[2];
     I.L.n_cover = I.moving() ? I.L.n_total : I.L.n_u;
-    // (with every listed point's per-stage coefficients)
-    e = launch_s_k(g, I.tag, I.L, lamo, coef, I.d.dt, I.d.b_mode, I.red_part, I.d.dt * y_scale(g) * g.dz / g.nx,
-                   I.S3(), cnt7, I.wall_sd(), s_done, st);
+    // (with every listed point's lambda, sigma and per-stage coefficients)
+    e = launch_s_k(g, I.tag, I.L, su, sv, sw, lamo, sigo, coef, I.d.dt, I.d.b_mode, I.red_part,
+                   I.d.dt * y_scale(g) * g.dz / g.nx, I.S3(), cnt7, I.wall_sd(), s_done, st);
     if (e != hipSuccess) { rc = fail(c, IBM_ERR_DEVICE, std::string("S_k: ") + hipGetErrorString(e)); break; }
     if (first && (rc = sync_stream(c, st))) break;
     I.geom_ready = true;

@@ -457,18 +457,16 @@ hipError_t launch_reduce_final(const double* part, int npart, int nsum, int nmax
                                hipStream_t st);
 
 // geometry
-// tags, lambda and sigma (stored at immersed-boundary points only) and the south-wall
-// point of every (k, i) column of u points: the lowest internal row wj (-1: none) and its
-// distance wd to the wall below, negative where that is the south box wall; with correct,
-// first the pending projection of the old geometry applied at every point with the old
-// tags and written over its predictor and pressure (f.us, f.vs, f.ws, f.pp;
+// tags (internal, and immersed-boundary: some arm shorter than its spacing) and the
+// south-wall point of every (k, i) column of u points: the lowest internal row wj (-1:
+// none) and its distance wd to the wall below, negative where that is the south box wall;
+// with correct, first the pending projection of the old geometry applied at every point
+// with the old tags and written over its predictor and pressure (f.us, f.vs, f.ws, f.pp;
 // corrected_point with c_k dt = ck_dt, Pi = pi[0])
 template <typename T>
-hipError_t launch_geom_lambda(const GridParams& g, const double* su, const double* sv, const double* sw,
-                              int ibm_on, uint8_t* tag, double* lam_u, double* lam_v, double* lam_w,
-                              double* sig_u, double* sig_v, double* sig_w, bool correct, const Fields<T>& f,
-                              const double* wallv, double ck_dt, const double* pi, int32_t* wj, double* wd,
-                              hipStream_t st);
+hipError_t launch_geom_tags(const GridParams& g, const double* su, const double* sv, const double* sw, int ibm_on,
+                            uint8_t* tag, bool correct, const Fields<T>& f, const double* wallv, double ck_dt,
+                            const double* pi, int32_t* wj, double* wd, hipStream_t st);
 // pressure tags, then counts[m * nblk + block] of nm <= 8 tag masks (packed 8 bits each
 // into masks) per block of 256 cells (nblk blocks cover the cells); *clear zeroed; with
 // chunks (nx a multiple of 64) the per-(row, 64-chunk) immersed-boundary counts as well;
@@ -542,25 +540,23 @@ struct ScanSet {
 inline int scan_tiles(int64_t n) { return n > 0 ? (int)((n + SCAN_TILE - 1) / SCAN_TILE) : 1; }
 hipError_t launch_scan_multi(ScanSet set, hipStream_t st);
 // the u, v, w immersed-boundary lists of capacities cap[] (laid end to end) from the
-// scanned per-block offsets of their masks (offsets[c * nblk + block]), with each point's
-// lambda and sigma (from lam_dense, sig_dense: three dense component arrays of n values);
-// overflow[0] set when a component has more points than its capacity
+// scanned per-block offsets of their masks (offsets[c * nblk + block]); overflow[0] set
+// when a component has more points than its capacity
 hipError_t launch_compact3(const uint8_t* tag, int64_t n, const int32_t* offsets, int nblk, int32_t* idx,
-                           const int cap[3], int32_t* overflow, const double* lam_dense, const double* sig_dense,
-                           double* lam_out, double* sig_out, hipStream_t st);
+                           const int cap[3], int32_t* overflow, hipStream_t st);
 // per-(row, 64-chunk) counts of the three immersed-boundary masks, [3][nrows cpr + 1]
 hipError_t launch_chunk_counts3(const uint8_t* tag, const GridParams& g, int cpr, int32_t* counts, hipStream_t st);
 hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t st);
 
-// every listed point's per-stage (B, 1/A) from its lambda (lam, list order) into coef,
-// and S3[k] = S_k (Sec. 2.4: c_k dt times the internal non-IBM u points plus the sum of
+// every listed point's lambda and sigma (from the signed distances su, sv, sw) into lam
+// and sig, and its per-stage (B, 1/A) into coef (list order), and S3[k] = S_k (Sec. 2.4: c_k dt times the internal non-IBM u points plus the sum of
 // 1/A_k over the IBM u points, times scale = dy dz / nx) with sd_out[k] the sum over the
 // IBM u points of sig / A_k; part holds the partial sums (4 (ncell/256 + 2 n_u/256 + 2)
 // doubles), cnt7 the tag counts (uniform grids), done a device counter that is zero
 // between launches
-hipError_t launch_s_k(const GridParams& g, const uint8_t* tag, const IbmLists& L, const double* lam, double2* coef,
-                      double dt, int b_mode, double* part, double scale, double* S3, const int32_t* cnt7,
-                      double* sd_out, unsigned* done, hipStream_t st);
+hipError_t launch_s_k(const GridParams& g, const uint8_t* tag, const IbmLists& L, const double* su, const double* sv,
+                      const double* sw, double* lam, double* sig, double2* coef, double dt, int b_mode, double* part,
+                      double scale, double* S3, const int32_t* cnt7, double* sd_out, unsigned* done, hipStream_t st);
 
 // state copy helpers
 template <typename T>

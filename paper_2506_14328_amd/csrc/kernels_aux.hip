@@ -31,6 +31,18 @@ __device__ __forceinline__ void arm_pair(double nu, double h, double d2, double 
   if (cross && delta < box) src += isinf(box) ? l : nu * d2 * h * r;
 }
 
+// Whether that arm changes the Laplacian's centre weight (a positive lambda share):
+// min(delta, box) < h.  With the signed distance crossing zero, delta < h holds exactly
+// when sQ < 0 up to the rounding of the quotient, so the IEEE quotient is formed only when
+// |sQ| is within 2^-40 of sP, where the rounding could decide.
+__device__ __forceinline__ bool arm_active(double h, double sP, double sQ, bool extQ, double box) {
+  if (!extQ) return false;
+  if (box < h) return true;
+  if (!(sQ <= 0.0)) return false;
+  if (sQ < -sP * 0x1p-40) return true;
+  return h * sP / (sP - sQ) < h;
+}
+
 // Wall-normal arm data of component q (0 u, 1 v, 2 w) on row j: the arms' spacings, their
 // second-derivative coefficients and whether the neighbour below / above is a box wall,
 // with that wall's distance (u, w: the south box face is a wall, so is the north one
@@ -125,24 +137,21 @@ __device__ __forceinline__ void south_wall_point(const GridParams& g, const doub
   wd[col] = box ? -d : d;   // negative: the wall is the south box wall (at rest)
 }
 
-// Tags of u, v, w and lambda per component at every cell (j, k, i), with the
-// wall-velocity coefficient sigma per component (both stored at immersed-boundary points
-// only: the list kernels read these arrays at the points of their lists), and the
-// south-wall point of every column (wj, wd).
+// Tags of u, v, w at every cell (j, k, i): internal, and carrying an immersed-boundary
+// correction (some stencil arm ends at a wall nearer than its neighbour: lambda > 0,
+// Eq. (7); lambda and sigma themselves are computed for the listed points only, by
+// k_list_coef), and the south-wall point of every column (wj, wd).
 //  sdf_u, sdf_w: (ny+1, nz, nx), row jj = j+1 holds row j; sdf_v: (ny, nz, nx) faces.
 // With `correct`, first the projection left pending by the last step is applied with the
 // cell's old tag and written over its predictor and pressure (f.us, f.vs, f.ws, f.pp):
 // this thread alone reads and writes those and the tag, and phi is only read here.
 template <typename T>
-__global__ __launch_bounds__(256) void k_geom_lambda(GridParams g, const double* __restrict__ su,
-                                                    const double* __restrict__ sv, const double* __restrict__ sw,
-                                                    int ibm_on, uint8_t* __restrict__ tag,
-                                                    double* __restrict__ lam_u, double* __restrict__ lam_v,
-                                                    double* __restrict__ lam_w, double* __restrict__ sig_u,
-                                                    double* __restrict__ sig_v, double* __restrict__ sig_w,
-                                                    int correct, Fields<T> f, const double* __restrict__ wallv,
-                                                    double ck_dt, const double* __restrict__ pi,
-                                                    int32_t* __restrict__ wj, double* __restrict__ wd) {
+__global__ __launch_bounds__(256) void k_geom_tags(GridParams g, const double* __restrict__ su,
+                                                  const double* __restrict__ sv, const double* __restrict__ sw,
+                                                  int ibm_on, uint8_t* __restrict__ tag, int correct, Fields<T> f,
+                                                  const double* __restrict__ wallv, double ck_dt,
+                                                  const double* __restrict__ pi, int32_t* __restrict__ wj,
+                                                  double* __restrict__ wd) {
   const int i = blockIdx.x * BX + threadIdx.x;
   const int k = blockIdx.y * BZ + threadIdx.y;
   const int j = blockIdx.z;
@@ -163,30 +172,21 @@ __global__ __launch_bounds__(256) void k_geom_lambda(GridParams g, const double*
     f.ws[c] = r.w;
     f.pp[c] = r.p;
   }
-  const double nu = g.nu;
-  const double dx2 = 1.0 / (g.dx * g.dx), dz2 = 1.0 / (g.dz * g.dz);
   uint8_t t = 0;
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
     const double* d = s7[q];
     const bool in = (q == 1) ? (j >= 1 && d[0] > 0.0) : (d[0] > 0.0);
-    double lam = 0.0, sg = 0.0;
-    if (in) {
-      const YArms ya = y_arms(g, q, j);
-      arm_pair(nu, g.dx, dx2, d[0], d[1], d[1] <= 0.0, INFINITY, lam, sg);
-      arm_pair(nu, g.dx, dx2, d[0], d[2], d[2] <= 0.0, INFINITY, lam, sg);
-      arm_pair(nu, g.dz, dz2, d[0], d[3], d[3] <= 0.0, INFINITY, lam, sg);
-      arm_pair(nu, g.dz, dz2, d[0], d[4], d[4] <= 0.0, INFINITY, lam, sg);
-      arm_pair(nu, ya.hdn, ya.cdn, d[0], d[5], ya.gdn || d[5] <= 0.0, ya.bdn, lam, sg);
-      arm_pair(nu, ya.hup, ya.cup, d[0], d[6], ya.gup || d[6] <= 0.0, ya.bup, lam, sg);
-      if (!ibm_on) lam = sg = 0.0;
-      t |= (q == 0) ? TAG_U : (q == 1 ? TAG_V : TAG_W);
-      if (lam > 0.0) t |= (q == 0) ? TAG_UI : (q == 1 ? TAG_VI : TAG_WI);
-    }
-    if (lam > 0.0) {
-      (q == 0 ? lam_u : (q == 1 ? lam_v : lam_w))[c] = lam;
-      (q == 0 ? sig_u : (q == 1 ? sig_v : sig_w))[c] = sg;
-    }
+    if (!in) continue;
+    t |= (q == 0) ? TAG_U : (q == 1 ? TAG_V : TAG_W);
+    const YArms ya = y_arms(g, q, j);
+    const bool ibm = ibm_on && (arm_active(g.dx, d[0], d[1], d[1] <= 0.0, INFINITY) ||
+                                arm_active(g.dx, d[0], d[2], d[2] <= 0.0, INFINITY) ||
+                                arm_active(g.dz, d[0], d[3], d[3] <= 0.0, INFINITY) ||
+                                arm_active(g.dz, d[0], d[4], d[4] <= 0.0, INFINITY) ||
+                                arm_active(ya.hdn, d[0], d[5], ya.gdn || d[5] <= 0.0, ya.bdn) ||
+                                arm_active(ya.hup, d[0], d[6], ya.gup || d[6] <= 0.0, ya.bup));
+    if (ibm) t |= (q == 0) ? TAG_UI : (q == 1 ? TAG_VI : TAG_WI);
   }
   tag[c] = t;
   // the threads of row 0 also locate their column's south-wall point (the first blocks
@@ -366,16 +366,12 @@ __device__ __forceinline__ double2 ibm_stage_coef(double lam, int k, double dt, 
 
 // The ascending cell indices of the u, v and w immersed-boundary points (tag bits
 // TAG_UI << c) at their scanned block offsets offsets[c * nblk + block], into the
-// component's list, which starts at list_off[c] and holds cap[c] entries, with each
-// listed point's lambda and sigma (from the dense per-component arrays, component c at
-// c * n); a point whose rank reaches the capacity is not written and sets overflow[0].
+// component's list, which starts at list_off[c] and holds cap[c] entries; a point whose
+// rank reaches the capacity is not written and sets overflow[0].
 __global__ __launch_bounds__(256) void k_compact3(const uint8_t* __restrict__ tag, int64_t n,
                                                  const int32_t* __restrict__ offsets, int nblk,
                                                  int32_t* __restrict__ idx, int off_v, int off_w, int cap_u,
-                                                 int cap_v, int cap_w, int32_t* __restrict__ overflow,
-                                                 const double* __restrict__ lam_dense,
-                                                 const double* __restrict__ sig_dense,
-                                                 double* __restrict__ lam_out, double* __restrict__ sig_out) {
+                                                 int cap_v, int cap_w, int32_t* __restrict__ overflow) {
   __shared__ int32_t wc[3][4];
   const int64_t e = blockIdx.x * 256ll + threadIdx.x;
   const uint8_t t = (e < n) ? tag[e] : uint8_t(0);
@@ -397,8 +393,6 @@ __global__ __launch_bounds__(256) void k_compact3(const uint8_t* __restrict__ ta
     if (r < cap) {
       const int q = off + r;
       idx[q] = (int32_t)e;
-      lam_out[q] = lam_dense[(size_t)c * n + e];
-      sig_out[q] = sig_dense[(size_t)c * n + e];
     } else {
       overflow[0] = 1;
     }
@@ -518,8 +512,9 @@ __global__ __launch_bounds__(1024) void k_s_final(const double* __restrict__ par
 }
 
 // Per entry of the three immersed-boundary lists (laid end to end: v at n_u, w at
-// n_u + n_v; entries beyond each list's count are skipped): its per-stage (B, 1/A) from
-// its lambda, into coef[k * n_total + entry].  The first nb2 blocks, which hold the whole
+// n_u + n_v; entries beyond each list's count are skipped): its lambda and sigma from the
+// signed distances around it (arm_pair over the six arms, Eq. (7)) into lam and L.sig,
+// and its per-stage (B, 1/A) into coef[k * n_total + entry].  The first nb2 blocks, which hold the whole
 // u list, also write the S_k partials of their u points: per stage the sum of 1/A_k
 // (weighted by the row's cell height on a stretched grid) into part[block * 4 + 1 + k], and
 // of sigma/A_k (the flow rate a moving wall adds, per unit c_k dt U_b) into
@@ -535,7 +530,9 @@ struct SFinal {
   double* sd_out;
   const int32_t* cnt7;
 };
-__global__ __launch_bounds__(256) void k_list_coef(GridParams g, IbmLists L, const double* __restrict__ lam,
+__global__ __launch_bounds__(256) void k_list_coef(GridParams g, IbmLists L, const double* __restrict__ su,
+                                                  const double* __restrict__ sv, const double* __restrict__ sw,
+                                                  double* __restrict__ lam, double* __restrict__ sig,
                                                   double2* __restrict__ coef, double dt, int b_mode, int nb2,
                                                   double* __restrict__ part, double* __restrict__ part_sd,
                                                   SFinal fin) {
@@ -545,8 +542,24 @@ __global__ __launch_bounds__(256) void k_list_coef(GridParams g, IbmLists L, con
   const int cap = cmp == 0 ? L.n_u : (cmp == 1 ? L.n_v : L.n_w);
   const bool valid = e < L.n_total && e - off < min(L.cnt[cmp], cap);
   double2 cf[3];
+  double sg = 0.0;
   if (valid) {
-    const double l = lam[e];
+    const unsigned cell = (unsigned)L.idx[e], nx = g.nx, nz = g.nz;
+    const unsigned row = cell / nx, i = cell - row * nx, j = row / nz, k = row - j * nz;
+    double d[7];
+    samples7(g, cmp == 0 ? su : (cmp == 1 ? sv : sw), cmp, (int)i, (int)k, (int)j, d);
+    const YArms ya = y_arms(g, cmp, (int)j);
+    const double nu = g.nu;
+    const double dx2 = 1.0 / (g.dx * g.dx), dz2 = 1.0 / (g.dz * g.dz);
+    double l = 0.0;
+    arm_pair(nu, g.dx, dx2, d[0], d[1], d[1] <= 0.0, INFINITY, l, sg);
+    arm_pair(nu, g.dx, dx2, d[0], d[2], d[2] <= 0.0, INFINITY, l, sg);
+    arm_pair(nu, g.dz, dz2, d[0], d[3], d[3] <= 0.0, INFINITY, l, sg);
+    arm_pair(nu, g.dz, dz2, d[0], d[4], d[4] <= 0.0, INFINITY, l, sg);
+    arm_pair(nu, ya.hdn, ya.cdn, d[0], d[5], ya.gdn || d[5] <= 0.0, ya.bdn, l, sg);
+    arm_pair(nu, ya.hup, ya.cup, d[0], d[6], ya.gup || d[6] <= 0.0, ya.bup, l, sg);
+    lam[e] = l;
+    sig[e] = sg;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       cf[k] = ibm_stage_coef(l, k, dt, b_mode);
@@ -555,7 +568,6 @@ __global__ __launch_bounds__(256) void k_list_coef(GridParams g, IbmLists L, con
   }
   if ((int)blockIdx.x >= nb2) return;   // (the whole block)
   const bool in = valid && cmp == 0;
-  const double sg = in ? L.sig[e] : 0.0;
   // a stretched grid weights each point by the cell height of its row
   const double wy = (g.stretched && in) ? g.ytab[YT_DYC * g.ystr + L.idx[e] / (g.nx * g.nz)] : 1.0;
   double v[3];
@@ -810,25 +822,21 @@ static inline dim3 cell_grid(const GridParams& g) {
 }
 
 template <typename T>
-hipError_t launch_geom_lambda(const GridParams& g, const double* su, const double* sv, const double* sw,
-                              int ibm_on, uint8_t* tag, double* lam_u, double* lam_v, double* lam_w,
-                              double* sig_u, double* sig_v, double* sig_w, bool correct, const Fields<T>& f,
-                              const double* wallv, double ck_dt, const double* pi, int32_t* wj, double* wd,
-                              hipStream_t st) {
+hipError_t launch_geom_tags(const GridParams& g, const double* su, const double* sv, const double* sw, int ibm_on,
+                            uint8_t* tag, bool correct, const Fields<T>& f, const double* wallv, double ck_dt,
+                            const double* pi, int32_t* wj, double* wd, hipStream_t st) {
   if (correct && (!f.us || !f.vs || !f.ws || !f.pp || !f.phi || !wallv || !pi)) return hipErrorInvalidValue;
   if (!wj || !wd) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_geom_lambda<T>, cell_grid(g), dim3(BX, BZ), 0, st, g, su, sv, sw, ibm_on, tag, lam_u, lam_v,
-                     lam_w, sig_u, sig_v, sig_w, correct ? 1 : 0, f, wallv, ck_dt, pi, wj, wd);
+  hipLaunchKernelGGL(k_geom_tags<T>, cell_grid(g), dim3(BX, BZ), 0, st, g, su, sv, sw, ibm_on, tag, correct ? 1 : 0,
+                     f, wallv, ck_dt, pi, wj, wd);
   return hipGetLastError();
 }
-template hipError_t launch_geom_lambda<double>(const GridParams&, const double*, const double*, const double*, int,
-                                               uint8_t*, double*, double*, double*, double*, double*, double*, bool,
-                                               const Fields<double>&, const double*, double, const double*, int32_t*,
-                                               double*, hipStream_t);
-template hipError_t launch_geom_lambda<float>(const GridParams&, const double*, const double*, const double*, int,
-                                              uint8_t*, double*, double*, double*, double*, double*, double*, bool,
-                                              const Fields<float>&, const double*, double, const double*, int32_t*,
-                                              double*, hipStream_t);
+template hipError_t launch_geom_tags<double>(const GridParams&, const double*, const double*, const double*, int,
+                                             uint8_t*, bool, const Fields<double>&, const double*, double,
+                                             const double*, int32_t*, double*, hipStream_t);
+template hipError_t launch_geom_tags<float>(const GridParams&, const double*, const double*, const double*, int,
+                                            uint8_t*, bool, const Fields<float>&, const double*, double,
+                                            const double*, int32_t*, double*, hipStream_t);
 
 hipError_t launch_geom_ptag_counts(const GridParams& g, uint8_t* tag, uint64_t masks, int nm, int32_t* counts,
                                    int nblk, int32_t* clear, int32_t* chunks, void* zphi, int zelem, double* zpi,
@@ -868,10 +876,9 @@ hipError_t launch_scan_multi(ScanSet set, hipStream_t st) {
 }
 
 hipError_t launch_compact3(const uint8_t* tag, int64_t n, const int32_t* offsets, int nblk, int32_t* idx,
-                           const int cap[3], int32_t* overflow, const double* lam_dense, const double* sig_dense,
-                           double* lam_out, double* sig_out, hipStream_t st) {
+                           const int cap[3], int32_t* overflow, hipStream_t st) {
   hipLaunchKernelGGL(k_compact3, dim3(nblk), dim3(256), 0, st, tag, n, offsets, nblk, idx, cap[0], cap[0] + cap[1],
-                     cap[0], cap[1], cap[2], overflow, lam_dense, sig_dense, lam_out, sig_out);
+                     cap[0], cap[1], cap[2], overflow);
   return hipGetLastError();
 }
 
@@ -890,9 +897,9 @@ hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_s_k(const GridParams& g, const uint8_t* tag, const IbmLists& L, const double* lam, double2* coef,
-                      double dt, int b_mode, double* part, double scale, double* S3, const int32_t* cnt7,
-                      double* sd_out, unsigned* done, hipStream_t st) {
+hipError_t launch_s_k(const GridParams& g, const uint8_t* tag, const IbmLists& L, const double* su, const double* sv,
+                      const double* sw, double* lam, double* sig, double2* coef, double dt, int b_mode, double* part,
+                      double scale, double* S3, const int32_t* cnt7, double* sd_out, unsigned* done, hipStream_t st) {
   // (on a uniform grid the internal non-IBM u points are counted by the tag counts, which
   // the final sums read; a stretched grid weights them by row and sums them here)
   const int nb1 = g.stretched ? (int)((g.ncell + 255) / 256) : 0;
@@ -906,7 +913,7 @@ hipError_t launch_s_k(const GridParams& g, const uint8_t* tag, const IbmLists& L
   if (fused) fin = SFinal{done, scale, S3, sd_out, cnt7};
   if (nb1 > 0) hipLaunchKernelGGL(k_s_cells, dim3(nb1), dim3(256), 0, st, g, tag, part);
   if (nbl > 0)
-    hipLaunchKernelGGL(k_list_coef, dim3(nbl), dim3(256), 0, st, g, L, lam, coef, dt, b_mode, nb2,
+    hipLaunchKernelGGL(k_list_coef, dim3(nbl), dim3(256), 0, st, g, L, su, sv, sw, lam, sig, coef, dt, b_mode, nb2,
                        part + (size_t)nb1 * 4, part_sd, fin);
   if (!fused)
     hipLaunchKernelGGL(k_s_final, dim3(1), dim3(1024), 0, st, part, nb1 + nb2, scale, S3, part_sd, nb2, sd_out,
