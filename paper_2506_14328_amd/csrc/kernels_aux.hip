@@ -142,9 +142,14 @@ __device__ __forceinline__ void south_wall_point(const GridParams& g, const doub
 // Eq. (7); lambda and sigma themselves are computed for the listed points only, by
 // k_list_coef), and the south-wall point of every column (wj, wd).
 //  sdf_u, sdf_w: (ny+1, nz, nx), row jj = j+1 holds row j; sdf_v: (ny, nz, nx) faces.
+// A block takes a 64 x 4 (x, z) tile through TAG_JC rows, marching up in y: each thread
+// keeps the samples of the rows below, at and above its cell in registers and loads one
+// new row per step; the x and z neighbours come from the row's tile in LDS (with a halo
+// of one point; lanes past the box hold the periodically continued samples).
 // With `correct`, first the projection left pending by the last step is applied with the
 // cell's old tag and written over its predictor and pressure (f.us, f.vs, f.ws, f.pp):
 // this thread alone reads and writes those and the tag, and phi is only read here.
+constexpr int TAG_JC = 8;
 template <typename T>
 __global__ __launch_bounds__(256) void k_geom_tags(GridParams g, const double* __restrict__ su,
                                                   const double* __restrict__ sv, const double* __restrict__ sw,
@@ -152,46 +157,85 @@ __global__ __launch_bounds__(256) void k_geom_tags(GridParams g, const double* _
                                                   const double* __restrict__ wallv, double ck_dt,
                                                   const double* __restrict__ pi, int32_t* __restrict__ wj,
                                                   double* __restrict__ wd) {
-  const int i = blockIdx.x * BX + threadIdx.x;
-  const int k = blockIdx.y * BZ + threadIdx.y;
-  const int j = blockIdx.z;
-  if (i >= g.nx || k >= g.nz) return;
-  const int nx = g.nx, nz = g.nz, plane = nx * nz;
-  const int c = (j * nz + k) * nx + i;
-  // every sample loaded up front
-  double s7[3][7];
+  __shared__ double tl[3][BZ + 2][BX + 2];
+  const int tx = threadIdx.x, tz = threadIdx.y;
+  const int nx = g.nx, nz = g.nz, ny1 = g.ny1, plane = nx * nz;
+  const int i = blockIdx.x * BX + tx, k = blockIdx.y * BZ + tz;
+  const bool act = i < nx && k < nz;
+  const int il = i % nx, kl = k % nz;   // (periodic continuation past the box)
+  const int j0 = blockIdx.z * TAG_JC, j1 = min(j0 + TAG_JC, ny1);
   const double* src[3] = {su, sv, sw};
-#pragma unroll
-  for (int q = 0; q < 3; ++q) samples7(g, src[q], q, i, k, j, s7[q]);
-  if (correct) {
-    const int im = wrap_m(i, nx), km = wrap_m(k, nz);
-    const Corrected<T> r = corrected_point<T>(g, f, wallv, tag[c], j, c, c - i + im, j > 0 ? c - plane : c,
-                                              c + (km - k) * nx, ck_dt, pi[0]);
-    f.us[c] = r.u;
-    f.vs[c] = r.v;
-    f.ws[c] = r.w;
-    f.pp[c] = r.p;
-  }
-  uint8_t t = 0;
+  // sample of component q for cell row j at (x, z) = (ii, kk): u and w on sample row j + 1,
+  // v on face j (face -1 clamped to face 0)
+  auto smp = [&](int q, int j, int ii, int kk) -> double {
+    const int r = q == 1 ? (j < 0 ? 0 : j) : j + 1;
+    return src[q][(size_t)r * plane + kk * nx + ii];
+  };
+  const int ihalo = tx == 0 ? (il == 0 ? nx - 1 : il - 1) : (il + 1 == nx ? 0 : il + 1);
+  const bool xh = tx == 0 || tx == BX - 1;
+  const int khalo = tz == 0 ? (kl == 0 ? nz - 1 : kl - 1) : (kl + 1 == nz ? 0 : kl + 1);
+  const bool zh = tz == 0 || tz == BZ - 1;
+  double dn[3], ce[3], up[3];
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
-    const double* d = s7[q];
-    const bool in = (q == 1) ? (j >= 1 && d[0] > 0.0) : (d[0] > 0.0);
-    if (!in) continue;
-    t |= (q == 0) ? TAG_U : (q == 1 ? TAG_V : TAG_W);
-    const YArms ya = y_arms(g, q, j);
-    const bool ibm = ibm_on && (arm_active(g.dx, d[0], d[1], d[1] <= 0.0, INFINITY) ||
-                                arm_active(g.dx, d[0], d[2], d[2] <= 0.0, INFINITY) ||
-                                arm_active(g.dz, d[0], d[3], d[3] <= 0.0, INFINITY) ||
-                                arm_active(g.dz, d[0], d[4], d[4] <= 0.0, INFINITY) ||
-                                arm_active(ya.hdn, d[0], d[5], ya.gdn || d[5] <= 0.0, ya.bdn) ||
-                                arm_active(ya.hup, d[0], d[6], ya.gup || d[6] <= 0.0, ya.bup));
-    if (ibm) t |= (q == 0) ? TAG_UI : (q == 1 ? TAG_VI : TAG_WI);
+    dn[q] = smp(q, j0 - 1, il, kl);
+    ce[q] = smp(q, j0, il, kl);
   }
-  tag[c] = t;
-  // the threads of row 0 also locate their column's south-wall point (the first blocks
-  // dispatched: their extra loads overlap with the rest of the grid)
-  if (j == 0) south_wall_point(g, su, ibm_on, i, k, wj, wd);
+  for (int j = j0; j < j1; ++j) {
+    double hx[3], hz[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      up[q] = smp(q, j + 1, il, kl);
+      hx[q] = xh ? smp(q, j, ihalo, kl) : 0.0;
+      hz[q] = zh ? smp(q, j, il, khalo) : 0.0;
+    }
+    __syncthreads();   // the previous row's tile has been read
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      tl[q][tz + 1][tx + 1] = ce[q];
+      if (xh) tl[q][tz + 1][tx == 0 ? 0 : BX + 1] = hx[q];
+      if (zh) tl[q][tz == 0 ? 0 : BZ + 1][tx + 1] = hz[q];
+    }
+    __syncthreads();
+    if (act) {
+      const int c = (j * nz + k) * nx + i;
+      if (correct) {
+        const int im = wrap_m(i, nx), km = wrap_m(k, nz);
+        const Corrected<T> r = corrected_point<T>(g, f, wallv, tag[c], j, c, c - i + im, j > 0 ? c - plane : c,
+                                                  c + (km - k) * nx, ck_dt, pi[0]);
+        f.us[c] = r.u;
+        f.vs[c] = r.v;
+        f.ws[c] = r.w;
+        f.pp[c] = r.p;
+      }
+      uint8_t t = 0;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const double sP = ce[q];
+        const bool in = (q == 1) ? (j >= 1 && sP > 0.0) : (sP > 0.0);
+        if (!in) continue;
+        t |= (q == 0) ? TAG_U : (q == 1 ? TAG_V : TAG_W);
+        const double sxm = tl[q][tz + 1][tx], sxp = tl[q][tz + 1][tx + 2];
+        const double szm = tl[q][tz][tx + 1], szp = tl[q][tz + 2][tx + 1];
+        const YArms ya = y_arms(g, q, j);
+        const bool ibm = ibm_on && (arm_active(g.dx, sP, sxm, sxm <= 0.0, INFINITY) ||
+                                    arm_active(g.dx, sP, sxp, sxp <= 0.0, INFINITY) ||
+                                    arm_active(g.dz, sP, szm, szm <= 0.0, INFINITY) ||
+                                    arm_active(g.dz, sP, szp, szp <= 0.0, INFINITY) ||
+                                    arm_active(ya.hdn, sP, dn[q], ya.gdn || dn[q] <= 0.0, ya.bdn) ||
+                                    arm_active(ya.hup, sP, up[q], ya.gup || up[q] <= 0.0, ya.bup));
+        if (ibm) t |= (q == 0) ? TAG_UI : (q == 1 ? TAG_VI : TAG_WI);
+      }
+      tag[c] = t;
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      dn[q] = ce[q];
+      ce[q] = up[q];
+    }
+  }
+  // the blocks of the first rows also locate their columns' south-wall points
+  if (j0 == 0 && act) south_wall_point(g, su, ibm_on, i, k, wj, wd);
 }
 
 // Pressure cell internal iff one of its six faces is an internal velocity point; then, per
@@ -827,8 +871,9 @@ hipError_t launch_geom_tags(const GridParams& g, const double* su, const double*
                             const double* pi, int32_t* wj, double* wd, hipStream_t st) {
   if (correct && (!f.us || !f.vs || !f.ws || !f.pp || !f.phi || !wallv || !pi)) return hipErrorInvalidValue;
   if (!wj || !wd) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_geom_tags<T>, cell_grid(g), dim3(BX, BZ), 0, st, g, su, sv, sw, ibm_on, tag, correct ? 1 : 0,
-                     f, wallv, ck_dt, pi, wj, wd);
+  const dim3 grid((g.nx + BX - 1) / BX, (g.nz + BZ - 1) / BZ, (g.ny1 + TAG_JC - 1) / TAG_JC);
+  hipLaunchKernelGGL(k_geom_tags<T>, grid, dim3(BX, BZ), 0, st, g, su, sv, sw, ibm_on, tag, correct ? 1 : 0, f,
+                     wallv, ck_dt, pi, wj, wd);
   return hipGetLastError();
 }
 template hipError_t launch_geom_tags<double>(const GridParams&, const double*, const double*, const double*, int,
