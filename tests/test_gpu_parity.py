@@ -391,6 +391,31 @@ def test_ensemble_autotune_joint(batch):
     g.close()
 
 
+def test_ensemble_branches_tuned_per_instance():
+    """An ensemble of per-instance graph branches is tuned one instance at a time (eager
+    trials): every state is left as it was, and the tuned ensemble still equals each
+    instance's oracle run."""
+    from paper_2506_14328_amd import IbmGrid
+    members = _ensemble_members()[:4]
+    refs = [oracle_run(c, 2) for c in members]
+    g = IbmGrid.ensemble(members, precision="fp64")
+    for i, (o, sdf, st) in enumerate(refs):
+        g.set_geometry(*[to_dev(a) for a in sdf], inst=i)
+        g.set_state(*[to_dev(a) for a in st], inst=i)
+    g.tune(graph=1, batch=0)
+    before = [[t.cpu().numpy() for t in g.get_state(inst=i)] for i in range(len(members))]
+    g.autotune(1)
+    for i in range(len(members)):
+        after = [t.cpu().numpy() for t in g.get_state(inst=i)]
+        assert all(np.array_equal(a, b) for a, b in zip(before[i], after))
+        assert g.stats(inst=i)["step"] == 0
+    g.step(2)
+    for i, (o, sdf, st) in enumerate(refs):
+        u, v, w, p = [t.cpu().numpy() for t in g.get_state(inst=i)]
+        assert rel_err(u, o.u) < 1e-12 and rel_err(v, o.v) < 1e-12 and rel_err(w, o.w) < 1e-12
+    g.close()
+
+
 def test_graph_replays_match_eager():
     """Every replay of the captured step (per-instance launches, or one launch per kernel
     for all instances) equals the eager per-instance launches bit for bit, with eager work
