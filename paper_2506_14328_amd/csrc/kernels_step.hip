@@ -634,14 +634,24 @@ __device__ __forceinline__ void k_div_fftx_body(GridParams g, Fields<T> f, IbmLi
   if (valid) {
     const int jr = row / g.nz;
     cplx<T>* out = f.spec + (size_t)jr * g.splane + (size_t)(row - jr * g.nz) * g.mhs;
-    for (int m = lane; m <= N; m += NL) {
-      const cplx<T> Zm = R[m == N ? 0 : m];
-      const cplx<T> Zc = cconj(R[m == 0 ? 0 : N - m]);
-      const cplx<T> s1 = cadd(Zm, Zc), d1 = csub(Zm, Zc);
+    // modes m and N - m from the same two values: X_{N-m} takes the twiddle
+    // e^{-2 pi i (N-m)/nx} = -conj(e^{-2 pi i m/nx}); m = 0 also gives X_N
+    for (int m = lane; m <= N / 2; m += NL) {
+      const cplx<T> Zm = R[m], Zn = R[m == 0 ? 0 : N - m];
       const double2 e64 = rtw[m];
       const cplx<T> e = {T(e64.x), T(e64.y)};
-      const cplx<T> t = cmul(e, d1);
-      out[m] = cplx<T>{T(0.5) * (s1.x + t.y), T(0.5) * (s1.y - t.x)};
+      {
+        const cplx<T> Zc = cconj(Zn);
+        const cplx<T> s1 = cadd(Zm, Zc), d1 = csub(Zm, Zc);
+        const cplx<T> t = cmul(e, d1);
+        out[m] = cplx<T>{T(0.5) * (s1.x + t.y), T(0.5) * (s1.y - t.x)};
+      }
+      if (2 * m != N) {
+        const cplx<T> Zc = cconj(Zm);
+        const cplx<T> s1 = cadd(Zn, Zc), d1 = csub(Zn, Zc);
+        const cplx<T> t = cmul(cplx<T>{-e.x, e.y}, d1);
+        out[N - m] = cplx<T>{T(0.5) * (s1.x + t.y), T(0.5) * (s1.y - t.x)};
+      }
     }
   }
 }
@@ -1101,14 +1111,24 @@ __device__ __forceinline__ void k_ifftx_body(GridParams g, const cplx<T>* __rest
   if (valid) {
     const int jr = row / g.nz;
     const cplx<T>* in = spec + (size_t)jr * g.splane + (size_t)(row - jr * g.nz) * g.mhs;
-    for (int m = lane; m < N; m += NL) {
-      const cplx<T> X = in[m];
-      const cplx<T> Xc = cconj(in[N - m]);
-      const cplx<T> s1 = cadd(X, Xc), d1 = csub(X, Xc);
+    // modes m and N - m from the same two loads: Z_{N-m} takes the twiddle
+    // e^{+2 pi i (N-m)/nx} = -conj(e^{+2 pi i m/nx})
+    for (int m = lane; m <= N / 2; m += NL) {
+      const cplx<T> X = in[m], Y = in[N - m];
       const double2 e64 = rtw[m];
       const cplx<T> e = {T(e64.x), T(-e64.y)};   // e^{+2 pi i m / nx}
-      const cplx<T> t = cmul(e, d1);
-      A[m] = cplx<T>{s1.x - t.y, s1.y + t.x};
+      {
+        const cplx<T> Yc = cconj(Y);
+        const cplx<T> s1 = cadd(X, Yc), d1 = csub(X, Yc);
+        const cplx<T> t = cmul(e, d1);
+        A[m] = cplx<T>{s1.x - t.y, s1.y + t.x};
+      }
+      if (m > 0 && 2 * m != N) {
+        const cplx<T> Xc = cconj(X);
+        const cplx<T> s1 = cadd(Y, Xc), d1 = csub(Y, Xc);
+        const cplx<T> t = cmul(cplx<T>{-e.x, e.y}, d1);
+        A[N - m] = cplx<T>{s1.x - t.y, s1.y + t.x};
+      }
     }
   }
   __syncthreads();
