@@ -150,6 +150,42 @@ def test_geometry_update_applies_the_pending_projection(precision):
     b.close()
 
 
+def test_many_geometry_updates_keep_the_oracle_trajectory():
+    """Thirty moves of the sphere in a row, the library's step graph on, with no state read
+    in between: every update's flow-rate coefficients S_k come from the last list block to
+    finish (a device counter that each update must leave at zero), so a stale or missed S_k
+    anywhere would show in the flow rate and the state after the last step."""
+    c = I.Case(nx=32, ny=17, nz=16, lx=2.0, lz=1.0, y_lo=-1.0, y_hi=1.0, nu=0.02, dt=0.01, q_target_or_pi=1.0,
+               seed=9, geometry="flat", geo_params=(0.0,))
+    vel = (0.5, 0.1, -0.2)
+    centre = np.array([0.6, -0.2, 0.45])
+    sdf = _body_sdf(c, centre, 0.3)
+    u0, v0, w0 = I.laminar_plus_solenoidal(c, sdf, c.seed, amp=0.05)
+    st = (u0, v0, w0, np.zeros_like(u0))
+    o = Oracle(OGrid.from_case(c))
+    o.set_geometry(*sdf)
+    o.set_wall_velocity(*vel)
+    o.set_state(*st)
+    g = gpu_grid(c, sdf, st)
+    g.set_wall_velocity(*vel)
+    g.tune(graph=1)
+    for n in range(30):
+        o.step(1)
+        g.step(1)
+        centre = centre + np.array(vel) * c.dt
+        sdf = _body_sdf(c, centre, 0.3)
+        o.set_geometry(*sdf)
+        g.set_geometry(*[to_dev(a) for a in sdf])
+    o.step(1)
+    g.step(1)
+    errs, _ = _errs(g, o)
+    _say(f"30 moves: {['%.1e' % e for e in errs]}")
+    assert max(errs) < 1e-12
+    s = g.stats()
+    assert s["n_ibm"][0] > 0 and s["nan_flag"] == 0
+    g.close()
+
+
 def test_zero_wall_velocity_is_bitwise_the_plain_step():
     c = case("wavy_small")
     o, sdf, st = oracle_run(c, 0)
