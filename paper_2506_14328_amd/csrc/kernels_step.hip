@@ -801,9 +801,15 @@ __global__ __launch_bounds__(512) void k_fftz_b(const FftzArgs<T>* __restrict__ 
 // in LDS; each thread then recovers its interior rows.  The spectrum is read once
 // and written once.  W = 256/P modes per block, lane = p * W + w.
 // ---------------------------------------------------------------------------------------
-// Row stride (in doubles) of the reduced-system arrays: W padded so that the four
-// segment groups of a wavefront fall into alternate halves of the LDS banks.
-__host__ __device__ inline int tri_rs(int W) { return W + ((8 - W % 16) + 16) % 16; }
+// Row stride (in doubles) of the reduced-system arrays.  A wavefront holds 64 / W segment
+// groups of W modes (8W bytes each) at a stride of two rows; with W a power of two up to
+// 16 the stride is 3W/2, so that the stride over a group's bytes is odd and successive
+// groups fall on different LDS banks (a stride of W put every group on the same half of
+// the banks); other W keep W padded to 8 modulo 16.
+__host__ __device__ inline int tri_rs(int W) {
+  if (W >= 2 && W <= 16 && (W & (W - 1)) == 0) return 3 * W / 2;
+  return W + ((8 - W % 16) + 16) % 16;
+}
 
 template <typename T, int LM, bool SY>
 __device__ __forceinline__ void k_tri_body(GridParams g, cplx<T>* __restrict__ spec,
