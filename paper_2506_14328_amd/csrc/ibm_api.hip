@@ -659,14 +659,12 @@ int set_geometry_impl(ibm_ctx* c, Instance& I, const double* su, const double* s
   const GridParams& g = I.g;
   hipStream_t st = c->stream;
   const size_t nc = (size_t)g.ncell;
-  const int nblk = (int)((nc + 255) / 256);
   const int cpr = (g.nx + IBM_WAVE - 1) / IBM_WAVE;
   const size_t nch = (size_t)g.nrows * cpr + 1;
   *sized = false;
-  // per-block counts of the seven tag masks and the scan's tile sums: allocated at the
-  // first geometry of the instance and kept
-  const int ntile = 7 * scan_tiles(nblk) + 3 * scan_tiles((int64_t)nch);
-  const size_t tmp_bytes = (size_t)(7 * nblk + 1) * 4 + (size_t)ntile * 4;
+  // the scan's tile sums: allocated at the first geometry of the instance and kept
+  const int ntile = 7 * scan_tiles((int64_t)nch);
+  const size_t tmp_bytes = (size_t)ntile * 4;
   if (!I.geo_tmp.p) {
     if (hipMalloc(&I.geo_tmp.p, tmp_bytes) != hipSuccess) {
       I.geo_tmp.p = nullptr;
@@ -674,20 +672,21 @@ int set_geometry_impl(ibm_ctx* c, Instance& I, const double* su, const double* s
     }
     I.geo_tmp.bytes = tmp_bytes;
   }
+  // per-(row, 64-wide chunk) counts of the seven tag masks, scanned in place into offsets
+  // (those of the three immersed-boundary masks index the lists)
   if (!I.ibm_choff.p) {
-    if (hipMalloc(&I.ibm_choff.p, 3 * nch * 4) != hipSuccess) {
+    if (hipMalloc(&I.ibm_choff.p, 7 * nch * 4) != hipSuccess) {
       I.ibm_choff.p = nullptr;
       return fail(c, IBM_ERR_OOM, "immersed-boundary chunk offsets");
     }
-    I.ibm_choff.bytes = 3 * nch * 4;
+    I.ibm_choff.bytes = 7 * nch * 4;
   }
-  int32_t* blk = (int32_t*)I.geo_tmp.p;
+  int32_t* choff = (int32_t*)I.ibm_choff.p;
   // I.itotal: [0..6] counts of internal u, v, w, p and immersed-boundary u, v, w points,
-  // [8] the lists' overflow flag, [16..18] totals of the chunk counts (not used), [24] the
-  // S_k blocks' completion counter (zero between launches)
+  // [8] the lists' overflow flag, [24] the S_k blocks' completion counter (zero between
+  // launches)
   int32_t* cnt7 = I.itotal;
   int32_t* overflow = I.itotal + 8;
-  int32_t* chunk_totals = I.itotal + 16;
   unsigned* s_done = reinterpret_cast<unsigned*>(I.itotal + 24);
   const bool first = !I.ibm_idx.p || I.lists_overflowed;
   int rc = IBM_OK;
@@ -703,38 +702,22 @@ int set_geometry_impl(ibm_ctx* c, Instance& I, const double* su, const double* s
         Fields<double> f = fields_of<double>(I);
         f.us = f.usp; f.vs = f.vsp; f.ws = f.wsp;   // the predictor awaiting its projection
         return launch_geom_tags<double>(g, su, sv, sw, I.d.ibm, I.tag, fuse, f, I.wallv(), ck_dt, I.pi(), I.wall_j,
-                                        I.wall_d, st);
+                                        I.wall_d, choff, overflow, st);
       }
       Fields<float> f = fields_of<float>(I);
       f.us = f.usp; f.vs = f.vsp; f.ws = f.wsp;
       return launch_geom_tags<float>(g, su, sv, sw, I.d.ibm, I.tag, fuse, f, I.wallv(), ck_dt, I.pi(), I.wall_j,
-                                     I.wall_d, st);
+                                     I.wall_d, choff, overflow, st);
     });
-    // pressure tags with the per-block counts of the seven masks (the overflow flag
-    // cleared), and the per-(row, 64-wide chunk) counts of the three immersed-boundary
-    // masks; then all ten count arrays scanned in place (offsets) in one launch
-    const uint64_t masks = (uint64_t)TAG_U | ((uint64_t)TAG_V << 8) | ((uint64_t)TAG_W << 16) |
-                           ((uint64_t)TAG_P << 24) | ((uint64_t)TAG_UI << 32) | ((uint64_t)TAG_VI << 40) |
-                           ((uint64_t)TAG_WI << 48);
-    int32_t* choff = (int32_t*)I.ibm_choff.p;
-    const bool whole_chunks = g.nx % IBM_WAVE == 0;
-    if (e == hipSuccess)
-      e = launch_geom_ptag_counts(g, I.tag, masks, 7, blk, nblk, overflow, whole_chunks ? choff : nullptr,
-                                  pending ? I.phi : nullptr, esz, pending ? I.pi() : nullptr, st);
-    if (e == hipSuccess && !whole_chunks) e = launch_chunk_counts3(I.tag, g, cpr, choff, st);
+    // the seven chunk-count arrays scanned in place (offsets), their totals into cnt7
     ScanSet set{};
     for (int m = 0; m < 7; ++m) {
-      set.counts[m] = blk + (size_t)m * nblk;
-      set.n[m] = nblk;
+      set.counts[m] = choff + (size_t)m * nch;
+      set.n[m] = (int)nch;
       set.total[m] = cnt7 + m;
     }
-    for (int m = 0; m < 3; ++m) {
-      set.counts[7 + m] = choff + (size_t)m * nch;
-      set.n[7 + m] = (int)nch;
-      set.total[7 + m] = chunk_totals + m;
-    }
-    set.narr = 10;
-    set.tsum = blk + 7 * (size_t)nblk + 1;
+    set.narr = 7;
+    set.tsum = (int32_t*)I.geo_tmp.p;
     set.tsum_cap = ntile;
     if (e == hipSuccess) e = launch_scan_multi(set, st);
     if (e != hipSuccess) { rc = fail(c, IBM_ERR_DEVICE, std::string("geometry: ") + hipGetErrorString(e)); break; }
@@ -778,11 +761,13 @@ int set_geometry_impl(ibm_ctx* c, Instance& I, const double* su, const double* s
     double2* coef = (double2*)I.ibm_coef.p;
     double* lamo = (double*)I.ibm_lam.p;
     double* sigo = (double*)I.ibm_sig.p;
-    e = launch_compact3(I.tag, g.ncell, blk + 4 * (size_t)nblk, nblk, idx, I.cap, overflow, st);
+    // (phi and Pi zeroed here: the tag kernel's correction has read phi)
+    e = launch_compact3(I.tag, g, cpr, choff + 4 * nch, choff + 5 * nch, choff + 6 * nch, idx, I.cap, overflow,
+                        pending ? I.phi : nullptr, esz, pending ? I.pi() : nullptr, st);
     if (e != hipSuccess) { rc = fail(c, IBM_ERR_DEVICE, std::string("ibm lists: ") + hipGetErrorString(e)); break; }
-    I.L.choff_u = choff;
-    I.L.choff_v = choff + nch;
-    I.L.choff_w = choff + 2 * nch;
+    I.L.choff_u = choff + 4 * nch;
+    I.L.choff_v = choff + 5 * nch;
+    I.L.choff_w = choff + 6 * nch;
     I.L.cpr = cpr;
     I.L.idx = idx;
     I.L.coef = coef;

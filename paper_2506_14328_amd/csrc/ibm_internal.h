@@ -457,7 +457,9 @@ hipError_t launch_reduce_final(const double* part, int npart, int nsum, int nmax
                                hipStream_t st);
 
 // geometry
-// tags (internal, and immersed-boundary: some arm shorter than its spacing) and the
+// tags (internal, immersed-boundary: some arm shorter than its spacing, and the pressure
+// tag), counts[m][row * cpr + chunk] of the seven masks (U, V, W, P, UI, VI, WI) per
+// 64-wide row chunk, nrows cpr + 1 entries per mask (the last zero), *clear zeroed, and the
 // south-wall point of every (k, i) column of u points: the lowest internal row wj (-1:
 // none) and its distance wd to the wall below, negative where that is the south box wall;
 // with correct, first the pending projection of the old geometry applied at every point
@@ -466,14 +468,8 @@ hipError_t launch_reduce_final(const double* part, int npart, int nsum, int nmax
 template <typename T>
 hipError_t launch_geom_tags(const GridParams& g, const double* su, const double* sv, const double* sw, int ibm_on,
                             uint8_t* tag, bool correct, const Fields<T>& f, const double* wallv, double ck_dt,
-                            const double* pi, int32_t* wj, double* wd, hipStream_t st);
-// pressure tags, then counts[m * nblk + block] of nm <= 8 tag masks (packed 8 bits each
-// into masks) per block of 256 cells (nblk blocks cover the cells); *clear zeroed; with
-// chunks (nx a multiple of 64) the per-(row, 64-chunk) immersed-boundary counts as well;
-// with zphi every cell's phi (zelem bytes each) zeroed, with zpi the mean pressure gradient
-hipError_t launch_geom_ptag_counts(const GridParams& g, uint8_t* tag, uint64_t masks, int nm, int32_t* counts,
-                                   int nblk, int32_t* clear, int32_t* chunks, void* zphi, int zelem, double* zpi,
-                                   hipStream_t st);
+                            const double* pi, int32_t* wj, double* wd, int32_t* counts, int32_t* clear,
+                            hipStream_t st);
 // masked projection (conjugate gradients on the internal pressure cells): partial-sum
 // slots of PCG_NPART doubles each
 constexpr int PCG_NPART = 1024;
@@ -540,12 +536,12 @@ struct ScanSet {
 inline int scan_tiles(int64_t n) { return n > 0 ? (int)((n + SCAN_TILE - 1) / SCAN_TILE) : 1; }
 hipError_t launch_scan_multi(ScanSet set, hipStream_t st);
 // the u, v, w immersed-boundary lists of capacities cap[] (laid end to end) from the
-// scanned per-block offsets of their masks (offsets[c * nblk + block]); overflow[0] set
-// when a component has more points than its capacity
-hipError_t launch_compact3(const uint8_t* tag, int64_t n, const int32_t* offsets, int nblk, int32_t* idx,
-                           const int cap[3], int32_t* overflow, hipStream_t st);
-// per-(row, 64-chunk) counts of the three immersed-boundary masks, [3][nrows cpr + 1]
-hipError_t launch_chunk_counts3(const uint8_t* tag, const GridParams& g, int cpr, int32_t* counts, hipStream_t st);
+// scanned per-(row, 64-chunk) offsets of their masks (off_u, off_v, off_w); overflow[0]
+// set when a component has more points than its capacity; with zphi every cell's phi
+// (zelem bytes) zeroed, with zpi the mean pressure gradient
+hipError_t launch_compact3(const uint8_t* tag, const GridParams& g, int cpr, const int32_t* off_u,
+                           const int32_t* off_v, const int32_t* off_w, int32_t* idx, const int cap[3],
+                           int32_t* overflow, void* zphi, int zelem, double* zpi, hipStream_t st);
 hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t st);
 
 // every listed point's lambda and sigma (from the signed distances su, sv, sw) into lam

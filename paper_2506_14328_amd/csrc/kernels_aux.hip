@@ -140,7 +140,9 @@ __device__ __forceinline__ void south_wall_point(const GridParams& g, const doub
 // Tags of u, v, w at every cell (j, k, i): internal, and carrying an immersed-boundary
 // correction (some stencil arm ends at a wall nearer than its neighbour: lambda > 0,
 // Eq. (7); lambda and sigma themselves are computed for the listed points only, by
-// k_list_coef), and the south-wall point of every column (wj, wd).
+// k_list_coef); the pressure tag; the counts of the seven tag masks per (row, 64-wide
+// chunk), counts[m * nch + row * cpr + chunk] with one zero entry at the end of each array
+// (nch = nrows cpr + 1); and the south-wall point of every column (wj, wd).
 //  sdf_u, sdf_w: (ny+1, nz, nx), row jj = j+1 holds row j; sdf_v: (ny, nz, nx) faces.
 // A block takes a 64 x 4 (x, z) tile through TAG_JC rows, marching up in y: each thread
 // keeps the samples of the rows below, at and above its cell in registers and loads one
@@ -156,7 +158,8 @@ __global__ __launch_bounds__(256) void k_geom_tags(GridParams g, const double* _
                                                   int ibm_on, uint8_t* __restrict__ tag, int correct, Fields<T> f,
                                                   const double* __restrict__ wallv, double ck_dt,
                                                   const double* __restrict__ pi, int32_t* __restrict__ wj,
-                                                  double* __restrict__ wd) {
+                                                  double* __restrict__ wd, int32_t* __restrict__ counts,
+                                                  int32_t* __restrict__ clear) {
   __shared__ double tl[3][BZ + 2][BX + 2];
   const int tx = threadIdx.x, tz = threadIdx.y;
   const int nx = g.nx, nz = g.nz, ny1 = g.ny1, plane = nx * nz;
@@ -181,6 +184,7 @@ __global__ __launch_bounds__(256) void k_geom_tags(GridParams g, const double* _
     dn[q] = smp(q, j0 - 1, il, kl);
     ce[q] = smp(q, j0, il, kl);
   }
+  uint8_t tg = 0;   // this row's tag (0 for lanes past the box)
   for (int j = j0; j < j1; ++j) {
     double hx[3], hz[3];
 #pragma unroll
@@ -226,74 +230,42 @@ __global__ __launch_bounds__(256) void k_geom_tags(GridParams g, const double* _
                                     arm_active(ya.hup, sP, up[q], ya.gup || up[q] <= 0.0, ya.bup));
         if (ibm) t |= (q == 0) ? TAG_UI : (q == 1 ? TAG_VI : TAG_WI);
       }
+      // the pressure cell is internal iff one of its six faces is an internal velocity
+      // point: its own west, south and back faces, or the east cell's u, the north cell's v
+      // (below the north box face) and the top cell's w
+      const bool ue = tl[0][tz + 1][tx + 2] > 0.0, vn = (j + 1 < ny1) && up[1] > 0.0, wt = tl[2][tz + 2][tx + 1] > 0.0;
+      if ((t & (TAG_U | TAG_V | TAG_W)) || ue || vn || wt) t |= TAG_P;
       tag[c] = t;
+      tg = t;
     }
+    // per-(row, 64-wide chunk) counts of the seven masks: a wave is the chunk blockIdx.x of
+    // row (j, k)
+    if (k < nz) {
+      const int nch = g.nrows * ((nx + BX - 1) / BX) + 1;
+      const int ch = (j * nz + k) * ((nx + BX - 1) / BX) + blockIdx.x;
+      const uint8_t msk[7] = {TAG_U, TAG_V, TAG_W, TAG_P, TAG_UI, TAG_VI, TAG_WI};
+#pragma unroll
+      for (int m = 0; m < 7; ++m) {
+        const uint64_t b = __ballot((tg & msk[m]) != 0);
+        if (tx == 0) counts[m * nch + ch] = __popcll(b);
+      }
+    }
+    tg = 0;
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       dn[q] = ce[q];
       ce[q] = up[q];
     }
   }
+  // one zero entry after each count array; the lists' overflow flag cleared (a kernel, so
+  // that a geometry update can be captured)
+  if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && tx == 0 && tz == 0) {
+    const int nch = g.nrows * ((nx + BX - 1) / BX) + 1;
+    for (int m = 0; m < 7; ++m) counts[m * nch + nch - 1] = 0;
+    clear[0] = 0;
+  }
   // the blocks of the first rows also locate their columns' south-wall points
   if (j0 == 0 && act) south_wall_point(g, su, ibm_on, i, k, wj, wd);
-}
-
-// Pressure cell internal iff one of its six faces is an internal velocity point; then, per
-// block of 256 consecutive cells, the number of cells with each of nm tag masks set (mask
-// m in bits 8m..8m+7 of masks): counts[m * nblk + block]; block 0 also zeroes *clear (the
-// lists' overflow flag, by a kernel so that a geometry update can be captured).  A
-// neighbour's tag may gain its pressure bit while it is read here; only its velocity bits,
-// which no thread changes, are used.
-// With chunks not null (rows of whole 64-wide chunks: nx a multiple of 64) it also
-// writes the per-(row, chunk) counts of the three immersed-boundary masks, laid out as
-// k_chunk_counts3 writes them (wave w of block b is chunk 4b + w).
-__global__ __launch_bounds__(256) void k_geom_ptag_counts(GridParams g, uint8_t* __restrict__ tag, uint64_t masks,
-                                                         int nm, int32_t* __restrict__ counts, int nblk,
-                                                         int32_t* __restrict__ clear, int32_t* __restrict__ chunks,
-                                                         unsigned char* __restrict__ zphi, int zelem,
-                                                         double* __restrict__ zpi) {
-  __shared__ int32_t wc[8][4];
-  const int64_t e = blockIdx.x * 256ll + threadIdx.x;
-  if (zphi && e < g.ncell) {
-    if (zelem == 8) reinterpret_cast<double*>(zphi)[e] = 0.0;
-    else reinterpret_cast<float*>(zphi)[e] = 0.0f;
-  }
-  if (zpi && e == 0) zpi[0] = 0.0;
-  uint8_t t = 0;
-  if (e < g.ncell) {
-    // (32-bit index arithmetic: the grid holds fewer than 2^31 cells)
-    const unsigned nx = g.nx, nz = g.nz, ue = (unsigned)e;
-    const unsigned row = ue / nx, i = ue - row * nx, j = row / nz, k = row - j * nz;
-    t = tag[e];
-    const uint8_t te = tag[ue - i + (i + 1 == nx ? 0u : i + 1)] & TAG_U;
-    const uint8_t tn = (j + 1 < (unsigned)g.ny1) ? (tag[ue + nx * nz] & TAG_V) : 0;
-    const uint8_t tt = tag[k + 1 == nz ? ue - k * nx : ue + nx] & TAG_W;
-    if ((t & (TAG_U | TAG_V | TAG_W)) || te || tn || tt) {
-      t |= TAG_P;
-      tag[e] = t;
-    }
-  }
-  if (clear && e == 0) clear[0] = 0;
-  const int lane = threadIdx.x % IBM_WAVE, wid = threadIdx.x / IBM_WAVE;
-  if (chunks) {
-    const int64_t nch = g.ncell / IBM_WAVE + 1;   // whole chunks, and one zero entry
-    const int64_t ch = e / IBM_WAVE;              // the same for every lane of the wave
-    for (int c = 0; c < 3; ++c) {
-      const uint64_t b = __ballot((t & (TAG_UI << c)) != 0);
-      if (lane == 0 && ch < nch - 1) chunks[c * nch + ch] = __popcll(b);
-      if (e == 0) chunks[c * nch + nch - 1] = 0;
-    }
-  }
-  for (int m = 0; m < nm; ++m) {
-    const uint8_t mask = uint8_t((masks >> (8 * m)) & 0xffu);
-    const uint64_t b = __ballot((t & mask) != 0);
-    if (lane == 0) wc[m][wid] = __popcll(b);
-  }
-  __syncthreads();
-  if ((int)threadIdx.x < nm) {
-    const int m = threadIdx.x;
-    counts[(size_t)m * nblk + blockIdx.x] = wc[m][0] + wc[m][1] + wc[m][2] + wc[m][3];
-  }
 }
 
 // Tiled exclusive scans of several count arrays (ScanSet): block b scans tile
@@ -409,64 +381,41 @@ __device__ __forceinline__ double2 ibm_stage_coef(double lam, int k, double dt, 
 }
 
 // The ascending cell indices of the u, v and w immersed-boundary points (tag bits
-// TAG_UI << c) at their scanned block offsets offsets[c * nblk + block], into the
-// component's list, which starts at list_off[c] and holds cap[c] entries; a point whose
-// rank reaches the capacity is not written and sets overflow[0].
-__global__ __launch_bounds__(256) void k_compact3(const uint8_t* __restrict__ tag, int64_t n,
-                                                 const int32_t* __restrict__ offsets, int nblk,
-                                                 int32_t* __restrict__ idx, int off_v, int off_w, int cap_u,
-                                                 int cap_v, int cap_w, int32_t* __restrict__ overflow) {
-  __shared__ int32_t wc[3][4];
-  const int64_t e = blockIdx.x * 256ll + threadIdx.x;
-  const uint8_t t = (e < n) ? tag[e] : uint8_t(0);
-  const int lane = threadIdx.x % IBM_WAVE, wid = threadIdx.x / IBM_WAVE;
-  uint64_t bal[3];
-  for (int c = 0; c < 3; ++c) {
-    bal[c] = __ballot((t & (TAG_UI << c)) != 0);
-    if (lane == 0) wc[c][wid] = __popcll(bal[c]);
+// TAG_UI << c) into the component's list, which starts at list_off[c] and holds cap[c]
+// entries: wave w of block b is the 64-wide chunk 4b + w (row r = chunk / cpr), whose
+// points go to the chunk's scanned offset offsets[c][chunk] plus their rank among the
+// chunk's flagged lanes; a point whose rank reaches the capacity is not written and sets
+// overflow[0].  With zphi every cell's phi (zelem bytes each) is zeroed too, with zpi the
+// mean pressure gradient: what is left of a projection applied earlier in the update.
+__global__ __launch_bounds__(256) void k_compact3(const uint8_t* __restrict__ tag, int nx, int nrows, int cpr,
+                                                 const int32_t* __restrict__ off_u, const int32_t* __restrict__ off_v,
+                                                 const int32_t* __restrict__ off_w, int32_t* __restrict__ idx,
+                                                 int lo_v, int lo_w, int cap_u, int cap_v, int cap_w,
+                                                 int32_t* __restrict__ overflow, unsigned char* __restrict__ zphi,
+                                                 int zelem, double* __restrict__ zpi) {
+  const int lane = threadIdx.x % IBM_WAVE;
+  const int ch = blockIdx.x * 4 + threadIdx.x / IBM_WAVE;
+  if (ch >= nrows * cpr) return;   // (whole waves)
+  const int row = ch / cpr, i = (ch - row * cpr) * IBM_WAVE + lane;
+  const bool in = i < nx;
+  const int e = row * nx + i;
+  const uint8_t t = in ? tag[e] : uint8_t(0);
+  if (in && zphi) {
+    if (zelem == 8) reinterpret_cast<double*>(zphi)[e] = 0.0;
+    else reinterpret_cast<float*>(zphi)[e] = 0.0f;
   }
-  __syncthreads();
+  if (zpi && ch == 0 && lane == 0) zpi[0] = 0.0;
   const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+#pragma unroll
   for (int c = 0; c < 3; ++c) {
+    const uint64_t bal = __ballot((t & (TAG_UI << c)) != 0);
     if (!(t & (TAG_UI << c))) continue;
-    int base = offsets[(size_t)c * nblk + blockIdx.x];
-    for (int w = 0; w < wid; ++w) base += wc[c][w];
-    const int r = base + __popcll(bal[c] & below);
+    const int r = (c == 0 ? off_u : (c == 1 ? off_v : off_w))[ch] + __popcll(bal & below);
     const int cap = c == 0 ? cap_u : (c == 1 ? cap_v : cap_w);
-    const int off = c == 0 ? 0 : (c == 1 ? off_v : off_w);
-    if (r < cap) {
-      const int q = off + r;
-      idx[q] = (int32_t)e;
-    } else {
-      overflow[0] = 1;
-    }
+    const int lo = c == 0 ? 0 : (c == 1 ? lo_v : lo_w);
+    if (r < cap) idx[lo + r] = e;
+    else overflow[0] = 1;
   }
-}
-
-// Flagged cells per 64-wide chunk of each grid row for the three immersed-boundary masks:
-// counts[c * (nrows cpr + 1) + row * cpr + ch]; one extra zero entry per mask.
-__global__ __launch_bounds__(256) void k_chunk_counts3(const uint8_t* __restrict__ tag, int nx, int nrows, int cpr,
-                                                      int32_t* __restrict__ counts) {
-  const int e = blockIdx.x * 256 + threadIdx.x;
-  const int nch = nrows * cpr + 1;
-  if (e >= nch) return;
-  if (e == nch - 1) {
-    for (int c = 0; c < 3; ++c) counts[c * nch + e] = 0;
-    return;
-  }
-  const int row = e / cpr, ch = e - row * cpr;
-  const int a = ch * IBM_WAVE, b = min(a + IBM_WAVE, nx);
-  const uint8_t* t = tag + (size_t)row * nx;
-  int n0 = 0, n1 = 0, n2 = 0;
-  for (int i = a; i < b; ++i) {
-    const uint8_t v = t[i];
-    n0 += (v & TAG_UI) ? 1 : 0;
-    n1 += (v & TAG_VI) ? 1 : 0;
-    n2 += (v & TAG_WI) ? 1 : 0;
-  }
-  counts[e] = n0;
-  counts[nch + e] = n1;
-  counts[2 * nch + e] = n2;
 }
 
 // bytes zeros from p (a kernel: no memset nodes in captured graphs): nvec 16-byte vectors
@@ -868,29 +817,22 @@ static inline dim3 cell_grid(const GridParams& g) {
 template <typename T>
 hipError_t launch_geom_tags(const GridParams& g, const double* su, const double* sv, const double* sw, int ibm_on,
                             uint8_t* tag, bool correct, const Fields<T>& f, const double* wallv, double ck_dt,
-                            const double* pi, int32_t* wj, double* wd, hipStream_t st) {
+                            const double* pi, int32_t* wj, double* wd, int32_t* counts, int32_t* clear,
+                            hipStream_t st) {
   if (correct && (!f.us || !f.vs || !f.ws || !f.pp || !f.phi || !wallv || !pi)) return hipErrorInvalidValue;
-  if (!wj || !wd) return hipErrorInvalidValue;
+  if (!wj || !wd || !counts || !clear) return hipErrorInvalidValue;
   const dim3 grid((g.nx + BX - 1) / BX, (g.nz + BZ - 1) / BZ, (g.ny1 + TAG_JC - 1) / TAG_JC);
   hipLaunchKernelGGL(k_geom_tags<T>, grid, dim3(BX, BZ), 0, st, g, su, sv, sw, ibm_on, tag, correct ? 1 : 0, f,
-                     wallv, ck_dt, pi, wj, wd);
+                     wallv, ck_dt, pi, wj, wd, counts, clear);
   return hipGetLastError();
 }
 template hipError_t launch_geom_tags<double>(const GridParams&, const double*, const double*, const double*, int,
                                              uint8_t*, bool, const Fields<double>&, const double*, double,
-                                             const double*, int32_t*, double*, hipStream_t);
+                                             const double*, int32_t*, double*, int32_t*, int32_t*, hipStream_t);
 template hipError_t launch_geom_tags<float>(const GridParams&, const double*, const double*, const double*, int,
                                             uint8_t*, bool, const Fields<float>&, const double*, double,
-                                            const double*, int32_t*, double*, hipStream_t);
+                                            const double*, int32_t*, double*, int32_t*, int32_t*, hipStream_t);
 
-hipError_t launch_geom_ptag_counts(const GridParams& g, uint8_t* tag, uint64_t masks, int nm, int32_t* counts,
-                                   int nblk, int32_t* clear, int32_t* chunks, void* zphi, int zelem, double* zpi,
-                                   hipStream_t st) {
-  if ((int64_t)nblk * 256 < g.ncell || nm > 8 || (chunks && g.nx % IBM_WAVE != 0)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_geom_ptag_counts, dim3(nblk), dim3(256), 0, st, g, tag, masks, nm, counts, nblk, clear,
-                     chunks, (unsigned char*)zphi, zelem, zpi);
-  return hipGetLastError();
-}
 
 
 template <typename T>
@@ -920,18 +862,16 @@ hipError_t launch_scan_multi(ScanSet set, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_compact3(const uint8_t* tag, int64_t n, const int32_t* offsets, int nblk, int32_t* idx,
-                           const int cap[3], int32_t* overflow, hipStream_t st) {
-  hipLaunchKernelGGL(k_compact3, dim3(nblk), dim3(256), 0, st, tag, n, offsets, nblk, idx, cap[0], cap[0] + cap[1],
-                     cap[0], cap[1], cap[2], overflow);
+hipError_t launch_compact3(const uint8_t* tag, const GridParams& g, int cpr, const int32_t* off_u,
+                           const int32_t* off_v, const int32_t* off_w, int32_t* idx, const int cap[3],
+                           int32_t* overflow, void* zphi, int zelem, double* zpi, hipStream_t st) {
+  const int nchunk = g.nrows * cpr;
+  hipLaunchKernelGGL(k_compact3, dim3((nchunk + 3) / 4), dim3(256), 0, st, tag, g.nx, g.nrows, cpr, off_u, off_v,
+                     off_w, idx, cap[0], cap[0] + cap[1], cap[0], cap[1], cap[2], overflow, (unsigned char*)zphi,
+                     zelem, zpi);
   return hipGetLastError();
 }
 
-hipError_t launch_chunk_counts3(const uint8_t* tag, const GridParams& g, int cpr, int32_t* counts, hipStream_t st) {
-  const int n = g.nrows * cpr + 1;
-  hipLaunchKernelGGL(k_chunk_counts3, dim3((n + 255) / 256), dim3(256), 0, st, tag, g.nx, g.nrows, cpr, counts);
-  return hipGetLastError();
-}
 
 
 hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t st) {
