@@ -126,7 +126,7 @@ struct ibm_ctx {
     const int *bo_mom = nullptr, *bo_cfr = nullptr, *bo_div = nullptr, *bo_fz = nullptr, *bo_tri = nullptr,
               *bo_ifx = nullptr;
     int n_mom = 0, n_cfr = 0, n_div = 0, n_fz = 0, n_tri = 0, n_ifx = 0;
-    int mb_div = 1, mb_fz = 1, mb_ifx = 1, lm_tri = 4, th_fz = 256;
+    int mb_div = 1, mb_fz = 1, rp_fz = 0, mb_ifx = 1, lm_tri = 4, th_fz = 256;
     size_t lds_div = 0, lds_fz = 0, lds_tri = 0, lds_ifx = 0;
     bool stretched = false;   // some instance has a stretched wall-normal grid
   } batch;
@@ -893,6 +893,20 @@ int build_batch(ibm_ctx* c) {
     b.mb_ifx = std::max(b.mb_ifx, mb);
     b.lds_ifx = std::max(b.lds_ifx, lds);
   }
+  // z FFTs: two planes per block with the next plane's columns in registers (RP per
+  // thread) when every instance's share of a column, at the launch's thread count, fits 8
+  int per = 0;
+  for (int i = 0; i < n; ++i) per = std::max(per, (c->inst[i].g.nz + b.th_fz / fzf[i].W - 1) / (b.th_fz / fzf[i].W));
+  b.rp_fz = per <= 4 ? 4 : (per <= 8 ? 8 : 0);
+  if (b.rp_fz) {
+    for (int i = 0; i < n; ++i) {
+      const GridParams& g = c->inst[i].g;
+      const int nb = fftz_blocks(g.mh, g.ny1, fzf[i].W, 2);
+      fzf[i].nj = fzi[i].nj = 2;
+      fzf[i].gx = fzi[i].gx = nb;
+      bo[3][i + 1] = nb;
+    }
+  }
   for (auto& v : bo)
     for (int i = 0; i < n; ++i) v[i + 1] += v[i];
   // pack everything into one host image (256-byte aligned pieces), then one device copy
@@ -966,10 +980,10 @@ int run_steps_batched(ibm_ctx* c, int nsteps, hipStream_t st, bool count = true)
       RUNK(c, K_CFR_PI, launch_cfr_pi_b<T>((const CfrArgs<T>*)b.cfr[k], b.bo_cfr, n, b.n_cfr, st));
       RUNK(c, K_DIV_FFTX, launch_div_fftx_b<T>((const DivArgs<T>*)b.div[k], b.bo_div, n, b.n_div, b.mb_div,
                                                b.lds_div, st));
-      RUNK(c, K_FFTZ_FWD, launch_fftz_b<T>((const FftzArgs<T>*)b.fzf, b.bo_fz, n, b.n_fz, b.mb_fz, b.lds_fz,
+      RUNK(c, K_FFTZ_FWD, launch_fftz_b<T>((const FftzArgs<T>*)b.fzf, b.bo_fz, n, b.n_fz, b.mb_fz, b.rp_fz, b.lds_fz,
                                            b.th_fz, st));
       RUNK(c, K_TRI, launch_tri_b<T>((const TriArgs<T>*)b.tri, b.bo_tri, n, b.n_tri, b.lm_tri, b.lds_tri, b.stretched, st));
-      RUNK(c, K_FFTZ_INV, launch_fftz_b<T>((const FftzArgs<T>*)b.fzi, b.bo_fz, n, b.n_fz, b.mb_fz, b.lds_fz,
+      RUNK(c, K_FFTZ_INV, launch_fftz_b<T>((const FftzArgs<T>*)b.fzi, b.bo_fz, n, b.n_fz, b.mb_fz, b.rp_fz, b.lds_fz,
                                            b.th_fz, st));
       RUNK(c, K_IFFTX, launch_ifftx_b<T>((const IfftxArgs<T>*)b.ifx, b.bo_ifx, n, b.n_ifx, b.mb_ifx, b.lds_ifx,
                                          st));

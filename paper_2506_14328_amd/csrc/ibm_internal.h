@@ -344,6 +344,13 @@ struct DivArgs {
   int gx;   // blocks along x of the instance's grid
 };
 
+// Blocks of one z-FFT launch: full blocks (W columns through NJ planes each) plus the
+// remainder columns gathered W at a time.
+__host__ __device__ inline int fftz_blocks(int mh, int ny1, int W, int NJ) {
+  const int gxf = mh / W, rem = mh - gxf * W;
+  return gxf * ((ny1 + NJ - 1) / NJ) + (rem * ny1 + W - 1) / W;
+}
+
 template <typename T>
 struct FftzArgs {
   GridParams g;
@@ -351,7 +358,8 @@ struct FftzArgs {
   FFTPlan pz;
   int sign;
   int W;
-  int gx;   // blocks along x of the instance's grid
+  int gx;   // blocks of the instance's launch
+  int nj;   // planes per full block
 };
 
 template <typename T>
@@ -407,7 +415,7 @@ template <typename T>
 hipError_t launch_div_fftx_b(const DivArgs<T>* args, const int* boff, int ninst, int ntot, int mb, size_t lds,
                              hipStream_t st);
 template <typename T>
-hipError_t launch_fftz_b(const FftzArgs<T>* args, const int* boff, int ninst, int ntot, int mb, size_t lds,
+hipError_t launch_fftz_b(const FftzArgs<T>* args, const int* boff, int ninst, int ntot, int mb, int rp, size_t lds,
                          int threads, hipStream_t st);
 template <typename T>
 hipError_t launch_tri_b(const TriArgs<T>* args, const int* boff, int ninst, int ntot, int lm, size_t lds,

@@ -761,28 +761,22 @@ __device__ __forceinline__ void k_fftz_body(GridParams g, cplx<T>* __restrict__ 
     for (int kz = lane; kz < nz; kz += nl) col[(size_t)kz * mhs] = A[(kz << lw) + w];
 }
 
-// Blocks of one z-FFT launch: full blocks (NJ planes each) plus the gathered remainder
-// columns.
-__host__ __device__ inline int fftz_blocks(int mh, int ny1, int W, int NJ) {
-  const int gxf = mh / W, rem = mh - gxf * W;
-  return gxf * ((ny1 + NJ - 1) / NJ) + (rem * ny1 + W - 1) / W;
-}
-
 template <typename T, int MB, int RP>
 __global__ __launch_bounds__(512) void k_fftz(GridParams g, cplx<T>* __restrict__ spec, FFTPlan pz, int sign,
                                              int W, int NJ) {
   k_fftz_body<T, MB, RP>(g, spec, pz, sign, W, NJ, blockIdx.x);
 }
 
-// The same for a batch of independent grids in one launch (block ranges boff), one plane
-// per block.
-template <typename T, int MB>
+// The same for a batch of independent grids in one launch (block ranges boff), a.nj
+// planes per full block (two, with the next plane held in RP registers per thread, when
+// every instance's share of a column fits them).
+template <typename T, int MB, int RP>
 __global__ __launch_bounds__(512) void k_fftz_b(const FftzArgs<T>* __restrict__ args,
     const int* __restrict__ boff, int ninst) {
   const int i = batch_instance(boff, ninst, blockIdx.x);
   const FftzArgs<T>& a = args[i];
   const int local = blockIdx.x - boff[i];
-  k_fftz_body<T, MB, 0>(a.g, a.spec, a.pz, a.sign, a.W, 1, local);
+  k_fftz_body<T, MB, RP>(a.g, a.spec, a.pz, a.sign, a.W, a.nj, local);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1581,7 +1575,7 @@ int plan_fftz(const GridParams& g, cplx<T>* spec, const FFTPlan& pz, int sign, c
   const int W = fftz_width<T>(g, pz, tu);
   const int nt = fftz_threads(pz, W);
   const int nb = fftz_blocks(g.mh, g.ny1, W, 1);
-  *a = FftzArgs<T>{g, spec, pz, sign, W, nb};
+  *a = FftzArgs<T>{g, spec, pz, sign, W, nb, 1};
   *mb = fft_max_bfly(pz, nt / W);
   *lds = ((size_t)W + 1) * g.nz * sizeof(cplx<T>);
   *threads = nt;
@@ -1650,16 +1644,32 @@ hipError_t launch_div_fftx_b(const DivArgs<T>* args, const int* boff, int ninst,
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_fftz_b(const FftzArgs<T>* args, const int* boff, int ninst, int ntot, int mb, size_t lds,
-                         int threads, hipStream_t st) {
-  const void* k = mb == 1 ? (const void*)k_fftz_b<T, 1> : (mb == 2 ? (const void*)k_fftz_b<T, 2> : (const void*)k_fftz_b<T, 4>);
-  hipError_t e = allow_lds(k, lds);
+template <typename T, int MB, int RP>
+static hipError_t launch_fftz_bv(const FftzArgs<T>* args, const int* boff, int ninst, int ntot, size_t lds,
+                                 int threads, hipStream_t st) {
+  hipError_t e = allow_lds((const void*)k_fftz_b<T, MB, RP>, lds);
   if (e != hipSuccess) return e;
-  if (mb == 1) hipLaunchKernelGGL((k_fftz_b<T, 1>), dim3(ntot), dim3(threads), lds, st, args, boff, ninst);
-  else if (mb == 2) hipLaunchKernelGGL((k_fftz_b<T, 2>), dim3(ntot), dim3(threads), lds, st, args, boff, ninst);
-  else hipLaunchKernelGGL((k_fftz_b<T, 4>), dim3(ntot), dim3(threads), lds, st, args, boff, ninst);
+  hipLaunchKernelGGL((k_fftz_b<T, MB, RP>), dim3(ntot), dim3(threads), lds, st, args, boff, ninst);
   return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fftz_b(const FftzArgs<T>* args, const int* boff, int ninst, int ntot, int mb, int rp, size_t lds,
+                         int threads, hipStream_t st) {
+  if (rp != 0 && rp != 4 && rp != 8) return hipErrorInvalidValue;
+  if (mb == 1) {
+    if (rp == 4) return launch_fftz_bv<T, 1, 4>(args, boff, ninst, ntot, lds, threads, st);
+    if (rp == 8) return launch_fftz_bv<T, 1, 8>(args, boff, ninst, ntot, lds, threads, st);
+    return launch_fftz_bv<T, 1, 0>(args, boff, ninst, ntot, lds, threads, st);
+  }
+  if (mb == 2) {
+    if (rp == 4) return launch_fftz_bv<T, 2, 4>(args, boff, ninst, ntot, lds, threads, st);
+    if (rp == 8) return launch_fftz_bv<T, 2, 8>(args, boff, ninst, ntot, lds, threads, st);
+    return launch_fftz_bv<T, 2, 0>(args, boff, ninst, ntot, lds, threads, st);
+  }
+  if (rp == 4) return launch_fftz_bv<T, 4, 4>(args, boff, ninst, ntot, lds, threads, st);
+  if (rp == 8) return launch_fftz_bv<T, 4, 8>(args, boff, ninst, ntot, lds, threads, st);
+  return launch_fftz_bv<T, 4, 0>(args, boff, ninst, ntot, lds, threads, st);
 }
 
 template <typename T>
@@ -1707,7 +1717,7 @@ hipError_t launch_ifftx_b(const IfftxArgs<T>* args, const int* boff, int ninst, 
   template hipError_t launch_momentum_b<T>(const MomArgs<T>*, const int*, int, int, bool, hipStream_t);               \
   template hipError_t launch_cfr_pi_b<T>(const CfrArgs<T>*, const int*, int, int, hipStream_t);                 \
   template hipError_t launch_div_fftx_b<T>(const DivArgs<T>*, const int*, int, int, int, size_t, hipStream_t);  \
-  template hipError_t launch_fftz_b<T>(const FftzArgs<T>*, const int*, int, int, int, size_t, int,              \
+  template hipError_t launch_fftz_b<T>(const FftzArgs<T>*, const int*, int, int, int, int, size_t, int,         \
                                        hipStream_t);                                                            \
   template hipError_t launch_tri_b<T>(const TriArgs<T>*, const int*, int, int, int, size_t, bool, hipStream_t);       \
   template hipError_t launch_ifftx_b<T>(const IfftxArgs<T>*, const int*, int, int, int, size_t, hipStream_t);
