@@ -893,16 +893,18 @@ int build_batch(ibm_ctx* c) {
     b.mb_ifx = std::max(b.mb_ifx, mb);
     b.lds_ifx = std::max(b.lds_ifx, lds);
   }
-  // z FFTs: two planes per block with the next plane's columns in registers (RP per
+  // z FFTs: four planes per block with the next plane's columns in registers (RP per
   // thread) when every instance's share of a column, at the launch's thread count, fits 8
+  // (the ensemble's many small planes: 307 us per launch with one plane per block, 291
+  // with two, 276 with four or eight)
   int per = 0;
   for (int i = 0; i < n; ++i) per = std::max(per, (c->inst[i].g.nz + b.th_fz / fzf[i].W - 1) / (b.th_fz / fzf[i].W));
   b.rp_fz = per <= 4 ? 4 : (per <= 8 ? 8 : 0);
   if (b.rp_fz) {
     for (int i = 0; i < n; ++i) {
       const GridParams& g = c->inst[i].g;
-      const int nb = fftz_blocks(g.mh, g.ny1, fzf[i].W, 2);
-      fzf[i].nj = fzi[i].nj = 2;
+      const int nb = fftz_blocks(g.mh, g.ny1, fzf[i].W, 4);
+      fzf[i].nj = fzi[i].nj = 4;
       fzf[i].gx = fzi[i].gx = nb;
       bo[3][i + 1] = nb;
     }

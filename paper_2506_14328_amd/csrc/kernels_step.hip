@@ -768,8 +768,8 @@ __global__ __launch_bounds__(512) void k_fftz(GridParams g, cplx<T>* __restrict_
 }
 
 // The same for a batch of independent grids in one launch (block ranges boff), a.nj
-// planes per full block (two, with the next plane held in RP registers per thread, when
-// every instance's share of a column fits them).
+// planes per full block (several, with the next plane held in RP registers per thread,
+// when every instance's share of a column fits them).
 template <typename T, int MB, int RP>
 __global__ __launch_bounds__(512) void k_fftz_b(const FftzArgs<T>* __restrict__ args,
     const int* __restrict__ boff, int ninst) {
