@@ -909,8 +909,12 @@ int build_batch(ibm_ctx* c) {
       bo[3][i + 1] = nb;
     }
   }
-  for (auto& v : bo)
+  // block offsets, then the instance of every block (the kernels' lookup table)
+  for (auto& v : bo) {
     for (int i = 0; i < n; ++i) v[i + 1] += v[i];
+    v.reserve(n + 1 + v[n]);
+    for (int i = 0; i < n; ++i) v.insert(v.end(), v[i + 1] - v[i], i);
+  }
   // pack everything into one host image (256-byte aligned pieces), then one device copy
   std::vector<unsigned char> img;
   auto put = [&](const void* src, size_t bytes) {
@@ -928,7 +932,7 @@ int build_batch(ibm_ctx* c) {
   const size_t o_fzf = put(fzf.data(), n * sizeof(FftzArgs<T>)), o_fzi = put(fzi.data(), n * sizeof(FftzArgs<T>));
   const size_t o_tri = put(tri.data(), n * sizeof(TriArgs<T>)), o_ifx = put(ifx.data(), n * sizeof(IfftxArgs<T>));
   size_t o_bo[6];
-  for (int q = 0; q < 6; ++q) o_bo[q] = put(bo[q].data(), (n + 1) * sizeof(int));
+  for (int q = 0; q < 6; ++q) o_bo[q] = put(bo[q].data(), bo[q].size() * sizeof(int));
   if (hipMalloc(&b.dbuf, img.size()) != hipSuccess) {
     b.dbuf = nullptr;
     return fail(c, IBM_ERR_OOM, "batched launch arguments");

@@ -17,15 +17,12 @@ constexpr int BZ = 4;   // z rows per block
 __device__ __forceinline__ int wrap_p(int i, int n) { return (i + 1 == n) ? 0 : i + 1; }
 __device__ __forceinline__ int wrap_m(int i, int n) { return (i == 0) ? n - 1 : i - 1; }
 
-// Instance of block b in a batched launch: boff[i] <= b < boff[i+1] (boff[0] = 0).
+// Instance of block b in a batched launch (boff[i] <= b < boff[i+1], boff[0] = 0): read
+// from the table of every block's instance that follows the ninst + 1 offsets (one load,
+// where a binary search over the offsets made a chain of dependent loads at every block's
+// start).
 __device__ __forceinline__ int batch_instance(const int* __restrict__ boff, int ninst, int b) {
-  int lo = 0, hi = ninst - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (boff[mid] <= b) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
+  return boff[ninst + 1 + b];
 }
 
 // ---------------------------------------------------------------------------------------
