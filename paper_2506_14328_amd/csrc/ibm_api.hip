@@ -198,11 +198,22 @@ hipError_t timed(ibm_ctx* c, int kid, F&& launch) {
 
 void set_last_error(const char* msg) { g_last_error = msg; }
 
+// Radices of a length-n transform: the power of two in 8s and 4s (8 8 .. 4 4 rather than
+// 8 8 .. 8 2 when the exponent is 1 mod 3, so that no radix-2 stage asks for n/2
+// butterflies: the lanes per sequence follow the largest stage's butterfly count), then
+// the 3s and the 5s.
 bool factor_235(int n, int* radix, int* nst) {
-  int k = 0;
-  while (n % 8 == 0 && k < 20) { radix[k++] = 8; n /= 8; }
-  while (n % 4 == 0 && k < 20) { radix[k++] = 4; n /= 4; }
-  while (n % 2 == 0 && k < 20) { radix[k++] = 2; n /= 2; }
+  int k = 0, a = 0;
+  while (n % 2 == 0 && a < 40) { ++a; n /= 2; }
+  int n8 = a / 3, n4 = 0, n2 = 0;
+  if (a % 3 == 2) n4 = 1;
+  if (a % 3 == 1) {
+    if (n8 > 0) { --n8; n4 = 2; }
+    else n2 = 1;
+  }
+  for (int i = 0; i < n8 && k < 20; ++i) radix[k++] = 8;
+  for (int i = 0; i < n4 && k < 20; ++i) radix[k++] = 4;
+  for (int i = 0; i < n2 && k < 20; ++i) radix[k++] = 2;
   while (n % 3 == 0 && k < 20) { radix[k++] = 3; n /= 3; }
   while (n % 5 == 0 && k < 20) { radix[k++] = 5; n /= 5; }
   *nst = k;
