@@ -1463,6 +1463,17 @@ hipError_t launch_fftz(const GridParams& g, cplx<T>* spec, const FFTPlan& pz, in
   return launch_fftz_v<T, 4, 0>(g, spec, pz, sign, W, nj, nt, lds, st);
 }
 
+// Modes per tridiagonal block with P threads per mode in at most tb threads: tb / P, or the
+// largest power of two below it when that still reads whole 128-byte lines of every row
+// (a run of W modes that is not a power of two starts and ends inside lines, and its
+// segment groups straddle the wavefronts).
+template <typename T>
+static int tri_width(int P, int tb) {
+  int w2 = 1;
+  while (2 * w2 * P <= tb) w2 *= 2;
+  return w2 * (int)sizeof(cplx<T>) >= 128 ? w2 : tb / P;
+}
+
 template <typename T>
 hipError_t launch_tri(const GridParams& g, cplx<T>* spec, const double* kx2, const double* kz2, double* mean_out,
                       const Tuning& tu, hipStream_t st) {
@@ -1473,8 +1484,9 @@ hipError_t launch_tri(const GridParams& g, cplx<T>* spec, const double* kx2, con
   if (P > 256) P = 256;
   // 128-thread blocks while their modes still fill whole 128-byte lines of every row read:
   // twice the blocks of 256 threads spread more evenly over the compute units
-  const int TB = (128 / P) * (int)sizeof(cplx<T>) >= 128 ? 128 : 256;
-  const int W = TB / P;                      // modes per block
+  const int TBM = (128 / P) * (int)sizeof(cplx<T>) >= 128 ? 128 : 256;
+  const int W = tri_width<T>(P, TBM);        // modes per block
+  const int TB = W * P;
   const size_t lds = (size_t)(4 * tri_rs(W) * 2 * P + 2 * P) * sizeof(double);
   const int gather = tri_gather(g);
   const dim3 grid(tri_blocks(g, W, gather));
@@ -1587,7 +1599,7 @@ int plan_tri(const GridParams& g, cplx<T>* spec, const double* kx2, const double
   int P = (n + L - 1) / L;
   if (P > n / 2) P = n / 2 > 0 ? n / 2 : 1;
   if (P > 256) P = 256;
-  const int W = 256 / P;
+  const int W = 256 / P;   // (the launch's 256 threads: a power-of-two W would leave some idle)
   const int gather = tri_gather(g);
   const int nb = tri_blocks(g, W, gather);
   *a = TriArgs<T>{g, spec, kx2, kz2, P, W, mean_out, nb, gather};
