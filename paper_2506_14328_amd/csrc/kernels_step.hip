@@ -1464,14 +1464,13 @@ hipError_t launch_fftz(const GridParams& g, cplx<T>* spec, const FFTPlan& pz, in
 }
 
 // Modes per tridiagonal block with P threads per mode in at most tb threads: tb / P, or the
-// largest power of two below it when that still reads whole 128-byte lines of every row
-// (a run of W modes that is not a power of two starts and ends inside lines, and its
-// segment groups straddle the wavefronts).
-template <typename T>
+// largest power of two below it when that is at least 8 (whole 128-byte lines of every row
+// in FP64, half lines in FP32; a run of W modes that is not a power of two starts and ends
+// inside lines, and its segment groups straddle the wavefronts).
 static int tri_width(int P, int tb) {
   int w2 = 1;
   while (2 * w2 * P <= tb) w2 *= 2;
-  return w2 * (int)sizeof(cplx<T>) >= 128 ? w2 : tb / P;
+  return w2 >= 8 ? w2 : tb / P;
 }
 
 template <typename T>
@@ -1485,7 +1484,7 @@ hipError_t launch_tri(const GridParams& g, cplx<T>* spec, const double* kx2, con
   // 128-thread blocks while their modes still fill whole 128-byte lines of every row read:
   // twice the blocks of 256 threads spread more evenly over the compute units
   const int TBM = (128 / P) * (int)sizeof(cplx<T>) >= 128 ? 128 : 256;
-  const int W = tri_width<T>(P, TBM);        // modes per block
+  const int W = tri_width(P, TBM);        // modes per block
   const int TB = W * P;
   const size_t lds = (size_t)(4 * tri_rs(W) * 2 * P + 2 * P) * sizeof(double);
   const int gather = tri_gather(g);
