@@ -477,9 +477,11 @@ __global__ __launch_bounds__(MXT * MZT) void k_momentum(GridParams g, Fields<T> 
                                    blockIdx.y, gridDim.x);
 }
 
-// The same for a batch of independent grids in one launch (block ranges boff).
+// The same for a batch of independent grids in one launch (block ranges boff); in FP64
+// held to 168 registers, 3 waves per SIMD like the single-grid kernel (170 without the
+// bound, which left 2).
 template <typename T, bool SY>
-__global__ __launch_bounds__(256) void k_momentum_b(const MomArgs<T>* __restrict__ args,
+__global__ __launch_bounds__(256, sizeof(T) == 8 && !SY ? 3 : 1) void k_momentum_b(const MomArgs<T>* __restrict__ args,
     const int* __restrict__ boff, int ninst) {
   const int i = batch_instance(boff, ninst, blockIdx.x);
   const MomArgs<T>& a = args[i];
