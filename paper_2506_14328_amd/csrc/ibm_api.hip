@@ -864,6 +864,7 @@ int build_batch(ibm_ctx* c) {
     dv[k].resize(n);
   }
   std::vector<int> bo[6];
+  std::vector<int> th_own(n, 256);   // each instance's own z-FFT threads
   for (auto& v : bo) v.assign(n + 1, 0);
   b.cur0.resize(n);
   for (int i = 0; i < n; ++i) {
@@ -894,6 +895,7 @@ int build_batch(ibm_ctx* c) {
     Fields<T> f = fields_of<T>(I);
     bo[3][i + 1] = plan_fftz<T>(g, f.spec, I.pz, -1, I.tu, &fzf[i], &mb, &lds, &th);
     (void)plan_fftz<T>(g, f.spec, I.pz, +1, I.tu, &fzi[i], &mb, &lds, &th);
+    th_own[i] = th;
     b.mb_fz = std::max(b.mb_fz, mb);
     b.lds_fz = std::max(b.lds_fz, lds);
     b.th_fz = std::max(b.th_fz, th);
@@ -903,6 +905,20 @@ int build_batch(ibm_ctx* c) {
     bo[5][i + 1] = plan_ifftx<T>(g, f.spec, f.phi, I.px, I.rtw, &ifx[i], &mb, &lds);
     b.mb_ifx = std::max(b.mb_ifx, mb);
     b.lds_ifx = std::max(b.lds_ifx, lds);
+  }
+  // z FFTs of instances planned for fewer threads than the launch runs: columns widened
+  // by the same factor (at most 64 modes, within the LDS), so that each column keeps the
+  // lanes of the instance's own plan
+  for (int i = 0; i < n; ++i) {
+    const GridParams& g = c->inst[i].g;
+    const int f = b.th_fz / th_own[i], W2 = fzf[i].W * f;
+    const size_t l2 = ((size_t)W2 + 1) * g.nz * sizeof(cplx<T>);
+    if (f > 1 && W2 <= 64 && W2 <= g.mh && l2 <= 163840) {
+      fzf[i].W = fzi[i].W = W2;
+      b.lds_fz = std::max(b.lds_fz, l2);
+      bo[3][i + 1] = fftz_blocks(g.mh, g.ny1, W2, 1);
+      fzf[i].gx = fzi[i].gx = bo[3][i + 1];
+    }
   }
   // z FFTs: four planes per block with the next plane's columns in registers (RP per
   // thread) when every instance's share of a column, at the launch's thread count, fits 8
